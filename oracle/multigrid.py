@@ -1,0 +1,85 @@
+"""Monolithic geometric multigrid hierarchy and V-cycle.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import this module.
+
+Paper passages followed:
+  * Sec. 3, eq. (TG-Operator-Biot): E_TG = E_s^{nu2} E_CGC E_s^{nu1}, E_s = I - omega M^{-1} A,
+    E_CGC = I - P A_H^{-1} R A, R = P^T, coarse operators by rediscretization; the
+    multilevel cycle replaces A_H^{-1} by the same cycle on the coarser level.
+  * Sec. 5.1: direct solve on the coarsest mesh.
+Readings: coarsest mesh 4 x 4 unless told otherwise; one omega on every level; the
+heterogeneous permeability is coarsened by averaging 1/K over the four children.
+"""
+import numpy as np
+import scipy.linalg as sla
+
+from .mesh import Mesh
+from .fem import Assembly, coarsen_inverse_K
+from .transfer import prolongation
+from .smoothers import AdditiveVanka, InexactBSR, patch_table
+
+
+class Level:
+    def __init__(self, n, params, K_tri):
+        self.mesh = Mesh(n)
+        self.asm = Assembly(self.mesh, params, K_tri)
+        self.A = self.asm.A
+        self.P = None          # prolongation from the next coarser level
+        self.smoother = None
+
+
+class Hierarchy:
+    """Levels 0 (finest, n) .. L-1 (coarsest, n_coarse)."""
+
+    def __init__(self, n, params, K_tri=1.0, smoother="vanka", omega=1.0, omega_J=1.0,
+                 nu1=1, nu2=1, n_coarse=4, levels=None):
+        if levels is not None:
+            n_coarse = n >> (levels - 1)
+        self.params = params
+        self.nu1, self.nu2 = int(nu1), int(nu2)
+        self.levels = []
+        Kinv = 1.0 / np.broadcast_to(np.asarray(K_tri, dtype=np.float64), (2 * n * n,))
+        nn = n
+        while True:
+            lev = Level(nn, params, 1.0 / Kinv)
+            self.levels.append(lev)
+            if nn <= n_coarse:
+                break
+            Kinv = coarsen_inverse_K(nn, Kinv)
+            nn //= 2
+        for l in range(len(self.levels) - 1):
+            _, self.levels[l].P = prolongation(self.levels[l].mesh, self.levels[l + 1].mesh)
+        for lev in self.levels[:-1]:
+            if smoother == "vanka":
+                _, slots = patch_table(lev.mesh, "full")
+                lev.smoother = AdditiveVanka(lev.A, slots, omega)
+            elif smoother == "bsr":
+                lev.smoother = InexactBSR(lev.asm, omega, omega_J)
+            else:
+                raise ValueError(smoother)
+        self.coarse_lu = sla.lu_factor(self.levels[-1].A.toarray())
+
+    @property
+    def A(self):
+        return self.levels[0].A
+
+    def vcycle(self, b, level=0):
+        """One V(nu1, nu2) cycle for A_level x = b from x = 0."""
+        lev = self.levels[level]
+        if level == len(self.levels) - 1:
+            return sla.lu_solve(self.coarse_lu, b)
+        x = np.zeros_like(b)
+        for _ in range(self.nu1):
+            x = lev.smoother.smooth(x, b)
+        r = b - lev.A @ x
+        xc = self.vcycle(lev.P.T @ r, level + 1)
+        x = x + lev.P @ xc
+        for _ in range(self.nu2):
+            x = lev.smoother.smooth(x, b)
+        return x
+
+    def error_propagation(self, e):
+        """Error propagation of one cycle used as a stationary iteration: e - V(A e).
+
+        With two levels this is the two-grid operator E_TG of Sec. 3 (exact coarse solve)."""
+        return e - self.vcycle(self.levels[0].A @ e)

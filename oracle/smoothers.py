@@ -1,0 +1,148 @@
+"""Vertex patches, additive Vanka and inexact Braess-Sarazin relaxation.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import this module.
+
+Paper passages followed:
+  * Sec. 3.2.1 (Vanka): for blocks l with restriction V_l, solve
+    V_l A V_l^T xhat_l = V_l r and update x <- x + omega sum_l V_l^T D_l xhat_l, with the
+    "natural weights" D_l = 1 / (number of patches containing the DoF).
+  * Sec. 3.2.1, Fig. patches: vertex patches; the full-system patch holds the two P1 DoFs
+    of the vertex, the bubble and RT0 DoFs of its six edges and the P0 DoFs of its six
+    triangles (20 DoFs); the displacement patch holds the P1 and bubble DoFs (8 DoFs).
+  * Sec. 3.2.2 and Appendix D (inexact BSR): M = [[F, B^T], [B, -C_2]] with
+    F = diag(A_{V,u}, tau D_w), D_w = diag(M_w), A_{V,u}^{-1} one additive Vanka sweep on
+    the displacement block with the 8-DoF patches, and C_2 chosen so that the Schur
+    complement of M is (1/omega_J) diag(S),
+        S = (1/M + alpha^2 / (lambda + 2 mu / d)) M_p + tau B_w D_w^{-1} B_w^T,  d = 2.
+
+Readings where the paper is silent (listed in the design notes):
+  * a patch is built for every vertex whose patch holds at least one free displacement or
+    Darcy DoF (full patch), resp. at least one free displacement DoF (displacement patch);
+    only the two corners (0,0) and (n,n) drop out, since their patches hold pressure only;
+  * the inner Vanka weight inside BSR and the Jacobi weight on D_w are 1.
+
+Patch slot order (20 slots; absent or eliminated DoFs are -1):
+    [ux(v), uy(v),
+     b on H(i-1,j), H(i,j), V(i,j-1), V(i,j), D(i-1,j), D(i,j-1),
+     w on the same six edges,
+     p on L(i,j), L(i-1,j), L(i,j-1), U(i-1,j-1), U(i-1,j), U(i,j-1)]
+"""
+import numpy as np
+
+from .mesh import Mesh
+
+EDGES_OF_VERTEX = [(0, -1, 0), (0, 0, 0), (1, 0, -1), (1, 0, 0), (2, -1, 0), (2, 0, -1)]
+TRIS_OF_VERTEX = [(0, 0, 0), (0, -1, 0), (0, 0, -1), (1, -1, -1), (1, -1, 0), (1, 0, -1)]
+
+
+def vertex_patch_slots(mesh: Mesh, i, j):
+    """The 20 slot entries (canonical free index or -1) of the patch of vertex (i, j)."""
+    s = [mesh.dof_ux(i, j), mesh.dof_uy(i, j)]
+    s += [mesh.dof_b(k, i + di, j + dj) for (k, di, dj) in EDGES_OF_VERTEX]
+    s += [mesh.dof_w(k, i + di, j + dj) for (k, di, dj) in EDGES_OF_VERTEX]
+    s += [mesh.dof_p(up, i + di, j + dj) for (up, di, dj) in TRIS_OF_VERTEX]
+    return np.array(s, dtype=np.int64)
+
+
+def patch_table(mesh: Mesh, kind="full"):
+    """Return (vertex ids, slots) of all kept patches, vertices in row-major (j, i) order.
+
+    kind = "full": 20 slots; kind = "u": the first 8 slots (displacement patch).
+    """
+    verts, rows = [], []
+    for j in range(mesh.n + 1):
+        for i in range(mesh.n + 1):
+            s = vertex_patch_slots(mesh, i, j)
+            if kind == "u":
+                s = s[:8]
+                keep = np.any(s >= 0)
+            else:
+                keep = np.any(s[:14] >= 0)
+            if keep:
+                verts.append(mesh.vid(i, j))
+                rows.append(s)
+    return np.array(verts, dtype=np.int64), np.array(rows, dtype=np.int64)
+
+
+def _dense_blocks(A, idx):
+    """Dense V_l A V_l^T for index sets idx (P, s) of one common size."""
+    P, s = idx.shape
+    r = np.repeat(idx, s, axis=1).ravel()
+    c = np.tile(idx, (1, s)).ravel()
+    vals = np.asarray(A[r, c]).ravel()
+    return vals.reshape(P, s, s)
+
+
+class AdditiveVanka:
+    """x <- x + omega * sum_l V_l^T D_l (V_l A V_l^T)^{-1} V_l (b - A x)."""
+
+    def __init__(self, A, slots, omega=1.0):
+        self.A = A.tocsr()
+        self.omega = float(omega)
+        n = A.shape[0]
+        mult = np.zeros(n)
+        self.groups = []   # (index array (P, s), patch matrices (P, s, s))
+        sets = [np.array(sorted(r[r >= 0])) for r in slots]
+        sizes = sorted(set(len(t) for t in sets))
+        for s in sizes:
+            idx = np.array([t for t in sets if len(t) == s], dtype=np.int64)
+            if s == 0:
+                continue
+            self.groups.append((idx, _dense_blocks(self.A, idx)))
+            np.add.at(mult, idx.ravel(), 1.0)
+        if np.any(mult == 0):
+            raise ValueError("some DoF lies in no patch")
+        self.weight = 1.0 / mult
+        self.n_patches = len(sets)
+
+    def correction(self, r):
+        """sum_l V_l^T D_l (V_l A V_l^T)^{-1} V_l r (LAPACK gesv per patch)."""
+        out = np.zeros_like(r)
+        for idx, Al in self.groups:
+            xl = np.linalg.solve(Al, r[idx][:, :, None])[:, :, 0]
+            np.add.at(out, idx.ravel(), (self.weight[idx] * xl).ravel())
+        return out
+
+    def smooth(self, x, b):
+        return x + self.omega * self.correction(b - self.A @ x)
+
+
+class InexactBSR:
+    """One inexact Braess-Sarazin step (Sec. 3.2.2, Appendix D)."""
+
+    def __init__(self, asm, omega, omega_J):
+        mesh = asm.mesh
+        P = asm.params
+        A = asm.A.tocsr()
+        self.A = A
+        su, sw, sp_ = asm.slices()
+        self.su, self.sw, self.sp = su, sw, sp_
+        self.omega = float(omega)
+        self.omega_J = float(omega_J)
+        Auu = A[su, su].tocsr()
+        self.Aup = A[su, sp_].tocsr()
+        self.Awp = A[sw, sp_].tocsr()
+        self.Apu = A[sp_, su].tocsr()
+        self.Apw = A[sp_, sw].tocsr()
+        self.Dww = A[sw, sw].diagonal()                         # tau D_w
+        _, uslots = patch_table(mesh, "u")
+        self.fu = AdditiveVanka(Auu, uslots, omega=1.0)        # A_{V,u}^{-1}
+        Mp = asm.free(asm.Mp_full)[sp_, sp_].diagonal()
+        d = 2.0
+        c_u = P.inv_M + P.alpha ** 2 / (P.lam + 2.0 * P.mu / d)
+        # tau B_w D_w^{-1} B_w^T = A_pw (tau D_w)^{-1} A_pw^T; its diagonal:
+        wdiag = np.asarray(self.Apw.multiply(self.Apw) @ (1.0 / self.Dww)).ravel()
+        self.diagS = c_u * Mp + wdiag
+
+    def step_correction(self, r):
+        ru, rw, rp = r[self.su], r[self.sw], r[self.sp]
+        zu = self.fu.correction(ru)
+        zw = rw / self.Dww
+        s = self.Apu @ zu + self.Apw @ zw - rp
+        dp = self.omega_J * s / self.diagS
+        du = self.fu.correction(ru - self.Aup @ dp)
+        dw = (rw - self.Awp @ dp) / self.Dww
+        return np.concatenate([du, dw, dp])
+
+    def smooth(self, x, b):
+        return x + self.omega * self.step_correction(b - self.A @ x)

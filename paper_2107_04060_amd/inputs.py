@@ -1,0 +1,132 @@
+"""Seeded synthetic inputs: right-hand sides, permeability fields and the workload
+definitions.  Holds none of the solver's arithmetic; both the GPU path's tests/bench and
+the CPU reference use exactly these arrays.
+
+Workloads (synthetic stand-ins; the paper's own experiments use manufactured solutions):
+  * small      16 x 16,   3 levels, lambda = mu = 1, K = 1, tau = 1, Vanka V(1,1), seed 0
+  * sweep256  256 x 256,  7 levels, E = 1, nu in {0.2, 0.49, 0.4999}, K in {1, 1e-3, 1e-6},
+              Vanka V(2,2) and inexact BSR V(1,1), seed 1
+  * grf1024  1024 x 1024, 9 levels, log10 K = -3 + GRF(corr 0.1), nu = 0.49, tau = 1e-2,
+              FP32 smoother, seed 2
+  * block2048 2048 x 2048, 10 levels, K in {1, 1e-6} on 64 x 64-cell blocks, nu = 0.4999,
+              16 right-hand sides, seed 3
+  * adjoint512 512 x 512, 8 levels, ln K = GRF(corr 0.05), seed 4 (observations seed 5)
+
+Biot modulus: the workloads do not state M.  The method depends on the parameters only
+through nu and the groups E / (alpha^2 M) and E tau K / (alpha^2 mu_f) (a constant
+rescaling of u, w and p maps one system onto another and leaves Vanka, BSR, the transfers
+and the rediscretized coarse operators invariant).  The paper fixes E = 3e4, M = 1e6,
+i.e. E / (alpha^2 M) = 0.03; the workloads keep that ratio: M = E / (0.03 alpha^2).
+"""
+import numpy as np
+
+PAPER_STORAGE_RATIO = 3.0e4 / 1.0e6      # E / (alpha^2 M) in all of the paper's tests
+
+
+def lame(E, nu):
+    mu = E / (2.0 + 2.0 * nu)
+    lam = E * nu / ((1.0 - 2.0 * nu) * (1.0 + nu))
+    return lam, mu
+
+
+def young_from_lame(lam, mu):
+    return mu * (3.0 * lam + 2.0 * mu) / (lam + mu)
+
+
+def biot_modulus(E, alpha=1.0):
+    """M with E / (alpha^2 M) equal to the paper's 0.03."""
+    return E / (PAPER_STORAGE_RATIO * alpha * alpha)
+
+
+def n_free(n):
+    return 10 * n * n - 8 * n + 2
+
+
+def rhs_uniform(n, seed, count=1):
+    """Right-hand side(s) iid uniform[-1, 1] in the canonical free-DoF order."""
+    rng = np.random.default_rng(seed)
+    out = rng.uniform(-1.0, 1.0, (count, n_free(n)))
+    return out[0] if count == 1 else out
+
+
+def grf_squares(n, corr_len, rng):
+    """Gaussian random field on the n x n squares of the unit square, standardized to
+    sample mean 0 and std 1: white noise on a zero-padded 2n x 2n periodic grid filtered
+    in Fourier space by the transform of exp(-r^2 / (2 l^2)), cropped to n x n.
+    Row-major [j, i]."""
+    m = 2 * n
+    noise = rng.standard_normal((m, m))
+    k = np.fft.fftfreq(m, d=1.0 / n)            # cycles per unit length
+    kx, ky = np.meshgrid(k, k, indexing="xy")
+    filt = np.exp(-0.5 * (2.0 * np.pi) ** 2 * corr_len ** 2 * (kx ** 2 + ky ** 2) / 2.0)
+    f = np.real(np.fft.ifft2(np.fft.fft2(noise) * filt))[:n, :n]
+    f = (f - f.mean()) / f.std()
+    return f
+
+
+def squares_to_triangles(f_sq):
+    """Per-square field [j, i] -> per-triangle array [L(j n + i) ..., U(j n + i) ...]."""
+    v = np.asarray(f_sq, dtype=np.float64).ravel()
+    return np.concatenate([v, v])
+
+
+def block_contrast_squares(n, block, rng, values=(1.0, 1e-6)):
+    """Piecewise-constant field on block x block cell tiles, each tile value drawn with
+    probability 1/2 from `values`."""
+    nb = max(1, n // block)
+    pick = rng.integers(0, 2, (nb, nb))
+    tiles = np.where(pick == 0, values[0], values[1])
+    return np.kron(tiles, np.ones((block, block)))[:n, :n]
+
+
+def workload(name):
+    """Definition dictionary of a named workload (params, mesh, smoother settings)."""
+    if name == "small":
+        lam, mu = 1.0, 1.0
+        E = young_from_lame(lam, mu)
+        return dict(name=name, n=16, levels=3, cases=[dict(lam=lam, mu=mu, K=1.0)],
+                    alpha=1.0, M=biot_modulus(E), mu_f=1.0, tau=1.0, seed=0,
+                    smoothers=["vanka"], nu12={"vanka": 1, "bsr": 1})
+    if name == "sweep256":
+        cases = []
+        for nu in (0.2, 0.49, 0.4999):
+            for K in (1.0, 1e-3, 1e-6):
+                lam, mu = lame(1.0, nu)
+                cases.append(dict(lam=lam, mu=mu, K=K, nu=nu))
+        return dict(name=name, n=256, levels=7, cases=cases, alpha=1.0, M=biot_modulus(1.0),
+                    mu_f=1.0, tau=1.0, seed=1, smoothers=["vanka", "bsr"],
+                    nu12={"vanka": 2, "bsr": 1})
+    if name == "grf1024":
+        lam, mu = lame(1.0, 0.49)
+        return dict(name=name, n=1024, levels=9, cases=[dict(lam=lam, mu=mu, nu=0.49)],
+                    alpha=1.0, M=biot_modulus(1.0), mu_f=1.0, tau=1e-2, seed=2,
+                    smoothers=["vanka"], nu12={"vanka": 2, "bsr": 1}, corr_len=0.1,
+                    log10K_mean=-3.0, log10K_std=1.0)
+    if name == "block2048":
+        lam, mu = lame(1.0, 0.4999)
+        return dict(name=name, n=2048, levels=10, cases=[dict(lam=lam, mu=mu, nu=0.4999)],
+                    alpha=1.0, M=biot_modulus(1.0), mu_f=1.0, tau=1.0, seed=3,
+                    smoothers=["vanka"], nu12={"vanka": 2, "bsr": 1}, block=64, n_rhs=16)
+    if name == "adjoint512":
+        lam, mu = lame(1.0, 0.3)
+        return dict(name=name, n=512, levels=8, cases=[dict(lam=lam, mu=mu, nu=0.3)],
+                    alpha=1.0, M=biot_modulus(1.0), mu_f=1.0, tau=1.0, seed=4, obs_seed=5,
+                    smoothers=["vanka"], nu12={"vanka": 2, "bsr": 1}, corr_len=0.05, batch=8)
+    raise KeyError(name)
+
+
+def permeability_triangles(name, n=None):
+    """Per-triangle permeability of a workload (array) or a scalar."""
+    w = workload(name)
+    n = w["n"] if n is None else n
+    if name == "grf1024":
+        rng = np.random.default_rng(w["seed"])
+        f = grf_squares(n, w["corr_len"], rng)
+        return squares_to_triangles(10.0 ** (w["log10K_mean"] + w["log10K_std"] * f))
+    if name == "block2048":
+        rng = np.random.default_rng(w["seed"])
+        return squares_to_triangles(block_contrast_squares(n, w["block"], rng))
+    if name == "adjoint512":
+        rng = np.random.default_rng(w["seed"])
+        return squares_to_triangles(np.exp(grf_squares(n, w["corr_len"], rng)))
+    return None

@@ -1,0 +1,228 @@
+"""Pins of the oracle's relaxation, cycle and Krylov solver: brute-force dense operators on
+tiny meshes, the paper's two-grid convergence factors (Tables 2 and 3), and FGMRES
+against a sparse direct solve and an explicit Krylov minimal-residual solution."""
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse.linalg as spla
+
+from oracle.mesh import Mesh
+from oracle.fem import Assembly, BiotParams
+from oracle.smoothers import AdditiveVanka, InexactBSR, patch_table, vertex_patch_slots
+from oracle.multigrid import Hierarchy
+from oracle.krylov import fgmres, fgmres_fixed
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.mark.parametrize("n", [2, 4, 8])
+def test_patch_counts_sizes_and_multiplicities(n):
+    m = Mesh(n)
+    verts, slots = patch_table(m, "full")
+    assert len(verts) == (n + 1) ** 2 - 2
+    assert m.vid(0, 0) not in verts and m.vid(n, n) not in verts
+    sizes = np.sum(slots >= 0, axis=1)
+    for v, s in zip(verts, sizes):
+        i, j = m.vert_ij[v]
+        if 0 < i < n and 0 < j < n:
+            assert s == 20
+    mult = np.zeros(m.n_free, dtype=int)
+    for s in slots:
+        mult[s[s >= 0]] += 1
+    assert np.all(mult >= 1)
+    assert np.all(mult[:2 * (n - 1) ** 2] == 1)                  # P1: own vertex only
+    assert np.all(mult[2 * (n - 1) ** 2:m.n_u + m.n_w] == 2)     # edges: both end points
+    p = mult[m.n_u + m.n_w:]
+    assert p[m.dof_p(False, 0, 0) - m.n_u - m.n_w] == 2          # L(0,0) touches corner (0,0)
+    assert p[m.dof_p(True, n - 1, n - 1) - m.n_u - m.n_w] == 2
+    assert np.sum(p == 3) == m.n_p - 2
+    uverts, uslots = patch_table(m, "u")
+    assert len(uverts) == (n + 1) ** 2 - 2 and uslots.shape[1] == 8
+
+
+def _params():
+    return BiotParams.from_E_nu(1.0, 0.3, alpha=0.9, M=30.0, mu_f=1.2, tau=0.8)
+
+
+def _dense_vanka_inverse(A, slots):
+    """sum_l V_l^T D_l (V_l A V_l^T)^{-1} V_l with explicit 0/1 restriction matrices."""
+    N = A.shape[0]
+    Ad = A.toarray()
+    Vs = []
+    for s in slots:
+        idx = sorted(s[s >= 0])
+        V = np.zeros((len(idx), N))
+        V[np.arange(len(idx)), idx] = 1.0
+        Vs.append(V)
+    mult = sum(V.sum(axis=0) for V in Vs)
+    Minv = np.zeros((N, N))
+    for V in Vs:
+        D = np.diag(1.0 / (V @ mult))
+        Minv += V.T @ D @ np.linalg.inv(V @ Ad @ V.T) @ V
+    return Minv
+
+
+def test_vanka_matches_dense_definition():
+    """Sec. 3.2.1: the additive Vanka update, built densely from V_l and D_l."""
+    m = Mesh(4)
+    K = np.random.default_rng(1).uniform(0.3, 2.0, m.n_tri)
+    asm = Assembly(m, _params(), K)
+    _, slots = patch_table(m, "full")
+    vk = AdditiveVanka(asm.A, slots, omega=0.7)
+    Minv = _dense_vanka_inverse(asm.A, slots)
+    r = np.random.default_rng(2).standard_normal(m.n_free)
+    assert np.allclose(vk.correction(r), Minv @ r, rtol=1e-11, atol=1e-11 * np.abs(Minv @ r).max())
+
+
+def test_inexact_bsr_matches_appendixD_matrix_form():
+    """Appendix D: one inexact BSR step applies M^{-1} with M = [[F, B^T], [B, -C_2]],
+    F = diag(A_{V,u}, tau D_w), C_2 = (1/omega_J) diag(S) - alpha^2 B_u A_{V,u}^{-1} B_u^T
+    - tau B_w D_w^{-1} B_w^T."""
+    m = Mesh(4)
+    p = _params()
+    K = np.random.default_rng(5).uniform(0.3, 2.0, m.n_tri)
+    asm = Assembly(m, p, K)
+    oj = 1.15
+    bsr = InexactBSR(asm, omega=0.8, omega_J=oj)
+    su, sw, sp_ = asm.slices()
+    A = asm.A.toarray()
+    _, uslots = patch_table(m, "u")
+    Auu = asm.A[su, su]
+    AVinv = _dense_vanka_inverse(Auu, uslots)
+    Mw = asm.free(asm.Mw_full)[sw, sw].toarray()
+    Dw = np.diag(np.diag(Mw))
+    Bu = asm.free(asm.Bu_full)[sp_, su].toarray()
+    Bw = asm.free(asm.Bw_full)[sp_, sw].toarray()
+    Mp = asm.free(asm.Mp_full)[sp_, sp_].toarray()
+    S = (p.inv_M + p.alpha ** 2 / (p.lam + p.mu)) * Mp + p.tau * Bw @ np.linalg.inv(Dw) @ Bw.T
+    C2 = (np.diag(np.diag(S)) / oj - p.alpha ** 2 * Bu @ AVinv @ Bu.T
+          - p.tau * Bw @ np.linalg.inv(Dw) @ Bw.T)
+    nu_, nw = Auu.shape[0], Mw.shape[0]
+    F = np.zeros((nu_ + nw, nu_ + nw))
+    F[:nu_, :nu_] = np.linalg.inv(AVinv)
+    F[nu_:, nu_:] = p.tau * Dw
+    B = np.hstack([p.alpha * Bu, p.tau * Bw])
+    Mfull = np.block([[F, B.T], [B, -C2]])
+    assert np.allclose(A[sp_, su], p.alpha * Bu) and np.allclose(A[sp_, sw], p.tau * Bw)
+    r = np.random.default_rng(6).standard_normal(m.n_free)
+    ref = np.linalg.solve(Mfull, r)
+    got = bsr.step_correction(r)
+    assert np.abs(got - ref).max() < 1e-9 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("smoother", ["vanka", "bsr"])
+def test_two_grid_operator_matches_dense_formula(smoother):
+    """Sec. 3, eq. (TG-Operator-Biot): E_TG = E_s^nu2 (I - P A_H^{-1} P^T A) E_s^nu1."""
+    n = 8
+    p = _params()
+    H = Hierarchy(n, p, smoother=smoother, omega=0.75, omega_J=1.1, nu1=2, nu2=1, levels=2)
+    A = H.levels[0].A.toarray()
+    Ac = H.levels[1].A.toarray()
+    P = H.levels[0].P.toarray()
+    N = A.shape[0]
+    sm = H.levels[0].smoother
+    Es = np.zeros((N, N))
+    for k in range(N):       # E_s = I - omega M^{-1} A, column by column through smooth(x, 0)
+        e = np.zeros(N)
+        e[k] = 1.0
+        Es[:, k] = sm.smooth(e, np.zeros(N))
+    Ecgc = np.eye(N) - P @ np.linalg.solve(Ac, P.T @ A)
+    Etg = Es @ Ecgc @ Es @ Es
+    v = np.random.default_rng(9).standard_normal(N)
+    assert np.abs(H.error_propagation(v) - Etg @ v).max() < 1e-10 * np.abs(Etg @ v).max()
+
+
+def _table(name):
+    rows = []
+    with open(os.path.join(GOLD, name)) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                rows.append([float(x) for x in line.split()])
+    return rows
+
+
+def _two_grid_radius(n, nu, k, smoother, omega, omega_J, nu12):
+    p = BiotParams.from_E_nu(3e4, nu, alpha=1.0, M=1e6, mu_f=1.0, tau=1.0)
+    H = Hierarchy(n, p, K_tri=k, smoother=smoother, omega=omega, omega_J=omega_J,
+                  nu1=nu12, nu2=nu12, levels=2)
+    N = H.A.shape[0]
+    op = spla.LinearOperator((N, N), matvec=H.error_propagation, dtype=float)
+    v0 = np.random.default_rng(0).uniform(-1, 1, N)
+    vals = spla.eigs(op, k=2, which="LM", tol=1e-3, maxiter=300, v0=v0, return_eigenvectors=False)
+    return float(np.abs(vals).max())
+
+
+TABLE2_CASES = [(0.4, 1.0), (0.49, 1e-6), (0.0, 1.0)]
+TABLE3_CASES = [(0.49, 1.0), (0.0, 1.0)]
+
+
+@pytest.mark.parametrize("nu,k", TABLE2_CASES)
+def test_two_grid_vanka_radius_table2(nu, k):
+    """Table 2: the asymptotic two-grid factor of additive Vanka V(2,2) at the paper's
+    optimised omega.  The oracle's spectral radius of E_TG (Dirichlet, h = 1/32 for run
+    time) must lie within 0.025 of the measured rho_N printed for h = 1/64."""
+    row = [r for r in _table("table2_vanka.txt") if r[0] == nu and r[1] == k][0]
+    rho = _two_grid_radius(32, nu, k, "vanka", row[2], 1.0, 2)
+    assert abs(rho - row[4]) < 0.025, (rho, row)
+
+
+@pytest.mark.parametrize("nu,k", TABLE3_CASES)
+def test_two_grid_bsr_radius_table3(nu, k):
+    """Table 3: inexact BSR V(1,1) at the paper's (omega_J, omega)."""
+    row = [r for r in _table("table3_bsr.txt") if r[0] == nu and r[1] == k][0]
+    rho = _two_grid_radius(32, nu, k, "bsr", row[3], row[2], 1)
+    assert abs(rho - row[5]) < 0.025, (rho, row)
+
+
+def test_fgmres_fixed_iterations_is_krylov_minimal_residual():
+    """k steps of right-preconditioned FGMRES with a fixed linear preconditioner M return
+    x = M y minimising ||b - A M y|| over the Krylov space K_k(A M, b)."""
+    n = 4
+    asm = Assembly(Mesh(n), _params())
+    H = Hierarchy(n * 2, _params(), smoother="vanka", omega=0.7, nu1=1, nu2=1, levels=2)
+    A = H.A
+    b = np.random.default_rng(4).standard_normal(A.shape[0])
+    Md = np.column_stack([H.vcycle(e) for e in np.eye(A.shape[0])])
+    AM = A.toarray() @ Md
+    for k in (1, 3, 6):
+        K = np.column_stack([np.linalg.matrix_power(AM, j) @ b for j in range(k)])
+        Q, _ = np.linalg.qr(K)
+        y, *_ = np.linalg.lstsq(AM @ Q, b, rcond=None)
+        ref = Md @ (Q @ y)
+        got = fgmres_fixed(A, b, H.vcycle, k)
+        assert np.abs(got - ref).max() < 1e-8 * np.abs(ref).max()
+    del asm
+
+
+@pytest.mark.parametrize("smoother,nu12,omega,omega_J", [("vanka", 2, 0.9, 1.0), ("bsr", 1, 0.6, 1.3)])
+def test_fgmres_vcycle_solves_small_config(smoother, nu12, omega, omega_J):
+    """Sec. 5.1 set-up on the 16 x 16 problem (lambda = mu = 1, K = 1, alpha = 1, tau = 1,
+    Biot modulus at the paper's storage ratio E / (alpha^2 M) = 0.03): FGMRES + 3-level
+    V-cycle reaches relative residual 1e-8 and agrees with a sparse direct solve."""
+    n = 16
+    E = 2.5                      # lambda = mu = 1  <=>  E = 2.5, nu = 0.25
+    p = BiotParams(1.0, 1.0, alpha=1.0, M=E / 0.03, mu_f=1.0, tau=1.0)
+    H = Hierarchy(n, p, smoother=smoother, omega=omega, omega_J=omega_J, nu1=nu12, nu2=nu12, levels=3)
+    A = H.A
+    b = np.random.default_rng(0).uniform(-1, 1, A.shape[0])
+    x, info = fgmres(A, b, H.vcycle, tol=1e-8, restart=30, maxit=200)
+    assert info["converged"] and info["iters"] < 60
+    assert np.linalg.norm(b - A @ x) <= 1e-8 * np.linalg.norm(b)
+    xs = spla.spsolve(A.tocsc(), b)
+    assert np.linalg.norm(A @ (x - xs)) <= 2e-8 * np.linalg.norm(b)
+    # forward error within cond(A) * tol (cond estimated by the dense spectrum)
+    ev = np.abs(np.linalg.eigvalsh(A.toarray()))
+    assert np.linalg.norm(x - xs) <= 2e-8 * ev.max() / ev.min() * np.linalg.norm(xs)
+
+
+def test_vanka_v11_is_not_a_convergent_two_grid_cycle():
+    """Sec. 4.3 uses nu1 = nu2 = 2 for Vanka: with the divergence-preserving P_u the
+    rediscretized coarse RQ term is a quarter of the Galerkin one, so coarse-grid
+    correction overshoots compressive modes and a single smoothing step per side cannot
+    damp them.  At the Table 2 parameters (nu = 0.4, k = 1) V(1,1) has rho(E_TG) >= 1 for
+    every omega on a 0.1 grid (h = 1/32), while V(2,2) at omega = 0.8 gives the printed ~0.40."""
+    rhos = [_two_grid_radius(32, 0.4, 1.0, "vanka", om, 1.0, 1) for om in (0.6, 0.7, 0.8, 0.9)]
+    assert min(rhos) > 0.97, rhos
+    assert _two_grid_radius(32, 0.4, 1.0, "vanka", 0.8, 1.0, 2) < 0.45
