@@ -1,0 +1,164 @@
+/*
+ * biot_mg.h -- C ABI of the MI355X (gfx950) monolithic multigrid solver for the
+ * reduced-quadrature (RQ) three-field Biot system of Adler, He, Hu, MacLachlan and Ohm,
+ * "Monolithic multigrid for a reduced-quadrature discretization of poroelasticity"
+ * (arXiv:2107.04060).
+ *
+ * Problem (Sec. 2.1, eqs. discrete1-discrete3, block_form; Sec. 2.3, block_form_rq):
+ * one backward-Euler step of Biot's model on the unit square, uniform n x n mesh with
+ * every square cut from its top-left to its bottom-right corner (Appendix A), spaces
+ * P1 + face bubbles (displacement u), RT0 (Darcy velocity w), P0 (pressure p); the
+ * symmetric saddle-point matrix
+ *     A = [[A_u^RQ, 0, alpha B_u^T], [0, tau M_w, tau B_w^T], [alpha B_u, tau B_w, -(1/M) M_p]]
+ * with A_u^RQ = 2 mu A_eps + lambda B_u^T M_p^{-1} B_u (Appendix A), Dirichlet data u = 0
+ * and w.n = 0 on the whole boundary (those DoFs are eliminated).
+ *
+ * Solver (Sec. 3 and 5.1): FGMRES (right preconditioned, flexible, x0 = 0) with one
+ * monolithic geometric-multigrid V(nu1, nu2) cycle as preconditioner: rediscretized
+ * coarse operators, block prolongation diag(P_u, P_w, P_p) with the divergence-
+ * preserving P_u of Sec. 3.1, restriction P^T, additive Vanka (Sec. 3.2.1) or inexact
+ * Braess-Sarazin (Sec. 3.2.2, Appendix D) relaxation, exact solve on the coarsest mesh.
+ *
+ * Vector layout.  Every vector crossing this ABI is a DEVICE pointer to FP64 values in
+ * the canonical free-DoF order of its mesh level (n_l = n >> l cells per side):
+ *     [u_x(interior vertices), u_y(interior vertices), b_H, b_V, b_D (interior edges),
+ *      w_H, w_V, w_D (interior edges), p_L, p_U]
+ * each block row-major in (j, i); H(i,j) is the edge (i,j)-(i+1,j) with unit normal +y,
+ * V(i,j) the edge (i,j)-(i,j+1) with normal +x, D(i,j) the diagonal (i,j+1)-(i+1,j)
+ * with normal (1,1)/sqrt(2); L(i,j) = {(i,j),(i+1,j),(i,j+1)}, U(i,j) = {(i+1,j),
+ * (i+1,j+1),(i,j+1)}.  Length 10 n^2 - 8 n + 2.  Bubble DoFs are normal displacements
+ * at edge midpoints (basis 4 l_p l_q n_e), RT0 DoFs normal fluxes (normal component 1).
+ * Per-triangle arrays are ordered [L(j n + i) for all cells, then U(j n + i)].
+ *
+ * Ownership.  The caller allocates and owns every pointer it passes; the library never
+ * frees caller memory and keeps no caller pointer after a call returns.  All device work
+ * of a call is enqueued on `stream` (a hipStream_t, NULL = default stream); calls return
+ * after enqueueing unless stated otherwise (solve synchronizes with the stream once per
+ * FGMRES iteration to read the Hessenberg column).  A context is not thread safe; several
+ * contexts may coexist.  All device memory a context needs is allocated by
+ * biot_assemble / biot_setup_hierarchy; later calls allocate nothing.
+ *
+ * Errors.  Every int-returning function returns one of the BIOT_* codes below and, on
+ * failure, leaves a message for biot_last_error().  No C++ exception crosses the ABI.
+ */
+#ifndef BIOT_MG_H
+#define BIOT_MG_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BIOT_OK 0
+#define BIOT_NOT_CONVERGED 1      /* solve: maxit reached; x holds the last iterate      */
+#define BIOT_ERR_ARG (-1)         /* invalid argument (message says which)               */
+#define BIOT_ERR_HIP (-2)         /* a HIP runtime call failed                            */
+#define BIOT_ERR_OOM (-3)         /* device allocation failed                             */
+#define BIOT_ERR_SINGULAR (-4)    /* zero / non-positive pivot in a setup factorization   */
+#define BIOT_ERR_NAN (-5)         /* NaN or Inf met in the Krylov iteration               */
+
+#define BIOT_SMOOTHER_VANKA 0     /* additive Vanka, 20-DoF vertex patches (Sec. 3.2.1)  */
+#define BIOT_SMOOTHER_BSR 1       /* inexact Braess-Sarazin (Sec. 3.2.2, Appendix D)     */
+
+#define BIOT_PREC_FP64 0          /* whole preconditioner in FP64                         */
+#define BIOT_PREC_FP32_SMOOTHER 1 /* V-cycle vectors and patch solves in FP32, FP64 outer */
+
+typedef struct biot_ctx biot_ctx;
+
+/* Physical and discretization parameters of one time step (Sec. 2, 2.1). */
+typedef struct {
+    int n;              /* cells per side of the finest mesh; power of two, 4 <= n <= 8192 */
+    double lambda;      /* Lame lambda >= 0                                                 */
+    double mu;          /* Lame mu > 0                                                      */
+    double alpha;       /* Biot-Willis coefficient (any real, usually in (0, 1])           */
+    double inv_M;       /* 1/M, reciprocal Biot modulus; > 0                                */
+    double mu_f;        /* fluid viscosity > 0                                              */
+    double tau;         /* time step > 0                                                    */
+    double K_scalar;    /* permeability used when K_tri == NULL; > 0                        */
+    const double* K_tri;/* device pointer to 2 n^2 per-triangle permeabilities (> 0), or NULL;
+                           read during biot_assemble only                                    */
+} biot_problem;
+
+/* Multigrid options (Sec. 3, 4.3, 5.1). */
+typedef struct {
+    int levels;         /* mesh levels incl. the finest, >= 2; coarsest n >> (levels-1) >= 2 */
+    int smoother;       /* BIOT_SMOOTHER_VANKA or BIOT_SMOOTHER_BSR                          */
+    int nu1, nu2;       /* pre / post smoothing steps, 0..16                                 */
+    double omega;       /* outer relaxation weight (Vanka and BSR)                           */
+    double omega_J;     /* BSR: weighted-Jacobi weight on the approximate Schur complement   */
+    int precision;      /* BIOT_PREC_FP64 or BIOT_PREC_FP32_SMOOTHER                         */
+} biot_mg_opts;
+
+/* FGMRES controls (in) and results (out). */
+typedef struct {
+    double tol;         /* in: stop when ||b - A x||_2 <= tol ||b||_2 (true residual)       */
+    int restart;        /* in: Krylov dimension m per cycle, 1..200                          */
+    int maxit;          /* in: maximum total FGMRES iterations                               */
+    int iters;          /* out: iterations performed                                         */
+    int converged;      /* out: 1 if the tolerance was met                                   */
+    double rel_res_true;/* out: ||b - A x||_2 / ||b||_2 recomputed in FP64 at the end        */
+} biot_solve_info;
+
+/* Assemble the rediscretized operator on the finest mesh (Sec. 2.3, block_form_rq):
+ * validates `prob`, allocates the context, uploads the stencil of the element matrices
+ * and the per-triangle 1/K.  Returns the context in *out (NULL on failure). */
+int biot_assemble(const biot_problem* prob, void* stream, biot_ctx** out);
+
+/* Build the multigrid hierarchy (Sec. 3): per-level rediscretized operators with 1/K
+ * averaged over the four children of each coarse triangle, transfer tables, Vanka /
+ * BSR patch data, dense inverse of the coarsest operator (Sec. 5.1).  May be called
+ * again with other options. */
+int biot_setup_hierarchy(biot_ctx* ctx, const biot_mg_opts* opts, void* stream);
+
+/* z = M^{-1} r: one V(nu1, nu2) cycle from a zero initial guess on the finest level.
+ * r and z: device FP64, canonical order of the finest level; may not alias. */
+int biot_vcycle(biot_ctx* ctx, const double* r, double* z, void* stream);
+
+/* Solve A x = b by FGMRES preconditioned with biot_vcycle (Sec. 5.1), x0 = 0.
+ * b, x: device FP64, canonical order, may not alias.  info: host pointer (in/out).
+ * Returns BIOT_OK, BIOT_NOT_CONVERGED (x = last iterate) or an error code. */
+int biot_solve(biot_ctx* ctx, const double* b, double* x, biot_solve_info* info, void* stream);
+
+/* y = A_l x on mesh level l (0 = finest): the rediscretized operator (block_form_rq). */
+int biot_apply_operator(biot_ctx* ctx, int level, const double* x, double* y, void* stream);
+
+/* One relaxation step on level l: x <- x + omega M_l^{-1} (b - A_l x) with the smoother
+ * chosen in setup (Vanka: Sec. 3.2.1; BSR: Sec. 3.2.2).  x is updated in place. */
+int biot_smooth(biot_ctx* ctx, int level, double* x, const double* b, void* stream);
+
+/* r_c = P_l^T r_f: restriction from level l to level l+1 (Sec. 3, eq. block_interp). */
+int biot_restrict(biot_ctx* ctx, int level, const double* r_f, double* r_c, void* stream);
+
+/* x_f += P_l x_c: prolongation from level l+1 to level l, divergence preserving for u
+ * (Sec. 3.1). */
+int biot_prolong_add(biot_ctx* ctx, int level, const double* x_c, double* x_f, void* stream);
+
+/* Re-assemble for new per-triangle permeabilities (device pointer, 2 n^2 values > 0):
+ * updates 1/K on every level, the patch data and the coarsest inverse.  The hierarchy
+ * options stay. */
+int biot_update_K(biot_ctx* ctx, const double* K_tri, void* stream);
+
+/* Per-triangle gradient of lambda^T A x with respect to theta_T = ln K_T, negated:
+ *   g_T = -lam^T (dA/dtheta_T) x = tau mu_f exp(-theta_T) lam_w|_T^T M_w^T(K=1) w|_T,
+ * the adjoint gradient of a loss L(x) when lam solves A lam = dL/dx (A is symmetric,
+ * Sec. 2.1).  x, lam: canonical finest-level vectors; g_tri: 2 n^2 outputs. */
+int biot_grad_logK(biot_ctx* ctx, const double* x, const double* lam, double* g_tri, void* stream);
+
+/* Layout export (host memory).  counts (optional, 12 ints): [n, n_free, 10 block sizes].
+ * patch_table (optional, host, ((n+1)^2 - 2) x 20 ints): the 20-slot Vanka patch of every
+ * vertex except (0,0) and (n,n), vertices in row-major (j, i) order, slots
+ *   [ux(v), uy(v), b on H(i-1,j), H(i,j), V(i,j-1), V(i,j), D(i-1,j), D(i,j-1),
+ *    w on the same six edges, p on L(i,j), L(i-1,j), L(i,j-1), U(i-1,j-1), U(i-1,j), U(i,j-1)]
+ * holding canonical indices, -1 for absent or eliminated DoFs.  Computed on the device by
+ * the same index arithmetic the Vanka kernels use.  Synchronizes the stream. */
+int biot_export_layout(biot_ctx* ctx, int* counts, int* patch_table, void* stream);
+
+/* Free every device allocation of the context (NULL is ignored). */
+void biot_destroy(biot_ctx* ctx);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* biot_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BIOT_MG_H */

@@ -1,0 +1,776 @@
+// C ABI of the RQ Biot monolithic multigrid library (declared in include/biot_mg.h):
+// context lifetime, hierarchy set-up, V-cycle and FGMRES orchestration on a HIP stream.
+//
+// Paper passages: Sec. 3 (V-cycle structure, rediscretization, R = P^T), Sec. 3.2
+// (relaxation), Sec. 5.1 (FGMRES with one V-cycle as preconditioner, zero initial guess,
+// direct coarsest solve).
+#include "../../include/biot_mg.h"
+#include "common.h"
+#include "kernels.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <stdexcept>
+
+namespace biot {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+// ---- device memory helper ---------------------------------------------------------------------
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void alloc(size_t b) {
+        release();
+        if (b == 0) return;
+        hipError_t e = hipMalloc(&p, b);
+        if (e != hipSuccess) {
+            p = nullptr;
+            throw std::bad_alloc();
+        }
+        bytes = b;
+    }
+    template <typename T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+template <typename T>
+static void upload(DevBuf& d, const std::vector<T>& h, hipStream_t st) {
+    d.alloc(std::max<size_t>(1, h.size()) * sizeof(T));
+    if (!h.empty()) BIOT_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st));
+}
+
+struct Level {
+    int n = 0;
+    double h = 0;
+    Layout L{};
+    Canon C{};
+    std::vector<StencilEntry> st_host;
+    int st_off_host[NTYPES + 1];
+    DevBuf st, st_off;                  // stencil (device)
+    DevBuf kinv64, kinv32;              // 2 planes each
+    DevBuf cls64, cls32, ucls64, ucls32, wblk64, wblk32;
+    DevBuf x64, b64, r64, t64;          // FP64 work vectors (padded)
+    DevBuf x32, b32, r32;               // FP32 work vectors (padded)
+    template <typename T>
+    LevelView<T> view() const;
+};
+
+template <>
+LevelView<double> Level::view<double>() const {
+    LevelView<double> v;
+    v.L = L;
+    v.kinv = kinv64.as<double>();
+    v.st = st.as<StencilEntry>();
+    v.st_off = st_off.as<int>();
+    v.cls = cls64.as<DevPatchClass<double>>();
+    v.wblk = wblk64.as<double>();
+    v.ucls = ucls64.as<DevUPatchClass<double>>();
+    return v;
+}
+template <>
+LevelView<float> Level::view<float>() const {
+    LevelView<float> v;
+    v.L = L;
+    v.kinv = kinv32.as<float>();
+    v.st = st.as<StencilEntry>();
+    v.st_off = st_off.as<int>();
+    v.cls = cls32.as<DevPatchClass<float>>();
+    v.wblk = wblk32.as<float>();
+    v.ucls = ucls32.as<DevUPatchClass<float>>();
+    return v;
+}
+
+}  // namespace biot
+
+using namespace biot;
+
+struct biot_ctx {
+    int n = 0;
+    PhysParams phys{};
+    double K_scalar = 1.0;
+    bool have_hierarchy = false;
+    biot_mg_opts opts{};
+    std::vector<std::unique_ptr<Level>> levels;   // levels[0] always exists after assemble
+    // transfers
+    DevBuf pro, pro_off, res, res_off;
+    // coarsest level
+    int coarse_N = 0;
+    DevBuf coarse_A, coarse_inv, coarse_idx, coarse_map, status;
+    // local RT0 mass (K = 1) of L and U for the adjoint gradient
+    DevBuf mloc;
+    // Krylov workspace
+    int krylov_m = 0;
+    DevBuf V, Z, w, partial, hdev, ydev, bpad, xpad, canon_tmp;
+};
+
+namespace biot {
+
+static void check_stream_error() {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw HipError{e, "kernel launch"};
+}
+
+// ---- per-level set-up ----------------------------------------------------------------------------
+static void level_alloc(Level& lv, int n, hipStream_t st) {
+    lv.n = n;
+    lv.h = 1.0 / n;
+    lv.L = make_layout(n);
+    lv.C = make_canon(n);
+    const size_t len = (size_t)lv.L.len;
+    lv.kinv64.alloc(2 * lv.L.plane * sizeof(double));
+    lv.kinv32.alloc(2 * lv.L.plane * sizeof(float));
+    for (DevBuf* b : {&lv.x64, &lv.b64, &lv.r64, &lv.t64}) {
+        b->alloc(len * sizeof(double));
+        launch_fill(b->as<double>(), lv.L.len, 0.0, st);
+    }
+}
+
+static void level_stencil(Level& lv, const PhysParams& p, hipStream_t st) {
+    lv.st_host = build_stencil(p, lv.h);
+    std::stable_sort(lv.st_host.begin(), lv.st_host.end(),
+                     [](const StencilEntry& a, const StencilEntry& b) { return a.out_t < b.out_t; });
+    for (int t = 0; t <= NTYPES; ++t) lv.st_off_host[t] = 0;
+    for (auto& e : lv.st_host) lv.st_off_host[e.out_t + 1]++;
+    for (int t = 0; t < NTYPES; ++t) lv.st_off_host[t + 1] += lv.st_off_host[t];
+    upload(lv.st, lv.st_host, st);
+    std::vector<int> off(lv.st_off_host, lv.st_off_host + NTYPES + 1);
+    upload(lv.st_off, off, st);
+}
+
+template <typename T>
+static std::vector<DevPatchClass<T>> convert_classes(const PatchClass* c) {
+    std::vector<DevPatchClass<T>> out(9);
+    for (int k = 0; k < 9; ++k) {
+        for (int a = 0; a < 8; ++a)
+            for (int b = 0; b < 8; ++b) out[k].Ainv[a][b] = (T)c[k].Ainv[a][b];
+        for (int a = 0; a < 8; ++a)
+            for (int q = 0; q < 6; ++q) out[k].H[a][q] = (T)c[k].H[a][q];
+        for (int q = 0; q < 6; ++q) {
+            for (int r = 0; r < 6; ++r) {
+                out[k].G[q][r] = (T)c[k].G[q][r];
+                out[k].Q[q][r] = (T)c[k].Q[q][r];
+            }
+            out[k].c[q] = (T)c[k].c[q];
+        }
+        for (int s = 0; s < PATCH; ++s) out[k].present[s] = c[k].present[s];
+    }
+    return out;
+}
+
+template <typename T>
+static std::vector<DevUPatchClass<T>> convert_uclasses(const UPatchClass* c) {
+    std::vector<DevUPatchClass<T>> out(9);
+    for (int k = 0; k < 9; ++k) {
+        for (int a = 0; a < 8; ++a)
+            for (int b = 0; b < 8; ++b) out[k].Ainv[a][b] = (T)c[k].Ainv[a][b];
+        for (int s = 0; s < 8; ++s) out[k].present[s] = c[k].present[s];
+    }
+    return out;
+}
+
+static void level_patch_data(Level& lv, hipStream_t st) {
+    PatchClass cls[9];
+    std::vector<WEntry> we;
+    build_patch_classes(lv.st_host, lv.n, cls, we);
+    std::vector<double> wblk(24, 0.0);
+    for (auto& e : we) {
+        bool placed = false;
+        for (int p = 0; p < 2 && !placed; ++p)
+            for (int q = 0; q < 2 && !placed; ++q)
+                if (star_wpair(e.k, p) == e.a && star_wpair(e.k, q) == e.b) {
+                    wblk[(e.k * 2 + p) * 2 + q] += e.coef;
+                    placed = true;
+                }
+        if (!placed) throw std::runtime_error("RT0 mass entry does not match the star edge pairs");
+    }
+    upload(lv.cls64, convert_classes<double>(cls), st);
+    upload(lv.cls32, convert_classes<float>(cls), st);
+    upload(lv.wblk64, wblk, st);
+    std::vector<float> wf(wblk.begin(), wblk.end());
+    upload(lv.wblk32, wf, st);
+    UPatchClass ucls[9];
+    build_upatch_classes(lv.st_host, lv.n, ucls);
+    upload(lv.ucls64, convert_uclasses<double>(ucls), st);
+    upload(lv.ucls32, convert_uclasses<float>(ucls), st);
+}
+
+static void levels_kinv(biot_ctx* c, const double* K_tri, hipStream_t st) {
+    Level& l0 = *c->levels[0];
+    launch_kinv_from_K(K_tri, c->K_scalar, l0.kinv64.as<double>(), l0.L, st);
+    for (size_t l = 1; l < c->levels.size(); ++l)
+        launch_kinv_coarsen(c->levels[l - 1]->kinv64.as<double>(), c->levels[l - 1]->L,
+                            c->levels[l]->kinv64.as<double>(), c->levels[l]->L, st);
+    for (auto& lv : c->levels) launch_convert(lv->kinv64.as<double>(), lv->kinv32.as<float>(), 2 * lv->L.plane, st);
+}
+
+static void coarse_setup(biot_ctx* c, hipStream_t st) {
+    Level& lc = *c->levels.back();
+    const Layout& L = lc.L;
+    std::vector<int> idx, map((size_t)L.len, -1);
+    for (int t = 0; t < NTYPES; ++t)
+        for (int j = 0; j <= L.n; ++j)
+            for (int i = 0; i <= L.n; ++i)
+                if (dof_free(t, i, j, L.n)) {
+                    long long p = t * L.plane + slot_index(L, i, j);
+                    map[(size_t)p] = (int)idx.size();
+                    idx.push_back((int)p);
+                }
+    const int N = (int)idx.size();
+    c->coarse_N = N;
+    upload(c->coarse_idx, idx, st);
+    upload(c->coarse_map, map, st);
+    c->coarse_A.alloc((size_t)N * N * sizeof(double));
+    c->coarse_inv.alloc((size_t)N * N * sizeof(double));
+    c->status.alloc(sizeof(int));
+}
+
+static void coarse_factor(biot_ctx* c, hipStream_t st) {
+    Level& lc = *c->levels.back();
+    const int N = c->coarse_N;
+    launch_coarse_matrix(lc.L, lc.st.as<StencilEntry>(), lc.st_off.as<int>(), lc.kinv64.as<double>(),
+                         c->coarse_idx.as<int>(), c->coarse_map.as<int>(), N, c->coarse_A.as<double>(), st);
+    launch_gauss_jordan(c->coarse_A.as<double>(), c->coarse_inv.as<double>(), N, c->status.as<int>(), st);
+    check_stream_error();
+    int status = 0;
+    BIOT_HIP(hipMemcpyAsync(&status, c->status.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    BIOT_HIP(hipStreamSynchronize(st));
+    if (status != 0) throw SingularError{"coarsest-level operator is singular"};
+}
+
+// ---- V-cycle -----------------------------------------------------------------------------------------
+template <typename T>
+struct VecSet;
+template <>
+struct VecSet<double> {
+    static double* x(Level& l) { return l.x64.as<double>(); }
+    static double* b(Level& l) { return l.b64.as<double>(); }
+    static double* r(Level& l) { return l.r64.as<double>(); }
+};
+template <>
+struct VecSet<float> {
+    static float* x(Level& l) { return l.x32.as<float>(); }
+    static float* b(Level& l) { return l.b32.as<float>(); }
+    static float* r(Level& l) { return l.r32.as<float>(); }
+};
+
+template <typename T>
+static void smooth_step(biot_ctx* c, int l, T* x, const T* b, T* r, bool x_is_zero, hipStream_t st) {
+    Level& lv = *c->levels[l];
+    LevelView<T> v = lv.view<T>();
+    const T om = (T)c->opts.omega;
+    if (c->opts.smoother == BIOT_SMOOTHER_VANKA) {
+        const T* rr = b;
+        if (!x_is_zero) {
+            launch_apply<T>(v, x, b, r, 1, st);
+            rr = r;
+        }
+        launch_vanka<T>(v, rr, x, om, x_is_zero ? 1 : 0, st);
+    } else {
+        throw ArgError{"smoother not available in this build"};
+    }
+}
+
+template <typename T>
+static void vcycle_level(biot_ctx* c, int l, hipStream_t st) {
+    Level& lv = *c->levels[l];
+    T* x = VecSet<T>::x(lv);
+    T* b = VecSet<T>::b(lv);
+    T* r = VecSet<T>::r(lv);
+    if (l == (int)c->levels.size() - 1) {
+        launch_coarse_solve<T>(c->coarse_inv.as<double>(), c->coarse_N, c->coarse_idx.as<int>(), b, x, st);
+        return;
+    }
+    Level& lc = *c->levels[l + 1];
+    for (int s = 0; s < c->opts.nu1; ++s) smooth_step<T>(c, l, x, b, r, s == 0, st);
+    if (c->opts.nu1 == 0) launch_fill(x, lv.L.len, (T)0, st);
+    launch_apply<T>(lv.view<T>(), x, b, r, 1, st);
+    launch_restrict<T>(lv.L, lc.L, r, VecSet<T>::b(lc), c->res.as<RestrictEntry>(), c->res_off.as<int>(), st);
+    vcycle_level<T>(c, l + 1, st);
+    launch_prolong_add<T>(lv.L, lc.L, VecSet<T>::x(lc), x, c->pro.as<ProlongEntry>(), c->pro_off.as<int>(), st);
+    for (int s = 0; s < c->opts.nu2; ++s) smooth_step<T>(c, l, x, b, r, false, st);
+}
+
+// z = M^{-1} v on padded FP64 vectors of level 0 (v is not modified).
+static void precond(biot_ctx* c, const double* v, double* z, hipStream_t st) {
+    Level& l0 = *c->levels[0];
+    if (c->opts.precision == BIOT_PREC_FP64) {
+        BIOT_HIP(hipMemcpyAsync(l0.b64.p, v, l0.L.len * sizeof(double), hipMemcpyDeviceToDevice, st));
+        vcycle_level<double>(c, 0, st);
+        BIOT_HIP(hipMemcpyAsync(z, l0.x64.p, l0.L.len * sizeof(double), hipMemcpyDeviceToDevice, st));
+    } else {
+        launch_convert(v, l0.b32.as<float>(), l0.L.len, st);
+        vcycle_level<float>(c, 0, st);
+        launch_convert(l0.x32.as<float>(), z, l0.L.len, st);
+    }
+}
+
+static void alloc_fp32(biot_ctx* c, hipStream_t st) {
+    for (auto& lp : c->levels) {
+        Level& lv = *lp;
+        if (lv.x32.p) continue;
+        for (DevBuf* b : {&lv.x32, &lv.b32, &lv.r32}) {
+            b->alloc((size_t)lv.L.len * sizeof(float));
+            launch_fill(b->as<float>(), lv.L.len, 0.0f, st);
+        }
+    }
+}
+
+// ---- FGMRES (Sec. 5.1), CGS2 Arnoldi, host Givens rotations ---------------------------------------
+static double dot_dev(biot_ctx* c, const double* a, const double* b, long long n, hipStream_t st) {
+    launch_multidot(a, n, 1, b, n, c->partial.as<double>(), RED_BLOCKS, st);
+    launch_reduce_partials(c->partial.as<double>(), RED_BLOCKS, 1, c->hdev.as<double>(), 0, st);
+    double h = 0;
+    BIOT_HIP(hipMemcpyAsync(&h, c->hdev.p, sizeof(double), hipMemcpyDeviceToHost, st));
+    BIOT_HIP(hipStreamSynchronize(st));
+    return h;
+}
+
+static void krylov_alloc(biot_ctx* c, int m) {
+    if (c->krylov_m >= m) return;
+    const Layout& L = c->levels[0]->L;
+    c->V.alloc((size_t)(m + 1) * L.len * sizeof(double));
+    c->Z.alloc((size_t)m * L.len * sizeof(double));
+    c->w.alloc((size_t)L.len * sizeof(double));
+    c->partial.alloc((size_t)RED_BLOCKS * (m + 2) * sizeof(double));
+    c->hdev.alloc((size_t)(2 * m + 4) * sizeof(double));
+    c->ydev.alloc((size_t)(m + 1) * sizeof(double));
+    c->bpad.alloc((size_t)L.len * sizeof(double));
+    c->xpad.alloc((size_t)L.len * sizeof(double));
+    c->krylov_m = m;
+}
+
+static int fgmres(biot_ctx* c, const double* b_canon, double* x_canon, biot_solve_info* info, hipStream_t st) {
+    Level& l0 = *c->levels[0];
+    const Layout& L = l0.L;
+    const long long n = L.len;
+    const int m = info->restart;
+    krylov_alloc(c, m);
+    double* V = c->V.as<double>();
+    double* Z = c->Z.as<double>();
+    double* w = c->w.as<double>();
+    double* b = c->bpad.as<double>();
+    double* x = c->xpad.as<double>();
+    double* hd = c->hdev.as<double>();
+    double* part = c->partial.as<double>();
+    launch_pack(b_canon, b, L, l0.C, st);
+    launch_fill(x, n, 0.0, st);
+    const double bnorm = std::sqrt(dot_dev(c, b, b, n, st));
+    info->iters = 0;
+    info->converged = 0;
+    info->rel_res_true = 0;
+    if (!(bnorm == bnorm) || std::isinf(bnorm)) throw std::domain_error("NaN/Inf in right-hand side");
+    if (bnorm == 0.0) {
+        launch_unpack(x, x_canon, L, l0.C, st);
+        info->converged = 1;
+        return BIOT_OK;
+    }
+    const double tol = info->tol;
+    // r = b - A x  (x = 0 -> r = b)
+    BIOT_HIP(hipMemcpyAsync(w, b, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    double beta = bnorm;
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2), y(m);
+    int it = 0;
+    while (true) {
+        if (beta <= tol * bnorm) {
+            info->converged = 1;
+            break;
+        }
+        if (it >= info->maxit) break;
+        // V_0 = r / beta
+        launch_scale(V, w, n, 1.0 / beta, st);
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int k = 0;
+        bool stop = false;
+        for (int j = 0; j < m; ++j) {
+            double* vj = V + (size_t)j * n;
+            double* zj = Z + (size_t)j * n;
+            precond(c, vj, zj, st);
+            launch_apply<double>(l0.view<double>(), zj, nullptr, w, 0, st);
+            // CGS2: two passes of classical Gram-Schmidt
+            launch_multidot(V, n, j + 1, w, n, part, RED_BLOCKS, st);
+            launch_reduce_partials(part, RED_BLOCKS, j + 1, hd, 0, st);
+            launch_update(w, V, n, j + 1, hd, n, st);
+            launch_multidot(V, n, j + 1, w, n, part, RED_BLOCKS, st);
+            launch_reduce_partials(part, RED_BLOCKS, j + 1, hd + m + 1, 0, st);
+            launch_update(w, V, n, j + 1, hd + m + 1, n, st);
+            launch_multidot(w, n, 1, w, n, part, RED_BLOCKS, st);
+            launch_reduce_partials(part, RED_BLOCKS, 1, hd + 2 * m + 2, 0, st);
+            launch_scale_inv_sqrt(V + (size_t)(j + 1) * n, w, n, hd + 2 * m + 2, st);
+            check_stream_error();
+            std::vector<double> hh(2 * m + 3);
+            BIOT_HIP(hipMemcpyAsync(hh.data(), hd, (2 * m + 3) * sizeof(double), hipMemcpyDeviceToHost, st));
+            BIOT_HIP(hipStreamSynchronize(st));
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[m + 1 + i];
+            const double hn = std::sqrt(hh[2 * m + 2]);
+            H[(size_t)(j + 1) * m + j] = hn;
+            for (int i = 0; i <= j + 1; ++i)
+                if (!(H[(size_t)i * m + j] == H[(size_t)i * m + j])) throw std::domain_error("NaN in Arnoldi");
+            for (int i = 0; i < j; ++i) {
+                const double a = H[(size_t)i * m + j], bb = H[(size_t)(i + 1) * m + j];
+                H[(size_t)i * m + j] = cs[i] * a + sn[i] * bb;
+                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
+            }
+            const double a = H[(size_t)j * m + j], bb = H[(size_t)(j + 1) * m + j];
+            const double den = std::hypot(a, bb);
+            cs[j] = a / den;
+            sn[j] = bb / den;
+            H[(size_t)j * m + j] = den;
+            H[(size_t)(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++it;
+            k = j + 1;
+            if (std::fabs(g[j + 1]) <= tol * bnorm || it >= info->maxit || hn == 0.0) {
+                stop = true;
+                break;
+            }
+        }
+        (void)stop;
+        // y = H^{-1} g (upper triangular k x k), x += Z y
+        for (int i = k - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int q = i + 1; q < k; ++q) s -= H[(size_t)i * m + q] * y[q];
+            y[i] = s / H[(size_t)i * m + i];
+        }
+        BIOT_HIP(hipMemcpyAsync(c->ydev.p, y.data(), k * sizeof(double), hipMemcpyHostToDevice, st));
+        launch_lincomb_add(x, Z, n, k, c->ydev.as<double>(), n, st);
+        // true residual
+        launch_apply<double>(l0.view<double>(), x, b, w, 1, st);
+        beta = std::sqrt(dot_dev(c, w, w, n, st));
+        if (!(beta == beta)) throw std::domain_error("NaN in residual");
+    }
+    info->iters = it;
+    info->rel_res_true = beta / bnorm;
+    launch_unpack(x, x_canon, L, l0.C, st);
+    check_stream_error();
+    return info->converged ? BIOT_OK : BIOT_NOT_CONVERGED;
+}
+
+}  // namespace biot
+
+// =================================================================================================
+// C ABI
+// =================================================================================================
+template <typename F>
+static int guarded(F&& f) {
+    try {
+        return f();
+    } catch (const ArgError& e) {
+        set_error(e.msg);
+        return BIOT_ERR_ARG;
+    } catch (const SingularError& e) {
+        set_error(e.msg);
+        return BIOT_ERR_SINGULAR;
+    } catch (const HipError& e) {
+        set_error(std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e));
+        return BIOT_ERR_HIP;
+    } catch (const std::bad_alloc&) {
+        (void)hipGetLastError();
+        set_error("device or host allocation failed");
+        return BIOT_ERR_OOM;
+    } catch (const std::domain_error& e) {
+        set_error(e.what());
+        return BIOT_ERR_NAN;
+    } catch (const std::exception& e) {
+        set_error(e.what());
+        return BIOT_ERR_ARG;
+    } catch (...) {
+        set_error("unknown failure");
+        return BIOT_ERR_ARG;
+    }
+}
+
+static hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
+
+static void require(bool ok, const char* msg) {
+    if (!ok) throw ArgError{msg};
+}
+
+static void require_ctx(biot_ctx* c) { require(c != nullptr, "null context"); }
+
+static void require_hierarchy(biot_ctx* c) {
+    require_ctx(c);
+    require(c->have_hierarchy, "biot_setup_hierarchy has not been called");
+}
+
+static void require_level(biot_ctx* c, int level) {
+    require_ctx(c);
+    require(level >= 0 && level < (int)c->levels.size(), "level out of range");
+}
+
+extern "C" {
+
+int biot_assemble(const biot_problem* prob, void* stream, biot_ctx** out) {
+    if (out) *out = nullptr;
+    return guarded([&]() {
+        require(prob != nullptr && out != nullptr, "null argument");
+        const int n = prob->n;
+        require(n >= 4 && n <= 8192 && (n & (n - 1)) == 0, "n must be a power of two in [4, 8192]");
+        require(prob->mu > 0 && prob->lambda >= 0, "need mu > 0 and lambda >= 0");
+        require(prob->inv_M > 0 && std::isfinite(prob->inv_M), "need 0 < 1/M < inf");
+        require(prob->mu_f > 0 && prob->tau > 0, "need mu_f > 0 and tau > 0");
+        require(std::isfinite(prob->alpha) && std::isfinite(prob->lambda) && std::isfinite(prob->mu),
+                "non-finite parameter");
+        require(prob->K_tri != nullptr || prob->K_scalar > 0, "need K_scalar > 0 when K_tri is NULL");
+        std::unique_ptr<biot_ctx> c(new biot_ctx);
+        c->n = n;
+        c->phys = PhysParams{prob->lambda, prob->mu, prob->alpha, prob->inv_M, prob->mu_f, prob->tau};
+        c->K_scalar = prob->K_scalar;
+        hipStream_t st = S(stream);
+        c->levels.emplace_back(new Level);
+        level_alloc(*c->levels[0], n, st);
+        level_stencil(*c->levels[0], c->phys, st);
+        launch_kinv_from_K(prob->K_tri, prob->K_scalar, c->levels[0]->kinv64.as<double>(), c->levels[0]->L, st);
+        launch_convert(c->levels[0]->kinv64.as<double>(), c->levels[0]->kinv32.as<float>(),
+                       2 * c->levels[0]->L.plane, st);
+        // local RT0 mass blocks for the adjoint: the K-tagged stencil entries of one triangle
+        {
+            std::vector<double> m(18, 0.0);
+            // L(i,j): local order D(i,j), V(i,j), H(i,j); U(i,j): H(i,j+1), D(i,j), V(i+1,j)
+            const int tl[3] = {T_WD, T_WV, T_WH}, tu[3] = {T_WH, T_WD, T_WV};
+            const int lo_i[2][3] = {{0, 0, 0}, {0, 0, 1}}, lo_j[2][3] = {{0, 0, 0}, {1, 0, 0}};
+            for (int u = 0; u < 2; ++u)
+                for (int a = 0; a < 3; ++a)
+                    for (int bq = 0; bq < 3; ++bq) {
+                        const int ta = u ? tu[a] : tl[a], tb = u ? tu[bq] : tl[bq];
+                        for (auto& e : c->levels[0]->st_host) {
+                            if (e.ktri != u || e.out_t != ta || e.in_t != tb) continue;
+                            // entry anchored at row slot s_a; triangle at s_a + (kdi, kdj) must be (0,0)
+                            if (lo_i[u][a] + e.kdi != 0 || lo_j[u][a] + e.kdj != 0) continue;
+                            if (e.di != lo_i[u][bq] - lo_i[u][a] || e.dj != lo_j[u][bq] - lo_j[u][a]) continue;
+                            m[u * 9 + a * 3 + bq] += e.coef;
+                        }
+                    }
+            upload(c->mloc, m, st);
+        }
+        check_stream_error();
+        BIOT_HIP(hipStreamSynchronize(st));
+        *out = c.release();
+        return BIOT_OK;
+    });
+}
+
+int biot_setup_hierarchy(biot_ctx* c, const biot_mg_opts* o, void* stream) {
+    return guarded([&]() {
+        require_ctx(c);
+        require(o != nullptr, "null options");
+        require(o->levels >= 2, "need at least 2 levels");
+        require((c->n >> (o->levels - 1)) >= 2 && ((c->n >> (o->levels - 1)) << (o->levels - 1)) == c->n,
+                "coarsest mesh n >> (levels-1) must be >= 2");
+        require(o->smoother == BIOT_SMOOTHER_VANKA || o->smoother == BIOT_SMOOTHER_BSR, "unknown smoother");
+        require(o->nu1 >= 0 && o->nu1 <= 16 && o->nu2 >= 0 && o->nu2 <= 16 && o->nu1 + o->nu2 >= 1,
+                "nu1, nu2 in [0, 16], nu1 + nu2 >= 1");
+        require(o->precision == BIOT_PREC_FP64 || o->precision == BIOT_PREC_FP32_SMOOTHER, "unknown precision");
+        require(std::isfinite(o->omega) && o->omega > 0, "omega must be positive");
+        const int nc = c->n >> (o->levels - 1);
+        require(nc <= 16, "coarsest mesh must have at most 16 cells per side (dense direct solve)");
+        hipStream_t st = S(stream);
+        c->have_hierarchy = false;
+        // (re)build levels 1..L-1
+        c->levels.resize(1);
+        for (int l = 1; l < o->levels; ++l) {
+            c->levels.emplace_back(new Level);
+            level_alloc(*c->levels[l], c->n >> l, st);
+            level_stencil(*c->levels[l], c->phys, st);
+        }
+        for (auto& lv : c->levels) level_patch_data(*lv, st);
+        std::vector<ProlongEntry> pro;
+        std::vector<RestrictEntry> res;
+        build_transfer_tables(pro, res);
+        std::vector<int> poff(41, 0), roff(NTYPES + 1, 0);
+        for (auto& e : pro) poff[(e.t_f * 2 + e.pi) * 2 + e.pj + 1]++;
+        for (int g = 0; g < 40; ++g) poff[g + 1] += poff[g];
+        for (auto& e : res) roff[e.t_c + 1]++;
+        for (int t = 0; t < NTYPES; ++t) roff[t + 1] += roff[t];
+        upload(c->pro, pro, st);
+        upload(c->pro_off, poff, st);
+        upload(c->res, res, st);
+        upload(c->res_off, roff, st);
+        for (size_t l = 1; l < c->levels.size(); ++l)
+            launch_kinv_coarsen(c->levels[l - 1]->kinv64.as<double>(), c->levels[l - 1]->L,
+                                c->levels[l]->kinv64.as<double>(), c->levels[l]->L, st);
+        for (auto& lv : c->levels)
+            launch_convert(lv->kinv64.as<double>(), lv->kinv32.as<float>(), 2 * lv->L.plane, st);
+        c->opts = *o;
+        if (o->precision == BIOT_PREC_FP32_SMOOTHER) alloc_fp32(c, st);
+        coarse_setup(c, st);
+        coarse_factor(c, st);
+        check_stream_error();
+        BIOT_HIP(hipStreamSynchronize(st));
+        c->have_hierarchy = true;
+        return BIOT_OK;
+    });
+}
+
+int biot_vcycle(biot_ctx* c, const double* r, double* z, void* stream) {
+    return guarded([&]() {
+        require_hierarchy(c);
+        require(r && z && r != z, "r and z must be distinct non-null device pointers");
+        hipStream_t st = S(stream);
+        Level& l0 = *c->levels[0];
+        launch_pack(r, l0.t64.as<double>(), l0.L, l0.C, st);
+        precond(c, l0.t64.as<double>(), l0.t64.as<double>(), st);
+        launch_unpack(l0.t64.as<double>(), z, l0.L, l0.C, st);
+        check_stream_error();
+        return BIOT_OK;
+    });
+}
+
+int biot_solve(biot_ctx* c, const double* b, double* x, biot_solve_info* info, void* stream) {
+    return guarded([&]() {
+        require_hierarchy(c);
+        require(b && x && b != x, "b and x must be distinct non-null device pointers");
+        require(info != nullptr, "null info");
+        require(info->restart >= 1 && info->restart <= 200, "restart in [1, 200]");
+        require(info->maxit >= 0, "maxit >= 0");
+        require(info->tol >= 0 && std::isfinite(info->tol), "tol >= 0");
+        return fgmres(c, b, x, info, S(stream));
+    });
+}
+
+int biot_apply_operator(biot_ctx* c, int level, const double* x, double* y, void* stream) {
+    return guarded([&]() {
+        require_level(c, level);
+        require(x && y && x != y, "x and y must be distinct non-null device pointers");
+        hipStream_t st = S(stream);
+        Level& lv = *c->levels[level];
+        launch_pack(x, lv.t64.as<double>(), lv.L, lv.C, st);
+        launch_apply<double>(lv.view<double>(), lv.t64.as<double>(), nullptr, lv.r64.as<double>(), 0, st);
+        launch_unpack(lv.r64.as<double>(), y, lv.L, lv.C, st);
+        check_stream_error();
+        return BIOT_OK;
+    });
+}
+
+int biot_smooth(biot_ctx* c, int level, double* x, const double* b, void* stream) {
+    return guarded([&]() {
+        require_hierarchy(c);
+        require_level(c, level);
+        require(level < (int)c->levels.size() - 1, "no smoother on the coarsest level");
+        require(x && b && (const double*)x != b, "x and b must be distinct non-null device pointers");
+        hipStream_t st = S(stream);
+        Level& lv = *c->levels[level];
+        launch_pack(x, lv.x64.as<double>(), lv.L, lv.C, st);
+        launch_pack(b, lv.b64.as<double>(), lv.L, lv.C, st);
+        if (c->opts.precision == BIOT_PREC_FP64) {
+            smooth_step<double>(c, level, lv.x64.as<double>(), lv.b64.as<double>(), lv.r64.as<double>(), false, st);
+        } else {
+            launch_convert(lv.x64.as<double>(), lv.x32.as<float>(), lv.L.len, st);
+            launch_convert(lv.b64.as<double>(), lv.b32.as<float>(), lv.L.len, st);
+            smooth_step<float>(c, level, lv.x32.as<float>(), lv.b32.as<float>(), lv.r32.as<float>(), false, st);
+            launch_convert(lv.x32.as<float>(), lv.x64.as<double>(), lv.L.len, st);
+        }
+        launch_unpack(lv.x64.as<double>(), x, lv.L, lv.C, st);
+        check_stream_error();
+        return BIOT_OK;
+    });
+}
+
+int biot_restrict(biot_ctx* c, int level, const double* r_f, double* r_c, void* stream) {
+    return guarded([&]() {
+        require_hierarchy(c);
+        require_level(c, level);
+        require(level + 1 < (int)c->levels.size(), "no coarser level");
+        require(r_f && r_c, "null pointer");
+        hipStream_t st = S(stream);
+        Level& lf = *c->levels[level];
+        Level& lc = *c->levels[level + 1];
+        launch_pack(r_f, lf.t64.as<double>(), lf.L, lf.C, st);
+        launch_restrict<double>(lf.L, lc.L, lf.t64.as<double>(), lc.t64.as<double>(), c->res.as<RestrictEntry>(),
+                                c->res_off.as<int>(), st);
+        launch_unpack(lc.t64.as<double>(), r_c, lc.L, lc.C, st);
+        check_stream_error();
+        return BIOT_OK;
+    });
+}
+
+int biot_prolong_add(biot_ctx* c, int level, const double* x_c, double* x_f, void* stream) {
+    return guarded([&]() {
+        require_hierarchy(c);
+        require_level(c, level);
+        require(level + 1 < (int)c->levels.size(), "no coarser level");
+        require(x_c && x_f, "null pointer");
+        hipStream_t st = S(stream);
+        Level& lf = *c->levels[level];
+        Level& lc = *c->levels[level + 1];
+        launch_pack(x_c, lc.t64.as<double>(), lc.L, lc.C, st);
+        launch_pack(x_f, lf.t64.as<double>(), lf.L, lf.C, st);
+        launch_prolong_add<double>(lf.L, lc.L, lc.t64.as<double>(), lf.t64.as<double>(), c->pro.as<ProlongEntry>(),
+                                   c->pro_off.as<int>(), st);
+        launch_unpack(lf.t64.as<double>(), x_f, lf.L, lf.C, st);
+        check_stream_error();
+        return BIOT_OK;
+    });
+}
+
+int biot_update_K(biot_ctx* c, const double* K_tri, void* stream) {
+    return guarded([&]() {
+        require_ctx(c);
+        require(K_tri != nullptr, "null K");
+        hipStream_t st = S(stream);
+        levels_kinv(c, K_tri, st);
+        if (c->have_hierarchy) coarse_factor(c, st);
+        check_stream_error();
+        return BIOT_OK;
+    });
+}
+
+int biot_grad_logK(biot_ctx* c, const double* x, const double* lam, double* g_tri, void* stream) {
+    return guarded([&]() {
+        require_ctx(c);
+        require(x && lam && g_tri, "null pointer");
+        hipStream_t st = S(stream);
+        Level& l0 = *c->levels[0];
+        launch_pack(x, l0.t64.as<double>(), l0.L, l0.C, st);
+        launch_pack(lam, l0.r64.as<double>(), l0.L, l0.C, st);
+        launch_grad_logK(l0.L, l0.t64.as<double>(), l0.r64.as<double>(), l0.kinv64.as<double>(),
+                         c->mloc.as<double>(), g_tri, st);
+        check_stream_error();
+        return BIOT_OK;
+    });
+}
+
+int biot_export_layout(biot_ctx* c, int* counts, int* patch_table, void* stream) {
+    return guarded([&]() {
+        require_ctx(c);
+        hipStream_t st = S(stream);
+        Level& l0 = *c->levels[0];
+        if (counts) {
+            counts[0] = c->n;
+            counts[1] = (int)l0.C.off[NTYPES];
+            for (int t = 0; t < NTYPES; ++t) counts[2 + t] = (int)l0.C.size[t];
+        }
+        if (patch_table) {
+            const size_t rows = (size_t)(c->n + 1) * (c->n + 1) - 2;
+            DevBuf d;
+            d.alloc(rows * PATCH * sizeof(int));
+            launch_patch_table(l0.L, l0.C, d.as<int>(), st);
+            check_stream_error();
+            BIOT_HIP(hipMemcpyAsync(patch_table, d.p, rows * PATCH * sizeof(int), hipMemcpyDeviceToHost, st));
+            BIOT_HIP(hipStreamSynchronize(st));
+        }
+        return BIOT_OK;
+    });
+}
+
+void biot_destroy(biot_ctx* c) { delete c; }
+
+const char* biot_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

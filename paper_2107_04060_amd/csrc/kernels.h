@@ -1,0 +1,92 @@
+// Launch wrappers of the device kernels (kernels.hip).  All launches go to `st`.
+#pragma once
+#include "common.h"
+
+namespace biot {
+
+template <typename T>
+struct DevPatchClass {
+    T Ainv[8][8];
+    T H[8][6];
+    T G[6][6];
+    T Q[6][6];
+    T c[6];
+    int present[PATCH];
+};
+
+template <typename T>
+struct DevUPatchClass {
+    T Ainv[8][8];
+    int present[8];
+};
+
+
+// Device view of one mesh level.
+template <typename T>
+struct LevelView {
+    Layout L;
+    const T* kinv;                 // 2 planes: 1/K of L and U triangles (padded)
+    const StencilEntry* st;        // operator stencil
+    const int* st_off;             // NTYPES + 1 offsets into st (device)
+    const DevPatchClass<T>* cls;   // 9 Vanka classes
+    const T* wblk;                 // 6 x 2 x 2 RT0-mass blocks of the star triangles (1/K = 1)
+    const DevUPatchClass<T>* ucls; // 9 displacement-patch classes (BSR)
+};
+
+// vector plumbing
+void launch_fill(double* x, long long n, double v, hipStream_t st);
+void launch_fill(float* x, long long n, float v, hipStream_t st);
+void launch_pack(const double* canon, double* padded, const Layout& L, const Canon& C, hipStream_t st);
+void launch_unpack(const double* padded, double* canon, const Layout& L, const Canon& C, hipStream_t st);
+void launch_convert(const double* src, float* dst, long long n, hipStream_t st);
+void launch_convert(const float* src, double* dst, long long n, hipStream_t st);
+
+// operator: y = A x (mode 0) or y = b - A x (mode 1)
+template <typename T>
+void launch_apply(const LevelView<T>& lv, const T* x, const T* b, T* y, int mode, hipStream_t st);
+
+// additive Vanka step: x <- (x_is_zero ? 0 : x) + omega * sum_l V_l^T D_l A_l^{-1} V_l r
+template <typename T>
+void launch_vanka(const LevelView<T>& lv, const T* r, T* x, T omega, int x_is_zero, hipStream_t st);
+
+// grid transfers
+template <typename T>
+void launch_restrict(const Layout& Lf, const Layout& Lc, const T* rf, T* rc, const RestrictEntry* tab,
+                     const int* off, hipStream_t st);
+template <typename T>
+void launch_prolong_add(const Layout& Lf, const Layout& Lc, const T* xc, T* xf, const ProlongEntry* tab,
+                        const int* off, hipStream_t st);
+
+// coarsest level
+template <typename T>
+void launch_coarse_solve(const double* Ainv, int N, const int* idx, const T* b, T* x, hipStream_t st);
+void launch_coarse_matrix(const Layout& L, const StencilEntry* st_tab, const int* st_off, const double* kinv,
+                          const int* free_idx, const int* free_map, int N, double* A, hipStream_t st);
+void launch_gauss_jordan(double* A, double* Inv, int N, int* status, hipStream_t st);
+
+// permeability
+void launch_kinv_from_K(const double* K_tri, double K_scalar, double* kinv, const Layout& L, hipStream_t st);
+void launch_kinv_coarsen(const double* kf, const Layout& Lf, double* kc, const Layout& Lc, hipStream_t st);
+
+// Krylov BLAS-1 (FP64)
+void launch_multidot(const double* V, long long ldv, int nv, const double* w, long long n, double* partial,
+                     int nblk, hipStream_t st);
+void launch_reduce_partials(const double* partial, int nblk, int nv, double* out, int accumulate,
+                            hipStream_t st);
+void launch_update(double* w, const double* V, long long ldv, int nv, const double* h, long long n,
+                   hipStream_t st);
+void launch_scale(double* dst, const double* src, long long n, double s, hipStream_t st);
+void launch_scale_inv_sqrt(double* dst, const double* src, long long n, const double* norm2, hipStream_t st);
+void launch_lincomb_add(double* x, const double* Z, long long ldz, int nv, const double* y, long long n,
+                        hipStream_t st);
+
+// adjoint: per-triangle  1/K_T * lam_w|_T^T  Mloc_T  w|_T  (Mloc: 2 types x 3 x 3)
+void launch_grad_logK(const Layout& L, const double* x, const double* lam, const double* kinv,
+                      const double* mloc, double* g_tri, hipStream_t st);
+
+// layout export
+void launch_patch_table(const Layout& L, const Canon& C, int* table, hipStream_t st);
+
+constexpr int RED_BLOCKS = 1024;
+
+}  // namespace biot
