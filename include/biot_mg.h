@@ -152,6 +152,15 @@ int biot_grad_logK(biot_ctx* ctx, const double* x, const double* lam, double* g_
  * the same index arithmetic the Vanka kernels use.  Synchronizes the stream. */
 int biot_export_layout(biot_ctx* ctx, int* counts, int* patch_table, void* stream);
 
+/* Kernel timing with HIP events (instrumentation, not part of the method).
+ * enable = 1: start recording an event pair around every launch of the additive-Vanka
+ *             kernel (on an iterate that is not identically zero) and of the residual
+ *             kernel on mesh level `level`; previous records are dropped.
+ * enable = 0: stop, synchronize `stream` and write out[0..3] = {total Vanka milliseconds,
+ *             number of Vanka launches, total residual milliseconds, number of residual
+ *             launches} (out: host pointer, may be NULL). */
+int biot_kernel_timing(biot_ctx* ctx, int enable, int level, double* out, void* stream);
+
 /* Free every device allocation of the context (NULL is ignored). */
 void biot_destroy(biot_ctx* ctx);
 

@@ -69,12 +69,13 @@ def load():
     lib.biot_update_K.argtypes = [P, P, P]
     lib.biot_grad_logK.argtypes = [P, P, P, P, P]
     lib.biot_export_layout.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), P]
+    lib.biot_kernel_timing.argtypes = [P, I, I, ctypes.POINTER(ctypes.c_double), P]
     lib.biot_destroy.argtypes = [P]
     lib.biot_destroy.restype = None
     lib.biot_last_error.restype = ctypes.c_char_p
     for name in ("biot_assemble", "biot_setup_hierarchy", "biot_vcycle", "biot_solve",
                  "biot_apply_operator", "biot_smooth", "biot_restrict", "biot_prolong_add",
-                 "biot_update_K", "biot_grad_logK", "biot_export_layout"):
+                 "biot_update_K", "biot_grad_logK", "biot_export_layout", "biot_kernel_timing"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -196,6 +197,14 @@ class BiotSolver:
         _check(load().biot_grad_logK(self._ctx, _dev(x, self.nf(), "x"), _dev(lam, self.nf(), "lam"),
                                      _dev(g), _stream()))
         return g
+
+    def timing_start(self, level=0):
+        _check(load().biot_kernel_timing(self._ctx, 1, int(level), None, _stream()))
+
+    def timing_stop(self, level=0):
+        out = (ctypes.c_double * 4)()
+        _check(load().biot_kernel_timing(self._ctx, 0, int(level), out, _stream()))
+        return dict(vanka_ms=out[0], vanka_launches=int(out[1]), resid_ms=out[2], resid_launches=int(out[3]))
 
     def export_layout(self, patches=True):
         counts = (ctypes.c_int * 12)()

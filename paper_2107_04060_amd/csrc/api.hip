@@ -7,6 +7,8 @@
 #include "../../include/biot_mg.h"
 #include "common.h"
 #include "kernels.h"
+#include "patch_solve.h"
+#include "structure.h"
 
 #include <algorithm>
 #include <cmath>
@@ -60,7 +62,9 @@ struct Level {
     Canon C{};
     std::vector<StencilEntry> st_host;
     int st_off_host[NTYPES + 1];
-    DevBuf st, st_off;                  // stencil (device)
+    DevBuf st, st_off;                  // stencil entry list (device; coarse matrix set-up)
+    DevBuf coef64, coef32;              // stencil coefficients in structure.h order
+    DevBuf minv64, minv32;              // deflated patch inverses for uniform K (9 x 20 x 20)
     DevBuf kinv64, kinv32;              // 2 planes each
     DevBuf cls64, cls32, ucls64, ucls32, wblk64, wblk32;
     DevBuf x64, b64, r64, t64;          // FP64 work vectors (padded)
@@ -74,11 +78,11 @@ LevelView<double> Level::view<double>() const {
     LevelView<double> v;
     v.L = L;
     v.kinv = kinv64.as<double>();
-    v.st = st.as<StencilEntry>();
-    v.st_off = st_off.as<int>();
+    v.coef = coef64.as<double>();
     v.cls = cls64.as<DevPatchClass<double>>();
     v.wblk = wblk64.as<double>();
     v.ucls = ucls64.as<DevUPatchClass<double>>();
+    v.minv = minv64.as<double>();
     return v;
 }
 template <>
@@ -86,11 +90,11 @@ LevelView<float> Level::view<float>() const {
     LevelView<float> v;
     v.L = L;
     v.kinv = kinv32.as<float>();
-    v.st = st.as<StencilEntry>();
-    v.st_off = st_off.as<int>();
+    v.coef = coef32.as<float>();
     v.cls = cls32.as<DevPatchClass<float>>();
     v.wblk = wblk32.as<float>();
     v.ucls = ucls32.as<DevUPatchClass<float>>();
+    v.minv = minv32.as<float>();
     return v;
 }
 
@@ -102,16 +106,26 @@ struct biot_ctx {
     int n = 0;
     PhysParams phys{};
     double K_scalar = 1.0;
+    bool K_uniform = true;                        // permeability is the scalar K_scalar
     bool have_hierarchy = false;
     biot_mg_opts opts{};
     std::vector<std::unique_ptr<Level>> levels;   // levels[0] always exists after assemble
-    // transfers
-    DevBuf pro, pro_off, res, res_off;
+    // transfers: prolongation weights (structure.h)
+    DevBuf pw64, pw32;
     // coarsest level
     int coarse_N = 0;
     DevBuf coarse_A, coarse_inv, coarse_idx, coarse_map, status;
     // local RT0 mass (K = 1) of L and U for the adjoint gradient
     DevBuf mloc;
+    // kernel timing (instrumentation)
+    bool prof_on = false;
+    int prof_level = 0;
+    std::vector<hipEvent_t> prof_ev[2];   // [0] Vanka, [1] residual: start/stop pairs
+    size_t prof_used[2] = {0, 0};
+    ~biot_ctx() {
+        for (auto& v : prof_ev)
+            for (auto e : v) (void)hipEventDestroy(e);
+    }
     // Krylov workspace
     int krylov_m = 0;
     DevBuf V, Z, w, partial, hdev, ydev, bpad, xpad, canon_tmp;
@@ -149,6 +163,11 @@ static void level_stencil(Level& lv, const PhysParams& p, hipStream_t st) {
     upload(lv.st, lv.st_host, st);
     std::vector<int> off(lv.st_off_host, lv.st_off_host + NTYPES + 1);
     upload(lv.st_off, off, st);
+    std::vector<double> coef(NSTENCIL);
+    build_stencil_coef(p, lv.h, coef.data());
+    upload(lv.coef64, coef, st);
+    std::vector<float> cf(coef.begin(), coef.end());
+    upload(lv.coef32, cf, st);
 }
 
 template <typename T>
@@ -182,7 +201,7 @@ static std::vector<DevUPatchClass<T>> convert_uclasses(const UPatchClass* c) {
     return out;
 }
 
-static void level_patch_data(Level& lv, hipStream_t st) {
+static void level_patch_data(Level& lv, bool uniform, double Kinv, hipStream_t st) {
     PatchClass cls[9];
     std::vector<WEntry> we;
     build_patch_classes(lv.st_host, lv.n, cls, we);
@@ -197,9 +216,29 @@ static void level_patch_data(Level& lv, hipStream_t st) {
                 }
         if (!placed) throw std::runtime_error("RT0 mass entry does not match the star edge pairs");
     }
-    upload(lv.cls64, convert_classes<double>(cls), st);
+    std::vector<DevPatchClass<double>> c64 = convert_classes<double>(cls);
+    upload(lv.cls64, c64, st);
     upload(lv.cls32, convert_classes<float>(cls), st);
     upload(lv.wblk64, wblk, st);
+    if (uniform) {
+        // deflated inverse of each class's patch matrix, column by column
+        std::vector<double> minv(9 * PATCH * PATCH, 0.0);
+        const double kv[6] = {Kinv, Kinv, Kinv, Kinv, Kinv, Kinv};
+        for (int k = 0; k < 9; ++k)
+            for (int j = 0; j < PATCH; ++j) {
+                if (!c64[k].present[j]) continue;
+                double e[PATCH] = {0}, col[PATCH];
+                e[j] = 1.0;
+                patch_solve<double>(e, c64[k], kv, wblk.data(), col, 1, false);
+                for (int a = 0; a < PATCH; ++a) minv[(k * PATCH + a) * PATCH + j] = c64[k].present[a] ? col[a] : 0.0;
+            }
+        upload(lv.minv64, minv, st);
+        std::vector<float> mf(minv.begin(), minv.end());
+        upload(lv.minv32, mf, st);
+    } else {
+        lv.minv64.release();
+        lv.minv32.release();
+    }
     std::vector<float> wf(wblk.begin(), wblk.end());
     upload(lv.wblk32, wf, st);
     UPatchClass ucls[9];
@@ -267,6 +306,26 @@ struct VecSet<float> {
     static float* r(Level& l) { return l.r32.as<float>(); }
 };
 
+// Event pair around one launch when kernel timing is on for this level (kind 0 Vanka,
+// 1 residual).  Returns the stop event to record after the launch, or nullptr.
+static hipEvent_t prof_begin(biot_ctx* c, int kind, int level, hipStream_t st) {
+    if (!c->prof_on || level != c->prof_level) return nullptr;
+    auto& pool = c->prof_ev[kind];
+    size_t& used = c->prof_used[kind];
+    while (pool.size() < used + 2) {
+        hipEvent_t e;
+        BIOT_HIP(hipEventCreate(&e));
+        pool.push_back(e);
+    }
+    BIOT_HIP(hipEventRecord(pool[used], st));
+    hipEvent_t stop = pool[used + 1];
+    used += 2;
+    return stop;
+}
+static void prof_end(hipEvent_t stop, hipStream_t st) {
+    if (stop) BIOT_HIP(hipEventRecord(stop, st));
+}
+
 template <typename T>
 static void smooth_step(biot_ctx* c, int l, T* x, const T* b, T* r, bool x_is_zero, hipStream_t st) {
     Level& lv = *c->levels[l];
@@ -275,14 +334,32 @@ static void smooth_step(biot_ctx* c, int l, T* x, const T* b, T* r, bool x_is_ze
     if (c->opts.smoother == BIOT_SMOOTHER_VANKA) {
         const T* rr = b;
         if (!x_is_zero) {
+            hipEvent_t e1 = prof_begin(c, 1, l, st);
             launch_apply<T>(v, x, b, r, 1, st);
+            prof_end(e1, st);
             rr = r;
         }
-        launch_vanka<T>(v, rr, x, om, x_is_zero ? 1 : 0, st);
+        hipEvent_t e0 = x_is_zero ? nullptr : prof_begin(c, 0, l, st);
+        if (c->K_uniform)
+            launch_vanka_uniform<T>(v, rr, x, om, x_is_zero ? 1 : 0, st);
+        else
+            launch_vanka<T>(v, rr, x, om, x_is_zero ? 1 : 0, st);
+        prof_end(e0, st);
     } else {
         throw ArgError{"smoother not available in this build"};
     }
 }
+
+template <typename T>
+struct PW;
+template <>
+struct PW<double> {
+    static const double* get(biot_ctx* c) { return c->pw64.as<double>(); }
+};
+template <>
+struct PW<float> {
+    static const float* get(biot_ctx* c) { return c->pw32.as<float>(); }
+};
 
 template <typename T>
 static void vcycle_level(biot_ctx* c, int l, hipStream_t st) {
@@ -298,9 +375,9 @@ static void vcycle_level(biot_ctx* c, int l, hipStream_t st) {
     for (int s = 0; s < c->opts.nu1; ++s) smooth_step<T>(c, l, x, b, r, s == 0, st);
     if (c->opts.nu1 == 0) launch_fill(x, lv.L.len, (T)0, st);
     launch_apply<T>(lv.view<T>(), x, b, r, 1, st);
-    launch_restrict<T>(lv.L, lc.L, r, VecSet<T>::b(lc), c->res.as<RestrictEntry>(), c->res_off.as<int>(), st);
+    launch_restrict<T>(lv.L, lc.L, r, VecSet<T>::b(lc), PW<T>::get(c), st);
     vcycle_level<T>(c, l + 1, st);
-    launch_prolong_add<T>(lv.L, lc.L, VecSet<T>::x(lc), x, c->pro.as<ProlongEntry>(), c->pro_off.as<int>(), st);
+    launch_prolong_add<T>(lv.L, lc.L, VecSet<T>::x(lc), x, PW<T>::get(c), st);
     for (int s = 0; s < c->opts.nu2; ++s) smooth_step<T>(c, l, x, b, r, false, st);
 }
 
@@ -532,6 +609,7 @@ int biot_assemble(const biot_problem* prob, void* stream, biot_ctx** out) {
         c->n = n;
         c->phys = PhysParams{prob->lambda, prob->mu, prob->alpha, prob->inv_M, prob->mu_f, prob->tau};
         c->K_scalar = prob->K_scalar;
+        c->K_uniform = (prob->K_tri == nullptr);
         hipStream_t st = S(stream);
         c->levels.emplace_back(new Level);
         level_alloc(*c->levels[0], n, st);
@@ -589,19 +667,14 @@ int biot_setup_hierarchy(biot_ctx* c, const biot_mg_opts* o, void* stream) {
             level_alloc(*c->levels[l], c->n >> l, st);
             level_stencil(*c->levels[l], c->phys, st);
         }
-        for (auto& lv : c->levels) level_patch_data(*lv, st);
-        std::vector<ProlongEntry> pro;
-        std::vector<RestrictEntry> res;
-        build_transfer_tables(pro, res);
-        std::vector<int> poff(41, 0), roff(NTYPES + 1, 0);
-        for (auto& e : pro) poff[(e.t_f * 2 + e.pi) * 2 + e.pj + 1]++;
-        for (int g = 0; g < 40; ++g) poff[g + 1] += poff[g];
-        for (auto& e : res) roff[e.t_c + 1]++;
-        for (int t = 0; t < NTYPES; ++t) roff[t + 1] += roff[t];
-        upload(c->pro, pro, st);
-        upload(c->pro_off, poff, st);
-        upload(c->res, res, st);
-        upload(c->res_off, roff, st);
+        for (auto& lv : c->levels) level_patch_data(*lv, c->K_uniform, 1.0 / c->K_scalar, st);
+        {
+            std::vector<double> w(NPWEIGHTS);
+            build_prolong_weights(w.data());
+            upload(c->pw64, w, st);
+            std::vector<float> wf(w.begin(), w.end());
+            upload(c->pw32, wf, st);
+        }
         for (size_t l = 1; l < c->levels.size(); ++l)
             launch_kinv_coarsen(c->levels[l - 1]->kinv64.as<double>(), c->levels[l - 1]->L,
                                 c->levels[l]->kinv64.as<double>(), c->levels[l]->L, st);
@@ -692,8 +765,7 @@ int biot_restrict(biot_ctx* c, int level, const double* r_f, double* r_c, void* 
         Level& lf = *c->levels[level];
         Level& lc = *c->levels[level + 1];
         launch_pack(r_f, lf.t64.as<double>(), lf.L, lf.C, st);
-        launch_restrict<double>(lf.L, lc.L, lf.t64.as<double>(), lc.t64.as<double>(), c->res.as<RestrictEntry>(),
-                                c->res_off.as<int>(), st);
+        launch_restrict<double>(lf.L, lc.L, lf.t64.as<double>(), lc.t64.as<double>(), c->pw64.as<double>(), st);
         launch_unpack(lc.t64.as<double>(), r_c, lc.L, lc.C, st);
         check_stream_error();
         return BIOT_OK;
@@ -711,8 +783,7 @@ int biot_prolong_add(biot_ctx* c, int level, const double* x_c, double* x_f, voi
         Level& lc = *c->levels[level + 1];
         launch_pack(x_c, lc.t64.as<double>(), lc.L, lc.C, st);
         launch_pack(x_f, lf.t64.as<double>(), lf.L, lf.C, st);
-        launch_prolong_add<double>(lf.L, lc.L, lc.t64.as<double>(), lf.t64.as<double>(), c->pro.as<ProlongEntry>(),
-                                   c->pro_off.as<int>(), st);
+        launch_prolong_add<double>(lf.L, lc.L, lc.t64.as<double>(), lf.t64.as<double>(), c->pw64.as<double>(), st);
         launch_unpack(lf.t64.as<double>(), x_f, lf.L, lf.C, st);
         check_stream_error();
         return BIOT_OK;
@@ -724,6 +795,7 @@ int biot_update_K(biot_ctx* c, const double* K_tri, void* stream) {
         require_ctx(c);
         require(K_tri != nullptr, "null K");
         hipStream_t st = S(stream);
+        c->K_uniform = false;
         levels_kinv(c, K_tri, st);
         if (c->have_hierarchy) coarse_factor(c, st);
         check_stream_error();
@@ -765,6 +837,36 @@ int biot_export_layout(biot_ctx* c, int* counts, int* patch_table, void* stream)
             BIOT_HIP(hipMemcpyAsync(patch_table, d.p, rows * PATCH * sizeof(int), hipMemcpyDeviceToHost, st));
             BIOT_HIP(hipStreamSynchronize(st));
         }
+        return BIOT_OK;
+    });
+}
+
+int biot_kernel_timing(biot_ctx* c, int enable, int level, double* out, void* stream) {
+    return guarded([&]() {
+        require_level(c, level);
+        hipStream_t st = S(stream);
+        if (enable) {
+            c->prof_on = true;
+            c->prof_level = level;
+            c->prof_used[0] = c->prof_used[1] = 0;
+            return BIOT_OK;
+        }
+        c->prof_on = false;
+        BIOT_HIP(hipStreamSynchronize(st));
+        double tot[2] = {0, 0};
+        for (int k = 0; k < 2; ++k)
+            for (size_t q = 0; q + 1 < c->prof_used[k]; q += 2) {
+                float ms = 0;
+                BIOT_HIP(hipEventElapsedTime(&ms, c->prof_ev[k][q], c->prof_ev[k][q + 1]));
+                tot[k] += ms;
+            }
+        if (out) {
+            out[0] = tot[0];
+            out[1] = (double)(c->prof_used[0] / 2);
+            out[2] = tot[1];
+            out[3] = (double)(c->prof_used[1] / 2);
+        }
+        c->prof_used[0] = c->prof_used[1] = 0;
         return BIOT_OK;
     });
 }

@@ -20,13 +20,15 @@ enum DofType : int {
 constexpr int NTYPES = 10;
 
 // ---- padded layout ------------------------------------------------------------------------
-// Each plane holds (n + 3) rows of `pitch` entries; slot (i, j), -1 <= i, j <= n + 1,
-// lives at (j + 1) * pitch + (i + 1).  Entries of absent or Dirichlet DoFs and of the
-// ghost ring are zero in every vector at all times.
+// Each plane holds (n + 4) rows of `pitch` entries; slot (i, j), -2 <= i, j <= n + 1,
+// lives at (j + 2) * pitch + (i + 2) (two ghost rows/columns below, one above, so that
+// every gather of a transfer or stencil stays inside the plane without bounds checks).
+// Entries of absent or Dirichlet DoFs and of the ghost ring are zero in every vector at
+// all times.
 struct Layout {
     int n;          // cells per side
-    int pitch;      // entries per row (>= n + 3, multiple of 16)
-    int rows;       // n + 3
+    int pitch;      // entries per row (>= n + 4, multiple of 16)
+    int rows;       // n + 4
     long long plane;// pitch * rows
     long long len;  // 10 * plane
 };
@@ -34,15 +36,15 @@ struct Layout {
 inline Layout make_layout(int n) {
     Layout L;
     L.n = n;
-    L.rows = n + 3;
-    L.pitch = ((n + 3 + 15) / 16) * 16;
+    L.rows = n + 4;
+    L.pitch = ((n + 4 + 15) / 16) * 16;
     L.plane = (long long)L.pitch * L.rows;
     L.len = NTYPES * L.plane;
     return L;
 }
 
 __host__ __device__ inline long long slot_index(const Layout& L, int i, int j) {
-    return (long long)(j + 1) * L.pitch + (i + 1);
+    return (long long)(j + 2) * L.pitch + (i + 2);
 }
 
 // Is the DoF of type t anchored at slot (i, j) free (exists and is not Dirichlet)?
@@ -184,8 +186,13 @@ struct PhysParams {
     double lambda, mu, alpha, inv_M, mu_f, tau;
 };
 
-// Stencil of the rediscretized operator on a mesh with cell size h.
+// Stencil of the rediscretized operator on a mesh with cell size h: coefficients in the
+// order of the compile-time structure (structure.h), and as an explicit entry list.
 std::vector<StencilEntry> build_stencil(const PhysParams& p, double h);
+// Stencil coefficients in the order of the compile-time structure (structure.h).
+void build_stencil_coef(const PhysParams& p, double h, double* coef);
+// Prolongation weights per (fine type, parity, coarse local DoF), see structure.h.
+void build_prolong_weights(double* w);
 // Gather tables of P (fine n -> coarse n/2); independent of h and of the parameters.
 void build_transfer_tables(std::vector<ProlongEntry>& pro, std::vector<RestrictEntry>& res);
 // Vanka class data (9 classes, index 3 * cj + ci) and w-block entries for mesh size n.

@@ -6,6 +6,7 @@
 // (A_u^RQ = 2 mu A_eps + lambda B_u^T M_p^-1 B_u), Sec. 3 (eq. block_interp, R = P^T),
 // Sec. 3.1 (divergence-preserving P_u), Sec. 3.2.1 (vertex patches).
 #include "common.h"
+#include "structure.h"
 
 #include <array>
 #include <cmath>
@@ -173,53 +174,58 @@ void local_matrix(const ElemMats& E, const PhysParams& p, double A[13][13], bool
 
 }  // namespace
 
-std::vector<StencilEntry> build_stencil(const PhysParams& p, double h) {
+void build_stencil_coef(const PhysParams& p, double h, double* coef) {
     Tri tris[2] = {make_tri(false), make_tri(true)};
     double A[2][13][13];
     bool kw[2][13][13];
-    for (int u = 0; u < 2; ++u) local_matrix(element_mats(tris[u], h), p, A[u], kw[u]);
-    std::vector<StencilEntry> out;
-    for (int t = 0; t < NTYPES; ++t) {
-        std::map<std::tuple<int, int, int>, double> merged;
-        std::vector<StencilEntry> kent;
-        double rowmax = 0;
+    for (int u = 0; u < 2; ++u) {
+        local_matrix(element_mats(tris[u], h), p, A[u], kw[u]);
+        for (int k = 0; k < 13; ++k) {
+            const LDof d = ldof(u, k);
+            if (d.t != tris[u].type[k] || d.di != tris[u].di[k] || d.dj != tris[u].dj[k])
+                throw std::runtime_error("local DoF map mismatch");
+            for (int k2 = 0; k2 < 13; ++k2)
+                if (!lcoupled(k, k2) && A[u][k][k2] != 0.0) throw std::runtime_error("coupling outside structure");
+        }
+    }
+    for (int q = 0; q < NSTENCIL; ++q) coef[q] = 0.0;
+    for (int t = 0; t < NTYPES; ++t)
         for (int sj = -1; sj <= 0; ++sj)
             for (int si = -1; si <= 0; ++si)
-                for (int u = 0; u < 2; ++u) {
-                    const Tri& T = tris[u];
+                for (int u = 0; u < 2; ++u)
                     for (int k = 0; k < 13; ++k) {
-                        if (T.type[k] != t || si + T.di[k] != 0 || sj + T.dj[k] != 0) continue;
-                        for (int kk = 0; kk < 13; ++kk) {
-                            double c = A[u][k][kk];
-                            if (c == 0.0) continue;
-                            rowmax = std::max(rowmax, std::fabs(c));
-                            int in = T.type[kk], ddi = si + T.di[kk], ddj = sj + T.dj[kk];
-                            if (kw[u][k][kk]) {
-                                StencilEntry e{};
-                                e.out_t = (int8_t)t; e.in_t = (int8_t)in;
-                                e.di = (int8_t)ddi; e.dj = (int8_t)ddj;
-                                e.ktri = (int8_t)u; e.kdi = (int8_t)si; e.kdj = (int8_t)sj;
-                                e.coef = c;
-                                kent.push_back(e);
-                            } else {
-                                merged[std::make_tuple(in, ddi, ddj)] += c;
-                            }
+                        const LDof r = ldof(u, k);
+                        if (r.t != t || si + r.di != 0 || sj + r.dj != 0) continue;
+                        for (int k2 = 0; k2 < 13; ++k2) {
+                            if (!lcoupled(k, k2)) continue;
+                            const SEnt en = stencil_key(u, si, sj, k2, lkdep(k, k2));
+                            int found = -1;
+                            for (int q = 0; q < SST.n[t]; ++q)
+                                if (sent_eq(SST.e[t][q], en)) found = q;
+                            if (found < 0) throw std::runtime_error("stencil structure mismatch");
+                            coef[SST.off[t] + found] += A[u][k][k2];
                         }
                     }
-                }
-        for (auto& kvp : merged) {
-            if (std::fabs(kvp.second) <= 1e-13 * rowmax) continue;  // exact cancellations
+}
+
+std::vector<StencilEntry> build_stencil(const PhysParams& p, double h) {
+    std::vector<double> coef(NSTENCIL);
+    build_stencil_coef(p, h, coef.data());
+    std::vector<StencilEntry> out;
+    for (int t = 0; t < NTYPES; ++t)
+        for (int q = 0; q < SST.n[t]; ++q) {
+            const SEnt& en = SST.e[t][q];
             StencilEntry e{};
             e.out_t = (int8_t)t;
-            e.in_t = (int8_t)std::get<0>(kvp.first);
-            e.di = (int8_t)std::get<1>(kvp.first);
-            e.dj = (int8_t)std::get<2>(kvp.first);
-            e.ktri = -1;
-            e.coef = kvp.second;
+            e.in_t = (int8_t)en.in;
+            e.di = (int8_t)en.di;
+            e.dj = (int8_t)en.dj;
+            e.ktri = (int8_t)en.kt;
+            e.kdi = (int8_t)en.kdi;
+            e.kdj = (int8_t)en.kdj;
+            e.coef = coef[SST.off[t] + q];
             out.push_back(e);
         }
-        for (auto& e : kent) out.push_back(e);
-    }
     return out;
 }
 
@@ -402,6 +408,24 @@ void local_prolongation(bool upper, std::vector<RawP>& raw) {
 }
 
 }  // namespace
+
+void build_prolong_weights(double* w) {
+    std::vector<RawP> raw[2];
+    local_prolongation(false, raw[0]);
+    local_prolongation(true, raw[1]);
+    for (int q = 0; q < NPWEIGHTS; ++q) w[q] = 0.0;
+    for (int t = 0; t < NTYPES; ++t)
+        for (int pj = 0; pj < 2; ++pj)
+            for (int pi = 0; pi < 2; ++pi) {
+                const int u = fine_tri(t, pi, pj);
+                for (int q = 0; q < fcount(t); ++q) {
+                    const LDof c = ldof(u, ffirst(t) + q);
+                    for (auto& r : raw[u])
+                        if (r.t_f == t && r.fi == pi && r.fj == pj && r.t_c == c.t && r.cI == c.di && r.cJ == c.dj)
+                            w[widx(t, pi, pj, q)] = r.w;
+                }
+            }
+}
 
 void build_transfer_tables(std::vector<ProlongEntry>& pro, std::vector<RestrictEntry>& res) {
     std::vector<RawP> raw;

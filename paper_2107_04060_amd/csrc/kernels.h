@@ -26,11 +26,11 @@ template <typename T>
 struct LevelView {
     Layout L;
     const T* kinv;                 // 2 planes: 1/K of L and U triangles (padded)
-    const StencilEntry* st;        // operator stencil
-    const int* st_off;             // NTYPES + 1 offsets into st (device)
+    const T* coef;                 // operator stencil coefficients (structure.h order, device)
     const DevPatchClass<T>* cls;   // 9 Vanka classes
     const T* wblk;                 // 6 x 2 x 2 RT0-mass blocks of the star triangles (1/K = 1)
     const DevUPatchClass<T>* ucls; // 9 displacement-patch classes (BSR)
+    const T* minv;                 // 9 x 20 x 20 deflated patch inverses (uniform K), or null
 };
 
 // vector plumbing
@@ -50,12 +50,16 @@ template <typename T>
 void launch_vanka(const LevelView<T>& lv, const T* r, T* x, T omega, int x_is_zero, hipStream_t st);
 
 // grid transfers
+// (w: the NPWEIGHTS prolongation weights of structure.h, device)
 template <typename T>
-void launch_restrict(const Layout& Lf, const Layout& Lc, const T* rf, T* rc, const RestrictEntry* tab,
-                     const int* off, hipStream_t st);
+void launch_restrict(const Layout& Lf, const Layout& Lc, const T* rf, T* rc, const T* w, hipStream_t st);
 template <typename T>
-void launch_prolong_add(const Layout& Lf, const Layout& Lc, const T* xc, T* xf, const ProlongEntry* tab,
-                        const int* off, hipStream_t st);
+void launch_prolong_add(const Layout& Lf, const Layout& Lc, const T* xc, T* xf, const T* w, hipStream_t st);
+
+// additive Vanka with one deflated patch inverse per vertex class (uniform permeability):
+// xhat = Minv[class] r_patch + gamma 1_p, gamma = -sum(r_p) / sum(c)
+template <typename T>
+void launch_vanka_uniform(const LevelView<T>& lv, const T* r, T* x, T omega, int x_is_zero, hipStream_t st);
 
 // coarsest level
 template <typename T>

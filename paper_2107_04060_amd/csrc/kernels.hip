@@ -4,6 +4,10 @@
 // additive Vanka -- Sec. 3.2.1; transfers -- Sec. 3 (eq. block_interp), 3.1; coarse direct
 // solve and FGMRES -- Sec. 5.1.
 #include "kernels.h"
+#include "patch_solve.h"
+#include "structure.h"
+
+#include <utility>
 
 #include <hip/hip_runtime.h>
 
@@ -96,30 +100,53 @@ void launch_convert(const float* src, double* dst, long long n, hipStream_t st) 
 // =========================================================================================
 // operator (rediscretized RQ Biot stencil)
 // =========================================================================================
+// One output row: sum over the compile-time stencil of the row's type.
+template <typename T, int t, int e>
+__device__ __forceinline__ T st_term(const T* __restrict__ x, const T* __restrict__ kinv, long long s, int pitch,
+                                     long long plane, const T* __restrict__ c) {
+    constexpr SEnt en = SST.e[t][e];
+    T cc = c[SST.off[t] + e];
+    if constexpr (en.kt >= 0) cc *= kinv[en.kt * plane + s + (long long)en.kdj * pitch + en.kdi];
+    return cc * x[en.in * plane + s + (long long)en.dj * pitch + en.di];
+}
+
+template <typename T, int t, int... E>
+__device__ __forceinline__ T st_row(const T* __restrict__ x, const T* __restrict__ kinv, long long s, int pitch,
+                                    long long plane, const T* __restrict__ c, std::integer_sequence<int, E...>) {
+    T acc = 0;
+    ((acc += st_term<T, t, E>(x, kinv, s, pitch, plane, c)), ...);
+    return acc;
+}
+
+template <typename T, int MODE, int t>
+__device__ __forceinline__ void st_out(const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ y,
+                                       const T* __restrict__ kinv, const Layout& L, long long s, int i, int j,
+                                       const T* __restrict__ c) {
+    // computed for every slot (neighbours stay inside the padded plane), masked on store
+    const bool f = dof_free(t, i, j, L.n);
+    const long long o = t * L.plane + s;
+    const T acc = st_row<T, t>(x, kinv, s, L.pitch, L.plane, c, std::make_integer_sequence<int, SST.n[t]>{});
+    const T val = MODE ? b[o] - acc : acc;
+    y[o] = f ? val : (T)0;
+}
+
+template <typename T, int MODE, int... Ts>
+__device__ __forceinline__ void st_all(const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ y,
+                                       const T* __restrict__ kinv, const Layout& L, long long s, int i, int j,
+                                       const T* __restrict__ c, std::integer_sequence<int, Ts...>) {
+    (st_out<T, MODE, Ts>(x, b, y, kinv, L, s, i, j, c), ...);
+}
+
+// y = A x (MODE 0) or y = b - A x (MODE 1) on slots [0, n]^2; absent DoFs get 0.
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_apply(const T* __restrict__ x, const T* __restrict__ b,
                                                T* __restrict__ y, const T* __restrict__ kinv, Layout L,
-                                               const StencilEntry* __restrict__ st,
-                                               const int* __restrict__ st_off) {
+                                               const T* __restrict__ coef) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i > L.n || j > L.n) return;
     const long long s = slot_index(L, i, j);
-    for (int t = 0; t < NTYPES; ++t) {
-        const bool f = dof_free(t, i, j, L.n);
-        T acc = 0;
-        if (f) {
-            const int e0 = st_off[t], e1 = st_off[t + 1];
-            for (int e = e0; e < e1; ++e) {
-                const StencilEntry E = st[e];
-                T c = (T)E.coef;
-                if (E.ktri >= 0) c *= kinv[E.ktri * L.plane + s + (long long)E.kdj * L.pitch + E.kdi];
-                acc += c * x[E.in_t * L.plane + s + (long long)E.dj * L.pitch + E.di];
-            }
-        }
-        const long long o = t * L.plane + s;
-        y[o] = f ? (MODE ? b[o] - acc : acc) : (T)0;
-    }
+    st_all<T, MODE>(x, b, y, kinv, L, s, i, j, coef, std::make_integer_sequence<int, NTYPES>{});
 }
 
 template <typename T>
@@ -127,9 +154,9 @@ void launch_apply(const LevelView<T>& lv, const T* x, const T* b, T* y, int mode
     dim3 blk(64, 4);
     dim3 grd((lv.L.n + 1 + 63) / 64, (lv.L.n + 1 + 3) / 4);
     if (mode)
-        hipLaunchKernelGGL((k_apply<T, 1>), grd, blk, 0, st, x, b, y, lv.kinv, lv.L, lv.st, lv.st_off);
+        hipLaunchKernelGGL((k_apply<T, 1>), grd, blk, 0, st, x, b, y, lv.kinv, lv.L, lv.coef);
     else
-        hipLaunchKernelGGL((k_apply<T, 0>), grd, blk, 0, st, x, b, y, lv.kinv, lv.L, lv.st, lv.st_off);
+        hipLaunchKernelGGL((k_apply<T, 0>), grd, blk, 0, st, x, b, y, lv.kinv, lv.L, lv.coef);
 }
 template void launch_apply<double>(const LevelView<double>&, const double*, const double*, double*, int,
                                    hipStream_t);
@@ -138,173 +165,38 @@ template void launch_apply<float>(const LevelView<float>&, const float*, const f
 // =========================================================================================
 // additive Vanka (Sec. 3.2.1)
 // =========================================================================================
-// Patch solve of one vertex patch by block elimination onto the six pressures:
-//   [[A, 0, Bh^T], [0, W, Q^T], [Bh, Q, -C]] (xu, xw, xp) = (ru, rw, rp)
-//   S xp = Bh A^-1 ru + Q W^-1 rw - rp,  S = C + Bh A^-1 Bh^T + Q W^-1 Q^T  (SPD),
-// with the pressure constant on the star (an exact eigenvector of S with eigenvalue
-// (1/M)|T|, since the patch velocities see no net flux of it) solved for in closed form
-// and removed from S by a rank-one shift before the Cholesky factorization.
-template <typename T>
-__device__ inline bool chol6(T A[6][6]) {
-#pragma unroll
-    for (int jj = 0; jj < 6; ++jj) {
-        T d = A[jj][jj];
-#pragma unroll
-        for (int k = 0; k < jj; ++k) d -= A[jj][k] * A[jj][k];
-        if (!(d > (T)0)) return false;
-        d = sqrt(d);
-        A[jj][jj] = d;
-        const T inv = (T)1 / d;
-#pragma unroll
-        for (int ii = jj + 1; ii < 6; ++ii) {
-            T s = A[ii][jj];
-#pragma unroll
-            for (int k = 0; k < jj; ++k) s -= A[ii][k] * A[jj][k];
-            A[ii][jj] = s * inv;
-        }
-    }
-    return true;
-}
-
-template <typename T>
-__device__ inline void cholsolve6(const T Lm[6][6], T v[6]) {
-#pragma unroll
-    for (int ii = 0; ii < 6; ++ii) {
-        T s = v[ii];
-#pragma unroll
-        for (int k = 0; k < ii; ++k) s -= Lm[ii][k] * v[k];
-        v[ii] = s / Lm[ii][ii];
-    }
-#pragma unroll
-    for (int ii = 5; ii >= 0; --ii) {
-        T s = v[ii];
-#pragma unroll
-        for (int k = ii + 1; k < 6; ++k) s -= Lm[k][ii] * v[k];
-        v[ii] = s / Lm[ii][ii];
-    }
-}
-
-template <typename T>
-__device__ void patch_solve(const T rr[PATCH], const DevPatchClass<T>& pc, const T kv[6],
-                            const T* __restrict__ wblk, T out[PATCH]) {
-    int pres[PATCH];
-#pragma unroll
-    for (int s = 0; s < PATCH; ++s) pres[s] = pc.present[s];
-    // y_u = A^-1 r_u
-    T yu[8];
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-        T s = 0;
-#pragma unroll
-        for (int b = 0; b < 8; ++b) s += pc.Ainv[a][b] * rr[b];
-        yu[a] = s;
-    }
-    // W (RT0 mass on the six star edges): star triangle k holds the edge pair star_wpair(k, 0..1)
-    T W[6][6];
-#pragma unroll
-    for (int a = 0; a < 6; ++a)
-#pragma unroll
-        for (int b = 0; b < 6; ++b) W[a][b] = 0;
-#pragma unroll
-    for (int kq = 0; kq < 6; ++kq)
-#pragma unroll
-        for (int p = 0; p < 2; ++p)
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int a = star_wpair(kq, p), b = star_wpair(kq, q);
-                if (pres[8 + a] && pres[8 + b]) W[a][b] += wblk[(kq * 2 + p) * 2 + q] * kv[kq];
-            }
-#pragma unroll
-    for (int a = 0; a < 6; ++a)
-        if (!pres[8 + a]) W[a][a] = 1;
-    chol6(W);
-    T yw[6];
-#pragma unroll
-    for (int a = 0; a < 6; ++a) yw[a] = rr[8 + a];
-    cholsolve6(W, yw);
-    // Z = W^-1 Q^T  (column q = W^-1 Q[q][:]^T)
-    T Z[6][6];
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        T v[6];
-#pragma unroll
-        for (int a = 0; a < 6; ++a) v[a] = pc.Q[q][a];
-        cholsolve6(W, v);
-#pragma unroll
-        for (int a = 0; a < 6; ++a) Z[a][q] = v[a];
-    }
-    // S = C + G + Q Z ; rhs = H^T r_u + Q y_w - r_p
-    T S[6][6], rhs[6];
-    int k = 0;
-    T sum_rp = 0, csum = 0, tr = 0;
-#pragma unroll
-    for (int q1 = 0; q1 < 6; ++q1) {
-#pragma unroll
-        for (int q2 = 0; q2 < 6; ++q2) {
-            T s = pc.G[q1][q2];
-#pragma unroll
-            for (int a = 0; a < 6; ++a) s += pc.Q[q1][a] * Z[a][q2];
-            S[q1][q2] = s;
-        }
-        S[q1][q1] += pc.c[q1];
-        T s = -rr[14 + q1];
-#pragma unroll
-        for (int a = 0; a < 8; ++a) s += pc.H[a][q1] * rr[a];
-#pragma unroll
-        for (int a = 0; a < 6; ++a) s += pc.Q[q1][a] * yw[a];
-        rhs[q1] = s;
-        if (pres[14 + q1]) {
-            ++k;
-            sum_rp += rr[14 + q1];
-            csum += pc.c[q1];
-            tr += S[q1][q1];
-        }
-    }
-    // star-mean pressure: x_p = x_perp + gamma 1 with gamma = (1^T rhs) / (k c0) = -sum(r_p) / sum(c)
-    const T gamma = -sum_rp / csum;
-    T mrhs = 0;
-#pragma unroll
-    for (int q = 0; q < 6; ++q)
-        if (pres[14 + q]) mrhs += rhs[q];
-    mrhs /= (T)k;
-    const T beta = tr / (T)(k * k);
-#pragma unroll
-    for (int q1 = 0; q1 < 6; ++q1) {
-#pragma unroll
-        for (int q2 = 0; q2 < 6; ++q2) {
-            if (pres[14 + q1] && pres[14 + q2])
-                S[q1][q2] += beta;
-            else
-                S[q1][q2] = (q1 == q2) ? (T)1 : (T)0;
-        }
-        rhs[q1] = pres[14 + q1] ? rhs[q1] - mrhs : (T)0;
-    }
-    chol6(S);
-    cholsolve6(S, rhs);
-    T xp[6];
-#pragma unroll
-    for (int q = 0; q < 6; ++q) xp[q] = pres[14 + q] ? rhs[q] + gamma : (T)0;
-    // back substitution
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-        T s = yu[a];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) s -= pc.H[a][q] * xp[q];
-        out[a] = pres[a] ? s : (T)0;
-    }
-#pragma unroll
-    for (int a = 0; a < 6; ++a) {
-        T s = yw[a];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) s -= Z[a][q] * xp[q];
-        out[8 + a] = pres[8 + a] ? s : (T)0;
-    }
-#pragma unroll
-    for (int q = 0; q < 6; ++q) out[14 + q] = xp[q];
-}
-
 constexpr int VT = 16;       // patches per tile side (threads)
 constexpr int VO = VT - 1;   // owned slots per tile side
+
+// Stage the residual of slots (i0-1 .. i0+VT-1) x (j0-1 .. j0+VT-1) into LDS; the loop has a
+// constant trip count and is unrolled so that all loads are in flight together.
+template <typename T>
+__device__ __forceinline__ void stage_residual(const T* __restrict__ r, const Layout& L, int i0, int j0, int tid,
+                                               T (&sr)[NTYPES][VT + 1][VT + 1]) {
+    constexpr int TS = (VT + 1) * (VT + 1);
+    constexpr int NV = NTYPES * TS;
+    constexpr int NIT = (NV + VT * VT - 1) / (VT * VT);
+    T v[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int q = tid + it * VT * VT;
+        const int t = q / TS, rem = q - t * TS, bb = rem / (VT + 1), aa = rem - bb * (VT + 1);
+        const int si = i0 - 1 + aa, sj = j0 - 1 + bb;
+        v[it] = (q < NV && si <= L.n + 1 && sj <= L.n + 1) ? r[t * L.plane + slot_index(L, si, sj)] : (T)0;
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int q = tid + it * VT * VT;
+        if (q < NV) (&sr[0][0][0])[q] = v[it];
+    }
+}
+
+// Vertex class (0 low edge, 1 interior, 2 high edge) ranges of a tile's vertices.
+__device__ __forceinline__ void tile_classes(int v0, int n, int& lo, int& hi) {
+    lo = v0 == 0 ? 0 : 1;
+    hi = (v0 + VT - 1 >= n) ? 2 : 1;
+    if (v0 + VT - 1 < 1) hi = 0;
+}
 
 __device__ inline double vanka_weight(int t, int i, int j, int n) {
     if (t <= T_UY) return 1.0;
@@ -323,20 +215,10 @@ __global__ __launch_bounds__(256) void k_vanka(const T* __restrict__ r, T* __res
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * VT + tx;
     const int i0 = blockIdx.x * VO, j0 = blockIdx.y * VO;
     const int n = L.n;
-    // stage the residual of slots (i0-1 .. i0+VT-1) x (j0-1 .. j0+VT-1)
-    constexpr int TS = (VT + 1) * (VT + 1);
-    for (int q = tid; q < NTYPES * TS; q += VT * VT) {
-        const int t = q / TS, rem = q - t * TS, bb = rem / (VT + 1), aa = rem - bb * (VT + 1);
-        const int si = i0 - 1 + aa, sj = j0 - 1 + bb;
-        T v = 0;
-        if (si >= -1 && si <= n + 1 && sj >= -1 && sj <= n + 1) v = r[t * L.plane + slot_index(L, si, sj)];
-        sr[t][bb][aa] = v;
-    }
+    stage_residual<T>(r, L, i0, j0, tid, sr);
     __syncthreads();
     const int vi = i0 + tx, vj = j0 + ty;
-    T out[PATCH];
-#pragma unroll
-    for (int s = 0; s < PATCH; ++s) out[s] = 0;
+    bool solved = false;
     if (vi <= n && vj <= n) {
         const int ci = vi == 0 ? 0 : (vi == n ? 2 : 1);
         const int cj = vj == 0 ? 0 : (vj == n ? 2 : 1);
@@ -359,11 +241,13 @@ __global__ __launch_bounds__(256) void k_vanka(const T* __restrict__ r, T* __res
                 star_tri(kq, ut, di, dj);
                 kv[kq] = kinv[ut * L.plane + slot_index(L, vi + di, vj + dj)];
             }
-            patch_solve<T>(rr, pc, kv, wblk, out);
+            patch_solve<T>(rr, pc, kv, wblk, &sc[0][ty][tx], VT * VT);
+            solved = true;
         }
     }
+    if (!solved)
 #pragma unroll
-    for (int s = 0; s < PATCH; ++s) sc[s][ty][tx] = out[s];
+        for (int s = 0; s < PATCH; ++s) sc[s][ty][tx] = 0;
     __syncthreads();
     if (tx < VO && ty < VO) {
         const int si = i0 + tx, sj = j0 + ty;
@@ -401,81 +285,259 @@ void launch_vanka(const LevelView<T>& lv, const T* r, T* x, T omega, int x_is_ze
 template void launch_vanka<double>(const LevelView<double>&, const double*, double*, double, int, hipStream_t);
 template void launch_vanka<float>(const LevelView<float>&, const float*, float*, float, int, hipStream_t);
 
-// =========================================================================================
-// grid transfers (Sec. 3, 3.1): gather forms of P^T and P
-// =========================================================================================
+// Uniform permeability: every patch of a vertex class has the same matrix; its deflated
+// inverse (the patch inverse with the star-mean pressure mode removed, built on the host by
+// the same elimination) is applied as a 20 x 20 product, and the star-mean pressure is added
+// in closed form.
 template <typename T>
-__global__ void k_restrict(const T* __restrict__ rf, T* __restrict__ rc, Layout Lf, Layout Lc,
-                           const RestrictEntry* __restrict__ tab, const int* __restrict__ off) {
-    const int I = blockIdx.x * blockDim.x + threadIdx.x;
-    const int J = blockIdx.y * blockDim.y + threadIdx.y;
-    if (I > Lc.n || J > Lc.n) return;
-    const long long sc = slot_index(Lc, I, J);
-    for (int t = 0; t < NTYPES; ++t) {
-        T acc = 0;
-        const bool f = dof_free(t, I, J, Lc.n);
-        if (f) {
-            for (int e = off[t]; e < off[t + 1]; ++e) {
-                const RestrictEntry E = tab[e];
-                const int fi = 2 * I + E.di, fj = 2 * J + E.dj;
-                if (fi < -1 || fi > Lf.n + 1 || fj < -1 || fj > Lf.n + 1) continue;
-                acc += (T)E.w * rf[E.t_f * Lf.plane + slot_index(Lf, fi, fj)];
+__global__ __launch_bounds__(256) void k_vanka_uniform(const T* __restrict__ r, T* __restrict__ x, Layout L,
+                                                       const DevPatchClass<T>* __restrict__ cls,
+                                                       const T* __restrict__ minv, T omega, int x_is_zero) {
+    __shared__ T sr[NTYPES][VT + 1][VT + 1];
+    __shared__ T acc[NTYPES][VT][VT];
+    __shared__ T ms[9][PATCH * PATCH];
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * VT + tx;
+    const int i0 = blockIdx.x * VO, j0 = blockIdx.y * VO;
+    const int n = L.n;
+    stage_residual<T>(r, L, i0, j0, tid, sr);
+    // deflated inverses of the vertex classes this tile touches (one class inside the mesh)
+    int cilo, cihi, cjlo, cjhi;
+    tile_classes(i0, n, cilo, cihi);
+    tile_classes(j0, n, cjlo, cjhi);
+    for (int cj = cjlo; cj <= cjhi; ++cj)
+        for (int ci = cilo; ci <= cihi; ++ci) {
+            const int cidx = 3 * cj + ci;
+            constexpr int NM = PATCH * PATCH;
+            constexpr int NIT = (NM + VT * VT - 1) / (VT * VT);
+            T mv[NIT];
+#pragma unroll
+            for (int it = 0; it < NIT; ++it) {
+                const int q = tid + it * VT * VT;
+                mv[it] = q < NM ? minv[cidx * NM + q] : (T)0;
+            }
+#pragma unroll
+            for (int it = 0; it < NIT; ++it) {
+                const int q = tid + it * VT * VT;
+                if (q < NM) ms[cidx][q] = mv[it];
             }
         }
-        rc[t * Lc.plane + sc] = f ? acc : (T)0;
+#pragma unroll
+    for (int it = 0; it < NTYPES; ++it) (&acc[0][0][0])[tid + it * VT * VT] = 0;
+    __syncthreads();
+    const int vi = i0 + tx, vj = j0 + ty;
+    T out[PATCH];
+#pragma unroll
+    for (int s = 0; s < PATCH; ++s) out[s] = 0;
+    if (vi <= n && vj <= n) {
+        const int ci = vi == 0 ? 0 : (vi == n ? 2 : 1);
+        const int cj = vj == 0 ? 0 : (vj == n ? 2 : 1);
+        const int cidx = 3 * cj + ci;
+        const DevPatchClass<T>& pc = cls[cidx];
+        bool keep = false;
+#pragma unroll
+        for (int s = 0; s < 14; ++s) keep = keep || pc.present[s];
+        if (keep) {
+            T rr[PATCH];
+#pragma unroll
+            for (int s = 0; s < PATCH; ++s) {
+                int t, di, dj;
+                patch_slot(s, t, di, dj);
+                rr[s] = sr[t][ty + 1 + dj][tx + 1 + di];
+            }
+            T srp = 0, csum = 0;
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+                if (pc.present[14 + q]) {
+                    srp += rr[14 + q];
+                    csum += pc.c[q];
+                }
+            const T gamma = -srp / csum;
+            const T* M = ms[cidx];
+#pragma unroll
+            for (int a = 0; a < PATCH; ++a) {
+                T v = 0;
+#pragma unroll
+                for (int b2 = 0; b2 < PATCH; ++b2) v += M[a * PATCH + b2] * rr[b2];
+                out[a] = v;
+            }
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+                if (pc.present[14 + q]) out[14 + q] += gamma;
+        }
+    }
+    // owned slot (a, b) collects from the patches of vertices (a..a+1, b..b+1): four
+    // conflict-free phases in a fixed order
+    __syncthreads();
+    acc[T_UX][ty][tx] += out[0];
+    acc[T_UY][ty][tx] += out[1];
+    acc[T_BH][ty][tx] += out[3];
+    acc[T_BV][ty][tx] += out[5];
+    acc[T_WH][ty][tx] += out[9];
+    acc[T_WV][ty][tx] += out[11];
+    acc[T_PL][ty][tx] += out[14];
+    __syncthreads();
+    if (tx > 0) {
+        acc[T_BH][ty][tx - 1] += out[2];
+        acc[T_BD][ty][tx - 1] += out[6];
+        acc[T_WH][ty][tx - 1] += out[8];
+        acc[T_WD][ty][tx - 1] += out[12];
+        acc[T_PL][ty][tx - 1] += out[15];
+        acc[T_PU][ty][tx - 1] += out[18];
+    }
+    __syncthreads();
+    if (ty > 0) {
+        acc[T_BV][ty - 1][tx] += out[4];
+        acc[T_BD][ty - 1][tx] += out[7];
+        acc[T_WV][ty - 1][tx] += out[10];
+        acc[T_WD][ty - 1][tx] += out[13];
+        acc[T_PL][ty - 1][tx] += out[16];
+        acc[T_PU][ty - 1][tx] += out[19];
+    }
+    __syncthreads();
+    if (tx > 0 && ty > 0) acc[T_PU][ty - 1][tx - 1] += out[17];
+    __syncthreads();
+    if (tx < VO && ty < VO) {
+        const int si = i0 + tx, sj = j0 + ty;
+        if (si <= n && sj <= n) {
+            const long long s0 = slot_index(L, si, sj);
+#pragma unroll
+            for (int t = 0; t < NTYPES; ++t) {
+                if (!dof_free(t, si, sj, n)) continue;
+                const long long o = t * L.plane + s0;
+                const T w = (T)vanka_weight(t, si, sj, n);
+                const T old = x_is_zero ? (T)0 : x[o];
+                x[o] = old + omega * w * acc[t][ty][tx];
+            }
+        }
     }
 }
 
 template <typename T>
-void launch_restrict(const Layout& Lf, const Layout& Lc, const T* rf, T* rc, const RestrictEntry* tab,
-                     const int* off, hipStream_t st) {
-    dim3 blk(64, 4);
-    dim3 grd((Lc.n + 1 + 63) / 64, (Lc.n + 1 + 3) / 4);
-    hipLaunchKernelGGL(k_restrict<T>, grd, blk, 0, st, rf, rc, Lf, Lc, tab, off);
+void launch_vanka_uniform(const LevelView<T>& lv, const T* r, T* x, T omega, int x_is_zero, hipStream_t st) {
+    dim3 blk(VT, VT);
+    dim3 grd((lv.L.n + 1 + VO - 1) / VO, (lv.L.n + 1 + VO - 1) / VO);
+    hipLaunchKernelGGL(k_vanka_uniform<T>, grd, blk, 0, st, r, x, lv.L, lv.cls, lv.minv, omega, x_is_zero);
 }
-template void launch_restrict<double>(const Layout&, const Layout&, const double*, double*, const RestrictEntry*,
-                                      const int*, hipStream_t);
-template void launch_restrict<float>(const Layout&, const Layout&, const float*, float*, const RestrictEntry*,
-                                     const int*, hipStream_t);
+template void launch_vanka_uniform<double>(const LevelView<double>&, const double*, double*, double, int,
+                                           hipStream_t);
+template void launch_vanka_uniform<float>(const LevelView<float>&, const float*, float*, float, int, hipStream_t);
 
-// off: 41 offsets, group g = (t_f * 2 + pi) * 2 + pj
+// =========================================================================================
+// grid transfers (Sec. 3, 3.1): gather forms of P^T and P
+// =========================================================================================
+template <typename T, int tc, int e>
+__device__ __forceinline__ T rs_term(const T* __restrict__ rf, const Layout& Lf, int I, int J,
+                                     const T* __restrict__ w) {
+    constexpr RTerm rt = RST.e[tc][e];
+    // fine slots 2I + di in [-2, n_f + 1]: inside the padded plane (zero outside the mesh)
+    return w[rt.w] * rf[rt.tf * Lf.plane + slot_index(Lf, 2 * I + rt.di, 2 * J + rt.dj)];
+}
+
+template <typename T, int tc, int... E>
+__device__ __forceinline__ T rs_row(const T* __restrict__ rf, const Layout& Lf, int I, int J,
+                                    const T* __restrict__ w, std::integer_sequence<int, E...>) {
+    T acc = 0;
+    ((acc += rs_term<T, tc, E>(rf, Lf, I, J, w)), ...);
+    return acc;
+}
+
+template <typename T, int tc>
+__device__ __forceinline__ void rs_out(const T* __restrict__ rf, T* __restrict__ rc, const Layout& Lf,
+                                       const Layout& Lc, int I, int J, const T* __restrict__ w) {
+    const long long o = tc * Lc.plane + slot_index(Lc, I, J);
+    const T v = rs_row<T, tc>(rf, Lf, I, J, w, std::make_integer_sequence<int, RST.n[tc]>{});
+    rc[o] = dof_free(tc, I, J, Lc.n) ? v : (T)0;
+}
+
+template <typename T, int... Ts>
+__device__ __forceinline__ void rs_all(const T* __restrict__ rf, T* __restrict__ rc, const Layout& Lf,
+                                       const Layout& Lc, int I, int J, const T* __restrict__ w,
+                                       std::integer_sequence<int, Ts...>) {
+    (rs_out<T, Ts>(rf, rc, Lf, Lc, I, J, w), ...);
+}
+
+// r_c = P^T r_f, one thread per coarse slot
 template <typename T>
-__global__ void k_prolong_add(const T* __restrict__ xc, T* __restrict__ xf, Layout Lf, Layout Lc,
-                              const ProlongEntry* __restrict__ tab, const int* __restrict__ off) {
+__global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ rf, T* __restrict__ rc, Layout Lf,
+                                                  Layout Lc, const T* __restrict__ w) {
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     const int J = blockIdx.y * blockDim.y + threadIdx.y;
     if (I > Lc.n || J > Lc.n) return;
-    for (int pj = 0; pj < 2; ++pj)
-        for (int pi = 0; pi < 2; ++pi) {
-            const int fi = 2 * I + pi, fj = 2 * J + pj;
-            if (fi > Lf.n || fj > Lf.n) continue;
-            const long long sf = slot_index(Lf, fi, fj);
-            for (int t = 0; t < NTYPES; ++t) {
-                if (!dof_free(t, fi, fj, Lf.n)) continue;
-                const int g = (t * 2 + pi) * 2 + pj;
-                T acc = 0;
-                for (int e = off[g]; e < off[g + 1]; ++e) {
-                    const ProlongEntry E = tab[e];
-                    const int ci = I + E.dI, cj = J + E.dJ;
-                    if (ci < -1 || ci > Lc.n + 1 || cj < -1 || cj > Lc.n + 1) continue;
-                    acc += (T)E.w * xc[E.t_c * Lc.plane + slot_index(Lc, ci, cj)];
-                }
-                xf[t * Lf.plane + sf] += acc;
-            }
-        }
+    rs_all<T>(rf, rc, Lf, Lc, I, J, w, std::make_integer_sequence<int, NTYPES>{});
 }
 
 template <typename T>
-void launch_prolong_add(const Layout& Lf, const Layout& Lc, const T* xc, T* xf, const ProlongEntry* tab,
-                        const int* off, hipStream_t st) {
+void launch_restrict(const Layout& Lf, const Layout& Lc, const T* rf, T* rc, const T* w, hipStream_t st) {
     dim3 blk(64, 4);
     dim3 grd((Lc.n + 1 + 63) / 64, (Lc.n + 1 + 3) / 4);
-    hipLaunchKernelGGL(k_prolong_add<T>, grd, blk, 0, st, xc, xf, Lf, Lc, tab, off);
+    hipLaunchKernelGGL(k_restrict<T>, grd, blk, 0, st, rf, rc, Lf, Lc, w);
 }
-template void launch_prolong_add<double>(const Layout&, const Layout&, const double*, double*, const ProlongEntry*,
-                                         const int*, hipStream_t);
-template void launch_prolong_add<float>(const Layout&, const Layout&, const float*, float*, const ProlongEntry*,
-                                        const int*, hipStream_t);
+template void launch_restrict<double>(const Layout&, const Layout&, const double*, double*, const double*,
+                                      hipStream_t);
+template void launch_restrict<float>(const Layout&, const Layout&, const float*, float*, const float*,
+                                     hipStream_t);
+
+// fine DoF (tf, parity): sum over the field's coarse local DoFs of its designated triangle;
+// xcl[t][dj][di] holds the coarse values of slots (I + di, J + dj), di, dj in {0, 1}
+template <typename T, int tf, int pi, int pj, int q>
+__device__ __forceinline__ T pr_term(const T (&xcl)[NTYPES][2][2], const T* __restrict__ w) {
+    constexpr LDof c = ldof(fine_tri(tf, pi, pj), ffirst(tf) + q);
+    return w[widx(tf, pi, pj, q)] * xcl[c.t][c.dj][c.di];
+}
+
+template <typename T, int tf, int pi, int pj, int... Q>
+__device__ __forceinline__ T pr_row(const T (&xcl)[NTYPES][2][2], const T* __restrict__ w,
+                                    std::integer_sequence<int, Q...>) {
+    T acc = 0;
+    ((acc += pr_term<T, tf, pi, pj, Q>(xcl, w)), ...);
+    return acc;
+}
+
+template <typename T, int pi, int pj, int tf>
+__device__ __forceinline__ void pr_out(const T (&xcl)[NTYPES][2][2], T* __restrict__ xf, const Layout& Lf, int I,
+                                       int J, const T* __restrict__ w) {
+    const int fi = 2 * I + pi, fj = 2 * J + pj;
+    const T acc = pr_row<T, tf, pi, pj>(xcl, w, std::make_integer_sequence<int, fcount(tf)>{});
+    if (dof_free(tf, fi, fj, Lf.n)) xf[tf * Lf.plane + slot_index(Lf, fi, fj)] += acc;
+}
+
+template <typename T, int pi, int pj, int... Ts>
+__device__ __forceinline__ void pr_all(const T (&xcl)[NTYPES][2][2], T* __restrict__ xf, const Layout& Lf, int I,
+                                       int J, const T* __restrict__ w, std::integer_sequence<int, Ts...>) {
+    (pr_out<T, pi, pj, Ts>(xcl, xf, Lf, I, J, w), ...);
+}
+
+// x_f += P x_c, one thread per coarse slot writing its four fine slots
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong_add(const T* __restrict__ xc, T* __restrict__ xf, Layout Lf,
+                                                     Layout Lc, const T* __restrict__ w) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    const int J = blockIdx.y * blockDim.y + threadIdx.y;
+    if (I > Lc.n || J > Lc.n) return;
+    T xcl[NTYPES][2][2];
+#pragma unroll
+    for (int t = 0; t < NTYPES; ++t)
+#pragma unroll
+        for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+            for (int di = 0; di < 2; ++di) xcl[t][dj][di] = xc[t * Lc.plane + slot_index(Lc, I + di, J + dj)];
+    constexpr auto seq = std::make_integer_sequence<int, NTYPES>{};
+    pr_all<T, 0, 0>(xcl, xf, Lf, I, J, w, seq);
+    pr_all<T, 1, 0>(xcl, xf, Lf, I, J, w, seq);
+    pr_all<T, 0, 1>(xcl, xf, Lf, I, J, w, seq);
+    pr_all<T, 1, 1>(xcl, xf, Lf, I, J, w, seq);
+}
+
+template <typename T>
+void launch_prolong_add(const Layout& Lf, const Layout& Lc, const T* xc, T* xf, const T* w, hipStream_t st) {
+    dim3 blk(64, 4);
+    dim3 grd((Lc.n + 1 + 63) / 64, (Lc.n + 1 + 3) / 4);
+    hipLaunchKernelGGL(k_prolong_add<T>, grd, blk, 0, st, xc, xf, Lf, Lc, w);
+}
+template void launch_prolong_add<double>(const Layout&, const Layout&, const double*, double*, const double*,
+                                         hipStream_t);
+template void launch_prolong_add<float>(const Layout&, const Layout&, const float*, float*, const float*,
+                                        hipStream_t);
 
 // =========================================================================================
 // coarsest level: dense inverse applied by one workgroup (Sec. 5.1 direct solve)
@@ -684,19 +746,25 @@ void launch_multidot(const double* V, long long ldv, int nv, const double* w, lo
     hipLaunchKernelGGL(k_multidot, dim3(nblk), dim3(256), 0, st, V, ldv, nv, w, n, partial);
 }
 
-__global__ void k_reduce_partials(const double* __restrict__ partial, int nblk, int nv, double* __restrict__ out,
-                                  int accumulate) {
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= nv) return;
+// out[v] (+)= sum_b partial[b][v]: one workgroup per vector, fixed-order tree (deterministic)
+__global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ partial, int nblk, int nv,
+                                                         double* __restrict__ out, int accumulate) {
+    __shared__ double red[256];
+    const int v = blockIdx.x;
     double s = 0;
-    for (int b = 0; b < nblk; ++b) s += partial[(long long)b * nv + v];
-    out[v] = accumulate ? out[v] + s : s;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += partial[(long long)b * nv + v];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[v] = accumulate ? out[v] + red[0] : red[0];
 }
 
 void launch_reduce_partials(const double* partial, int nblk, int nv, double* out, int accumulate,
                             hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce_partials, dim3((nv + 63) / 64), dim3(64), 0, st, partial, nblk, nv, out,
-                       accumulate);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(nv), dim3(256), 0, st, partial, nblk, nv, out, accumulate);
 }
 
 __global__ void k_update(double* __restrict__ w, const double* __restrict__ V, long long ldv, int nv,
