@@ -18,6 +18,42 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+CSRC = os.path.join(ROOT, "paper_2107_04060_amd", "csrc")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_vanka_uniform_sweep256_fp64.md")
+
+
+def kernel_source_hash():
+    """sha256 over the HIP/C++ sources of the library (file names and contents, sorted)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            h.update(name.encode())
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per finest-level Vanka launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the kernel sources changed
+    since the counters were taken (or no summary exists)."""
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            text = f.read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return int(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -30,6 +66,9 @@ def parse():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--copy-calib-mb", type=int, default=0,
+                    help="before the warm-up, copy a device buffer of this many MiB once (the plain "
+                         "copy kernel that scales the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -103,6 +142,12 @@ def main():
             if record is not None:
                 record.append(info)
 
+    if args.copy_calib_mb > 0:
+        src = torch.ones(args.copy_calib_mb * 2**20 // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step(None)
     for r in runs:
@@ -137,9 +182,10 @@ def main():
     if vk_n > 0:
         avg_s = vk_ms / vk_n * 1e-3
         achieved = bytes_per_launch / avg_s / 1e9
-        roofline = {"kernel": "k_vanka (additive Vanka, finest level)", "bound": "hbm",
+        traffic = measured_traffic() if (args.workload == "sweep256" and args.precision == "fp64") else None
+        roofline = {"kernel": "k_vanka_uniform (additive Vanka, finest level)", "bound": "hbm",
                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "avg_launch_us": round(avg_s * 1e6, 2), "launches": vk_n,
                     "algorithmic_bytes_per_launch": bytes_per_launch}
     resid = None

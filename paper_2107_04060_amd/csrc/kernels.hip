@@ -264,14 +264,13 @@ __global__ __launch_bounds__(256) void k_vanka(const T* __restrict__ r, T* __res
             c[T_PL] = sc[14][ty][tx] + sc[15][ty][tx + 1] + sc[16][ty + 1][tx];
             c[T_PU] = sc[17][ty + 1][tx + 1] + sc[18][ty][tx + 1] + sc[19][ty + 1][tx];
             const long long s0 = slot_index(L, si, sj);
+            T old[NTYPES];
 #pragma unroll
-            for (int t = 0; t < NTYPES; ++t) {
-                if (!dof_free(t, si, sj, n)) continue;
-                const long long o = t * L.plane + s0;
-                const T w = (T)vanka_weight(t, si, sj, n);
-                const T old = x_is_zero ? (T)0 : x[o];
-                x[o] = old + omega * w * c[t];
-            }
+            for (int t = 0; t < NTYPES; ++t) old[t] = x_is_zero ? (T)0 : x[t * L.plane + s0];
+#pragma unroll
+            for (int t = 0; t < NTYPES; ++t)
+                if (dof_free(t, si, sj, n))
+                    x[t * L.plane + s0] = old[t] + omega * (T)vanka_weight(t, si, sj, n) * c[t];
         }
     }
 }
@@ -400,14 +399,13 @@ __global__ __launch_bounds__(256) void k_vanka_uniform(const T* __restrict__ r, 
         const int si = i0 + tx, sj = j0 + ty;
         if (si <= n && sj <= n) {
             const long long s0 = slot_index(L, si, sj);
+            T old[NTYPES];
 #pragma unroll
-            for (int t = 0; t < NTYPES; ++t) {
-                if (!dof_free(t, si, sj, n)) continue;
-                const long long o = t * L.plane + s0;
-                const T w = (T)vanka_weight(t, si, sj, n);
-                const T old = x_is_zero ? (T)0 : x[o];
-                x[o] = old + omega * w * acc[t][ty][tx];
-            }
+            for (int t = 0; t < NTYPES; ++t) old[t] = x_is_zero ? (T)0 : x[t * L.plane + s0];
+#pragma unroll
+            for (int t = 0; t < NTYPES; ++t)
+                if (dof_free(t, si, sj, n))
+                    x[t * L.plane + s0] = old[t] + omega * (T)vanka_weight(t, si, sj, n) * acc[t][ty][tx];
         }
     }
 }
@@ -494,17 +492,19 @@ __device__ __forceinline__ T pr_row(const T (&xcl)[NTYPES][2][2], const T* __res
 }
 
 template <typename T, int pi, int pj, int tf>
-__device__ __forceinline__ void pr_out(const T (&xcl)[NTYPES][2][2], T* __restrict__ xf, const Layout& Lf, int I,
-                                       int J, const T* __restrict__ w) {
+__device__ __forceinline__ void pr_out(const T (&xcl)[NTYPES][2][2], const T (&xfl)[NTYPES][2][2],
+                                       T* __restrict__ xf, const Layout& Lf, int I, int J,
+                                       const T* __restrict__ w) {
     const int fi = 2 * I + pi, fj = 2 * J + pj;
     const T acc = pr_row<T, tf, pi, pj>(xcl, w, std::make_integer_sequence<int, fcount(tf)>{});
-    if (dof_free(tf, fi, fj, Lf.n)) xf[tf * Lf.plane + slot_index(Lf, fi, fj)] += acc;
+    if (dof_free(tf, fi, fj, Lf.n)) xf[tf * Lf.plane + slot_index(Lf, fi, fj)] = xfl[tf][pj][pi] + acc;
 }
 
 template <typename T, int pi, int pj, int... Ts>
-__device__ __forceinline__ void pr_all(const T (&xcl)[NTYPES][2][2], T* __restrict__ xf, const Layout& Lf, int I,
-                                       int J, const T* __restrict__ w, std::integer_sequence<int, Ts...>) {
-    (pr_out<T, pi, pj, Ts>(xcl, xf, Lf, I, J, w), ...);
+__device__ __forceinline__ void pr_all(const T (&xcl)[NTYPES][2][2], const T (&xfl)[NTYPES][2][2],
+                                       T* __restrict__ xf, const Layout& Lf, int I, int J,
+                                       const T* __restrict__ w, std::integer_sequence<int, Ts...>) {
+    (pr_out<T, pi, pj, Ts>(xcl, xfl, xf, Lf, I, J, w), ...);
 }
 
 // x_f += P x_c, one thread per coarse slot writing its four fine slots
@@ -521,11 +521,19 @@ __global__ __launch_bounds__(256) void k_prolong_add(const T* __restrict__ xc, T
         for (int dj = 0; dj < 2; ++dj)
 #pragma unroll
             for (int di = 0; di < 2; ++di) xcl[t][dj][di] = xc[t * Lc.plane + slot_index(Lc, I + di, J + dj)];
+    // current values of the four fine slots (2I + 1 <= n_f + 1 stays inside the padded plane)
+    T xfl[NTYPES][2][2];
+#pragma unroll
+    for (int t = 0; t < NTYPES; ++t)
+#pragma unroll
+        for (int pj = 0; pj < 2; ++pj)
+#pragma unroll
+            for (int pi = 0; pi < 2; ++pi) xfl[t][pj][pi] = xf[t * Lf.plane + slot_index(Lf, 2 * I + pi, 2 * J + pj)];
     constexpr auto seq = std::make_integer_sequence<int, NTYPES>{};
-    pr_all<T, 0, 0>(xcl, xf, Lf, I, J, w, seq);
-    pr_all<T, 1, 0>(xcl, xf, Lf, I, J, w, seq);
-    pr_all<T, 0, 1>(xcl, xf, Lf, I, J, w, seq);
-    pr_all<T, 1, 1>(xcl, xf, Lf, I, J, w, seq);
+    pr_all<T, 0, 0>(xcl, xfl, xf, Lf, I, J, w, seq);
+    pr_all<T, 1, 0>(xcl, xfl, xf, Lf, I, J, w, seq);
+    pr_all<T, 0, 1>(xcl, xfl, xf, Lf, I, J, w, seq);
+    pr_all<T, 1, 1>(xcl, xfl, xf, Lf, I, J, w, seq);
 }
 
 template <typename T>
