@@ -223,26 +223,35 @@ class SolveFn(torch.autograd.Function):
     same hierarchy (A is symmetric) and the per-triangle gradient kernel."""
 
     @staticmethod
-    def forward(ctx, theta, b, solver, tol, restart, maxit):
+    def forward(ctx, theta, b, solver, tol, restart, maxit, adj_tol):
         solver.update_K(torch.exp(theta.detach()))
+        token = object()
+        solver._k_token = token
         x, info = solver.solve(b.detach().contiguous(), tol=tol, restart=restart, maxit=maxit)
         if not info["converged"]:
             raise BiotError(BIOT_NOT_CONVERGED, "forward solve did not converge")
         ctx.solver = solver
-        ctx.opts = (tol, restart, maxit)
-        ctx.save_for_backward(x)
+        ctx.token = token
+        ctx.opts = (adj_tol, restart, maxit)
+        ctx.save_for_backward(x, theta.detach())
         return x
 
     @staticmethod
     def backward(ctx, gx):
-        (x,) = ctx.saved_tensors
+        x, theta = ctx.saved_tensors
         tol, restart, maxit = ctx.opts
+        if getattr(ctx.solver, "_k_token", None) is not ctx.token:
+            # the solver was re-assembled for another theta since this forward pass
+            ctx.solver.update_K(torch.exp(theta))
+            ctx.solver._k_token = ctx.token
         lam, info = ctx.solver.solve(gx.contiguous(), tol=tol, restart=restart, maxit=maxit)
         if not info["converged"]:
             raise BiotError(BIOT_NOT_CONVERGED, "adjoint solve did not converge")
         g_theta = ctx.solver.grad_logK(x, lam)
-        return g_theta, lam, None, None, None, None
+        return g_theta, lam, None, None, None, None, None
 
 
-def solve(theta, b, solver, tol=1e-10, restart=30, maxit=500):
-    return SolveFn.apply(theta, b, solver, tol, restart, maxit)
+def solve(theta, b, solver, tol=1e-10, restart=30, maxit=500, adj_tol=None):
+    """x = A(theta)^{-1} b, differentiable in theta (per-triangle ln K) and b.  The adjoint
+    solve of the backward pass runs to adj_tol (default: tol)."""
+    return SolveFn.apply(theta, b, solver, tol, restart, maxit, tol if adj_tol is None else adj_tol)

@@ -66,9 +66,12 @@ struct Level {
     DevBuf coef64, coef32;              // stencil coefficients in structure.h order
     DevBuf minv64, minv32;              // deflated patch inverses for uniform K (9 x 20 x 20)
     DevBuf kinv64, kinv32;              // 2 planes each
-    DevBuf cls64, cls32, ucls64, ucls32, wblk64, wblk32;
+    DevBuf cls64, cls32, wblk64, wblk32;
+    DevBuf uinv64, uinv32;              // displacement-patch inverses (BSR), 9 x 8 x 8
+    DevBuf bsrd64, bsrd32;              // BSR diagonal data, 5 planes
     DevBuf x64, b64, r64, t64;          // FP64 work vectors (padded)
     DevBuf x32, b32, r32;               // FP32 work vectors (padded)
+    DevBuf bs64, bs32;                  // BSR scratch vector (padded)
     template <typename T>
     LevelView<T> view() const;
 };
@@ -81,7 +84,8 @@ LevelView<double> Level::view<double>() const {
     v.coef = coef64.as<double>();
     v.cls = cls64.as<DevPatchClass<double>>();
     v.wblk = wblk64.as<double>();
-    v.ucls = ucls64.as<DevUPatchClass<double>>();
+    v.uinv = uinv64.as<double>();
+    v.bsrd = bsrd64.as<double>();
     v.minv = minv64.as<double>();
     return v;
 }
@@ -93,7 +97,8 @@ LevelView<float> Level::view<float>() const {
     v.coef = coef32.as<float>();
     v.cls = cls32.as<DevPatchClass<float>>();
     v.wblk = wblk32.as<float>();
-    v.ucls = ucls32.as<DevUPatchClass<float>>();
+    v.uinv = uinv32.as<float>();
+    v.bsrd = bsrd32.as<float>();
     v.minv = minv32.as<float>();
     return v;
 }
@@ -191,13 +196,11 @@ static std::vector<DevPatchClass<T>> convert_classes(const PatchClass* c) {
 }
 
 template <typename T>
-static std::vector<DevUPatchClass<T>> convert_uclasses(const UPatchClass* c) {
-    std::vector<DevUPatchClass<T>> out(9);
-    for (int k = 0; k < 9; ++k) {
+static std::vector<T> convert_uinv(const UPatchClass* c) {
+    std::vector<T> out(9 * 64);
+    for (int k = 0; k < 9; ++k)
         for (int a = 0; a < 8; ++a)
-            for (int b = 0; b < 8; ++b) out[k].Ainv[a][b] = (T)c[k].Ainv[a][b];
-        for (int s = 0; s < 8; ++s) out[k].present[s] = c[k].present[s];
-    }
+            for (int b = 0; b < 8; ++b) out[(k * 8 + a) * 8 + b] = (T)c[k].Ainv[a][b];
     return out;
 }
 
@@ -243,8 +246,8 @@ static void level_patch_data(Level& lv, bool uniform, double Kinv, hipStream_t s
     upload(lv.wblk32, wf, st);
     UPatchClass ucls[9];
     build_upatch_classes(lv.st_host, lv.n, ucls);
-    upload(lv.ucls64, convert_uclasses<double>(ucls), st);
-    upload(lv.ucls32, convert_uclasses<float>(ucls), st);
+    upload(lv.uinv64, convert_uinv<double>(ucls), st);
+    upload(lv.uinv32, convert_uinv<float>(ucls), st);
 }
 
 static void levels_kinv(biot_ctx* c, const double* K_tri, hipStream_t st) {
@@ -254,6 +257,27 @@ static void levels_kinv(biot_ctx* c, const double* K_tri, hipStream_t st) {
         launch_kinv_coarsen(c->levels[l - 1]->kinv64.as<double>(), c->levels[l - 1]->L,
                             c->levels[l]->kinv64.as<double>(), c->levels[l]->L, st);
     for (auto& lv : c->levels) launch_convert(lv->kinv64.as<double>(), lv->kinv32.as<float>(), 2 * lv->L.plane, st);
+}
+
+// BSR diagonal data of every smoothing level from the current 1/K (Appendix D)
+static void levels_bsr(biot_ctx* c, hipStream_t st) {
+    const PhysParams& p = c->phys;
+    const double cu = p.inv_M + p.alpha * p.alpha / (p.lambda + p.mu);
+    for (size_t l = 0; l + 1 < c->levels.size(); ++l) {
+        Level& lv = *c->levels[l];
+        const size_t len = (size_t)lv.L.len;
+        if (!lv.bsrd64.p) {
+            lv.bsrd64.alloc(5 * lv.L.plane * sizeof(double));
+            lv.bsrd32.alloc(5 * lv.L.plane * sizeof(float));
+            lv.bs64.alloc(len * sizeof(double));
+            lv.bs32.alloc(len * sizeof(float));
+            launch_fill(lv.bs64.as<double>(), lv.L.len, 0.0, st);
+            launch_fill(lv.bs32.as<float>(), lv.L.len, 0.0f, st);
+        }
+        const double area = 0.5 * lv.h * lv.h;
+        launch_bsr_diag<double>(lv.view<double>(), cu * area, lv.bsrd64.as<double>(), st);
+        launch_convert(lv.bsrd64.as<double>(), lv.bsrd32.as<float>(), 5 * lv.L.plane, st);
+    }
 }
 
 static void coarse_setup(biot_ctx* c, hipStream_t st) {
@@ -298,12 +322,14 @@ struct VecSet<double> {
     static double* x(Level& l) { return l.x64.as<double>(); }
     static double* b(Level& l) { return l.b64.as<double>(); }
     static double* r(Level& l) { return l.r64.as<double>(); }
+    static double* s(Level& l) { return l.bs64.as<double>(); }
 };
 template <>
 struct VecSet<float> {
     static float* x(Level& l) { return l.x32.as<float>(); }
     static float* b(Level& l) { return l.b32.as<float>(); }
     static float* r(Level& l) { return l.r32.as<float>(); }
+    static float* s(Level& l) { return l.bs32.as<float>(); }
 };
 
 // Event pair around one launch when kernel timing is on for this level (kind 0 Vanka,
@@ -346,7 +372,13 @@ static void smooth_step(biot_ctx* c, int l, T* x, const T* b, T* r, bool x_is_ze
             launch_vanka<T>(v, rr, x, om, x_is_zero ? 1 : 0, st);
         prof_end(e0, st);
     } else {
-        throw ArgError{"smoother not available in this build"};
+        const T* rr = b;
+        if (!x_is_zero) {
+            launch_apply<T>(v, x, b, r, 1, st);
+            rr = r;
+        }
+        T* t = VecSet<T>::s(lv);
+        launch_bsr<T>(v, rr, t, x, om, (T)c->opts.omega_J, x_is_zero ? 1 : 0, st);
     }
 }
 
@@ -656,6 +688,8 @@ int biot_setup_hierarchy(biot_ctx* c, const biot_mg_opts* o, void* stream) {
                 "nu1, nu2 in [0, 16], nu1 + nu2 >= 1");
         require(o->precision == BIOT_PREC_FP64 || o->precision == BIOT_PREC_FP32_SMOOTHER, "unknown precision");
         require(std::isfinite(o->omega) && o->omega > 0, "omega must be positive");
+        require(o->smoother != BIOT_SMOOTHER_BSR || (std::isfinite(o->omega_J) && o->omega_J > 0),
+                "BSR needs omega_J > 0");
         const int nc = c->n >> (o->levels - 1);
         require(nc <= 16, "coarsest mesh must have at most 16 cells per side (dense direct solve)");
         hipStream_t st = S(stream);
@@ -682,6 +716,7 @@ int biot_setup_hierarchy(biot_ctx* c, const biot_mg_opts* o, void* stream) {
             launch_convert(lv->kinv64.as<double>(), lv->kinv32.as<float>(), 2 * lv->L.plane, st);
         c->opts = *o;
         if (o->precision == BIOT_PREC_FP32_SMOOTHER) alloc_fp32(c, st);
+        if (o->smoother == BIOT_SMOOTHER_BSR) levels_bsr(c, st);
         coarse_setup(c, st);
         coarse_factor(c, st);
         check_stream_error();
@@ -797,6 +832,7 @@ int biot_update_K(biot_ctx* c, const double* K_tri, void* stream) {
         hipStream_t st = S(stream);
         c->K_uniform = false;
         levels_kinv(c, K_tri, st);
+        if (c->have_hierarchy && c->opts.smoother == BIOT_SMOOTHER_BSR) levels_bsr(c, st);
         if (c->have_hierarchy) coarse_factor(c, st);
         check_stream_error();
         return BIOT_OK;

@@ -14,12 +14,6 @@ struct DevPatchClass {
     int present[PATCH];
 };
 
-template <typename T>
-struct DevUPatchClass {
-    T Ainv[8][8];
-    int present[8];
-};
-
 
 // Device view of one mesh level.
 template <typename T>
@@ -29,7 +23,8 @@ struct LevelView {
     const T* coef;                 // operator stencil coefficients (structure.h order, device)
     const DevPatchClass<T>* cls;   // 9 Vanka classes
     const T* wblk;                 // 6 x 2 x 2 RT0-mass blocks of the star triangles (1/K = 1)
-    const DevUPatchClass<T>* ucls; // 9 displacement-patch classes (BSR)
+    const T* uinv;                 // 9 x 8 x 8 displacement-patch inverses (BSR; identity on absent DoFs)
+    const T* bsrd;                 // BSR diagonal data, 5 planes (k_bsr_wdiag / k_bsr_sdiag)
     const T* minv;                 // 9 x 20 x 20 deflated patch inverses (uniform K), or null
 };
 
@@ -60,6 +55,15 @@ void launch_prolong_add(const Layout& Lf, const Layout& Lc, const T* xc, T* xf, 
 // xhat = Minv[class] r_patch + gamma 1_p, gamma = -sum(r_p) / sum(c)
 template <typename T>
 void launch_vanka_uniform(const LevelView<T>& lv, const T* r, T* x, T omega, int x_is_zero, hipStream_t st);
+
+// inexact Braess-Sarazin: diagonal data of a level (1 / (tau D_w), 1 / diag(S)); cS =
+// (1/M + alpha^2 / (lambda + mu)) |T|
+template <typename T>
+void launch_bsr_diag(const LevelView<T>& lv, T cS, T* d, hipStream_t st);
+// one BSR step on the residual r (t: scratch vector of the level)
+template <typename T>
+void launch_bsr(const LevelView<T>& lv, const T* r, T* t, T* x, T omega, T omega_J, int x_is_zero,
+                hipStream_t st);
 
 // coarsest level
 template <typename T>

@@ -421,6 +421,309 @@ template void launch_vanka_uniform<double>(const LevelView<double>&, const doubl
 template void launch_vanka_uniform<float>(const LevelView<float>&, const float*, float*, float, int, hipStream_t);
 
 // =========================================================================================
+// inexact Braess-Sarazin relaxation (Sec. 3.2.2, Appendix D)
+// =========================================================================================
+// One step on the residual r:
+//   z_u = F_u^{-1} r_u            (additive Vanka on the displacement block, 8-DoF patches)
+//   z_w = r_w / (tau D_w)         (D_w = diag M_w(K))
+//   dp  = omega_J (A_pu z_u + A_pw z_w - r_p) / diag(S)
+//   du  = F_u^{-1} (r_u - A_up dp),  dw = (r_w - A_wp dp) / (tau D_w)
+//   x  += omega (du, dw, dp)
+// with diag(S)_T = (1/M + alpha^2 / (lambda + mu)) |T| + sum_e (tau B_w)_{Te}^2 / (tau D_w)_e.
+// Three launches: k_bsr_first (z_u, z_w), k_bsr_schur (dp), k_bsr_second (update).
+
+template <int... Ts, typename F>
+__device__ __forceinline__ void static_for(std::integer_sequence<int, Ts...>, F&& f) {
+    (f(std::integral_constant<int, Ts>{}), ...);
+}
+
+// sum over the entries e of row type t with predicate Sel(column type) of
+// coef_e (* 1/K) * v[column slot]
+template <typename T, int t, template <int> class Sel, int... E>
+__device__ __forceinline__ T st_row_sel(const T* __restrict__ v, const T* __restrict__ kinv, long long s,
+                                        int pitch, long long plane, const T* __restrict__ c,
+                                        std::integer_sequence<int, E...>) {
+    T acc = 0;
+    static_for(std::integer_sequence<int, E...>{}, [&](auto ec) {
+        constexpr int e = decltype(ec)::value;
+        constexpr SEnt en = SST.e[t][e];
+        if constexpr (Sel<en.in>::value) {
+            T cc = c[SST.off[t] + e];
+            if constexpr (en.kt >= 0) cc *= kinv[en.kt * plane + s + (long long)en.kdj * pitch + en.kdi];
+            acc += cc * v[en.in * plane + s + (long long)en.dj * pitch + en.di];
+        }
+    });
+    return acc;
+}
+template <int tin>
+struct SelU : std::integral_constant<bool, (tfield(tin) == 0)> {};
+template <int tin>
+struct SelUW : std::integral_constant<bool, (tfield(tin) != 2)> {};
+template <int tin>
+struct SelP : std::integral_constant<bool, (tfield(tin) == 2)> {};
+
+constexpr int BSR_W = 0;   // planes 0..2 of the diagonal data: 1 / (tau D_w) of w_H, w_V, w_D
+constexpr int BSR_S = 3;   // planes 3..4: 1 / diag(S) of p_L, p_U
+
+// diagonal of the RT0 block: the entries of a w row on its own slot
+template <typename T>
+__global__ __launch_bounds__(256) void k_bsr_wdiag(const T* __restrict__ kinv, const T* __restrict__ coef,
+                                                   Layout L, T* __restrict__ d) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i > L.n || j > L.n) return;
+    const long long s = slot_index(L, i, j);
+    static_for(std::integer_sequence<int, T_WH, T_WV, T_WD>{}, [&](auto tc) {
+        constexpr int t = decltype(tc)::value;
+        T v = 0;
+        static_for(std::make_integer_sequence<int, SST.n[t]>{}, [&](auto ec) {
+            constexpr SEnt en = SST.e[t][decltype(ec)::value];
+            if constexpr (en.in == t && en.di == 0 && en.dj == 0) {
+                T cc = coef[SST.off[t] + decltype(ec)::value];
+                if constexpr (en.kt >= 0) cc *= kinv[en.kt * L.plane + s + (long long)en.kdj * L.pitch + en.kdi];
+                v += cc;
+            }
+        });
+        d[(BSR_W + t - T_WH) * L.plane + s] = dof_free(t, i, j, L.n) ? (T)1 / v : (T)0;
+    });
+}
+
+// diag(S) of the P0 rows from the RT0 diagonal (k_bsr_wdiag first)
+template <typename T>
+__global__ __launch_bounds__(256) void k_bsr_sdiag(const T* __restrict__ coef, Layout L, T cS,
+                                                   T* __restrict__ d) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i > L.n || j > L.n) return;
+    const long long s = slot_index(L, i, j);
+    static_for(std::integer_sequence<int, T_PL, T_PU>{}, [&](auto tc) {
+        constexpr int t = decltype(tc)::value;
+        T v = cS;
+        static_for(std::make_integer_sequence<int, SST.n[t]>{}, [&](auto ec) {
+            constexpr SEnt en = SST.e[t][decltype(ec)::value];
+            if constexpr (tfield(en.in) == 1) {
+                static_assert(en.kt < 0, "B_w does not depend on K");
+                const T cc = coef[SST.off[t] + decltype(ec)::value];
+                // column slots s + (0..1, 0..1) lie inside the padded plane
+                v += cc * cc * d[(BSR_W + en.in - T_WH) * L.plane + s + (long long)en.dj * L.pitch + en.di];
+            }
+        });
+        d[(BSR_S + t - T_PL) * L.plane + s] = dof_free(t, i, j, L.n) ? (T)1 / v : (T)0;
+    });
+}
+
+template <typename T>
+void launch_bsr_diag(const LevelView<T>& lv, T cS, T* d, hipStream_t st) {
+    dim3 blk(64, 4);
+    dim3 grd((lv.L.n + 1 + 63) / 64, (lv.L.n + 1 + 3) / 4);
+    hipLaunchKernelGGL(k_bsr_wdiag<T>, grd, blk, 0, st, lv.kinv, lv.coef, lv.L, d);
+    hipLaunchKernelGGL(k_bsr_sdiag<T>, grd, blk, 0, st, lv.coef, lv.L, cS, d);
+}
+template void launch_bsr_diag<double>(const LevelView<double>&, double, double*, hipStream_t);
+template void launch_bsr_diag<float>(const LevelView<float>&, float, float*, hipStream_t);
+
+constexpr int NU = 5;   // displacement DoF types ux, uy, bH, bV, bD
+
+// Displacement-patch solves of the vertices of a tile: su holds the displacement residual
+// of slots (i0-1 .. i0+VT-1)^2, the patch corrections go to so (8 per vertex).
+template <typename T>
+__device__ __forceinline__ void upatch_solves(const T (&su)[NU][VT + 1][VT + 1], const T (&ui)[9][64],
+                                              T (&so)[8][VT][VT], int vi, int vj, int n, int tx, int ty) {
+    T out[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) out[a] = 0;
+    if (vi <= n && vj <= n) {
+        const int ci = vi == 0 ? 0 : (vi == n ? 2 : 1);
+        const int cj = vj == 0 ? 0 : (vj == n ? 2 : 1);
+        const T* M = ui[3 * cj + ci];
+        T rr[8];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            int t, di, dj;
+            patch_slot(a, t, di, dj);
+            rr[a] = su[t][ty + 1 + dj][tx + 1 + di];
+        }
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            T v = 0;
+#pragma unroll
+            for (int b2 = 0; b2 < 8; ++b2) v += M[a * 8 + b2] * rr[b2];
+            out[a] = v;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 8; ++a) so[a][ty][tx] = out[a];
+}
+
+// weighted sum of the patch corrections at owned slot (tx, ty): P1 in one patch, bubbles
+// in the two patches of their end points (weight 1/2)
+template <typename T>
+__device__ __forceinline__ void upatch_gather(const T (&so)[8][VT][VT], int tx, int ty, T (&du)[NU]) {
+    du[T_UX] = so[0][ty][tx];
+    du[T_UY] = so[1][ty][tx];
+    du[T_BH] = (T)0.5 * (so[3][ty][tx] + so[2][ty][tx + 1]);
+    du[T_BV] = (T)0.5 * (so[5][ty][tx] + so[4][ty + 1][tx]);
+    du[T_BD] = (T)0.5 * (so[6][ty][tx + 1] + so[7][ty + 1][tx]);
+}
+
+template <typename T>
+__device__ __forceinline__ void load_uinv(const T* __restrict__ uinv, T (&ui)[9][64], int tid) {
+    T v[3];
+#pragma unroll
+    for (int it = 0; it < 3; ++it) {
+        const int q = tid + it * VT * VT;
+        v[it] = q < 9 * 64 ? uinv[q] : (T)0;
+    }
+#pragma unroll
+    for (int it = 0; it < 3; ++it) {
+        const int q = tid + it * VT * VT;
+        if (q < 9 * 64) (&ui[0][0])[q] = v[it];
+    }
+}
+
+// t_u = F_u^{-1} r_u, t_w = r_w / (tau D_w) on the owned slots of the tile
+template <typename T>
+__global__ __launch_bounds__(256) void k_bsr_first(const T* __restrict__ r, T* __restrict__ t, Layout L,
+                                                   const T* __restrict__ uinv, const T* __restrict__ d) {
+    __shared__ T su[NU][VT + 1][VT + 1];
+    __shared__ T so[8][VT][VT];
+    __shared__ T ui[9][64];
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * VT + tx;
+    const int i0 = blockIdx.x * VO, j0 = blockIdx.y * VO;
+    const int n = L.n;
+    {
+        constexpr int TS = (VT + 1) * (VT + 1);
+        constexpr int NV = NU * TS;
+        constexpr int NIT = (NV + VT * VT - 1) / (VT * VT);
+        T v[NIT];
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int q = tid + it * VT * VT;
+            const int tt = q / TS, rem = q - tt * TS, bb = rem / (VT + 1), aa = rem - bb * (VT + 1);
+            const int si = i0 - 1 + aa, sj = j0 - 1 + bb;
+            v[it] = (q < NV && si <= n + 1 && sj <= n + 1) ? r[tt * L.plane + slot_index(L, si, sj)] : (T)0;
+        }
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int q = tid + it * VT * VT;
+            if (q < NV) (&su[0][0][0])[q] = v[it];
+        }
+    }
+    load_uinv(uinv, ui, tid);
+    const int si = i0 + tx, sj = j0 + ty;
+    const bool own = tx < VO && ty < VO && si <= n && sj <= n;
+    const long long s0 = own ? slot_index(L, si, sj) : 0;
+    T rw[3], dw[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        rw[q] = own ? r[(T_WH + q) * L.plane + s0] : (T)0;
+        dw[q] = own ? d[(BSR_W + q) * L.plane + s0] : (T)0;
+    }
+    __syncthreads();
+    upatch_solves<T>(su, ui, so, si, sj, n, tx, ty);
+    __syncthreads();
+    if (own) {
+        T du[NU];
+        upatch_gather<T>(so, tx, ty, du);
+#pragma unroll
+        for (int q = 0; q < NU; ++q) t[q * L.plane + s0] = dof_free(q, si, sj, n) ? du[q] : (T)0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) t[(T_WH + q) * L.plane + s0] = rw[q] * dw[q];
+    }
+}
+
+// t_p = omega_J (A_pu t_u + A_pw t_w - r_p) / diag(S), one thread per slot
+template <typename T>
+__global__ __launch_bounds__(256) void k_bsr_schur(const T* __restrict__ r, T* __restrict__ t, Layout L,
+                                                   const T* __restrict__ coef, const T* __restrict__ d,
+                                                   T omega_J) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i > L.n || j > L.n) return;
+    const long long s = slot_index(L, i, j);
+    static_for(std::integer_sequence<int, T_PL, T_PU>{}, [&](auto tc) {
+        constexpr int tp = decltype(tc)::value;
+        const T a = st_row_sel<T, tp, SelUW>(t, nullptr, s, L.pitch, L.plane, coef,
+                                             std::make_integer_sequence<int, SST.n[tp]>{});
+        const T v = omega_J * (a - r[tp * L.plane + s]) * d[(BSR_S + tp - T_PL) * L.plane + s];
+        t[tp * L.plane + s] = dof_free(tp, i, j, L.n) ? v : (T)0;
+    });
+}
+
+// x += omega (F_u^{-1}(r_u - A_up t_p), (r_w - A_wp t_p) / (tau D_w), t_p)
+template <typename T>
+__global__ __launch_bounds__(256) void k_bsr_second(const T* __restrict__ r, const T* __restrict__ t,
+                                                    T* __restrict__ x, Layout L, const T* __restrict__ uinv,
+                                                    const T* __restrict__ coef, const T* __restrict__ d,
+                                                    T omega, int x_is_zero) {
+    __shared__ T su[NU][VT + 1][VT + 1];
+    __shared__ T so[8][VT][VT];
+    __shared__ T ui[9][64];
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * VT + tx;
+    const int i0 = blockIdx.x * VO, j0 = blockIdx.y * VO;
+    const int n = L.n;
+    // displacement residual after the pressure update, slots (i0-1 .. i0+VT-1)^2; its
+    // pressure columns reach slots -1..0 away, inside the two-deep low ghost ring
+    for (int q = tid; q < (VT + 1) * (VT + 1); q += VT * VT) {
+        const int bb = q / (VT + 1), aa = q - bb * (VT + 1);
+        const int si = i0 - 1 + aa, sj = j0 - 1 + bb;
+        const bool in = si <= n + 1 && sj <= n + 1;
+        const long long s = in ? slot_index(L, si, sj) : 0;
+        static_for(std::make_integer_sequence<int, NU>{}, [&](auto tc) {
+            constexpr int tu = decltype(tc)::value;
+            T v = 0;
+            if (in && dof_free(tu, si, sj, n))
+                v = r[tu * L.plane + s] - st_row_sel<T, tu, SelP>(t, nullptr, s, L.pitch, L.plane, coef,
+                                                                std::make_integer_sequence<int, SST.n[tu]>{});
+            su[tu][bb][aa] = v;
+        });
+    }
+    load_uinv(uinv, ui, tid);
+    const int si = i0 + tx, sj = j0 + ty;
+    const bool own = tx < VO && ty < VO && si <= n && sj <= n;
+    const long long s0 = own ? slot_index(L, si, sj) : 0;
+    T old[NTYPES];
+#pragma unroll
+    for (int q = 0; q < NTYPES; ++q) old[q] = (own && !x_is_zero) ? x[q * L.plane + s0] : (T)0;
+    __syncthreads();
+    upatch_solves<T>(su, ui, so, si, sj, n, tx, ty);
+    __syncthreads();
+    if (own) {
+        T du[NU];
+        upatch_gather<T>(so, tx, ty, du);
+#pragma unroll
+        for (int q = 0; q < NU; ++q)
+            if (dof_free(q, si, sj, n)) x[q * L.plane + s0] = old[q] + omega * du[q];
+        static_for(std::integer_sequence<int, T_WH, T_WV, T_WD>{}, [&](auto tc) {
+            constexpr int tw = decltype(tc)::value;
+            const T a = st_row_sel<T, tw, SelP>(t, nullptr, s0, L.pitch, L.plane, coef,
+                                                std::make_integer_sequence<int, SST.n[tw]>{});
+            const T dwv = (r[tw * L.plane + s0] - a) * d[(BSR_W + tw - T_WH) * L.plane + s0];
+            if (dof_free(tw, si, sj, n)) x[tw * L.plane + s0] = old[tw] + omega * dwv;
+        });
+#pragma unroll
+        for (int q = T_PL; q <= T_PU; ++q)
+            if (dof_free(q, si, sj, n)) x[q * L.plane + s0] = old[q] + omega * t[q * L.plane + s0];
+    }
+}
+
+template <typename T>
+void launch_bsr(const LevelView<T>& lv, const T* r, T* t, T* x, T omega, T omega_J, int x_is_zero,
+                hipStream_t st) {
+    dim3 tb(VT, VT);
+    dim3 tg((lv.L.n + 1 + VO - 1) / VO, (lv.L.n + 1 + VO - 1) / VO);
+    dim3 sb(64, 4);
+    dim3 sg((lv.L.n + 1 + 63) / 64, (lv.L.n + 1 + 3) / 4);
+    hipLaunchKernelGGL(k_bsr_first<T>, tg, tb, 0, st, r, t, lv.L, lv.uinv, lv.bsrd);
+    hipLaunchKernelGGL(k_bsr_schur<T>, sg, sb, 0, st, r, t, lv.L, lv.coef, lv.bsrd, omega_J);
+    hipLaunchKernelGGL(k_bsr_second<T>, tg, tb, 0, st, r, t, x, lv.L, lv.uinv, lv.coef, lv.bsrd, omega, x_is_zero);
+}
+template void launch_bsr<double>(const LevelView<double>&, const double*, double*, double*, double, double, int,
+                                 hipStream_t);
+template void launch_bsr<float>(const LevelView<float>&, const float*, float*, float*, float, float, int,
+                                hipStream_t);
+
+// =========================================================================================
 // grid transfers (Sec. 3, 3.1): gather forms of P^T and P
 // =========================================================================================
 template <typename T, int tc, int e>

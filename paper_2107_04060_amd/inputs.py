@@ -10,7 +10,9 @@ Workloads (synthetic stand-ins; the paper's own experiments use manufactured sol
               FP32 smoother, seed 2
   * block2048 2048 x 2048, 10 levels, K in {1, 1e-6} on 64 x 64-cell blocks, nu = 0.4999,
               16 right-hand sides, seed 3
-  * adjoint512 512 x 512, 8 levels, ln K = GRF(corr 0.05), seed 4 (observations seed 5)
+  * adjoint512 512 x 512, 8 levels, ln K = GRF(corr 0.05), 8 samples from seed 4;
+              p_obs = p(theta_obs), theta_obs = GRF(corr 0.05) from seed 5; right-hand side
+              from seed 4; loss 0.5 ||p(theta) - p_obs||^2
 
 Biot modulus: the workloads do not state M.  The method depends on the parameters only
 through nu and the groups E / (alpha^2 M) and E tau K / (alpha^2 mu_f) (a constant
@@ -115,6 +117,18 @@ def workload(name):
     raise KeyError(name)
 
 
+def adjoint_fields(n, count=1):
+    """Log-permeability fields of the adjoint workload: `count` samples theta = ln K, drawn
+    in sequence from its seed, and theta_obs from the observation seed (standardized Gaussian
+    random fields, correlation length 0.05).  The observed pressures are those of the
+    solution for theta_obs with the same right-hand side."""
+    w = workload("adjoint512")
+    rng = np.random.default_rng(w["seed"])
+    thetas = [squares_to_triangles(grf_squares(n, w["corr_len"], rng)) for _ in range(count)]
+    obs = squares_to_triangles(grf_squares(n, w["corr_len"], np.random.default_rng(w["obs_seed"])))
+    return thetas, obs
+
+
 def permeability_triangles(name, n=None):
     """Per-triangle permeability of a workload (array) or a scalar."""
     w = workload(name)
@@ -127,8 +141,7 @@ def permeability_triangles(name, n=None):
         rng = np.random.default_rng(w["seed"])
         return squares_to_triangles(block_contrast_squares(n, w["block"], rng))
     if name == "adjoint512":
-        rng = np.random.default_rng(w["seed"])
-        return squares_to_triangles(np.exp(grf_squares(n, w["corr_len"], rng)))
+        return np.exp(adjoint_fields(n, 1)[0][0])
     return None
 
 

@@ -1,0 +1,152 @@
+"""The adjoint: the per-triangle gradient kernel, the autograd wrapper against the oracle's
+direct-solve adjoint on a 16 x 16 copy, and central finite differences of the GPU loss in 20
+random directions on the 512 x 512 workload.
+
+Gradient: theta_T = ln K_T, L = 0.5 ||p(theta) - p_obs||^2, x = A(theta)^{-1} b; the
+backward pass solves A lam = dL/dx with the same hierarchy (A is symmetric) and evaluates
+g_T = tau mu_f e^{-theta_T} lam_w|_T^T M_w^T w|_T (Sec. 2.1: K enters only through M_w(K))."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_2107_04060_amd import inputs  # noqa: E402
+from oracle.mesh import Mesh  # noqa: E402
+from oracle.fem import Assembly, BiotParams  # noqa: E402
+from oracle import adjoint  # noqa: E402
+from gpu_cases import perm, params, solver, rel  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def binding():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2107_04060_amd import binding as b
+    b.load()
+    return b
+
+
+def _t(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _workload(n):
+    w = inputs.workload("adjoint512")
+    lam, mu = w["cases"][0]["lam"], w["cases"][0]["mu"]
+    P = BiotParams(lam, mu, alpha=w["alpha"], M=w["M"], mu_f=w["mu_f"], tau=w["tau"])
+    (theta,), theta_obs = inputs.adjoint_fields(n, 1)
+    b = inputs.rhs_uniform(n, w["seed"])
+    return w, P, theta, theta_obs, b
+
+
+def _gpu_solver(binding, w, n, levels):
+    lam_, mu_ = w["cases"][0]["lam"], w["cases"][0]["mu"]
+    s = binding.BiotSolver(n, lam_, mu_, alpha=w["alpha"], M=w["M"], mu_f=w["mu_f"], tau=w["tau"], K=1.0)
+    s.setup(levels=levels, smoother="vanka", nu1=2, nu2=2, omega=0.8)
+    return s
+
+
+def _gpu_pressure(s, theta, b, n, tol):
+    """Pressure block of the GPU solution for theta (the observations, for theta_obs)."""
+    s.update_K(_t(np.exp(theta)))
+    x, info = s.solve(_t(b), tol=tol, restart=30, maxit=1000)
+    assert info["converged"]
+    return x[10 * n * n - 8 * n + 2 - 2 * n * n:].cpu().numpy()
+
+
+def test_grad_kernel_parity(binding):
+    n = 16
+    K = perm(n, "hetero")
+    s = solver(binding, torch, n, "small", 1.0)
+    s.update_K(_t(K))
+    asm = Assembly(Mesh(n), params("small"), K)
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal(asm.n_free)
+    lam = rng.standard_normal(asm.n_free)
+    g = s.grad_logK(_t(x), _t(lam)).cpu().numpy()
+    assert rel(g, adjoint.grad_terms(asm, x, lam)) < 1e-13
+    s.close()
+
+
+def _gpu_loss_grad(binding, s, theta, b, p_obs, n, tol, adj_tol=None):
+    from paper_2107_04060_amd.binding import solve
+    th = _t(theta).requires_grad_(True)
+    x = solve(th, _t(b), s, tol=tol, restart=30, maxit=1000, adj_tol=adj_tol)
+    nu = 10 * n * n - 8 * n + 2 - 2 * n * n
+    d = x[nu:] - _t(p_obs)
+    L = 0.5 * (d * d).sum()
+    L.backward()
+    return float(L), th.grad.cpu().numpy()
+
+
+def test_autograd_matches_oracle_dense_adjoint(binding):
+    """16 x 16 copy of the adjoint workload: loss and gradient against the oracle's direct
+    solves; both GPU solves run to 1e-12."""
+    import scipy.sparse.linalg as spla
+    n = 16
+    w, P, theta, theta_obs, b = _workload(n)
+    s = _gpu_solver(binding, w, n, 3)
+    L, g = _gpu_loss_grad(binding, s, theta, b, _gpu_pressure(s, theta_obs, b, n, 1e-13), n, 1e-12)
+    asm_obs = Assembly(Mesh(n), P, np.exp(theta_obs))
+    p_obs = spla.spsolve(asm_obs.A.tocsc(), b)[asm_obs.slices()[2]]
+    Lo, go, _, _ = adjoint.loss_and_grad(n, P, theta, b, p_obs)
+    print("  loss %.10e oracle %.10e; grad rel diff %.2e" % (L, Lo, rel(g, go)), flush=True)
+    assert abs(L - Lo) <= 1e-8 * abs(Lo)
+    assert rel(g, go) < 1e-7
+    s.close()
+
+
+def test_batch_reuses_solver(binding):
+    """Two parameter samples through one solver: the backward pass of the first sample
+    re-assembles its own permeability, so its gradient equals the one computed alone."""
+    n = 16
+    w, P, theta, theta_obs, b = _workload(n)
+    theta2 = theta[::-1].copy()
+    s = _gpu_solver(binding, w, n, 3)
+    p_obs = _gpu_pressure(s, theta_obs, b, n, 1e-12)
+    _, g_alone = _gpu_loss_grad(binding, s, theta, b, p_obs, n, 1e-12)
+    from paper_2107_04060_amd.binding import solve
+    ths = [_t(t).requires_grad_(True) for t in (theta, theta2)]
+    xs = [solve(th, _t(b), s, tol=1e-12, restart=30, maxit=1000) for th in ths]
+    nu = 10 * n * n - 8 * n + 2 - 2 * n * n
+    loss = sum(0.5 * ((x[nu:] - _t(p_obs)) ** 2).sum() for x in xs)
+    loss.backward()
+    assert rel(ths[0].grad.cpu().numpy(), g_alone) < 1e-9
+    s.close()
+
+
+def test_finite_differences_512(binding):
+    """512 x 512 adjoint workload: g . d against central differences of the GPU loss in 20
+    random directions, h = 1e-6, forward solves to 1e-12, adjoint solve to 1e-10 (the
+    adjoint right-hand side may carry a mean pressure, which excites the nearly singular
+    constant-pressure mode; rounding in A lam then bounds its attainable relative residual
+    near 1e-11)."""
+    n = 512
+    w, P, theta, theta_obs, b = _workload(n)
+    s = _gpu_solver(binding, w, n, w["levels"])
+    p_obs = _gpu_pressure(s, theta_obs, b, n, 1e-12)
+    L, g = _gpu_loss_grad(binding, s, theta, b, p_obs, n, 1e-12, adj_tol=1e-10)
+    print("  loss %.6e" % L, flush=True)
+    from paper_2107_04060_amd.binding import solve
+    nu = 10 * n * n - 8 * n + 2 - 2 * n * n
+    pobs = _t(p_obs)
+
+    def loss(th):
+        with torch.no_grad():
+            x = solve(_t(th), _t(b), s, tol=1e-12, restart=30, maxit=1000)
+            return float(0.5 * ((x[nu:] - pobs) ** 2).sum())
+
+    rng = np.random.default_rng(20)
+    h = 1e-6
+    worst = 0.0
+    for k in range(20):
+        d = rng.standard_normal(theta.size)
+        fd = (loss(theta + h * d) - loss(theta - h * d)) / (2 * h)
+        an = float(g @ d)
+        e = abs(fd - an) / max(abs(an), 1e-300)
+        worst = max(worst, e)
+        print("  dir %2d  fd %.10e  adjoint %.10e  rel %.2e" % (k, fd, an, e), flush=True)
+    assert worst < 1e-4
+    s.close()
