@@ -62,7 +62,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sweep256")
-    ap.add_argument("--smoothers", default="vanka")
+    ap.add_argument("--smoothers", default="vanka,bsr")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-8)
@@ -73,7 +73,7 @@ def parse():
 
 
 def weights(smoother, nu, K):
-    """Relaxation weights of the workload's parameter sets (see the design notes)."""
+    """LFA-optimized relaxation weights of the workload's parameter sets."""
     from paper_2107_04060_amd import inputs
     return inputs.relaxation_weights(smoother, nu, K)
 

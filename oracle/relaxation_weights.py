@@ -1,0 +1,95 @@
+"""Relaxation weights of the synthetic workloads from the two-grid LFA (oracle/lfa.py), as
+the paper chooses its weights (Sec. 4.3, Sec. 5: brute-force search of the LFA-predicted
+two-grid factor).
+
+TEST INFRASTRUCTURE ONLY: run by hand, it writes paper_2107_04060_amd/relaxation_weights.json,
+the table of weights the workloads use.  Nothing in the product path imports this module.
+
+    python -m oracle.relaxation_weights
+
+Each parameter set is analysed at its own cell size h and physical parameters.  Vanka:
+omega on a 0.02 grid; inexact BSR: (omega_J, omega) on a 0.05 grid with 16 x 16 frequency
+samples, then a 0.01 pattern search with 32 x 32 samples.  Heterogeneous permeabilities use
+a representative constant K (the geometric mean of the field's range).
+"""
+import json
+import os
+import sys
+
+import numpy as np
+
+from .fem import BiotParams
+from .lfa import TwoGridLFA
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+OUT = os.path.join(ROOT, "paper_2107_04060_amd", "relaxation_weights.json")
+
+
+def vanka_weight(P, h, K, nu12):
+    L = TwoGridLFA(P, h, K=K, smoother="vanka", nu=2 * nu12)
+    w, r = L.optimize_vanka(0.5, 1.1, 0.02)
+    return {"omega": w, "omega_J": 1.0, "rho_lfa": round(r, 4)}
+
+
+def bsr_weights(P, h, K, nu12):
+    Lc = TwoGridLFA(P, h, K=K, smoother="bsr", nu=2 * nu12, samples=16)
+    best = (np.inf, None, None)
+    for a in np.round(np.arange(0.6, 1.6001, 0.05), 4):
+        Q = Lc.smoother_symbols(a)
+        for b in np.round(np.arange(0.4, 1.3001, 0.05), 4):
+            r = Lc.rho(b, Q=Q)
+            if r < best[0]:
+                best = (r, a, b)
+    L = TwoGridLFA(P, h, K=K, smoother="bsr", nu=2 * nu12)
+    _, a, b = best
+    cur = L.rho(b, a)
+    while True:
+        moves = [(a + da, b + db) for da in (-0.01, 0.0, 0.01) for db in (-0.01, 0.0, 0.01) if (da, db) != (0, 0)]
+        vals = [(L.rho(round(bb, 4), round(aa, 4)), round(aa, 4), round(bb, 4)) for aa, bb in moves]
+        r, aa, bb = min(vals)
+        if r >= cur - 1e-6:
+            break
+        cur, a, b = r, aa, bb
+    return {"omega": float(b), "omega_J": float(a), "rho_lfa": round(cur, 4)}
+
+
+def lame(E, nu):
+    return E * nu / ((1 - 2 * nu) * (1 + nu)), E / (2 + 2 * nu)
+
+
+def main():
+    M = 1.0 / 0.03                      # E / (alpha^2 M) = 0.03 with E = 1
+    out = {"_doc": "LFA-optimized relaxation weights of the synthetic workloads, written by "
+                   "oracle/relaxation_weights.py (two-grid LFA, Sec. 4).", "sweep256": {}}
+    for nu in (0.2, 0.49, 0.4999):
+        lam, mu = lame(1.0, nu)
+        P = BiotParams(lam, mu, alpha=1.0, M=M, mu_f=1.0, tau=1.0)
+        for K in (1.0, 1e-3, 1e-6):
+            key = "%g/%g" % (nu, K)
+            v = vanka_weight(P, 1 / 256, K, 2)
+            b = bsr_weights(P, 1 / 256, K, 1)
+            out["sweep256"][key] = {"vanka": v, "bsr": b}
+            print("sweep256", key, v, b, flush=True)
+    # 16 x 16: lambda = mu = 1, E = 2.5
+    P = BiotParams(1.0, 1.0, alpha=1.0, M=2.5 / 0.03, mu_f=1.0, tau=1.0)
+    out["small"] = {"vanka": vanka_weight(P, 1 / 16, 1.0, 2), "bsr": bsr_weights(P, 1 / 16, 1.0, 1)}
+    print("small", out["small"], flush=True)
+    lam, mu = lame(1.0, 0.49)
+    P = BiotParams(lam, mu, alpha=1.0, M=M, mu_f=1.0, tau=1e-2)
+    out["grf1024"] = {"vanka": vanka_weight(P, 1 / 1024, 1e-3, 2)}
+    print("grf1024", out["grf1024"], flush=True)
+    lam, mu = lame(1.0, 0.4999)
+    P = BiotParams(lam, mu, alpha=1.0, M=M, mu_f=1.0, tau=1.0)
+    out["block2048"] = {"vanka": vanka_weight(P, 1 / 2048, 1e-3, 2)}
+    print("block2048", out["block2048"], flush=True)
+    lam, mu = lame(1.0, 0.3)
+    P = BiotParams(lam, mu, alpha=1.0, M=M, mu_f=1.0, tau=1.0)
+    out["adjoint512"] = {"vanka": vanka_weight(P, 1 / 512, 1.0, 2)}
+    print("adjoint512", out["adjoint512"], flush=True)
+    with open(OUT, "w") as f:
+        json.dump(out, f, indent=1, sort_keys=True)
+    print("wrote", OUT)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -64,13 +64,13 @@ struct Level {
     int st_off_host[NTYPES + 1];
     DevBuf st, st_off;                  // stencil entry list (device; coarse matrix set-up)
     DevBuf coef64, coef32;              // stencil coefficients in structure.h order
-    DevBuf minv64, minv32;              // deflated patch inverses for uniform K (9 x 20 x 20)
+    DevBuf minv64, minv32;              // full patch inverses per vertex class, uniform K (9 x 20 x 20)
     DevBuf kinv64, kinv32;              // 2 planes each
     DevBuf cls64, cls32, wblk64, wblk32;
     DevBuf uinv64, uinv32;              // displacement-patch inverses (BSR), 9 x 8 x 8
     DevBuf bsrd64, bsrd32;              // BSR diagonal data, 5 planes
-    DevBuf x64, b64, r64, t64;          // FP64 work vectors (padded)
-    DevBuf x32, b32, r32;               // FP32 work vectors (padded)
+    DevBuf x64, b64, r64, t64, x2_64;   // FP64 work vectors (padded); x64 / x2_64: iterate pair
+    DevBuf x32, b32, r32, x2_32;        // FP32 work vectors (padded)
     DevBuf bs64, bs32;                  // BSR scratch vector (padded)
     template <typename T>
     LevelView<T> view() const;
@@ -130,10 +130,13 @@ struct biot_ctx {
     ~biot_ctx() {
         for (auto& v : prof_ev)
             for (auto e : v) (void)hipEventDestroy(e);
+        if (hhost) (void)hipHostFree(hhost);
     }
     // Krylov workspace
     int krylov_m = 0;
     DevBuf V, Z, w, partial, hdev, ydev, bpad, xpad, canon_tmp;
+    double* hhost = nullptr;          // mapped pinned mirror of the Gram-Schmidt results
+    double* hhost_dev = nullptr;      // its device address
 };
 
 namespace biot {
@@ -152,7 +155,7 @@ static void level_alloc(Level& lv, int n, hipStream_t st) {
     const size_t len = (size_t)lv.L.len;
     lv.kinv64.alloc(2 * lv.L.plane * sizeof(double));
     lv.kinv32.alloc(2 * lv.L.plane * sizeof(float));
-    for (DevBuf* b : {&lv.x64, &lv.b64, &lv.r64, &lv.t64}) {
+    for (DevBuf* b : {&lv.x64, &lv.b64, &lv.r64, &lv.t64, &lv.x2_64}) {
         b->alloc(len * sizeof(double));
         launch_fill(b->as<double>(), lv.L.len, 0.0, st);
     }
@@ -224,7 +227,8 @@ static void level_patch_data(Level& lv, bool uniform, double Kinv, hipStream_t s
     upload(lv.cls32, convert_classes<float>(cls), st);
     upload(lv.wblk64, wblk, st);
     if (uniform) {
-        // deflated inverse of each class's patch matrix, column by column
+        // inverse of each class's patch matrix, column by column (zero rows and columns on
+        // absent DoFs; zero for the pressure-only corner classes)
         std::vector<double> minv(9 * PATCH * PATCH, 0.0);
         const double kv[6] = {Kinv, Kinv, Kinv, Kinv, Kinv, Kinv};
         for (int k = 0; k < 9; ++k)
@@ -232,7 +236,7 @@ static void level_patch_data(Level& lv, bool uniform, double Kinv, hipStream_t s
                 if (!c64[k].present[j]) continue;
                 double e[PATCH] = {0}, col[PATCH];
                 e[j] = 1.0;
-                patch_solve<double>(e, c64[k], kv, wblk.data(), col, 1, false);
+                patch_solve<double>(e, c64[k], kv, wblk.data(), col, 1);
                 for (int a = 0; a < PATCH; ++a) minv[(k * PATCH + a) * PATCH + j] = c64[k].present[a] ? col[a] : 0.0;
             }
         upload(lv.minv64, minv, st);
@@ -352,34 +356,46 @@ static void prof_end(hipEvent_t stop, hipStream_t st) {
     if (stop) BIOT_HIP(hipEventRecord(stop, st));
 }
 
+// The two iterate buffers of a level (the fused Vanka step reads one and writes the other).
 template <typename T>
-static void smooth_step(biot_ctx* c, int l, T* x, const T* b, T* r, bool x_is_zero, hipStream_t st) {
+struct XBuf;
+template <>
+struct XBuf<double> {
+    static double* get(Level& l, int k) { return (k ? l.x2_64 : l.x64).as<double>(); }
+};
+template <>
+struct XBuf<float> {
+    static float* get(Level& l, int k) { return (k ? l.x2_32 : l.x32).as<float>(); }
+};
+
+// One relaxation step on level l from the iterate x (nullptr: zero).  Vanka writes the new
+// iterate to dst (dst != x); BSR updates in place (dst == x, or x == nullptr).  Returns dst.
+template <typename T>
+static T* relax(biot_ctx* c, int l, const T* x, const T* b, T* dst, hipStream_t st) {
     Level& lv = *c->levels[l];
     LevelView<T> v = lv.view<T>();
     const T om = (T)c->opts.omega;
     if (c->opts.smoother == BIOT_SMOOTHER_VANKA) {
-        const T* rr = b;
-        if (!x_is_zero) {
-            hipEvent_t e1 = prof_begin(c, 1, l, st);
-            launch_apply<T>(v, x, b, r, 1, st);
-            prof_end(e1, st);
-            rr = r;
-        }
-        hipEvent_t e0 = x_is_zero ? nullptr : prof_begin(c, 0, l, st);
-        if (c->K_uniform)
-            launch_vanka_uniform<T>(v, rr, x, om, x_is_zero ? 1 : 0, st);
-        else
-            launch_vanka<T>(v, rr, x, om, x_is_zero ? 1 : 0, st);
+        hipEvent_t e0 = x ? prof_begin(c, 0, l, st) : nullptr;
+        launch_vanka_step<T>(v, x, b, dst, c->K_uniform, (T)(1.0 / c->K_scalar), om, st);
         prof_end(e0, st);
-    } else {
-        const T* rr = b;
-        if (!x_is_zero) {
-            launch_apply<T>(v, x, b, r, 1, st);
-            rr = r;
-        }
-        T* t = VecSet<T>::s(lv);
-        launch_bsr<T>(v, rr, t, x, om, (T)c->opts.omega_J, x_is_zero ? 1 : 0, st);
+        return dst;
     }
+    const T* rr = b;
+    if (x) {
+        T* r = VecSet<T>::r(lv);
+        launch_apply<T>(v, dst, b, r, 1, st);
+        rr = r;
+    }
+    launch_bsr<T>(v, rr, VecSet<T>::s(lv), dst, om, (T)c->opts.omega_J, x ? 0 : 1, st);
+    return dst;
+}
+
+// Times the iterate moves to the other buffer during the smoothing on one level (the first
+// step from zero writes buffer 0).
+static int buffer_moves(const biot_mg_opts& o) {
+    if (o.smoother != BIOT_SMOOTHER_VANKA) return 0;
+    return (o.nu1 > 0 ? o.nu1 - 1 : 0) + o.nu2;
 }
 
 template <typename T>
@@ -393,37 +409,50 @@ struct PW<float> {
     static const float* get(biot_ctx* c) { return c->pw32.as<float>(); }
 };
 
+// V(nu1, nu2) cycle on level l for A_l x = b from x = 0, iterate buffers buf0 / buf1 (both zero
+// on absent DoFs).  Returns the buffer that holds the result.
 template <typename T>
-static void vcycle_level(biot_ctx* c, int l, hipStream_t st) {
+static T* vcycle_level(biot_ctx* c, int l, const T* b, T* buf0, T* buf1, hipStream_t st) {
     Level& lv = *c->levels[l];
-    T* x = VecSet<T>::x(lv);
-    T* b = VecSet<T>::b(lv);
-    T* r = VecSet<T>::r(lv);
     if (l == (int)c->levels.size() - 1) {
-        launch_coarse_solve<T>(c->coarse_inv.as<double>(), c->coarse_N, c->coarse_idx.as<int>(), b, x, st);
-        return;
+        launch_coarse_solve<T>(c->coarse_inv.as<double>(), c->coarse_N, c->coarse_idx.as<int>(), b, buf0, st);
+        return buf0;
+    }
+    const bool inplace = c->opts.smoother != BIOT_SMOOTHER_VANKA;
+    T* cur = nullptr;
+    auto next = [&]() { return cur == nullptr ? buf0 : (inplace ? cur : (cur == buf0 ? buf1 : buf0)); };
+    for (int s = 0; s < c->opts.nu1; ++s) cur = relax<T>(c, l, cur, b, next(), st);
+    if (!cur) {
+        launch_fill(buf0, lv.L.len, (T)0, st);
+        cur = buf0;
     }
     Level& lc = *c->levels[l + 1];
-    for (int s = 0; s < c->opts.nu1; ++s) smooth_step<T>(c, l, x, b, r, s == 0, st);
-    if (c->opts.nu1 == 0) launch_fill(x, lv.L.len, (T)0, st);
-    launch_apply<T>(lv.view<T>(), x, b, r, 1, st);
-    launch_restrict<T>(lv.L, lc.L, r, VecSet<T>::b(lc), PW<T>::get(c), st);
-    vcycle_level<T>(c, l + 1, st);
-    launch_prolong_add<T>(lv.L, lc.L, VecSet<T>::x(lc), x, PW<T>::get(c), st);
-    for (int s = 0; s < c->opts.nu2; ++s) smooth_step<T>(c, l, x, b, r, false, st);
+    T* r = VecSet<T>::r(lv);
+    hipEvent_t e1 = prof_begin(c, 1, l, st);
+    launch_apply<T>(lv.view<T>(), cur, b, r, 1, st);
+    prof_end(e1, st);
+    T* bc = VecSet<T>::b(lc);
+    launch_restrict<T>(lv.L, lc.L, r, bc, PW<T>::get(c), st);
+    T* xc = vcycle_level<T>(c, l + 1, bc, XBuf<T>::get(lc, 0), XBuf<T>::get(lc, 1), st);
+    launch_prolong_add<T>(lv.L, lc.L, xc, cur, PW<T>::get(c), st);
+    for (int s = 0; s < c->opts.nu2; ++s) cur = relax<T>(c, l, cur, b, next(), st);
+    return cur;
 }
 
-// z = M^{-1} v on padded FP64 vectors of level 0 (v is not modified).
+// z = M^{-1} v on padded FP64 vectors of level 0 (v is not modified; z is zero on absent DoFs
+// and may be used as an iterate buffer).
 static void precond(biot_ctx* c, const double* v, double* z, hipStream_t st) {
     Level& l0 = *c->levels[0];
     if (c->opts.precision == BIOT_PREC_FP64) {
-        BIOT_HIP(hipMemcpyAsync(l0.b64.p, v, l0.L.len * sizeof(double), hipMemcpyDeviceToDevice, st));
-        vcycle_level<double>(c, 0, st);
-        BIOT_HIP(hipMemcpyAsync(z, l0.x64.p, l0.L.len * sizeof(double), hipMemcpyDeviceToDevice, st));
+        // start in the buffer that makes the last step land in z
+        const bool even = buffer_moves(c->opts) % 2 == 0;
+        double* other = l0.x64.as<double>();
+        double* res = vcycle_level<double>(c, 0, v, even ? z : other, even ? other : z, st);
+        if (res != z) BIOT_HIP(hipMemcpyAsync(z, res, l0.L.len * sizeof(double), hipMemcpyDeviceToDevice, st));
     } else {
         launch_convert(v, l0.b32.as<float>(), l0.L.len, st);
-        vcycle_level<float>(c, 0, st);
-        launch_convert(l0.x32.as<float>(), z, l0.L.len, st);
+        float* res = vcycle_level<float>(c, 0, l0.b32.as<float>(), l0.x32.as<float>(), l0.x2_32.as<float>(), st);
+        launch_convert(res, z, l0.L.len, st);
     }
 }
 
@@ -431,7 +460,7 @@ static void alloc_fp32(biot_ctx* c, hipStream_t st) {
     for (auto& lp : c->levels) {
         Level& lv = *lp;
         if (lv.x32.p) continue;
-        for (DevBuf* b : {&lv.x32, &lv.b32, &lv.r32}) {
+        for (DevBuf* b : {&lv.x32, &lv.b32, &lv.r32, &lv.x2_32}) {
             b->alloc((size_t)lv.L.len * sizeof(float));
             launch_fill(b->as<float>(), lv.L.len, 0.0f, st);
         }
@@ -439,27 +468,43 @@ static void alloc_fp32(biot_ctx* c, hipStream_t st) {
 }
 
 // ---- FGMRES (Sec. 5.1), CGS2 Arnoldi, host Givens rotations ---------------------------------------
-static double dot_dev(biot_ctx* c, const double* a, const double* b, long long n, hipStream_t st) {
-    launch_multidot(a, n, 1, b, n, c->partial.as<double>(), RED_BLOCKS, st);
-    launch_reduce_partials(c->partial.as<double>(), RED_BLOCKS, 1, c->hdev.as<double>(), 0, st);
-    double h = 0;
-    BIOT_HIP(hipMemcpyAsync(&h, c->hdev.p, sizeof(double), hipMemcpyDeviceToHost, st));
-    BIOT_HIP(hipStreamSynchronize(st));
-    return h;
-}
+// Layout of the Gram-Schmidt results (device hdev, host mirror hhost), restart m:
+//   [0, m+1]: pass-1 dots V_i . w (i <= j) and w . w;  [m+2, 2m+3]: pass-2 dots;
+//   2m+4: |w|^2 after pass 1;  2m+5: second-pass flag;  2m+6: |w|^2 after pass 2;  2m+7: scratch
+static int kslot_n1(int m) { return 2 * m + 4; }
+static int kslot_flag(int m) { return 2 * m + 5; }
+static int kslot_n2(int m) { return 2 * m + 6; }
+static int kslot_tmp(int m) { return 2 * m + 7; }
 
-static void krylov_alloc(biot_ctx* c, int m) {
+static void krylov_alloc(biot_ctx* c, int m, hipStream_t st) {
     if (c->krylov_m >= m) return;
     const Layout& L = c->levels[0]->L;
     c->V.alloc((size_t)(m + 1) * L.len * sizeof(double));
     c->Z.alloc((size_t)m * L.len * sizeof(double));
+    // absent DoFs stay zero in every Krylov vector (the kernels never write them)
+    launch_fill(c->V.as<double>(), (long long)(m + 1) * L.len, 0.0, st);
+    launch_fill(c->Z.as<double>(), (long long)m * L.len, 0.0, st);
     c->w.alloc((size_t)L.len * sizeof(double));
-    c->partial.alloc((size_t)RED_BLOCKS * (m + 2) * sizeof(double));
-    c->hdev.alloc((size_t)(2 * m + 4) * sizeof(double));
+    c->partial.alloc((size_t)RED_BLOCKS * std::max(m + 2, 4) * sizeof(double));
+    c->hdev.alloc((size_t)(2 * m + 8) * sizeof(double));
     c->ydev.alloc((size_t)(m + 1) * sizeof(double));
     c->bpad.alloc((size_t)L.len * sizeof(double));
     c->xpad.alloc((size_t)L.len * sizeof(double));
+    if (c->hhost) BIOT_HIP(hipHostFree(c->hhost));
+    c->hhost = nullptr;
+    BIOT_HIP(hipHostMalloc((void**)&c->hhost, (size_t)(2 * m + 8) * sizeof(double),
+                           hipHostMallocMapped | hipHostMallocCoherent));
+    BIOT_HIP(hipHostGetDevicePointer((void**)&c->hhost_dev, c->hhost, 0));
     c->krylov_m = m;
+}
+
+// |a|^2 (synchronizes the stream)
+static double norm2_dev(biot_ctx* c, const double* a, long long n, hipStream_t st) {
+    const int m = c->krylov_m;
+    launch_gs_dots(nullptr, 0, 0, a, n, c->partial.as<double>(), c->hdev.as<double>() + kslot_tmp(m),
+                   c->hhost_dev + kslot_tmp(m), nullptr, st);
+    BIOT_HIP(hipStreamSynchronize(st));
+    return c->hhost[kslot_tmp(m)];
 }
 
 static int fgmres(biot_ctx* c, const double* b_canon, double* x_canon, biot_solve_info* info, hipStream_t st) {
@@ -467,17 +512,20 @@ static int fgmres(biot_ctx* c, const double* b_canon, double* x_canon, biot_solv
     const Layout& L = l0.L;
     const long long n = L.len;
     const int m = info->restart;
-    krylov_alloc(c, m);
+    krylov_alloc(c, m, st);
+    const int M = c->krylov_m;                // layout of the result slots
     double* V = c->V.as<double>();
     double* Z = c->Z.as<double>();
     double* w = c->w.as<double>();
     double* b = c->bpad.as<double>();
     double* x = c->xpad.as<double>();
     double* hd = c->hdev.as<double>();
+    double* hh = c->hhost_dev;
+    const double* hhost = c->hhost;
     double* part = c->partial.as<double>();
     launch_pack(b_canon, b, L, l0.C, st);
     launch_fill(x, n, 0.0, st);
-    const double bnorm = std::sqrt(dot_dev(c, b, b, n, st));
+    const double bnorm = std::sqrt(norm2_dev(c, b, n, st));
     info->iters = 0;
     info->converged = 0;
     info->rel_res_true = 0;
@@ -491,7 +539,7 @@ static int fgmres(biot_ctx* c, const double* b_canon, double* x_canon, biot_solv
     // r = b - A x  (x = 0 -> r = b)
     BIOT_HIP(hipMemcpyAsync(w, b, n * sizeof(double), hipMemcpyDeviceToDevice, st));
     double beta = bnorm;
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2), y(m);
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
     int it = 0;
     while (true) {
         if (beta <= tol * bnorm) {
@@ -511,22 +559,20 @@ static int fgmres(biot_ctx* c, const double* b_canon, double* x_canon, biot_solv
             double* zj = Z + (size_t)j * n;
             precond(c, vj, zj, st);
             launch_apply<double>(l0.view<double>(), zj, nullptr, w, 0, st);
-            // CGS2: two passes of classical Gram-Schmidt
-            launch_multidot(V, n, j + 1, w, n, part, RED_BLOCKS, st);
-            launch_reduce_partials(part, RED_BLOCKS, j + 1, hd, 0, st);
-            launch_update(w, V, n, j + 1, hd, n, st);
-            launch_multidot(V, n, j + 1, w, n, part, RED_BLOCKS, st);
-            launch_reduce_partials(part, RED_BLOCKS, j + 1, hd + m + 1, 0, st);
-            launch_update(w, V, n, j + 1, hd + m + 1, n, st);
-            launch_multidot(w, n, 1, w, n, part, RED_BLOCKS, st);
-            launch_reduce_partials(part, RED_BLOCKS, 1, hd + 2 * m + 2, 0, st);
-            launch_scale_inv_sqrt(V + (size_t)(j + 1) * n, w, n, hd + 2 * m + 2, st);
+            // CGS with a second pass when the first one cancels (|w| drops below |w_0| / sqrt 2)
+            launch_gs_dots(V, n, j + 1, w, n, part, hd, hh, nullptr, st);
+            launch_gs_update(w, V, n, j + 1, hd, n, part, hd + kslot_n1(M), hd + j + 1, hd + kslot_flag(M),
+                             hh + kslot_n1(M), nullptr, st);
+            launch_gs_dots(V, n, j + 1, w, n, part, hd + M + 2, hh + M + 2, hd + kslot_flag(M), st);
+            launch_gs_update(w, V, n, j + 1, hd + M + 2, n, part, hd + kslot_n2(M), nullptr, nullptr,
+                             hh + kslot_n2(M), hd + kslot_flag(M), st);
+            launch_normalize(V + (size_t)(j + 1) * n, w, n, hd + kslot_n1(M), hd + kslot_n2(M), hd + kslot_flag(M),
+                             st);
             check_stream_error();
-            std::vector<double> hh(2 * m + 3);
-            BIOT_HIP(hipMemcpyAsync(hh.data(), hd, (2 * m + 3) * sizeof(double), hipMemcpyDeviceToHost, st));
             BIOT_HIP(hipStreamSynchronize(st));
-            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[m + 1 + i];
-            const double hn = std::sqrt(hh[2 * m + 2]);
+            const bool second = hhost[kslot_flag(M)] != 0.0;
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hhost[i] + (second ? hhost[M + 2 + i] : 0.0);
+            const double hn = std::sqrt(second ? hhost[kslot_n2(M)] : hhost[kslot_n1(M)]);
             H[(size_t)(j + 1) * m + j] = hn;
             for (int i = 0; i <= j + 1; ++i)
                 if (!(H[(size_t)i * m + j] == H[(size_t)i * m + j])) throw std::domain_error("NaN in Arnoldi");
@@ -550,7 +596,7 @@ static int fgmres(biot_ctx* c, const double* b_canon, double* x_canon, biot_solv
                 break;
             }
         }
-        (void)stop;
+    (void)stop;
         // y = H^{-1} g (upper triangular k x k), x += Z y
         for (int i = k - 1; i >= 0; --i) {
             double s = g[i];
@@ -561,7 +607,7 @@ static int fgmres(biot_ctx* c, const double* b_canon, double* x_canon, biot_solv
         launch_lincomb_add(x, Z, n, k, c->ydev.as<double>(), n, st);
         // true residual
         launch_apply<double>(l0.view<double>(), x, b, w, 1, st);
-        beta = std::sqrt(dot_dev(c, w, w, n, st));
+        beta = std::sqrt(norm2_dev(c, w, n, st));
         if (!(beta == beta)) throw std::domain_error("NaN in residual");
     }
     info->iters = it;
@@ -732,8 +778,8 @@ int biot_vcycle(biot_ctx* c, const double* r, double* z, void* stream) {
         require(r && z && r != z, "r and z must be distinct non-null device pointers");
         hipStream_t st = S(stream);
         Level& l0 = *c->levels[0];
-        launch_pack(r, l0.t64.as<double>(), l0.L, l0.C, st);
-        precond(c, l0.t64.as<double>(), l0.t64.as<double>(), st);
+        launch_pack(r, l0.b64.as<double>(), l0.L, l0.C, st);
+        precond(c, l0.b64.as<double>(), l0.t64.as<double>(), st);
         launch_unpack(l0.t64.as<double>(), z, l0.L, l0.C, st);
         check_stream_error();
         return BIOT_OK;
@@ -776,15 +822,19 @@ int biot_smooth(biot_ctx* c, int level, double* x, const double* b, void* stream
         Level& lv = *c->levels[level];
         launch_pack(x, lv.x64.as<double>(), lv.L, lv.C, st);
         launch_pack(b, lv.b64.as<double>(), lv.L, lv.C, st);
+        const bool vanka = c->opts.smoother == BIOT_SMOOTHER_VANKA;
         if (c->opts.precision == BIOT_PREC_FP64) {
-            smooth_step<double>(c, level, lv.x64.as<double>(), lv.b64.as<double>(), lv.r64.as<double>(), false, st);
+            double* x0 = lv.x64.as<double>();
+            double* res = relax<double>(c, level, x0, lv.b64.as<double>(), vanka ? lv.x2_64.as<double>() : x0, st);
+            launch_unpack(res, x, lv.L, lv.C, st);
         } else {
-            launch_convert(lv.x64.as<double>(), lv.x32.as<float>(), lv.L.len, st);
+            float* x0 = lv.x32.as<float>();
+            launch_convert(lv.x64.as<double>(), x0, lv.L.len, st);
             launch_convert(lv.b64.as<double>(), lv.b32.as<float>(), lv.L.len, st);
-            smooth_step<float>(c, level, lv.x32.as<float>(), lv.b32.as<float>(), lv.r32.as<float>(), false, st);
-            launch_convert(lv.x32.as<float>(), lv.x64.as<double>(), lv.L.len, st);
+            float* res = relax<float>(c, level, x0, lv.b32.as<float>(), vanka ? lv.x2_32.as<float>() : x0, st);
+            launch_convert(res, lv.x64.as<double>(), lv.L.len, st);
+            launch_unpack(lv.x64.as<double>(), x, lv.L, lv.C, st);
         }
-        launch_unpack(lv.x64.as<double>(), x, lv.L, lv.C, st);
         check_stream_error();
         return BIOT_OK;
     });

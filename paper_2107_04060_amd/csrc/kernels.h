@@ -25,7 +25,7 @@ struct LevelView {
     const T* wblk;                 // 6 x 2 x 2 RT0-mass blocks of the star triangles (1/K = 1)
     const T* uinv;                 // 9 x 8 x 8 displacement-patch inverses (BSR; identity on absent DoFs)
     const T* bsrd;                 // BSR diagonal data, 5 planes (k_bsr_wdiag / k_bsr_sdiag)
-    const T* minv;                 // 9 x 20 x 20 deflated patch inverses (uniform K), or null
+    const T* minv;                 // 9 x 20 x 20 full patch inverses (uniform K), or null
 };
 
 // vector plumbing
@@ -40,9 +40,13 @@ void launch_convert(const float* src, double* dst, long long n, hipStream_t st);
 template <typename T>
 void launch_apply(const LevelView<T>& lv, const T* x, const T* b, T* y, int mode, hipStream_t st);
 
-// additive Vanka step: x <- (x_is_zero ? 0 : x) + omega * sum_l V_l^T D_l A_l^{-1} V_l r
+// fused residual + additive Vanka step (Sec. 3.2.1):
+//   x_out = x_in + omega * sum_l V_l^T D_l A_l^{-1} V_l (b - A x_in)
+// x_in == nullptr means x_in = 0.  x_out must not alias x_in.  uniform: one patch inverse per
+// vertex class (lv.minv, full inverses), 1/K = kinv_s; else per-patch elimination with lv.kinv.
 template <typename T>
-void launch_vanka(const LevelView<T>& lv, const T* r, T* x, T omega, int x_is_zero, hipStream_t st);
+void launch_vanka_step(const LevelView<T>& lv, const T* x_in, const T* b, T* x_out, bool uniform, T kinv_s,
+                       T omega, hipStream_t st);
 
 // grid transfers
 // (w: the NPWEIGHTS prolongation weights of structure.h, device)
@@ -50,11 +54,6 @@ template <typename T>
 void launch_restrict(const Layout& Lf, const Layout& Lc, const T* rf, T* rc, const T* w, hipStream_t st);
 template <typename T>
 void launch_prolong_add(const Layout& Lf, const Layout& Lc, const T* xc, T* xf, const T* w, hipStream_t st);
-
-// additive Vanka with one deflated patch inverse per vertex class (uniform permeability):
-// xhat = Minv[class] r_patch + gamma 1_p, gamma = -sum(r_p) / sum(c)
-template <typename T>
-void launch_vanka_uniform(const LevelView<T>& lv, const T* r, T* x, T omega, int x_is_zero, hipStream_t st);
 
 // inexact Braess-Sarazin: diagonal data of a level (1 / (tau D_w), 1 / diag(S)); cS =
 // (1/M + alpha^2 / (lambda + mu)) |T|
@@ -77,16 +76,22 @@ void launch_kinv_from_K(const double* K_tri, double K_scalar, double* kinv, cons
 void launch_kinv_coarsen(const double* kf, const Layout& Lf, double* kc, const Layout& Lc, hipStream_t st);
 
 // Krylov BLAS-1 (FP64)
-void launch_multidot(const double* V, long long ldv, int nv, const double* w, long long n, double* partial,
-                     int nblk, hipStream_t st);
-void launch_reduce_partials(const double* partial, int nblk, int nv, double* out, int accumulate,
-                            hipStream_t st);
-void launch_update(double* w, const double* V, long long ldv, int nv, const double* h, long long n,
-                   hipStream_t st);
 void launch_scale(double* dst, const double* src, long long n, double s, hipStream_t st);
-void launch_scale_inv_sqrt(double* dst, const double* src, long long n, const double* norm2, hipStream_t st);
 void launch_lincomb_add(double* x, const double* Z, long long ldz, int nv, const double* y, long long n,
                         hipStream_t st);
+// one classical Gram-Schmidt pass, each call two launches (partial sums, then a fixed-order
+// reduction; partial: max(RED_BLOCKS x (nv + 1), 4 RED_BLOCKS) doubles).  dots: out[q] = V_q . w,
+// out[nv] = w . w.  update: w -= V h, norm2 = w . w, flag (optional) = (norm2 < 0.5 prev).
+// host: optional mirror of the outputs (mapped memory; flag goes to host[1]).  run_if: every
+// launch returns at once when *run_if == 0.
+void launch_gs_dots(const double* V, long long ldv, int nv, const double* w, long long n, double* partial,
+                    double* out, double* host, const double* run_if, hipStream_t st);
+void launch_gs_update(double* w, const double* V, long long ldv, int nv, const double* h, long long n,
+                      double* partial, double* norm2, const double* prev, double* flag, double* host,
+                      const double* run_if, hipStream_t st);
+// dst = src / sqrt(*na), or / sqrt(*nb) when sel != nullptr and *sel != 0
+void launch_normalize(double* dst, const double* src, long long n, const double* na, const double* nb,
+                      const double* sel, hipStream_t st);
 
 // adjoint: per-triangle  1/K_T * lam_w|_T^T  Mloc_T  w|_T  (Mloc: 2 types x 3 x 3)
 void launch_grad_logK(const Layout& L, const double* x, const double* lam, const double* kinv,
@@ -95,6 +100,6 @@ void launch_grad_logK(const Layout& L, const double* x, const double* lam, const
 // layout export
 void launch_patch_table(const Layout& L, const Canon& C, int* table, hipStream_t st);
 
-constexpr int RED_BLOCKS = 1024;
+constexpr int RED_BLOCKS = 1024;  // Gram-Schmidt partial sums: RED_BLOCKS x (vectors + 1), >= 4 RED_BLOCKS
 
 }  // namespace biot

@@ -7,11 +7,18 @@
 #include "patch_solve.h"
 #include "structure.h"
 
+#include <type_traits>
 #include <utility>
 
 #include <hip/hip_runtime.h>
 
 namespace biot {
+
+// compile-time loop: f(std::integral_constant<int, T>) for every T of the sequence
+template <int... Ts, typename F>
+__device__ __forceinline__ void static_for(std::integer_sequence<int, Ts...>, F&& f) {
+    (f(std::integral_constant<int, Ts>{}), ...);
+}
 
 // =========================================================================================
 // vector plumbing
@@ -163,40 +170,49 @@ template void launch_apply<double>(const LevelView<double>&, const double*, cons
 template void launch_apply<float>(const LevelView<float>&, const float*, const float*, float*, int, hipStream_t);
 
 // =========================================================================================
-// additive Vanka (Sec. 3.2.1)
+// additive Vanka (Sec. 3.2.1), fused with the residual
 // =========================================================================================
-constexpr int VT = 16;       // patches per tile side (threads)
+// One step  x_out = x_in + omega sum_l V_l^T D_l A_l^{-1} V_l (b - A x_in)  per launch.  A block
+// of 16 x 16 threads handles a tile of VT x VT vertices starting at (i0, j0) and owns the slots
+// of its first VO x VO vertices.  Every thread forms the residual of one slot of
+// (i0-1 .. i0+VT)^2 from x_in staged in LDS on a two-slot halo; the threads of the VT x VT
+// vertices solve their patches; the owned slots gather the weighted corrections.  x_in and
+// x_out are different buffers (neighbouring tiles read x_in on the halo).  ZERO: x_in = 0, the
+// residual is b and x_in is not read.
+constexpr int TB = 16;       // threads per block side
+constexpr int TPB = TB * TB; // threads per block
+constexpr int VT = TB - 1;   // vertices per tile side
 constexpr int VO = VT - 1;   // owned slots per tile side
+constexpr int XS = VT + 3;   // staged x_in: slots i0-2 .. i0+VT
+constexpr int RW = VT + 1;   // residual: slots i0-1 .. i0+VT-1 (one per thread)
+constexpr int KW = VT + 2;   // staged 1/K: slots i0-2 .. i0+VT-1
+static_assert(RW == TB, "one residual slot per thread");
 
-// Stage the residual of slots (i0-1 .. i0+VT-1) x (j0-1 .. j0+VT-1) into LDS; the loop has a
-// constant trip count and is unrolled so that all loads are in flight together.
-template <typename T>
-__device__ __forceinline__ void stage_residual(const T* __restrict__ r, const Layout& L, int i0, int j0, int tid,
-                                               T (&sr)[NTYPES][VT + 1][VT + 1]) {
-    constexpr int TS = (VT + 1) * (VT + 1);
-    constexpr int NV = NTYPES * TS;
-    constexpr int NIT = (NV + VT * VT - 1) / (VT * VT);
+// Loads of NP planes of a W x W slot window starting at slot (s0i, s0j) (zero outside the
+// padded plane), kept in registers so that all loads of a phase are in flight together.
+template <typename T, int NP, int W>
+struct Window {
+    static constexpr int NV = NP * W * W;
+    static constexpr int NIT = (NV + TPB - 1) / TPB;
     T v[NIT];
+    __device__ __forceinline__ void load(const T* __restrict__ src, long long plane, const Layout& L, int s0i,
+                                         int s0j, int tid) {
 #pragma unroll
-    for (int it = 0; it < NIT; ++it) {
-        const int q = tid + it * VT * VT;
-        const int t = q / TS, rem = q - t * TS, bb = rem / (VT + 1), aa = rem - bb * (VT + 1);
-        const int si = i0 - 1 + aa, sj = j0 - 1 + bb;
-        v[it] = (q < NV && si <= L.n + 1 && sj <= L.n + 1) ? r[t * L.plane + slot_index(L, si, sj)] : (T)0;
+        for (int it = 0; it < NIT; ++it) {
+            const int q = tid + it * TPB;
+            const int p = q / (W * W), rem = q - p * (W * W), bj = rem / W, ai = rem - bj * W;
+            const int si = s0i + ai, sj = s0j + bj;
+            v[it] = (q < NV && si <= L.n + 1 && sj <= L.n + 1) ? src[p * plane + slot_index(L, si, sj)] : (T)0;
+        }
     }
+    __device__ __forceinline__ void store(T* dst, int tid) const {
 #pragma unroll
-    for (int it = 0; it < NIT; ++it) {
-        const int q = tid + it * VT * VT;
-        if (q < NV) (&sr[0][0][0])[q] = v[it];
+        for (int it = 0; it < NIT; ++it) {
+            const int q = tid + it * TPB;
+            if (q < NV) dst[q] = v[it];
+        }
     }
-}
-
-// Vertex class (0 low edge, 1 interior, 2 high edge) ranges of a tile's vertices.
-__device__ __forceinline__ void tile_classes(int v0, int n, int& lo, int& hi) {
-    lo = v0 == 0 ? 0 : 1;
-    hi = (v0 + VT - 1 >= n) ? 2 : 1;
-    if (v0 + VT - 1 < 1) hi = 0;
-}
+};
 
 __device__ inline double vanka_weight(int t, int i, int j, int n) {
     if (t <= T_UY) return 1.0;
@@ -205,220 +221,290 @@ __device__ inline double vanka_weight(int t, int i, int j, int n) {
     return (i == n - 1 && j == n - 1) ? 0.5 : 1.0 / 3.0;
 }
 
+// out = M rr for a 20 x 20 row-major M
 template <typename T>
-__global__ __launch_bounds__(256) void k_vanka(const T* __restrict__ r, T* __restrict__ x,
-                                               const T* __restrict__ kinv, Layout L,
-                                               const DevPatchClass<T>* __restrict__ cls,
-                                               const T* __restrict__ wblk, T omega, int x_is_zero) {
-    __shared__ T sr[NTYPES][VT + 1][VT + 1];
-    __shared__ T sc[PATCH][VT][VT];
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * VT + tx;
-    const int i0 = blockIdx.x * VO, j0 = blockIdx.y * VO;
-    const int n = L.n;
-    stage_residual<T>(r, L, i0, j0, tid, sr);
-    __syncthreads();
-    const int vi = i0 + tx, vj = j0 + ty;
-    bool solved = false;
-    if (vi <= n && vj <= n) {
-        const int ci = vi == 0 ? 0 : (vi == n ? 2 : 1);
-        const int cj = vj == 0 ? 0 : (vj == n ? 2 : 1);
-        const DevPatchClass<T>& pc = cls[3 * cj + ci];
-        bool keep = false;
+__device__ __forceinline__ void matvec20(const T* __restrict__ M, const T (&rr)[PATCH], T (&out)[PATCH]) {
 #pragma unroll
-        for (int s = 0; s < 14; ++s) keep = keep || pc.present[s];
-        if (keep) {
-            T rr[PATCH];
+    for (int a = 0; a < PATCH; ++a) {
+        T v = 0;
 #pragma unroll
-            for (int s = 0; s < PATCH; ++s) {
-                int t, di, dj;
-                patch_slot(s, t, di, dj);
-                rr[s] = sr[t][ty + 1 + dj][tx + 1 + di];
-            }
-            T kv[6];
-#pragma unroll
-            for (int kq = 0; kq < 6; ++kq) {
-                int ut, di, dj;
-                star_tri(kq, ut, di, dj);
-                kv[kq] = kinv[ut * L.plane + slot_index(L, vi + di, vj + dj)];
-            }
-            patch_solve<T>(rr, pc, kv, wblk, &sc[0][ty][tx], VT * VT);
-            solved = true;
-        }
-    }
-    if (!solved)
-#pragma unroll
-        for (int s = 0; s < PATCH; ++s) sc[s][ty][tx] = 0;
-    __syncthreads();
-    if (tx < VO && ty < VO) {
-        const int si = i0 + tx, sj = j0 + ty;
-        if (si <= n && sj <= n) {
-            T c[NTYPES];
-            c[T_UX] = sc[0][ty][tx];
-            c[T_UY] = sc[1][ty][tx];
-            c[T_BH] = sc[3][ty][tx] + sc[2][ty][tx + 1];
-            c[T_BV] = sc[5][ty][tx] + sc[4][ty + 1][tx];
-            c[T_BD] = sc[6][ty][tx + 1] + sc[7][ty + 1][tx];
-            c[T_WH] = sc[9][ty][tx] + sc[8][ty][tx + 1];
-            c[T_WV] = sc[11][ty][tx] + sc[10][ty + 1][tx];
-            c[T_WD] = sc[12][ty][tx + 1] + sc[13][ty + 1][tx];
-            c[T_PL] = sc[14][ty][tx] + sc[15][ty][tx + 1] + sc[16][ty + 1][tx];
-            c[T_PU] = sc[17][ty + 1][tx + 1] + sc[18][ty][tx + 1] + sc[19][ty + 1][tx];
-            const long long s0 = slot_index(L, si, sj);
-            T old[NTYPES];
-#pragma unroll
-            for (int t = 0; t < NTYPES; ++t) old[t] = x_is_zero ? (T)0 : x[t * L.plane + s0];
-#pragma unroll
-            for (int t = 0; t < NTYPES; ++t)
-                if (dof_free(t, si, sj, n))
-                    x[t * L.plane + s0] = old[t] + omega * (T)vanka_weight(t, si, sj, n) * c[t];
-        }
+        for (int b2 = 0; b2 < PATCH; ++b2) v += M[a * PATCH + b2] * rr[b2];
+        out[a] = v;
     }
 }
 
-template <typename T>
-void launch_vanka(const LevelView<T>& lv, const T* r, T* x, T omega, int x_is_zero, hipStream_t st) {
-    dim3 blk(VT, VT);
-    dim3 grd((lv.L.n + 1 + VO - 1) / VO, (lv.L.n + 1 + VO - 1) / VO);
-    hipLaunchKernelGGL(k_vanka<T>, grd, blk, 0, st, r, x, lv.kinv, lv.L, lv.cls, lv.wblk, omega, x_is_zero);
+// LDS offset of patch slot s relative to the residual entry of its vertex (rs[0][vj+1][vi+1])
+__host__ __device__ constexpr int pslot_off(int s) {
+    const int tt[PATCH] = {T_UX, T_UY, T_BH, T_BH, T_BV, T_BV, T_BD, T_BD, T_WH, T_WH,
+                           T_WV, T_WV, T_WD, T_WD, T_PL, T_PL, T_PL, T_PU, T_PU, T_PU};
+    const int ddi[PATCH] = {0, 0, -1, 0, 0, 0, -1, 0, -1, 0, 0, 0, -1, 0, 0, -1, 0, -1, -1, 0};
+    const int ddj[PATCH] = {0, 0, 0, 0, -1, 0, 0, -1, 0, 0, -1, 0, 0, -1, 0, 0, -1, -1, 0, -1};
+    return tt[s] * RW * RW + ddj[s] * RW + ddi[s];
 }
-template void launch_vanka<double>(const LevelView<double>&, const double*, double*, double, int, hipStream_t);
-template void launch_vanka<float>(const LevelView<float>&, const float*, float*, float, int, hipStream_t);
 
-// Uniform permeability: every patch of a vertex class has the same matrix; its deflated
-// inverse (the patch inverse with the star-mean pressure mode removed, built on the host by
-// the same elimination) is applied as a 20 x 20 product, and the star-mean pressure is added
-// in closed form.
-template <typename T>
-__global__ __launch_bounds__(256) void k_vanka_uniform(const T* __restrict__ r, T* __restrict__ x, Layout L,
-                                                       const DevPatchClass<T>* __restrict__ cls,
-                                                       const T* __restrict__ minv, T omega, int x_is_zero) {
-    __shared__ T sr[NTYPES][VT + 1][VT + 1];
-    __shared__ T acc[NTYPES][VT][VT];
-    __shared__ T ms[9][PATCH * PATCH];
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * VT + tx;
+// Class-inverse application on the matrix cores (FP64 16x16x4 MFMA), one wave per row of
+// the tile: out[a][p] = sum_b M[a][b] r[b][p] for the 16 patches p of a row (the patch index
+// is the column of the product, the 20 patch slots its reduction index; M padded to 32 rows).
+// Lane layouts of the instruction: A[i][k] in lane 16 k + i, B[k][j] in lane 16 k + j, and
+// the result D[i][j] in lane 16 (i % 4) + j, element i / 4 (rows l / 16 + 4 v).
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void mfma_class_frag(const double* M, int lane, double (&af)[2][5]) {
+    const int i = lane & 15, kq = lane >> 4;
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int ks = 0; ks < 5; ++ks) {
+            const int row = i + 16 * mb, col = kq + 4 * ks;
+            af[mb][ks] = row < PATCH ? M[row * PATCH + col] : 0.0;
+        }
+}
+
+// LDS of the fused step.  The staged x_in and the residual are dead once the patch residuals
+// are in registers; the patch corrections then reuse their space.
+template <typename T, bool UNIFORM, int NCLS>
+struct VankaLds {
+    union {
+        struct {
+            T xs[NTYPES][XS][XS];
+            T rs[NTYPES][RW][RW];
+        } a;
+        T so[PATCH][VT][VT];
+    } u;
+    T ks[UNIFORM ? 1 : 2][UNIFORM ? 1 : KW][UNIFORM ? 1 : KW];   // 1/K of the L, U triangles
+    T ms[UNIFORM ? NCLS : 1][UNIFORM ? PATCH * PATCH : 1];       // class inverses of the tile
+};
+
+template <typename T, bool UNIFORM, bool ZERO, int NCLS>
+__global__ __launch_bounds__(TPB) void k_vanka_step(const T* __restrict__ x_in, const T* __restrict__ b,
+                                                    T* __restrict__ x_out, Layout L, const T* __restrict__ kinv,
+                                                    T kinv_s, const T* __restrict__ coef,
+                                                    const DevPatchClass<T>* __restrict__ cls,
+                                                    const T* __restrict__ wblk, const T* __restrict__ minv,
+                                                    T omega) {
+    __shared__ VankaLds<T, UNIFORM, NCLS> sh;
+    auto& xs = sh.u.a.xs;
+    auto& rs = sh.u.a.rs;
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TB + tx;
     const int i0 = blockIdx.x * VO, j0 = blockIdx.y * VO;
     const int n = L.n;
-    stage_residual<T>(r, L, i0, j0, tid, sr);
-    // deflated inverses of the vertex classes this tile touches (one class inside the mesh)
-    int cilo, cihi, cjlo, cjhi;
-    tile_classes(i0, n, cilo, cihi);
-    tile_classes(j0, n, cjlo, cjhi);
-    for (int cj = cjlo; cj <= cjhi; ++cj)
-        for (int ci = cilo; ci <= cihi; ++ci) {
-            const int cidx = 3 * cj + ci;
+    // vertex classes of the tile (0 low edge, 1 interior, 2 high edge per direction); their
+    // matrices sit in ms[(cj - cjlo) * cw + (ci - cilo)]
+    const int cilo = i0 == 0 ? 0 : 1, cihi = (i0 + VT - 1 >= n) ? 2 : 1;
+    const int cjlo = j0 == 0 ? 0 : 1, cjhi = (j0 + VT - 1 >= n) ? 2 : 1;
+    const int cw = cihi - cilo + 1;
+    // ---- staging: b (and x_in, 1/K), class inverses ---------------------------------------------
+    {
+        if constexpr (UNIFORM) {
             constexpr int NM = PATCH * PATCH;
-            constexpr int NIT = (NM + VT * VT - 1) / (VT * VT);
-            T mv[NIT];
+            constexpr int NIT = (NM + TPB - 1) / TPB;
+            const int nc = cw * (cjhi - cjlo + 1);
+            for (int k = 0; k < nc; ++k) {
+                const int cidx = 3 * (cjlo + k / cw) + cilo + k % cw;
+                T mv[NIT];
 #pragma unroll
-            for (int it = 0; it < NIT; ++it) {
-                const int q = tid + it * VT * VT;
-                mv[it] = q < NM ? minv[cidx * NM + q] : (T)0;
-            }
+                for (int it = 0; it < NIT; ++it) {
+                    const int q = tid + it * TPB;
+                    mv[it] = q < NM ? minv[cidx * NM + q] : (T)0;
+                }
 #pragma unroll
-            for (int it = 0; it < NIT; ++it) {
-                const int q = tid + it * VT * VT;
-                if (q < NM) ms[cidx][q] = mv[it];
+                for (int it = 0; it < NIT; ++it) {
+                    const int q = tid + it * TPB;
+                    if (q < NM) sh.ms[k][q] = mv[it];
+                }
             }
         }
-#pragma unroll
-    for (int it = 0; it < NTYPES; ++it) (&acc[0][0][0])[tid + it * VT * VT] = 0;
+        Window<T, NTYPES, RW> wb;
+        wb.load(b, L.plane, L, i0 - 1, j0 - 1, tid);
+        Window<T, NTYPES, XS> wx;
+        if constexpr (!ZERO) wx.load(x_in, L.plane, L, i0 - 2, j0 - 2, tid);
+        Window<T, 2, KW> wk;
+        if constexpr (!UNIFORM) wk.load(kinv, L.plane, L, i0 - 2, j0 - 2, tid);
+        wb.store(&rs[0][0][0], tid);
+        if constexpr (!ZERO) wx.store(&xs[0][0][0], tid);
+        if constexpr (!UNIFORM) wk.store(&sh.ks[0][0][0], tid);
+    }
     __syncthreads();
+    // ---- residual r = b - A x_in of slot (i0-1+tx, j0-1+ty), zero on absent DoFs -----------------
+    if constexpr (!ZERO) {
+        const int si = i0 - 1 + tx, sj = j0 - 1 + ty;
+        const bool in = si <= n + 1 && sj <= n + 1;
+        T rv[NTYPES];
+        static_for(std::make_integer_sequence<int, NTYPES>{}, [&](auto tc) {
+            constexpr int t = decltype(tc)::value;
+            T acc = 0;
+            static_for(std::make_integer_sequence<int, SST.n[t]>{}, [&](auto ec) {
+                constexpr int e = decltype(ec)::value;
+                constexpr SEnt en = SST.e[t][e];
+                T cc = coef[SST.off[t] + e];
+                if constexpr (en.kt >= 0) {
+                    if constexpr (UNIFORM)
+                        cc *= kinv_s;
+                    else
+                        cc *= sh.ks[en.kt][ty + 1 + en.kdj][tx + 1 + en.kdi];
+                }
+                acc += cc * xs[en.in][ty + 1 + en.dj][tx + 1 + en.di];
+            });
+            rv[t] = (in && dof_free(t, si, sj, n)) ? rs[t][ty][tx] - acc : (T)0;
+        });
+#pragma unroll
+        for (int t = 0; t < NTYPES; ++t) rs[t][ty][tx] = rv[t];
+        __syncthreads();
+    }
+    // ---- patch solves of the tile's vertices ----------------------------------------------------
     const int vi = i0 + tx, vj = j0 + ty;
+    const bool patch = tx < VT && ty < VT;
+    T xown[NTYPES];
+#pragma unroll
+    for (int t = 0; t < NTYPES; ++t) xown[t] = (ZERO || !patch) ? (T)0 : xs[t][ty + 2][tx + 2];
+    if constexpr (UNIFORM && std::is_same<T, double>::value) {
+        // wave w applies the class inverses to the patches of tile rows 4 w .. 4 w + 3
+        const int lane = tid & 63, wave = tid >> 6;
+        const int jl = lane & 15, kq = lane >> 4;
+        const int pvi = i0 + jl;
+        const int ci_l = pvi == 0 ? 0 : (pvi == n ? 2 : 1);
+        const int bcol = jl < VT ? jl : VT - 1;       // column 15 holds no patch: any finite data
+        // residuals of the patches (B operand) of the wave's rows, read before the corrections
+        // overwrite the residual array
+        double bf[4][5];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int pty = min(4 * wave + r, VT - 1);
+            const double* base = &rs[0][0][0] + (pty + 1) * RW + (bcol + 1);
+#pragma unroll
+            for (int ks = 0; ks < 5; ++ks) {
+                const int o = kq == 0 ? pslot_off(4 * ks) : kq == 1 ? pslot_off(4 * ks + 1)
+                            : kq == 2 ? pslot_off(4 * ks + 2) : pslot_off(4 * ks + 3);
+                bf[r][ks] = base[o];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int pty = 4 * wave + r;
+            const int pvj = j0 + pty;
+            if (pty >= VT || pvj > n) continue;      // uniform over the wave
+            const int cj = pvj == 0 ? 0 : (pvj == n ? 2 : 1);
+            for (int ci = cilo; ci <= cihi; ++ci) {
+                double cf[2][5];
+                mfma_class_frag(sh.ms[(cj - cjlo) * cw + (ci - cilo)], lane, cf);
+                v4d acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+#pragma unroll
+                for (int ks = 0; ks < 5; ++ks) {
+                    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(cf[0][ks], bf[r][ks], acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(cf[1][ks], bf[r][ks], acc1, 0, 0, 0);
+                }
+                // rows a = kq + 4 v + 16 mb of patch (jl, pty)
+                if (ci_l == ci && jl < VT) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        sh.u.so[kq + 4 * v][pty][jl] = acc0[v];
+                        if (kq + 4 * v + 16 < PATCH) sh.u.so[kq + 4 * v + 16][pty][jl] = acc1[v];
+                    }
+                }
+            }
+        }
+    } else {
     T out[PATCH];
 #pragma unroll
     for (int s = 0; s < PATCH; ++s) out[s] = 0;
-    if (vi <= n && vj <= n) {
+    if (patch && vi <= n && vj <= n) {
         const int ci = vi == 0 ? 0 : (vi == n ? 2 : 1);
         const int cj = vj == 0 ? 0 : (vj == n ? 2 : 1);
         const int cidx = 3 * cj + ci;
-        const DevPatchClass<T>& pc = cls[cidx];
-        bool keep = false;
+        T rr[PATCH];
 #pragma unroll
-        for (int s = 0; s < 14; ++s) keep = keep || pc.present[s];
-        if (keep) {
-            T rr[PATCH];
+        for (int s = 0; s < PATCH; ++s) {
+            int t, di, dj;
+            patch_slot(s, t, di, dj);
+            rr[s] = rs[t][ty + 1 + dj][tx + 1 + di];
+        }
+        if constexpr (UNIFORM) {
+            // full patch inverse of the vertex class (zero rows and columns on absent DoFs, zero
+            // for the two pressure-only corner vertices)
+            matvec20<T>(sh.ms[(cj - cjlo) * cw + (ci - cilo)], rr, out);
+        } else {
+            const DevPatchClass<T>& pc = cls[cidx];
+            bool keep = false;
 #pragma unroll
-            for (int s = 0; s < PATCH; ++s) {
-                int t, di, dj;
-                patch_slot(s, t, di, dj);
-                rr[s] = sr[t][ty + 1 + dj][tx + 1 + di];
-            }
-            T srp = 0, csum = 0;
+            for (int s = 0; s < 14; ++s) keep = keep || pc.present[s];
+            if (keep) {
+                T kv[6];
 #pragma unroll
-            for (int q = 0; q < 6; ++q)
-                if (pc.present[14 + q]) {
-                    srp += rr[14 + q];
-                    csum += pc.c[q];
+                for (int kq = 0; kq < 6; ++kq) {
+                    int ut, di, dj;
+                    star_tri(kq, ut, di, dj);
+                    kv[kq] = sh.ks[ut][ty + 2 + dj][tx + 2 + di];
                 }
-            const T gamma = -srp / csum;
-            const T* M = ms[cidx];
-#pragma unroll
-            for (int a = 0; a < PATCH; ++a) {
-                T v = 0;
-#pragma unroll
-                for (int b2 = 0; b2 < PATCH; ++b2) v += M[a * PATCH + b2] * rr[b2];
-                out[a] = v;
+                patch_solve<T>(rr, pc, kv, wblk, out, 1);
             }
-#pragma unroll
-            for (int q = 0; q < 6; ++q)
-                if (pc.present[14 + q]) out[14 + q] += gamma;
         }
     }
-    // owned slot (a, b) collects from the patches of vertices (a..a+1, b..b+1): four
-    // conflict-free phases in a fixed order
     __syncthreads();
-    acc[T_UX][ty][tx] += out[0];
-    acc[T_UY][ty][tx] += out[1];
-    acc[T_BH][ty][tx] += out[3];
-    acc[T_BV][ty][tx] += out[5];
-    acc[T_WH][ty][tx] += out[9];
-    acc[T_WV][ty][tx] += out[11];
-    acc[T_PL][ty][tx] += out[14];
-    __syncthreads();
-    if (tx > 0) {
-        acc[T_BH][ty][tx - 1] += out[2];
-        acc[T_BD][ty][tx - 1] += out[6];
-        acc[T_WH][ty][tx - 1] += out[8];
-        acc[T_WD][ty][tx - 1] += out[12];
-        acc[T_PL][ty][tx - 1] += out[15];
-        acc[T_PU][ty][tx - 1] += out[18];
+    if (patch) {
+#pragma unroll
+        for (int s = 0; s < PATCH; ++s) sh.u.so[s][ty][tx] = out[s];
+    }
     }
     __syncthreads();
-    if (ty > 0) {
-        acc[T_BV][ty - 1][tx] += out[4];
-        acc[T_BD][ty - 1][tx] += out[7];
-        acc[T_WV][ty - 1][tx] += out[10];
-        acc[T_WD][ty - 1][tx] += out[13];
-        acc[T_PL][ty - 1][tx] += out[16];
-        acc[T_PU][ty - 1][tx] += out[19];
-    }
-    __syncthreads();
-    if (tx > 0 && ty > 0) acc[T_PU][ty - 1][tx - 1] += out[17];
-    __syncthreads();
+    // ---- weighted gather on the owned slots --------------------------------------------------------
     if (tx < VO && ty < VO) {
         const int si = i0 + tx, sj = j0 + ty;
         if (si <= n && sj <= n) {
+            const auto& so = sh.u.so;
+            T c[NTYPES];
+            c[T_UX] = so[0][ty][tx];
+            c[T_UY] = so[1][ty][tx];
+            c[T_BH] = so[3][ty][tx] + so[2][ty][tx + 1];
+            c[T_BV] = so[5][ty][tx] + so[4][ty + 1][tx];
+            c[T_BD] = so[6][ty][tx + 1] + so[7][ty + 1][tx];
+            c[T_WH] = so[9][ty][tx] + so[8][ty][tx + 1];
+            c[T_WV] = so[11][ty][tx] + so[10][ty + 1][tx];
+            c[T_WD] = so[12][ty][tx + 1] + so[13][ty + 1][tx];
+            c[T_PL] = so[14][ty][tx] + so[15][ty][tx + 1] + so[16][ty + 1][tx];
+            c[T_PU] = so[17][ty + 1][tx + 1] + so[18][ty][tx + 1] + so[19][ty + 1][tx];
             const long long s0 = slot_index(L, si, sj);
-            T old[NTYPES];
-#pragma unroll
-            for (int t = 0; t < NTYPES; ++t) old[t] = x_is_zero ? (T)0 : x[t * L.plane + s0];
 #pragma unroll
             for (int t = 0; t < NTYPES; ++t)
                 if (dof_free(t, si, sj, n))
-                    x[t * L.plane + s0] = old[t] + omega * (T)vanka_weight(t, si, sj, n) * acc[t][ty][tx];
+                    x_out[t * L.plane + s0] = xown[t] + omega * (T)vanka_weight(t, si, sj, n) * c[t];
         }
     }
 }
 
-template <typename T>
-void launch_vanka_uniform(const LevelView<T>& lv, const T* r, T* x, T omega, int x_is_zero, hipStream_t st) {
-    dim3 blk(VT, VT);
+template <typename T, bool UNIFORM, bool ZERO>
+static void launch_vanka_step_t(const LevelView<T>& lv, const T* x_in, const T* b, T* x_out, T kinv_s, T omega,
+                                hipStream_t st) {
+    dim3 blk(TB, TB);
     dim3 grd((lv.L.n + 1 + VO - 1) / VO, (lv.L.n + 1 + VO - 1) / VO);
-    hipLaunchKernelGGL(k_vanka_uniform<T>, grd, blk, 0, st, r, x, lv.L, lv.cls, lv.minv, omega, x_is_zero);
+    // a tile spans at most two vertex classes per direction unless it covers the whole mesh
+    if (UNIFORM && lv.L.n + 1 <= VT)
+        hipLaunchKernelGGL((k_vanka_step<T, UNIFORM, ZERO, 9>), grd, blk, 0, st, x_in, b, x_out, lv.L, lv.kinv,
+                           kinv_s, lv.coef, lv.cls, lv.wblk, lv.minv, omega);
+    else
+        hipLaunchKernelGGL((k_vanka_step<T, UNIFORM, ZERO, 4>), grd, blk, 0, st, x_in, b, x_out, lv.L, lv.kinv,
+                           kinv_s, lv.coef, lv.cls, lv.wblk, lv.minv, omega);
 }
-template void launch_vanka_uniform<double>(const LevelView<double>&, const double*, double*, double, int,
-                                           hipStream_t);
-template void launch_vanka_uniform<float>(const LevelView<float>&, const float*, float*, float, int, hipStream_t);
+
+template <typename T>
+void launch_vanka_step(const LevelView<T>& lv, const T* x_in, const T* b, T* x_out, bool uniform, T kinv_s,
+                       T omega, hipStream_t st) {
+    if (uniform) {
+        if (x_in)
+            launch_vanka_step_t<T, true, false>(lv, x_in, b, x_out, kinv_s, omega, st);
+        else
+            launch_vanka_step_t<T, true, true>(lv, x_in, b, x_out, kinv_s, omega, st);
+    } else {
+        if (x_in)
+            launch_vanka_step_t<T, false, false>(lv, x_in, b, x_out, kinv_s, omega, st);
+        else
+            launch_vanka_step_t<T, false, true>(lv, x_in, b, x_out, kinv_s, omega, st);
+    }
+}
+template void launch_vanka_step<double>(const LevelView<double>&, const double*, const double*, double*, bool,
+                                        double, double, hipStream_t);
+template void launch_vanka_step<float>(const LevelView<float>&, const float*, const float*, float*, bool, float,
+                                       float, hipStream_t);
 
 // =========================================================================================
 // inexact Braess-Sarazin relaxation (Sec. 3.2.2, Appendix D)
@@ -432,10 +518,6 @@ template void launch_vanka_uniform<float>(const LevelView<float>&, const float*,
 // with diag(S)_T = (1/M + alpha^2 / (lambda + mu)) |T| + sum_e (tau B_w)_{Te}^2 / (tau D_w)_e.
 // Three launches: k_bsr_first (z_u, z_w), k_bsr_schur (dp), k_bsr_second (update).
 
-template <int... Ts, typename F>
-__device__ __forceinline__ void static_for(std::integer_sequence<int, Ts...>, F&& f) {
-    (f(std::integral_constant<int, Ts>{}), ...);
-}
 
 // sum over the entries e of row type t with predicate Sel(column type) of
 // coef_e (* 1/K) * v[column slot]
@@ -523,12 +605,14 @@ template void launch_bsr_diag<double>(const LevelView<double>&, double, double*,
 template void launch_bsr_diag<float>(const LevelView<float>&, float, float*, hipStream_t);
 
 constexpr int NU = 5;   // displacement DoF types ux, uy, bH, bV, bD
+constexpr int BT = 16;  // vertices per BSR tile side (threads)
+constexpr int BO = BT - 1;
 
 // Displacement-patch solves of the vertices of a tile: su holds the displacement residual
-// of slots (i0-1 .. i0+VT-1)^2, the patch corrections go to so (8 per vertex).
+// of slots (i0-1 .. i0+BT-1)^2, the patch corrections go to so (8 per vertex).
 template <typename T>
-__device__ __forceinline__ void upatch_solves(const T (&su)[NU][VT + 1][VT + 1], const T (&ui)[9][64],
-                                              T (&so)[8][VT][VT], int vi, int vj, int n, int tx, int ty) {
+__device__ __forceinline__ void upatch_solves(const T (&su)[NU][BT + 1][BT + 1], const T (&ui)[9][64],
+                                              T (&so)[8][BT][BT], int vi, int vj, int n, int tx, int ty) {
     T out[8];
 #pragma unroll
     for (int a = 0; a < 8; ++a) out[a] = 0;
@@ -558,7 +642,7 @@ __device__ __forceinline__ void upatch_solves(const T (&su)[NU][VT + 1][VT + 1],
 // weighted sum of the patch corrections at owned slot (tx, ty): P1 in one patch, bubbles
 // in the two patches of their end points (weight 1/2)
 template <typename T>
-__device__ __forceinline__ void upatch_gather(const T (&so)[8][VT][VT], int tx, int ty, T (&du)[NU]) {
+__device__ __forceinline__ void upatch_gather(const T (&so)[8][BT][BT], int tx, int ty, T (&du)[NU]) {
     du[T_UX] = so[0][ty][tx];
     du[T_UY] = so[1][ty][tx];
     du[T_BH] = (T)0.5 * (so[3][ty][tx] + so[2][ty][tx + 1]);
@@ -571,12 +655,12 @@ __device__ __forceinline__ void load_uinv(const T* __restrict__ uinv, T (&ui)[9]
     T v[3];
 #pragma unroll
     for (int it = 0; it < 3; ++it) {
-        const int q = tid + it * VT * VT;
+        const int q = tid + it * BT * BT;
         v[it] = q < 9 * 64 ? uinv[q] : (T)0;
     }
 #pragma unroll
     for (int it = 0; it < 3; ++it) {
-        const int q = tid + it * VT * VT;
+        const int q = tid + it * BT * BT;
         if (q < 9 * 64) (&ui[0][0])[q] = v[it];
     }
 }
@@ -585,33 +669,33 @@ __device__ __forceinline__ void load_uinv(const T* __restrict__ uinv, T (&ui)[9]
 template <typename T>
 __global__ __launch_bounds__(256) void k_bsr_first(const T* __restrict__ r, T* __restrict__ t, Layout L,
                                                    const T* __restrict__ uinv, const T* __restrict__ d) {
-    __shared__ T su[NU][VT + 1][VT + 1];
-    __shared__ T so[8][VT][VT];
+    __shared__ T su[NU][BT + 1][BT + 1];
+    __shared__ T so[8][BT][BT];
     __shared__ T ui[9][64];
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * VT + tx;
-    const int i0 = blockIdx.x * VO, j0 = blockIdx.y * VO;
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * BT + tx;
+    const int i0 = blockIdx.x * BO, j0 = blockIdx.y * BO;
     const int n = L.n;
     {
-        constexpr int TS = (VT + 1) * (VT + 1);
+        constexpr int TS = (BT + 1) * (BT + 1);
         constexpr int NV = NU * TS;
-        constexpr int NIT = (NV + VT * VT - 1) / (VT * VT);
+        constexpr int NIT = (NV + BT * BT - 1) / (BT * BT);
         T v[NIT];
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
-            const int q = tid + it * VT * VT;
-            const int tt = q / TS, rem = q - tt * TS, bb = rem / (VT + 1), aa = rem - bb * (VT + 1);
+            const int q = tid + it * BT * BT;
+            const int tt = q / TS, rem = q - tt * TS, bb = rem / (BT + 1), aa = rem - bb * (BT + 1);
             const int si = i0 - 1 + aa, sj = j0 - 1 + bb;
             v[it] = (q < NV && si <= n + 1 && sj <= n + 1) ? r[tt * L.plane + slot_index(L, si, sj)] : (T)0;
         }
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
-            const int q = tid + it * VT * VT;
+            const int q = tid + it * BT * BT;
             if (q < NV) (&su[0][0][0])[q] = v[it];
         }
     }
     load_uinv(uinv, ui, tid);
     const int si = i0 + tx, sj = j0 + ty;
-    const bool own = tx < VO && ty < VO && si <= n && sj <= n;
+    const bool own = tx < BO && ty < BO && si <= n && sj <= n;
     const long long s0 = own ? slot_index(L, si, sj) : 0;
     T rw[3], dw[3];
 #pragma unroll
@@ -656,16 +740,16 @@ __global__ __launch_bounds__(256) void k_bsr_second(const T* __restrict__ r, con
                                                     T* __restrict__ x, Layout L, const T* __restrict__ uinv,
                                                     const T* __restrict__ coef, const T* __restrict__ d,
                                                     T omega, int x_is_zero) {
-    __shared__ T su[NU][VT + 1][VT + 1];
-    __shared__ T so[8][VT][VT];
+    __shared__ T su[NU][BT + 1][BT + 1];
+    __shared__ T so[8][BT][BT];
     __shared__ T ui[9][64];
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * VT + tx;
-    const int i0 = blockIdx.x * VO, j0 = blockIdx.y * VO;
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * BT + tx;
+    const int i0 = blockIdx.x * BO, j0 = blockIdx.y * BO;
     const int n = L.n;
-    // displacement residual after the pressure update, slots (i0-1 .. i0+VT-1)^2; its
+    // displacement residual after the pressure update, slots (i0-1 .. i0+BT-1)^2; its
     // pressure columns reach slots -1..0 away, inside the two-deep low ghost ring
-    for (int q = tid; q < (VT + 1) * (VT + 1); q += VT * VT) {
-        const int bb = q / (VT + 1), aa = q - bb * (VT + 1);
+    for (int q = tid; q < (BT + 1) * (BT + 1); q += BT * BT) {
+        const int bb = q / (BT + 1), aa = q - bb * (BT + 1);
         const int si = i0 - 1 + aa, sj = j0 - 1 + bb;
         const bool in = si <= n + 1 && sj <= n + 1;
         const long long s = in ? slot_index(L, si, sj) : 0;
@@ -680,7 +764,7 @@ __global__ __launch_bounds__(256) void k_bsr_second(const T* __restrict__ r, con
     }
     load_uinv(uinv, ui, tid);
     const int si = i0 + tx, sj = j0 + ty;
-    const bool own = tx < VO && ty < VO && si <= n && sj <= n;
+    const bool own = tx < BO && ty < BO && si <= n && sj <= n;
     const long long s0 = own ? slot_index(L, si, sj) : 0;
     T old[NTYPES];
 #pragma unroll
@@ -710,8 +794,8 @@ __global__ __launch_bounds__(256) void k_bsr_second(const T* __restrict__ r, con
 template <typename T>
 void launch_bsr(const LevelView<T>& lv, const T* r, T* t, T* x, T omega, T omega_J, int x_is_zero,
                 hipStream_t st) {
-    dim3 tb(VT, VT);
-    dim3 tg((lv.L.n + 1 + VO - 1) / VO, (lv.L.n + 1 + VO - 1) / VO);
+    dim3 tb(BT, BT);
+    dim3 tg((lv.L.n + 1 + BO - 1) / BO, (lv.L.n + 1 + BO - 1) / BO);
     dim3 sb(64, 4);
     dim3 sg((lv.L.n + 1 + 63) / 64, (lv.L.n + 1 + 3) / 4);
     hipLaunchKernelGGL(k_bsr_first<T>, tg, tb, 0, st, r, t, lv.L, lv.uinv, lv.bsrd);
@@ -1020,92 +1104,134 @@ void launch_kinv_coarsen(const double* kf, const Layout& Lf, double* kc, const L
 }
 
 // =========================================================================================
-// Krylov BLAS-1 (FP64, deterministic two-stage reductions)
+// Krylov BLAS-1 (FP64, deterministic reductions)
 // =========================================================================================
-__global__ __launch_bounds__(256) void k_multidot(const double* __restrict__ V, long long ldv, int nv,
-                                                  const double* __restrict__ w, long long n,
-                                                  double* __restrict__ partial) {
-    __shared__ double red[4][256];
+// ---- classical Gram-Schmidt pass: dots, update with norm, deterministic reductions ----------------
+// The partial sums of each block go to partial[q * np + b] (np blocks); a second kernel adds them
+// in a fixed order.  Kernels given run_if return at once when *run_if == 0.
+constexpr int DOT_BLOCKS = RED_BLOCKS;     // dot-product blocks (contiguous chunks)
+constexpr int UPD_BLOCKS = 4 * RED_BLOCKS; // update blocks (grid stride)
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// partial sums of V_q . w (q < nv) and of w . w (slot nv), four vectors per pass over the chunk
+__global__ __launch_bounds__(256) void k_gs_dots(const double* __restrict__ V, long long ldv, int nv,
+                                                 const double* __restrict__ w, long long n,
+                                                 double* __restrict__ partial, const double* run_if) {
+    if (run_if && *run_if == 0.0) return;
+    __shared__ double red[5][256];
     const long long chunk = (n + gridDim.x - 1) / gridDim.x;
     const long long lo = (long long)blockIdx.x * chunk;
     const long long hi = min(n, lo + chunk);
-    for (int v0 = 0; v0 < nv; v0 += 4) {
-        double acc[4] = {0, 0, 0, 0};
+    for (int v0 = 0; v0 == 0 || v0 < nv; v0 += 4) {
+        double acc[5] = {0, 0, 0, 0, 0};
         for (long long e = lo + threadIdx.x; e < hi; e += blockDim.x) {
             const double we = w[e];
 #pragma unroll
             for (int q = 0; q < 4; ++q)
                 if (v0 + q < nv) acc[q] += V[(long long)(v0 + q) * ldv + e] * we;
+            if (v0 == 0) acc[4] += we * we;
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) red[q][threadIdx.x] = acc[q];
+        for (int q = 0; q < 5; ++q) red[q][threadIdx.x] = acc[q];
         __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if ((int)threadIdx.x < s)
+        for (int st = 128; st > 0; st >>= 1) {
+            if ((int)threadIdx.x < st)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + s];
+                for (int q = 0; q < 5; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + st];
             __syncthreads();
         }
         if (threadIdx.x < 4 && v0 + (int)threadIdx.x < nv)
-            partial[(long long)blockIdx.x * nv + v0 + threadIdx.x] = red[threadIdx.x][0];
+            partial[(long long)(v0 + threadIdx.x) * gridDim.x + blockIdx.x] = red[threadIdx.x][0];
+        if (threadIdx.x == 4 && v0 == 0) partial[(long long)nv * gridDim.x + blockIdx.x] = red[4][0];
         __syncthreads();
     }
 }
 
-void launch_multidot(const double* V, long long ldv, int nv, const double* w, long long n, double* partial,
-                     int nblk, hipStream_t st) {
-    hipLaunchKernelGGL(k_multidot, dim3(nblk), dim3(256), 0, st, V, ldv, nv, w, n, partial);
-}
-
-// out[v] (+)= sum_b partial[b][v]: one workgroup per vector, fixed-order tree (deterministic)
-__global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ partial, int nblk, int nv,
-                                                         double* __restrict__ out, int accumulate) {
-    __shared__ double red[256];
-    const int v = blockIdx.x;
-    double s = 0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += partial[(long long)b * nv + v];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[v] = accumulate ? out[v] + red[0] : red[0];
-}
-
-void launch_reduce_partials(const double* partial, int nblk, int nv, double* out, int accumulate,
-                            hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce_partials, dim3(nv), dim3(256), 0, st, partial, nblk, nv, out, accumulate);
-}
-
-__global__ void k_update(double* __restrict__ w, const double* __restrict__ V, long long ldv, int nv,
-                         const double* __restrict__ h, long long n) {
+// w -= sum_q h[q] V_q, with partial sums of the new w . w
+__global__ __launch_bounds__(256) void k_gs_update(double* __restrict__ w, const double* __restrict__ V,
+                                                   long long ldv, int nv, const double* __restrict__ h,
+                                                   long long n, double* __restrict__ partial,
+                                                   const double* run_if) {
+    if (run_if && *run_if == 0.0) return;
+    __shared__ double wred[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double acc = 0;
     long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (; e < n; e += stride) {
-        double s = w[e];
-        for (int q = 0; q < nv; ++q) s -= h[q] * V[(long long)q * ldv + e];
-        w[e] = s;
+        double sv = w[e];
+        for (int q = 0; q < nv; ++q) sv -= h[q] * V[(long long)q * ldv + e];
+        w[e] = sv;
+        acc += sv * sv;
+    }
+    const double t = wave_sum(acc);
+    if (lane == 0) wred[wave] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = wred[0] + wred[1] + wred[2] + wred[3];
+}
+
+// out[q] = sum_b partial[q * np + b], one block per q (fixed order); host: optional mirror.
+// flag (block 0, optional): 1 when out[0] < 0.5 * prev (the Daniel-Gragg-Kaufman-Stewart test
+// for a second orthogonalization pass, eta = 1/sqrt(2)).
+__global__ __launch_bounds__(256) void k_gs_reduce(const double* __restrict__ partial, int np,
+                                                   double* __restrict__ out, double* __restrict__ host,
+                                                   const double* __restrict__ prev, double* __restrict__ flag,
+                                                   const double* run_if) {
+    if (run_if && *run_if == 0.0) return;
+    __shared__ double wred[4];
+    const int q = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double sv = 0;
+    for (int b2 = threadIdx.x; b2 < np; b2 += blockDim.x) sv += partial[(long long)q * np + b2];
+    const double t = wave_sum(sv);
+    if (lane == 0) wred[wave] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double r = wred[0] + wred[1] + wred[2] + wred[3];
+        out[q] = r;
+        if (host) host[q] = r;
+        if (flag) {
+            *flag = (r < 0.5 * (*prev)) ? 1.0 : 0.0;
+            if (host) host[1] = *flag;
+        }
     }
 }
 
-void launch_update(double* w, const double* V, long long ldv, int nv, const double* h, long long n,
-                   hipStream_t st) {
-    int blocks = (int)std::min<long long>((n + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_update, dim3(blocks), dim3(256), 0, st, w, V, ldv, nv, h, n);
+void launch_gs_dots(const double* V, long long ldv, int nv, const double* w, long long n, double* partial,
+                    double* out, double* host, const double* run_if, hipStream_t st) {
+    hipLaunchKernelGGL(k_gs_dots, dim3(DOT_BLOCKS), dim3(256), 0, st, V, ldv, nv, w, n, partial, run_if);
+    hipLaunchKernelGGL(k_gs_reduce, dim3(nv + 1), dim3(256), 0, st, partial, DOT_BLOCKS, out, host, nullptr,
+                       nullptr, run_if);
 }
 
-__global__ void k_scale_inv_sqrt(double* __restrict__ dst, const double* __restrict__ src, long long n,
-                                 const double* __restrict__ norm2) {
-    const double s = 1.0 / sqrt(*norm2);
+void launch_gs_update(double* w, const double* V, long long ldv, int nv, const double* h, long long n,
+                      double* partial, double* norm2, const double* prev, double* flag, double* host,
+                      const double* run_if, hipStream_t st) {
+    hipLaunchKernelGGL(k_gs_update, dim3(UPD_BLOCKS), dim3(256), 0, st, w, V, ldv, nv, h, n, partial, run_if);
+    hipLaunchKernelGGL(k_gs_reduce, dim3(1), dim3(256), 0, st, partial, UPD_BLOCKS, norm2, host, prev, flag,
+                       run_if);
+}
+
+// dst = src / sqrt(*na), or / sqrt(*nb) when sel != nullptr and *sel != 0
+__global__ void k_normalize(double* __restrict__ dst, const double* __restrict__ src, long long n,
+                            const double* __restrict__ na, const double* __restrict__ nb,
+                            const double* __restrict__ sel) {
+    const double nv = (sel && *sel != 0.0) ? *nb : *na;
+    const double s = 1.0 / sqrt(nv);
     long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (; e < n; e += stride) dst[e] = src[e] * s;
 }
 
-void launch_scale_inv_sqrt(double* dst, const double* src, long long n, const double* norm2, hipStream_t st) {
+void launch_normalize(double* dst, const double* src, long long n, const double* na, const double* nb,
+                      const double* sel, hipStream_t st) {
     int blocks = (int)std::min<long long>((n + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_scale_inv_sqrt, dim3(blocks), dim3(256), 0, st, dst, src, n, norm2);
+    hipLaunchKernelGGL(k_normalize, dim3(blocks), dim3(256), 0, st, dst, src, n, na, nb, sel);
 }
 
 __global__ void k_scale(double* __restrict__ dst, const double* __restrict__ src, long long n, double s) {

@@ -145,20 +145,27 @@ def permeability_triangles(name, n=None):
     return None
 
 
-# Relaxation weights of the 256 x 256 workload.  Provisional: taken from the paper's
-# LFA-optimized Tables 2 (Vanka V(2,2)) and 3 (inexact BSR V(1,1)) at the row whose
-# dimensionless groups match (Poisson ratio, and E tau K / (alpha^2 mu_f) = 3e4 k in the
-# paper's runs, = K here), until the local Fourier analysis of this build supplies them.
-_VANKA_W = {0.2: {1.0: 0.90, 1e-3: 0.88, 1e-6: 0.80},
-            0.49: {1.0: 0.74, 1e-3: 0.74, 1e-6: 0.75},
-            0.4999: {1.0: 0.72, 1e-3: 0.72, 1e-6: 0.73}}
-_BSR_W = {0.2: {1.0: (0.71, 1.00), 1e-3: (0.78, 1.05), 1e-6: (0.90, 1.05)},
-          0.49: {1.0: (0.69, 1.07), 1e-3: (0.69, 1.23), 1e-6: (0.85, 1.17)},
-          0.4999: {1.0: (0.68, 1.00), 1e-3: (0.68, 0.86), 1e-6: (0.70, 1.13)}}
+# Relaxation weights: the two-grid LFA optimum of every parameter set (Sec. 4), computed by the
+# CPU reference's local Fourier analysis at the workload's own cell size and parameters and
+# stored in relaxation_weights.json (heterogeneous permeabilities use the geometric mean of
+# their range as the representative constant K).
+_WEIGHTS = None
 
 
-def relaxation_weights(smoother, nu, K):
-    """(omega, omega_J) for a parameter set of the 256 x 256 workload."""
-    if smoother == "vanka":
-        return _VANKA_W[nu][K], 1.0
-    return _BSR_W[nu][K]
+def _weights_table():
+    global _WEIGHTS
+    if _WEIGHTS is None:
+        import json
+        import os
+        with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "relaxation_weights.json")) as f:
+            _WEIGHTS = json.load(f)
+    return _WEIGHTS
+
+
+def relaxation_weights(smoother, nu=None, K=None, workload="sweep256"):
+    """(omega, omega_J) of a smoother for a workload (for sweep256: of its set (nu, K))."""
+    tab = _weights_table()[workload]
+    if workload == "sweep256":
+        tab = tab["%g/%g" % (nu, K)]
+    e = tab[smoother]
+    return e["omega"], e["omega_J"]
