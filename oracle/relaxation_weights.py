@@ -9,7 +9,8 @@ the table of weights the workloads use.  Nothing in the product path imports thi
 
 Each parameter set is analysed at its own cell size h and physical parameters.  Vanka:
 omega on a 0.02 grid; inexact BSR: (omega_J, omega) on a 0.05 grid with 16 x 16 frequency
-samples, then a 0.01 pattern search with 32 x 32 samples.  Heterogeneous permeabilities use
+samples, then a 0.01 pattern search with 32 x 32 samples; where the factor is flat in omega_J
+(within 1e-3 of the optimum at the chosen omega) the omega_J nearest 1 is taken.  Heterogeneous permeabilities use
 a representative constant K (the geometric mean of the field's range).
 """
 import json
@@ -50,7 +51,14 @@ def bsr_weights(P, h, K, nu12):
         if r >= cur - 1e-6:
             break
         cur, a, b = r, aa, bb
-    return {"omega": float(b), "omega_J": float(a), "rho_lfa": round(cur, 4)}
+    # where the factor is flat in omega_J (within 1e-3 of the optimum) take the weight nearest
+    # 1, plain Jacobi on the approximate Schur complement
+    best_a, best_r = a, cur
+    for aa in np.round(np.arange(0.6, 1.6001, 0.01), 4):
+        r = L.rho(b, aa)
+        if r <= cur + 1e-3 and abs(aa - 1.0) < abs(best_a - 1.0):
+            best_a, best_r = aa, r
+    return {"omega": float(b), "omega_J": float(best_a), "rho_lfa": round(best_r, 4)}
 
 
 def lame(E, nu):

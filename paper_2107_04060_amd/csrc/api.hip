@@ -64,9 +64,9 @@ struct Level {
     int st_off_host[NTYPES + 1];
     DevBuf st, st_off;                  // stencil entry list (device; coarse matrix set-up)
     DevBuf coef64, coef32;              // stencil coefficients in structure.h order
-    DevBuf minv64, minv32;              // full patch inverses per vertex class, uniform K (9 x 20 x 20)
+    DevBuf minv64;                      // full patch inverses per vertex class, uniform K (9 x 20 x 20)
     DevBuf kinv64, kinv32;              // 2 planes each
-    DevBuf cls64, cls32, wblk64, wblk32;
+    DevBuf cls64, wblk64;               // per-class elimination data, RT0 blocks (FP64 for both precisions)
     DevBuf uinv64, uinv32;              // displacement-patch inverses (BSR), 9 x 8 x 8
     DevBuf bsrd64, bsrd32;              // BSR diagonal data, 5 planes
     DevBuf x64, b64, r64, t64, x2_64;   // FP64 work vectors (padded); x64 / x2_64: iterate pair
@@ -95,11 +95,11 @@ LevelView<float> Level::view<float>() const {
     v.L = L;
     v.kinv = kinv32.as<float>();
     v.coef = coef32.as<float>();
-    v.cls = cls32.as<DevPatchClass<float>>();
-    v.wblk = wblk32.as<float>();
+    v.cls = cls64.as<DevPatchClass<double>>();
+    v.wblk = wblk64.as<double>();
     v.uinv = uinv32.as<float>();
     v.bsrd = bsrd32.as<float>();
-    v.minv = minv32.as<float>();
+    v.minv = minv64.as<double>();
     return v;
 }
 
@@ -224,7 +224,6 @@ static void level_patch_data(Level& lv, bool uniform, double Kinv, hipStream_t s
     }
     std::vector<DevPatchClass<double>> c64 = convert_classes<double>(cls);
     upload(lv.cls64, c64, st);
-    upload(lv.cls32, convert_classes<float>(cls), st);
     upload(lv.wblk64, wblk, st);
     if (uniform) {
         // inverse of each class's patch matrix, column by column (zero rows and columns on
@@ -240,14 +239,9 @@ static void level_patch_data(Level& lv, bool uniform, double Kinv, hipStream_t s
                 for (int a = 0; a < PATCH; ++a) minv[(k * PATCH + a) * PATCH + j] = c64[k].present[a] ? col[a] : 0.0;
             }
         upload(lv.minv64, minv, st);
-        std::vector<float> mf(minv.begin(), minv.end());
-        upload(lv.minv32, mf, st);
     } else {
         lv.minv64.release();
-        lv.minv32.release();
     }
-    std::vector<float> wf(wblk.begin(), wblk.end());
-    upload(lv.wblk32, wf, st);
     UPatchClass ucls[9];
     build_upatch_classes(lv.st_host, lv.n, ucls);
     upload(lv.uinv64, convert_uinv<double>(ucls), st);

@@ -221,18 +221,6 @@ __device__ inline double vanka_weight(int t, int i, int j, int n) {
     return (i == n - 1 && j == n - 1) ? 0.5 : 1.0 / 3.0;
 }
 
-// out = M rr for a 20 x 20 row-major M
-template <typename T>
-__device__ __forceinline__ void matvec20(const T* __restrict__ M, const T (&rr)[PATCH], T (&out)[PATCH]) {
-#pragma unroll
-    for (int a = 0; a < PATCH; ++a) {
-        T v = 0;
-#pragma unroll
-        for (int b2 = 0; b2 < PATCH; ++b2) v += M[a * PATCH + b2] * rr[b2];
-        out[a] = v;
-    }
-}
-
 // LDS offset of patch slot s relative to the residual entry of its vertex (rs[0][vj+1][vi+1])
 __host__ __device__ constexpr int pslot_off(int s) {
     const int tt[PATCH] = {T_UX, T_UY, T_BH, T_BH, T_BV, T_BV, T_BD, T_BD, T_WH, T_WH,
@@ -272,16 +260,16 @@ struct VankaLds {
         T so[PATCH][VT][VT];
     } u;
     T ks[UNIFORM ? 1 : 2][UNIFORM ? 1 : KW][UNIFORM ? 1 : KW];   // 1/K of the L, U triangles
-    T ms[UNIFORM ? NCLS : 1][UNIFORM ? PATCH * PATCH : 1];       // class inverses of the tile
+    double ms[UNIFORM ? NCLS : 1][UNIFORM ? PATCH * PATCH : 1];  // class inverses of the tile (FP64)
 };
 
 template <typename T, bool UNIFORM, bool ZERO, int NCLS>
 __global__ __launch_bounds__(TPB) void k_vanka_step(const T* __restrict__ x_in, const T* __restrict__ b,
                                                     T* __restrict__ x_out, Layout L, const T* __restrict__ kinv,
                                                     T kinv_s, const T* __restrict__ coef,
-                                                    const DevPatchClass<T>* __restrict__ cls,
-                                                    const T* __restrict__ wblk, const T* __restrict__ minv,
-                                                    T omega) {
+                                                    const DevPatchClass<double>* __restrict__ cls,
+                                                    const double* __restrict__ wblk,
+                                                    const double* __restrict__ minv, T omega) {
     __shared__ VankaLds<T, UNIFORM, NCLS> sh;
     auto& xs = sh.u.a.xs;
     auto& rs = sh.u.a.rs;
@@ -301,11 +289,11 @@ __global__ __launch_bounds__(TPB) void k_vanka_step(const T* __restrict__ x_in, 
             const int nc = cw * (cjhi - cjlo + 1);
             for (int k = 0; k < nc; ++k) {
                 const int cidx = 3 * (cjlo + k / cw) + cilo + k % cw;
-                T mv[NIT];
+                double mv[NIT];
 #pragma unroll
                 for (int it = 0; it < NIT; ++it) {
                     const int q = tid + it * TPB;
-                    mv[it] = q < NM ? minv[cidx * NM + q] : (T)0;
+                    mv[it] = q < NM ? minv[cidx * NM + q] : 0.0;
                 }
 #pragma unroll
                 for (int it = 0; it < NIT; ++it) {
@@ -357,7 +345,8 @@ __global__ __launch_bounds__(TPB) void k_vanka_step(const T* __restrict__ x_in, 
     T xown[NTYPES];
 #pragma unroll
     for (int t = 0; t < NTYPES; ++t) xown[t] = (ZERO || !patch) ? (T)0 : xs[t][ty + 2][tx + 2];
-    if constexpr (UNIFORM && std::is_same<T, double>::value) {
+    // The patch arithmetic is FP64 for either storage precision T.
+    if constexpr (UNIFORM) {
         // wave w applies the class inverses to the patches of tile rows 4 w .. 4 w + 3
         const int lane = tid & 63, wave = tid >> 6;
         const int jl = lane & 15, kq = lane >> 4;
@@ -370,12 +359,12 @@ __global__ __launch_bounds__(TPB) void k_vanka_step(const T* __restrict__ x_in, 
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int pty = min(4 * wave + r, VT - 1);
-            const double* base = &rs[0][0][0] + (pty + 1) * RW + (bcol + 1);
+            const T* base = &rs[0][0][0] + (pty + 1) * RW + (bcol + 1);
 #pragma unroll
             for (int ks = 0; ks < 5; ++ks) {
                 const int o = kq == 0 ? pslot_off(4 * ks) : kq == 1 ? pslot_off(4 * ks + 1)
                             : kq == 2 ? pslot_off(4 * ks + 2) : pslot_off(4 * ks + 3);
-                bf[r][ks] = base[o];
+                bf[r][ks] = (double)base[o];
             }
         }
         __syncthreads();
@@ -398,53 +387,47 @@ __global__ __launch_bounds__(TPB) void k_vanka_step(const T* __restrict__ x_in, 
                 if (ci_l == ci && jl < VT) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        sh.u.so[kq + 4 * v][pty][jl] = acc0[v];
-                        if (kq + 4 * v + 16 < PATCH) sh.u.so[kq + 4 * v + 16][pty][jl] = acc1[v];
+                        sh.u.so[kq + 4 * v][pty][jl] = (T)acc0[v];
+                        if (kq + 4 * v + 16 < PATCH) sh.u.so[kq + 4 * v + 16][pty][jl] = (T)acc1[v];
                     }
                 }
             }
         }
     } else {
-    T out[PATCH];
+        // per-patch elimination (permeability varies from patch to patch)
+        double out[PATCH];
 #pragma unroll
-    for (int s = 0; s < PATCH; ++s) out[s] = 0;
-    if (patch && vi <= n && vj <= n) {
-        const int ci = vi == 0 ? 0 : (vi == n ? 2 : 1);
-        const int cj = vj == 0 ? 0 : (vj == n ? 2 : 1);
-        const int cidx = 3 * cj + ci;
-        T rr[PATCH];
-#pragma unroll
-        for (int s = 0; s < PATCH; ++s) {
-            int t, di, dj;
-            patch_slot(s, t, di, dj);
-            rr[s] = rs[t][ty + 1 + dj][tx + 1 + di];
-        }
-        if constexpr (UNIFORM) {
-            // full patch inverse of the vertex class (zero rows and columns on absent DoFs, zero
-            // for the two pressure-only corner vertices)
-            matvec20<T>(sh.ms[(cj - cjlo) * cw + (ci - cilo)], rr, out);
-        } else {
-            const DevPatchClass<T>& pc = cls[cidx];
+        for (int s = 0; s < PATCH; ++s) out[s] = 0;
+        if (patch && vi <= n && vj <= n) {
+            const int ci = vi == 0 ? 0 : (vi == n ? 2 : 1);
+            const int cj = vj == 0 ? 0 : (vj == n ? 2 : 1);
+            const DevPatchClass<double>& pc = cls[3 * cj + ci];
             bool keep = false;
 #pragma unroll
             for (int s = 0; s < 14; ++s) keep = keep || pc.present[s];
             if (keep) {
-                T kv[6];
+                double rr[PATCH];
+#pragma unroll
+                for (int s = 0; s < PATCH; ++s) {
+                    int t, di, dj;
+                    patch_slot(s, t, di, dj);
+                    rr[s] = (double)rs[t][ty + 1 + dj][tx + 1 + di];
+                }
+                double kv[6];
 #pragma unroll
                 for (int kq = 0; kq < 6; ++kq) {
                     int ut, di, dj;
                     star_tri(kq, ut, di, dj);
-                    kv[kq] = sh.ks[ut][ty + 2 + dj][tx + 2 + di];
+                    kv[kq] = (double)sh.ks[ut][ty + 2 + dj][tx + 2 + di];
                 }
-                patch_solve<T>(rr, pc, kv, wblk, out, 1);
+                patch_solve<double>(rr, pc, kv, wblk, out, 1);
             }
         }
-    }
-    __syncthreads();
-    if (patch) {
+        __syncthreads();
+        if (patch) {
 #pragma unroll
-        for (int s = 0; s < PATCH; ++s) sh.u.so[s][ty][tx] = out[s];
-    }
+            for (int s = 0; s < PATCH; ++s) sh.u.so[s][ty][tx] = (T)out[s];
+        }
     }
     __syncthreads();
     // ---- weighted gather on the owned slots --------------------------------------------------------

@@ -1,15 +1,13 @@
-"""The precision form: V-cycle vectors, transfers and patch solves in FP32 (patch inverses
-and coarse inverse built in FP64, then rounded), FP64 FGMRES with an FP64 true residual.
+"""The precision form: V-cycle vectors, residuals and transfers stored and computed in FP32;
+patch arithmetic (class inverses on the matrix cores, per-patch elimination, BSR pieces built
+in FP64) in FP64; FP64 FGMRES with an FP64 true residual.
 
 The contract is the outer solve: FGMRES with the FP32 cycle reaches the FP64 tolerance 1e-8
 in the true residual, recomputed on the CPU with the oracle's matrix, in at most a few more
 iterations than the FP64 form; the error against the oracle's direct solution is reported
-per field.  The cycle itself is an approximation of the FP64 cycle whose deviation is
-reported, not matched: a patch solve in FP32 carries a relative error up to
-eps_32 * cond(patch), and the Vanka patch matrices reach cond ~ 1e6, so per-field deviations
-of 1e-3 .. 1e-1 are expected (BSR's diagonal Schur step and 8 x 8 displacement patches stay
-near 1e-5).  The cycle test only bounds the deviation by 0.2, where the preconditioner would
-stop being the same method."""
+per field.  The cycle itself differs from the FP64 cycle by the rounding of the stored
+vectors (unit roundoff 6e-8) carried through the linear cycle; the bound 1e-4 allows an
+amplification of ~1700, the measured deviations are ~1e-5."""
 import numpy as np
 import pytest
 
@@ -49,7 +47,7 @@ def test_fp32_cycle_close_to_fp64_oracle(binding, smoother, kind):
     r = inputs.rhs_uniform(n, 7)
     err = rel(s.vcycle(_t(r)).cpu().numpy(), H.vcycle(r))
     print("  %s %s fp32 cycle rel diff %.2e" % (smoother, kind, err), flush=True)
-    assert err < 0.2
+    assert err < 1e-4
     s.close()
 
 
