@@ -375,13 +375,8 @@ static T* relax(biot_ctx* c, int l, const T* x, const T* b, T* dst, hipStream_t 
         prof_end(e0, st);
         return dst;
     }
-    const T* rr = b;
-    if (x) {
-        T* r = VecSet<T>::r(lv);
-        launch_apply<T>(v, dst, b, r, 1, st);
-        rr = r;
-    }
-    launch_bsr<T>(v, rr, VecSet<T>::s(lv), dst, om, (T)c->opts.omega_J, x ? 0 : 1, st);
+    launch_bsr_step<T>(v, dst, b, VecSet<T>::r(lv), VecSet<T>::s(lv), x == nullptr, c->K_uniform,
+                       (T)(1.0 / c->K_scalar), om, (T)c->opts.omega_J, nullptr, nullptr, nullptr, nullptr, st);
     return dst;
 }
 
@@ -421,15 +416,31 @@ static T* vcycle_level(biot_ctx* c, int l, const T* b, T* buf0, T* buf1, hipStre
         cur = buf0;
     }
     Level& lc = *c->levels[l + 1];
-    T* r = VecSet<T>::r(lv);
-    hipEvent_t e1 = prof_begin(c, 1, l, st);
-    launch_apply<T>(lv.view<T>(), cur, b, r, 1, st);
-    prof_end(e1, st);
     T* bc = VecSet<T>::b(lc);
-    launch_restrict<T>(lv.L, lc.L, r, bc, PW<T>::get(c), st);
+    hipEvent_t e1 = prof_begin(c, 1, l, st);
+    launch_residual_restrict<T>(lv.view<T>(), lc.L, cur, b, bc, c->K_uniform, (T)(1.0 / c->K_scalar),
+                                PW<T>::get(c), st);
+    prof_end(e1, st);
     T* xc = vcycle_level<T>(c, l + 1, bc, XBuf<T>::get(lc, 0), XBuf<T>::get(lc, 1), st);
-    launch_prolong_add<T>(lv.L, lc.L, xc, cur, PW<T>::get(c), st);
-    for (int s = 0; s < c->opts.nu2; ++s) cur = relax<T>(c, l, cur, b, next(), st);
+    int s0 = 0;
+    if (c->opts.nu2 > 0) {
+        // prolongation fused into the first post-smoothing step
+        const T kinv_s = (T)(1.0 / c->K_scalar);
+        if (!inplace) {
+            T* dst = next();
+            launch_vanka_step<T>(lv.view<T>(), cur, b, dst, c->K_uniform, kinv_s, (T)c->opts.omega, st, xc, &lc.L,
+                                 PW<T>::get(c));
+            cur = dst;
+        } else {
+            T* other = cur == buf0 ? buf1 : buf0;
+            launch_bsr_step<T>(lv.view<T>(), cur, b, VecSet<T>::r(lv), VecSet<T>::s(lv), false, c->K_uniform, kinv_s,
+                               (T)c->opts.omega, (T)c->opts.omega_J, xc, &lc.L, PW<T>::get(c), other, st);
+        }
+        s0 = 1;
+    } else {
+        launch_prolong_add<T>(lv.L, lc.L, xc, cur, PW<T>::get(c), st);
+    }
+    for (int s = s0; s < c->opts.nu2; ++s) cur = relax<T>(c, l, cur, b, next(), st);
     return cur;
 }
 

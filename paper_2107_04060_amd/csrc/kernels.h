@@ -44,9 +44,12 @@ void launch_apply(const LevelView<T>& lv, const T* x, const T* b, T* y, int mode
 //   x_out = x_in + omega * sum_l V_l^T D_l A_l^{-1} V_l (b - A x_in)
 // x_in == nullptr means x_in = 0.  x_out must not alias x_in.  uniform: one patch inverse per
 // vertex class (lv.minv, full inverses), 1/K = kinv_s; else per-patch elimination with lv.kinv.
+// xc != nullptr: the iterate is x_in + P x_c (coarse level layout *Lc, prolongation weights
+// pw), i.e. the prolongation of the coarse-grid correction is fused into the step.
 template <typename T>
 void launch_vanka_step(const LevelView<T>& lv, const T* x_in, const T* b, T* x_out, bool uniform, T kinv_s,
-                       T omega, hipStream_t st);
+                       T omega, hipStream_t st, const T* xc = nullptr, const Layout* Lc = nullptr,
+                       const T* pw = nullptr);
 
 // grid transfers
 // (w: the NPWEIGHTS prolongation weights of structure.h, device)
@@ -54,15 +57,21 @@ template <typename T>
 void launch_restrict(const Layout& Lf, const Layout& Lc, const T* rf, T* rc, const T* w, hipStream_t st);
 template <typename T>
 void launch_prolong_add(const Layout& Lf, const Layout& Lc, const T* xc, T* xf, const T* w, hipStream_t st);
+// r_c = P^T (b - A_f x) in one launch (the fine residual is not stored); uniform: 1/K = kinv_s
+template <typename T>
+void launch_residual_restrict(const LevelView<T>& lf, const Layout& Lc, const T* x, const T* b, T* rc,
+                              bool uniform, T kinv_s, const T* w, hipStream_t st);
 
 // inexact Braess-Sarazin: diagonal data of a level (1 / (tau D_w), 1 / diag(S)); cS =
 // (1/M + alpha^2 / (lambda + mu)) |T|
 template <typename T>
 void launch_bsr_diag(const LevelView<T>& lv, T cS, T* d, hipStream_t st);
-// one BSR step on the residual r (t: scratch vector of the level)
+// one BSR step x <- x + omega M_BSR^{-1} (b - A x) in two launches (r, t: scratch vectors of the
+// level; x_is_zero: x = 0 on entry).  xc != nullptr: the iterate is x + P x_c (coarse layout
+// *Lc, prolongation weights pw), formed into xtmp (!= x) on the way; the result is in x.
 template <typename T>
-void launch_bsr(const LevelView<T>& lv, const T* r, T* t, T* x, T omega, T omega_J, int x_is_zero,
-                hipStream_t st);
+void launch_bsr_step(const LevelView<T>& lv, T* x, const T* b, T* r, T* t, bool x_is_zero, bool uniform, T kinv_s,
+                     T omega, T omega_J, const T* xc, const Layout* Lc, const T* pw, T* xtmp, hipStream_t st);
 
 // coarsest level
 template <typename T>

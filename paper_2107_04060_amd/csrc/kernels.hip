@@ -248,9 +248,25 @@ __device__ __forceinline__ void mfma_class_frag(const double* M, int lane, doubl
         }
 }
 
+// (P x_c) at the fine DoF of type tf anchored at fine slot (2 I + pi, 2 J + pj), from the
+// coarse values xcs[t][J - Jc0 + .][I - Ic0 + .] (designated coarse triangle, structure.h)
+constexpr int PCW = (VT + 3) / 2 + 2;   // staged coarse window of the prolongation (11)
+
+template <typename T, int tf, int pi, int pj>
+__device__ __forceinline__ T prolong_value(const T (&xcs)[NTYPES][PCW][PCW], int ci, int cj,
+                                           const T* __restrict__ w) {
+    T acc = 0;
+    static_for(std::make_integer_sequence<int, fcount(tf)>{}, [&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        constexpr LDof c = ldof(fine_tri(tf, pi, pj), ffirst(tf) + q);
+        acc += w[widx(tf, pi, pj, q)] * xcs[c.t][cj + c.dj][ci + c.di];
+    });
+    return acc;
+}
+
 // LDS of the fused step.  The staged x_in and the residual are dead once the patch residuals
 // are in registers; the patch corrections then reuse their space.
-template <typename T, bool UNIFORM, int NCLS>
+template <typename T, bool UNIFORM, int NCLS, bool PROL>
 struct VankaLds {
     union {
         struct {
@@ -261,16 +277,22 @@ struct VankaLds {
     } u;
     T ks[UNIFORM ? 1 : 2][UNIFORM ? 1 : KW][UNIFORM ? 1 : KW];   // 1/K of the L, U triangles
     double ms[UNIFORM ? NCLS : 1][UNIFORM ? PATCH * PATCH : 1];  // class inverses of the tile (FP64)
+    T xcs[PROL ? NTYPES : 1][PROL ? PCW : 1][PROL ? PCW : 1];   // coarse iterate (prolongation)
 };
 
-template <typename T, bool UNIFORM, bool ZERO, int NCLS>
+// PROL: the iterate is x_in + P x_c (prolongation of the coarse-grid correction, Sec. 3),
+// formed on the staged window; x_out = x_in + P x_c + omega (...).
+template <typename T, bool UNIFORM, bool ZERO, int NCLS, bool PROL>
 __global__ __launch_bounds__(TPB) void k_vanka_step(const T* __restrict__ x_in, const T* __restrict__ b,
                                                     T* __restrict__ x_out, Layout L, const T* __restrict__ kinv,
                                                     T kinv_s, const T* __restrict__ coef,
                                                     const DevPatchClass<double>* __restrict__ cls,
                                                     const double* __restrict__ wblk,
-                                                    const double* __restrict__ minv, T omega) {
-    __shared__ VankaLds<T, UNIFORM, NCLS> sh;
+                                                    const double* __restrict__ minv, T omega,
+                                                    const T* __restrict__ xc, Layout Lc,
+                                                    const T* __restrict__ pw) {
+    static_assert(!(PROL && ZERO), "the prolongation needs an iterate");
+    __shared__ VankaLds<T, UNIFORM, NCLS, PROL> sh;
     auto& xs = sh.u.a.xs;
     auto& rs = sh.u.a.rs;
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TB + tx;
@@ -308,11 +330,36 @@ __global__ __launch_bounds__(TPB) void k_vanka_step(const T* __restrict__ x_in, 
         if constexpr (!ZERO) wx.load(x_in, L.plane, L, i0 - 2, j0 - 2, tid);
         Window<T, 2, KW> wk;
         if constexpr (!UNIFORM) wk.load(kinv, L.plane, L, i0 - 2, j0 - 2, tid);
+        // coarse slots i0/2 - 1 .. i0/2 + PCW - 2 feed the fine window i0 - 2 .. i0 + VT + 1
+        Window<T, NTYPES, PCW> wc;
+        if constexpr (PROL) wc.load(xc, Lc.plane, Lc, i0 / 2 - 1, j0 / 2 - 1, tid);
         wb.store(&rs[0][0][0], tid);
         if constexpr (!ZERO) wx.store(&xs[0][0][0], tid);
         if constexpr (!UNIFORM) wk.store(&sh.ks[0][0][0], tid);
+        if constexpr (PROL) wc.store(&sh.xcs[0][0][0], tid);
     }
     __syncthreads();
+    if constexpr (PROL) {
+        // x += P x_c on the staged window (free fine DoFs only): the thread of coarse window slot
+        // (ci, cj) fills its four fine slots (2 I + pi, 2 J + pj), parities known at compile time
+        constexpr int NCW = (XS + 1) / 2;        // coarse slots whose fine slots meet the window
+        if (tid < NCW * NCW) {
+            const int cj = tid / NCW, ci = tid - cj * NCW;
+            const int I = i0 / 2 - 1 + ci, J = j0 / 2 - 1 + cj;
+            static_for(std::make_integer_sequence<int, 4>{}, [&](auto pc) {
+                constexpr int pi = decltype(pc)::value & 1, pj = decltype(pc)::value >> 1;
+                const int a = 2 * ci + pi, bb = 2 * cj + pj;   // window index of fine slot (2I+pi, 2J+pj)
+                if (a < XS && bb < XS) {
+                    static_for(std::make_integer_sequence<int, NTYPES>{}, [&](auto tcn) {
+                        constexpr int tf = decltype(tcn)::value;
+                        if (dof_free(tf, 2 * I + pi, 2 * J + pj, n))
+                            xs[tf][bb][a] += prolong_value<T, tf, pi, pj>(sh.xcs, ci, cj, pw);
+                    });
+                }
+            });
+        }
+        __syncthreads();
+    }
     // ---- residual r = b - A x_in of slot (i0-1+tx, j0-1+ty), zero on absent DoFs -----------------
     if constexpr (!ZERO) {
         const int si = i0 - 1 + tx, sj = j0 - 1 + ty;
@@ -455,39 +502,45 @@ __global__ __launch_bounds__(TPB) void k_vanka_step(const T* __restrict__ x_in, 
     }
 }
 
-template <typename T, bool UNIFORM, bool ZERO>
+template <typename T, bool UNIFORM, bool ZERO, bool PROL>
 static void launch_vanka_step_t(const LevelView<T>& lv, const T* x_in, const T* b, T* x_out, T kinv_s, T omega,
-                                hipStream_t st) {
+                                const T* xc, const Layout& Lc, const T* pw, hipStream_t st) {
     dim3 blk(TB, TB);
     dim3 grd((lv.L.n + 1 + VO - 1) / VO, (lv.L.n + 1 + VO - 1) / VO);
     // a tile spans at most two vertex classes per direction unless it covers the whole mesh
     if (UNIFORM && lv.L.n + 1 <= VT)
-        hipLaunchKernelGGL((k_vanka_step<T, UNIFORM, ZERO, 9>), grd, blk, 0, st, x_in, b, x_out, lv.L, lv.kinv,
-                           kinv_s, lv.coef, lv.cls, lv.wblk, lv.minv, omega);
+        hipLaunchKernelGGL((k_vanka_step<T, UNIFORM, ZERO, 9, PROL>), grd, blk, 0, st, x_in, b, x_out, lv.L,
+                           lv.kinv, kinv_s, lv.coef, lv.cls, lv.wblk, lv.minv, omega, xc, Lc, pw);
     else
-        hipLaunchKernelGGL((k_vanka_step<T, UNIFORM, ZERO, 4>), grd, blk, 0, st, x_in, b, x_out, lv.L, lv.kinv,
-                           kinv_s, lv.coef, lv.cls, lv.wblk, lv.minv, omega);
+        hipLaunchKernelGGL((k_vanka_step<T, UNIFORM, ZERO, 4, PROL>), grd, blk, 0, st, x_in, b, x_out, lv.L,
+                           lv.kinv, kinv_s, lv.coef, lv.cls, lv.wblk, lv.minv, omega, xc, Lc, pw);
 }
 
 template <typename T>
 void launch_vanka_step(const LevelView<T>& lv, const T* x_in, const T* b, T* x_out, bool uniform, T kinv_s,
-                       T omega, hipStream_t st) {
+                       T omega, hipStream_t st, const T* xc, const Layout* Lc, const T* pw) {
+    const Layout lc = Lc ? *Lc : lv.L;
+    if (xc && !x_in) throw ArgError{"the prolongation needs an iterate"};
     if (uniform) {
-        if (x_in)
-            launch_vanka_step_t<T, true, false>(lv, x_in, b, x_out, kinv_s, omega, st);
+        if (xc)
+            launch_vanka_step_t<T, true, false, true>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, st);
+        else if (x_in)
+            launch_vanka_step_t<T, true, false, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, st);
         else
-            launch_vanka_step_t<T, true, true>(lv, x_in, b, x_out, kinv_s, omega, st);
+            launch_vanka_step_t<T, true, true, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, st);
     } else {
-        if (x_in)
-            launch_vanka_step_t<T, false, false>(lv, x_in, b, x_out, kinv_s, omega, st);
+        if (xc)
+            launch_vanka_step_t<T, false, false, true>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, st);
+        else if (x_in)
+            launch_vanka_step_t<T, false, false, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, st);
         else
-            launch_vanka_step_t<T, false, true>(lv, x_in, b, x_out, kinv_s, omega, st);
+            launch_vanka_step_t<T, false, true, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, st);
     }
 }
 template void launch_vanka_step<double>(const LevelView<double>&, const double*, const double*, double*, bool,
-                                        double, double, hipStream_t);
+                                        double, double, hipStream_t, const double*, const Layout*, const double*);
 template void launch_vanka_step<float>(const LevelView<float>&, const float*, const float*, float*, bool, float,
-                                       float, hipStream_t);
+                                       float, hipStream_t, const float*, const Layout*, const float*);
 
 // =========================================================================================
 // inexact Braess-Sarazin relaxation (Sec. 3.2.2, Appendix D)
@@ -499,33 +552,8 @@ template void launch_vanka_step<float>(const LevelView<float>&, const float*, co
 //   du  = F_u^{-1} (r_u - A_up dp),  dw = (r_w - A_wp dp) / (tau D_w)
 //   x  += omega (du, dw, dp)
 // with diag(S)_T = (1/M + alpha^2 / (lambda + mu)) |T| + sum_e (tau B_w)_{Te}^2 / (tau D_w)_e.
-// Three launches: k_bsr_first (z_u, z_w), k_bsr_schur (dp), k_bsr_second (update).
+// Two launches: k_bsr_first (residual, z_u, z_w), k_bsr_second (dp on its window, update).
 
-
-// sum over the entries e of row type t with predicate Sel(column type) of
-// coef_e (* 1/K) * v[column slot]
-template <typename T, int t, template <int> class Sel, int... E>
-__device__ __forceinline__ T st_row_sel(const T* __restrict__ v, const T* __restrict__ kinv, long long s,
-                                        int pitch, long long plane, const T* __restrict__ c,
-                                        std::integer_sequence<int, E...>) {
-    T acc = 0;
-    static_for(std::integer_sequence<int, E...>{}, [&](auto ec) {
-        constexpr int e = decltype(ec)::value;
-        constexpr SEnt en = SST.e[t][e];
-        if constexpr (Sel<en.in>::value) {
-            T cc = c[SST.off[t] + e];
-            if constexpr (en.kt >= 0) cc *= kinv[en.kt * plane + s + (long long)en.kdj * pitch + en.kdi];
-            acc += cc * v[en.in * plane + s + (long long)en.dj * pitch + en.di];
-        }
-    });
-    return acc;
-}
-template <int tin>
-struct SelU : std::integral_constant<bool, (tfield(tin) == 0)> {};
-template <int tin>
-struct SelUW : std::integral_constant<bool, (tfield(tin) != 2)> {};
-template <int tin>
-struct SelP : std::integral_constant<bool, (tfield(tin) == 2)> {};
 
 constexpr int BSR_W = 0;   // planes 0..2 of the diagonal data: 1 / (tau D_w) of w_H, w_V, w_D
 constexpr int BSR_S = 3;   // planes 3..4: 1 / diag(S) of p_L, p_U
@@ -588,14 +616,17 @@ template void launch_bsr_diag<double>(const LevelView<double>&, double, double*,
 template void launch_bsr_diag<float>(const LevelView<float>&, float, float*, hipStream_t);
 
 constexpr int NU = 5;   // displacement DoF types ux, uy, bH, bV, bD
-constexpr int BT = 16;  // vertices per BSR tile side (threads)
-constexpr int BO = BT - 1;
 
-// Displacement-patch solves of the vertices of a tile: su holds the displacement residual
-// of slots (i0-1 .. i0+BT-1)^2, the patch corrections go to so (8 per vertex).
+// Tiles as in the Vanka step: 16 x 16 threads, VT x VT vertices from (i0, j0), VO x VO owned
+// slots; one residual slot of (i0-1 .. i0+VT-1)^2 per thread.
+
+// displacement-patch solves (8 x 8 class inverses, identity on absent DoFs) of the tile's
+// vertices from the displacement residual ru (slots i0-1 .. i0+VT-1): so[a][ty][tx]
 template <typename T>
-__device__ __forceinline__ void upatch_solves(const T (&su)[NU][BT + 1][BT + 1], const T (&ui)[9][64],
-                                              T (&so)[8][BT][BT], int vi, int vj, int n, int tx, int ty) {
+__device__ __forceinline__ void upatch_solves(const T (&ru)[NU][RW][RW], const T (&ui)[9][64], T (&so)[8][VT][VT],
+                                              int i0, int j0, int n, int tx, int ty) {
+    if (tx >= VT || ty >= VT) return;
+    const int vi = i0 + tx, vj = j0 + ty;
     T out[8];
 #pragma unroll
     for (int a = 0; a < 8; ++a) out[a] = 0;
@@ -608,7 +639,7 @@ __device__ __forceinline__ void upatch_solves(const T (&su)[NU][BT + 1][BT + 1],
         for (int a = 0; a < 8; ++a) {
             int t, di, dj;
             patch_slot(a, t, di, dj);
-            rr[a] = su[t][ty + 1 + dj][tx + 1 + di];
+            rr[a] = ru[t][ty + 1 + dj][tx + 1 + di];
         }
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
@@ -622,10 +653,10 @@ __device__ __forceinline__ void upatch_solves(const T (&su)[NU][BT + 1][BT + 1],
     for (int a = 0; a < 8; ++a) so[a][ty][tx] = out[a];
 }
 
-// weighted sum of the patch corrections at owned slot (tx, ty): P1 in one patch, bubbles
-// in the two patches of their end points (weight 1/2)
+// weighted sum of the patch corrections at owned slot (tx, ty): P1 in one patch, bubbles in
+// the two patches of their end points (weight 1/2)
 template <typename T>
-__device__ __forceinline__ void upatch_gather(const T (&so)[8][BT][BT], int tx, int ty, T (&du)[NU]) {
+__device__ __forceinline__ void upatch_gather(const T (&so)[8][VT][VT], int tx, int ty, T (&du)[NU]) {
     du[T_UX] = so[0][ty][tx];
     du[T_UY] = so[1][ty][tx];
     du[T_BH] = (T)0.5 * (so[3][ty][tx] + so[2][ty][tx + 1]);
@@ -638,157 +669,271 @@ __device__ __forceinline__ void load_uinv(const T* __restrict__ uinv, T (&ui)[9]
     T v[3];
 #pragma unroll
     for (int it = 0; it < 3; ++it) {
-        const int q = tid + it * BT * BT;
+        const int q = tid + it * TPB;
         v[it] = q < 9 * 64 ? uinv[q] : (T)0;
     }
 #pragma unroll
     for (int it = 0; it < 3; ++it) {
-        const int q = tid + it * BT * BT;
+        const int q = tid + it * TPB;
         if (q < 9 * 64) (&ui[0][0])[q] = v[it];
     }
 }
 
-// t_u = F_u^{-1} r_u, t_w = r_w / (tau D_w) on the owned slots of the tile
-template <typename T>
-__global__ __launch_bounds__(256) void k_bsr_first(const T* __restrict__ r, T* __restrict__ t, Layout L,
-                                                   const T* __restrict__ uinv, const T* __restrict__ d) {
-    __shared__ T su[NU][BT + 1][BT + 1];
-    __shared__ T so[8][BT][BT];
-    __shared__ T ui[9][64];
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * BT + tx;
-    const int i0 = blockIdx.x * BO, j0 = blockIdx.y * BO;
+template <typename T, bool UNIFORM, bool PROL>
+struct BsrFirstLds {
+    T xs[NTYPES][XS][XS];
+    T rs[NTYPES][RW][RW];
+    T so[8][VT][VT];
+    T ui[9][64];
+    T ks[UNIFORM ? 1 : 2][UNIFORM ? 1 : KW][UNIFORM ? 1 : KW];
+    T xcs[PROL ? NTYPES : 1][PROL ? PCW : 1][PROL ? PCW : 1];
+};
+
+// First half of a BSR step: r = b - A x (x: x_in, or x_in + P x_c with PROL, or 0 with ZERO),
+// t_u = F_u^{-1} r_u, t_w = r_w / (tau D_w).  Writes r and t on the owned slots, and with PROL
+// the prolongated iterate to x_pro (neighbouring tiles still read x_in on their halo).
+template <typename T, bool UNIFORM, bool ZERO, bool PROL>
+__global__ __launch_bounds__(TPB) void k_bsr_first(const T* __restrict__ x_in, T* __restrict__ x_pro,
+                                                   const T* __restrict__ b,
+                                                   T* __restrict__ r, T* __restrict__ t, Layout L,
+                                                   const T* __restrict__ kinv, T kinv_s,
+                                                   const T* __restrict__ coef, const T* __restrict__ uinv,
+                                                   const T* __restrict__ d, const T* __restrict__ xc, Layout Lc,
+                                                   const T* __restrict__ pw) {
+    static_assert(!(PROL && ZERO), "the prolongation needs an iterate");
+    __shared__ BsrFirstLds<T, UNIFORM, PROL> sh;
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TB + tx;
+    const int i0 = blockIdx.x * VO, j0 = blockIdx.y * VO;
     const int n = L.n;
     {
-        constexpr int TS = (BT + 1) * (BT + 1);
-        constexpr int NV = NU * TS;
-        constexpr int NIT = (NV + BT * BT - 1) / (BT * BT);
-        T v[NIT];
-#pragma unroll
-        for (int it = 0; it < NIT; ++it) {
-            const int q = tid + it * BT * BT;
-            const int tt = q / TS, rem = q - tt * TS, bb = rem / (BT + 1), aa = rem - bb * (BT + 1);
-            const int si = i0 - 1 + aa, sj = j0 - 1 + bb;
-            v[it] = (q < NV && si <= n + 1 && sj <= n + 1) ? r[tt * L.plane + slot_index(L, si, sj)] : (T)0;
-        }
-#pragma unroll
-        for (int it = 0; it < NIT; ++it) {
-            const int q = tid + it * BT * BT;
-            if (q < NV) (&su[0][0][0])[q] = v[it];
-        }
-    }
-    load_uinv(uinv, ui, tid);
-    const int si = i0 + tx, sj = j0 + ty;
-    const bool own = tx < BO && ty < BO && si <= n && sj <= n;
-    const long long s0 = own ? slot_index(L, si, sj) : 0;
-    T rw[3], dw[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        rw[q] = own ? r[(T_WH + q) * L.plane + s0] : (T)0;
-        dw[q] = own ? d[(BSR_W + q) * L.plane + s0] : (T)0;
+        Window<T, NTYPES, RW> wb;
+        wb.load(b, L.plane, L, i0 - 1, j0 - 1, tid);
+        Window<T, NTYPES, XS> wx;
+        if constexpr (!ZERO) wx.load(x_in, L.plane, L, i0 - 2, j0 - 2, tid);
+        Window<T, 2, KW> wk;
+        if constexpr (!UNIFORM && !ZERO) wk.load(kinv, L.plane, L, i0 - 2, j0 - 2, tid);
+        Window<T, NTYPES, PCW> wc;
+        if constexpr (PROL) wc.load(xc, Lc.plane, Lc, i0 / 2 - 1, j0 / 2 - 1, tid);
+        load_uinv(uinv, sh.ui, tid);
+        wb.store(&sh.rs[0][0][0], tid);
+        if constexpr (!ZERO) wx.store(&sh.xs[0][0][0], tid);
+        if constexpr (!UNIFORM && !ZERO) wk.store(&sh.ks[0][0][0], tid);
+        if constexpr (PROL) wc.store(&sh.xcs[0][0][0], tid);
     }
     __syncthreads();
-    upatch_solves<T>(su, ui, so, si, sj, n, tx, ty);
-    __syncthreads();
-    if (own) {
-        T du[NU];
-        upatch_gather<T>(so, tx, ty, du);
-#pragma unroll
-        for (int q = 0; q < NU; ++q) t[q * L.plane + s0] = dof_free(q, si, sj, n) ? du[q] : (T)0;
-#pragma unroll
-        for (int q = 0; q < 3; ++q) t[(T_WH + q) * L.plane + s0] = rw[q] * dw[q];
+    if constexpr (PROL) {
+        constexpr int NCW = (XS + 1) / 2;
+        if (tid < NCW * NCW) {
+            const int cj = tid / NCW, ci = tid - cj * NCW;
+            const int I = i0 / 2 - 1 + ci, J = j0 / 2 - 1 + cj;
+            static_for(std::make_integer_sequence<int, 4>{}, [&](auto pc) {
+                constexpr int pi = decltype(pc)::value & 1, pj = decltype(pc)::value >> 1;
+                const int a = 2 * ci + pi, bb = 2 * cj + pj;
+                if (a < XS && bb < XS) {
+                    static_for(std::make_integer_sequence<int, NTYPES>{}, [&](auto tcn) {
+                        constexpr int tf = decltype(tcn)::value;
+                        if (dof_free(tf, 2 * I + pi, 2 * J + pj, n))
+                            sh.xs[tf][bb][a] += prolong_value<T, tf, pi, pj>(sh.xcs, ci, cj, pw);
+                    });
+                }
+            });
+        }
+        __syncthreads();
     }
-}
-
-// t_p = omega_J (A_pu t_u + A_pw t_w - r_p) / diag(S), one thread per slot
-template <typename T>
-__global__ __launch_bounds__(256) void k_bsr_schur(const T* __restrict__ r, T* __restrict__ t, Layout L,
-                                                   const T* __restrict__ coef, const T* __restrict__ d,
-                                                   T omega_J) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    if (i > L.n || j > L.n) return;
-    const long long s = slot_index(L, i, j);
-    static_for(std::integer_sequence<int, T_PL, T_PU>{}, [&](auto tc) {
-        constexpr int tp = decltype(tc)::value;
-        const T a = st_row_sel<T, tp, SelUW>(t, nullptr, s, L.pitch, L.plane, coef,
-                                             std::make_integer_sequence<int, SST.n[tp]>{});
-        const T v = omega_J * (a - r[tp * L.plane + s]) * d[(BSR_S + tp - T_PL) * L.plane + s];
-        t[tp * L.plane + s] = dof_free(tp, i, j, L.n) ? v : (T)0;
-    });
-}
-
-// x += omega (F_u^{-1}(r_u - A_up t_p), (r_w - A_wp t_p) / (tau D_w), t_p)
-template <typename T>
-__global__ __launch_bounds__(256) void k_bsr_second(const T* __restrict__ r, const T* __restrict__ t,
-                                                    T* __restrict__ x, Layout L, const T* __restrict__ uinv,
-                                                    const T* __restrict__ coef, const T* __restrict__ d,
-                                                    T omega, int x_is_zero) {
-    __shared__ T su[NU][BT + 1][BT + 1];
-    __shared__ T so[8][BT][BT];
-    __shared__ T ui[9][64];
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * BT + tx;
-    const int i0 = blockIdx.x * BO, j0 = blockIdx.y * BO;
-    const int n = L.n;
-    // displacement residual after the pressure update, slots (i0-1 .. i0+BT-1)^2; its
-    // pressure columns reach slots -1..0 away, inside the two-deep low ghost ring
-    for (int q = tid; q < (BT + 1) * (BT + 1); q += BT * BT) {
-        const int bb = q / (BT + 1), aa = q - bb * (BT + 1);
-        const int si = i0 - 1 + aa, sj = j0 - 1 + bb;
+    if constexpr (!ZERO) {
+        const int si = i0 - 1 + tx, sj = j0 - 1 + ty;
         const bool in = si <= n + 1 && sj <= n + 1;
-        const long long s = in ? slot_index(L, si, sj) : 0;
-        static_for(std::make_integer_sequence<int, NU>{}, [&](auto tc) {
-            constexpr int tu = decltype(tc)::value;
-            T v = 0;
-            if (in && dof_free(tu, si, sj, n))
-                v = r[tu * L.plane + s] - st_row_sel<T, tu, SelP>(t, nullptr, s, L.pitch, L.plane, coef,
-                                                                std::make_integer_sequence<int, SST.n[tu]>{});
-            su[tu][bb][aa] = v;
+        T rv[NTYPES];
+        static_for(std::make_integer_sequence<int, NTYPES>{}, [&](auto tcn) {
+            constexpr int tt = decltype(tcn)::value;
+            T acc = 0;
+            static_for(std::make_integer_sequence<int, SST.n[tt]>{}, [&](auto ec) {
+                constexpr int e = decltype(ec)::value;
+                constexpr SEnt en = SST.e[tt][e];
+                T cc = coef[SST.off[tt] + e];
+                if constexpr (en.kt >= 0) {
+                    if constexpr (UNIFORM)
+                        cc *= kinv_s;
+                    else
+                        cc *= sh.ks[en.kt][ty + 1 + en.kdj][tx + 1 + en.kdi];
+                }
+                acc += cc * sh.xs[en.in][ty + 1 + en.dj][tx + 1 + en.di];
+            });
+            rv[tt] = (in && dof_free(tt, si, sj, n)) ? sh.rs[tt][ty][tx] - acc : (T)0;
+        });
+#pragma unroll
+        for (int tt = 0; tt < NTYPES; ++tt) sh.rs[tt][ty][tx] = rv[tt];
+        __syncthreads();
+    }
+    upatch_solves<T>(reinterpret_cast<const T(&)[NU][RW][RW]>(sh.rs), sh.ui, sh.so, i0, j0, n, tx, ty);
+    __syncthreads();
+    if (tx < VO && ty < VO) {
+        const int si = i0 + tx, sj = j0 + ty;
+        if (si <= n && sj <= n) {
+            const long long s0 = slot_index(L, si, sj);
+            T du[NU];
+            upatch_gather<T>(sh.so, tx, ty, du);
+#pragma unroll
+            for (int q = 0; q < NU; ++q) t[q * L.plane + s0] = dof_free(q, si, sj, n) ? du[q] : (T)0;
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                t[(T_WH + q) * L.plane + s0] = sh.rs[T_WH + q][ty + 1][tx + 1] * d[(BSR_W + q) * L.plane + s0];
+#pragma unroll
+            for (int q = 0; q < NTYPES; ++q) r[q * L.plane + s0] = sh.rs[q][ty + 1][tx + 1];
+            if constexpr (PROL) {
+#pragma unroll
+                for (int q = 0; q < NTYPES; ++q)
+                    if (dof_free(q, si, sj, n)) x_pro[q * L.plane + s0] = sh.xs[q][ty + 2][tx + 2];
+            }
+        }
+    }
+}
+
+// Second half: dp = omega_J (A_pu t_u + A_pw t_w - r_p) / diag(S) on the window the update
+// needs, then x_dst = x_src + omega (F_u^{-1}(r_u - A_up dp), (r_w - A_wp dp) / (tau D_w), dp)
+// on the owned slots (x_dst may be x_src: each slot is read and written by its own thread).
+constexpr int TW = VT + 4;   // staged t: slots i0-2 .. i0+VT+1
+constexpr int DW = VT + 3;   // pressure update: slots i0-2 .. i0+VT
+
+template <typename T>
+struct BsrSecondLds {
+    T ts[8][TW][TW];         // t_u, t_w
+    T dp[2][DW][DW];         // r_p, then the pressure update
+    T ds[2][DW][DW];         // 1 / diag(S)
+    T ru[NU][RW][RW];        // r_u, then r_u - A_up dp
+    T so[8][VT][VT];
+    T ui[9][64];
+};
+
+template <typename T, bool ZERO>
+__global__ __launch_bounds__(TPB) void k_bsr_second(const T* __restrict__ r, const T* __restrict__ t,
+                                                    const T* x_src, T* x, Layout L, const T* __restrict__ uinv,
+                                                    const T* __restrict__ coef, const T* __restrict__ d,
+                                                    T omega, T omega_J) {
+    __shared__ BsrSecondLds<T> sh;
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TB + tx;
+    const int i0 = blockIdx.x * VO, j0 = blockIdx.y * VO;
+    const int n = L.n;
+    {
+        Window<T, 8, TW> wt;
+        wt.load(t, L.plane, L, i0 - 2, j0 - 2, tid);
+        Window<T, 2, DW> wp;
+        wp.load(r + T_PL * L.plane, L.plane, L, i0 - 2, j0 - 2, tid);
+        Window<T, 2, DW> wd;
+        wd.load(d + BSR_S * L.plane, L.plane, L, i0 - 2, j0 - 2, tid);
+        Window<T, NU, RW> wr;
+        wr.load(r, L.plane, L, i0 - 1, j0 - 1, tid);
+        load_uinv(uinv, sh.ui, tid);
+        wt.store(&sh.ts[0][0][0], tid);
+        wp.store(&sh.dp[0][0][0], tid);
+        wd.store(&sh.ds[0][0][0], tid);
+        wr.store(&sh.ru[0][0][0], tid);
+    }
+    __syncthreads();
+    // pressure update on slots (i0-2 .. i0+VT)^2; its columns reach t at +0 .. +1
+    for (int q = tid; q < DW * DW; q += TPB) {
+        const int bb = q / DW, a = q - bb * DW;
+        const int si = i0 - 2 + a, sj = j0 - 2 + bb;
+        static_for(std::integer_sequence<int, T_PL, T_PU>{}, [&](auto tc) {
+            constexpr int tp = decltype(tc)::value;
+            T acc = 0;
+            static_for(std::make_integer_sequence<int, SST.n[tp]>{}, [&](auto ec) {
+                constexpr int e = decltype(ec)::value;
+                constexpr SEnt en = SST.e[tp][e];
+                if constexpr (tfield(en.in) != 2) {
+                    static_assert(en.kt < 0, "the pressure rows do not depend on K");
+                    acc += coef[SST.off[tp] + e] * sh.ts[en.in][bb + en.dj][a + en.di];
+                }
+            });
+            const T v = omega_J * (acc - sh.dp[tp - T_PL][bb][a]) * sh.ds[tp - T_PL][bb][a];
+            sh.dp[tp - T_PL][bb][a] = dof_free(tp, si, sj, n) ? v : (T)0;
         });
     }
-    load_uinv(uinv, ui, tid);
-    const int si = i0 + tx, sj = j0 + ty;
-    const bool own = tx < BO && ty < BO && si <= n && sj <= n;
-    const long long s0 = own ? slot_index(L, si, sj) : 0;
-    T old[NTYPES];
-#pragma unroll
-    for (int q = 0; q < NTYPES; ++q) old[q] = (own && !x_is_zero) ? x[q * L.plane + s0] : (T)0;
     __syncthreads();
-    upatch_solves<T>(su, ui, so, si, sj, n, tx, ty);
-    __syncthreads();
-    if (own) {
-        T du[NU];
-        upatch_gather<T>(so, tx, ty, du);
-#pragma unroll
-        for (int q = 0; q < NU; ++q)
-            if (dof_free(q, si, sj, n)) x[q * L.plane + s0] = old[q] + omega * du[q];
-        static_for(std::integer_sequence<int, T_WH, T_WV, T_WD>{}, [&](auto tc) {
-            constexpr int tw = decltype(tc)::value;
-            const T a = st_row_sel<T, tw, SelP>(t, nullptr, s0, L.pitch, L.plane, coef,
-                                                std::make_integer_sequence<int, SST.n[tw]>{});
-            const T dwv = (r[tw * L.plane + s0] - a) * d[(BSR_W + tw - T_WH) * L.plane + s0];
-            if (dof_free(tw, si, sj, n)) x[tw * L.plane + s0] = old[tw] + omega * dwv;
+    // displacement residual after the pressure update, slot (i0-1+tx, j0-1+ty); its pressure
+    // columns reach dp at -1 .. 0
+    {
+        const int si = i0 - 1 + tx, sj = j0 - 1 + ty;
+        T rv[NU];
+        static_for(std::make_integer_sequence<int, NU>{}, [&](auto tcn) {
+            constexpr int tu = decltype(tcn)::value;
+            T acc = 0;
+            static_for(std::make_integer_sequence<int, SST.n[tu]>{}, [&](auto ec) {
+                constexpr int e = decltype(ec)::value;
+                constexpr SEnt en = SST.e[tu][e];
+                if constexpr (tfield(en.in) == 2) acc += coef[SST.off[tu] + e] * sh.dp[en.in - T_PL][ty + 1 + en.dj][tx + 1 + en.di];
+            });
+            rv[tu] = dof_free(tu, si, sj, n) ? sh.ru[tu][ty][tx] - acc : (T)0;
         });
+        __syncthreads();
 #pragma unroll
-        for (int q = T_PL; q <= T_PU; ++q)
-            if (dof_free(q, si, sj, n)) x[q * L.plane + s0] = old[q] + omega * t[q * L.plane + s0];
+        for (int q = 0; q < NU; ++q) sh.ru[q][ty][tx] = rv[q];
+    }
+    __syncthreads();
+    upatch_solves<T>(sh.ru, sh.ui, sh.so, i0, j0, n, tx, ty);
+    __syncthreads();
+    if (tx < VO && ty < VO) {
+        const int si = i0 + tx, sj = j0 + ty;
+        if (si <= n && sj <= n) {
+            const long long s0 = slot_index(L, si, sj);
+            T du[NU];
+            upatch_gather<T>(sh.so, tx, ty, du);
+#pragma unroll
+            for (int q = 0; q < NU; ++q)
+                if (dof_free(q, si, sj, n)) x[q * L.plane + s0] = (ZERO ? (T)0 : x_src[q * L.plane + s0]) + omega * du[q];
+            static_for(std::integer_sequence<int, T_WH, T_WV, T_WD>{}, [&](auto tc) {
+                constexpr int tw = decltype(tc)::value;
+                T acc = 0;
+                static_for(std::make_integer_sequence<int, SST.n[tw]>{}, [&](auto ec) {
+                    constexpr int e = decltype(ec)::value;
+                    constexpr SEnt en = SST.e[tw][e];
+                    if constexpr (tfield(en.in) == 2) acc += coef[SST.off[tw] + e] * sh.dp[en.in - T_PL][ty + 2 + en.dj][tx + 2 + en.di];
+                });
+                const T dwv = (r[tw * L.plane + s0] - acc) * d[(BSR_W + tw - T_WH) * L.plane + s0];
+                if (dof_free(tw, si, sj, n)) x[tw * L.plane + s0] = (ZERO ? (T)0 : x_src[tw * L.plane + s0]) + omega * dwv;
+            });
+#pragma unroll
+            for (int q = T_PL; q <= T_PU; ++q)
+                if (dof_free(q, si, sj, n))
+                    x[q * L.plane + s0] = (ZERO ? (T)0 : x_src[q * L.plane + s0]) + omega * sh.dp[q - T_PL][ty + 2][tx + 2];
+        }
     }
 }
 
 template <typename T>
-void launch_bsr(const LevelView<T>& lv, const T* r, T* t, T* x, T omega, T omega_J, int x_is_zero,
-                hipStream_t st) {
-    dim3 tb(BT, BT);
-    dim3 tg((lv.L.n + 1 + BO - 1) / BO, (lv.L.n + 1 + BO - 1) / BO);
-    dim3 sb(64, 4);
-    dim3 sg((lv.L.n + 1 + 63) / 64, (lv.L.n + 1 + 3) / 4);
-    hipLaunchKernelGGL(k_bsr_first<T>, tg, tb, 0, st, r, t, lv.L, lv.uinv, lv.bsrd);
-    hipLaunchKernelGGL(k_bsr_schur<T>, sg, sb, 0, st, r, t, lv.L, lv.coef, lv.bsrd, omega_J);
-    hipLaunchKernelGGL(k_bsr_second<T>, tg, tb, 0, st, r, t, x, lv.L, lv.uinv, lv.coef, lv.bsrd, omega, x_is_zero);
+void launch_bsr_step(const LevelView<T>& lv, T* x, const T* b, T* r, T* t, bool x_is_zero, bool uniform, T kinv_s,
+                     T omega, T omega_J, const T* xc, const Layout* Lc, const T* pw, T* xtmp, hipStream_t st) {
+    dim3 blk(TB, TB);
+    dim3 grd((lv.L.n + 1 + VO - 1) / VO, (lv.L.n + 1 + VO - 1) / VO);
+    const Layout lc = Lc ? *Lc : lv.L;
+    if (xc && (x_is_zero || !xtmp || xtmp == x)) throw ArgError{"the prolongation needs an iterate and a buffer"};
+#define BIOT_BSR_FIRST(U, Z, P)                                                                                  \
+    hipLaunchKernelGGL((k_bsr_first<T, U, Z, P>), grd, blk, 0, st, x, xtmp, b, r, t, lv.L, lv.kinv, kinv_s,     \
+                       lv.coef, lv.uinv, lv.bsrd, xc, lc, pw)
+    if (x_is_zero)
+        BIOT_BSR_FIRST(true, true, false);
+    else if (uniform && xc)
+        BIOT_BSR_FIRST(true, false, true);
+    else if (uniform)
+        BIOT_BSR_FIRST(true, false, false);
+    else if (xc)
+        BIOT_BSR_FIRST(false, false, true);
+    else
+        BIOT_BSR_FIRST(false, false, false);
+#undef BIOT_BSR_FIRST
+    const T* xsrc = xc ? xtmp : x;
+    if (x_is_zero)
+        hipLaunchKernelGGL((k_bsr_second<T, true>), grd, blk, 0, st, r, t, xsrc, x, lv.L, lv.uinv, lv.coef, lv.bsrd,
+                           omega, omega_J);
+    else
+        hipLaunchKernelGGL((k_bsr_second<T, false>), grd, blk, 0, st, r, t, xsrc, x, lv.L, lv.uinv, lv.coef, lv.bsrd,
+                           omega, omega_J);
 }
-template void launch_bsr<double>(const LevelView<double>&, const double*, double*, double*, double, double, int,
-                                 hipStream_t);
-template void launch_bsr<float>(const LevelView<float>&, const float*, float*, float*, float, float, int,
-                                hipStream_t);
+template void launch_bsr_step<double>(const LevelView<double>&, double*, const double*, double*, double*, bool, bool,
+                                      double, double, double, const double*, const Layout*, const double*, double*,
+                                      hipStream_t);
+template void launch_bsr_step<float>(const LevelView<float>&, float*, const float*, float*, float*, bool, bool, float,
+                                     float, float, const float*, const Layout*, const float*, float*, hipStream_t);
 
 // =========================================================================================
 // grid transfers (Sec. 3, 3.1): gather forms of P^T and P
@@ -844,6 +989,152 @@ template void launch_restrict<double>(const Layout&, const Layout&, const double
                                       hipStream_t);
 template void launch_restrict<float>(const Layout&, const Layout&, const float*, float*, const float*,
                                      hipStream_t);
+
+// r_c = P^T (b - A x) without storing the fine residual.  A block of 16 x 16 threads owns a
+// tile of RT x RT coarse slots from (I0, J0); each thread forms the fine residual of one slot
+// of the window (2 I0 - 2 .. 2 I0 + 2 RT + 1)^2 that the restriction reads (fine offsets
+// -2 .. +1 per coarse slot), from x staged on a one-slot wider window.
+constexpr int RT = 7;                // coarse slots per tile side
+constexpr int RRW = 2 * RT + 2;      // fine residual window (= 16, one slot per thread)
+constexpr int RXW = RRW + 2;         // staged x window
+static_assert(RRW == TB, "one fine residual slot per thread");
+
+template <typename T, bool UNIFORM>
+struct ResRestrictLds {
+    T xs[NTYPES][RXW][RXW];
+    T rs[NTYPES][RRW][RRW];
+    T ks[UNIFORM ? 1 : 2][UNIFORM ? 1 : RXW][UNIFORM ? 1 : RXW];
+};
+
+template <typename T, int tc, int e>
+__device__ __forceinline__ T rr_term(const T (&rs)[NTYPES][RRW][RRW], int cx, int cy, const T* __restrict__ w) {
+    constexpr RTerm rt = RST.e[tc][e];
+    return w[rt.w] * rs[rt.tf][2 * cy + 2 + rt.dj][2 * cx + 2 + rt.di];
+}
+
+template <typename T, int tc, int... E>
+__device__ __forceinline__ T rr_row(const T (&rs)[NTYPES][RRW][RRW], int cx, int cy, const T* __restrict__ w,
+                                    std::integer_sequence<int, E...>) {
+    T acc = 0;
+    ((acc += rr_term<T, tc, E>(rs, cx, cy, w)), ...);
+    return acc;
+}
+
+template <typename T, bool UNIFORM>
+__global__ __launch_bounds__(TPB) void k_residual_restrict(const T* __restrict__ x, const T* __restrict__ b,
+                                                           T* __restrict__ rc, Layout Lf, Layout Lc,
+                                                           const T* __restrict__ kinv, T kinv_s,
+                                                           const T* __restrict__ coef, const T* __restrict__ w) {
+    __shared__ ResRestrictLds<T, UNIFORM> sh;
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TB + tx;
+    const int I0 = blockIdx.x * RT, J0 = blockIdx.y * RT;
+    const int f0i = 2 * I0 - 2, f0j = 2 * J0 - 2;   // fine origin of the residual window
+    const int n = Lf.n;
+    {
+        // x on (f0 - 1 .. f0 + RRW)^2; slots below -2 lie outside the padded plane and only
+        // feed residuals of slots outside the mesh (masked)
+        constexpr int NV = NTYPES * RXW * RXW;
+        constexpr int NIT = (NV + TPB - 1) / TPB;
+        T v[NIT];
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int q = tid + it * TPB;
+            const int p = q / (RXW * RXW), rem = q - p * (RXW * RXW), bj = rem / RXW, ai = rem - bj * RXW;
+            const int si = f0i - 1 + ai, sj = f0j - 1 + bj;
+            v[it] = (q < NV && si >= -2 && sj >= -2 && si <= n + 1 && sj <= n + 1)
+                        ? x[p * Lf.plane + slot_index(Lf, si, sj)] : (T)0;
+        }
+        T bv[NTYPES];
+        const int si = f0i + tx, sj = f0j + ty;
+        const bool inb = si >= -2 && sj >= -2 && si <= n + 1 && sj <= n + 1;
+#pragma unroll
+        for (int t = 0; t < NTYPES; ++t) bv[t] = inb ? b[t * Lf.plane + slot_index(Lf, si, sj)] : (T)0;
+        T kv[UNIFORM ? 1 : (2 * RXW * RXW + TPB - 1) / TPB];
+        if constexpr (!UNIFORM) {
+#pragma unroll
+            for (int it = 0; it < (2 * RXW * RXW + TPB - 1) / TPB; ++it) {
+                const int q = tid + it * TPB;
+                const int p = q / (RXW * RXW), rem = q - p * (RXW * RXW), bj = rem / RXW, ai = rem - bj * RXW;
+                const int ki = f0i - 1 + ai, kj = f0j - 1 + bj;
+                kv[it] = (q < 2 * RXW * RXW && ki >= -2 && kj >= -2 && ki <= n + 1 && kj <= n + 1)
+                             ? kinv[p * Lf.plane + slot_index(Lf, ki, kj)] : (T)0;
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int q = tid + it * TPB;
+            if (q < NV) (&sh.xs[0][0][0])[q] = v[it];
+        }
+#pragma unroll
+        for (int t = 0; t < NTYPES; ++t) sh.rs[t][ty][tx] = bv[t];
+        if constexpr (!UNIFORM) {
+#pragma unroll
+            for (int it = 0; it < (2 * RXW * RXW + TPB - 1) / TPB; ++it) {
+                const int q = tid + it * TPB;
+                if (q < 2 * RXW * RXW) (&sh.ks[0][0][0])[q] = kv[it];
+            }
+        }
+    }
+    __syncthreads();
+    // fine residual of slot (f0i + tx, f0j + ty), zero on absent DoFs
+    {
+        const int si = f0i + tx, sj = f0j + ty;
+        T rv[NTYPES];
+        static_for(std::make_integer_sequence<int, NTYPES>{}, [&](auto tcn) {
+            constexpr int t = decltype(tcn)::value;
+            T acc = 0;
+            static_for(std::make_integer_sequence<int, SST.n[t]>{}, [&](auto ec) {
+                constexpr int e = decltype(ec)::value;
+                constexpr SEnt en = SST.e[t][e];
+                T cc = coef[SST.off[t] + e];
+                if constexpr (en.kt >= 0) {
+                    if constexpr (UNIFORM)
+                        cc *= kinv_s;
+                    else
+                        cc *= sh.ks[en.kt][ty + 1 + en.kdj][tx + 1 + en.kdi];
+                }
+                acc += cc * sh.xs[en.in][ty + 1 + en.dj][tx + 1 + en.di];
+            });
+            rv[t] = dof_free(t, si, sj, n) ? sh.rs[t][ty][tx] - acc : (T)0;
+        });
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < NTYPES; ++t) sh.rs[t][ty][tx] = rv[t];
+    }
+    __syncthreads();
+    // restriction of the tile's coarse slots: wave (q / 64) handles one coarse DoF type, so the
+    // compile-time restriction row is uniform over the wave
+    static_assert(RT * RT <= 64, "one coarse tile per wave");
+    for (int q = tid; q < NTYPES * 64; q += TPB) {
+        const int tc = q >> 6, slot = q & 63;
+        const int cy = slot / RT, cx = slot - cy * RT;
+        const int I = I0 + cx, J = J0 + cy;
+        if (slot >= RT * RT || I > Lc.n || J > Lc.n) continue;
+        T v = 0;
+        static_for(std::make_integer_sequence<int, NTYPES>{}, [&](auto tcn) {
+            constexpr int tcc = decltype(tcn)::value;
+            if (tcc == tc) v = rr_row<T, tcc>(sh.rs, cx, cy, w, std::make_integer_sequence<int, RST.n[tcc]>{});
+        });
+        rc[tc * Lc.plane + slot_index(Lc, I, J)] = dof_free(tc, I, J, Lc.n) ? v : (T)0;
+    }
+}
+
+template <typename T>
+void launch_residual_restrict(const LevelView<T>& lf, const Layout& Lc, const T* x, const T* b, T* rc,
+                              bool uniform, T kinv_s, const T* w, hipStream_t st) {
+    dim3 blk(TB, TB);
+    dim3 grd((Lc.n + 1 + RT - 1) / RT, (Lc.n + 1 + RT - 1) / RT);
+    if (uniform)
+        hipLaunchKernelGGL((k_residual_restrict<T, true>), grd, blk, 0, st, x, b, rc, lf.L, Lc, lf.kinv, kinv_s,
+                           lf.coef, w);
+    else
+        hipLaunchKernelGGL((k_residual_restrict<T, false>), grd, blk, 0, st, x, b, rc, lf.L, Lc, lf.kinv, kinv_s,
+                           lf.coef, w);
+}
+template void launch_residual_restrict<double>(const LevelView<double>&, const Layout&, const double*,
+                                               const double*, double*, bool, double, const double*, hipStream_t);
+template void launch_residual_restrict<float>(const LevelView<float>&, const Layout&, const float*, const float*,
+                                              float*, bool, float, const float*, hipStream_t);
 
 // fine DoF (tf, parity): sum over the field's coarse local DoFs of its designated triangle;
 // xcl[t][dj][di] holds the coarse values of slots (I + di, J + dj), di, dj in {0, 1}
