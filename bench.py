@@ -3,9 +3,11 @@
 1e-8 on the 256 x 256 workload (9 parameter sets: nu in {0.2, 0.49, 0.4999} x K in
 {1, 1e-3, 1e-6}, E = 1, tau = 1, right-hand side uniform[-1, 1] from seed 1, 7 levels).
 
-One step = one full solve of every (parameter set, smoother) pair, hierarchies built
-beforehand, inputs resident in device memory.  Metric: free DoFs solved per second
-(MDOF/s).  Prints one JSON line.
+One step = one full solve of every (parameter set, smoother) pair (9 sets x {Vanka V(2,2),
+inexact BSR V(1,1)}, LFA-optimized weights), hierarchies built beforehand, inputs resident in
+device memory; the independent solves run concurrently on --streams streams.  Metric: free
+DoFs solved per second over the whole step (MDOF/s).  Prints one JSON line; "sequential"
+repeats one step with the solves one after the other.
 """
 import argparse
 import json
@@ -19,7 +21,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 CSRC = os.path.join(ROOT, "paper_2107_04060_amd", "csrc")
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_vanka_uniform_sweep256_fp64.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_vanka_step_sweep256_fp64.md")
 
 
 def kernel_source_hash():
@@ -66,6 +68,11 @@ def parse():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--streams", type=int, default=8,
+                    help="the independent solves of a step run concurrently on this many streams (one host "
+                         "thread each)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the precision-form and adjoint comparisons reported beside the headline")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="before the warm-up, copy a device buffer of this many MiB once (the plain "
                          "copy kernel that scales the HBM byte counters)")
@@ -102,6 +109,91 @@ def cpu_baseline(case, b, iters, nu12, omega, omega_J, smoother, n, levels):
                       % (nu12, nu12, smoother, case["nu"], case["K"], n, n, t_it, iters)}
 
 
+def _timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return r, (time.perf_counter() - t) * 1e3
+
+
+def precision_extra(binding, inputs, torch):
+    """The 1024 x 1024 heterogeneous-permeability workload solved by the plain FP64 form and by the
+    precision form (FP32 vectors and residuals, FP64 patch arithmetic and Krylov), same right-hand
+    side, tolerance 1e-8 in the FP64 true residual; the relative difference of the two solutions."""
+    import numpy as np
+    w = inputs.workload("grf1024")
+    c = w["cases"][0]
+    n = w["n"]
+    K = torch.tensor(inputs.permeability_triangles("grf1024"), dtype=torch.float64, device="cuda")
+    om, omj = inputs.relaxation_weights("vanka", workload="grf1024")
+    b = torch.tensor(inputs.rhs_uniform(n, w["seed"]), dtype=torch.float64, device="cuda")
+    res = {}
+    sol = {}
+    for prec in ("fp64", "fp32"):
+        s = binding.BiotSolver(n, c["lam"], c["mu"], alpha=w["alpha"], M=w["M"], mu_f=w["mu_f"], tau=w["tau"], K=K)
+        s.setup(levels=w["levels"], smoother="vanka", nu1=2, nu2=2, omega=om, omega_J=omj, precision=prec)
+        s.solve(b, tol=1e-8, restart=30, maxit=300)                     # warm-up
+        (x, info), ms = _timed(lambda: s.solve(b, tol=1e-8, restart=30, maxit=300))
+        sol[prec] = x
+        res[prec] = {"ms": round(ms, 3), "iters": info["iters"], "rel_res_true": info["rel_res_true"],
+                     "MDOF/s": round(inputs.n_free(n) / (ms * 1e-3) / 1e6, 2)}
+        s.close()
+    # per field (canonical order u, w, p); p with its mean removed, since the constant pressure
+    # is the near-null mode that dominates |x| for a random right-hand side
+    nu_, nw_ = 5 * n * n - 6 * n + 2, 3 * n * n - 2 * n
+    diff = {}
+    for name, a, z in (("u", 0, nu_), ("w", nu_, nu_ + nw_), ("p_mean_removed", nu_ + nw_, None)):
+        x32, x64 = sol["fp32"][a:z], sol["fp64"][a:z]
+        if name.startswith("p"):
+            x32, x64 = x32 - x32.mean(), x64 - x64.mean()
+        diff[name] = float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
+    res["rel_diff_fp32_vs_fp64_solution"] = diff
+    res["speedup_fp32_form"] = round(res["fp64"]["ms"] / res["fp32"]["ms"], 3)
+    res["workload"] = "grf1024 (1024x1024, log10 K = -3 + GRF(0.1), nu 0.49, tau 1e-2, Vanka V(2,2))"
+    return res
+
+
+def adjoint_extra(binding, inputs, torch, batch=8):
+    """The 512 x 512 adjoint workload: for each of `batch` log-permeability samples, the forward
+    solve alone, and forward + adjoint solve + per-triangle gradient (FP64, 1e-10)."""
+    from paper_2107_04060_amd.binding import solve
+    w = inputs.workload("adjoint512")
+    c = w["cases"][0]
+    n = w["n"]
+    thetas, theta_obs = inputs.adjoint_fields(n, batch)
+    om, omj = inputs.relaxation_weights("vanka", workload="adjoint512")
+    s = binding.BiotSolver(n, c["lam"], c["mu"], alpha=w["alpha"], M=w["M"], mu_f=w["mu_f"], tau=w["tau"], K=1.0)
+    s.setup(levels=w["levels"], smoother="vanka", nu1=2, nu2=2, omega=om, omega_J=omj)
+    b = torch.tensor(inputs.rhs_uniform(n, w["seed"]), dtype=torch.float64, device="cuda")
+    nu = inputs.n_free(n) - 2 * n * n
+    s.update_K(torch.exp(torch.tensor(theta_obs, dtype=torch.float64, device="cuda")))
+    p_obs = s.solve(b, tol=1e-12, restart=30, maxit=1000)[0][nu:].clone()
+    th = [torch.tensor(t, dtype=torch.float64, device="cuda") for t in thetas]
+    fwd_ms = grad_ms = 0.0
+    for t in th:
+        def fwd():
+            with torch.no_grad():
+                return solve(t, b, s, tol=1e-10, restart=30, maxit=1000)
+        _, ms = _timed(fwd)
+        fwd_ms += ms
+
+        def both():
+            tt = t.clone().requires_grad_(True)
+            x = solve(tt, b, s, tol=1e-10, restart=30, maxit=1000)
+            loss = 0.5 * ((x[nu:] - p_obs) ** 2).sum()
+            loss.backward()
+            return tt.grad
+        _, ms = _timed(both)
+        grad_ms += ms
+    s.close()
+    return {"workload": "adjoint512 (512x512, ln K = GRF(0.05), batch %d, tol 1e-10)" % batch,
+            "forward_ms_per_sample": round(fwd_ms / batch, 3),
+            "forward_adjoint_gradient_ms_per_sample": round(grad_ms / batch, 3),
+            "gradient_over_forward": round(grad_ms / fwd_ms, 3)}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -136,11 +228,38 @@ def main():
             runs.append(dict(solver=s, smoother=sm, case=case, omega=om, omega_J=omj, nu12=nu12))
     torch.cuda.synchronize()
 
+    # the solves of a step are independent systems: with --streams K they are dealt round-robin to
+    # K host threads, each issuing its solves on a stream of its own (default priority)
+    nstreams = max(1, min(args.streams, len(runs)))
+    streams = [torch.cuda.Stream() for _ in range(nstreams)] if nstreams > 1 else [torch.cuda.current_stream()]
+    xs = [torch.empty_like(b) for _ in runs]
+    bs = [b.clone() for _ in range(nstreams)]
+    torch.cuda.synchronize()
+
+    def work(k, out, stride=None):
+        stride = nstreams if stride is None else stride
+        with torch.cuda.stream(streams[k]):
+            for idx in range(k, len(runs), stride):
+                t_a = time.perf_counter()
+                _, info = runs[idx]["solver"].solve(bs[k], tol=args.tol, restart=30, maxit=400, out=xs[idx])
+                streams[k].synchronize()
+                info["solve_ms"] = (time.perf_counter() - t_a) * 1e3
+                out[idx] = info
+            streams[k].synchronize()
+
     def step(record):
-        for r in runs:
-            _, info = r["solver"].solve(b, tol=args.tol, restart=30, maxit=400, out=x)
-            if record is not None:
-                record.append(info)
+        out = [None] * len(runs)
+        if nstreams == 1:
+            work(0, out)
+        else:
+            import threading
+            th = [threading.Thread(target=work, args=(k, out)) for k in range(nstreams)]
+            for t in th:
+                t.start()
+            for t in th:
+                t.join()
+        if record is not None:
+            record.extend(out)
 
     if args.copy_calib_mb > 0:
         src = torch.ones(args.copy_calib_mb * 2**20 // 8, dtype=torch.float64, device="cuda")
@@ -150,8 +269,6 @@ def main():
         del src, dst
     for _ in range(args.warmup):
         step(None)
-    for r in runs:
-        r["solver"].timing_start(0)
     infos = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -159,6 +276,21 @@ def main():
         step(infos)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    solves_per_step = len(runs)
+    value = solves_per_step * nf / (ms_per_step * 1e-3) / 1e6
+    # one more step, solves one after the other on one stream (outside the timed region): the
+    # per-smoother rates and per-solve times without concurrency, and the finest-level kernel
+    # durations (HIP events around every launch, on the stream the kernels run on) without other
+    # streams sharing the device
+    seq = [None] * len(runs)
+    for r in runs:
+        r["solver"].timing_start(0)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    work(0, seq, stride=1)
+    torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - t2) * 1e3
     vk_ms, vk_n, rs_ms, rs_n = 0.0, 0, 0.0, 0
     for r in runs:
         t = r["solver"].timing_stop(0)
@@ -166,34 +298,48 @@ def main():
         vk_n += t["vanka_launches"]
         rs_ms += t["resid_ms"]
         rs_n += t["resid_launches"]
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    solves_per_step = len(runs)
-    value = solves_per_step * nf / (ms_per_step * 1e-3) / 1e6
     per_case = []
     for k, r in enumerate(runs):
         info = infos[k]
         per_case.append({"smoother": r["smoother"], "nu": r["case"]["nu"], "K": r["case"]["K"],
                          "omega": r["omega"], "omega_J": r["omega_J"], "iters": info["iters"],
-                         "rel_res_true": info["rel_res_true"], "converged": info["converged"]})
+                         "rel_res_true": info["rel_res_true"], "converged": info["converged"],
+                         "solve_ms_sequential": round(seq[k]["solve_ms"], 3)})
+    per_smoother = {}
+    for sm in smoothers:
+        ms_sm = [seq[k]["solve_ms"] for k, r in enumerate(runs) if r["smoother"] == sm]
+        its = [seq[k]["iters"] for k, r in enumerate(runs) if r["smoother"] == sm]
+        per_smoother[sm] = {"MDOF/s": round(len(ms_sm) * nf / (sum(ms_sm) * 1e-3) / 1e6, 3),
+                            "solves": len(ms_sm), "iters": sum(its),
+                            "ms_per_iteration": round(sum(ms_sm) / max(1, sum(its)), 4)}
+    sequential = {"value": round(len(runs) * nf / (seq_ms * 1e-3) / 1e6, 3), "ms_per_step": round(seq_ms, 3),
+                  "per_smoother": per_smoother}
     all_conv = all(i["converged"] for i in infos)
     word = 8 if args.precision == "fp64" else 4
-    bytes_per_launch = 3 * word * nf + 2 * word * n * n
+    # fused step with constant K: read x_in and b, write x_out
+    bytes_per_launch = 3 * word * nf
     roofline = None
     if vk_n > 0:
         avg_s = vk_ms / vk_n * 1e-3
         achieved = bytes_per_launch / avg_s / 1e9
         traffic = measured_traffic() if (args.workload == "sweep256" and args.precision == "fp64") else None
-        roofline = {"kernel": "k_vanka_uniform (additive Vanka, finest level)", "bound": "hbm",
+        roofline = {"kernel": "k_vanka_step (fused residual + additive Vanka, finest level)", "bound": "hbm",
                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "avg_launch_us": round(avg_s * 1e6, 2), "launches": vk_n,
+                    "timed_in": "the sequential step (one stream)",
                     "algorithmic_bytes_per_launch": bytes_per_launch}
     resid = None
     if rs_n > 0:
         avg_r = rs_ms / rs_n * 1e-3
-        rb = 3 * word * nf + 2 * word * n * n
-        resid = {"kernel": "k_apply residual (finest level)", "avg_launch_us": round(avg_r * 1e6, 2),
-                 "achieved_GBs": round(rb / avg_r / 1e9, 1), "launches": rs_n}
+        rb = 2 * word * nf + word * inputs.n_free(n // 2)      # read x, b; write the coarse right-hand side
+        resid = {"kernel": "k_residual_restrict (finest level)", "avg_launch_us": round(avg_r * 1e6, 2),
+                 "achieved_GBs": round(rb / avg_r / 1e9, 1), "launches": rs_n,
+                 "algorithmic_bytes_per_launch": rb}
+    extras = None
+    if not args.no_extras and args.workload == "sweep256":
+        extras = {"precision_form": precision_extra(binding, inputs, torch),
+                  "adjoint": adjoint_extra(binding, inputs, torch)}
     cpu = None
     if not args.no_cpu_baseline:
         r0 = runs[0]
@@ -206,8 +352,10 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32-smoother/f64-krylov",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "levels": levels, "free_dofs": nf,
-                   "solves_per_step": solves_per_step, "smoothers": smoothers,
+                   "solves_per_step": solves_per_step, "smoothers": smoothers, "streams": nstreams,
+                   "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
                    "precision": args.precision, "tol": args.tol, "all_converged": all_conv},
+        "sequential": sequential, "extras": extras,
         "roofline": roofline, "residual_kernel": resid, "cpu_baseline": cpu, "cases": per_case,
     }
     print(json.dumps(out), flush=True)

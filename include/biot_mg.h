@@ -35,8 +35,11 @@
  * of a call is enqueued on `stream` (a hipStream_t, NULL = default stream); calls return
  * after enqueueing unless stated otherwise (solve synchronizes with the stream once per
  * FGMRES iteration to read the Hessenberg column).  A context is not thread safe; several
- * contexts may coexist.  All device memory a context needs is allocated by
- * biot_assemble / biot_setup_hierarchy; later calls allocate nothing.
+ * contexts may coexist; contexts on different streams may run concurrently from different
+ * host threads.  Device memory is allocated by biot_assemble and biot_setup_hierarchy, and
+ * by the first biot_solve with a given restart length m (the Krylov workspace: 2 m + 4
+ * finest-level FP64 vectors and a few scalars, kept for later solves with restart <= m);
+ * no other call allocates.
  *
  * Errors.  Every int-returning function returns one of the BIOT_* codes below and, on
  * failure, leaves a message for biot_last_error().  No C++ exception crosses the ABI.
@@ -60,7 +63,9 @@ extern "C" {
 #define BIOT_SMOOTHER_BSR 1       /* inexact Braess-Sarazin (Sec. 3.2.2, Appendix D)     */
 
 #define BIOT_PREC_FP64 0          /* whole preconditioner in FP64                         */
-#define BIOT_PREC_FP32_SMOOTHER 1 /* V-cycle vectors and patch solves in FP32, FP64 outer */
+#define BIOT_PREC_FP32_SMOOTHER 1 /* V-cycle vectors, residuals and transfers in FP32;
+                                     patch solves and the coarsest solve in FP64 arithmetic;
+                                     FGMRES and its true residual in FP64                  */
 
 typedef struct biot_ctx biot_ctx;
 
@@ -153,9 +158,11 @@ int biot_grad_logK(biot_ctx* ctx, const double* x, const double* lam, double* g_
 int biot_export_layout(biot_ctx* ctx, int* counts, int* patch_table, void* stream);
 
 /* Kernel timing with HIP events (instrumentation, not part of the method).
- * enable = 1: start recording an event pair around every launch of the additive-Vanka
- *             kernel (on an iterate that is not identically zero) and of the residual
- *             kernel on mesh level `level`; previous records are dropped.
+ * enable = 1: start recording an event pair around every launch, on mesh level `level`,
+ *             of the fused residual + additive-Vanka step (steps on an iterate that is not
+ *             identically zero and that do not also add the prolongated coarse correction)
+ *             and of the fused residual + restriction kernel; previous records are
+ *             dropped.  Events are recorded on `stream` of the calls that launch them.
  * enable = 0: stop, synchronize `stream` and write out[0..3] = {total Vanka milliseconds,
  *             number of Vanka launches, total residual milliseconds, number of residual
  *             launches} (out: host pointer, may be NULL). */

@@ -330,10 +330,11 @@ struct VecSet<float> {
     static float* s(Level& l) { return l.bs32.as<float>(); }
 };
 
-// Event pair around one launch when kernel timing is on for this level (kind 0 Vanka,
-// 1 residual).  Returns the stop event to record after the launch, or nullptr.
-static hipEvent_t prof_begin(biot_ctx* c, int kind, int level, hipStream_t st) {
-    if (!c->prof_on || level != c->prof_level) return nullptr;
+// Event pair for one launch when kernel timing is on for this level (kind 0 Vanka, 1 residual):
+// the launch records the kernel's own start and end in it.  Null events otherwise.
+static LaunchTiming prof_events(biot_ctx* c, int kind, int level) {
+    LaunchTiming t;
+    if (!c->prof_on || level != c->prof_level) return t;
     auto& pool = c->prof_ev[kind];
     size_t& used = c->prof_used[kind];
     while (pool.size() < used + 2) {
@@ -341,13 +342,10 @@ static hipEvent_t prof_begin(biot_ctx* c, int kind, int level, hipStream_t st) {
         BIOT_HIP(hipEventCreate(&e));
         pool.push_back(e);
     }
-    BIOT_HIP(hipEventRecord(pool[used], st));
-    hipEvent_t stop = pool[used + 1];
+    t.start = pool[used];
+    t.stop = pool[used + 1];
     used += 2;
-    return stop;
-}
-static void prof_end(hipEvent_t stop, hipStream_t st) {
-    if (stop) BIOT_HIP(hipEventRecord(stop, st));
+    return t;
 }
 
 // The two iterate buffers of a level (the fused Vanka step reads one and writes the other).
@@ -370,9 +368,9 @@ static T* relax(biot_ctx* c, int l, const T* x, const T* b, T* dst, hipStream_t 
     LevelView<T> v = lv.view<T>();
     const T om = (T)c->opts.omega;
     if (c->opts.smoother == BIOT_SMOOTHER_VANKA) {
-        hipEvent_t e0 = x ? prof_begin(c, 0, l, st) : nullptr;
-        launch_vanka_step<T>(v, x, b, dst, c->K_uniform, (T)(1.0 / c->K_scalar), om, st);
-        prof_end(e0, st);
+        const LaunchTiming tm = x ? prof_events(c, 0, l) : LaunchTiming{};
+        launch_vanka_step<T>(v, x, b, dst, c->K_uniform, (T)(1.0 / c->K_scalar), om, st, nullptr, nullptr, nullptr,
+                             &tm);
         return dst;
     }
     launch_bsr_step<T>(v, dst, b, VecSet<T>::r(lv), VecSet<T>::s(lv), x == nullptr, c->K_uniform,
@@ -417,10 +415,9 @@ static T* vcycle_level(biot_ctx* c, int l, const T* b, T* buf0, T* buf1, hipStre
     }
     Level& lc = *c->levels[l + 1];
     T* bc = VecSet<T>::b(lc);
-    hipEvent_t e1 = prof_begin(c, 1, l, st);
+    const LaunchTiming tm = prof_events(c, 1, l);
     launch_residual_restrict<T>(lv.view<T>(), lc.L, cur, b, bc, c->K_uniform, (T)(1.0 / c->K_scalar),
-                                PW<T>::get(c), st);
-    prof_end(e1, st);
+                                PW<T>::get(c), st, &tm);
     T* xc = vcycle_level<T>(c, l + 1, bc, XBuf<T>::get(lc, 0), XBuf<T>::get(lc, 1), st);
     int s0 = 0;
     if (c->opts.nu2 > 0) {
@@ -563,7 +560,12 @@ static int fgmres(biot_ctx* c, const double* b_canon, double* x_canon, biot_solv
             double* vj = V + (size_t)j * n;
             double* zj = Z + (size_t)j * n;
             precond(c, vj, zj, st);
-            launch_apply<double>(l0.view<double>(), zj, nullptr, w, 0, st);
+            // Arnoldi on the shifted vector w = v_j - A z_j (A z_j = v_j - w): with a good
+            // preconditioner A z_j is close to v_j, so A z_j itself lies almost entirely in the
+            // Krylov basis and orthogonalizing it cancels nearly everything, while the shifted
+            // vector keeps the part that is new.  Its coefficients are h'_i = delta_ij - h_i and
+            // the orthogonalized remainder is -h_{j+1,j} v_{j+1}.
+            launch_apply<double>(l0.view<double>(), zj, vj, w, 1, st);
             // CGS with a second pass when the first one cancels (|w| drops below |w_0| / sqrt 2)
             launch_gs_dots(V, n, j + 1, w, n, part, hd, hh, nullptr, st);
             launch_gs_update(w, V, n, j + 1, hd, n, part, hd + kslot_n1(M), hd + j + 1, hd + kslot_flag(M),
@@ -576,9 +578,11 @@ static int fgmres(biot_ctx* c, const double* b_canon, double* x_canon, biot_solv
             check_stream_error();
             BIOT_HIP(hipStreamSynchronize(st));
             const bool second = hhost[kslot_flag(M)] != 0.0;
-            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hhost[i] + (second ? hhost[M + 2 + i] : 0.0);
+            for (int i = 0; i <= j; ++i)
+                H[(size_t)i * m + j] = (i == j ? 1.0 : 0.0) - (hhost[i] + (second ? hhost[M + 2 + i] : 0.0));
             const double hn = std::sqrt(second ? hhost[kslot_n2(M)] : hhost[kslot_n1(M)]);
-            H[(size_t)(j + 1) * m + j] = hn;
+            // v_{j+1} = w / |w| is minus the direction of the unshifted remainder
+            H[(size_t)(j + 1) * m + j] = -hn;
             for (int i = 0; i <= j + 1; ++i)
                 if (!(H[(size_t)i * m + j] == H[(size_t)i * m + j])) throw std::domain_error("NaN in Arnoldi");
             for (int i = 0; i < j; ++i) {
@@ -601,7 +605,7 @@ static int fgmres(biot_ctx* c, const double* b_canon, double* x_canon, biot_solv
                 break;
             }
         }
-    (void)stop;
+        (void)stop;
         // y = H^{-1} g (upper triangular k x k), x += Z y
         for (int i = k - 1; i >= 0; --i) {
             double s = g[i];

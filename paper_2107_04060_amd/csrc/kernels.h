@@ -40,6 +40,12 @@ void launch_convert(const float* src, double* dst, long long n, hipStream_t st);
 template <typename T>
 void launch_apply(const LevelView<T>& lv, const T* x, const T* b, T* y, int mode, hipStream_t st);
 
+// Optional event pair recording the start and the end of one launch (the kernel's own
+// timestamps, through hipExtLaunchKernel); instrumentation only.
+struct LaunchTiming {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
 // fused residual + additive Vanka step (Sec. 3.2.1):
 //   x_out = x_in + omega * sum_l V_l^T D_l A_l^{-1} V_l (b - A x_in)
 // x_in == nullptr means x_in = 0.  x_out must not alias x_in.  uniform: one patch inverse per
@@ -49,7 +55,7 @@ void launch_apply(const LevelView<T>& lv, const T* x, const T* b, T* y, int mode
 template <typename T>
 void launch_vanka_step(const LevelView<T>& lv, const T* x_in, const T* b, T* x_out, bool uniform, T kinv_s,
                        T omega, hipStream_t st, const T* xc = nullptr, const Layout* Lc = nullptr,
-                       const T* pw = nullptr);
+                       const T* pw = nullptr, const LaunchTiming* tm = nullptr);
 
 // grid transfers
 // (w: the NPWEIGHTS prolongation weights of structure.h, device)
@@ -60,7 +66,7 @@ void launch_prolong_add(const Layout& Lf, const Layout& Lc, const T* xc, T* xf, 
 // r_c = P^T (b - A_f x) in one launch (the fine residual is not stored); uniform: 1/K = kinv_s
 template <typename T>
 void launch_residual_restrict(const LevelView<T>& lf, const Layout& Lc, const T* x, const T* b, T* rc,
-                              bool uniform, T kinv_s, const T* w, hipStream_t st);
+                              bool uniform, T kinv_s, const T* w, hipStream_t st, const LaunchTiming* tm = nullptr);
 
 // inexact Braess-Sarazin: diagonal data of a level (1 / (tau D_w), 1 / diag(S)); cS =
 // (1/M + alpha^2 / (lambda + mu)) |T|

@@ -10,6 +10,7 @@
 #include <type_traits>
 #include <utility>
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 namespace biot {
@@ -214,6 +215,34 @@ struct Window {
     }
 };
 
+// Tile of this block.  The dispatcher deals consecutive block ids to the 8 XCDs in turn; the
+// tiles are renumbered so that the blocks one XCD receives cover a contiguous band of tiles,
+// whose shared halo cache lines then meet in that XCD's L2.
+constexpr int NXCD = 8;
+__device__ __forceinline__ void xcd_tile(int& bx, int& by) {
+    const int nb = gridDim.x * gridDim.y;
+    const int b = blockIdx.y * gridDim.x + blockIdx.x;
+    const int xcd = b % NXCD, k = b / NXCD;
+    const int base = nb / NXCD, rem = nb % NXCD;
+    const int t = xcd * base + min(xcd, rem) + k;
+    by = t / gridDim.x;
+    bx = t - by * gridDim.x;
+}
+
+// A table of N <= TPB per-level constants (stencil coefficients, transfer weights) staged in
+// LDS together with the tile's windows: one vector load per thread, issued with the others.
+// Read from LDS (a broadcast), the constants cost no memory round trip inside the compute
+// phase, where scalar loads would wait on the scalar cache one batch at a time.
+template <typename T, int N>
+struct Table {
+    static_assert(N <= TPB, "one element per thread");
+    T v;
+    __device__ __forceinline__ void load(const T* __restrict__ src, int tid) { v = tid < N ? src[tid] : (T)0; }
+    __device__ __forceinline__ void store(T* dst, int tid) const {
+        if (tid < N) dst[tid] = v;
+    }
+};
+
 __device__ inline double vanka_weight(int t, int i, int j, int n) {
     if (t <= T_UY) return 1.0;
     if (t <= T_WD) return 0.5;
@@ -278,6 +307,8 @@ struct VankaLds {
     T ks[UNIFORM ? 1 : 2][UNIFORM ? 1 : KW][UNIFORM ? 1 : KW];   // 1/K of the L, U triangles
     double ms[UNIFORM ? NCLS : 1][UNIFORM ? PATCH * PATCH : 1];  // class inverses of the tile (FP64)
     T xcs[PROL ? NTYPES : 1][PROL ? PCW : 1][PROL ? PCW : 1];   // coarse iterate (prolongation)
+    T cf[NSTENCIL];                                              // stencil coefficients
+    T pwl[PROL ? NPWEIGHTS : 1];                                 // prolongation weights
 };
 
 // PROL: the iterate is x_in + P x_c (prolongation of the coarse-grid correction, Sec. 3),
@@ -296,7 +327,9 @@ __global__ __launch_bounds__(TPB) void k_vanka_step(const T* __restrict__ x_in, 
     auto& xs = sh.u.a.xs;
     auto& rs = sh.u.a.rs;
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TB + tx;
-    const int i0 = blockIdx.x * VO, j0 = blockIdx.y * VO;
+    int bx, by;
+    xcd_tile(bx, by);
+    const int i0 = bx * VO, j0 = by * VO;
     const int n = L.n;
     // vertex classes of the tile (0 low edge, 1 interior, 2 high edge per direction); their
     // matrices sit in ms[(cj - cjlo) * cw + (ci - cilo)]
@@ -305,22 +338,21 @@ __global__ __launch_bounds__(TPB) void k_vanka_step(const T* __restrict__ x_in, 
     const int cw = cihi - cilo + 1;
     // ---- staging: b (and x_in, 1/K), class inverses ---------------------------------------------
     {
+        // every load of the staging phase is issued before the first LDS store, so the tile
+        // waits for one memory latency, not one per class
+        constexpr int NM = PATCH * PATCH;
+        constexpr int NIT = (NM + TPB - 1) / TPB;
+        constexpr int NCL = UNIFORM ? NCLS : 1;
+        const int nc = cw * (cjhi - cjlo + 1);
+        double mv[NCL][NIT];
         if constexpr (UNIFORM) {
-            constexpr int NM = PATCH * PATCH;
-            constexpr int NIT = (NM + TPB - 1) / TPB;
-            const int nc = cw * (cjhi - cjlo + 1);
-            for (int k = 0; k < nc; ++k) {
+#pragma unroll
+            for (int k = 0; k < NCL; ++k) {
                 const int cidx = 3 * (cjlo + k / cw) + cilo + k % cw;
-                double mv[NIT];
 #pragma unroll
                 for (int it = 0; it < NIT; ++it) {
                     const int q = tid + it * TPB;
-                    mv[it] = q < NM ? minv[cidx * NM + q] : 0.0;
-                }
-#pragma unroll
-                for (int it = 0; it < NIT; ++it) {
-                    const int q = tid + it * TPB;
-                    if (q < NM) sh.ms[k][q] = mv[it];
+                    mv[k][it] = (k < nc && q < NM) ? minv[cidx * NM + q] : 0.0;
                 }
             }
         }
@@ -333,6 +365,21 @@ __global__ __launch_bounds__(TPB) void k_vanka_step(const T* __restrict__ x_in, 
         // coarse slots i0/2 - 1 .. i0/2 + PCW - 2 feed the fine window i0 - 2 .. i0 + VT + 1
         Window<T, NTYPES, PCW> wc;
         if constexpr (PROL) wc.load(xc, Lc.plane, Lc, i0 / 2 - 1, j0 / 2 - 1, tid);
+        Table<T, NSTENCIL> tcf;
+        if constexpr (!ZERO) tcf.load(coef, tid);
+        Table<T, NPWEIGHTS> tpw;
+        if constexpr (PROL) tpw.load(pw, tid);
+        if constexpr (!ZERO) tcf.store(sh.cf, tid);
+        if constexpr (PROL) tpw.store(sh.pwl, tid);
+        if constexpr (UNIFORM) {
+#pragma unroll
+            for (int k = 0; k < NCL; ++k)
+#pragma unroll
+                for (int it = 0; it < NIT; ++it) {
+                    const int q = tid + it * TPB;
+                    if (k < nc && q < NM) sh.ms[k][q] = mv[k][it];
+                }
+        }
         wb.store(&rs[0][0][0], tid);
         if constexpr (!ZERO) wx.store(&xs[0][0][0], tid);
         if constexpr (!UNIFORM) wk.store(&sh.ks[0][0][0], tid);
@@ -353,7 +400,7 @@ __global__ __launch_bounds__(TPB) void k_vanka_step(const T* __restrict__ x_in, 
                     static_for(std::make_integer_sequence<int, NTYPES>{}, [&](auto tcn) {
                         constexpr int tf = decltype(tcn)::value;
                         if (dof_free(tf, 2 * I + pi, 2 * J + pj, n))
-                            xs[tf][bb][a] += prolong_value<T, tf, pi, pj>(sh.xcs, ci, cj, pw);
+                            xs[tf][bb][a] += prolong_value<T, tf, pi, pj>(sh.xcs, ci, cj, sh.pwl);
                     });
                 }
             });
@@ -371,7 +418,7 @@ __global__ __launch_bounds__(TPB) void k_vanka_step(const T* __restrict__ x_in, 
             static_for(std::make_integer_sequence<int, SST.n[t]>{}, [&](auto ec) {
                 constexpr int e = decltype(ec)::value;
                 constexpr SEnt en = SST.e[t][e];
-                T cc = coef[SST.off[t] + e];
+                T cc = sh.cf[SST.off[t] + e];
                 if constexpr (en.kt >= 0) {
                     if constexpr (UNIFORM)
                         cc *= kinv_s;
@@ -394,49 +441,103 @@ __global__ __launch_bounds__(TPB) void k_vanka_step(const T* __restrict__ x_in, 
     for (int t = 0; t < NTYPES; ++t) xown[t] = (ZERO || !patch) ? (T)0 : xs[t][ty + 2][tx + 2];
     // The patch arithmetic is FP64 for either storage precision T.
     if constexpr (UNIFORM) {
-        // wave w applies the class inverses to the patches of tile rows 4 w .. 4 w + 3
+        // The products run over batches of up to 16 patches that share one class inverse: each
+        // tile row (its patches at interior-class columns), each boundary column of the tile
+        // (its patches at interior-class rows) and each corner patch.  Wave w takes rows
+        // w, w + 4, w + 8, w + 12 and the boundary batches dealt to it (the i-th present one goes
+        // to wave 3 - i % 4), so a boundary tile costs one product per batch, not one per class
+        // present in a row.
         const int lane = tid & 63, wave = tid >> 6;
         const int jl = lane & 15, kq = lane >> 4;
-        const int pvi = i0 + jl;
-        const int ci_l = pvi == 0 ? 0 : (pvi == n ? 2 : 1);
-        const int bcol = jl < VT ? jl : VT - 1;       // column 15 holds no patch: any finite data
-        // residuals of the patches (B operand) of the wave's rows, read before the corrections
-        // overwrite the residual array
-        double bf[4][5];
+        auto vcls = [n](int v) { return v == 0 ? 0 : (v == n ? 2 : 1); };
+        const int bcl = i0 == 0 ? 0 : -1, bcr = n - i0 < VT ? n - i0 : -1;   // tile columns of i = 0, n
+        const int brb = j0 == 0 ? 0 : -1, brt = n - j0 < VT ? n - j0 : -1;   // tile rows of j = 0, n
+        // boundary batches e in a fixed order: left, right column; corners (l,b), (r,b), (l,t),
+        // (r,t): tile column eti(e) and, for corners, tile row etj(e); -1 where the tile does
+        // not reach that boundary
+        auto eti = [&](int e) { return (e & 1) ? bcr : bcl; };
+        auto etj = [&](int e) { return e < 2 ? 0 : (e < 4 ? brb : brt); };
+        auto epr = [&](int e) { return eti(e) >= 0 && etj(e) >= 0; };
+        // batch slots of this wave: 0..3 rows, 4..5 boundary batches (e index, or -1)
+        int ex0 = -1, ex1 = -1;
+        {
+            int cnt = 0;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int pty = min(4 * wave + r, VT - 1);
-            const T* base = &rs[0][0][0] + (pty + 1) * RW + (bcol + 1);
+            for (int e = 0; e < 6; ++e)
+                if (epr(e)) {
+                    if (cnt == 3 - wave) ex0 = e;
+                    if (cnt == 7 - wave) ex1 = e;
+                    ++cnt;
+                }
+        }
+        // batch s: active, class (cj, ci), the lane's patch (pti, ptj) and whether it belongs to it
+        auto batch = [&](int s, bool& act, int& cj, int& ci, int& pti, int& ptj, bool& own) {
+            if (s < 4) {
+                ptj = wave + 4 * s;
+                pti = jl;
+                act = ptj < VT && j0 + ptj <= n;
+                cj = act ? vcls(j0 + ptj) : 1;
+                ci = 1;
+                own = act && pti < VT && i0 + pti <= n && vcls(i0 + pti) == 1;
+            } else {
+                const int e = s == 4 ? ex0 : ex1;
+                act = e >= 0;
+                if (e >= 0 && e < 2) {             // boundary column
+                    pti = eti(e);
+                    ptj = jl;
+                    ci = vcls(i0 + pti);
+                    cj = 1;
+                    own = ptj < VT && j0 + ptj <= n && vcls(j0 + ptj) == 1;
+                } else if (e >= 2) {               // corner patch, column 0 of the product
+                    pti = eti(e);
+                    ptj = etj(e);
+                    ci = vcls(i0 + pti);
+                    cj = vcls(j0 + ptj);
+                    own = jl == 0;
+                } else {
+                    pti = ptj = 0;
+                    ci = cj = 1;
+                    own = false;
+                }
+            }
+        };
+        // residuals of the batches' patches (B operand), read before the corrections overwrite
+        // the residual array; lanes outside a batch read any patch of the tile
+        double bf[6][5];
+#pragma unroll
+        for (int sb = 0; sb < 6; ++sb) {
+            bool act, own;
+            int cj, ci, pti, ptj;
+            batch(sb, act, cj, ci, pti, ptj, own);
+            const T* base = &rs[0][0][0] + (min(ptj, VT - 1) + 1) * RW + (min(pti, VT - 1) + 1);
 #pragma unroll
             for (int ks = 0; ks < 5; ++ks) {
                 const int o = kq == 0 ? pslot_off(4 * ks) : kq == 1 ? pslot_off(4 * ks + 1)
                             : kq == 2 ? pslot_off(4 * ks + 2) : pslot_off(4 * ks + 3);
-                bf[r][ks] = (double)base[o];
+                bf[sb][ks] = act ? (double)base[o] : 0.0;
             }
         }
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int pty = 4 * wave + r;
-            const int pvj = j0 + pty;
-            if (pty >= VT || pvj > n) continue;      // uniform over the wave
-            const int cj = pvj == 0 ? 0 : (pvj == n ? 2 : 1);
-            for (int ci = cilo; ci <= cihi; ++ci) {
-                double cf[2][5];
-                mfma_class_frag(sh.ms[(cj - cjlo) * cw + (ci - cilo)], lane, cf);
-                v4d acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+        for (int sb = 0; sb < 6; ++sb) {
+            bool act, own;
+            int cj, ci, pti, ptj;
+            batch(sb, act, cj, ci, pti, ptj, own);
+            if (!act) continue;                    // uniform over the wave
+            double cf[2][5];
+            mfma_class_frag(sh.ms[(cj - cjlo) * cw + (ci - cilo)], lane, cf);
+            v4d acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
 #pragma unroll
-                for (int ks = 0; ks < 5; ++ks) {
-                    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(cf[0][ks], bf[r][ks], acc0, 0, 0, 0);
-                    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(cf[1][ks], bf[r][ks], acc1, 0, 0, 0);
-                }
-                // rows a = kq + 4 v + 16 mb of patch (jl, pty)
-                if (ci_l == ci && jl < VT) {
+            for (int ks = 0; ks < 5; ++ks) {
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(cf[0][ks], bf[sb][ks], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(cf[1][ks], bf[sb][ks], acc1, 0, 0, 0);
+            }
+            // rows a = kq + 4 v + 16 mb of the lane's patch
+            if (own) {
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        sh.u.so[kq + 4 * v][pty][jl] = (T)acc0[v];
-                        if (kq + 4 * v + 16 < PATCH) sh.u.so[kq + 4 * v + 16][pty][jl] = (T)acc1[v];
-                    }
+                for (int v = 0; v < 4; ++v) {
+                    sh.u.so[kq + 4 * v][ptj][pti] = (T)acc0[v];
+                    if (kq + 4 * v + 16 < PATCH) sh.u.so[kq + 4 * v + 16][ptj][pti] = (T)acc1[v];
                 }
             }
         }
@@ -504,43 +605,46 @@ __global__ __launch_bounds__(TPB) void k_vanka_step(const T* __restrict__ x_in, 
 
 template <typename T, bool UNIFORM, bool ZERO, bool PROL>
 static void launch_vanka_step_t(const LevelView<T>& lv, const T* x_in, const T* b, T* x_out, T kinv_s, T omega,
-                                const T* xc, const Layout& Lc, const T* pw, hipStream_t st) {
+                                const T* xc, const Layout& Lc, const T* pw, const LaunchTiming* tm, hipStream_t st) {
     dim3 blk(TB, TB);
     dim3 grd((lv.L.n + 1 + VO - 1) / VO, (lv.L.n + 1 + VO - 1) / VO);
+    hipEvent_t e0 = tm ? tm->start : nullptr, e1 = tm ? tm->stop : nullptr;
     // a tile spans at most two vertex classes per direction unless it covers the whole mesh
     if (UNIFORM && lv.L.n + 1 <= VT)
-        hipLaunchKernelGGL((k_vanka_step<T, UNIFORM, ZERO, 9, PROL>), grd, blk, 0, st, x_in, b, x_out, lv.L,
-                           lv.kinv, kinv_s, lv.coef, lv.cls, lv.wblk, lv.minv, omega, xc, Lc, pw);
+        hipExtLaunchKernelGGL((k_vanka_step<T, UNIFORM, ZERO, 9, PROL>), grd, blk, 0, st, e0, e1, 0, x_in, b, x_out,
+                              lv.L, lv.kinv, kinv_s, lv.coef, lv.cls, lv.wblk, lv.minv, omega, xc, Lc, pw);
     else
-        hipLaunchKernelGGL((k_vanka_step<T, UNIFORM, ZERO, 4, PROL>), grd, blk, 0, st, x_in, b, x_out, lv.L,
-                           lv.kinv, kinv_s, lv.coef, lv.cls, lv.wblk, lv.minv, omega, xc, Lc, pw);
+        hipExtLaunchKernelGGL((k_vanka_step<T, UNIFORM, ZERO, 4, PROL>), grd, blk, 0, st, e0, e1, 0, x_in, b, x_out,
+                              lv.L, lv.kinv, kinv_s, lv.coef, lv.cls, lv.wblk, lv.minv, omega, xc, Lc, pw);
 }
 
 template <typename T>
 void launch_vanka_step(const LevelView<T>& lv, const T* x_in, const T* b, T* x_out, bool uniform, T kinv_s,
-                       T omega, hipStream_t st, const T* xc, const Layout* Lc, const T* pw) {
+                       T omega, hipStream_t st, const T* xc, const Layout* Lc, const T* pw, const LaunchTiming* tm) {
     const Layout lc = Lc ? *Lc : lv.L;
     if (xc && !x_in) throw ArgError{"the prolongation needs an iterate"};
     if (uniform) {
         if (xc)
-            launch_vanka_step_t<T, true, false, true>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, st);
+            launch_vanka_step_t<T, true, false, true>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st);
         else if (x_in)
-            launch_vanka_step_t<T, true, false, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, st);
+            launch_vanka_step_t<T, true, false, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st);
         else
-            launch_vanka_step_t<T, true, true, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, st);
+            launch_vanka_step_t<T, true, true, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st);
     } else {
         if (xc)
-            launch_vanka_step_t<T, false, false, true>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, st);
+            launch_vanka_step_t<T, false, false, true>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st);
         else if (x_in)
-            launch_vanka_step_t<T, false, false, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, st);
+            launch_vanka_step_t<T, false, false, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st);
         else
-            launch_vanka_step_t<T, false, true, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, st);
+            launch_vanka_step_t<T, false, true, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st);
     }
 }
 template void launch_vanka_step<double>(const LevelView<double>&, const double*, const double*, double*, bool,
-                                        double, double, hipStream_t, const double*, const Layout*, const double*);
+                                        double, double, hipStream_t, const double*, const Layout*, const double*,
+                                        const LaunchTiming*);
 template void launch_vanka_step<float>(const LevelView<float>&, const float*, const float*, float*, bool, float,
-                                       float, hipStream_t, const float*, const Layout*, const float*);
+                                       float, hipStream_t, const float*, const Layout*, const float*,
+                                       const LaunchTiming*);
 
 // =========================================================================================
 // inexact Braess-Sarazin relaxation (Sec. 3.2.2, Appendix D)
@@ -687,6 +791,8 @@ struct BsrFirstLds {
     T ui[9][64];
     T ks[UNIFORM ? 1 : 2][UNIFORM ? 1 : KW][UNIFORM ? 1 : KW];
     T xcs[PROL ? NTYPES : 1][PROL ? PCW : 1][PROL ? PCW : 1];
+    T cf[NSTENCIL];
+    T pwl[PROL ? NPWEIGHTS : 1];
 };
 
 // First half of a BSR step: r = b - A x (x: x_in, or x_in + P x_c with PROL, or 0 with ZERO),
@@ -703,7 +809,9 @@ __global__ __launch_bounds__(TPB) void k_bsr_first(const T* __restrict__ x_in, T
     static_assert(!(PROL && ZERO), "the prolongation needs an iterate");
     __shared__ BsrFirstLds<T, UNIFORM, PROL> sh;
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TB + tx;
-    const int i0 = blockIdx.x * VO, j0 = blockIdx.y * VO;
+    int bx, by;
+    xcd_tile(bx, by);
+    const int i0 = bx * VO, j0 = by * VO;
     const int n = L.n;
     {
         Window<T, NTYPES, RW> wb;
@@ -714,7 +822,13 @@ __global__ __launch_bounds__(TPB) void k_bsr_first(const T* __restrict__ x_in, T
         if constexpr (!UNIFORM && !ZERO) wk.load(kinv, L.plane, L, i0 - 2, j0 - 2, tid);
         Window<T, NTYPES, PCW> wc;
         if constexpr (PROL) wc.load(xc, Lc.plane, Lc, i0 / 2 - 1, j0 / 2 - 1, tid);
+        Table<T, NSTENCIL> tcf;
+        if constexpr (!ZERO) tcf.load(coef, tid);
+        Table<T, NPWEIGHTS> tpw;
+        if constexpr (PROL) tpw.load(pw, tid);
         load_uinv(uinv, sh.ui, tid);
+        if constexpr (!ZERO) tcf.store(sh.cf, tid);
+        if constexpr (PROL) tpw.store(sh.pwl, tid);
         wb.store(&sh.rs[0][0][0], tid);
         if constexpr (!ZERO) wx.store(&sh.xs[0][0][0], tid);
         if constexpr (!UNIFORM && !ZERO) wk.store(&sh.ks[0][0][0], tid);
@@ -733,7 +847,7 @@ __global__ __launch_bounds__(TPB) void k_bsr_first(const T* __restrict__ x_in, T
                     static_for(std::make_integer_sequence<int, NTYPES>{}, [&](auto tcn) {
                         constexpr int tf = decltype(tcn)::value;
                         if (dof_free(tf, 2 * I + pi, 2 * J + pj, n))
-                            sh.xs[tf][bb][a] += prolong_value<T, tf, pi, pj>(sh.xcs, ci, cj, pw);
+                            sh.xs[tf][bb][a] += prolong_value<T, tf, pi, pj>(sh.xcs, ci, cj, sh.pwl);
                     });
                 }
             });
@@ -750,7 +864,7 @@ __global__ __launch_bounds__(TPB) void k_bsr_first(const T* __restrict__ x_in, T
             static_for(std::make_integer_sequence<int, SST.n[tt]>{}, [&](auto ec) {
                 constexpr int e = decltype(ec)::value;
                 constexpr SEnt en = SST.e[tt][e];
-                T cc = coef[SST.off[tt] + e];
+                T cc = sh.cf[SST.off[tt] + e];
                 if constexpr (en.kt >= 0) {
                     if constexpr (UNIFORM)
                         cc *= kinv_s;
@@ -803,6 +917,7 @@ struct BsrSecondLds {
     T ru[NU][RW][RW];        // r_u, then r_u - A_up dp
     T so[8][VT][VT];
     T ui[9][64];
+    T cf[NSTENCIL];
 };
 
 template <typename T, bool ZERO>
@@ -812,7 +927,9 @@ __global__ __launch_bounds__(TPB) void k_bsr_second(const T* __restrict__ r, con
                                                     T omega, T omega_J) {
     __shared__ BsrSecondLds<T> sh;
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TB + tx;
-    const int i0 = blockIdx.x * VO, j0 = blockIdx.y * VO;
+    int bx, by;
+    xcd_tile(bx, by);
+    const int i0 = bx * VO, j0 = by * VO;
     const int n = L.n;
     {
         Window<T, 8, TW> wt;
@@ -823,7 +940,10 @@ __global__ __launch_bounds__(TPB) void k_bsr_second(const T* __restrict__ r, con
         wd.load(d + BSR_S * L.plane, L.plane, L, i0 - 2, j0 - 2, tid);
         Window<T, NU, RW> wr;
         wr.load(r, L.plane, L, i0 - 1, j0 - 1, tid);
+        Table<T, NSTENCIL> tcf;
+        tcf.load(coef, tid);
         load_uinv(uinv, sh.ui, tid);
+        tcf.store(sh.cf, tid);
         wt.store(&sh.ts[0][0][0], tid);
         wp.store(&sh.dp[0][0][0], tid);
         wd.store(&sh.ds[0][0][0], tid);
@@ -842,7 +962,7 @@ __global__ __launch_bounds__(TPB) void k_bsr_second(const T* __restrict__ r, con
                 constexpr SEnt en = SST.e[tp][e];
                 if constexpr (tfield(en.in) != 2) {
                     static_assert(en.kt < 0, "the pressure rows do not depend on K");
-                    acc += coef[SST.off[tp] + e] * sh.ts[en.in][bb + en.dj][a + en.di];
+                    acc += sh.cf[SST.off[tp] + e] * sh.ts[en.in][bb + en.dj][a + en.di];
                 }
             });
             const T v = omega_J * (acc - sh.dp[tp - T_PL][bb][a]) * sh.ds[tp - T_PL][bb][a];
@@ -861,7 +981,7 @@ __global__ __launch_bounds__(TPB) void k_bsr_second(const T* __restrict__ r, con
             static_for(std::make_integer_sequence<int, SST.n[tu]>{}, [&](auto ec) {
                 constexpr int e = decltype(ec)::value;
                 constexpr SEnt en = SST.e[tu][e];
-                if constexpr (tfield(en.in) == 2) acc += coef[SST.off[tu] + e] * sh.dp[en.in - T_PL][ty + 1 + en.dj][tx + 1 + en.di];
+                if constexpr (tfield(en.in) == 2) acc += sh.cf[SST.off[tu] + e] * sh.dp[en.in - T_PL][ty + 1 + en.dj][tx + 1 + en.di];
             });
             rv[tu] = dof_free(tu, si, sj, n) ? sh.ru[tu][ty][tx] - acc : (T)0;
         });
@@ -887,7 +1007,7 @@ __global__ __launch_bounds__(TPB) void k_bsr_second(const T* __restrict__ r, con
                 static_for(std::make_integer_sequence<int, SST.n[tw]>{}, [&](auto ec) {
                     constexpr int e = decltype(ec)::value;
                     constexpr SEnt en = SST.e[tw][e];
-                    if constexpr (tfield(en.in) == 2) acc += coef[SST.off[tw] + e] * sh.dp[en.in - T_PL][ty + 2 + en.dj][tx + 2 + en.di];
+                    if constexpr (tfield(en.in) == 2) acc += sh.cf[SST.off[tw] + e] * sh.dp[en.in - T_PL][ty + 2 + en.dj][tx + 2 + en.di];
                 });
                 const T dwv = (r[tw * L.plane + s0] - acc) * d[(BSR_W + tw - T_WH) * L.plane + s0];
                 if (dof_free(tw, si, sj, n)) x[tw * L.plane + s0] = (ZERO ? (T)0 : x_src[tw * L.plane + s0]) + omega * dwv;
@@ -1004,6 +1124,7 @@ struct ResRestrictLds {
     T xs[NTYPES][RXW][RXW];
     T rs[NTYPES][RRW][RRW];
     T ks[UNIFORM ? 1 : 2][UNIFORM ? 1 : RXW][UNIFORM ? 1 : RXW];
+    T cf[NSTENCIL];
 };
 
 template <typename T, int tc, int e>
@@ -1027,7 +1148,9 @@ __global__ __launch_bounds__(TPB) void k_residual_restrict(const T* __restrict__
                                                            const T* __restrict__ coef, const T* __restrict__ w) {
     __shared__ ResRestrictLds<T, UNIFORM> sh;
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TB + tx;
-    const int I0 = blockIdx.x * RT, J0 = blockIdx.y * RT;
+    int bx, by;
+    xcd_tile(bx, by);
+    const int I0 = bx * RT, J0 = by * RT;
     const int f0i = 2 * I0 - 2, f0j = 2 * J0 - 2;   // fine origin of the residual window
     const int n = Lf.n;
     {
@@ -1049,6 +1172,8 @@ __global__ __launch_bounds__(TPB) void k_residual_restrict(const T* __restrict__
         const bool inb = si >= -2 && sj >= -2 && si <= n + 1 && sj <= n + 1;
 #pragma unroll
         for (int t = 0; t < NTYPES; ++t) bv[t] = inb ? b[t * Lf.plane + slot_index(Lf, si, sj)] : (T)0;
+        Table<T, NSTENCIL> tcf;
+        tcf.load(coef, tid);
         T kv[UNIFORM ? 1 : (2 * RXW * RXW + TPB - 1) / TPB];
         if constexpr (!UNIFORM) {
 #pragma unroll
@@ -1067,6 +1192,7 @@ __global__ __launch_bounds__(TPB) void k_residual_restrict(const T* __restrict__
         }
 #pragma unroll
         for (int t = 0; t < NTYPES; ++t) sh.rs[t][ty][tx] = bv[t];
+        tcf.store(sh.cf, tid);
         if constexpr (!UNIFORM) {
 #pragma unroll
             for (int it = 0; it < (2 * RXW * RXW + TPB - 1) / TPB; ++it) {
@@ -1086,7 +1212,7 @@ __global__ __launch_bounds__(TPB) void k_residual_restrict(const T* __restrict__
             static_for(std::make_integer_sequence<int, SST.n[t]>{}, [&](auto ec) {
                 constexpr int e = decltype(ec)::value;
                 constexpr SEnt en = SST.e[t][e];
-                T cc = coef[SST.off[t] + e];
+                T cc = sh.cf[SST.off[t] + e];
                 if constexpr (en.kt >= 0) {
                     if constexpr (UNIFORM)
                         cc *= kinv_s;
@@ -1121,20 +1247,22 @@ __global__ __launch_bounds__(TPB) void k_residual_restrict(const T* __restrict__
 
 template <typename T>
 void launch_residual_restrict(const LevelView<T>& lf, const Layout& Lc, const T* x, const T* b, T* rc,
-                              bool uniform, T kinv_s, const T* w, hipStream_t st) {
+                              bool uniform, T kinv_s, const T* w, hipStream_t st, const LaunchTiming* tm) {
     dim3 blk(TB, TB);
     dim3 grd((Lc.n + 1 + RT - 1) / RT, (Lc.n + 1 + RT - 1) / RT);
+    hipEvent_t e0 = tm ? tm->start : nullptr, e1 = tm ? tm->stop : nullptr;
     if (uniform)
-        hipLaunchKernelGGL((k_residual_restrict<T, true>), grd, blk, 0, st, x, b, rc, lf.L, Lc, lf.kinv, kinv_s,
-                           lf.coef, w);
+        hipExtLaunchKernelGGL((k_residual_restrict<T, true>), grd, blk, 0, st, e0, e1, 0, x, b, rc, lf.L, Lc, lf.kinv,
+                              kinv_s, lf.coef, w);
     else
-        hipLaunchKernelGGL((k_residual_restrict<T, false>), grd, blk, 0, st, x, b, rc, lf.L, Lc, lf.kinv, kinv_s,
-                           lf.coef, w);
+        hipExtLaunchKernelGGL((k_residual_restrict<T, false>), grd, blk, 0, st, e0, e1, 0, x, b, rc, lf.L, Lc, lf.kinv,
+                              kinv_s, lf.coef, w);
 }
 template void launch_residual_restrict<double>(const LevelView<double>&, const Layout&, const double*,
-                                               const double*, double*, bool, double, const double*, hipStream_t);
+                                               const double*, double*, bool, double, const double*, hipStream_t,
+                                               const LaunchTiming*);
 template void launch_residual_restrict<float>(const LevelView<float>&, const Layout&, const float*, const float*,
-                                              float*, bool, float, const float*, hipStream_t);
+                                              float*, bool, float, const float*, hipStream_t, const LaunchTiming*);
 
 // fine DoF (tf, parity): sum over the field's coarse local DoFs of its designated triangle;
 // xcl[t][dj][di] holds the coarse values of slots (I + di, J + dj), di, dj in {0, 1}
