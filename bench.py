@@ -228,18 +228,25 @@ def main():
             runs.append(dict(solver=s, smoother=sm, case=case, omega=om, omega_J=omj, nu12=nu12))
     torch.cuda.synchronize()
 
-    # the solves of a step are independent systems: with --streams K they are dealt round-robin to
-    # K host threads, each issuing its solves on a stream of its own (default priority)
+    # the solves of a step are independent systems: with --streams K, K host threads each issue
+    # solves on a stream of their own (default priority), taking the next solve from a shared
+    # queue, longest first by the previous step's solve times (a greedy longest-processing-time
+    # schedule; the first step takes them in workload order)
+    import threading
     nstreams = max(1, min(args.streams, len(runs)))
     streams = [torch.cuda.Stream() for _ in range(nstreams)] if nstreams > 1 else [torch.cuda.current_stream()]
     xs = [torch.empty_like(b) for _ in runs]
     bs = [b.clone() for _ in range(nstreams)]
     torch.cuda.synchronize()
+    order = list(range(len(runs)))
 
-    def work(k, out, stride=None):
-        stride = nstreams if stride is None else stride
+    def work(k, out, queue, lock):
         with torch.cuda.stream(streams[k]):
-            for idx in range(k, len(runs), stride):
+            while True:
+                with lock:
+                    if not queue:
+                        break
+                    idx = queue.pop(0)
                 t_a = time.perf_counter()
                 _, info = runs[idx]["solver"].solve(bs[k], tol=args.tol, restart=30, maxit=400, out=xs[idx])
                 streams[k].synchronize()
@@ -247,19 +254,22 @@ def main():
                 out[idx] = info
             streams[k].synchronize()
 
-    def step(record):
+    def step(record, sequential=False):
         out = [None] * len(runs)
-        if nstreams == 1:
-            work(0, out)
+        queue, lock = list(order), threading.Lock()
+        if nstreams == 1 or sequential:
+            work(0, out, list(range(len(runs))), lock)
         else:
-            import threading
-            th = [threading.Thread(target=work, args=(k, out)) for k in range(nstreams)]
+            th = [threading.Thread(target=work, args=(k, out, queue, lock)) for k in range(nstreams)]
             for t in th:
                 t.start()
             for t in th:
                 t.join()
+        if not sequential:
+            order[:] = sorted(range(len(runs)), key=lambda i: -out[i]["solve_ms"])
         if record is not None:
             record.extend(out)
+        return out
 
     if args.copy_calib_mb > 0:
         src = torch.ones(args.copy_calib_mb * 2**20 // 8, dtype=torch.float64, device="cuda")
@@ -283,12 +293,11 @@ def main():
     # per-smoother rates and per-solve times without concurrency, and the finest-level kernel
     # durations (HIP events around every launch, on the stream the kernels run on) without other
     # streams sharing the device
-    seq = [None] * len(runs)
     for r in runs:
         r["solver"].timing_start(0)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    work(0, seq, stride=1)
+    seq = step(None, sequential=True)
     torch.cuda.synchronize()
     seq_ms = (time.perf_counter() - t2) * 1e3
     vk_ms, vk_n, rs_ms, rs_n = 0.0, 0, 0.0, 0
@@ -353,7 +362,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "levels": levels, "free_dofs": nf,
                    "solves_per_step": solves_per_step, "smoothers": smoothers, "streams": nstreams,
-                   "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
+                   "schedule": "greedy longest-first over the streams",
                    "precision": args.precision, "tol": args.tol, "all_converged": all_conv},
         "sequential": sequential, "extras": extras,
         "roofline": roofline, "residual_kernel": resid, "cpu_baseline": cpu, "cases": per_case,
