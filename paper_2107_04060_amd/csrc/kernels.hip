@@ -313,22 +313,20 @@ struct VankaLds {
 
 // PROL: the iterate is x_in + P x_c (prolongation of the coarse-grid correction, Sec. 3),
 // formed on the staged window; x_out = x_in + P x_c + omega (...).
+// One tile (bx, by) of the step, by the 16 x 16 threads of a block with LDS sh.
 template <typename T, bool UNIFORM, bool ZERO, int NCLS, bool PROL>
-__global__ __launch_bounds__(TPB) void k_vanka_step(const T* __restrict__ x_in, const T* __restrict__ b,
-                                                    T* __restrict__ x_out, Layout L, const T* __restrict__ kinv,
-                                                    T kinv_s, const T* __restrict__ coef,
-                                                    const DevPatchClass<double>* __restrict__ cls,
-                                                    const double* __restrict__ wblk,
-                                                    const double* __restrict__ minv, T omega,
-                                                    const T* __restrict__ xc, Layout Lc,
-                                                    const T* __restrict__ pw) {
+__device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, const T* __restrict__ b,
+                                                T* __restrict__ x_out, const Layout& L, const T* __restrict__ kinv,
+                                                T kinv_s, const T* __restrict__ coef,
+                                                const DevPatchClass<double>* __restrict__ cls,
+                                                const double* __restrict__ wblk, const double* __restrict__ minv,
+                                                T omega, const T* __restrict__ xc, const Layout& Lc,
+                                                const T* __restrict__ pw, int bx, int by,
+                                                VankaLds<T, UNIFORM, NCLS, PROL>& sh) {
     static_assert(!(PROL && ZERO), "the prolongation needs an iterate");
-    __shared__ VankaLds<T, UNIFORM, NCLS, PROL> sh;
     auto& xs = sh.u.a.xs;
     auto& rs = sh.u.a.rs;
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TB + tx;
-    int bx, by;
-    xcd_tile(bx, by);
     const int i0 = bx * VO, j0 = by * VO;
     const int n = L.n;
     // vertex classes of the tile (0 low edge, 1 interior, 2 high edge per direction); their
@@ -603,6 +601,22 @@ __global__ __launch_bounds__(TPB) void k_vanka_step(const T* __restrict__ x_in, 
     }
 }
 
+template <typename T, bool UNIFORM, bool ZERO, int NCLS, bool PROL>
+__global__ __launch_bounds__(TPB) void k_vanka_step(const T* __restrict__ x_in, const T* __restrict__ b,
+                                                    T* __restrict__ x_out, Layout L, const T* __restrict__ kinv,
+                                                    T kinv_s, const T* __restrict__ coef,
+                                                    const DevPatchClass<double>* __restrict__ cls,
+                                                    const double* __restrict__ wblk,
+                                                    const double* __restrict__ minv, T omega,
+                                                    const T* __restrict__ xc, Layout Lc,
+                                                    const T* __restrict__ pw) {
+    __shared__ VankaLds<T, UNIFORM, NCLS, PROL> sh;
+    int bx, by;
+    xcd_tile(bx, by);
+    vanka_step_tile<T, UNIFORM, ZERO, NCLS, PROL>(x_in, b, x_out, L, kinv, kinv_s, coef, cls, wblk, minv, omega, xc,
+                                                  Lc, pw, bx, by, sh);
+}
+
 template <typename T, bool UNIFORM, bool ZERO, bool PROL>
 static void launch_vanka_step_t(const LevelView<T>& lv, const T* x_in, const T* b, T* x_out, T kinv_s, T omega,
                                 const T* xc, const Layout& Lc, const T* pw, const LaunchTiming* tm, hipStream_t st) {
@@ -799,18 +813,15 @@ struct BsrFirstLds {
 // t_u = F_u^{-1} r_u, t_w = r_w / (tau D_w).  Writes r and t on the owned slots, and with PROL
 // the prolongated iterate to x_pro (neighbouring tiles still read x_in on their halo).
 template <typename T, bool UNIFORM, bool ZERO, bool PROL>
-__global__ __launch_bounds__(TPB) void k_bsr_first(const T* __restrict__ x_in, T* __restrict__ x_pro,
-                                                   const T* __restrict__ b,
-                                                   T* __restrict__ r, T* __restrict__ t, Layout L,
-                                                   const T* __restrict__ kinv, T kinv_s,
-                                                   const T* __restrict__ coef, const T* __restrict__ uinv,
-                                                   const T* __restrict__ d, const T* __restrict__ xc, Layout Lc,
-                                                   const T* __restrict__ pw) {
+__device__ __forceinline__ void bsr_first_tile(const T* __restrict__ x_in, T* __restrict__ x_pro,
+                                               const T* __restrict__ b, T* __restrict__ r, T* __restrict__ t,
+                                               const Layout& L, const T* __restrict__ kinv, T kinv_s,
+                                               const T* __restrict__ coef, const T* __restrict__ uinv,
+                                               const T* __restrict__ d, const T* __restrict__ xc, const Layout& Lc,
+                                               const T* __restrict__ pw, int bx, int by,
+                                               BsrFirstLds<T, UNIFORM, PROL>& sh) {
     static_assert(!(PROL && ZERO), "the prolongation needs an iterate");
-    __shared__ BsrFirstLds<T, UNIFORM, PROL> sh;
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TB + tx;
-    int bx, by;
-    xcd_tile(bx, by);
     const int i0 = bx * VO, j0 = by * VO;
     const int n = L.n;
     {
@@ -903,6 +914,21 @@ __global__ __launch_bounds__(TPB) void k_bsr_first(const T* __restrict__ x_in, T
     }
 }
 
+template <typename T, bool UNIFORM, bool ZERO, bool PROL>
+__global__ __launch_bounds__(TPB) void k_bsr_first(const T* __restrict__ x_in, T* __restrict__ x_pro,
+                                                   const T* __restrict__ b,
+                                                   T* __restrict__ r, T* __restrict__ t, Layout L,
+                                                   const T* __restrict__ kinv, T kinv_s,
+                                                   const T* __restrict__ coef, const T* __restrict__ uinv,
+                                                   const T* __restrict__ d, const T* __restrict__ xc, Layout Lc,
+                                                   const T* __restrict__ pw) {
+    __shared__ BsrFirstLds<T, UNIFORM, PROL> sh;
+    int bx, by;
+    xcd_tile(bx, by);
+    bsr_first_tile<T, UNIFORM, ZERO, PROL>(x_in, x_pro, b, r, t, L, kinv, kinv_s, coef, uinv, d, xc, Lc, pw, bx, by,
+                                           sh);
+}
+
 // Second half: dp = omega_J (A_pu t_u + A_pw t_w - r_p) / diag(S) on the window the update
 // needs, then x_dst = x_src + omega (F_u^{-1}(r_u - A_up dp), (r_w - A_wp dp) / (tau D_w), dp)
 // on the owned slots (x_dst may be x_src: each slot is read and written by its own thread).
@@ -921,14 +947,11 @@ struct BsrSecondLds {
 };
 
 template <typename T, bool ZERO>
-__global__ __launch_bounds__(TPB) void k_bsr_second(const T* __restrict__ r, const T* __restrict__ t,
-                                                    const T* x_src, T* x, Layout L, const T* __restrict__ uinv,
-                                                    const T* __restrict__ coef, const T* __restrict__ d,
-                                                    T omega, T omega_J) {
-    __shared__ BsrSecondLds<T> sh;
+__device__ __forceinline__ void bsr_second_tile(const T* __restrict__ r, const T* __restrict__ t, const T* x_src,
+                                                T* x, const Layout& L, const T* __restrict__ uinv,
+                                                const T* __restrict__ coef, const T* __restrict__ d, T omega,
+                                                T omega_J, int bx, int by, BsrSecondLds<T>& sh) {
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TB + tx;
-    int bx, by;
-    xcd_tile(bx, by);
     const int i0 = bx * VO, j0 = by * VO;
     const int n = L.n;
     {
@@ -1018,6 +1041,17 @@ __global__ __launch_bounds__(TPB) void k_bsr_second(const T* __restrict__ r, con
                     x[q * L.plane + s0] = (ZERO ? (T)0 : x_src[q * L.plane + s0]) + omega * sh.dp[q - T_PL][ty + 2][tx + 2];
         }
     }
+}
+
+template <typename T, bool ZERO>
+__global__ __launch_bounds__(TPB) void k_bsr_second(const T* __restrict__ r, const T* __restrict__ t,
+                                                    const T* x_src, T* x, Layout L, const T* __restrict__ uinv,
+                                                    const T* __restrict__ coef, const T* __restrict__ d,
+                                                    T omega, T omega_J) {
+    __shared__ BsrSecondLds<T> sh;
+    int bx, by;
+    xcd_tile(bx, by);
+    bsr_second_tile<T, ZERO>(r, t, x_src, x, L, uinv, coef, d, omega, omega_J, bx, by, sh);
 }
 
 template <typename T>
@@ -1142,14 +1176,12 @@ __device__ __forceinline__ T rr_row(const T (&rs)[NTYPES][RRW][RRW], int cx, int
 }
 
 template <typename T, bool UNIFORM>
-__global__ __launch_bounds__(TPB) void k_residual_restrict(const T* __restrict__ x, const T* __restrict__ b,
-                                                           T* __restrict__ rc, Layout Lf, Layout Lc,
-                                                           const T* __restrict__ kinv, T kinv_s,
-                                                           const T* __restrict__ coef, const T* __restrict__ w) {
-    __shared__ ResRestrictLds<T, UNIFORM> sh;
+__device__ __forceinline__ void residual_restrict_tile(const T* __restrict__ x, const T* __restrict__ b,
+                                                       T* __restrict__ rc, const Layout& Lf, const Layout& Lc,
+                                                       const T* __restrict__ kinv, T kinv_s,
+                                                       const T* __restrict__ coef, const T* __restrict__ w, int bx,
+                                                       int by, ResRestrictLds<T, UNIFORM>& sh) {
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TB + tx;
-    int bx, by;
-    xcd_tile(bx, by);
     const int I0 = bx * RT, J0 = by * RT;
     const int f0i = 2 * I0 - 2, f0j = 2 * J0 - 2;   // fine origin of the residual window
     const int n = Lf.n;
@@ -1243,6 +1275,17 @@ __global__ __launch_bounds__(TPB) void k_residual_restrict(const T* __restrict__
         });
         rc[tc * Lc.plane + slot_index(Lc, I, J)] = dof_free(tc, I, J, Lc.n) ? v : (T)0;
     }
+}
+
+template <typename T, bool UNIFORM>
+__global__ __launch_bounds__(TPB) void k_residual_restrict(const T* __restrict__ x, const T* __restrict__ b,
+                                                           T* __restrict__ rc, Layout Lf, Layout Lc,
+                                                           const T* __restrict__ kinv, T kinv_s,
+                                                           const T* __restrict__ coef, const T* __restrict__ w) {
+    __shared__ ResRestrictLds<T, UNIFORM> sh;
+    int bx, by;
+    xcd_tile(bx, by);
+    residual_restrict_tile<T, UNIFORM>(x, b, rc, Lf, Lc, kinv, kinv_s, coef, w, bx, by, sh);
 }
 
 template <typename T>
@@ -1340,24 +1383,45 @@ template void launch_prolong_add<float>(const Layout&, const Layout&, const floa
 // coarsest level: dense inverse applied by one workgroup (Sec. 5.1 direct solve)
 // =========================================================================================
 template <typename T>
-__global__ __launch_bounds__(256) void k_coarse_solve(const double* __restrict__ Ainv, int N,
-                                                      const int* __restrict__ idx, const T* __restrict__ b,
-                                                      T* __restrict__ x) {
-    extern __shared__ double bb[];
-    for (int k = threadIdx.x; k < N; k += blockDim.x) bb[k] = (double)b[idx[k]];
+__device__ __forceinline__ void coarse_solve_block(const double* __restrict__ AinvT, int N, const int* __restrict__ idx,
+                                                   const T* __restrict__ b, T* __restrict__ x, double* bb, int tid,
+                                                   int nt) {
+    for (int k = tid; k < N; k += nt) bb[k] = (double)b[idx[k]];
     __syncthreads();
-    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+    for (int k = tid; k < N; k += nt) {
         double s = 0;
-        const double* row = Ainv + (long long)k * N;
-        for (int l = 0; l < N; ++l) s += row[l] * bb[l];
+        for (int l = 0; l < N; ++l) s += AinvT[(long long)l * N + k] * bb[l];
         x[idx[k]] = (T)s;
     }
 }
 
+// x = A_c^{-1} b on the free DoFs of the coarsest level (AinvT: the inverse, transposed, so that
+// the threads of a row step read consecutive entries)
 template <typename T>
-void launch_coarse_solve(const double* Ainv, int N, const int* idx, const T* b, T* x, hipStream_t st) {
-    hipLaunchKernelGGL(k_coarse_solve<T>, dim3(1), dim3(256), N * sizeof(double), st, Ainv, N, idx, b, x);
+__global__ __launch_bounds__(256) void k_coarse_solve(const double* __restrict__ AinvT, int N,
+                                                      const int* __restrict__ idx, const T* __restrict__ b,
+                                                      T* __restrict__ x) {
+    extern __shared__ double bb[];
+    coarse_solve_block<T>(AinvT, N, idx, b, x, bb, threadIdx.x, blockDim.x);
 }
+
+template <typename T>
+void launch_coarse_solve(const double* AinvT, int N, const int* idx, const T* b, T* x, hipStream_t st) {
+    hipLaunchKernelGGL(k_coarse_solve<T>, dim3(1), dim3(256), N * sizeof(double), st, AinvT, N, idx, b, x);
+}
+
+__global__ void k_transpose(const double* __restrict__ A, double* __restrict__ AT, int N) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (long long)N * N) return;
+    const int r = (int)(q / N), c = (int)(q - (long long)r * N);
+    AT[(long long)c * N + r] = A[q];
+}
+
+void launch_transpose(const double* A, double* AT, int N, hipStream_t st) {
+    const long long nn = (long long)N * N;
+    hipLaunchKernelGGL(k_transpose, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, A, AT, N);
+}
+
 template void launch_coarse_solve<double>(const double*, int, const int*, const double*, double*, hipStream_t);
 template void launch_coarse_solve<float>(const double*, int, const int*, const float*, float*, hipStream_t);
 
@@ -1520,36 +1584,41 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// partial sums of V_q . w (q < nv) and of w . w (slot nv), four vectors per pass over the chunk
+// partial sums of V_q . w (q < nv) and of w . w (slot nv), GSV vectors per pass over the chunk;
+// each value is summed within a wave by a butterfly, then over the 4 waves in a fixed order
+constexpr int GSV = 8;
 __global__ __launch_bounds__(256) void k_gs_dots(const double* __restrict__ V, long long ldv, int nv,
                                                  const double* __restrict__ w, long long n,
                                                  double* __restrict__ partial, const double* run_if) {
     if (run_if && *run_if == 0.0) return;
-    __shared__ double red[5][256];
+    __shared__ double red[4][GSV + 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const long long chunk = (n + gridDim.x - 1) / gridDim.x;
     const long long lo = (long long)blockIdx.x * chunk;
     const long long hi = min(n, lo + chunk);
-    for (int v0 = 0; v0 == 0 || v0 < nv; v0 += 4) {
-        double acc[5] = {0, 0, 0, 0, 0};
+    for (int v0 = 0; v0 == 0 || v0 < nv; v0 += GSV) {
+        double acc[GSV + 1];
+#pragma unroll
+        for (int q = 0; q <= GSV; ++q) acc[q] = 0;
         for (long long e = lo + threadIdx.x; e < hi; e += blockDim.x) {
             const double we = w[e];
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < GSV; ++q)
                 if (v0 + q < nv) acc[q] += V[(long long)(v0 + q) * ldv + e] * we;
-            if (v0 == 0) acc[4] += we * we;
+            if (v0 == 0) acc[GSV] += we * we;
         }
 #pragma unroll
-        for (int q = 0; q < 5; ++q) red[q][threadIdx.x] = acc[q];
+        for (int q = 0; q <= GSV; ++q) {
+            const double t = wave_sum(acc[q]);
+            if (lane == 0) red[wave][q] = t;
+        }
         __syncthreads();
-        for (int st = 128; st > 0; st >>= 1) {
-            if ((int)threadIdx.x < st)
-#pragma unroll
-                for (int q = 0; q < 5; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + st];
-            __syncthreads();
+        const int q = threadIdx.x;
+        if (q <= GSV) {
+            const double r = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+            if (q < GSV && v0 + q < nv) partial[(long long)(v0 + q) * gridDim.x + blockIdx.x] = r;
+            if (q == GSV && v0 == 0) partial[(long long)nv * gridDim.x + blockIdx.x] = r;
         }
-        if (threadIdx.x < 4 && v0 + (int)threadIdx.x < nv)
-            partial[(long long)(v0 + threadIdx.x) * gridDim.x + blockIdx.x] = red[threadIdx.x][0];
-        if (threadIdx.x == 4 && v0 == 0) partial[(long long)nv * gridDim.x + blockIdx.x] = red[4][0];
         __syncthreads();
     }
 }
