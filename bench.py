@@ -24,21 +24,25 @@ CSRC = os.path.join(ROOT, "paper_2107_04060_amd", "csrc")
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_vanka_step_sweep256_fp64.md")
 
 
+# sources that define the finest-level Vanka step (its traffic summary is valid while they are
+# unchanged)
+VANKA_SOURCES = ["vanka.hip", "tile.h", "patch_solve.h", "structure.h", "common.h", "kernels.h"]
+
+
 def kernel_source_hash():
-    """sha256 over the HIP/C++ sources of the library (file names and contents, sorted)."""
+    """sha256 over the sources of the Vanka step kernel (file names and contents, in order)."""
     import hashlib
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".h", ".cpp")):
-            h.update(name.encode())
-            with open(os.path.join(CSRC, name), "rb") as f:
-                h.update(f.read())
+    for name in VANKA_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()
 
 
 def measured_traffic():
     """HBM bytes per finest-level Vanka launch from the committed rocprofv3 counter summary
-    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the kernel sources changed
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the Vanka step's sources changed
     since the counters were taken (or no summary exists)."""
     try:
         with open(TRAFFIC_PROFILE) as f:

@@ -305,10 +305,6 @@ static void coarse_factor(biot_ctx* c, hipStream_t st) {
     launch_coarse_matrix(lc.L, lc.st.as<StencilEntry>(), lc.st_off.as<int>(), lc.kinv64.as<double>(),
                          c->coarse_idx.as<int>(), c->coarse_map.as<int>(), N, c->coarse_A.as<double>(), st);
     launch_gauss_jordan(c->coarse_A.as<double>(), c->coarse_inv.as<double>(), N, c->status.as<int>(), st);
-    // the solve kernels read the inverse transposed
-    launch_transpose(c->coarse_inv.as<double>(), c->coarse_A.as<double>(), N, st);
-    BIOT_HIP(hipMemcpyAsync(c->coarse_inv.p, c->coarse_A.p, (size_t)N * N * sizeof(double), hipMemcpyDeviceToDevice,
-                            st));
     check_stream_error();
     int status = 0;
     BIOT_HIP(hipMemcpyAsync(&status, c->status.p, sizeof(int), hipMemcpyDeviceToHost, st));

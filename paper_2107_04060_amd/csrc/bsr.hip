@@ -1,0 +1,438 @@
+// Inexact Braess-Sarazin relaxation (Sec. 3.2.2, Appendix D) in two fused launches.
+#include "tile.h"
+#include "patch_solve.h"
+
+#include <hip/hip_runtime.h>
+
+namespace biot {
+
+// =========================================================================================
+// inexact Braess-Sarazin relaxation (Sec. 3.2.2, Appendix D)
+// =========================================================================================
+// One step on the residual r:
+//   z_u = F_u^{-1} r_u            (additive Vanka on the displacement block, 8-DoF patches)
+//   z_w = r_w / (tau D_w)         (D_w = diag M_w(K))
+//   dp  = omega_J (A_pu z_u + A_pw z_w - r_p) / diag(S)
+//   du  = F_u^{-1} (r_u - A_up dp),  dw = (r_w - A_wp dp) / (tau D_w)
+//   x  += omega (du, dw, dp)
+// with diag(S)_T = (1/M + alpha^2 / (lambda + mu)) |T| + sum_e (tau B_w)_{Te}^2 / (tau D_w)_e.
+// Two launches: k_bsr_first (residual, z_u, z_w), k_bsr_second (dp on its window, update).
+
+
+constexpr int BSR_W = 0;   // planes 0..2 of the diagonal data: 1 / (tau D_w) of w_H, w_V, w_D
+constexpr int BSR_S = 3;   // planes 3..4: 1 / diag(S) of p_L, p_U
+
+// diagonal of the RT0 block: the entries of a w row on its own slot
+template <typename T>
+__global__ __launch_bounds__(256) void k_bsr_wdiag(const T* __restrict__ kinv, const T* __restrict__ coef,
+                                                   Layout L, T* __restrict__ d) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i > L.n || j > L.n) return;
+    const long long s = slot_index(L, i, j);
+    static_for(std::integer_sequence<int, T_WH, T_WV, T_WD>{}, [&](auto tc) {
+        constexpr int t = decltype(tc)::value;
+        T v = 0;
+        static_for(std::make_integer_sequence<int, SST.n[t]>{}, [&](auto ec) {
+            constexpr SEnt en = SST.e[t][decltype(ec)::value];
+            if constexpr (en.in == t && en.di == 0 && en.dj == 0) {
+                T cc = coef[SST.off[t] + decltype(ec)::value];
+                if constexpr (en.kt >= 0) cc *= kinv[en.kt * L.plane + s + (long long)en.kdj * L.pitch + en.kdi];
+                v += cc;
+            }
+        });
+        d[(BSR_W + t - T_WH) * L.plane + s] = dof_free(t, i, j, L.n) ? (T)1 / v : (T)0;
+    });
+}
+
+// diag(S) of the P0 rows from the RT0 diagonal (k_bsr_wdiag first)
+template <typename T>
+__global__ __launch_bounds__(256) void k_bsr_sdiag(const T* __restrict__ coef, Layout L, T cS,
+                                                   T* __restrict__ d) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i > L.n || j > L.n) return;
+    const long long s = slot_index(L, i, j);
+    static_for(std::integer_sequence<int, T_PL, T_PU>{}, [&](auto tc) {
+        constexpr int t = decltype(tc)::value;
+        T v = cS;
+        static_for(std::make_integer_sequence<int, SST.n[t]>{}, [&](auto ec) {
+            constexpr SEnt en = SST.e[t][decltype(ec)::value];
+            if constexpr (tfield(en.in) == 1) {
+                static_assert(en.kt < 0, "B_w does not depend on K");
+                const T cc = coef[SST.off[t] + decltype(ec)::value];
+                // column slots s + (0..1, 0..1) lie inside the padded plane
+                v += cc * cc * d[(BSR_W + en.in - T_WH) * L.plane + s + (long long)en.dj * L.pitch + en.di];
+            }
+        });
+        d[(BSR_S + t - T_PL) * L.plane + s] = dof_free(t, i, j, L.n) ? (T)1 / v : (T)0;
+    });
+}
+
+template <typename T>
+void launch_bsr_diag(const LevelView<T>& lv, T cS, T* d, hipStream_t st) {
+    dim3 blk(64, 4);
+    dim3 grd((lv.L.n + 1 + 63) / 64, (lv.L.n + 1 + 3) / 4);
+    hipLaunchKernelGGL(k_bsr_wdiag<T>, grd, blk, 0, st, lv.kinv, lv.coef, lv.L, d);
+    hipLaunchKernelGGL(k_bsr_sdiag<T>, grd, blk, 0, st, lv.coef, lv.L, cS, d);
+}
+template void launch_bsr_diag<double>(const LevelView<double>&, double, double*, hipStream_t);
+template void launch_bsr_diag<float>(const LevelView<float>&, float, float*, hipStream_t);
+
+constexpr int NU = 5;   // displacement DoF types ux, uy, bH, bV, bD
+
+// Tiles as in the Vanka step: 16 x 16 threads, VT x VT vertices from (i0, j0), VO x VO owned
+// slots; one residual slot of (i0-1 .. i0+VT-1)^2 per thread.
+
+// displacement-patch solves (8 x 8 class inverses, identity on absent DoFs) of the tile's
+// vertices from the displacement residual ru (slots i0-1 .. i0+VT-1): so[a][ty][tx]
+template <typename T>
+__device__ __forceinline__ void upatch_solves(const T (&ru)[NU][RW][RW], const T (&ui)[9][64], T (&so)[8][VT][VT],
+                                              int i0, int j0, int n, int tx, int ty) {
+    if (tx >= VT || ty >= VT) return;
+    const int vi = i0 + tx, vj = j0 + ty;
+    T out[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) out[a] = 0;
+    if (vi <= n && vj <= n) {
+        const int ci = vi == 0 ? 0 : (vi == n ? 2 : 1);
+        const int cj = vj == 0 ? 0 : (vj == n ? 2 : 1);
+        const T* M = ui[3 * cj + ci];
+        T rr[8];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            int t, di, dj;
+            patch_slot(a, t, di, dj);
+            rr[a] = ru[t][ty + 1 + dj][tx + 1 + di];
+        }
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            T v = 0;
+#pragma unroll
+            for (int b2 = 0; b2 < 8; ++b2) v += M[a * 8 + b2] * rr[b2];
+            out[a] = v;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 8; ++a) so[a][ty][tx] = out[a];
+}
+
+// weighted sum of the patch corrections at owned slot (tx, ty): P1 in one patch, bubbles in
+// the two patches of their end points (weight 1/2)
+template <typename T>
+__device__ __forceinline__ void upatch_gather(const T (&so)[8][VT][VT], int tx, int ty, T (&du)[NU]) {
+    du[T_UX] = so[0][ty][tx];
+    du[T_UY] = so[1][ty][tx];
+    du[T_BH] = (T)0.5 * (so[3][ty][tx] + so[2][ty][tx + 1]);
+    du[T_BV] = (T)0.5 * (so[5][ty][tx] + so[4][ty + 1][tx]);
+    du[T_BD] = (T)0.5 * (so[6][ty][tx + 1] + so[7][ty + 1][tx]);
+}
+
+template <typename T>
+__device__ __forceinline__ void load_uinv(const T* __restrict__ uinv, T (&ui)[9][64], int tid) {
+    T v[3];
+#pragma unroll
+    for (int it = 0; it < 3; ++it) {
+        const int q = tid + it * TPB;
+        v[it] = q < 9 * 64 ? uinv[q] : (T)0;
+    }
+#pragma unroll
+    for (int it = 0; it < 3; ++it) {
+        const int q = tid + it * TPB;
+        if (q < 9 * 64) (&ui[0][0])[q] = v[it];
+    }
+}
+
+template <typename T, bool UNIFORM, bool PROL>
+struct BsrFirstLds {
+    T xs[NTYPES][XS][XS];
+    T rs[NTYPES][RW][RW];
+    T so[8][VT][VT];
+    T ui[9][64];
+    T ks[UNIFORM ? 1 : 2][UNIFORM ? 1 : KW][UNIFORM ? 1 : KW];
+    T xcs[PROL ? NTYPES : 1][PROL ? PCW : 1][PROL ? PCW : 1];
+    T cf[NSTENCIL];
+    T pwl[PROL ? NPWEIGHTS : 1];
+};
+
+// First half of a BSR step: r = b - A x (x: x_in, or x_in + P x_c with PROL, or 0 with ZERO),
+// t_u = F_u^{-1} r_u, t_w = r_w / (tau D_w).  Writes r and t on the owned slots, and with PROL
+// the prolongated iterate to x_pro (neighbouring tiles still read x_in on their halo).
+template <typename T, bool UNIFORM, bool ZERO, bool PROL>
+__device__ __forceinline__ void bsr_first_tile(const T* __restrict__ x_in, T* __restrict__ x_pro,
+                                               const T* __restrict__ b, T* __restrict__ r, T* __restrict__ t,
+                                               const Layout& L, const T* __restrict__ kinv, T kinv_s,
+                                               const T* __restrict__ coef, const T* __restrict__ uinv,
+                                               const T* __restrict__ d, const T* __restrict__ xc, const Layout& Lc,
+                                               const T* __restrict__ pw, int bx, int by,
+                                               BsrFirstLds<T, UNIFORM, PROL>& sh) {
+    static_assert(!(PROL && ZERO), "the prolongation needs an iterate");
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TB + tx;
+    const int i0 = bx * VO, j0 = by * VO;
+    const int n = L.n;
+    {
+        Window<T, NTYPES, RW> wb;
+        wb.load(b, L.plane, L, i0 - 1, j0 - 1, tid);
+        Window<T, NTYPES, XS> wx;
+        if constexpr (!ZERO) wx.load(x_in, L.plane, L, i0 - 2, j0 - 2, tid);
+        Window<T, 2, KW> wk;
+        if constexpr (!UNIFORM && !ZERO) wk.load(kinv, L.plane, L, i0 - 2, j0 - 2, tid);
+        Window<T, NTYPES, PCW> wc;
+        if constexpr (PROL) wc.load(xc, Lc.plane, Lc, i0 / 2 - 1, j0 / 2 - 1, tid);
+        Table<T, NSTENCIL> tcf;
+        if constexpr (!ZERO) tcf.load(coef, tid);
+        Table<T, NPWEIGHTS> tpw;
+        if constexpr (PROL) tpw.load(pw, tid);
+        load_uinv(uinv, sh.ui, tid);
+        if constexpr (!ZERO) tcf.store(sh.cf, tid);
+        if constexpr (PROL) tpw.store(sh.pwl, tid);
+        wb.store(&sh.rs[0][0][0], tid);
+        if constexpr (!ZERO) wx.store(&sh.xs[0][0][0], tid);
+        if constexpr (!UNIFORM && !ZERO) wk.store(&sh.ks[0][0][0], tid);
+        if constexpr (PROL) wc.store(&sh.xcs[0][0][0], tid);
+    }
+    __syncthreads();
+    if constexpr (PROL) {
+        constexpr int NCW = (XS + 1) / 2;
+        if (tid < NCW * NCW) {
+            const int cj = tid / NCW, ci = tid - cj * NCW;
+            const int I = i0 / 2 - 1 + ci, J = j0 / 2 - 1 + cj;
+            static_for(std::make_integer_sequence<int, 4>{}, [&](auto pc) {
+                constexpr int pi = decltype(pc)::value & 1, pj = decltype(pc)::value >> 1;
+                const int a = 2 * ci + pi, bb = 2 * cj + pj;
+                if (a < XS && bb < XS) {
+                    static_for(std::make_integer_sequence<int, NTYPES>{}, [&](auto tcn) {
+                        constexpr int tf = decltype(tcn)::value;
+                        if (dof_free(tf, 2 * I + pi, 2 * J + pj, n))
+                            sh.xs[tf][bb][a] += prolong_value<T, tf, pi, pj>(sh.xcs, ci, cj, sh.pwl);
+                    });
+                }
+            });
+        }
+        __syncthreads();
+    }
+    if constexpr (!ZERO) {
+        const int si = i0 - 1 + tx, sj = j0 - 1 + ty;
+        const bool in = si <= n + 1 && sj <= n + 1;
+        T rv[NTYPES];
+        static_for(std::make_integer_sequence<int, NTYPES>{}, [&](auto tcn) {
+            constexpr int tt = decltype(tcn)::value;
+            T acc = 0;
+            static_for(std::make_integer_sequence<int, SST.n[tt]>{}, [&](auto ec) {
+                constexpr int e = decltype(ec)::value;
+                constexpr SEnt en = SST.e[tt][e];
+                T cc = sh.cf[SST.off[tt] + e];
+                if constexpr (en.kt >= 0) {
+                    if constexpr (UNIFORM)
+                        cc *= kinv_s;
+                    else
+                        cc *= sh.ks[en.kt][ty + 1 + en.kdj][tx + 1 + en.kdi];
+                }
+                acc += cc * sh.xs[en.in][ty + 1 + en.dj][tx + 1 + en.di];
+            });
+            rv[tt] = (in && dof_free(tt, si, sj, n)) ? sh.rs[tt][ty][tx] - acc : (T)0;
+        });
+#pragma unroll
+        for (int tt = 0; tt < NTYPES; ++tt) sh.rs[tt][ty][tx] = rv[tt];
+        __syncthreads();
+    }
+    upatch_solves<T>(reinterpret_cast<const T(&)[NU][RW][RW]>(sh.rs), sh.ui, sh.so, i0, j0, n, tx, ty);
+    __syncthreads();
+    if (tx < VO && ty < VO) {
+        const int si = i0 + tx, sj = j0 + ty;
+        if (si <= n && sj <= n) {
+            const long long s0 = slot_index(L, si, sj);
+            T du[NU];
+            upatch_gather<T>(sh.so, tx, ty, du);
+#pragma unroll
+            for (int q = 0; q < NU; ++q) t[q * L.plane + s0] = dof_free(q, si, sj, n) ? du[q] : (T)0;
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                t[(T_WH + q) * L.plane + s0] = sh.rs[T_WH + q][ty + 1][tx + 1] * d[(BSR_W + q) * L.plane + s0];
+#pragma unroll
+            for (int q = 0; q < NTYPES; ++q) r[q * L.plane + s0] = sh.rs[q][ty + 1][tx + 1];
+            if constexpr (PROL) {
+#pragma unroll
+                for (int q = 0; q < NTYPES; ++q)
+                    if (dof_free(q, si, sj, n)) x_pro[q * L.plane + s0] = sh.xs[q][ty + 2][tx + 2];
+            }
+        }
+    }
+}
+
+template <typename T, bool UNIFORM, bool ZERO, bool PROL>
+__global__ __launch_bounds__(TPB) void k_bsr_first(const T* __restrict__ x_in, T* __restrict__ x_pro,
+                                                   const T* __restrict__ b,
+                                                   T* __restrict__ r, T* __restrict__ t, Layout L,
+                                                   const T* __restrict__ kinv, T kinv_s,
+                                                   const T* __restrict__ coef, const T* __restrict__ uinv,
+                                                   const T* __restrict__ d, const T* __restrict__ xc, Layout Lc,
+                                                   const T* __restrict__ pw) {
+    __shared__ BsrFirstLds<T, UNIFORM, PROL> sh;
+    int bx, by;
+    xcd_tile(bx, by);
+    bsr_first_tile<T, UNIFORM, ZERO, PROL>(x_in, x_pro, b, r, t, L, kinv, kinv_s, coef, uinv, d, xc, Lc, pw, bx, by,
+                                           sh);
+}
+
+// Second half: dp = omega_J (A_pu t_u + A_pw t_w - r_p) / diag(S) on the window the update
+// needs, then x_dst = x_src + omega (F_u^{-1}(r_u - A_up dp), (r_w - A_wp dp) / (tau D_w), dp)
+// on the owned slots (x_dst may be x_src: each slot is read and written by its own thread).
+constexpr int TW = VT + 4;   // staged t: slots i0-2 .. i0+VT+1
+constexpr int DW = VT + 3;   // pressure update: slots i0-2 .. i0+VT
+
+template <typename T>
+struct BsrSecondLds {
+    T ts[8][TW][TW];         // t_u, t_w
+    T dp[2][DW][DW];         // r_p, then the pressure update
+    T ds[2][DW][DW];         // 1 / diag(S)
+    T ru[NU][RW][RW];        // r_u, then r_u - A_up dp
+    T so[8][VT][VT];
+    T ui[9][64];
+    T cf[NSTENCIL];
+};
+
+template <typename T, bool ZERO>
+__device__ __forceinline__ void bsr_second_tile(const T* __restrict__ r, const T* __restrict__ t, const T* x_src,
+                                                T* x, const Layout& L, const T* __restrict__ uinv,
+                                                const T* __restrict__ coef, const T* __restrict__ d, T omega,
+                                                T omega_J, int bx, int by, BsrSecondLds<T>& sh) {
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TB + tx;
+    const int i0 = bx * VO, j0 = by * VO;
+    const int n = L.n;
+    {
+        Window<T, 8, TW> wt;
+        wt.load(t, L.plane, L, i0 - 2, j0 - 2, tid);
+        Window<T, 2, DW> wp;
+        wp.load(r + T_PL * L.plane, L.plane, L, i0 - 2, j0 - 2, tid);
+        Window<T, 2, DW> wd;
+        wd.load(d + BSR_S * L.plane, L.plane, L, i0 - 2, j0 - 2, tid);
+        Window<T, NU, RW> wr;
+        wr.load(r, L.plane, L, i0 - 1, j0 - 1, tid);
+        Table<T, NSTENCIL> tcf;
+        tcf.load(coef, tid);
+        load_uinv(uinv, sh.ui, tid);
+        tcf.store(sh.cf, tid);
+        wt.store(&sh.ts[0][0][0], tid);
+        wp.store(&sh.dp[0][0][0], tid);
+        wd.store(&sh.ds[0][0][0], tid);
+        wr.store(&sh.ru[0][0][0], tid);
+    }
+    __syncthreads();
+    // pressure update on slots (i0-2 .. i0+VT)^2; its columns reach t at +0 .. +1
+    for (int q = tid; q < DW * DW; q += TPB) {
+        const int bb = q / DW, a = q - bb * DW;
+        const int si = i0 - 2 + a, sj = j0 - 2 + bb;
+        static_for(std::integer_sequence<int, T_PL, T_PU>{}, [&](auto tc) {
+            constexpr int tp = decltype(tc)::value;
+            T acc = 0;
+            static_for(std::make_integer_sequence<int, SST.n[tp]>{}, [&](auto ec) {
+                constexpr int e = decltype(ec)::value;
+                constexpr SEnt en = SST.e[tp][e];
+                if constexpr (tfield(en.in) != 2) {
+                    static_assert(en.kt < 0, "the pressure rows do not depend on K");
+                    acc += sh.cf[SST.off[tp] + e] * sh.ts[en.in][bb + en.dj][a + en.di];
+                }
+            });
+            const T v = omega_J * (acc - sh.dp[tp - T_PL][bb][a]) * sh.ds[tp - T_PL][bb][a];
+            sh.dp[tp - T_PL][bb][a] = dof_free(tp, si, sj, n) ? v : (T)0;
+        });
+    }
+    __syncthreads();
+    // displacement residual after the pressure update, slot (i0-1+tx, j0-1+ty); its pressure
+    // columns reach dp at -1 .. 0
+    {
+        const int si = i0 - 1 + tx, sj = j0 - 1 + ty;
+        T rv[NU];
+        static_for(std::make_integer_sequence<int, NU>{}, [&](auto tcn) {
+            constexpr int tu = decltype(tcn)::value;
+            T acc = 0;
+            static_for(std::make_integer_sequence<int, SST.n[tu]>{}, [&](auto ec) {
+                constexpr int e = decltype(ec)::value;
+                constexpr SEnt en = SST.e[tu][e];
+                if constexpr (tfield(en.in) == 2) acc += sh.cf[SST.off[tu] + e] * sh.dp[en.in - T_PL][ty + 1 + en.dj][tx + 1 + en.di];
+            });
+            rv[tu] = dof_free(tu, si, sj, n) ? sh.ru[tu][ty][tx] - acc : (T)0;
+        });
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NU; ++q) sh.ru[q][ty][tx] = rv[q];
+    }
+    __syncthreads();
+    upatch_solves<T>(sh.ru, sh.ui, sh.so, i0, j0, n, tx, ty);
+    __syncthreads();
+    if (tx < VO && ty < VO) {
+        const int si = i0 + tx, sj = j0 + ty;
+        if (si <= n && sj <= n) {
+            const long long s0 = slot_index(L, si, sj);
+            T du[NU];
+            upatch_gather<T>(sh.so, tx, ty, du);
+#pragma unroll
+            for (int q = 0; q < NU; ++q)
+                if (dof_free(q, si, sj, n)) x[q * L.plane + s0] = (ZERO ? (T)0 : x_src[q * L.plane + s0]) + omega * du[q];
+            static_for(std::integer_sequence<int, T_WH, T_WV, T_WD>{}, [&](auto tc) {
+                constexpr int tw = decltype(tc)::value;
+                T acc = 0;
+                static_for(std::make_integer_sequence<int, SST.n[tw]>{}, [&](auto ec) {
+                    constexpr int e = decltype(ec)::value;
+                    constexpr SEnt en = SST.e[tw][e];
+                    if constexpr (tfield(en.in) == 2) acc += sh.cf[SST.off[tw] + e] * sh.dp[en.in - T_PL][ty + 2 + en.dj][tx + 2 + en.di];
+                });
+                const T dwv = (r[tw * L.plane + s0] - acc) * d[(BSR_W + tw - T_WH) * L.plane + s0];
+                if (dof_free(tw, si, sj, n)) x[tw * L.plane + s0] = (ZERO ? (T)0 : x_src[tw * L.plane + s0]) + omega * dwv;
+            });
+#pragma unroll
+            for (int q = T_PL; q <= T_PU; ++q)
+                if (dof_free(q, si, sj, n))
+                    x[q * L.plane + s0] = (ZERO ? (T)0 : x_src[q * L.plane + s0]) + omega * sh.dp[q - T_PL][ty + 2][tx + 2];
+        }
+    }
+}
+
+template <typename T, bool ZERO>
+__global__ __launch_bounds__(TPB) void k_bsr_second(const T* __restrict__ r, const T* __restrict__ t,
+                                                    const T* x_src, T* x, Layout L, const T* __restrict__ uinv,
+                                                    const T* __restrict__ coef, const T* __restrict__ d,
+                                                    T omega, T omega_J) {
+    __shared__ BsrSecondLds<T> sh;
+    int bx, by;
+    xcd_tile(bx, by);
+    bsr_second_tile<T, ZERO>(r, t, x_src, x, L, uinv, coef, d, omega, omega_J, bx, by, sh);
+}
+
+template <typename T>
+void launch_bsr_step(const LevelView<T>& lv, T* x, const T* b, T* r, T* t, bool x_is_zero, bool uniform, T kinv_s,
+                     T omega, T omega_J, const T* xc, const Layout* Lc, const T* pw, T* xtmp, hipStream_t st) {
+    dim3 blk(TB, TB);
+    dim3 grd((lv.L.n + 1 + VO - 1) / VO, (lv.L.n + 1 + VO - 1) / VO);
+    const Layout lc = Lc ? *Lc : lv.L;
+    if (xc && (x_is_zero || !xtmp || xtmp == x)) throw ArgError{"the prolongation needs an iterate and a buffer"};
+#define BIOT_BSR_FIRST(U, Z, P)                                                                                  \
+    hipLaunchKernelGGL((k_bsr_first<T, U, Z, P>), grd, blk, 0, st, x, xtmp, b, r, t, lv.L, lv.kinv, kinv_s,     \
+                       lv.coef, lv.uinv, lv.bsrd, xc, lc, pw)
+    if (x_is_zero)
+        BIOT_BSR_FIRST(true, true, false);
+    else if (uniform && xc)
+        BIOT_BSR_FIRST(true, false, true);
+    else if (uniform)
+        BIOT_BSR_FIRST(true, false, false);
+    else if (xc)
+        BIOT_BSR_FIRST(false, false, true);
+    else
+        BIOT_BSR_FIRST(false, false, false);
+#undef BIOT_BSR_FIRST
+    const T* xsrc = xc ? xtmp : x;
+    if (x_is_zero)
+        hipLaunchKernelGGL((k_bsr_second<T, true>), grd, blk, 0, st, r, t, xsrc, x, lv.L, lv.uinv, lv.coef, lv.bsrd,
+                           omega, omega_J);
+    else
+        hipLaunchKernelGGL((k_bsr_second<T, false>), grd, blk, 0, st, r, t, xsrc, x, lv.L, lv.uinv, lv.coef, lv.bsrd,
+                           omega, omega_J);
+}
+template void launch_bsr_step<double>(const LevelView<double>&, double*, const double*, double*, double*, bool, bool,
+                                      double, double, double, const double*, const Layout*, const double*, double*,
+                                      hipStream_t);
+template void launch_bsr_step<float>(const LevelView<float>&, float*, const float*, float*, float*, bool, bool, float,
+                                     float, float, const float*, const Layout*, const float*, float*, hipStream_t);
+
+}  // namespace biot

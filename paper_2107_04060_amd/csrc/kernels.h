@@ -1,4 +1,5 @@
-// Launch wrappers of the device kernels (kernels.hip).  All launches go to `st`.
+// Launch wrappers of the device kernels (kernels.hip, vanka.hip, bsr.hip, transfer.hip,
+// krylov.hip).  All launches go to `st`.
 #pragma once
 #include "common.h"
 
@@ -79,11 +80,9 @@ template <typename T>
 void launch_bsr_step(const LevelView<T>& lv, T* x, const T* b, T* r, T* t, bool x_is_zero, bool uniform, T kinv_s,
                      T omega, T omega_J, const T* xc, const Layout* Lc, const T* pw, T* xtmp, hipStream_t st);
 
-// coarsest level (AinvT: the inverse of the coarsest operator, transposed)
+// coarsest level (Ainv: the inverse of the coarsest operator, row-major)
 template <typename T>
-void launch_coarse_solve(const double* AinvT, int N, const int* idx, const T* b, T* x, hipStream_t st);
-void launch_transpose(const double* A, double* AT, int N, hipStream_t st);
-
+void launch_coarse_solve(const double* Ainv, int N, const int* idx, const T* b, T* x, hipStream_t st);
 void launch_coarse_matrix(const Layout& L, const StencilEntry* st_tab, const int* st_off, const double* kinv,
                           const int* free_idx, const int* free_map, int N, double* A, hipStream_t st);
 void launch_gauss_jordan(double* A, double* Inv, int N, int* status, hipStream_t st);

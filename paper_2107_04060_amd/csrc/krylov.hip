@@ -1,0 +1,171 @@
+// FGMRES vector kernels (Sec. 5.1): classical Gram-Schmidt passes with deterministic two-stage
+// reductions, normalization, scaling and the solution update.
+#include "kernels.h"
+#include "tile.h"
+
+#include <algorithm>
+
+#include <hip/hip_runtime.h>
+
+namespace biot {
+
+// =========================================================================================
+// Krylov BLAS-1 (FP64, deterministic reductions)
+// =========================================================================================
+// ---- classical Gram-Schmidt pass: dots, update with norm, deterministic reductions ----------------
+// The partial sums of each block go to partial[q * np + b] (np blocks); a second kernel adds them
+// in a fixed order.  Kernels given run_if return at once when *run_if == 0.
+constexpr int DOT_BLOCKS = RED_BLOCKS;     // dot-product blocks (contiguous chunks)
+constexpr int UPD_BLOCKS = 4 * RED_BLOCKS; // update blocks (grid stride)
+
+
+// partial sums of V_q . w (q < nv) and of w . w (slot nv), GSV vectors per pass over the chunk;
+// each value is summed within a wave by a butterfly, then over the 4 waves in a fixed order
+constexpr int GSV = 8;
+__global__ __launch_bounds__(256) void k_gs_dots(const double* __restrict__ V, long long ldv, int nv,
+                                                 const double* __restrict__ w, long long n,
+                                                 double* __restrict__ partial, const double* run_if) {
+    if (run_if && *run_if == 0.0) return;
+    __shared__ double red[4][GSV + 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long long chunk = (n + gridDim.x - 1) / gridDim.x;
+    const long long lo = (long long)blockIdx.x * chunk;
+    const long long hi = min(n, lo + chunk);
+    for (int v0 = 0; v0 == 0 || v0 < nv; v0 += GSV) {
+        double acc[GSV + 1];
+#pragma unroll
+        for (int q = 0; q <= GSV; ++q) acc[q] = 0;
+        for (long long e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+            const double we = w[e];
+#pragma unroll
+            for (int q = 0; q < GSV; ++q)
+                if (v0 + q < nv) acc[q] += V[(long long)(v0 + q) * ldv + e] * we;
+            if (v0 == 0) acc[GSV] += we * we;
+        }
+#pragma unroll
+        for (int q = 0; q <= GSV; ++q) {
+            const double t = wave_sum(acc[q]);
+            if (lane == 0) red[wave][q] = t;
+        }
+        __syncthreads();
+        const int q = threadIdx.x;
+        if (q <= GSV) {
+            const double r = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+            if (q < GSV && v0 + q < nv) partial[(long long)(v0 + q) * gridDim.x + blockIdx.x] = r;
+            if (q == GSV && v0 == 0) partial[(long long)nv * gridDim.x + blockIdx.x] = r;
+        }
+        __syncthreads();
+    }
+}
+
+// w -= sum_q h[q] V_q, with partial sums of the new w . w
+__global__ __launch_bounds__(256) void k_gs_update(double* __restrict__ w, const double* __restrict__ V,
+                                                   long long ldv, int nv, const double* __restrict__ h,
+                                                   long long n, double* __restrict__ partial,
+                                                   const double* run_if) {
+    if (run_if && *run_if == 0.0) return;
+    __shared__ double wred[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double acc = 0;
+    long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (; e < n; e += stride) {
+        double sv = w[e];
+        for (int q = 0; q < nv; ++q) sv -= h[q] * V[(long long)q * ldv + e];
+        w[e] = sv;
+        acc += sv * sv;
+    }
+    const double t = wave_sum(acc);
+    if (lane == 0) wred[wave] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = wred[0] + wred[1] + wred[2] + wred[3];
+}
+
+// out[q] = sum_b partial[q * np + b], one block per q (fixed order); host: optional mirror.
+// flag (block 0, optional): 1 when out[0] < 0.5 * prev (the Daniel-Gragg-Kaufman-Stewart test
+// for a second orthogonalization pass, eta = 1/sqrt(2)).
+__global__ __launch_bounds__(256) void k_gs_reduce(const double* __restrict__ partial, int np,
+                                                   double* __restrict__ out, double* __restrict__ host,
+                                                   const double* __restrict__ prev, double* __restrict__ flag,
+                                                   const double* run_if) {
+    if (run_if && *run_if == 0.0) return;
+    __shared__ double wred[4];
+    const int q = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double sv = 0;
+    for (int b2 = threadIdx.x; b2 < np; b2 += blockDim.x) sv += partial[(long long)q * np + b2];
+    const double t = wave_sum(sv);
+    if (lane == 0) wred[wave] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double r = wred[0] + wred[1] + wred[2] + wred[3];
+        out[q] = r;
+        if (host) host[q] = r;
+        if (flag) {
+            *flag = (r < 0.5 * (*prev)) ? 1.0 : 0.0;
+            if (host) host[1] = *flag;
+        }
+    }
+}
+
+void launch_gs_dots(const double* V, long long ldv, int nv, const double* w, long long n, double* partial,
+                    double* out, double* host, const double* run_if, hipStream_t st) {
+    hipLaunchKernelGGL(k_gs_dots, dim3(DOT_BLOCKS), dim3(256), 0, st, V, ldv, nv, w, n, partial, run_if);
+    hipLaunchKernelGGL(k_gs_reduce, dim3(nv + 1), dim3(256), 0, st, partial, DOT_BLOCKS, out, host, nullptr,
+                       nullptr, run_if);
+}
+
+void launch_gs_update(double* w, const double* V, long long ldv, int nv, const double* h, long long n,
+                      double* partial, double* norm2, const double* prev, double* flag, double* host,
+                      const double* run_if, hipStream_t st) {
+    hipLaunchKernelGGL(k_gs_update, dim3(UPD_BLOCKS), dim3(256), 0, st, w, V, ldv, nv, h, n, partial, run_if);
+    hipLaunchKernelGGL(k_gs_reduce, dim3(1), dim3(256), 0, st, partial, UPD_BLOCKS, norm2, host, prev, flag,
+                       run_if);
+}
+
+// dst = src / sqrt(*na), or / sqrt(*nb) when sel != nullptr and *sel != 0
+__global__ void k_normalize(double* __restrict__ dst, const double* __restrict__ src, long long n,
+                            const double* __restrict__ na, const double* __restrict__ nb,
+                            const double* __restrict__ sel) {
+    const double nv = (sel && *sel != 0.0) ? *nb : *na;
+    const double s = 1.0 / sqrt(nv);
+    long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (; e < n; e += stride) dst[e] = src[e] * s;
+}
+
+void launch_normalize(double* dst, const double* src, long long n, const double* na, const double* nb,
+                      const double* sel, hipStream_t st) {
+    int blocks = (int)std::min<long long>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_normalize, dim3(blocks), dim3(256), 0, st, dst, src, n, na, nb, sel);
+}
+
+__global__ void k_scale(double* __restrict__ dst, const double* __restrict__ src, long long n, double s) {
+    long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (; e < n; e += stride) dst[e] = src[e] * s;
+}
+
+void launch_scale(double* dst, const double* src, long long n, double s, hipStream_t st) {
+    int blocks = (int)std::min<long long>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_scale, dim3(blocks), dim3(256), 0, st, dst, src, n, s);
+}
+
+__global__ void k_lincomb_add(double* __restrict__ x, const double* __restrict__ Z, long long ldz, int nv,
+                              const double* __restrict__ y, long long n) {
+    long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (; e < n; e += stride) {
+        double s = x[e];
+        for (int q = 0; q < nv; ++q) s += y[q] * Z[(long long)q * ldz + e];
+        x[e] = s;
+    }
+}
+
+void launch_lincomb_add(double* x, const double* Z, long long ldz, int nv, const double* y, long long n,
+                        hipStream_t st) {
+    int blocks = (int)std::min<long long>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_lincomb_add, dim3(blocks), dim3(256), 0, st, x, Z, ldz, nv, y, n);
+}
+
+}  // namespace biot

@@ -1,0 +1,109 @@
+// Tile machinery shared by the fused stencil kernels (additive Vanka step, inexact BSR,
+// residual + restriction): compile-time loops, the 16 x 16-thread tile geometry, LDS staging of
+// windows and constant tables, the XCD-aware tile numbering, and the prolongation fused into a
+// relaxation step (Sec. 3, eq. block_interp).
+#pragma once
+
+#include "kernels.h"
+#include "structure.h"
+
+#include <type_traits>
+#include <utility>
+
+#include <hip/hip_runtime.h>
+
+namespace biot {
+
+// sum over the 64 lanes of a wave (butterfly; every lane gets the same, order-fixed result)
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// compile-time loop: f(std::integral_constant<int, T>) for every T of the sequence
+template <int... Ts, typename F>
+__device__ __forceinline__ void static_for(std::integer_sequence<int, Ts...>, F&& f) {
+    (f(std::integral_constant<int, Ts>{}), ...);
+}
+
+constexpr int TB = 16;       // threads per block side
+constexpr int TPB = TB * TB; // threads per block
+constexpr int VT = TB - 1;   // vertices per tile side
+constexpr int VO = VT - 1;   // owned slots per tile side
+constexpr int XS = VT + 3;   // staged x_in: slots i0-2 .. i0+VT
+constexpr int RW = VT + 1;   // residual: slots i0-1 .. i0+VT-1 (one per thread)
+constexpr int KW = VT + 2;   // staged 1/K: slots i0-2 .. i0+VT-1
+static_assert(RW == TB, "one residual slot per thread");
+
+// Loads of NP planes of a W x W slot window starting at slot (s0i, s0j) (zero outside the
+// padded plane), kept in registers so that all loads of a phase are in flight together.
+template <typename T, int NP, int W>
+struct Window {
+    static constexpr int NV = NP * W * W;
+    static constexpr int NIT = (NV + TPB - 1) / TPB;
+    T v[NIT];
+    __device__ __forceinline__ void load(const T* __restrict__ src, long long plane, const Layout& L, int s0i,
+                                         int s0j, int tid) {
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int q = tid + it * TPB;
+            const int p = q / (W * W), rem = q - p * (W * W), bj = rem / W, ai = rem - bj * W;
+            const int si = s0i + ai, sj = s0j + bj;
+            v[it] = (q < NV && si <= L.n + 1 && sj <= L.n + 1) ? src[p * plane + slot_index(L, si, sj)] : (T)0;
+        }
+    }
+    __device__ __forceinline__ void store(T* dst, int tid) const {
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int q = tid + it * TPB;
+            if (q < NV) dst[q] = v[it];
+        }
+    }
+};
+
+// Tile of this block.  The dispatcher deals consecutive block ids to the 8 XCDs in turn; the
+// tiles are renumbered so that the blocks one XCD receives cover a contiguous band of tiles,
+// whose shared halo cache lines then meet in that XCD's L2.
+constexpr int NXCD = 8;
+__device__ __forceinline__ void xcd_tile(int& bx, int& by) {
+    const int nb = gridDim.x * gridDim.y;
+    const int b = blockIdx.y * gridDim.x + blockIdx.x;
+    const int xcd = b % NXCD, k = b / NXCD;
+    const int base = nb / NXCD, rem = nb % NXCD;
+    const int t = xcd * base + min(xcd, rem) + k;
+    by = t / gridDim.x;
+    bx = t - by * gridDim.x;
+}
+
+// A table of N <= TPB per-level constants (stencil coefficients, transfer weights) staged in
+// LDS together with the tile's windows: one vector load per thread, issued with the others.
+// Read from LDS (a broadcast), the constants cost no memory round trip inside the compute
+// phase, where scalar loads would wait on the scalar cache one batch at a time.
+template <typename T, int N>
+struct Table {
+    static_assert(N <= TPB, "one element per thread");
+    T v;
+    __device__ __forceinline__ void load(const T* __restrict__ src, int tid) { v = tid < N ? src[tid] : (T)0; }
+    __device__ __forceinline__ void store(T* dst, int tid) const {
+        if (tid < N) dst[tid] = v;
+    }
+};
+
+// (P x_c) at the fine DoF of type tf anchored at fine slot (2 I + pi, 2 J + pj), from the
+// coarse values xcs[t][J - Jc0 + .][I - Ic0 + .] (designated coarse triangle, structure.h)
+constexpr int PCW = (VT + 3) / 2 + 2;   // staged coarse window of the prolongation (11)
+
+template <typename T, int tf, int pi, int pj>
+__device__ __forceinline__ T prolong_value(const T (&xcs)[NTYPES][PCW][PCW], int ci, int cj,
+                                           const T* __restrict__ w) {
+    T acc = 0;
+    static_for(std::make_integer_sequence<int, fcount(tf)>{}, [&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        constexpr LDof c = ldof(fine_tri(tf, pi, pj), ffirst(tf) + q);
+        acc += w[widx(tf, pi, pj, q)] * xcs[c.t][cj + c.dj][ci + c.di];
+    });
+    return acc;
+}
+
+}  // namespace biot

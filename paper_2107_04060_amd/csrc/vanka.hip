@@ -1,0 +1,422 @@
+// Fused residual + additive Vanka relaxation step (Sec. 3.2.1) for gfx950: FP64 matrix-core
+// products for constant permeability, per-patch elimination otherwise.
+#include "tile.h"
+#include "patch_solve.h"
+
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+
+namespace biot {
+
+// =========================================================================================
+// additive Vanka (Sec. 3.2.1), fused with the residual
+// =========================================================================================
+// One step  x_out = x_in + omega sum_l V_l^T D_l A_l^{-1} V_l (b - A x_in)  per launch.  A block
+// of 16 x 16 threads handles a tile of VT x VT vertices starting at (i0, j0) and owns the slots
+// of its first VO x VO vertices.  Every thread forms the residual of one slot of
+// (i0-1 .. i0+VT)^2 from x_in staged in LDS on a two-slot halo; the threads of the VT x VT
+// vertices solve their patches; the owned slots gather the weighted corrections.  x_in and
+// x_out are different buffers (neighbouring tiles read x_in on the halo).  ZERO: x_in = 0, the
+// residual is b and x_in is not read.
+__device__ inline double vanka_weight(int t, int i, int j, int n) {
+    if (t <= T_UY) return 1.0;
+    if (t <= T_WD) return 0.5;
+    if (t == T_PL) return (i == 0 && j == 0) ? 0.5 : 1.0 / 3.0;
+    return (i == n - 1 && j == n - 1) ? 0.5 : 1.0 / 3.0;
+}
+
+// LDS offset of patch slot s relative to the residual entry of its vertex (rs[0][vj+1][vi+1])
+__host__ __device__ constexpr int pslot_off(int s) {
+    const int tt[PATCH] = {T_UX, T_UY, T_BH, T_BH, T_BV, T_BV, T_BD, T_BD, T_WH, T_WH,
+                           T_WV, T_WV, T_WD, T_WD, T_PL, T_PL, T_PL, T_PU, T_PU, T_PU};
+    const int ddi[PATCH] = {0, 0, -1, 0, 0, 0, -1, 0, -1, 0, 0, 0, -1, 0, 0, -1, 0, -1, -1, 0};
+    const int ddj[PATCH] = {0, 0, 0, 0, -1, 0, 0, -1, 0, 0, -1, 0, 0, -1, 0, 0, -1, -1, 0, -1};
+    return tt[s] * RW * RW + ddj[s] * RW + ddi[s];
+}
+
+// Class-inverse application on the matrix cores (FP64 16x16x4 MFMA), one wave per row of
+// the tile: out[a][p] = sum_b M[a][b] r[b][p] for the 16 patches p of a row (the patch index
+// is the column of the product, the 20 patch slots its reduction index; M padded to 32 rows).
+// Lane layouts of the instruction: A[i][k] in lane 16 k + i, B[k][j] in lane 16 k + j, and
+// the result D[i][j] in lane 16 (i % 4) + j, element i / 4 (rows l / 16 + 4 v).
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void mfma_class_frag(const double* M, int lane, double (&af)[2][5]) {
+    const int i = lane & 15, kq = lane >> 4;
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int ks = 0; ks < 5; ++ks) {
+            const int row = i + 16 * mb, col = kq + 4 * ks;
+            af[mb][ks] = row < PATCH ? M[row * PATCH + col] : 0.0;
+        }
+}
+
+// LDS of the fused step.  The staged x_in and the residual are dead once the patch residuals
+// are in registers; the patch corrections then reuse their space.
+template <typename T, bool UNIFORM, int NCLS, bool PROL>
+struct VankaLds {
+    union {
+        struct {
+            T xs[NTYPES][XS][XS];
+            T rs[NTYPES][RW][RW];
+        } a;
+        T so[PATCH][VT][VT];
+    } u;
+    T ks[UNIFORM ? 1 : 2][UNIFORM ? 1 : KW][UNIFORM ? 1 : KW];   // 1/K of the L, U triangles
+    double ms[UNIFORM ? NCLS : 1][UNIFORM ? PATCH * PATCH : 1];  // class inverses of the tile (FP64)
+    T xcs[PROL ? NTYPES : 1][PROL ? PCW : 1][PROL ? PCW : 1];   // coarse iterate (prolongation)
+    T cf[NSTENCIL];                                              // stencil coefficients
+    T pwl[PROL ? NPWEIGHTS : 1];                                 // prolongation weights
+};
+
+// PROL: the iterate is x_in + P x_c (prolongation of the coarse-grid correction, Sec. 3),
+// formed on the staged window; x_out = x_in + P x_c + omega (...).
+// One tile (bx, by) of the step, by the 16 x 16 threads of a block with LDS sh.
+template <typename T, bool UNIFORM, bool ZERO, int NCLS, bool PROL>
+__device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, const T* __restrict__ b,
+                                                T* __restrict__ x_out, const Layout& L, const T* __restrict__ kinv,
+                                                T kinv_s, const T* __restrict__ coef,
+                                                const DevPatchClass<double>* __restrict__ cls,
+                                                const double* __restrict__ wblk, const double* __restrict__ minv,
+                                                T omega, const T* __restrict__ xc, const Layout& Lc,
+                                                const T* __restrict__ pw, int bx, int by,
+                                                VankaLds<T, UNIFORM, NCLS, PROL>& sh) {
+    static_assert(!(PROL && ZERO), "the prolongation needs an iterate");
+    auto& xs = sh.u.a.xs;
+    auto& rs = sh.u.a.rs;
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TB + tx;
+    const int i0 = bx * VO, j0 = by * VO;
+    const int n = L.n;
+    // vertex classes of the tile (0 low edge, 1 interior, 2 high edge per direction); their
+    // matrices sit in ms[(cj - cjlo) * cw + (ci - cilo)]
+    const int cilo = i0 == 0 ? 0 : 1, cihi = (i0 + VT - 1 >= n) ? 2 : 1;
+    const int cjlo = j0 == 0 ? 0 : 1, cjhi = (j0 + VT - 1 >= n) ? 2 : 1;
+    const int cw = cihi - cilo + 1;
+    // ---- staging: b (and x_in, 1/K), class inverses ---------------------------------------------
+    {
+        // every load of the staging phase is issued before the first LDS store, so the tile
+        // waits for one memory latency, not one per class
+        constexpr int NM = PATCH * PATCH;
+        constexpr int NIT = (NM + TPB - 1) / TPB;
+        constexpr int NCL = UNIFORM ? NCLS : 1;
+        const int nc = cw * (cjhi - cjlo + 1);
+        double mv[NCL][NIT];
+        if constexpr (UNIFORM) {
+#pragma unroll
+            for (int k = 0; k < NCL; ++k) {
+                const int cidx = 3 * (cjlo + k / cw) + cilo + k % cw;
+#pragma unroll
+                for (int it = 0; it < NIT; ++it) {
+                    const int q = tid + it * TPB;
+                    mv[k][it] = (k < nc && q < NM) ? minv[cidx * NM + q] : 0.0;
+                }
+            }
+        }
+        Window<T, NTYPES, RW> wb;
+        wb.load(b, L.plane, L, i0 - 1, j0 - 1, tid);
+        Window<T, NTYPES, XS> wx;
+        if constexpr (!ZERO) wx.load(x_in, L.plane, L, i0 - 2, j0 - 2, tid);
+        Window<T, 2, KW> wk;
+        if constexpr (!UNIFORM) wk.load(kinv, L.plane, L, i0 - 2, j0 - 2, tid);
+        // coarse slots i0/2 - 1 .. i0/2 + PCW - 2 feed the fine window i0 - 2 .. i0 + VT + 1
+        Window<T, NTYPES, PCW> wc;
+        if constexpr (PROL) wc.load(xc, Lc.plane, Lc, i0 / 2 - 1, j0 / 2 - 1, tid);
+        Table<T, NSTENCIL> tcf;
+        if constexpr (!ZERO) tcf.load(coef, tid);
+        Table<T, NPWEIGHTS> tpw;
+        if constexpr (PROL) tpw.load(pw, tid);
+        if constexpr (!ZERO) tcf.store(sh.cf, tid);
+        if constexpr (PROL) tpw.store(sh.pwl, tid);
+        if constexpr (UNIFORM) {
+#pragma unroll
+            for (int k = 0; k < NCL; ++k)
+#pragma unroll
+                for (int it = 0; it < NIT; ++it) {
+                    const int q = tid + it * TPB;
+                    if (k < nc && q < NM) sh.ms[k][q] = mv[k][it];
+                }
+        }
+        wb.store(&rs[0][0][0], tid);
+        if constexpr (!ZERO) wx.store(&xs[0][0][0], tid);
+        if constexpr (!UNIFORM) wk.store(&sh.ks[0][0][0], tid);
+        if constexpr (PROL) wc.store(&sh.xcs[0][0][0], tid);
+    }
+    __syncthreads();
+    if constexpr (PROL) {
+        // x += P x_c on the staged window (free fine DoFs only): the thread of coarse window slot
+        // (ci, cj) fills its four fine slots (2 I + pi, 2 J + pj), parities known at compile time
+        constexpr int NCW = (XS + 1) / 2;        // coarse slots whose fine slots meet the window
+        if (tid < NCW * NCW) {
+            const int cj = tid / NCW, ci = tid - cj * NCW;
+            const int I = i0 / 2 - 1 + ci, J = j0 / 2 - 1 + cj;
+            static_for(std::make_integer_sequence<int, 4>{}, [&](auto pc) {
+                constexpr int pi = decltype(pc)::value & 1, pj = decltype(pc)::value >> 1;
+                const int a = 2 * ci + pi, bb = 2 * cj + pj;   // window index of fine slot (2I+pi, 2J+pj)
+                if (a < XS && bb < XS) {
+                    static_for(std::make_integer_sequence<int, NTYPES>{}, [&](auto tcn) {
+                        constexpr int tf = decltype(tcn)::value;
+                        if (dof_free(tf, 2 * I + pi, 2 * J + pj, n))
+                            xs[tf][bb][a] += prolong_value<T, tf, pi, pj>(sh.xcs, ci, cj, sh.pwl);
+                    });
+                }
+            });
+        }
+        __syncthreads();
+    }
+    // ---- residual r = b - A x_in of slot (i0-1+tx, j0-1+ty), zero on absent DoFs -----------------
+    if constexpr (!ZERO) {
+        const int si = i0 - 1 + tx, sj = j0 - 1 + ty;
+        const bool in = si <= n + 1 && sj <= n + 1;
+        T rv[NTYPES];
+        static_for(std::make_integer_sequence<int, NTYPES>{}, [&](auto tc) {
+            constexpr int t = decltype(tc)::value;
+            T acc = 0;
+            static_for(std::make_integer_sequence<int, SST.n[t]>{}, [&](auto ec) {
+                constexpr int e = decltype(ec)::value;
+                constexpr SEnt en = SST.e[t][e];
+                T cc = sh.cf[SST.off[t] + e];
+                if constexpr (en.kt >= 0) {
+                    if constexpr (UNIFORM)
+                        cc *= kinv_s;
+                    else
+                        cc *= sh.ks[en.kt][ty + 1 + en.kdj][tx + 1 + en.kdi];
+                }
+                acc += cc * xs[en.in][ty + 1 + en.dj][tx + 1 + en.di];
+            });
+            rv[t] = (in && dof_free(t, si, sj, n)) ? rs[t][ty][tx] - acc : (T)0;
+        });
+#pragma unroll
+        for (int t = 0; t < NTYPES; ++t) rs[t][ty][tx] = rv[t];
+        __syncthreads();
+    }
+    // ---- patch solves of the tile's vertices ----------------------------------------------------
+    const int vi = i0 + tx, vj = j0 + ty;
+    const bool patch = tx < VT && ty < VT;
+    T xown[NTYPES];
+#pragma unroll
+    for (int t = 0; t < NTYPES; ++t) xown[t] = (ZERO || !patch) ? (T)0 : xs[t][ty + 2][tx + 2];
+    // The patch arithmetic is FP64 for either storage precision T.
+    if constexpr (UNIFORM) {
+        // The products run over batches of up to 16 patches that share one class inverse: each
+        // tile row (its patches at interior-class columns), each boundary column of the tile
+        // (its patches at interior-class rows) and each corner patch.  Wave w takes rows
+        // w, w + 4, w + 8, w + 12 and the boundary batches dealt to it (the i-th present one goes
+        // to wave 3 - i % 4), so a boundary tile costs one product per batch, not one per class
+        // present in a row.
+        const int lane = tid & 63, wave = tid >> 6;
+        const int jl = lane & 15, kq = lane >> 4;
+        auto vcls = [n](int v) { return v == 0 ? 0 : (v == n ? 2 : 1); };
+        const int bcl = i0 == 0 ? 0 : -1, bcr = n - i0 < VT ? n - i0 : -1;   // tile columns of i = 0, n
+        const int brb = j0 == 0 ? 0 : -1, brt = n - j0 < VT ? n - j0 : -1;   // tile rows of j = 0, n
+        // boundary batches e in a fixed order: left, right column; corners (l,b), (r,b), (l,t),
+        // (r,t): tile column eti(e) and, for corners, tile row etj(e); -1 where the tile does
+        // not reach that boundary
+        auto eti = [&](int e) { return (e & 1) ? bcr : bcl; };
+        auto etj = [&](int e) { return e < 2 ? 0 : (e < 4 ? brb : brt); };
+        auto epr = [&](int e) { return eti(e) >= 0 && etj(e) >= 0; };
+        // batch slots of this wave: 0..3 rows, 4..5 boundary batches (e index, or -1)
+        int ex0 = -1, ex1 = -1;
+        {
+            int cnt = 0;
+#pragma unroll
+            for (int e = 0; e < 6; ++e)
+                if (epr(e)) {
+                    if (cnt == 3 - wave) ex0 = e;
+                    if (cnt == 7 - wave) ex1 = e;
+                    ++cnt;
+                }
+        }
+        // batch s: active, class (cj, ci), the lane's patch (pti, ptj) and whether it belongs to it
+        auto batch = [&](int s, bool& act, int& cj, int& ci, int& pti, int& ptj, bool& own) {
+            if (s < 4) {
+                ptj = wave + 4 * s;
+                pti = jl;
+                act = ptj < VT && j0 + ptj <= n;
+                cj = act ? vcls(j0 + ptj) : 1;
+                ci = 1;
+                own = act && pti < VT && i0 + pti <= n && vcls(i0 + pti) == 1;
+            } else {
+                const int e = s == 4 ? ex0 : ex1;
+                act = e >= 0;
+                if (e >= 0 && e < 2) {             // boundary column
+                    pti = eti(e);
+                    ptj = jl;
+                    ci = vcls(i0 + pti);
+                    cj = 1;
+                    own = ptj < VT && j0 + ptj <= n && vcls(j0 + ptj) == 1;
+                } else if (e >= 2) {               // corner patch, column 0 of the product
+                    pti = eti(e);
+                    ptj = etj(e);
+                    ci = vcls(i0 + pti);
+                    cj = vcls(j0 + ptj);
+                    own = jl == 0;
+                } else {
+                    pti = ptj = 0;
+                    ci = cj = 1;
+                    own = false;
+                }
+            }
+        };
+        // residuals of the batches' patches (B operand), read before the corrections overwrite
+        // the residual array; lanes outside a batch read any patch of the tile
+        double bf[6][5];
+#pragma unroll
+        for (int sb = 0; sb < 6; ++sb) {
+            bool act, own;
+            int cj, ci, pti, ptj;
+            batch(sb, act, cj, ci, pti, ptj, own);
+            const T* base = &rs[0][0][0] + (min(ptj, VT - 1) + 1) * RW + (min(pti, VT - 1) + 1);
+#pragma unroll
+            for (int ks = 0; ks < 5; ++ks) {
+                const int o = kq == 0 ? pslot_off(4 * ks) : kq == 1 ? pslot_off(4 * ks + 1)
+                            : kq == 2 ? pslot_off(4 * ks + 2) : pslot_off(4 * ks + 3);
+                bf[sb][ks] = act ? (double)base[o] : 0.0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int sb = 0; sb < 6; ++sb) {
+            bool act, own;
+            int cj, ci, pti, ptj;
+            batch(sb, act, cj, ci, pti, ptj, own);
+            if (!act) continue;                    // uniform over the wave
+            double cf[2][5];
+            mfma_class_frag(sh.ms[(cj - cjlo) * cw + (ci - cilo)], lane, cf);
+            v4d acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+#pragma unroll
+            for (int ks = 0; ks < 5; ++ks) {
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(cf[0][ks], bf[sb][ks], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(cf[1][ks], bf[sb][ks], acc1, 0, 0, 0);
+            }
+            // rows a = kq + 4 v + 16 mb of the lane's patch
+            if (own) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    sh.u.so[kq + 4 * v][ptj][pti] = (T)acc0[v];
+                    if (kq + 4 * v + 16 < PATCH) sh.u.so[kq + 4 * v + 16][ptj][pti] = (T)acc1[v];
+                }
+            }
+        }
+    } else {
+        // per-patch elimination (permeability varies from patch to patch)
+        double out[PATCH];
+#pragma unroll
+        for (int s = 0; s < PATCH; ++s) out[s] = 0;
+        if (patch && vi <= n && vj <= n) {
+            const int ci = vi == 0 ? 0 : (vi == n ? 2 : 1);
+            const int cj = vj == 0 ? 0 : (vj == n ? 2 : 1);
+            const DevPatchClass<double>& pc = cls[3 * cj + ci];
+            bool keep = false;
+#pragma unroll
+            for (int s = 0; s < 14; ++s) keep = keep || pc.present[s];
+            if (keep) {
+                double rr[PATCH];
+#pragma unroll
+                for (int s = 0; s < PATCH; ++s) {
+                    int t, di, dj;
+                    patch_slot(s, t, di, dj);
+                    rr[s] = (double)rs[t][ty + 1 + dj][tx + 1 + di];
+                }
+                double kv[6];
+#pragma unroll
+                for (int kq = 0; kq < 6; ++kq) {
+                    int ut, di, dj;
+                    star_tri(kq, ut, di, dj);
+                    kv[kq] = (double)sh.ks[ut][ty + 2 + dj][tx + 2 + di];
+                }
+                patch_solve<double>(rr, pc, kv, wblk, out, 1);
+            }
+        }
+        __syncthreads();
+        if (patch) {
+#pragma unroll
+            for (int s = 0; s < PATCH; ++s) sh.u.so[s][ty][tx] = (T)out[s];
+        }
+    }
+    __syncthreads();
+    // ---- weighted gather on the owned slots --------------------------------------------------------
+    if (tx < VO && ty < VO) {
+        const int si = i0 + tx, sj = j0 + ty;
+        if (si <= n && sj <= n) {
+            const auto& so = sh.u.so;
+            T c[NTYPES];
+            c[T_UX] = so[0][ty][tx];
+            c[T_UY] = so[1][ty][tx];
+            c[T_BH] = so[3][ty][tx] + so[2][ty][tx + 1];
+            c[T_BV] = so[5][ty][tx] + so[4][ty + 1][tx];
+            c[T_BD] = so[6][ty][tx + 1] + so[7][ty + 1][tx];
+            c[T_WH] = so[9][ty][tx] + so[8][ty][tx + 1];
+            c[T_WV] = so[11][ty][tx] + so[10][ty + 1][tx];
+            c[T_WD] = so[12][ty][tx + 1] + so[13][ty + 1][tx];
+            c[T_PL] = so[14][ty][tx] + so[15][ty][tx + 1] + so[16][ty + 1][tx];
+            c[T_PU] = so[17][ty + 1][tx + 1] + so[18][ty][tx + 1] + so[19][ty + 1][tx];
+            const long long s0 = slot_index(L, si, sj);
+#pragma unroll
+            for (int t = 0; t < NTYPES; ++t)
+                if (dof_free(t, si, sj, n))
+                    x_out[t * L.plane + s0] = xown[t] + omega * (T)vanka_weight(t, si, sj, n) * c[t];
+        }
+    }
+}
+
+template <typename T, bool UNIFORM, bool ZERO, int NCLS, bool PROL>
+__global__ __launch_bounds__(TPB) void k_vanka_step(const T* __restrict__ x_in, const T* __restrict__ b,
+                                                    T* __restrict__ x_out, Layout L, const T* __restrict__ kinv,
+                                                    T kinv_s, const T* __restrict__ coef,
+                                                    const DevPatchClass<double>* __restrict__ cls,
+                                                    const double* __restrict__ wblk,
+                                                    const double* __restrict__ minv, T omega,
+                                                    const T* __restrict__ xc, Layout Lc,
+                                                    const T* __restrict__ pw) {
+    __shared__ VankaLds<T, UNIFORM, NCLS, PROL> sh;
+    int bx, by;
+    xcd_tile(bx, by);
+    vanka_step_tile<T, UNIFORM, ZERO, NCLS, PROL>(x_in, b, x_out, L, kinv, kinv_s, coef, cls, wblk, minv, omega, xc,
+                                                  Lc, pw, bx, by, sh);
+}
+
+template <typename T, bool UNIFORM, bool ZERO, bool PROL>
+static void launch_vanka_step_t(const LevelView<T>& lv, const T* x_in, const T* b, T* x_out, T kinv_s, T omega,
+                                const T* xc, const Layout& Lc, const T* pw, const LaunchTiming* tm, hipStream_t st) {
+    dim3 blk(TB, TB);
+    dim3 grd((lv.L.n + 1 + VO - 1) / VO, (lv.L.n + 1 + VO - 1) / VO);
+    hipEvent_t e0 = tm ? tm->start : nullptr, e1 = tm ? tm->stop : nullptr;
+    // a tile spans at most two vertex classes per direction unless it covers the whole mesh
+    if (UNIFORM && lv.L.n + 1 <= VT)
+        hipExtLaunchKernelGGL((k_vanka_step<T, UNIFORM, ZERO, 9, PROL>), grd, blk, 0, st, e0, e1, 0, x_in, b, x_out,
+                              lv.L, lv.kinv, kinv_s, lv.coef, lv.cls, lv.wblk, lv.minv, omega, xc, Lc, pw);
+    else
+        hipExtLaunchKernelGGL((k_vanka_step<T, UNIFORM, ZERO, 4, PROL>), grd, blk, 0, st, e0, e1, 0, x_in, b, x_out,
+                              lv.L, lv.kinv, kinv_s, lv.coef, lv.cls, lv.wblk, lv.minv, omega, xc, Lc, pw);
+}
+
+template <typename T>
+void launch_vanka_step(const LevelView<T>& lv, const T* x_in, const T* b, T* x_out, bool uniform, T kinv_s,
+                       T omega, hipStream_t st, const T* xc, const Layout* Lc, const T* pw, const LaunchTiming* tm) {
+    const Layout lc = Lc ? *Lc : lv.L;
+    if (xc && !x_in) throw ArgError{"the prolongation needs an iterate"};
+    if (uniform) {
+        if (xc)
+            launch_vanka_step_t<T, true, false, true>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st);
+        else if (x_in)
+            launch_vanka_step_t<T, true, false, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st);
+        else
+            launch_vanka_step_t<T, true, true, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st);
+    } else {
+        if (xc)
+            launch_vanka_step_t<T, false, false, true>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st);
+        else if (x_in)
+            launch_vanka_step_t<T, false, false, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st);
+        else
+            launch_vanka_step_t<T, false, true, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st);
+    }
+}
+template void launch_vanka_step<double>(const LevelView<double>&, const double*, const double*, double*, bool,
+                                        double, double, hipStream_t, const double*, const Layout*, const double*,
+                                        const LaunchTiming*);
+template void launch_vanka_step<float>(const LevelView<float>&, const float*, const float*, float*, bool, float,
+                                       float, hipStream_t, const float*, const Layout*, const float*,
+                                       const LaunchTiming*);
+
+}  // namespace biot
