@@ -470,10 +470,10 @@ static void alloc_fp32(biot_ctx* c, hipStream_t st) {
 }
 
 // ---- FGMRES (Sec. 5.1), CGS2 Arnoldi, host Givens rotations ---------------------------------------
-// Layout of the Gram-Schmidt results (device hdev, host mirror hhost), restart m:
-//   [0, m+1]: pass-1 dots V_i . w (i <= j) and w . w;  [m+2, 2m+3]: pass-2 dots;
-//   2m+4: |w|^2 after pass 1;  2m+5: second-pass flag;  2m+6: |w|^2 after pass 2;  2m+7: scratch
-static int kslot_n1(int m) { return 2 * m + 4; }
+// Layout of the Gram-Schmidt results (device hdev, host mirror hhost), restart m, column j:
+//   [0, j+1]: pass-1 dots V_i . w (i <= j) and |w|^2 before pass 1;
+//   [m+2, m+j+3]: pass-2 dots and |w|^2 after pass 1;
+//   2m+5: second-pass flag;  2m+6: |w|^2 after pass 2;  2m+7: scratch
 static int kslot_flag(int m) { return 2 * m + 5; }
 static int kslot_n2(int m) { return 2 * m + 6; }
 static int kslot_tmp(int m) { return 2 * m + 7; }
@@ -566,21 +566,31 @@ static int fgmres(biot_ctx* c, const double* b_canon, double* x_canon, biot_solv
             // vector keeps the part that is new.  Its coefficients are h'_i = delta_ij - h_i and
             // the orthogonalized remainder is -h_{j+1,j} v_{j+1}.
             launch_apply<double>(l0.view<double>(), zj, vj, w, 1, st);
-            // CGS with a second pass when the first one cancels (|w| drops below |w_0| / sqrt 2)
-            launch_gs_dots(V, n, j + 1, w, n, part, hd, hh, nullptr, st);
-            launch_gs_update(w, V, n, j + 1, hd, n, part, hd + kslot_n1(M), hd + j + 1, hd + kslot_flag(M),
-                             hh + kslot_n1(M), nullptr, st);
-            launch_gs_dots(V, n, j + 1, w, n, part, hd + M + 2, hh + M + 2, hd + kslot_flag(M), st);
-            launch_gs_update(w, V, n, j + 1, hd + M + 2, n, part, hd + kslot_n2(M), nullptr, nullptr,
+            // CGS with a second pass when the first one cancels (|w| drops below |w_0| / sqrt 2).
+            // Pass one's update also forms pass two's dot products (V is read once for both), so
+            // the second pass costs one more update only when it runs.
+            const int nv = j + 1;
+            const bool fused = nv <= GS_FUSED;
+            launch_gs_dots(V, n, nv, w, n, part, hd, hh, nullptr, st);
+            if (fused) {
+                launch_gs_update_dots(w, V, n, nv, hd, n, part, hd + M + 2, hh + M + 2, hd + nv, hd + kslot_flag(M),
+                                      hh + kslot_flag(M), st);
+            } else {
+                launch_gs_update(w, V, n, nv, hd, n, part, hd + M + 2 + nv, hd + nv, hd + kslot_flag(M),
+                                 nullptr, nullptr, st);
+                launch_gs_dots(V, n, nv, w, n, part, hd + M + 2, hh + M + 2, hd + kslot_flag(M), st);
+                BIOT_HIP(hipMemcpyAsync(hh + kslot_flag(M), hd + kslot_flag(M), sizeof(double),
+                                        hipMemcpyDeviceToDevice, st));
+            }
+            launch_gs_update(w, V, n, nv, hd + M + 2, n, part, hd + kslot_n2(M), nullptr, nullptr,
                              hh + kslot_n2(M), hd + kslot_flag(M), st);
-            launch_normalize(V + (size_t)(j + 1) * n, w, n, hd + kslot_n1(M), hd + kslot_n2(M), hd + kslot_flag(M),
-                             st);
+            launch_normalize(V + (size_t)nv * n, w, n, hd + M + 2 + nv, hd + kslot_n2(M), hd + kslot_flag(M), st);
             check_stream_error();
             BIOT_HIP(hipStreamSynchronize(st));
             const bool second = hhost[kslot_flag(M)] != 0.0;
             for (int i = 0; i <= j; ++i)
                 H[(size_t)i * m + j] = (i == j ? 1.0 : 0.0) - (hhost[i] + (second ? hhost[M + 2 + i] : 0.0));
-            const double hn = std::sqrt(second ? hhost[kslot_n2(M)] : hhost[kslot_n1(M)]);
+            const double hn = std::sqrt(second ? hhost[kslot_n2(M)] : hhost[M + 2 + nv]);
             // v_{j+1} = w / |w| is minus the direction of the unshifted remainder
             H[(size_t)(j + 1) * m + j] = -hn;
             for (int i = 0; i <= j + 1; ++i)

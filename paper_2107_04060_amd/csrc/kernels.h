@@ -105,6 +105,13 @@ void launch_gs_dots(const double* V, long long ldv, int nv, const double* w, lon
 void launch_gs_update(double* w, const double* V, long long ldv, int nv, const double* h, long long n,
                       double* partial, double* norm2, const double* prev, double* flag, double* host,
                       const double* run_if, hipStream_t st);
+// the first pass's update fused with the second pass's dot products (nv <= GS_FUSED): w -= V h,
+// out[q] = V_q . w (q < nv) and out[nv] = w . w of the new w; flag = (out[nv] < 0.5 prev),
+// mirrored to host_flag; host: optional mirror of out.  Two launches.
+constexpr int GS_FUSED = 32;
+void launch_gs_update_dots(double* w, const double* V, long long ldv, int nv, const double* h, long long n,
+                           double* partial, double* out, double* host, const double* prev, double* flag,
+                           double* host_flag, hipStream_t st);
 // dst = src / sqrt(*na), or / sqrt(*nb) when sel != nullptr and *sel != 0
 void launch_normalize(double* dst, const double* src, long long n, const double* na, const double* nb,
                       const double* sel, hipStream_t st);

@@ -81,12 +81,60 @@ __global__ __launch_bounds__(256) void k_gs_update(double* __restrict__ w, const
     if (threadIdx.x == 0) partial[blockIdx.x] = wred[0] + wred[1] + wred[2] + wred[3];
 }
 
+// w -= sum_q h[q] V_q (q < nv <= GS_FUSED), with partial sums of V_q . w and w . w of the new w
+// (slots 0..nv-1 and nv): the dot products of the next Gram-Schmidt pass, taken while V is read
+// for this one.  Contiguous chunks per block; every element's V_q stay in registers.
+__global__ __launch_bounds__(256) void k_gs_update_dots(double* __restrict__ w, const double* __restrict__ V,
+                                                        long long ldv, int nv, const double* __restrict__ h,
+                                                        long long n, double* __restrict__ partial,
+                                                        const double* run_if) {
+    if (run_if && *run_if == 0.0) return;
+    __shared__ double red[4][GS_FUSED + 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long long chunk = (n + gridDim.x - 1) / gridDim.x;
+    const long long lo = (long long)blockIdx.x * chunk;
+    const long long hi = min(n, lo + chunk);
+    double hq[GS_FUSED], acc[GS_FUSED + 1];
+#pragma unroll
+    for (int q = 0; q < GS_FUSED; ++q) hq[q] = q < nv ? h[q] : 0.0;
+#pragma unroll
+    for (int q = 0; q <= GS_FUSED; ++q) acc[q] = 0;
+    for (long long e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+        double v[GS_FUSED];
+#pragma unroll
+        for (int q = 0; q < GS_FUSED; ++q) v[q] = q < nv ? V[(long long)q * ldv + e] : 0.0;
+        double sv = w[e];
+#pragma unroll
+        for (int q = 0; q < GS_FUSED; ++q) sv -= hq[q] * v[q];
+        w[e] = sv;
+#pragma unroll
+        for (int q = 0; q < GS_FUSED; ++q) acc[q] += v[q] * sv;
+        acc[GS_FUSED] += sv * sv;
+    }
+    // output slots: q < nv the dot products, nv the new w . w (accumulated in acc[GS_FUSED])
+#pragma unroll
+    for (int q = 0; q <= GS_FUSED; ++q) {
+        if (q < nv || q == GS_FUSED) {
+            const double t = wave_sum(acc[q]);
+            if (lane == 0) red[wave][q] = t;
+        }
+    }
+    __syncthreads();
+    const int q = threadIdx.x;
+    if (q < nv || q == GS_FUSED) {
+        const double r = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+        partial[(long long)(q == GS_FUSED ? nv : q) * gridDim.x + blockIdx.x] = r;
+    }
+}
+
 // out[q] = sum_b partial[q * np + b], one block per q (fixed order); host: optional mirror.
-// flag (block 0, optional): 1 when out[0] < 0.5 * prev (the Daniel-Gragg-Kaufman-Stewart test
-// for a second orthogonalization pass, eta = 1/sqrt(2)).
+// flag (optional): set by the block of q == flag_q to 1 when out[flag_q] < 0.5 * prev (the
+// Daniel-Gragg-Kaufman-Stewart test for a second orthogonalization pass, eta = 1/sqrt(2)), and
+// mirrored to *host_flag when given.
 __global__ __launch_bounds__(256) void k_gs_reduce(const double* __restrict__ partial, int np,
                                                    double* __restrict__ out, double* __restrict__ host,
                                                    const double* __restrict__ prev, double* __restrict__ flag,
+                                                   double* __restrict__ host_flag, int flag_q,
                                                    const double* run_if) {
     if (run_if && *run_if == 0.0) return;
     __shared__ double wred[4];
@@ -101,9 +149,10 @@ __global__ __launch_bounds__(256) void k_gs_reduce(const double* __restrict__ pa
         const double r = wred[0] + wred[1] + wred[2] + wred[3];
         out[q] = r;
         if (host) host[q] = r;
-        if (flag) {
-            *flag = (r < 0.5 * (*prev)) ? 1.0 : 0.0;
-            if (host) host[1] = *flag;
+        if (flag && q == flag_q) {
+            const double f = (r < 0.5 * (*prev)) ? 1.0 : 0.0;
+            *flag = f;
+            if (host_flag) *host_flag = f;
         }
     }
 }
@@ -112,7 +161,7 @@ void launch_gs_dots(const double* V, long long ldv, int nv, const double* w, lon
                     double* out, double* host, const double* run_if, hipStream_t st) {
     hipLaunchKernelGGL(k_gs_dots, dim3(DOT_BLOCKS), dim3(256), 0, st, V, ldv, nv, w, n, partial, run_if);
     hipLaunchKernelGGL(k_gs_reduce, dim3(nv + 1), dim3(256), 0, st, partial, DOT_BLOCKS, out, host, nullptr,
-                       nullptr, run_if);
+                       nullptr, nullptr, 0, run_if);
 }
 
 void launch_gs_update(double* w, const double* V, long long ldv, int nv, const double* h, long long n,
@@ -120,7 +169,16 @@ void launch_gs_update(double* w, const double* V, long long ldv, int nv, const d
                       const double* run_if, hipStream_t st) {
     hipLaunchKernelGGL(k_gs_update, dim3(UPD_BLOCKS), dim3(256), 0, st, w, V, ldv, nv, h, n, partial, run_if);
     hipLaunchKernelGGL(k_gs_reduce, dim3(1), dim3(256), 0, st, partial, UPD_BLOCKS, norm2, host, prev, flag,
-                       run_if);
+                       host ? host + 1 : nullptr, 0, run_if);
+}
+
+void launch_gs_update_dots(double* w, const double* V, long long ldv, int nv, const double* h, long long n,
+                           double* partial, double* out, double* host, const double* prev, double* flag,
+                           double* host_flag, hipStream_t st) {
+    if (nv < 1 || nv > GS_FUSED) throw ArgError{"fused Gram-Schmidt pass: 1 <= nv <= GS_FUSED"};
+    hipLaunchKernelGGL(k_gs_update_dots, dim3(DOT_BLOCKS), dim3(256), 0, st, w, V, ldv, nv, h, n, partial, nullptr);
+    hipLaunchKernelGGL(k_gs_reduce, dim3(nv + 1), dim3(256), 0, st, partial, DOT_BLOCKS, out, host, prev, flag,
+                       host_flag, nv, nullptr);
 }
 
 // dst = src / sqrt(*na), or / sqrt(*nb) when sel != nullptr and *sel != 0
