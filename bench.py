@@ -198,6 +198,35 @@ def adjoint_extra(binding, inputs, torch, batch=8):
             "gradient_over_forward": round(grad_ms / fwd_ms, 3)}
 
 
+def large_mesh_extra(binding, inputs, torch, n=2048, cycles=4):
+    """Finest-level kernel durations on a 2048 x 2048 mesh (41.9 M free DoFs, 10 levels, constant
+    K, nu = 0.49): V(2,2) Vanka cycles with HIP-event kernel timing, algorithmic bytes per launch
+    over the average launch time."""
+    lam, mu = inputs.lame(1.0, 0.49)
+    om, omj = inputs.relaxation_weights("vanka", 0.49, 1e-3)
+    s = binding.BiotSolver(n, lam, mu, alpha=1.0, M=inputs.biot_modulus(1.0), mu_f=1.0, tau=1.0, K=1e-3)
+    s.setup(levels=10, smoother="vanka", nu1=2, nu2=2, omega=om, omega_J=omj)
+    nf = inputs.n_free(n)
+    r = torch.rand(nf, dtype=torch.float64, device="cuda") * 2 - 1
+    s.vcycle(r)
+    torch.cuda.synchronize()
+    s.timing_start(0)
+    for _ in range(cycles):
+        s.vcycle(r)
+    t = s.timing_stop(0)
+    s.close()
+    vk = t["vanka_ms"] / t["vanka_launches"] * 1e-3
+    rr = t["resid_ms"] / t["resid_launches"] * 1e-3
+    vb = 3 * 8 * nf
+    rb = 2 * 8 * nf + 8 * inputs.n_free(n // 2)
+    return {"workload": "2048x2048, 10 levels, nu 0.49, K 1e-3, FP64, V(2,2) Vanka cycles",
+            "k_vanka_step": {"avg_launch_us": round(vk * 1e6, 1), "algorithmic_bytes_per_launch": vb,
+                             "achieved_GBs": round(vb / vk / 1e9, 1), "frac": round(vb / vk / 1e9 / HBM_PEAK_GBS, 3)},
+            "k_residual_restrict": {"avg_launch_us": round(rr * 1e6, 1), "algorithmic_bytes_per_launch": rb,
+                                    "achieved_GBs": round(rb / rr / 1e9, 1),
+                                    "frac": round(rb / rr / 1e9 / HBM_PEAK_GBS, 3)}}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -352,7 +381,8 @@ def main():
     extras = None
     if not args.no_extras and args.workload == "sweep256":
         extras = {"precision_form": precision_extra(binding, inputs, torch),
-                  "adjoint": adjoint_extra(binding, inputs, torch)}
+                  "adjoint": adjoint_extra(binding, inputs, torch),
+                  "kernels_2048": large_mesh_extra(binding, inputs, torch)}
     cpu = None
     if not args.no_cpu_baseline:
         r0 = runs[0]

@@ -38,16 +38,16 @@ static_assert(RW == TB, "one residual slot per thread");
 
 // Loads of NP planes of a W x W slot window starting at slot (s0i, s0j) (zero outside the
 // padded plane), kept in registers so that all loads of a phase are in flight together.
-template <typename T, int NP, int W>
+template <typename T, int NP, int W, int NT = TPB>
 struct Window {
     static constexpr int NV = NP * W * W;
-    static constexpr int NIT = (NV + TPB - 1) / TPB;
+    static constexpr int NIT = (NV + NT - 1) / NT;
     T v[NIT];
     __device__ __forceinline__ void load(const T* __restrict__ src, long long plane, const Layout& L, int s0i,
                                          int s0j, int tid) {
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
-            const int q = tid + it * TPB;
+            const int q = tid + it * NT;
             const int p = q / (W * W), rem = q - p * (W * W), bj = rem / W, ai = rem - bj * W;
             const int si = s0i + ai, sj = s0j + bj;
             v[it] = (q < NV && si <= L.n + 1 && sj <= L.n + 1) ? src[p * plane + slot_index(L, si, sj)] : (T)0;
@@ -56,7 +56,7 @@ struct Window {
     __device__ __forceinline__ void store(T* dst, int tid) const {
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
-            const int q = tid + it * TPB;
+            const int q = tid + it * NT;
             if (q < NV) dst[q] = v[it];
         }
     }
@@ -82,7 +82,7 @@ __device__ __forceinline__ void xcd_tile(int& bx, int& by) {
 // phase, where scalar loads would wait on the scalar cache one batch at a time.
 template <typename T, int N>
 struct Table {
-    static_assert(N <= TPB, "one element per thread");
+    static_assert(N <= TPB, "one element per thread (blocks have at least TPB threads)");
     T v;
     __device__ __forceinline__ void load(const T* __restrict__ src, int tid) { v = tid < N ? src[tid] : (T)0; }
     __device__ __forceinline__ void store(T* dst, int tid) const {

@@ -72,8 +72,17 @@ struct VankaLds {
 
 // PROL: the iterate is x_in + P x_c (prolongation of the coarse-grid correction, Sec. 3),
 // formed on the staged window; x_out = x_in + P x_c + omega (...).
-// One tile (bx, by) of the step, by the 16 x 16 threads of a block with LDS sh.
-template <typename T, bool UNIFORM, bool ZERO, int NCLS, bool PROL>
+// DoF types whose residual (rgroup) and whose gathered correction (ggroup) thread layer z of
+// NZ computes: with two layers each gets about half of the stencil entries and of the outputs.
+__host__ __device__ constexpr int rgroup(int t, int NZ) {
+    return NZ == 1 ? 0 : ((t == T_UX || t == T_UY || t == T_WH || t == T_WV) ? 0 : 1);
+}
+__host__ __device__ constexpr int ggroup(int t, int NZ) { return NZ == 1 ? 0 : (t <= T_BD ? 0 : 1); }
+
+// One tile (bx, by) of the step, by the 16 x 16 x NZ threads of a block with LDS sh.  Thread
+// (tx, ty, tz) stages and gathers for slot (tx, ty) the DoF types of its layer tz; the patch
+// products are spread over the block's 4 NZ waves.
+template <typename T, bool UNIFORM, bool ZERO, int NCLS, bool PROL, int NZ>
 __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, const T* __restrict__ b,
                                                 T* __restrict__ x_out, const Layout& L, const T* __restrict__ kinv,
                                                 T kinv_s, const T* __restrict__ coef,
@@ -85,7 +94,10 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
     static_assert(!(PROL && ZERO), "the prolongation needs an iterate");
     auto& xs = sh.u.a.xs;
     auto& rs = sh.u.a.rs;
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TB + tx;
+    static_assert(NZ == 1 || (NZ == 2 && UNIFORM), "two thread layers for constant K only");
+    constexpr int NTH = TPB * NZ;
+    const int tx = threadIdx.x, ty = threadIdx.y, tz = NZ > 1 ? (int)threadIdx.z : 0;
+    const int tid = (tz * TB + ty) * TB + tx;
     const int i0 = bx * VO, j0 = by * VO;
     const int n = L.n;
     // vertex classes of the tile (0 low edge, 1 interior, 2 high edge per direction); their
@@ -98,7 +110,7 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
         // every load of the staging phase is issued before the first LDS store, so the tile
         // waits for one memory latency, not one per class
         constexpr int NM = PATCH * PATCH;
-        constexpr int NIT = (NM + TPB - 1) / TPB;
+        constexpr int NIT = (NM + NTH - 1) / NTH;
         constexpr int NCL = UNIFORM ? NCLS : 1;
         const int nc = cw * (cjhi - cjlo + 1);
         double mv[NCL][NIT];
@@ -108,19 +120,19 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
                 const int cidx = 3 * (cjlo + k / cw) + cilo + k % cw;
 #pragma unroll
                 for (int it = 0; it < NIT; ++it) {
-                    const int q = tid + it * TPB;
+                    const int q = tid + it * NTH;
                     mv[k][it] = (k < nc && q < NM) ? minv[cidx * NM + q] : 0.0;
                 }
             }
         }
-        Window<T, NTYPES, RW> wb;
+        Window<T, NTYPES, RW, NTH> wb;
         wb.load(b, L.plane, L, i0 - 1, j0 - 1, tid);
-        Window<T, NTYPES, XS> wx;
+        Window<T, NTYPES, XS, NTH> wx;
         if constexpr (!ZERO) wx.load(x_in, L.plane, L, i0 - 2, j0 - 2, tid);
-        Window<T, 2, KW> wk;
+        Window<T, 2, KW, NTH> wk;
         if constexpr (!UNIFORM) wk.load(kinv, L.plane, L, i0 - 2, j0 - 2, tid);
         // coarse slots i0/2 - 1 .. i0/2 + PCW - 2 feed the fine window i0 - 2 .. i0 + VT + 1
-        Window<T, NTYPES, PCW> wc;
+        Window<T, NTYPES, PCW, NTH> wc;
         if constexpr (PROL) wc.load(xc, Lc.plane, Lc, i0 / 2 - 1, j0 / 2 - 1, tid);
         Table<T, NSTENCIL> tcf;
         if constexpr (!ZERO) tcf.load(coef, tid);
@@ -133,7 +145,7 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
             for (int k = 0; k < NCL; ++k)
 #pragma unroll
                 for (int it = 0; it < NIT; ++it) {
-                    const int q = tid + it * TPB;
+                    const int q = tid + it * NTH;
                     if (k < nc && q < NM) sh.ms[k][q] = mv[k][it];
                 }
         }
@@ -171,6 +183,7 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
         T rv[NTYPES];
         static_for(std::make_integer_sequence<int, NTYPES>{}, [&](auto tc) {
             constexpr int t = decltype(tc)::value;
+            if (rgroup(t, NZ) != tz) return;       // uniform over the wave
             T acc = 0;
             static_for(std::make_integer_sequence<int, SST.n[t]>{}, [&](auto ec) {
                 constexpr int e = decltype(ec)::value;
@@ -186,8 +199,10 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
             });
             rv[t] = (in && dof_free(t, si, sj, n)) ? rs[t][ty][tx] - acc : (T)0;
         });
-#pragma unroll
-        for (int t = 0; t < NTYPES; ++t) rs[t][ty][tx] = rv[t];
+        static_for(std::make_integer_sequence<int, NTYPES>{}, [&](auto tc) {
+            constexpr int t = decltype(tc)::value;
+            if (rgroup(t, NZ) == tz) rs[t][ty][tx] = rv[t];
+        });
         __syncthreads();
     }
     // ---- patch solves of the tile's vertices ----------------------------------------------------
@@ -195,15 +210,20 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
     const bool patch = tx < VT && ty < VT;
     T xown[NTYPES];
 #pragma unroll
-    for (int t = 0; t < NTYPES; ++t) xown[t] = (ZERO || !patch) ? (T)0 : xs[t][ty + 2][tx + 2];
+    for (int t = 0; t < NTYPES; ++t)
+        xown[t] = (ZERO || !patch || ggroup(t, NZ) != tz) ? (T)0 : xs[t][ty + 2][tx + 2];
     // The patch arithmetic is FP64 for either storage precision T.
     if constexpr (UNIFORM) {
         // The products run over batches of up to 16 patches that share one class inverse: each
         // tile row (its patches at interior-class columns), each boundary column of the tile
-        // (its patches at interior-class rows) and each corner patch.  Wave w takes rows
-        // w, w + 4, w + 8, w + 12 and the boundary batches dealt to it (the i-th present one goes
-        // to wave 3 - i % 4), so a boundary tile costs one product per batch, not one per class
-        // present in a row.
+        // (its patches at interior-class rows) and each corner patch.  Of the NW waves, wave w
+        // takes rows w, w + NW, ... and the boundary batches dealt to it (the i-th present one
+        // goes to wave NW - 1 - i % NW), so a boundary tile costs one product per batch, not one
+        // per class present in a row.
+        constexpr int NW = 4 * NZ;                 // waves of the block
+        constexpr int RPW = (VT + NW - 1) / NW;    // row batches per wave
+        constexpr int EPW = (6 + NW - 1) / NW;     // boundary batches per wave
+        constexpr int NB = RPW + EPW;
         const int lane = tid & 63, wave = tid >> 6;
         const int jl = lane & 15, kq = lane >> 4;
         auto vcls = [n](int v) { return v == 0 ? 0 : (v == n ? 2 : 1); };
@@ -215,29 +235,29 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
         auto eti = [&](int e) { return (e & 1) ? bcr : bcl; };
         auto etj = [&](int e) { return e < 2 ? 0 : (e < 4 ? brb : brt); };
         auto epr = [&](int e) { return eti(e) >= 0 && etj(e) >= 0; };
-        // batch slots of this wave: 0..3 rows, 4..5 boundary batches (e index, or -1)
+        // batch slots of this wave: 0..RPW-1 rows, then EPW boundary batches (e index, or -1)
         int ex0 = -1, ex1 = -1;
         {
             int cnt = 0;
 #pragma unroll
             for (int e = 0; e < 6; ++e)
                 if (epr(e)) {
-                    if (cnt == 3 - wave) ex0 = e;
-                    if (cnt == 7 - wave) ex1 = e;
+                    if (cnt == NW - 1 - wave) ex0 = e;
+                    if (EPW > 1 && cnt == 2 * NW - 1 - wave) ex1 = e;
                     ++cnt;
                 }
         }
         // batch s: active, class (cj, ci), the lane's patch (pti, ptj) and whether it belongs to it
         auto batch = [&](int s, bool& act, int& cj, int& ci, int& pti, int& ptj, bool& own) {
-            if (s < 4) {
-                ptj = wave + 4 * s;
+            if (s < RPW) {
+                ptj = wave + NW * s;
                 pti = jl;
                 act = ptj < VT && j0 + ptj <= n;
                 cj = act ? vcls(j0 + ptj) : 1;
                 ci = 1;
                 own = act && pti < VT && i0 + pti <= n && vcls(i0 + pti) == 1;
             } else {
-                const int e = s == 4 ? ex0 : ex1;
+                const int e = s == RPW ? ex0 : ex1;
                 act = e >= 0;
                 if (e >= 0 && e < 2) {             // boundary column
                     pti = eti(e);
@@ -260,9 +280,9 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
         };
         // residuals of the batches' patches (B operand), read before the corrections overwrite
         // the residual array; lanes outside a batch read any patch of the tile
-        double bf[6][5];
+        double bf[NB][5];
 #pragma unroll
-        for (int sb = 0; sb < 6; ++sb) {
+        for (int sb = 0; sb < NB; ++sb) {
             bool act, own;
             int cj, ci, pti, ptj;
             batch(sb, act, cj, ci, pti, ptj, own);
@@ -276,7 +296,7 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
         }
         __syncthreads();
 #pragma unroll
-        for (int sb = 0; sb < 6; ++sb) {
+        for (int sb = 0; sb < NB; ++sb) {
             bool act, own;
             int cj, ci, pti, ptj;
             batch(sb, act, cj, ci, pti, ptj, own);
@@ -341,27 +361,32 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
         if (si <= n && sj <= n) {
             const auto& so = sh.u.so;
             T c[NTYPES];
-            c[T_UX] = so[0][ty][tx];
-            c[T_UY] = so[1][ty][tx];
-            c[T_BH] = so[3][ty][tx] + so[2][ty][tx + 1];
-            c[T_BV] = so[5][ty][tx] + so[4][ty + 1][tx];
-            c[T_BD] = so[6][ty][tx + 1] + so[7][ty + 1][tx];
-            c[T_WH] = so[9][ty][tx] + so[8][ty][tx + 1];
-            c[T_WV] = so[11][ty][tx] + so[10][ty + 1][tx];
-            c[T_WD] = so[12][ty][tx + 1] + so[13][ty + 1][tx];
-            c[T_PL] = so[14][ty][tx] + so[15][ty][tx + 1] + so[16][ty + 1][tx];
-            c[T_PU] = so[17][ty + 1][tx + 1] + so[18][ty][tx + 1] + so[19][ty + 1][tx];
+            if (ggroup(T_BD, NZ) == tz) {          // layer of the displacement types
+                c[T_UX] = so[0][ty][tx];
+                c[T_UY] = so[1][ty][tx];
+                c[T_BH] = so[3][ty][tx] + so[2][ty][tx + 1];
+                c[T_BV] = so[5][ty][tx] + so[4][ty + 1][tx];
+                c[T_BD] = so[6][ty][tx + 1] + so[7][ty + 1][tx];
+            }
+            if (ggroup(T_PU, NZ) == tz) {          // layer of the Darcy and pressure types
+                c[T_WH] = so[9][ty][tx] + so[8][ty][tx + 1];
+                c[T_WV] = so[11][ty][tx] + so[10][ty + 1][tx];
+                c[T_WD] = so[12][ty][tx + 1] + so[13][ty + 1][tx];
+                c[T_PL] = so[14][ty][tx] + so[15][ty][tx + 1] + so[16][ty + 1][tx];
+                c[T_PU] = so[17][ty + 1][tx + 1] + so[18][ty][tx + 1] + so[19][ty + 1][tx];
+            }
             const long long s0 = slot_index(L, si, sj);
-#pragma unroll
-            for (int t = 0; t < NTYPES; ++t)
-                if (dof_free(t, si, sj, n))
+            static_for(std::make_integer_sequence<int, NTYPES>{}, [&](auto tc) {
+                constexpr int t = decltype(tc)::value;
+                if (ggroup(t, NZ) == tz && dof_free(t, si, sj, n))
                     x_out[t * L.plane + s0] = xown[t] + omega * (T)vanka_weight(t, si, sj, n) * c[t];
+            });
         }
     }
 }
 
-template <typename T, bool UNIFORM, bool ZERO, int NCLS, bool PROL>
-__global__ __launch_bounds__(TPB) void k_vanka_step(const T* __restrict__ x_in, const T* __restrict__ b,
+template <typename T, bool UNIFORM, bool ZERO, int NCLS, bool PROL, int NZ>
+__global__ __launch_bounds__(TPB * NZ, 2 * NZ) void k_vanka_step(const T* __restrict__ x_in, const T* __restrict__ b,
                                                     T* __restrict__ x_out, Layout L, const T* __restrict__ kinv,
                                                     T kinv_s, const T* __restrict__ coef,
                                                     const DevPatchClass<double>* __restrict__ cls,
@@ -372,23 +397,28 @@ __global__ __launch_bounds__(TPB) void k_vanka_step(const T* __restrict__ x_in, 
     __shared__ VankaLds<T, UNIFORM, NCLS, PROL> sh;
     int bx, by;
     xcd_tile(bx, by);
-    vanka_step_tile<T, UNIFORM, ZERO, NCLS, PROL>(x_in, b, x_out, L, kinv, kinv_s, coef, cls, wblk, minv, omega, xc,
-                                                  Lc, pw, bx, by, sh);
+    vanka_step_tile<T, UNIFORM, ZERO, NCLS, PROL, NZ>(x_in, b, x_out, L, kinv, kinv_s, coef, cls, wblk, minv, omega,
+                                                      xc, Lc, pw, bx, by, sh);
 }
+
+// thread layers of the constant-K step (two: 512 threads per tile, each phase split over twice
+// the waves; variable K keeps one layer, its per-patch eliminations already fill a layer)
+constexpr int VANKA_LAYERS = 2;
 
 template <typename T, bool UNIFORM, bool ZERO, bool PROL>
 static void launch_vanka_step_t(const LevelView<T>& lv, const T* x_in, const T* b, T* x_out, T kinv_s, T omega,
                                 const T* xc, const Layout& Lc, const T* pw, const LaunchTiming* tm, hipStream_t st) {
-    dim3 blk(TB, TB);
+    constexpr int NZ = UNIFORM ? VANKA_LAYERS : 1;
+    dim3 blk(TB, TB, NZ);
     dim3 grd((lv.L.n + 1 + VO - 1) / VO, (lv.L.n + 1 + VO - 1) / VO);
     hipEvent_t e0 = tm ? tm->start : nullptr, e1 = tm ? tm->stop : nullptr;
     // a tile spans at most two vertex classes per direction unless it covers the whole mesh
     if (UNIFORM && lv.L.n + 1 <= VT)
-        hipExtLaunchKernelGGL((k_vanka_step<T, UNIFORM, ZERO, 9, PROL>), grd, blk, 0, st, e0, e1, 0, x_in, b, x_out,
-                              lv.L, lv.kinv, kinv_s, lv.coef, lv.cls, lv.wblk, lv.minv, omega, xc, Lc, pw);
+        hipExtLaunchKernelGGL((k_vanka_step<T, UNIFORM, ZERO, 9, PROL, NZ>), grd, blk, 0, st, e0, e1, 0, x_in, b,
+                              x_out, lv.L, lv.kinv, kinv_s, lv.coef, lv.cls, lv.wblk, lv.minv, omega, xc, Lc, pw);
     else
-        hipExtLaunchKernelGGL((k_vanka_step<T, UNIFORM, ZERO, 4, PROL>), grd, blk, 0, st, e0, e1, 0, x_in, b, x_out,
-                              lv.L, lv.kinv, kinv_s, lv.coef, lv.cls, lv.wblk, lv.minv, omega, xc, Lc, pw);
+        hipExtLaunchKernelGGL((k_vanka_step<T, UNIFORM, ZERO, 4, PROL, NZ>), grd, blk, 0, st, e0, e1, 0, x_in, b,
+                              x_out, lv.L, lv.kinv, kinv_s, lv.coef, lv.cls, lv.wblk, lv.minv, omega, xc, Lc, pw);
 }
 
 template <typename T>
