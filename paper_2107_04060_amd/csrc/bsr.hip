@@ -86,14 +86,16 @@ constexpr int NU = 5;   // displacement DoF types ux, uy, bH, bV, bD
 
 // displacement-patch solves (8 x 8 class inverses, identity on absent DoFs) of the tile's
 // vertices from the displacement residual ru (slots i0-1 .. i0+VT-1): so[a][ty][tx]
-template <typename T>
+// With NZ thread layers, layer tz forms the outputs a = tz * 8 / NZ .. (tz + 1) * 8 / NZ - 1.
+template <typename T, int NZ>
 __device__ __forceinline__ void upatch_solves(const T (&ru)[NU][RW][RW], const T (&ui)[9][64], T (&so)[8][VT][VT],
-                                              int i0, int j0, int n, int tx, int ty) {
+                                              int i0, int j0, int n, int tx, int ty, int tz) {
+    constexpr int NA = 8 / NZ;
     if (tx >= VT || ty >= VT) return;
     const int vi = i0 + tx, vj = j0 + ty;
-    T out[8];
+    T out[NA];
 #pragma unroll
-    for (int a = 0; a < 8; ++a) out[a] = 0;
+    for (int a = 0; a < NA; ++a) out[a] = 0;
     if (vi <= n && vj <= n) {
         const int ci = vi == 0 ? 0 : (vi == n ? 2 : 1);
         const int cj = vj == 0 ? 0 : (vj == n ? 2 : 1);
@@ -106,15 +108,15 @@ __device__ __forceinline__ void upatch_solves(const T (&ru)[NU][RW][RW], const T
             rr[a] = ru[t][ty + 1 + dj][tx + 1 + di];
         }
 #pragma unroll
-        for (int a = 0; a < 8; ++a) {
+        for (int a = 0; a < NA; ++a) {
             T v = 0;
 #pragma unroll
-            for (int b2 = 0; b2 < 8; ++b2) v += M[a * 8 + b2] * rr[b2];
+            for (int b2 = 0; b2 < 8; ++b2) v += M[(tz * NA + a) * 8 + b2] * rr[b2];
             out[a] = v;
         }
     }
 #pragma unroll
-    for (int a = 0; a < 8; ++a) so[a][ty][tx] = out[a];
+    for (int a = 0; a < NA; ++a) so[tz * NA + a][ty][tx] = out[a];
 }
 
 // weighted sum of the patch corrections at owned slot (tx, ty): P1 in one patch, bubbles in
@@ -128,20 +130,24 @@ __device__ __forceinline__ void upatch_gather(const T (&so)[8][VT][VT], int tx, 
     du[T_BD] = (T)0.5 * (so[6][ty][tx + 1] + so[7][ty + 1][tx]);
 }
 
-template <typename T>
+template <typename T, int NTH>
 __device__ __forceinline__ void load_uinv(const T* __restrict__ uinv, T (&ui)[9][64], int tid) {
-    T v[3];
+    constexpr int NIT = (9 * 64 + NTH - 1) / NTH;
+    T v[NIT];
 #pragma unroll
-    for (int it = 0; it < 3; ++it) {
-        const int q = tid + it * TPB;
+    for (int it = 0; it < NIT; ++it) {
+        const int q = tid + it * NTH;
         v[it] = q < 9 * 64 ? uinv[q] : (T)0;
     }
 #pragma unroll
-    for (int it = 0; it < 3; ++it) {
-        const int q = tid + it * TPB;
+    for (int it = 0; it < NIT; ++it) {
+        const int q = tid + it * NTH;
         if (q < 9 * 64) (&ui[0][0])[q] = v[it];
     }
 }
+
+// layer of a displacement type in the displacement residual of the second half
+__host__ __device__ constexpr int ugroup(int t, int NZ) { return NZ == 1 ? 0 : (t <= T_UY ? 0 : 1); }
 
 template <typename T, bool UNIFORM, bool PROL>
 struct BsrFirstLds {
@@ -158,7 +164,7 @@ struct BsrFirstLds {
 // First half of a BSR step: r = b - A x (x: x_in, or x_in + P x_c with PROL, or 0 with ZERO),
 // t_u = F_u^{-1} r_u, t_w = r_w / (tau D_w).  Writes r and t on the owned slots, and with PROL
 // the prolongated iterate to x_pro (neighbouring tiles still read x_in on their halo).
-template <typename T, bool UNIFORM, bool ZERO, bool PROL>
+template <typename T, bool UNIFORM, bool ZERO, bool PROL, int NZ>
 __device__ __forceinline__ void bsr_first_tile(const T* __restrict__ x_in, T* __restrict__ x_pro,
                                                const T* __restrict__ b, T* __restrict__ r, T* __restrict__ t,
                                                const Layout& L, const T* __restrict__ kinv, T kinv_s,
@@ -167,23 +173,25 @@ __device__ __forceinline__ void bsr_first_tile(const T* __restrict__ x_in, T* __
                                                const T* __restrict__ pw, int bx, int by,
                                                BsrFirstLds<T, UNIFORM, PROL>& sh) {
     static_assert(!(PROL && ZERO), "the prolongation needs an iterate");
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TB + tx;
+    constexpr int NTH = TPB * NZ;
+    const int tx = threadIdx.x, ty = threadIdx.y, tz = NZ > 1 ? (int)threadIdx.z : 0;
+    const int tid = (tz * TB + ty) * TB + tx;
     const int i0 = bx * VO, j0 = by * VO;
     const int n = L.n;
     {
-        Window<T, NTYPES, RW> wb;
+        Window<T, NTYPES, RW, NTH> wb;
         wb.load(b, L.plane, L, i0 - 1, j0 - 1, tid);
-        Window<T, NTYPES, XS> wx;
+        Window<T, NTYPES, XS, NTH> wx;
         if constexpr (!ZERO) wx.load(x_in, L.plane, L, i0 - 2, j0 - 2, tid);
-        Window<T, 2, KW> wk;
+        Window<T, 2, KW, NTH> wk;
         if constexpr (!UNIFORM && !ZERO) wk.load(kinv, L.plane, L, i0 - 2, j0 - 2, tid);
-        Window<T, NTYPES, PCW> wc;
+        Window<T, NTYPES, PCW, NTH> wc;
         if constexpr (PROL) wc.load(xc, Lc.plane, Lc, i0 / 2 - 1, j0 / 2 - 1, tid);
         Table<T, NSTENCIL> tcf;
         if constexpr (!ZERO) tcf.load(coef, tid);
         Table<T, NPWEIGHTS> tpw;
         if constexpr (PROL) tpw.load(pw, tid);
-        load_uinv(uinv, sh.ui, tid);
+        load_uinv<T, NTH>(uinv, sh.ui, tid);
         if constexpr (!ZERO) tcf.store(sh.cf, tid);
         if constexpr (PROL) tpw.store(sh.pwl, tid);
         wb.store(&sh.rs[0][0][0], tid);
@@ -217,6 +225,7 @@ __device__ __forceinline__ void bsr_first_tile(const T* __restrict__ x_in, T* __
         T rv[NTYPES];
         static_for(std::make_integer_sequence<int, NTYPES>{}, [&](auto tcn) {
             constexpr int tt = decltype(tcn)::value;
+            if (rgroup(tt, NZ) != tz) return;      // uniform over the wave
             T acc = 0;
             static_for(std::make_integer_sequence<int, SST.n[tt]>{}, [&](auto ec) {
                 constexpr int e = decltype(ec)::value;
@@ -232,36 +241,42 @@ __device__ __forceinline__ void bsr_first_tile(const T* __restrict__ x_in, T* __
             });
             rv[tt] = (in && dof_free(tt, si, sj, n)) ? sh.rs[tt][ty][tx] - acc : (T)0;
         });
-#pragma unroll
-        for (int tt = 0; tt < NTYPES; ++tt) sh.rs[tt][ty][tx] = rv[tt];
+        static_for(std::make_integer_sequence<int, NTYPES>{}, [&](auto tcn) {
+            constexpr int tt = decltype(tcn)::value;
+            if (rgroup(tt, NZ) == tz) sh.rs[tt][ty][tx] = rv[tt];
+        });
         __syncthreads();
     }
-    upatch_solves<T>(reinterpret_cast<const T(&)[NU][RW][RW]>(sh.rs), sh.ui, sh.so, i0, j0, n, tx, ty);
+    upatch_solves<T, NZ>(reinterpret_cast<const T(&)[NU][RW][RW]>(sh.rs), sh.ui, sh.so, i0, j0, n, tx, ty, tz);
     __syncthreads();
     if (tx < VO && ty < VO) {
         const int si = i0 + tx, sj = j0 + ty;
         if (si <= n && sj <= n) {
             const long long s0 = slot_index(L, si, sj);
-            T du[NU];
-            upatch_gather<T>(sh.so, tx, ty, du);
+            if (ggroup(T_BD, NZ) == tz) {          // displacement types
+                T du[NU];
+                upatch_gather<T>(sh.so, tx, ty, du);
 #pragma unroll
-            for (int q = 0; q < NU; ++q) t[q * L.plane + s0] = dof_free(q, si, sj, n) ? du[q] : (T)0;
-#pragma unroll
-            for (int q = 0; q < 3; ++q)
-                t[(T_WH + q) * L.plane + s0] = sh.rs[T_WH + q][ty + 1][tx + 1] * d[(BSR_W + q) * L.plane + s0];
-#pragma unroll
-            for (int q = 0; q < NTYPES; ++q) r[q * L.plane + s0] = sh.rs[q][ty + 1][tx + 1];
-            if constexpr (PROL) {
-#pragma unroll
-                for (int q = 0; q < NTYPES; ++q)
-                    if (dof_free(q, si, sj, n)) x_pro[q * L.plane + s0] = sh.xs[q][ty + 2][tx + 2];
+                for (int q = 0; q < NU; ++q) t[q * L.plane + s0] = dof_free(q, si, sj, n) ? du[q] : (T)0;
             }
+            if (ggroup(T_WH, NZ) == tz) {          // Darcy types
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
+                    t[(T_WH + q) * L.plane + s0] = sh.rs[T_WH + q][ty + 1][tx + 1] * d[(BSR_W + q) * L.plane + s0];
+            }
+            static_for(std::make_integer_sequence<int, NTYPES>{}, [&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                if (ggroup(q, NZ) != tz) return;
+                r[q * L.plane + s0] = sh.rs[q][ty + 1][tx + 1];
+                if constexpr (PROL)
+                    if (dof_free(q, si, sj, n)) x_pro[q * L.plane + s0] = sh.xs[q][ty + 2][tx + 2];
+            });
         }
     }
 }
 
-template <typename T, bool UNIFORM, bool ZERO, bool PROL>
-__global__ __launch_bounds__(TPB) void k_bsr_first(const T* __restrict__ x_in, T* __restrict__ x_pro,
+template <typename T, bool UNIFORM, bool ZERO, bool PROL, int NZ>
+__global__ __launch_bounds__(TPB * NZ, 2 * NZ) void k_bsr_first(const T* __restrict__ x_in, T* __restrict__ x_pro,
                                                    const T* __restrict__ b,
                                                    T* __restrict__ r, T* __restrict__ t, Layout L,
                                                    const T* __restrict__ kinv, T kinv_s,
@@ -271,8 +286,8 @@ __global__ __launch_bounds__(TPB) void k_bsr_first(const T* __restrict__ x_in, T
     __shared__ BsrFirstLds<T, UNIFORM, PROL> sh;
     int bx, by;
     xcd_tile(bx, by);
-    bsr_first_tile<T, UNIFORM, ZERO, PROL>(x_in, x_pro, b, r, t, L, kinv, kinv_s, coef, uinv, d, xc, Lc, pw, bx, by,
-                                           sh);
+    bsr_first_tile<T, UNIFORM, ZERO, PROL, NZ>(x_in, x_pro, b, r, t, L, kinv, kinv_s, coef, uinv, d, xc, Lc, pw, bx,
+                                               by, sh);
 }
 
 // Second half: dp = omega_J (A_pu t_u + A_pw t_w - r_p) / diag(S) on the window the update
@@ -292,26 +307,28 @@ struct BsrSecondLds {
     T cf[NSTENCIL];
 };
 
-template <typename T, bool ZERO>
+template <typename T, bool ZERO, int NZ>
 __device__ __forceinline__ void bsr_second_tile(const T* __restrict__ r, const T* __restrict__ t, const T* x_src,
                                                 T* x, const Layout& L, const T* __restrict__ uinv,
                                                 const T* __restrict__ coef, const T* __restrict__ d, T omega,
                                                 T omega_J, int bx, int by, BsrSecondLds<T>& sh) {
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TB + tx;
+    constexpr int NTH = TPB * NZ;
+    const int tx = threadIdx.x, ty = threadIdx.y, tz = NZ > 1 ? (int)threadIdx.z : 0;
+    const int tid = (tz * TB + ty) * TB + tx;
     const int i0 = bx * VO, j0 = by * VO;
     const int n = L.n;
     {
-        Window<T, 8, TW> wt;
+        Window<T, 8, TW, NTH> wt;
         wt.load(t, L.plane, L, i0 - 2, j0 - 2, tid);
-        Window<T, 2, DW> wp;
+        Window<T, 2, DW, NTH> wp;
         wp.load(r + T_PL * L.plane, L.plane, L, i0 - 2, j0 - 2, tid);
-        Window<T, 2, DW> wd;
+        Window<T, 2, DW, NTH> wd;
         wd.load(d + BSR_S * L.plane, L.plane, L, i0 - 2, j0 - 2, tid);
-        Window<T, NU, RW> wr;
+        Window<T, NU, RW, NTH> wr;
         wr.load(r, L.plane, L, i0 - 1, j0 - 1, tid);
         Table<T, NSTENCIL> tcf;
         tcf.load(coef, tid);
-        load_uinv(uinv, sh.ui, tid);
+        load_uinv<T, NTH>(uinv, sh.ui, tid);
         tcf.store(sh.cf, tid);
         wt.store(&sh.ts[0][0][0], tid);
         wp.store(&sh.dp[0][0][0], tid);
@@ -320,7 +337,7 @@ __device__ __forceinline__ void bsr_second_tile(const T* __restrict__ r, const T
     }
     __syncthreads();
     // pressure update on slots (i0-2 .. i0+VT)^2; its columns reach t at +0 .. +1
-    for (int q = tid; q < DW * DW; q += TPB) {
+    for (int q = tid; q < DW * DW; q += NTH) {
         const int bb = q / DW, a = q - bb * DW;
         const int si = i0 - 2 + a, sj = j0 - 2 + bb;
         static_for(std::integer_sequence<int, T_PL, T_PU>{}, [&](auto tc) {
@@ -346,6 +363,7 @@ __device__ __forceinline__ void bsr_second_tile(const T* __restrict__ r, const T
         T rv[NU];
         static_for(std::make_integer_sequence<int, NU>{}, [&](auto tcn) {
             constexpr int tu = decltype(tcn)::value;
+            if (ugroup(tu, NZ) != tz) return;      // uniform over the wave
             T acc = 0;
             static_for(std::make_integer_sequence<int, SST.n[tu]>{}, [&](auto ec) {
                 constexpr int e = decltype(ec)::value;
@@ -355,21 +373,27 @@ __device__ __forceinline__ void bsr_second_tile(const T* __restrict__ r, const T
             rv[tu] = dof_free(tu, si, sj, n) ? sh.ru[tu][ty][tx] - acc : (T)0;
         });
         __syncthreads();
-#pragma unroll
-        for (int q = 0; q < NU; ++q) sh.ru[q][ty][tx] = rv[q];
+        static_for(std::make_integer_sequence<int, NU>{}, [&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            if (ugroup(q, NZ) == tz) sh.ru[q][ty][tx] = rv[q];
+        });
     }
     __syncthreads();
-    upatch_solves<T>(sh.ru, sh.ui, sh.so, i0, j0, n, tx, ty);
+    upatch_solves<T, NZ>(sh.ru, sh.ui, sh.so, i0, j0, n, tx, ty, tz);
     __syncthreads();
     if (tx < VO && ty < VO) {
         const int si = i0 + tx, sj = j0 + ty;
         if (si <= n && sj <= n) {
             const long long s0 = slot_index(L, si, sj);
-            T du[NU];
-            upatch_gather<T>(sh.so, tx, ty, du);
+            if (ggroup(T_BD, NZ) == tz) {          // displacement types
+                T du[NU];
+                upatch_gather<T>(sh.so, tx, ty, du);
 #pragma unroll
-            for (int q = 0; q < NU; ++q)
-                if (dof_free(q, si, sj, n)) x[q * L.plane + s0] = (ZERO ? (T)0 : x_src[q * L.plane + s0]) + omega * du[q];
+                for (int q = 0; q < NU; ++q)
+                    if (dof_free(q, si, sj, n))
+                        x[q * L.plane + s0] = (ZERO ? (T)0 : x_src[q * L.plane + s0]) + omega * du[q];
+            }
+            if (ggroup(T_PU, NZ) != tz) return;    // the Darcy and pressure types below
             static_for(std::integer_sequence<int, T_WH, T_WV, T_WD>{}, [&](auto tc) {
                 constexpr int tw = decltype(tc)::value;
                 T acc = 0;
@@ -389,26 +413,27 @@ __device__ __forceinline__ void bsr_second_tile(const T* __restrict__ r, const T
     }
 }
 
-template <typename T, bool ZERO>
-__global__ __launch_bounds__(TPB) void k_bsr_second(const T* __restrict__ r, const T* __restrict__ t,
+template <typename T, bool ZERO, int NZ>
+__global__ __launch_bounds__(TPB * NZ, 2 * NZ) void k_bsr_second(const T* __restrict__ r, const T* __restrict__ t,
                                                     const T* x_src, T* x, Layout L, const T* __restrict__ uinv,
                                                     const T* __restrict__ coef, const T* __restrict__ d,
                                                     T omega, T omega_J) {
     __shared__ BsrSecondLds<T> sh;
     int bx, by;
     xcd_tile(bx, by);
-    bsr_second_tile<T, ZERO>(r, t, x_src, x, L, uinv, coef, d, omega, omega_J, bx, by, sh);
+    bsr_second_tile<T, ZERO, NZ>(r, t, x_src, x, L, uinv, coef, d, omega, omega_J, bx, by, sh);
 }
 
 template <typename T>
 void launch_bsr_step(const LevelView<T>& lv, T* x, const T* b, T* r, T* t, bool x_is_zero, bool uniform, T kinv_s,
                      T omega, T omega_J, const T* xc, const Layout* Lc, const T* pw, T* xtmp, hipStream_t st) {
-    dim3 blk(TB, TB);
+    constexpr int NZ = 2;   // two thread layers: residual types, patch outputs and updates split
+    dim3 blk(TB, TB, NZ);
     dim3 grd((lv.L.n + 1 + VO - 1) / VO, (lv.L.n + 1 + VO - 1) / VO);
     const Layout lc = Lc ? *Lc : lv.L;
     if (xc && (x_is_zero || !xtmp || xtmp == x)) throw ArgError{"the prolongation needs an iterate and a buffer"};
 #define BIOT_BSR_FIRST(U, Z, P)                                                                                  \
-    hipLaunchKernelGGL((k_bsr_first<T, U, Z, P>), grd, blk, 0, st, x, xtmp, b, r, t, lv.L, lv.kinv, kinv_s,     \
+    hipLaunchKernelGGL((k_bsr_first<T, U, Z, P, NZ>), grd, blk, 0, st, x, xtmp, b, r, t, lv.L, lv.kinv, kinv_s, \
                        lv.coef, lv.uinv, lv.bsrd, xc, lc, pw)
     if (x_is_zero)
         BIOT_BSR_FIRST(true, true, false);
@@ -423,11 +448,11 @@ void launch_bsr_step(const LevelView<T>& lv, T* x, const T* b, T* r, T* t, bool 
 #undef BIOT_BSR_FIRST
     const T* xsrc = xc ? xtmp : x;
     if (x_is_zero)
-        hipLaunchKernelGGL((k_bsr_second<T, true>), grd, blk, 0, st, r, t, xsrc, x, lv.L, lv.uinv, lv.coef, lv.bsrd,
-                           omega, omega_J);
+        hipLaunchKernelGGL((k_bsr_second<T, true, NZ>), grd, blk, 0, st, r, t, xsrc, x, lv.L, lv.uinv, lv.coef,
+                           lv.bsrd, omega, omega_J);
     else
-        hipLaunchKernelGGL((k_bsr_second<T, false>), grd, blk, 0, st, r, t, xsrc, x, lv.L, lv.uinv, lv.coef, lv.bsrd,
-                           omega, omega_J);
+        hipLaunchKernelGGL((k_bsr_second<T, false, NZ>), grd, blk, 0, st, r, t, xsrc, x, lv.L, lv.uinv, lv.coef,
+                           lv.bsrd, omega, omega_J);
 }
 template void launch_bsr_step<double>(const LevelView<double>&, double*, const double*, double*, double*, bool, bool,
                                       double, double, double, const double*, const Layout*, const double*, double*,

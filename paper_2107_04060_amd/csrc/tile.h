@@ -62,6 +62,14 @@ struct Window {
     }
 };
 
+// Kernels with NZ thread layers of 16 x 16 split the DoF types of a slot among the layers:
+// rgroup(t) is the layer that forms the residual of type t (two layers get about half of the
+// 159 stencil entries each), ggroup(t) the layer that writes type t's output.
+__host__ __device__ constexpr int rgroup(int t, int NZ) {
+    return NZ == 1 ? 0 : ((t == T_UX || t == T_UY || t == T_WH || t == T_WV) ? 0 : 1);
+}
+__host__ __device__ constexpr int ggroup(int t, int NZ) { return NZ == 1 ? 0 : (t <= T_BD ? 0 : 1); }
+
 // Tile of this block.  The dispatcher deals consecutive block ids to the 8 XCDs in turn; the
 // tiles are renumbered so that the blocks one XCD receives cover a contiguous band of tiles,
 // whose shared halo cache lines then meet in that XCD's L2.

@@ -93,13 +93,15 @@ __device__ __forceinline__ T rr_row(const T (&rs)[NTYPES][RRW][RRW], int cx, int
     return acc;
 }
 
-template <typename T, bool UNIFORM>
+template <typename T, bool UNIFORM, int NZ>
 __device__ __forceinline__ void residual_restrict_tile(const T* __restrict__ x, const T* __restrict__ b,
                                                        T* __restrict__ rc, const Layout& Lf, const Layout& Lc,
                                                        const T* __restrict__ kinv, T kinv_s,
                                                        const T* __restrict__ coef, const T* __restrict__ w, int bx,
                                                        int by, ResRestrictLds<T, UNIFORM>& sh) {
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TB + tx;
+    constexpr int NTH = TPB * NZ;
+    const int tx = threadIdx.x, ty = threadIdx.y, tz = NZ > 1 ? (int)threadIdx.z : 0;
+    const int tid = (tz * TB + ty) * TB + tx;
     const int I0 = bx * RT, J0 = by * RT;
     const int f0i = 2 * I0 - 2, f0j = 2 * J0 - 2;   // fine origin of the residual window
     const int n = Lf.n;
@@ -107,11 +109,11 @@ __device__ __forceinline__ void residual_restrict_tile(const T* __restrict__ x, 
         // x on (f0 - 1 .. f0 + RRW)^2; slots below -2 lie outside the padded plane and only
         // feed residuals of slots outside the mesh (masked)
         constexpr int NV = NTYPES * RXW * RXW;
-        constexpr int NIT = (NV + TPB - 1) / TPB;
+        constexpr int NIT = (NV + NTH - 1) / NTH;
         T v[NIT];
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
-            const int q = tid + it * TPB;
+            const int q = tid + it * NTH;
             const int p = q / (RXW * RXW), rem = q - p * (RXW * RXW), bj = rem / RXW, ai = rem - bj * RXW;
             const int si = f0i - 1 + ai, sj = f0j - 1 + bj;
             v[it] = (q < NV && si >= -2 && sj >= -2 && si <= n + 1 && sj <= n + 1)
@@ -121,14 +123,15 @@ __device__ __forceinline__ void residual_restrict_tile(const T* __restrict__ x, 
         const int si = f0i + tx, sj = f0j + ty;
         const bool inb = si >= -2 && sj >= -2 && si <= n + 1 && sj <= n + 1;
 #pragma unroll
-        for (int t = 0; t < NTYPES; ++t) bv[t] = inb ? b[t * Lf.plane + slot_index(Lf, si, sj)] : (T)0;
+        for (int t = 0; t < NTYPES; ++t)
+            bv[t] = (inb && rgroup(t, NZ) == tz) ? b[t * Lf.plane + slot_index(Lf, si, sj)] : (T)0;
         Table<T, NSTENCIL> tcf;
         tcf.load(coef, tid);
-        T kv[UNIFORM ? 1 : (2 * RXW * RXW + TPB - 1) / TPB];
+        T kv[UNIFORM ? 1 : (2 * RXW * RXW + NTH - 1) / NTH];
         if constexpr (!UNIFORM) {
 #pragma unroll
-            for (int it = 0; it < (2 * RXW * RXW + TPB - 1) / TPB; ++it) {
-                const int q = tid + it * TPB;
+            for (int it = 0; it < (2 * RXW * RXW + NTH - 1) / NTH; ++it) {
+                const int q = tid + it * NTH;
                 const int p = q / (RXW * RXW), rem = q - p * (RXW * RXW), bj = rem / RXW, ai = rem - bj * RXW;
                 const int ki = f0i - 1 + ai, kj = f0j - 1 + bj;
                 kv[it] = (q < 2 * RXW * RXW && ki >= -2 && kj >= -2 && ki <= n + 1 && kj <= n + 1)
@@ -137,16 +140,17 @@ __device__ __forceinline__ void residual_restrict_tile(const T* __restrict__ x, 
         }
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
-            const int q = tid + it * TPB;
+            const int q = tid + it * NTH;
             if (q < NV) (&sh.xs[0][0][0])[q] = v[it];
         }
 #pragma unroll
-        for (int t = 0; t < NTYPES; ++t) sh.rs[t][ty][tx] = bv[t];
+        for (int t = 0; t < NTYPES; ++t)
+            if (rgroup(t, NZ) == tz) sh.rs[t][ty][tx] = bv[t];
         tcf.store(sh.cf, tid);
         if constexpr (!UNIFORM) {
 #pragma unroll
-            for (int it = 0; it < (2 * RXW * RXW + TPB - 1) / TPB; ++it) {
-                const int q = tid + it * TPB;
+            for (int it = 0; it < (2 * RXW * RXW + NTH - 1) / NTH; ++it) {
+                const int q = tid + it * NTH;
                 if (q < 2 * RXW * RXW) (&sh.ks[0][0][0])[q] = kv[it];
             }
         }
@@ -158,6 +162,7 @@ __device__ __forceinline__ void residual_restrict_tile(const T* __restrict__ x, 
         T rv[NTYPES];
         static_for(std::make_integer_sequence<int, NTYPES>{}, [&](auto tcn) {
             constexpr int t = decltype(tcn)::value;
+            if (rgroup(t, NZ) != tz) return;       // uniform over the wave
             T acc = 0;
             static_for(std::make_integer_sequence<int, SST.n[t]>{}, [&](auto ec) {
                 constexpr int e = decltype(ec)::value;
@@ -173,15 +178,16 @@ __device__ __forceinline__ void residual_restrict_tile(const T* __restrict__ x, 
             });
             rv[t] = dof_free(t, si, sj, n) ? sh.rs[t][ty][tx] - acc : (T)0;
         });
-        __syncthreads();
-#pragma unroll
-        for (int t = 0; t < NTYPES; ++t) sh.rs[t][ty][tx] = rv[t];
+        static_for(std::make_integer_sequence<int, NTYPES>{}, [&](auto tcn) {
+            constexpr int t = decltype(tcn)::value;
+            if (rgroup(t, NZ) == tz) sh.rs[t][ty][tx] = rv[t];
+        });
     }
     __syncthreads();
     // restriction of the tile's coarse slots: wave (q / 64) handles one coarse DoF type, so the
     // compile-time restriction row is uniform over the wave
     static_assert(RT * RT <= 64, "one coarse tile per wave");
-    for (int q = tid; q < NTYPES * 64; q += TPB) {
+    for (int q = tid; q < NTYPES * 64; q += NTH) {
         const int tc = q >> 6, slot = q & 63;
         const int cy = slot / RT, cx = slot - cy * RT;
         const int I = I0 + cx, J = J0 + cy;
@@ -195,29 +201,30 @@ __device__ __forceinline__ void residual_restrict_tile(const T* __restrict__ x, 
     }
 }
 
-template <typename T, bool UNIFORM>
-__global__ __launch_bounds__(TPB) void k_residual_restrict(const T* __restrict__ x, const T* __restrict__ b,
+template <typename T, bool UNIFORM, int NZ>
+__global__ __launch_bounds__(TPB * NZ) void k_residual_restrict(const T* __restrict__ x, const T* __restrict__ b,
                                                            T* __restrict__ rc, Layout Lf, Layout Lc,
                                                            const T* __restrict__ kinv, T kinv_s,
                                                            const T* __restrict__ coef, const T* __restrict__ w) {
     __shared__ ResRestrictLds<T, UNIFORM> sh;
     int bx, by;
     xcd_tile(bx, by);
-    residual_restrict_tile<T, UNIFORM>(x, b, rc, Lf, Lc, kinv, kinv_s, coef, w, bx, by, sh);
+    residual_restrict_tile<T, UNIFORM, NZ>(x, b, rc, Lf, Lc, kinv, kinv_s, coef, w, bx, by, sh);
 }
 
 template <typename T>
 void launch_residual_restrict(const LevelView<T>& lf, const Layout& Lc, const T* x, const T* b, T* rc,
                               bool uniform, T kinv_s, const T* w, hipStream_t st, const LaunchTiming* tm) {
-    dim3 blk(TB, TB);
+    constexpr int NZ = 2;   // two thread layers: the residual's types split between them
+    dim3 blk(TB, TB, NZ);
     dim3 grd((Lc.n + 1 + RT - 1) / RT, (Lc.n + 1 + RT - 1) / RT);
     hipEvent_t e0 = tm ? tm->start : nullptr, e1 = tm ? tm->stop : nullptr;
     if (uniform)
-        hipExtLaunchKernelGGL((k_residual_restrict<T, true>), grd, blk, 0, st, e0, e1, 0, x, b, rc, lf.L, Lc, lf.kinv,
-                              kinv_s, lf.coef, w);
+        hipExtLaunchKernelGGL((k_residual_restrict<T, true, NZ>), grd, blk, 0, st, e0, e1, 0, x, b, rc, lf.L, Lc,
+                              lf.kinv, kinv_s, lf.coef, w);
     else
-        hipExtLaunchKernelGGL((k_residual_restrict<T, false>), grd, blk, 0, st, e0, e1, 0, x, b, rc, lf.L, Lc, lf.kinv,
-                              kinv_s, lf.coef, w);
+        hipExtLaunchKernelGGL((k_residual_restrict<T, false, NZ>), grd, blk, 0, st, e0, e1, 0, x, b, rc, lf.L, Lc,
+                              lf.kinv, kinv_s, lf.coef, w);
 }
 template void launch_residual_restrict<double>(const LevelView<double>&, const Layout&, const double*,
                                                const double*, double*, bool, double, const double*, hipStream_t,

@@ -72,13 +72,6 @@ struct VankaLds {
 
 // PROL: the iterate is x_in + P x_c (prolongation of the coarse-grid correction, Sec. 3),
 // formed on the staged window; x_out = x_in + P x_c + omega (...).
-// DoF types whose residual (rgroup) and whose gathered correction (ggroup) thread layer z of
-// NZ computes: with two layers each gets about half of the stencil entries and of the outputs.
-__host__ __device__ constexpr int rgroup(int t, int NZ) {
-    return NZ == 1 ? 0 : ((t == T_UX || t == T_UY || t == T_WH || t == T_WV) ? 0 : 1);
-}
-__host__ __device__ constexpr int ggroup(int t, int NZ) { return NZ == 1 ? 0 : (t <= T_BD ? 0 : 1); }
-
 // One tile (bx, by) of the step, by the 16 x 16 x NZ threads of a block with LDS sh.  Thread
 // (tx, ty, tz) stages and gathers for slot (tx, ty) the DoF types of its layer tz; the patch
 // products are spread over the block's 4 NZ waves.
