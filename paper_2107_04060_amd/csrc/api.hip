@@ -577,7 +577,7 @@ static int fgmres(biot_ctx* c, const double* b_canon, double* x_canon, biot_solv
                                       hh + kslot_flag(M), st);
             } else {
                 launch_gs_update(w, V, n, nv, hd, n, part, hd + M + 2 + nv, hd + nv, hd + kslot_flag(M),
-                                 nullptr, nullptr, st);
+                                 hh + M + 2 + nv, nullptr, st);
                 launch_gs_dots(V, n, nv, w, n, part, hd + M + 2, hh + M + 2, hd + kslot_flag(M), st);
                 BIOT_HIP(hipMemcpyAsync(hh + kslot_flag(M), hd + kslot_flag(M), sizeof(double),
                                         hipMemcpyDeviceToDevice, st));
