@@ -379,7 +379,7 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
 }
 
 template <typename T, bool UNIFORM, bool ZERO, int NCLS, bool PROL, int NZ>
-__global__ __launch_bounds__(TPB * NZ, 2 * NZ) void k_vanka_step(const T* __restrict__ x_in, const T* __restrict__ b,
+__global__ __launch_bounds__(TPB * NZ, NZ == 2 ? 4 : 1) void k_vanka_step(const T* __restrict__ x_in, const T* __restrict__ b,
                                                     T* __restrict__ x_out, Layout L, const T* __restrict__ kinv,
                                                     T kinv_s, const T* __restrict__ coef,
                                                     const DevPatchClass<double>* __restrict__ cls,
