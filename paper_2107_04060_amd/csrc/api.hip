@@ -223,6 +223,9 @@ static void level_patch_data(Level& lv, bool uniform, double Kinv, hipStream_t s
         if (!placed) throw std::runtime_error("RT0 mass entry does not match the star edge pairs");
     }
     std::vector<DevPatchClass<double>> c64 = convert_classes<double>(cls);
+    // the variable-K smoother solves interior-tile patches with every slot taken as present
+    for (int a = 0; a < PATCH; ++a)
+        if (!c64[4].present[a]) throw std::runtime_error("interior patch class with an absent slot");
     upload(lv.cls64, c64, st);
     upload(lv.wblk64, wblk, st);
     if (uniform) {

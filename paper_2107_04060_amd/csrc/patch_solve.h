@@ -18,17 +18,17 @@ namespace biot {
 // packed lower triangle of a symmetric 6 x 6 matrix
 __host__ __device__ constexpr int tri6(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
 
+// Cholesky factor L (A = L L^T) in place, with 1 / L[j][j] stored on the diagonal so that the
+// triangular solves multiply instead of divide
 template <typename T>
-__host__ __device__ inline bool chol6p(T a[21]) {
+__host__ __device__ inline void chol6p(T a[21]) {
 #pragma unroll
     for (int jj = 0; jj < 6; ++jj) {
         T d = a[tri6(jj, jj)];
 #pragma unroll
         for (int k = 0; k < jj; ++k) d -= a[tri6(jj, k)] * a[tri6(jj, k)];
-        if (!(d > (T)0)) return false;
-        d = sqrt(d);
-        a[tri6(jj, jj)] = d;
-        const T inv = (T)1 / d;
+        const T inv = (T)1 / sqrt(d);
+        a[tri6(jj, jj)] = inv;
 #pragma unroll
         for (int ii = jj + 1; ii < 6; ++ii) {
             T s = a[tri6(ii, jj)];
@@ -37,36 +37,37 @@ __host__ __device__ inline bool chol6p(T a[21]) {
             a[tri6(ii, jj)] = s * inv;
         }
     }
-    return true;
 }
 
+// v <- L^-1 v
 template <typename T>
-__host__ __device__ inline void cholsolve6p(const T l[21], T v[6]) {
+__host__ __device__ inline void fwd6p(const T l[21], T v[6]) {
 #pragma unroll
     for (int ii = 0; ii < 6; ++ii) {
         T s = v[ii];
 #pragma unroll
         for (int k = 0; k < ii; ++k) s -= l[tri6(ii, k)] * v[k];
-        v[ii] = s / l[tri6(ii, ii)];
+        v[ii] = s * l[tri6(ii, ii)];
     }
+}
+
+// v <- L^-T v
+template <typename T>
+__host__ __device__ inline void bwd6p(const T l[21], T v[6]) {
 #pragma unroll
     for (int ii = 5; ii >= 0; --ii) {
         T s = v[ii];
 #pragma unroll
         for (int k = ii + 1; k < 6; ++k) s -= l[tri6(k, ii)] * v[k];
-        v[ii] = s / l[tri6(ii, ii)];
+        v[ii] = s * l[tri6(ii, ii)];
     }
 }
 
-// rr: patch residual (absent slots hold 0); kv: 1/K of the six star triangles;
-// wblk: RT0 mass blocks of the star triangles (1/K = 1); out[a * ostride], a = 0..19.
-// with_mean = false omits the star-mean pressure term (the deflated solve).
-template <typename T>
-__host__ __device__ inline void patch_solve(const T rr[PATCH], const DevPatchClass<T>& pc, const T kv[6],
-                                            const T* __restrict__ wblk, T* out, int ostride,
-                                            bool with_mean = true) {
-    // W: RT0 mass on the six star edges; star triangle k holds the edge pair star_wpair(k, .)
-    T w[21];
+// W: RT0 mass on the six star edges, star triangle k holding the edge pair star_wpair(k, .),
+// unit diagonal on absent edges; factored in place
+template <typename T, bool ALLP = false>
+__host__ __device__ inline void star_w_factor(const DevPatchClass<T>& pc, const T kv[6], const T* __restrict__ wblk,
+                                              T w[21]) {
 #pragma unroll
     for (int q = 0; q < 21; ++q) w[q] = 0;
 #pragma unroll
@@ -76,51 +77,64 @@ __host__ __device__ inline void patch_solve(const T rr[PATCH], const DevPatchCla
 #pragma unroll
             for (int q = 0; q <= p; ++q) {
                 const int a = star_wpair(kq, p), b = star_wpair(kq, q);
-                if (pc.present[8 + a] && pc.present[8 + b]) w[tri6(a, b)] += wblk[(kq * 2 + p) * 2 + q] * kv[kq];
+                if (ALLP || (pc.present[8 + a] && pc.present[8 + b])) w[tri6(a, b)] += wblk[(kq * 2 + p) * 2 + q] * kv[kq];
             }
 #pragma unroll
     for (int a = 0; a < 6; ++a)
-        if (!pc.present[8 + a]) w[tri6(a, a)] = 1;
+        if (!ALLP && !pc.present[8 + a]) w[tri6(a, a)] = 1;
     chol6p(w);
-    // y_w = W^-1 r_w
-    T yw[6];
+}
+
+// rr: patch residual (absent slots hold 0); kv: 1/K of the six star triangles;
+// wblk: RT0 mass blocks of the star triangles (1/K = 1); out[a * ostride], a = 0..19.
+// with_mean = false omits the star-mean pressure term (the deflated solve).
+// ALLP: every slot of the patch is present (interior class), known at compile time.
+// With W = L L^T, Q W^-1 Q^T = Z^T Z for Z = L^-1 Q^T, Q W^-1 r_w = Z^T zr for zr = L^-1 r_w, and
+// x_w = L^-T (zr - Z x_p): seven forward substitutions and one backward one, no divisions
+// beyond the two factorizations.
+template <typename T, bool ALLP = false>
+__host__ __device__ inline void patch_solve(const T rr[PATCH], const DevPatchClass<T>& pc, const T kv[6],
+                                            const T* __restrict__ wblk, T* out, int ostride,
+                                            bool with_mean = true) {
+    T w[21];
+    star_w_factor<T, ALLP>(pc, kv, wblk, w);
+    // zr = L^-1 r_w; z[q] = L^-1 (row q of Q)^T
+    T zr[6];
 #pragma unroll
-    for (int a = 0; a < 6; ++a) yw[a] = rr[8 + a];
-    cholsolve6p(w, yw);
-    // S = C + G + Q W^-1 Q^T (column by column), rhs = H^T r_u + Q y_w - r_p
+    for (int a = 0; a < 6; ++a) zr[a] = rr[8 + a];
+    fwd6p(w, zr);
+    T z[6][6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+#pragma unroll
+        for (int a = 0; a < 6; ++a) z[q][a] = pc.Q[q][a];
+        fwd6p(w, z[q]);
+    }
+    // S = C + G + Z^T Z, rhs = H^T r_u + Z^T zr - r_p
     T s[21], rhs[6];
 #pragma unroll
     for (int q1 = 0; q1 < 6; ++q1) {
 #pragma unroll
-        for (int q2 = 0; q2 <= q1; ++q2) s[tri6(q1, q2)] = pc.G[q1][q2];
+        for (int q2 = 0; q2 <= q1; ++q2) {
+            T v = pc.G[q1][q2];
+#pragma unroll
+            for (int a = 0; a < 6; ++a) v += z[q1][a] * z[q2][a];
+            s[tri6(q1, q2)] = v;
+        }
         s[tri6(q1, q1)] += pc.c[q1];
         T v = -rr[14 + q1];
 #pragma unroll
         for (int a = 0; a < 8; ++a) v += pc.H[a][q1] * rr[a];
 #pragma unroll
-        for (int a = 0; a < 6; ++a) v += pc.Q[q1][a] * yw[a];
+        for (int a = 0; a < 6; ++a) v += z[q1][a] * zr[a];
         rhs[q1] = v;
-    }
-#pragma unroll
-    for (int q2 = 0; q2 < 6; ++q2) {
-        T z[6];
-#pragma unroll
-        for (int a = 0; a < 6; ++a) z[a] = pc.Q[q2][a];
-        cholsolve6p(w, z);
-#pragma unroll
-        for (int q1 = q2; q1 < 6; ++q1) {
-            T v = 0;
-#pragma unroll
-            for (int a = 0; a < 6; ++a) v += pc.Q[q1][a] * z[a];
-            s[tri6(q1, q2)] += v;
-        }
     }
     // star-mean pressure in closed form; rank-one shift on the remaining system
     int k = 0;
     T sum_rp = 0, csum = 0, tr = 0, mrhs = 0;
 #pragma unroll
     for (int q = 0; q < 6; ++q)
-        if (pc.present[14 + q]) {
+        if (ALLP || pc.present[14 + q]) {
             ++k;
             sum_rp += rr[14 + q];
             csum += pc.c[q];
@@ -128,24 +142,26 @@ __host__ __device__ inline void patch_solve(const T rr[PATCH], const DevPatchCla
             mrhs += rhs[q];
         }
     const T gamma = -sum_rp / csum;
-    mrhs /= (T)k;
-    const T beta = tr / (T)(k * k);
+    const T rk = (T)1 / (T)k;
+    mrhs *= rk;
+    const T beta = tr * rk * rk;
 #pragma unroll
     for (int q1 = 0; q1 < 6; ++q1) {
 #pragma unroll
         for (int q2 = 0; q2 <= q1; ++q2) {
-            if (pc.present[14 + q1] && pc.present[14 + q2])
+            if (ALLP || (pc.present[14 + q1] && pc.present[14 + q2]))
                 s[tri6(q1, q2)] += beta;
             else
                 s[tri6(q1, q2)] = (q1 == q2) ? (T)1 : (T)0;
         }
-        rhs[q1] = pc.present[14 + q1] ? rhs[q1] - mrhs : (T)0;
+        rhs[q1] = (ALLP || pc.present[14 + q1]) ? rhs[q1] - mrhs : (T)0;
     }
     chol6p(s);
-    cholsolve6p(s, rhs);
+    fwd6p(s, rhs);
+    bwd6p(s, rhs);
     T xp[6];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) xp[q] = pc.present[14 + q] ? rhs[q] + (with_mean ? gamma : (T)0) : (T)0;
+    for (int q = 0; q < 6; ++q) xp[q] = (ALLP || pc.present[14 + q]) ? rhs[q] + (with_mean ? gamma : (T)0) : (T)0;
     // x_u = A^-1 r_u - H x_p
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
@@ -154,20 +170,20 @@ __host__ __device__ inline void patch_solve(const T rr[PATCH], const DevPatchCla
         for (int b = 0; b < 8; ++b) v += pc.Ainv[a][b] * rr[b];
 #pragma unroll
         for (int q = 0; q < 6; ++q) v -= pc.H[a][q] * xp[q];
-        out[a * ostride] = pc.present[a] ? v : (T)0;
+        out[a * ostride] = (ALLP || pc.present[a]) ? v : (T)0;
     }
-    // x_w = W^-1 (r_w - Q^T x_p)
+    // x_w = W^-1 (r_w - Q^T x_p) = L^-T (zr - sum_q x_p[q] z[q])
     T xw[6];
 #pragma unroll
     for (int a = 0; a < 6; ++a) {
-        T v = rr[8 + a];
+        T v = zr[a];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) v -= pc.Q[q][a] * xp[q];
+        for (int q = 0; q < 6; ++q) v -= z[q][a] * xp[q];
         xw[a] = v;
     }
-    cholsolve6p(w, xw);
+    bwd6p(w, xw);
 #pragma unroll
-    for (int a = 0; a < 6; ++a) out[(8 + a) * ostride] = pc.present[8 + a] ? xw[a] : (T)0;
+    for (int a = 0; a < 6; ++a) out[(8 + a) * ostride] = (ALLP || pc.present[8 + a]) ? xw[a] : (T)0;
 #pragma unroll
     for (int q = 0; q < 6; ++q) out[(14 + q) * ostride] = xp[q];
 }

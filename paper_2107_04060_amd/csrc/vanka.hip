@@ -65,6 +65,8 @@ struct VankaLds {
     } u;
     T ks[UNIFORM ? 1 : 2][UNIFORM ? 1 : KW][UNIFORM ? 1 : KW];   // 1/K of the L, U triangles
     double ms[UNIFORM ? NCLS : 1][UNIFORM ? PATCH * PATCH : 1];  // class inverses of the tile (FP64)
+    // patch classes of the tile (variable K)
+    std::conditional_t<UNIFORM, char, DevPatchClass<double>> pcs[UNIFORM ? 1 : NCLS];
     T xcs[PROL ? NTYPES : 1][PROL ? PCW : 1][PROL ? PCW : 1];   // coarse iterate (prolongation)
     T cf[NSTENCIL];                                              // stencil coefficients
     T pwl[PROL ? NPWEIGHTS : 1];                                 // prolongation weights
@@ -107,6 +109,18 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
         constexpr int NCL = UNIFORM ? NCLS : 1;
         const int nc = cw * (cjhi - cjlo + 1);
         double mv[NCL][NIT];
+        // variable K: the tile's patch classes, as words of 8 bytes
+        constexpr int NPW = sizeof(DevPatchClass<double>) / sizeof(double);
+        static_assert(NPW * sizeof(double) == sizeof(DevPatchClass<double>) && NPW <= NTH, "class staging");
+        constexpr int NPC = UNIFORM ? 1 : NCLS;
+        double pv[NPC];
+        if constexpr (!UNIFORM) {
+#pragma unroll
+            for (int k = 0; k < NPC; ++k) {
+                const int cidx = 3 * (cjlo + k / cw) + cilo + k % cw;
+                pv[k] = (k < nc && tid < NPW) ? reinterpret_cast<const double*>(cls + cidx)[tid] : 0.0;
+            }
+        }
         if constexpr (UNIFORM) {
 #pragma unroll
             for (int k = 0; k < NCL; ++k) {
@@ -141,6 +155,11 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
                     const int q = tid + it * NTH;
                     if (k < nc && q < NM) sh.ms[k][q] = mv[k][it];
                 }
+        }
+        if constexpr (!UNIFORM) {
+#pragma unroll
+            for (int k = 0; k < NPC; ++k)
+                if (k < nc && tid < NPW) reinterpret_cast<double*>(&sh.pcs[k])[tid] = pv[k];
         }
         wb.store(&rs[0][0][0], tid);
         if constexpr (!ZERO) wx.store(&xs[0][0][0], tid);
@@ -312,33 +331,39 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
             }
         }
     } else {
-        // per-patch elimination (permeability varies from patch to patch)
+        // per-patch elimination (permeability varies from patch to patch), class data from LDS.
+        // A tile that meets no boundary holds interior-class patches only, every slot present.
         double out[PATCH];
 #pragma unroll
         for (int s = 0; s < PATCH; ++s) out[s] = 0;
-        if (patch && vi <= n && vj <= n) {
-            const int ci = vi == 0 ? 0 : (vi == n ? 2 : 1);
-            const int cj = vj == 0 ? 0 : (vj == n ? 2 : 1);
-            const DevPatchClass<double>& pc = cls[3 * cj + ci];
-            bool keep = false;
+        const bool inner = cilo == 1 && cihi == 1 && cjlo == 1 && cjhi == 1;
+        const bool act = patch && vi <= n && vj <= n;
+        double rr[PATCH], kv[6];
+        if (act) {
 #pragma unroll
-            for (int s = 0; s < 14; ++s) keep = keep || pc.present[s];
-            if (keep) {
-                double rr[PATCH];
+            for (int s = 0; s < PATCH; ++s) {
+                int t, di, dj;
+                patch_slot(s, t, di, dj);
+                rr[s] = (double)rs[t][ty + 1 + dj][tx + 1 + di];
+            }
 #pragma unroll
-                for (int s = 0; s < PATCH; ++s) {
-                    int t, di, dj;
-                    patch_slot(s, t, di, dj);
-                    rr[s] = (double)rs[t][ty + 1 + dj][tx + 1 + di];
-                }
-                double kv[6];
+            for (int kq = 0; kq < 6; ++kq) {
+                int ut, di, dj;
+                star_tri(kq, ut, di, dj);
+                kv[kq] = (double)sh.ks[ut][ty + 2 + dj][tx + 2 + di];
+            }
+        }
+        if (act) {
+            if (inner) {
+                patch_solve<double, true>(rr, sh.pcs[0], kv, wblk, out, 1);
+            } else {
+                const int ci = vi == 0 ? 0 : (vi == n ? 2 : 1);
+                const int cj = vj == 0 ? 0 : (vj == n ? 2 : 1);
+                const DevPatchClass<double>& pc = sh.pcs[(cj - cjlo) * cw + (ci - cilo)];
+                bool keep = false;
 #pragma unroll
-                for (int kq = 0; kq < 6; ++kq) {
-                    int ut, di, dj;
-                    star_tri(kq, ut, di, dj);
-                    kv[kq] = (double)sh.ks[ut][ty + 2 + dj][tx + 2 + di];
-                }
-                patch_solve<double>(rr, pc, kv, wblk, out, 1);
+                for (int s = 0; s < 14; ++s) keep = keep || pc.present[s];
+                if (keep) patch_solve<double>(rr, pc, kv, wblk, out, 1);
             }
         }
         __syncthreads();
@@ -406,7 +431,7 @@ static void launch_vanka_step_t(const LevelView<T>& lv, const T* x_in, const T* 
     dim3 grd((lv.L.n + 1 + VO - 1) / VO, (lv.L.n + 1 + VO - 1) / VO);
     hipEvent_t e0 = tm ? tm->start : nullptr, e1 = tm ? tm->stop : nullptr;
     // a tile spans at most two vertex classes per direction unless it covers the whole mesh
-    if (UNIFORM && lv.L.n + 1 <= VT)
+    if (lv.L.n + 1 <= VT)
         hipExtLaunchKernelGGL((k_vanka_step<T, UNIFORM, ZERO, 9, PROL, NZ>), grd, blk, 0, st, e0, e1, 0, x_in, b,
                               x_out, lv.L, lv.kinv, kinv_s, lv.coef, lv.cls, lv.wblk, lv.minv, omega, xc, Lc, pw);
     else
