@@ -69,7 +69,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sweep256")
     ap.add_argument("--smoothers", default="vanka,bsr")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "fp32_patch"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--streams", type=int, default=8,
@@ -124,8 +124,10 @@ def _timed(fn):
 
 def precision_extra(binding, inputs, torch):
     """The 1024 x 1024 heterogeneous-permeability workload solved by the plain FP64 form and by the
-    precision form (FP32 vectors and residuals, FP64 patch arithmetic and Krylov), same right-hand
-    side, tolerance 1e-8 in the FP64 true residual; the relative difference of the two solutions."""
+    two precision forms: "fp32" (FP32 vectors and residuals, FP64 patch arithmetic and Krylov) and
+    "fp32_patch" (the variable-K Vanka eliminations in FP32 too); same right-hand side, tolerance
+    1e-8 in the FP64 true residual; per field, the relative difference of each FP32 form's
+    solution from the FP64 one."""
     import numpy as np
     w = inputs.workload("grf1024")
     c = w["cases"][0]
@@ -135,7 +137,8 @@ def precision_extra(binding, inputs, torch):
     b = torch.tensor(inputs.rhs_uniform(n, w["seed"]), dtype=torch.float64, device="cuda")
     res = {}
     sol = {}
-    for prec in ("fp64", "fp32"):
+    forms = ("fp64", "fp32", "fp32_patch")
+    for prec in forms:
         s = binding.BiotSolver(n, c["lam"], c["mu"], alpha=w["alpha"], M=w["M"], mu_f=w["mu_f"], tau=w["tau"], K=K)
         s.setup(levels=w["levels"], smoother="vanka", nu1=2, nu2=2, omega=om, omega_J=omj, precision=prec)
         s.solve(b, tol=1e-8, restart=30, maxit=300)                     # warm-up
@@ -147,14 +150,15 @@ def precision_extra(binding, inputs, torch):
     # per field (canonical order u, w, p); p with its mean removed, since the constant pressure
     # is the near-null mode that dominates |x| for a random right-hand side
     nu_, nw_ = 5 * n * n - 6 * n + 2, 3 * n * n - 2 * n
-    diff = {}
-    for name, a, z in (("u", 0, nu_), ("w", nu_, nu_ + nw_), ("p_mean_removed", nu_ + nw_, None)):
-        x32, x64 = sol["fp32"][a:z], sol["fp64"][a:z]
-        if name.startswith("p"):
-            x32, x64 = x32 - x32.mean(), x64 - x64.mean()
-        diff[name] = float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
-    res["rel_diff_fp32_vs_fp64_solution"] = diff
-    res["speedup_fp32_form"] = round(res["fp64"]["ms"] / res["fp32"]["ms"], 3)
+    for prec in forms[1:]:
+        diff = {}
+        for name, a, z in (("u", 0, nu_), ("w", nu_, nu_ + nw_), ("p_mean_removed", nu_ + nw_, None)):
+            x32, x64 = sol[prec][a:z], sol["fp64"][a:z]
+            if name.startswith("p"):
+                x32, x64 = x32 - x32.mean(), x64 - x64.mean()
+            diff[name] = float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
+        res[prec]["rel_diff_vs_fp64_solution"] = diff
+        res[prec]["speedup_vs_fp64"] = round(res["fp64"]["ms"] / res[prec]["ms"], 3)
     res["workload"] = "grf1024 (1024x1024, log10 K = -3 + GRF(0.1), nu 0.49, tau 1e-2, Vanka V(2,2))"
     return res
 

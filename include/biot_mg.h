@@ -66,6 +66,15 @@ extern "C" {
 #define BIOT_PREC_FP32_SMOOTHER 1 /* V-cycle vectors, residuals and transfers in FP32;
                                      patch solves and the coarsest solve in FP64 arithmetic;
                                      FGMRES and its true residual in FP64                  */
+#define BIOT_PREC_FP32_PATCH 2    /* as BIOT_PREC_FP32_SMOOTHER, and the variable-K Vanka
+                                     patch eliminations in FP32 arithmetic as well (faster:
+                                     half the registers).  Their error is FP32 roundoff times
+                                     the conditioning of the patch blocks: fine for moderate
+                                     permeability contrast, not for strong contrast (1e6)
+                                     with near-incompressibility, where the cycle stops
+                                     being a usable preconditioner; use
+                                     BIOT_PREC_FP32_SMOOTHER there.  Constant K and BSR are
+                                     as in BIOT_PREC_FP32_SMOOTHER.                        */
 
 typedef struct biot_ctx biot_ctx;
 
@@ -90,7 +99,7 @@ typedef struct {
     int nu1, nu2;       /* pre / post smoothing steps, 0..16                                 */
     double omega;       /* outer relaxation weight (Vanka and BSR)                           */
     double omega_J;     /* BSR: weighted-Jacobi weight on the approximate Schur complement   */
-    int precision;      /* BIOT_PREC_FP64 or BIOT_PREC_FP32_SMOOTHER                         */
+    int precision;      /* BIOT_PREC_FP64, BIOT_PREC_FP32_SMOOTHER or BIOT_PREC_FP32_PATCH    */
 } biot_mg_opts;
 
 /* FGMRES controls (in) and results (out). */

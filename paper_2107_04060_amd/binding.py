@@ -20,7 +20,7 @@ BIOT_ERR_OOM = -3
 BIOT_ERR_SINGULAR = -4
 BIOT_ERR_NAN = -5
 SMOOTHERS = {"vanka": 0, "bsr": 1}
-PRECISIONS = {"fp64": 0, "fp32": 1}
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_patch": 2}
 
 _lib = None
 

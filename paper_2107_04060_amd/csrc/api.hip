@@ -66,7 +66,9 @@ struct Level {
     DevBuf coef64, coef32;              // stencil coefficients in structure.h order
     DevBuf minv64;                      // full patch inverses per vertex class, uniform K (9 x 20 x 20)
     DevBuf kinv64, kinv32;              // 2 planes each
-    DevBuf cls64, wblk64;               // per-class elimination data, RT0 blocks (FP64 for both precisions)
+    DevBuf cls64, wblk64;               // per-class elimination data, RT0 blocks (FP64)
+    DevBuf cls32, wblk32;               // the same in FP32 (FP32 variable-K eliminations)
+    bool patch32 = false;               // FP32 variable-K eliminations on this level
     DevBuf uinv64, uinv32;              // displacement-patch inverses (BSR), 9 x 8 x 8
     DevBuf bsrd64, bsrd32;              // BSR diagonal data, 5 planes
     DevBuf x64, b64, r64, t64, x2_64;   // FP64 work vectors (padded); x64 / x2_64: iterate pair
@@ -84,6 +86,9 @@ LevelView<double> Level::view<double>() const {
     v.coef = coef64.as<double>();
     v.cls = cls64.as<DevPatchClass<double>>();
     v.wblk = wblk64.as<double>();
+    v.cls32 = cls32.as<DevPatchClass<float>>();
+    v.wblk32 = wblk32.as<float>();
+    v.patch32 = false;
     v.uinv = uinv64.as<double>();
     v.bsrd = bsrd64.as<double>();
     v.minv = minv64.as<double>();
@@ -97,6 +102,9 @@ LevelView<float> Level::view<float>() const {
     v.coef = coef32.as<float>();
     v.cls = cls64.as<DevPatchClass<double>>();
     v.wblk = wblk64.as<double>();
+    v.cls32 = cls32.as<DevPatchClass<float>>();
+    v.wblk32 = wblk32.as<float>();
+    v.patch32 = patch32;
     v.uinv = uinv32.as<float>();
     v.bsrd = bsrd32.as<float>();
     v.minv = minv64.as<double>();
@@ -228,6 +236,10 @@ static void level_patch_data(Level& lv, bool uniform, double Kinv, hipStream_t s
         if (!c64[4].present[a]) throw std::runtime_error("interior patch class with an absent slot");
     upload(lv.cls64, c64, st);
     upload(lv.wblk64, wblk, st);
+    std::vector<DevPatchClass<float>> c32 = convert_classes<float>(cls);
+    std::vector<float> wblk32(wblk.begin(), wblk.end());
+    upload(lv.cls32, c32, st);
+    upload(lv.wblk32, wblk32, st);
     if (uniform) {
         // inverse of each class's patch matrix, column by column (zero rows and columns on
         // absent DoFs; zero for the pressure-only corner classes)
@@ -754,7 +766,8 @@ int biot_setup_hierarchy(biot_ctx* c, const biot_mg_opts* o, void* stream) {
         require(o->smoother == BIOT_SMOOTHER_VANKA || o->smoother == BIOT_SMOOTHER_BSR, "unknown smoother");
         require(o->nu1 >= 0 && o->nu1 <= 16 && o->nu2 >= 0 && o->nu2 <= 16 && o->nu1 + o->nu2 >= 1,
                 "nu1, nu2 in [0, 16], nu1 + nu2 >= 1");
-        require(o->precision == BIOT_PREC_FP64 || o->precision == BIOT_PREC_FP32_SMOOTHER, "unknown precision");
+        require(o->precision == BIOT_PREC_FP64 || o->precision == BIOT_PREC_FP32_SMOOTHER ||
+                    o->precision == BIOT_PREC_FP32_PATCH, "unknown precision");
         require(std::isfinite(o->omega) && o->omega > 0, "omega must be positive");
         require(o->smoother != BIOT_SMOOTHER_BSR || (std::isfinite(o->omega_J) && o->omega_J > 0),
                 "BSR needs omega_J > 0");
@@ -783,7 +796,8 @@ int biot_setup_hierarchy(biot_ctx* c, const biot_mg_opts* o, void* stream) {
         for (auto& lv : c->levels)
             launch_convert(lv->kinv64.as<double>(), lv->kinv32.as<float>(), 2 * lv->L.plane, st);
         c->opts = *o;
-        if (o->precision == BIOT_PREC_FP32_SMOOTHER) alloc_fp32(c, st);
+        if (o->precision != BIOT_PREC_FP64) alloc_fp32(c, st);
+        for (auto& lp : c->levels) lp->patch32 = o->precision == BIOT_PREC_FP32_PATCH;
         if (o->smoother == BIOT_SMOOTHER_BSR) levels_bsr(c, st);
         coarse_setup(c, st);
         coarse_factor(c, st);

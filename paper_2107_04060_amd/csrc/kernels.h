@@ -22,8 +22,11 @@ struct LevelView {
     Layout L;
     const T* kinv;                 // 2 planes: 1/K of L and U triangles (padded)
     const T* coef;                 // operator stencil coefficients (structure.h order, device)
-    const DevPatchClass<double>* cls; // 9 Vanka classes (patch arithmetic is FP64 in both precisions)
+    const DevPatchClass<double>* cls; // 9 Vanka classes (variable-K elimination in FP64)
     const double* wblk;            // 6 x 2 x 2 RT0-mass blocks of the star triangles (1/K = 1)
+    const DevPatchClass<float>* cls32; // the same in FP32, for the FP32 elimination
+    const float* wblk32;
+    bool patch32;                  // variable-K Vanka eliminations in FP32 (FP32 vectors only)
     const T* uinv;                 // 9 x 8 x 8 displacement-patch inverses (BSR; identity on absent DoFs)
     const T* bsrd;                 // BSR diagonal data, 5 planes (k_bsr_wdiag / k_bsr_sdiag)
     const double* minv;            // 9 x 20 x 20 full patch inverses (uniform K), or null

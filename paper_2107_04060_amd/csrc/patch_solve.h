@@ -159,9 +159,12 @@ __host__ __device__ inline void patch_solve(const T rr[PATCH], const DevPatchCla
     chol6p(s);
     fwd6p(s, rhs);
     bwd6p(s, rhs);
+    // x_p = xp0 + gamma on the present pressures.  The star constant carries no flux
+    // (Bh^T 1 = Q^T 1 = 0), so the back-substitutions take the deflated part xp0 alone: the
+    // same values in exact arithmetic, without cancelling the often large gamma in rounding.
     T xp[6];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) xp[q] = (ALLP || pc.present[14 + q]) ? rhs[q] + (with_mean ? gamma : (T)0) : (T)0;
+    for (int q = 0; q < 6; ++q) xp[q] = (ALLP || pc.present[14 + q]) ? rhs[q] : (T)0;
     // x_u = A^-1 r_u - H x_p
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
@@ -185,7 +188,8 @@ __host__ __device__ inline void patch_solve(const T rr[PATCH], const DevPatchCla
 #pragma unroll
     for (int a = 0; a < 6; ++a) out[(8 + a) * ostride] = (ALLP || pc.present[8 + a]) ? xw[a] : (T)0;
 #pragma unroll
-    for (int q = 0; q < 6; ++q) out[(14 + q) * ostride] = xp[q];
+    for (int q = 0; q < 6; ++q)
+        out[(14 + q) * ostride] = (ALLP || pc.present[14 + q]) ? xp[q] + (with_mean ? gamma : (T)0) : (T)0;
 }
 
 }  // namespace biot

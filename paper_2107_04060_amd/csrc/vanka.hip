@@ -54,7 +54,7 @@ __device__ __forceinline__ void mfma_class_frag(const double* M, int lane, doubl
 
 // LDS of the fused step.  The staged x_in and the residual are dead once the patch residuals
 // are in registers; the patch corrections then reuse their space.
-template <typename T, bool UNIFORM, int NCLS, bool PROL>
+template <typename T, typename P, bool UNIFORM, int NCLS, bool PROL>
 struct VankaLds {
     union {
         struct {
@@ -66,7 +66,7 @@ struct VankaLds {
     T ks[UNIFORM ? 1 : 2][UNIFORM ? 1 : KW][UNIFORM ? 1 : KW];   // 1/K of the L, U triangles
     double ms[UNIFORM ? NCLS : 1][UNIFORM ? PATCH * PATCH : 1];  // class inverses of the tile (FP64)
     // patch classes of the tile (variable K)
-    std::conditional_t<UNIFORM, char, DevPatchClass<double>> pcs[UNIFORM ? 1 : NCLS];
+    std::conditional_t<UNIFORM, char, DevPatchClass<P>> pcs[UNIFORM ? 1 : NCLS];
     T xcs[PROL ? NTYPES : 1][PROL ? PCW : 1][PROL ? PCW : 1];   // coarse iterate (prolongation)
     T cf[NSTENCIL];                                              // stencil coefficients
     T pwl[PROL ? NPWEIGHTS : 1];                                 // prolongation weights
@@ -76,16 +76,17 @@ struct VankaLds {
 // formed on the staged window; x_out = x_in + P x_c + omega (...).
 // One tile (bx, by) of the step, by the 16 x 16 x NZ threads of a block with LDS sh.  Thread
 // (tx, ty, tz) stages and gathers for slot (tx, ty) the DoF types of its layer tz; the patch
-// products are spread over the block's 4 NZ waves.
-template <typename T, bool UNIFORM, bool ZERO, int NCLS, bool PROL, int NZ>
+// products are spread over the block's 4 NZ waves.  P: arithmetic of the variable-K patch
+// eliminations (FP64, or FP32 with FP32 storage on request).
+template <typename T, typename P, bool UNIFORM, bool ZERO, int NCLS, bool PROL, int NZ>
 __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, const T* __restrict__ b,
                                                 T* __restrict__ x_out, const Layout& L, const T* __restrict__ kinv,
                                                 T kinv_s, const T* __restrict__ coef,
-                                                const DevPatchClass<double>* __restrict__ cls,
-                                                const double* __restrict__ wblk, const double* __restrict__ minv,
+                                                const DevPatchClass<P>* __restrict__ cls,
+                                                const P* __restrict__ wblk, const double* __restrict__ minv,
                                                 T omega, const T* __restrict__ xc, const Layout& Lc,
                                                 const T* __restrict__ pw, int bx, int by,
-                                                VankaLds<T, UNIFORM, NCLS, PROL>& sh) {
+                                                VankaLds<T, P, UNIFORM, NCLS, PROL>& sh) {
     static_assert(!(PROL && ZERO), "the prolongation needs an iterate");
     auto& xs = sh.u.a.xs;
     auto& rs = sh.u.a.rs;
@@ -109,16 +110,16 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
         constexpr int NCL = UNIFORM ? NCLS : 1;
         const int nc = cw * (cjhi - cjlo + 1);
         double mv[NCL][NIT];
-        // variable K: the tile's patch classes, as words of 8 bytes
-        constexpr int NPW = sizeof(DevPatchClass<double>) / sizeof(double);
-        static_assert(NPW * sizeof(double) == sizeof(DevPatchClass<double>) && NPW <= NTH, "class staging");
+        // variable K: the tile's patch classes, as words of sizeof(P) bytes
+        constexpr int NPW = sizeof(DevPatchClass<P>) / sizeof(P);
+        static_assert(NPW * sizeof(P) == sizeof(DevPatchClass<P>) && NPW <= NTH, "class staging");
         constexpr int NPC = UNIFORM ? 1 : NCLS;
-        double pv[NPC];
+        P pv[NPC];
         if constexpr (!UNIFORM) {
 #pragma unroll
             for (int k = 0; k < NPC; ++k) {
                 const int cidx = 3 * (cjlo + k / cw) + cilo + k % cw;
-                pv[k] = (k < nc && tid < NPW) ? reinterpret_cast<const double*>(cls + cidx)[tid] : 0.0;
+                pv[k] = (k < nc && tid < NPW) ? reinterpret_cast<const P*>(cls + cidx)[tid] : (P)0;
             }
         }
         if constexpr (UNIFORM) {
@@ -159,7 +160,7 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
         if constexpr (!UNIFORM) {
 #pragma unroll
             for (int k = 0; k < NPC; ++k)
-                if (k < nc && tid < NPW) reinterpret_cast<double*>(&sh.pcs[k])[tid] = pv[k];
+                if (k < nc && tid < NPW) reinterpret_cast<P*>(&sh.pcs[k])[tid] = pv[k];
         }
         wb.store(&rs[0][0][0], tid);
         if constexpr (!ZERO) wx.store(&xs[0][0][0], tid);
@@ -224,7 +225,7 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
 #pragma unroll
     for (int t = 0; t < NTYPES; ++t)
         xown[t] = (ZERO || !patch || ggroup(t, NZ) != tz) ? (T)0 : xs[t][ty + 2][tx + 2];
-    // The patch arithmetic is FP64 for either storage precision T.
+    // Constant K: FP64 class inverses on the matrix cores for either storage precision T.
     if constexpr (UNIFORM) {
         // The products run over batches of up to 16 patches that share one class inverse: each
         // tile row (its patches at interior-class columns), each boundary column of the tile
@@ -331,39 +332,38 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
             }
         }
     } else {
-        // per-patch elimination (permeability varies from patch to patch), class data from LDS.
-        // A tile that meets no boundary holds interior-class patches only, every slot present.
-        double out[PATCH];
+        // per-patch elimination (permeability varies from patch to patch) in precision P, class
+        // data from LDS.  A tile that meets no boundary holds interior-class patches only, every
+        // slot present.
+        P out[PATCH];
 #pragma unroll
         for (int s = 0; s < PATCH; ++s) out[s] = 0;
         const bool inner = cilo == 1 && cihi == 1 && cjlo == 1 && cjhi == 1;
         const bool act = patch && vi <= n && vj <= n;
-        double rr[PATCH], kv[6];
+        P rr[PATCH], kv[6];
         if (act) {
 #pragma unroll
             for (int s = 0; s < PATCH; ++s) {
                 int t, di, dj;
                 patch_slot(s, t, di, dj);
-                rr[s] = (double)rs[t][ty + 1 + dj][tx + 1 + di];
+                rr[s] = (P)rs[t][ty + 1 + dj][tx + 1 + di];
             }
 #pragma unroll
             for (int kq = 0; kq < 6; ++kq) {
                 int ut, di, dj;
                 star_tri(kq, ut, di, dj);
-                kv[kq] = (double)sh.ks[ut][ty + 2 + dj][tx + 2 + di];
+                kv[kq] = (P)sh.ks[ut][ty + 2 + dj][tx + 2 + di];
             }
-        }
-        if (act) {
             if (inner) {
-                patch_solve<double, true>(rr, sh.pcs[0], kv, wblk, out, 1);
+                patch_solve<P, true>(rr, sh.pcs[0], kv, wblk, out, 1);
             } else {
                 const int ci = vi == 0 ? 0 : (vi == n ? 2 : 1);
                 const int cj = vj == 0 ? 0 : (vj == n ? 2 : 1);
-                const DevPatchClass<double>& pc = sh.pcs[(cj - cjlo) * cw + (ci - cilo)];
+                const DevPatchClass<P>& pc = sh.pcs[(cj - cjlo) * cw + (ci - cilo)];
                 bool keep = false;
 #pragma unroll
                 for (int s = 0; s < 14; ++s) keep = keep || pc.present[s];
-                if (keep) patch_solve<double>(rr, pc, kv, wblk, out, 1);
+                if (keep) patch_solve<P>(rr, pc, kv, wblk, out, 1);
             }
         }
         __syncthreads();
@@ -403,40 +403,62 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
     }
 }
 
-template <typename T, bool UNIFORM, bool ZERO, int NCLS, bool PROL, int NZ>
-__global__ __launch_bounds__(TPB * NZ, NZ == 2 ? 4 : 1) void k_vanka_step(const T* __restrict__ x_in, const T* __restrict__ b,
+template <typename T, typename P, bool UNIFORM, bool ZERO, int NCLS, bool PROL, int NZ>
+__global__ __launch_bounds__(TPB * NZ, NZ == 2 ? 4 : (sizeof(P) == 4 ? 2 : 1)) void k_vanka_step(const T* __restrict__ x_in, const T* __restrict__ b,
                                                     T* __restrict__ x_out, Layout L, const T* __restrict__ kinv,
                                                     T kinv_s, const T* __restrict__ coef,
-                                                    const DevPatchClass<double>* __restrict__ cls,
-                                                    const double* __restrict__ wblk,
+                                                    const DevPatchClass<P>* __restrict__ cls,
+                                                    const P* __restrict__ wblk,
                                                     const double* __restrict__ minv, T omega,
                                                     const T* __restrict__ xc, Layout Lc,
                                                     const T* __restrict__ pw) {
-    __shared__ VankaLds<T, UNIFORM, NCLS, PROL> sh;
+    __shared__ VankaLds<T, P, UNIFORM, NCLS, PROL> sh;
     int bx, by;
     xcd_tile(bx, by);
-    vanka_step_tile<T, UNIFORM, ZERO, NCLS, PROL, NZ>(x_in, b, x_out, L, kinv, kinv_s, coef, cls, wblk, minv, omega,
+    vanka_step_tile<T, P, UNIFORM, ZERO, NCLS, PROL, NZ>(x_in, b, x_out, L, kinv, kinv_s, coef, cls, wblk, minv, omega,
                                                       xc, Lc, pw, bx, by, sh);
 }
 
 // thread layers of the constant-K step (two: 512 threads per tile, each phase split over twice
-// the waves; variable K keeps one layer, its per-patch eliminations already fill a layer)
+// the waves; variable K keeps one layer, its per-patch eliminations already fill a layer: one
+// wave per SIMD in FP64, whose elimination takes over 256 registers, two in FP32)
 constexpr int VANKA_LAYERS = 2;
 
-template <typename T, bool UNIFORM, bool ZERO, bool PROL>
+template <typename T, typename P, bool UNIFORM, bool ZERO, bool PROL>
 static void launch_vanka_step_t(const LevelView<T>& lv, const T* x_in, const T* b, T* x_out, T kinv_s, T omega,
                                 const T* xc, const Layout& Lc, const T* pw, const LaunchTiming* tm, hipStream_t st) {
     constexpr int NZ = UNIFORM ? VANKA_LAYERS : 1;
     dim3 blk(TB, TB, NZ);
     dim3 grd((lv.L.n + 1 + VO - 1) / VO, (lv.L.n + 1 + VO - 1) / VO);
     hipEvent_t e0 = tm ? tm->start : nullptr, e1 = tm ? tm->stop : nullptr;
+    const DevPatchClass<P>* cls;
+    const P* wblk;
+    if constexpr (std::is_same_v<P, float>) {
+        cls = lv.cls32;
+        wblk = lv.wblk32;
+    } else {
+        cls = lv.cls;
+        wblk = lv.wblk;
+    }
     // a tile spans at most two vertex classes per direction unless it covers the whole mesh
     if (lv.L.n + 1 <= VT)
-        hipExtLaunchKernelGGL((k_vanka_step<T, UNIFORM, ZERO, 9, PROL, NZ>), grd, blk, 0, st, e0, e1, 0, x_in, b,
-                              x_out, lv.L, lv.kinv, kinv_s, lv.coef, lv.cls, lv.wblk, lv.minv, omega, xc, Lc, pw);
+        hipExtLaunchKernelGGL((k_vanka_step<T, P, UNIFORM, ZERO, 9, PROL, NZ>), grd, blk, 0, st, e0, e1, 0, x_in, b,
+                              x_out, lv.L, lv.kinv, kinv_s, lv.coef, cls, wblk, lv.minv, omega, xc, Lc, pw);
     else
-        hipExtLaunchKernelGGL((k_vanka_step<T, UNIFORM, ZERO, 4, PROL, NZ>), grd, blk, 0, st, e0, e1, 0, x_in, b,
-                              x_out, lv.L, lv.kinv, kinv_s, lv.coef, lv.cls, lv.wblk, lv.minv, omega, xc, Lc, pw);
+        hipExtLaunchKernelGGL((k_vanka_step<T, P, UNIFORM, ZERO, 4, PROL, NZ>), grd, blk, 0, st, e0, e1, 0, x_in, b,
+                              x_out, lv.L, lv.kinv, kinv_s, lv.coef, cls, wblk, lv.minv, omega, xc, Lc, pw);
+}
+
+// the ZERO / PROL forms of one (T, P, UNIFORM)
+template <typename T, typename P, bool UNIFORM>
+static void launch_vanka_forms(const LevelView<T>& lv, const T* x_in, const T* b, T* x_out, T kinv_s, T omega,
+                               const T* xc, const Layout& lc, const T* pw, const LaunchTiming* tm, hipStream_t st) {
+    if (xc)
+        launch_vanka_step_t<T, P, UNIFORM, false, true>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st);
+    else if (x_in)
+        launch_vanka_step_t<T, P, UNIFORM, false, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st);
+    else
+        launch_vanka_step_t<T, P, UNIFORM, true, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st);
 }
 
 template <typename T>
@@ -445,20 +467,16 @@ void launch_vanka_step(const LevelView<T>& lv, const T* x_in, const T* b, T* x_o
     const Layout lc = Lc ? *Lc : lv.L;
     if (xc && !x_in) throw ArgError{"the prolongation needs an iterate"};
     if (uniform) {
-        if (xc)
-            launch_vanka_step_t<T, true, false, true>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st);
-        else if (x_in)
-            launch_vanka_step_t<T, true, false, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st);
-        else
-            launch_vanka_step_t<T, true, true, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st);
-    } else {
-        if (xc)
-            launch_vanka_step_t<T, false, false, true>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st);
-        else if (x_in)
-            launch_vanka_step_t<T, false, false, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st);
-        else
-            launch_vanka_step_t<T, false, true, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st);
+        launch_vanka_forms<T, double, true>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st);
+        return;
     }
+    if constexpr (std::is_same_v<T, float>) {
+        if (lv.patch32) {
+            launch_vanka_forms<T, float, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st);
+            return;
+        }
+    }
+    launch_vanka_forms<T, double, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st);
 }
 template void launch_vanka_step<double>(const LevelView<double>&, const double*, const double*, double*, bool,
                                         double, double, hipStream_t, const double*, const Layout*, const double*,

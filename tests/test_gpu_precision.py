@@ -1,13 +1,18 @@
-"""The precision form: V-cycle vectors, residuals and transfers stored and computed in FP32;
-patch arithmetic (class inverses on the matrix cores, per-patch elimination, BSR pieces built
-in FP64) in FP64; FP64 FGMRES with an FP64 true residual.
+"""The precision forms.  "fp32": V-cycle vectors, residuals and transfers stored and computed
+in FP32, the patch arithmetic (constant-K class inverses on the FP64 matrix cores, variable-K
+eliminations, BSR pieces) in FP64.  "fp32_patch": the same with the variable-K Vanka
+eliminations in FP32 as well.  Both: FP64 FGMRES with an FP64 true residual.
 
 The contract is the outer solve: FGMRES with the FP32 cycle reaches the FP64 tolerance 1e-8
 in the true residual, recomputed on the CPU with the oracle's matrix, in at most a few more
 iterations than the FP64 form; the error against the oracle's direct solution is reported
-per field.  The cycle itself differs from the FP64 cycle by the rounding of the stored
-vectors (unit roundoff 6e-8) carried through the linear cycle; the bound 1e-4 allows an
-amplification of ~1700, the measured deviations are ~1e-5."""
+per field.  With FP64 patch arithmetic the cycle itself differs from the FP64 cycle by the
+rounding of the stored vectors (unit roundoff 6e-8) carried through the linear cycle; the
+bound 1e-4 allows an amplification of ~1700, the measured deviations are ~1e-5.  FP32
+eliminations carry their own error: FP32 roundoff times the conditioning of a patch's Darcy
+and Schur blocks, up to 1e-4 relative on interior patches and up to 0.1 on the Darcy block of
+some boundary classes against the FP64 elimination on the same class tables; through the same
+linear cycle the bound is 5e-2 (measured 1.8e-2), with the outer contract unchanged."""
 import numpy as np
 import pytest
 
@@ -35,24 +40,25 @@ def _t(a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
 
 
-@pytest.mark.parametrize("smoother,kind", [("vanka", "const"), ("vanka", "hetero"), ("bsr", "hetero")])
-def test_fp32_cycle_close_to_fp64_oracle(binding, smoother, kind):
+@pytest.mark.parametrize("smoother,kind,precision", [("vanka", "const", "fp32"), ("vanka", "hetero", "fp32"),
+                                                     ("bsr", "hetero", "fp32"), ("vanka", "hetero", "fp32_patch")])
+def test_fp32_cycle_close_to_fp64_oracle(binding, smoother, kind, precision):
     n, levels = 32, 4
     nu = 2 if smoother == "vanka" else 1
     K = perm(n, kind)
     s = solver(binding, torch, n, "small", K, levels=levels, smoother=smoother, nu=nu, omega=0.8,
-               omega_J=1.1, precision="fp32")
+               omega_J=1.1, precision=precision)
     H = Hierarchy(n, params("small"), K_tri=K, smoother=smoother, omega=0.8, omega_J=1.1, nu1=nu, nu2=nu,
                   levels=levels)
     r = inputs.rhs_uniform(n, 7)
     err = rel(s.vcycle(_t(r)).cpu().numpy(), H.vcycle(r))
-    print("  %s %s fp32 cycle rel diff %.2e" % (smoother, kind, err), flush=True)
-    assert err < 1e-4
+    print("  %s %s %s cycle rel diff %.2e" % (smoother, kind, precision, err), flush=True)
+    assert err < (5e-2 if precision == "fp32_patch" else 1e-4)
     s.close()
 
 
-@pytest.mark.parametrize("smoother", ["vanka", "bsr"])
-def test_fp32_solve_reaches_fp64_tolerance(binding, smoother):
+@pytest.mark.parametrize("smoother,precision", [("vanka", "fp32"), ("bsr", "fp32"), ("vanka", "fp32_patch")])
+def test_fp32_solve_reaches_fp64_tolerance(binding, smoother, precision):
     import scipy.sparse.linalg as spla
     n, levels = 64, 5
     nu = 2 if smoother == "vanka" else 1
@@ -61,7 +67,7 @@ def test_fp32_solve_reaches_fp64_tolerance(binding, smoother):
     K = perm(n, "hetero") * (1.0 if smoother == "vanka" else 1e-3)
     b = inputs.rhs_uniform(n, 2)
     res = {}
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", precision):
         s = solver(binding, torch, n, "stiff", K, levels=levels, smoother=smoother, nu=nu, omega=om,
                    omega_J=omj, precision=prec)
         x, info = s.solve(_t(b), tol=1e-8, restart=30, maxit=400)
@@ -70,12 +76,12 @@ def test_fp32_solve_reaches_fp64_tolerance(binding, smoother):
     asm = Assembly(Mesh(n), params("stiff"), K)
     A = asm.A
     xs = spla.spsolve(A.tocsc(), b)
-    x32, i32 = res["fp32"]
+    x32, i32 = res[precision]
     i64 = res["fp64"][1]
     assert i64["converged"] and i32["converged"]
     assert np.linalg.norm(b - A @ x32) <= 1e-8 * np.linalg.norm(b) * (1 + 1e-6)
     fields = dict(zip("uwp", asm.slices()))
     errs = {f: rel(x32[sl], xs[sl]) for f, sl in fields.items()}
-    print("  %s iters fp64 %d fp32 %d; fp32 error vs direct solve: u %.2e w %.2e p %.2e"
-          % (smoother, i64["iters"], i32["iters"], errs["u"], errs["w"], errs["p"]), flush=True)
+    print("  %s iters fp64 %d %s %d; %s error vs direct solve: u %.2e w %.2e p %.2e"
+          % (smoother, i64["iters"], precision, i32["iters"], precision, errs["u"], errs["w"], errs["p"]), flush=True)
     assert i32["iters"] <= i64["iters"] + 3
