@@ -201,22 +201,7 @@ __device__ __forceinline__ void bsr_first_tile(const T* __restrict__ x_in, T* __
     }
     __syncthreads();
     if constexpr (PROL) {
-        constexpr int NCW = (XS + 1) / 2;
-        if (tid < NCW * NCW) {
-            const int cj = tid / NCW, ci = tid - cj * NCW;
-            const int I = i0 / 2 - 1 + ci, J = j0 / 2 - 1 + cj;
-            static_for(std::make_integer_sequence<int, 4>{}, [&](auto pc) {
-                constexpr int pi = decltype(pc)::value & 1, pj = decltype(pc)::value >> 1;
-                const int a = 2 * ci + pi, bb = 2 * cj + pj;
-                if (a < XS && bb < XS) {
-                    static_for(std::make_integer_sequence<int, NTYPES>{}, [&](auto tcn) {
-                        constexpr int tf = decltype(tcn)::value;
-                        if (dof_free(tf, 2 * I + pi, 2 * J + pj, n))
-                            sh.xs[tf][bb][a] += prolong_value<T, tf, pi, pj>(sh.xcs, ci, cj, sh.pwl);
-                    });
-                }
-            });
-        }
+        prolong_window<T, NTH>(sh.xs, sh.xcs, sh.pwl, i0, j0, n, tid);
         __syncthreads();
     }
     if constexpr (!ZERO) {

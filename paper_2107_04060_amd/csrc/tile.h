@@ -114,4 +114,34 @@ __device__ __forceinline__ T prolong_value(const T (&xcs)[NTYPES][PCW][PCW], int
     return acc;
 }
 
+// x += P x_c on a staged fine window xs (fine slots i0 - 2 .. i0 + VT, free fine DoFs only) from
+// the staged coarse window xcs (coarse slots i0/2 - 1 ..).  Work item: one fine slot, all types.
+// The NTH threads are dealt to the four parity classes (2 I + pi, 2 J + pj) of the fine slots,
+// NTH / 4 to a class, so the parity, and with it the prolongation stencil, is uniform over a
+// wave and known at compile time.
+template <typename T, int NTH>
+__device__ __forceinline__ void prolong_window(T (&xs)[NTYPES][XS][XS], const T (&xcs)[NTYPES][PCW][PCW],
+                                               const T* __restrict__ pwl, int i0, int j0, int n, int tid) {
+    constexpr int NCW = (XS + 1) / 2;          // coarse slots whose fine slots meet the window
+    constexpr int TPC = NTH / 4;               // threads per parity class
+    static_assert(TPC % 64 == 0, "one parity class per wave");
+    const int pcls = tid / TPC, r0 = tid - pcls * TPC;
+    static_for(std::make_integer_sequence<int, 4>{}, [&](auto pc) {
+        constexpr int pi = decltype(pc)::value & 1, pj = decltype(pc)::value >> 1;
+        if (pcls != decltype(pc)::value) return;   // uniform over the wave
+        for (int r = r0; r < NCW * NCW; r += TPC) {
+            const int cj = r / NCW, ci = r - cj * NCW;
+            const int a = 2 * ci + pi, bb = 2 * cj + pj;   // window index of fine slot (2I+pi, 2J+pj)
+            if (a < XS && bb < XS) {
+                const int I = i0 / 2 - 1 + ci, J = j0 / 2 - 1 + cj;
+                static_for(std::make_integer_sequence<int, NTYPES>{}, [&](auto tcn) {
+                    constexpr int tf = decltype(tcn)::value;
+                    if (dof_free(tf, 2 * I + pi, 2 * J + pj, n))
+                        xs[tf][bb][a] += prolong_value<T, tf, pi, pj>(xcs, ci, cj, pwl);
+                });
+            }
+        }
+    });
+}
+
 }  // namespace biot

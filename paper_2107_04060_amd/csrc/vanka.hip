@@ -169,24 +169,7 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
     }
     __syncthreads();
     if constexpr (PROL) {
-        // x += P x_c on the staged window (free fine DoFs only): the thread of coarse window slot
-        // (ci, cj) fills its four fine slots (2 I + pi, 2 J + pj), parities known at compile time
-        constexpr int NCW = (XS + 1) / 2;        // coarse slots whose fine slots meet the window
-        if (tid < NCW * NCW) {
-            const int cj = tid / NCW, ci = tid - cj * NCW;
-            const int I = i0 / 2 - 1 + ci, J = j0 / 2 - 1 + cj;
-            static_for(std::make_integer_sequence<int, 4>{}, [&](auto pc) {
-                constexpr int pi = decltype(pc)::value & 1, pj = decltype(pc)::value >> 1;
-                const int a = 2 * ci + pi, bb = 2 * cj + pj;   // window index of fine slot (2I+pi, 2J+pj)
-                if (a < XS && bb < XS) {
-                    static_for(std::make_integer_sequence<int, NTYPES>{}, [&](auto tcn) {
-                        constexpr int tf = decltype(tcn)::value;
-                        if (dof_free(tf, 2 * I + pi, 2 * J + pj, n))
-                            xs[tf][bb][a] += prolong_value<T, tf, pi, pj>(sh.xcs, ci, cj, sh.pwl);
-                    });
-                }
-            });
-        }
+        prolong_window<T, NTH>(xs, sh.xcs, sh.pwl, i0, j0, n, tid);
         __syncthreads();
     }
     // ---- residual r = b - A x_in of slot (i0-1+tx, j0-1+ty), zero on absent DoFs -----------------
