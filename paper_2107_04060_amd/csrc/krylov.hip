@@ -81,13 +81,16 @@ __global__ __launch_bounds__(256) void k_gs_update(double* __restrict__ w, const
     if (threadIdx.x == 0) partial[blockIdx.x] = wred[0] + wred[1] + wred[2] + wred[3];
 }
 
-// w -= sum_q h[q] V_q (q < nv <= GS_FUSED), with partial sums of V_q . w and w . w of the new w
-// (slots 0..nv-1 and nv): the dot products of the next Gram-Schmidt pass, taken while V is read
-// for this one.  Contiguous chunks per block; every element's V_q stay in registers.
-__global__ __launch_bounds__(256) void k_gs_update_dots(double* __restrict__ w, const double* __restrict__ V,
-                                                        long long ldv, int nv, const double* __restrict__ h,
-                                                        long long n, double* __restrict__ partial,
-                                                        const double* run_if) {
+// Single pass over V_q (q < nv <= GS_FUSED) and w: partial sums of V_q . w (slots 0..nv-1) and
+// w . w (slot nv).  UPDATE: first w -= sum_q h[q] V_q, the sums then taken on the new w (the
+// dot products of the next Gram-Schmidt pass, taken while V is read for this one).  Contiguous
+// chunks per block; every element's V_q are loaded at once and stay in registers.
+constexpr int FUSED_BLOCKS = 512;          // blocks of the single-pass kernels
+template <bool UPDATE>
+__global__ __launch_bounds__(256) void k_gs_fused(double* __restrict__ w, const double* __restrict__ V,
+                                                  long long ldv, int nv, const double* __restrict__ h,
+                                                  long long n, double* __restrict__ partial,
+                                                  const double* run_if) {
     if (run_if && *run_if == 0.0) return;
     __shared__ double red[4][GS_FUSED + 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -96,7 +99,7 @@ __global__ __launch_bounds__(256) void k_gs_update_dots(double* __restrict__ w, 
     const long long hi = min(n, lo + chunk);
     double hq[GS_FUSED], acc[GS_FUSED + 1];
 #pragma unroll
-    for (int q = 0; q < GS_FUSED; ++q) hq[q] = q < nv ? h[q] : 0.0;
+    for (int q = 0; q < GS_FUSED; ++q) hq[q] = (UPDATE && q < nv) ? h[q] : 0.0;
 #pragma unroll
     for (int q = 0; q <= GS_FUSED; ++q) acc[q] = 0;
     for (long long e = lo + threadIdx.x; e < hi; e += blockDim.x) {
@@ -104,14 +107,16 @@ __global__ __launch_bounds__(256) void k_gs_update_dots(double* __restrict__ w, 
 #pragma unroll
         for (int q = 0; q < GS_FUSED; ++q) v[q] = q < nv ? V[(long long)q * ldv + e] : 0.0;
         double sv = w[e];
+        if constexpr (UPDATE) {
 #pragma unroll
-        for (int q = 0; q < GS_FUSED; ++q) sv -= hq[q] * v[q];
-        w[e] = sv;
+            for (int q = 0; q < GS_FUSED; ++q) sv -= hq[q] * v[q];
+            w[e] = sv;
+        }
 #pragma unroll
         for (int q = 0; q < GS_FUSED; ++q) acc[q] += v[q] * sv;
         acc[GS_FUSED] += sv * sv;
     }
-    // output slots: q < nv the dot products, nv the new w . w (accumulated in acc[GS_FUSED])
+    // output slots: q < nv the dot products, nv the w . w (accumulated in acc[GS_FUSED])
 #pragma unroll
     for (int q = 0; q <= GS_FUSED; ++q) {
         if (q < nv || q == GS_FUSED) {
@@ -159,8 +164,14 @@ __global__ __launch_bounds__(256) void k_gs_reduce(const double* __restrict__ pa
 
 void launch_gs_dots(const double* V, long long ldv, int nv, const double* w, long long n, double* partial,
                     double* out, double* host, const double* run_if, hipStream_t st) {
-    hipLaunchKernelGGL(k_gs_dots, dim3(DOT_BLOCKS), dim3(256), 0, st, V, ldv, nv, w, n, partial, run_if);
-    hipLaunchKernelGGL(k_gs_reduce, dim3(nv + 1), dim3(256), 0, st, partial, DOT_BLOCKS, out, host, nullptr,
+    // one pass over all vectors up to GS_FUSED of them, else groups of GSV per pass
+    const int np = nv <= GS_FUSED ? FUSED_BLOCKS : DOT_BLOCKS;
+    if (nv <= GS_FUSED)
+        hipLaunchKernelGGL(k_gs_fused<false>, dim3(np), dim3(256), 0, st, const_cast<double*>(w), V, ldv, nv,
+                           nullptr, n, partial, run_if);
+    else
+        hipLaunchKernelGGL(k_gs_dots, dim3(np), dim3(256), 0, st, V, ldv, nv, w, n, partial, run_if);
+    hipLaunchKernelGGL(k_gs_reduce, dim3(nv + 1), dim3(256), 0, st, partial, np, out, host, nullptr,
                        nullptr, nullptr, 0, run_if);
 }
 
@@ -176,8 +187,9 @@ void launch_gs_update_dots(double* w, const double* V, long long ldv, int nv, co
                            double* partial, double* out, double* host, const double* prev, double* flag,
                            double* host_flag, hipStream_t st) {
     if (nv < 1 || nv > GS_FUSED) throw ArgError{"fused Gram-Schmidt pass: 1 <= nv <= GS_FUSED"};
-    hipLaunchKernelGGL(k_gs_update_dots, dim3(DOT_BLOCKS), dim3(256), 0, st, w, V, ldv, nv, h, n, partial, nullptr);
-    hipLaunchKernelGGL(k_gs_reduce, dim3(nv + 1), dim3(256), 0, st, partial, DOT_BLOCKS, out, host, prev, flag,
+    hipLaunchKernelGGL(k_gs_fused<true>, dim3(FUSED_BLOCKS), dim3(256), 0, st, w, V, ldv, nv, h, n, partial,
+                       nullptr);
+    hipLaunchKernelGGL(k_gs_reduce, dim3(nv + 1), dim3(256), 0, st, partial, FUSED_BLOCKS, out, host, prev, flag,
                        host_flag, nv, nullptr);
 }
 
