@@ -77,6 +77,9 @@ def parse():
                          "thread each)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the precision-form and adjoint comparisons reported beside the headline")
+    ap.add_argument("--block2048", action="store_true",
+                    help="also run the 2048 x 2048 block-permeability workload's 16 right-hand sides in the FP64 "
+                         "and FP32 forms (about two minutes)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="before the warm-up, copy a device buffer of this many MiB once (the plain "
                          "copy kernel that scales the HBM byte counters)")
@@ -122,6 +125,74 @@ def _timed(fn):
     return r, (time.perf_counter() - t) * 1e3
 
 
+def field_diffs(x, ref, n):
+    """Per field (canonical order u, w, p) |x - ref| / |ref|; p with its mean removed, since the
+    constant pressure is the near-null mode that dominates |x| for a random right-hand side."""
+    import torch
+    nu_, nw_ = 5 * n * n - 6 * n + 2, 3 * n * n - 2 * n
+    out = {}
+    for name, a, z in (("u", 0, nu_), ("w", nu_, nu_ + nw_), ("p_mean_removed", nu_ + nw_, None)):
+        xa, ra = x[a:z], ref[a:z]
+        if name.startswith("p"):
+            xa, ra = xa - xa.mean(), ra - ra.mean()
+        out[name] = float(torch.linalg.norm(xa - ra) / torch.linalg.norm(ra))
+    return out
+
+
+def block2048_extra(binding, inputs, torch, forms=("fp64", "fp32")):
+    """The 2048 x 2048 block-permeability workload (41.9 M free DoFs, K = 1 or 1e-6 per 64 x 64-cell
+    block, nu = 0.4999): its 16 right-hand sides solved in sequence with the hierarchy reused, in the
+    FP64 form and the FP32 form (tolerance 1e-8, restart 100); per form the iterations of each
+    right-hand side and the median solve time; the first right-hand side's solution against the
+    FP64 form at 1e-12."""
+    import numpy as np
+    w = inputs.workload("block2048")
+    c = w["cases"][0]
+    n = w["n"]
+    nf = inputs.n_free(n)
+    K = torch.tensor(inputs.permeability_triangles("block2048"), dtype=torch.float64, device="cuda")
+    om, omj = inputs.relaxation_weights("vanka", workload="block2048")
+    rhs = inputs.rhs_uniform(n, w["seed"], count=w["n_rhs"])
+    res = {"workload": "block2048 (2048x2048, K 1 or 1e-6 per 64x64-cell block, nu 0.4999, Vanka V(2,2), "
+                       "%d right-hand sides, restart 100)" % w["n_rhs"]}
+    first = {}
+    for prec in forms:
+        s = binding.BiotSolver(n, c["lam"], c["mu"], alpha=w["alpha"], M=w["M"], mu_f=w["mu_f"], tau=w["tau"], K=K)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.setup(levels=w["levels"], smoother="vanka", nu1=2, nu2=2, omega=om, omega_J=omj, precision=prec)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        iters, ms, conv = [], [], True
+        for k in range(w["n_rhs"]):
+            b = torch.tensor(rhs[k], dtype=torch.float64, device="cuda")
+            (x, info), t = _timed(lambda: s.solve(b, tol=1e-8, restart=100, maxit=600))
+            iters.append(info["iters"])
+            ms.append(round(t, 1))
+            conv = conv and bool(info["converged"])
+            if k == 0:
+                first[prec] = x
+            print("block2048 %s rhs %d: %d iterations, %.0f ms" % (prec, k, info["iters"], t), file=sys.stderr,
+                  flush=True)
+        s.close()
+        med = float(np.median(ms))
+        res[prec] = {"setup_s": round(setup_s, 2), "iters": iters, "ms": ms, "median_ms": med,
+                     "MDOF/s_median": round(nf / (med * 1e-3) / 1e6, 2), "all_converged": conv}
+    s = binding.BiotSolver(n, c["lam"], c["mu"], alpha=w["alpha"], M=w["M"], mu_f=w["mu_f"], tau=w["tau"], K=K)
+    s.setup(levels=w["levels"], smoother="vanka", nu1=2, nu2=2, omega=om, omega_J=omj, precision="fp64")
+    xref, iref = s.solve(torch.tensor(rhs[0], dtype=torch.float64, device="cuda"), tol=1e-12, restart=100,
+                         maxit=1500)
+    s.close()
+    res["reference"] = {"form": "fp64", "tol": 1e-12, "rhs": 0, "iters": iref["iters"],
+                        "rel_res_true": iref["rel_res_true"]}
+    for prec in forms:
+        res[prec]["rhs0_rel_err_vs_reference"] = field_diffs(first[prec], xref, n)
+    for prec in forms[1:]:
+        res[prec]["rhs0_rel_diff_vs_fp64_solution"] = field_diffs(first[prec], first["fp64"], n)
+        res[prec]["speedup_vs_fp64"] = round(res["fp64"]["median_ms"] / res[prec]["median_ms"], 3)
+    return res
+
+
 def precision_extra(binding, inputs, torch):
     """The 1024 x 1024 heterogeneous-permeability workload solved by the plain FP64 form and by the
     two precision forms: "fp32" (FP32 vectors and residuals, FP64 patch arithmetic and Krylov) and
@@ -147,17 +218,16 @@ def precision_extra(binding, inputs, torch):
         res[prec] = {"ms": round(ms, 3), "iters": info["iters"], "rel_res_true": info["rel_res_true"],
                      "MDOF/s": round(inputs.n_free(n) / (ms * 1e-3) / 1e6, 2)}
         s.close()
-    # per field (canonical order u, w, p); p with its mean removed, since the constant pressure
-    # is the near-null mode that dominates |x| for a random right-hand side
-    nu_, nw_ = 5 * n * n - 6 * n + 2, 3 * n * n - 2 * n
+    # reference: the FP64 form at 1e-12 (the oracle's FGMRES does not finish at this size)
+    s = binding.BiotSolver(n, c["lam"], c["mu"], alpha=w["alpha"], M=w["M"], mu_f=w["mu_f"], tau=w["tau"], K=K)
+    s.setup(levels=w["levels"], smoother="vanka", nu1=2, nu2=2, omega=om, omega_J=omj, precision="fp64")
+    xref, iref = s.solve(b, tol=1e-12, restart=30, maxit=600)
+    s.close()
+    res["reference"] = {"form": "fp64", "tol": 1e-12, "iters": iref["iters"], "rel_res_true": iref["rel_res_true"]}
+    for prec in forms:
+        res[prec]["rel_err_vs_reference"] = field_diffs(sol[prec], xref, n)
     for prec in forms[1:]:
-        diff = {}
-        for name, a, z in (("u", 0, nu_), ("w", nu_, nu_ + nw_), ("p_mean_removed", nu_ + nw_, None)):
-            x32, x64 = sol[prec][a:z], sol["fp64"][a:z]
-            if name.startswith("p"):
-                x32, x64 = x32 - x32.mean(), x64 - x64.mean()
-            diff[name] = float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
-        res[prec]["rel_diff_vs_fp64_solution"] = diff
+        res[prec]["rel_diff_vs_fp64_solution"] = field_diffs(sol[prec], sol["fp64"], n)
         res[prec]["speedup_vs_fp64"] = round(res["fp64"]["ms"] / res[prec]["ms"], 3)
     res["workload"] = "grf1024 (1024x1024, log10 K = -3 + GRF(0.1), nu 0.49, tau 1e-2, Vanka V(2,2))"
     return res
@@ -387,6 +457,9 @@ def main():
         extras = {"precision_form": precision_extra(binding, inputs, torch),
                   "adjoint": adjoint_extra(binding, inputs, torch),
                   "kernels_2048": large_mesh_extra(binding, inputs, torch)}
+    if args.block2048:
+        extras = extras or {}
+        extras["block2048"] = block2048_extra(binding, inputs, torch)
     cpu = None
     if not args.no_cpu_baseline:
         r0 = runs[0]
