@@ -32,7 +32,7 @@ class Hierarchy:
     """Levels 0 (finest, n) .. L-1 (coarsest, n_coarse)."""
 
     def __init__(self, n, params, K_tri=1.0, smoother="vanka", omega=1.0, omega_J=1.0,
-                 nu1=1, nu2=1, n_coarse=4, levels=None):
+                 nu1=1, nu2=1, n_coarse=4, levels=None, schur_sweeps=1, omega_S=1.0):
         if levels is not None:
             n_coarse = n >> (levels - 1)
         self.params = params
@@ -54,7 +54,7 @@ class Hierarchy:
                 _, slots = patch_table(lev.mesh, "full")
                 lev.smoother = AdditiveVanka(lev.A, slots, omega)
             elif smoother == "bsr":
-                lev.smoother = InexactBSR(lev.asm, omega, omega_J)
+                lev.smoother = InexactBSR(lev.asm, omega, omega_J, schur_sweeps, omega_S)
             else:
                 raise ValueError(smoother)
         self.coarse_lu = sla.lu_factor(self.levels[-1].A.toarray())

@@ -108,9 +108,15 @@ class AdditiveVanka:
 
 
 class InexactBSR:
-    """One inexact Braess-Sarazin step (Sec. 3.2.2, Appendix D)."""
+    """One inexact Braess-Sarazin step (Sec. 3.2.2, Appendix D).
 
-    def __init__(self, asm, omega, omega_J):
+    The pressure correction solves the approximate Schur complement system
+    S_hat dp = s, S_hat = c_u M_p + A_pw (tau D_w)^{-1} A_pw^T.  schur_sweeps = 1 is the paper's
+    form: one weighted-Jacobi step dp = omega_J s / diag(S_hat).  schur_sweeps = k > 1 runs k
+    Jacobi sweeps with weight omega_S from dp = 0 instead, a short inner iteration on S_hat
+    (exact BSR as k grows)."""
+
+    def __init__(self, asm, omega, omega_J, schur_sweeps=1, omega_S=1.0):
         mesh = asm.mesh
         P = asm.params
         A = asm.A.tocsr()
@@ -133,13 +139,30 @@ class InexactBSR:
         # tau B_w D_w^{-1} B_w^T = A_pw (tau D_w)^{-1} A_pw^T; its diagonal:
         wdiag = np.asarray(self.Apw.multiply(self.Apw) @ (1.0 / self.Dww)).ravel()
         self.diagS = c_u * Mp + wdiag
+        self.cMp = c_u * Mp
+        self.schur_sweeps = int(schur_sweeps)
+        self.omega_S = float(omega_S)
+        if self.schur_sweeps < 1:
+            raise ValueError("schur_sweeps >= 1")
+
+    def schur_apply(self, dp):
+        """S_hat dp = c_u M_p dp + A_pw (tau D_w)^{-1} A_pw^T dp."""
+        return self.cMp * dp + self.Apw @ ((self.Apw.T @ dp) / self.Dww)
+
+    def schur_solve(self, s):
+        if self.schur_sweeps == 1:
+            return self.omega_J * s / self.diagS
+        dp = np.zeros_like(s)
+        for _ in range(self.schur_sweeps):
+            dp = dp + self.omega_S * (s - self.schur_apply(dp)) / self.diagS
+        return dp
 
     def step_correction(self, r):
         ru, rw, rp = r[self.su], r[self.sw], r[self.sp]
         zu = self.fu.correction(ru)
         zw = rw / self.Dww
         s = self.Apu @ zu + self.Apw @ zw - rp
-        dp = self.omega_J * s / self.diagS
+        dp = self.schur_solve(s)
         du = self.fu.correction(ru - self.Aup @ dp)
         dw = (rw - self.Awp @ dp) / self.Dww
         return np.concatenate([du, dw, dp])
