@@ -100,6 +100,12 @@ typedef struct {
     double omega;       /* outer relaxation weight (Vanka and BSR)                           */
     double omega_J;     /* BSR: weighted-Jacobi weight on the approximate Schur complement   */
     int precision;      /* BIOT_PREC_FP64, BIOT_PREC_FP32_SMOOTHER or BIOT_PREC_FP32_PATCH    */
+    int schur_sweeps;   /* BSR: 0 or 1 = the single weighted-Jacobi step with omega_J on the
+                           approximate Schur complement (Sec. 3.2.2); k in 2..64 = k Jacobi
+                           sweeps with weight omega_S from zero instead, a short inner
+                           iteration towards exact BSR (two more launches per sweep level-wide,
+                           more robust for small K and nu near 1/2)                         */
+    double omega_S;     /* BSR with schur_sweeps >= 2: weight of the sweeps, in (0, 1]       */
 } biot_mg_opts;
 
 /* FGMRES controls (in) and results (out). */

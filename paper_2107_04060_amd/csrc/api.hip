@@ -74,6 +74,8 @@ struct Level {
     DevBuf x64, b64, r64, t64, x2_64;   // FP64 work vectors (padded); x64 / x2_64: iterate pair
     DevBuf x32, b32, r32, x2_32;        // FP32 work vectors (padded)
     DevBuf bs64, bs32;                  // BSR scratch vector (padded)
+    DevBuf sch64, sch32;                // BSR Schur sweeps: s and two pressure buffers (6 planes)
+    double cS = 0;                      // (1/M + alpha^2 / (lambda + mu)) |T| of this level
     template <typename T>
     LevelView<T> view() const;
 };
@@ -286,8 +288,13 @@ static void levels_bsr(biot_ctx* c, hipStream_t st) {
             lv.bs32.alloc(len * sizeof(float));
             launch_fill(lv.bs64.as<double>(), lv.L.len, 0.0, st);
             launch_fill(lv.bs32.as<float>(), lv.L.len, 0.0f, st);
+            lv.sch64.alloc(6 * lv.L.plane * sizeof(double));
+            lv.sch32.alloc(6 * lv.L.plane * sizeof(float));
+            launch_fill(lv.sch64.as<double>(), 6 * lv.L.plane, 0.0, st);
+            launch_fill(lv.sch32.as<float>(), 6 * lv.L.plane, 0.0f, st);
         }
         const double area = 0.5 * lv.h * lv.h;
+        lv.cS = cu * area;
         launch_bsr_diag<double>(lv.view<double>(), cu * area, lv.bsrd64.as<double>(), st);
         launch_convert(lv.bsrd64.as<double>(), lv.bsrd32.as<float>(), 5 * lv.L.plane, st);
     }
@@ -336,6 +343,7 @@ struct VecSet<double> {
     static double* b(Level& l) { return l.b64.as<double>(); }
     static double* r(Level& l) { return l.r64.as<double>(); }
     static double* s(Level& l) { return l.bs64.as<double>(); }
+    static double* sch(Level& l) { return l.sch64.as<double>(); }
 };
 template <>
 struct VecSet<float> {
@@ -343,6 +351,7 @@ struct VecSet<float> {
     static float* b(Level& l) { return l.b32.as<float>(); }
     static float* r(Level& l) { return l.r32.as<float>(); }
     static float* s(Level& l) { return l.bs32.as<float>(); }
+    static float* sch(Level& l) { return l.sch32.as<float>(); }
 };
 
 // Event pair for one launch when kernel timing is on for this level (kind 0 Vanka, 1 residual):
@@ -375,6 +384,12 @@ struct XBuf<float> {
     static float* get(Level& l, int k) { return (k ? l.x2_32 : l.x32).as<float>(); }
 };
 
+// BSR Schur sweeps of level l (sweeps <= 1: the single step, no descriptor needed)
+template <typename T>
+static SchurSweeps<T> schur_sweeps(biot_ctx* c, Level& lv) {
+    return SchurSweeps<T>{c->opts.schur_sweeps, (T)c->opts.omega_S, (T)lv.cS, VecSet<T>::sch(lv)};
+}
+
 // One relaxation step on level l from the iterate x (nullptr: zero).  Vanka writes the new
 // iterate to dst (dst != x); BSR updates in place (dst == x, or x == nullptr).  Returns dst.
 template <typename T>
@@ -388,8 +403,9 @@ static T* relax(biot_ctx* c, int l, const T* x, const T* b, T* dst, hipStream_t 
                              &tm);
         return dst;
     }
+    const SchurSweeps<T> sw = schur_sweeps<T>(c, lv);
     launch_bsr_step<T>(v, dst, b, VecSet<T>::r(lv), VecSet<T>::s(lv), x == nullptr, c->K_uniform,
-                       (T)(1.0 / c->K_scalar), om, (T)c->opts.omega_J, nullptr, nullptr, nullptr, nullptr, st);
+                       (T)(1.0 / c->K_scalar), om, (T)c->opts.omega_J, nullptr, nullptr, nullptr, nullptr, st, &sw);
     return dst;
 }
 
@@ -445,8 +461,9 @@ static T* vcycle_level(biot_ctx* c, int l, const T* b, T* buf0, T* buf1, hipStre
             cur = dst;
         } else {
             T* other = cur == buf0 ? buf1 : buf0;
+            const SchurSweeps<T> sw = schur_sweeps<T>(c, lv);
             launch_bsr_step<T>(lv.view<T>(), cur, b, VecSet<T>::r(lv), VecSet<T>::s(lv), false, c->K_uniform, kinv_s,
-                               (T)c->opts.omega, (T)c->opts.omega_J, xc, &lc.L, PW<T>::get(c), other, st);
+                               (T)c->opts.omega, (T)c->opts.omega_J, xc, &lc.L, PW<T>::get(c), other, st, &sw);
         }
         s0 = 1;
     } else {
@@ -771,6 +788,9 @@ int biot_setup_hierarchy(biot_ctx* c, const biot_mg_opts* o, void* stream) {
         require(std::isfinite(o->omega) && o->omega > 0, "omega must be positive");
         require(o->smoother != BIOT_SMOOTHER_BSR || (std::isfinite(o->omega_J) && o->omega_J > 0),
                 "BSR needs omega_J > 0");
+        require(o->schur_sweeps >= 0 && o->schur_sweeps <= 64, "schur_sweeps in [0, 64]");
+        require(o->schur_sweeps <= 1 || (std::isfinite(o->omega_S) && o->omega_S > 0 && o->omega_S <= 1),
+                "Schur sweeps need omega_S in (0, 1]");
         const int nc = c->n >> (o->levels - 1);
         require(nc <= 16, "coarsest mesh must have at most 16 cells per side (dense direct solve)");
         hipStream_t st = S(stream);

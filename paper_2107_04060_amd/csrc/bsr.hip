@@ -292,11 +292,14 @@ struct BsrSecondLds {
     T cf[NSTENCIL];
 };
 
-template <typename T, bool ZERO, int NZ>
+// DPIN: the pressure correction comes from dpin (2 planes, the Schur sweeps below) instead of the
+// single weighted-Jacobi step formed here.
+template <typename T, bool ZERO, int NZ, bool DPIN>
 __device__ __forceinline__ void bsr_second_tile(const T* __restrict__ r, const T* __restrict__ t, const T* x_src,
                                                 T* x, const Layout& L, const T* __restrict__ uinv,
                                                 const T* __restrict__ coef, const T* __restrict__ d, T omega,
-                                                T omega_J, int bx, int by, BsrSecondLds<T>& sh) {
+                                                T omega_J, const T* __restrict__ dpin, int bx, int by,
+                                                BsrSecondLds<T>& sh) {
     constexpr int NTH = TPB * NZ;
     const int tx = threadIdx.x, ty = threadIdx.y, tz = NZ > 1 ? (int)threadIdx.z : 0;
     const int tid = (tz * TB + ty) * TB + tx;
@@ -304,24 +307,25 @@ __device__ __forceinline__ void bsr_second_tile(const T* __restrict__ r, const T
     const int n = L.n;
     {
         Window<T, 8, TW, NTH> wt;
-        wt.load(t, L.plane, L, i0 - 2, j0 - 2, tid);
+        if constexpr (!DPIN) wt.load(t, L.plane, L, i0 - 2, j0 - 2, tid);
         Window<T, 2, DW, NTH> wp;
-        wp.load(r + T_PL * L.plane, L.plane, L, i0 - 2, j0 - 2, tid);
+        wp.load(DPIN ? dpin : r + T_PL * L.plane, L.plane, L, i0 - 2, j0 - 2, tid);
         Window<T, 2, DW, NTH> wd;
-        wd.load(d + BSR_S * L.plane, L.plane, L, i0 - 2, j0 - 2, tid);
+        if constexpr (!DPIN) wd.load(d + BSR_S * L.plane, L.plane, L, i0 - 2, j0 - 2, tid);
         Window<T, NU, RW, NTH> wr;
         wr.load(r, L.plane, L, i0 - 1, j0 - 1, tid);
         Table<T, NSTENCIL> tcf;
         tcf.load(coef, tid);
         load_uinv<T, NTH>(uinv, sh.ui, tid);
         tcf.store(sh.cf, tid);
-        wt.store(&sh.ts[0][0][0], tid);
+        if constexpr (!DPIN) wt.store(&sh.ts[0][0][0], tid);
         wp.store(&sh.dp[0][0][0], tid);
-        wd.store(&sh.ds[0][0][0], tid);
+        if constexpr (!DPIN) wd.store(&sh.ds[0][0][0], tid);
         wr.store(&sh.ru[0][0][0], tid);
     }
     __syncthreads();
     // pressure update on slots (i0-2 .. i0+VT)^2; its columns reach t at +0 .. +1
+    if constexpr (!DPIN)
     for (int q = tid; q < DW * DW; q += NTH) {
         const int bb = q / DW, a = q - bb * DW;
         const int si = i0 - 2 + a, sj = j0 - 2 + bb;
@@ -398,20 +402,92 @@ __device__ __forceinline__ void bsr_second_tile(const T* __restrict__ r, const T
     }
 }
 
-template <typename T, bool ZERO, int NZ>
+template <typename T, bool ZERO, int NZ, bool DPIN>
 __global__ __launch_bounds__(TPB * NZ, 2 * NZ) void k_bsr_second(const T* __restrict__ r, const T* __restrict__ t,
                                                     const T* x_src, T* x, Layout L, const T* __restrict__ uinv,
                                                     const T* __restrict__ coef, const T* __restrict__ d,
-                                                    T omega, T omega_J) {
+                                                    T omega, T omega_J, const T* __restrict__ dpin) {
     __shared__ BsrSecondLds<T> sh;
     int bx, by;
     xcd_tile(bx, by);
-    bsr_second_tile<T, ZERO, NZ>(r, t, x_src, x, L, uinv, coef, d, omega, omega_J, bx, by, sh);
+    bsr_second_tile<T, ZERO, NZ, DPIN>(r, t, x_src, x, L, uinv, coef, d, omega, omega_J, dpin, bx, by, sh);
+}
+
+// ---- approximate Schur complement sweeps (Sec. 3.2.2, Appendix D) ------------------------------
+// S_hat dp = cS dp + sum over the RT0 columns e of a pressure row of A_pw[T,e] (tau D_w)^{-1}_e
+// (A_wp dp)_e, cS = (1/M + alpha^2 / (lambda + mu)) |T|.  k_schur_init forms s = (the pressure rows
+// of A on the u and w columns) t - r_p on every cell and the first sweep from zero,
+// dp = omega_S s / diag(S_hat); k_schur_sweep is one weighted-Jacobi sweep
+// dp' = dp + omega_S (s - S_hat dp) / diag(S_hat).  One thread per slot; absent DoFs get 0 (the
+// buffers' halo slots are never written and stay 0).  Column offsets stay within one slot, inside
+// the padded plane.
+template <typename T>
+__global__ __launch_bounds__(256) void k_schur_init(const T* __restrict__ r, const T* __restrict__ t,
+                                                    const T* __restrict__ coef, const T* __restrict__ d, Layout L,
+                                                    T omega_S, T* __restrict__ s_out, T* __restrict__ dp_out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i > L.n || j > L.n) return;
+    const long long s0 = slot_index(L, i, j);
+    static_for(std::integer_sequence<int, T_PL, T_PU>{}, [&](auto tc) {
+        constexpr int tp = decltype(tc)::value;
+        T acc = 0;
+        static_for(std::make_integer_sequence<int, SST.n[tp]>{}, [&](auto ec) {
+            constexpr int e = decltype(ec)::value;
+            constexpr SEnt en = SST.e[tp][e];
+            if constexpr (tfield(en.in) != 2)
+                acc += coef[SST.off[tp] + e] * t[en.in * L.plane + s0 + (long long)en.dj * L.pitch + en.di];
+        });
+        const bool f = dof_free(tp, i, j, L.n);
+        const T sv = f ? acc - r[tp * L.plane + s0] : (T)0;
+        s_out[(tp - T_PL) * L.plane + s0] = sv;
+        dp_out[(tp - T_PL) * L.plane + s0] = f ? omega_S * sv * d[(BSR_S + tp - T_PL) * L.plane + s0] : (T)0;
+    });
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_schur_sweep(const T* __restrict__ s_in, const T* __restrict__ dp_in,
+                                                     const T* __restrict__ coef, const T* __restrict__ d, Layout L,
+                                                     T omega_S, T cS, T* __restrict__ dp_out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i > L.n || j > L.n) return;
+    const long long s0 = slot_index(L, i, j);
+    static_for(std::integer_sequence<int, T_PL, T_PU>{}, [&](auto tc) {
+        constexpr int tp = decltype(tc)::value;
+        if (!dof_free(tp, i, j, L.n)) {
+            dp_out[(tp - T_PL) * L.plane + s0] = (T)0;
+            return;
+        }
+        const T dp = dp_in[(tp - T_PL) * L.plane + s0];
+        T sd = cS * dp;
+        static_for(std::make_integer_sequence<int, SST.n[tp]>{}, [&](auto ec) {
+            constexpr int e1 = decltype(ec)::value;
+            constexpr SEnt en1 = SST.e[tp][e1];
+            if constexpr (tfield(en1.in) == 1) {
+                if (dof_free(en1.in, i + en1.di, j + en1.dj, L.n)) {
+                    const long long ws = s0 + (long long)en1.dj * L.pitch + en1.di;
+                    T g = 0;
+                    static_for(std::make_integer_sequence<int, SST.n[en1.in]>{}, [&](auto fc) {
+                        constexpr int e2 = decltype(fc)::value;
+                        constexpr SEnt en2 = SST.e[en1.in][e2];
+                        if constexpr (tfield(en2.in) == 2)
+                            g += coef[SST.off[en1.in] + e2] *
+                                 dp_in[(en2.in - T_PL) * L.plane + ws + (long long)en2.dj * L.pitch + en2.di];
+                    });
+                    sd += coef[SST.off[tp] + e1] * g * d[(BSR_W + en1.in - T_WH) * L.plane + ws];
+                }
+            }
+        });
+        dp_out[(tp - T_PL) * L.plane + s0] =
+            dp + omega_S * (s_in[(tp - T_PL) * L.plane + s0] - sd) * d[(BSR_S + tp - T_PL) * L.plane + s0];
+    });
 }
 
 template <typename T>
 void launch_bsr_step(const LevelView<T>& lv, T* x, const T* b, T* r, T* t, bool x_is_zero, bool uniform, T kinv_s,
-                     T omega, T omega_J, const T* xc, const Layout* Lc, const T* pw, T* xtmp, hipStream_t st) {
+                     T omega, T omega_J, const T* xc, const Layout* Lc, const T* pw, T* xtmp, hipStream_t st,
+                     const SchurSweeps<T>* sw) {
     constexpr int NZ = 2;   // two thread layers: residual types, patch outputs and updates split
     dim3 blk(TB, TB, NZ);
     dim3 grd((lv.L.n + 1 + VO - 1) / VO, (lv.L.n + 1 + VO - 1) / VO);
@@ -432,17 +508,41 @@ void launch_bsr_step(const LevelView<T>& lv, T* x, const T* b, T* r, T* t, bool 
         BIOT_BSR_FIRST(false, false, false);
 #undef BIOT_BSR_FIRST
     const T* xsrc = xc ? xtmp : x;
-    if (x_is_zero)
-        hipLaunchKernelGGL((k_bsr_second<T, true, NZ>), grd, blk, 0, st, r, t, xsrc, x, lv.L, lv.uinv, lv.coef,
-                           lv.bsrd, omega, omega_J);
+    const T* dp = nullptr;
+    if (sw && sw->sweeps > 1) {
+        if (!sw->buf) throw ArgError{"Schur sweeps need their buffer"};
+        // sw->buf: s (2 planes), then two pressure buffers of 2 planes each
+        T* sv = sw->buf;
+        T* pa = sw->buf + 2 * lv.L.plane;
+        T* pb = sw->buf + 4 * lv.L.plane;
+        dim3 cb(64, 4);
+        dim3 cg((lv.L.n + 1 + 63) / 64, (lv.L.n + 1 + 3) / 4);
+        hipLaunchKernelGGL(k_schur_init<T>, cg, cb, 0, st, r, t, lv.coef, lv.bsrd, lv.L, sw->omega_S, sv, pa);
+        for (int k = 1; k < sw->sweeps; ++k) {
+            hipLaunchKernelGGL(k_schur_sweep<T>, cg, cb, 0, st, sv, pa, lv.coef, lv.bsrd, lv.L, sw->omega_S, sw->cS,
+                               pb);
+            std::swap(pa, pb);
+        }
+        dp = pa;
+    }
+#define BIOT_BSR_SECOND(Z, D)                                                                                    \
+    hipLaunchKernelGGL((k_bsr_second<T, Z, NZ, D>), grd, blk, 0, st, r, t, xsrc, x, lv.L, lv.uinv, lv.coef,     \
+                       lv.bsrd, omega, omega_J, dp)
+    if (x_is_zero && dp)
+        BIOT_BSR_SECOND(true, true);
+    else if (x_is_zero)
+        BIOT_BSR_SECOND(true, false);
+    else if (dp)
+        BIOT_BSR_SECOND(false, true);
     else
-        hipLaunchKernelGGL((k_bsr_second<T, false, NZ>), grd, blk, 0, st, r, t, xsrc, x, lv.L, lv.uinv, lv.coef,
-                           lv.bsrd, omega, omega_J);
+        BIOT_BSR_SECOND(false, false);
+#undef BIOT_BSR_SECOND
 }
 template void launch_bsr_step<double>(const LevelView<double>&, double*, const double*, double*, double*, bool, bool,
                                       double, double, double, const double*, const Layout*, const double*, double*,
-                                      hipStream_t);
+                                      hipStream_t, const SchurSweeps<double>*);
 template void launch_bsr_step<float>(const LevelView<float>&, float*, const float*, float*, float*, bool, bool, float,
-                                     float, float, const float*, const Layout*, const float*, float*, hipStream_t);
+                                     float, float, const float*, const Layout*, const float*, float*, hipStream_t,
+                                     const SchurSweeps<float>*);
 
 }  // namespace biot

@@ -79,9 +79,20 @@ void launch_bsr_diag(const LevelView<T>& lv, T cS, T* d, hipStream_t st);
 // one BSR step x <- x + omega M_BSR^{-1} (b - A x) in two launches (r, t: scratch vectors of the
 // level; x_is_zero: x = 0 on entry).  xc != nullptr: the iterate is x + P x_c (coarse layout
 // *Lc, prolongation weights pw), formed into xtmp (!= x) on the way; the result is in x.
+// sw (optional): the pressure correction from sweeps > 1 weighted-Jacobi sweeps (weight omega_S)
+// on the approximate Schur complement instead of the single step with omega_J; cS = (1/M +
+// alpha^2 / (lambda + mu)) |T|; buf: 6 zero-initialized planes of the level.
+template <typename T>
+struct SchurSweeps {
+    int sweeps;
+    T omega_S;
+    T cS;
+    T* buf;
+};
 template <typename T>
 void launch_bsr_step(const LevelView<T>& lv, T* x, const T* b, T* r, T* t, bool x_is_zero, bool uniform, T kinv_s,
-                     T omega, T omega_J, const T* xc, const Layout* Lc, const T* pw, T* xtmp, hipStream_t st);
+                     T omega, T omega_J, const T* xc, const Layout* Lc, const T* pw, T* xtmp, hipStream_t st,
+                     const SchurSweeps<T>* sw = nullptr);
 
 // coarsest level (Ainv: the inverse of the coarsest operator, row-major)
 template <typename T>
