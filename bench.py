@@ -193,6 +193,36 @@ def block2048_extra(binding, inputs, torch, forms=("fp64", "fp32")):
     return res
 
 
+def schur_extra(binding, inputs, torch, sweeps=2, omega_S=1.0):
+    """BSR V(1,1) on the sweep256 parameter sets, one solve at a time (FP64, 1e-8): the paper's
+    single weighted-Jacobi step on the approximate Schur complement against `sweeps` Jacobi
+    sweeps (weight omega_S) with the same outer weights; iterations and solve times per set."""
+    w = inputs.workload("sweep256")
+    n, levels = w["n"], w["levels"]
+    b = torch.tensor(inputs.rhs_uniform(n, w["seed"]), dtype=torch.float64, device="cuda")
+    rows = []
+    tot = {1: [0, 0.0], sweeps: [0, 0.0]}
+    for case in w["cases"]:
+        om, omj = inputs.relaxation_weights("bsr", case["nu"], case["K"])
+        row = {"nu": case["nu"], "K": case["K"]}
+        for k in (1, sweeps):
+            s = binding.BiotSolver(n, case["lam"], case["mu"], alpha=w["alpha"], M=w["M"], mu_f=w["mu_f"],
+                                   tau=w["tau"], K=case["K"])
+            s.setup(levels=levels, smoother="bsr", nu1=1, nu2=1, omega=om, omega_J=omj, schur_sweeps=k,
+                    omega_S=omega_S)
+            s.solve(b, tol=1e-8, restart=30, maxit=500)                 # warm-up
+            (x, info), ms = _timed(lambda: s.solve(b, tol=1e-8, restart=30, maxit=500))
+            s.close()
+            row["sweeps_%d" % k] = {"iters": info["iters"], "ms": round(ms, 2), "converged": bool(info["converged"])}
+            tot[k][0] += info["iters"]
+            tot[k][1] += ms
+        rows.append(row)
+    return {"workload": "sweep256 BSR V(1,1) parameter sets, one solve at a time, FP64, 1e-8",
+            "sweeps": sweeps, "omega_S": omega_S, "cases": rows,
+            "total": {"sweeps_1": {"iters": tot[1][0], "ms": round(tot[1][1], 1)},
+                      "sweeps_%d" % sweeps: {"iters": tot[sweeps][0], "ms": round(tot[sweeps][1], 1)}}}
+
+
 def precision_extra(binding, inputs, torch):
     """The 1024 x 1024 heterogeneous-permeability workload solved by the plain FP64 form and by the
     two precision forms: "fp32" (FP32 vectors and residuals, FP64 patch arithmetic and Krylov) and
@@ -456,7 +486,8 @@ def main():
     if not args.no_extras and args.workload == "sweep256":
         extras = {"precision_form": precision_extra(binding, inputs, torch),
                   "adjoint": adjoint_extra(binding, inputs, torch),
-                  "kernels_2048": large_mesh_extra(binding, inputs, torch)}
+                  "kernels_2048": large_mesh_extra(binding, inputs, torch),
+                  "bsr_schur_sweeps": schur_extra(binding, inputs, torch)}
     if args.block2048:
         extras = extras or {}
         extras["block2048"] = block2048_extra(binding, inputs, torch)
