@@ -32,11 +32,14 @@ class Hierarchy:
     """Levels 0 (finest, n) .. L-1 (coarsest, n_coarse)."""
 
     def __init__(self, n, params, K_tri=1.0, smoother="vanka", omega=1.0, omega_J=1.0,
-                 nu1=1, nu2=1, n_coarse=4, levels=None, schur_sweeps=1, omega_S=1.0):
+                 nu1=1, nu2=1, n_coarse=4, levels=None, schur_sweeps=1, omega_S=1.0, gamma=1):
         if levels is not None:
             n_coarse = n >> (levels - 1)
         self.params = params
         self.nu1, self.nu2 = int(nu1), int(nu2)
+        self.gamma = int(gamma)                 # coarse corrections per level: 1 V-cycle, 2 W-cycle
+        if self.gamma < 1:
+            raise ValueError("gamma >= 1")
         self.levels = []
         Kinv = 1.0 / np.broadcast_to(np.asarray(K_tri, dtype=np.float64), (2 * n * n,))
         nn = n
@@ -64,7 +67,10 @@ class Hierarchy:
         return self.levels[0].A
 
     def vcycle(self, b, level=0):
-        """One V(nu1, nu2) cycle for A_level x = b from x = 0."""
+        """One V(nu1, nu2) cycle for A_level x = b from x = 0; with gamma > 1 the coarse
+        correction is gamma cycles of the next level (a W-cycle for gamma = 2), each further one
+        on the residual left by the previous ones, except at the coarsest level, whose direct
+        solve is exact."""
         lev = self.levels[level]
         if level == len(self.levels) - 1:
             return sla.lu_solve(self.coarse_lu, b)
@@ -72,7 +78,11 @@ class Hierarchy:
         for _ in range(self.nu1):
             x = lev.smoother.smooth(x, b)
         r = b - lev.A @ x
-        xc = self.vcycle(lev.P.T @ r, level + 1)
+        bc = lev.P.T @ r
+        xc = self.vcycle(bc, level + 1)
+        if level + 1 < len(self.levels) - 1:
+            for _ in range(self.gamma - 1):
+                xc = xc + self.vcycle(bc - self.levels[level + 1].A @ xc, level + 1)
         x = x + lev.P @ xc
         for _ in range(self.nu2):
             x = lev.smoother.smooth(x, b)
