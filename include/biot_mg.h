@@ -106,6 +106,10 @@ typedef struct {
                            iteration towards exact BSR (two more launches per sweep level-wide,
                            more robust for small K and nu near 1/2)                         */
     double omega_S;     /* BSR with schur_sweeps >= 2: weight of the sweeps, in (0, 1]       */
+    int gamma;          /* cycle index, 0 or 1 = V-cycle, 2 = W-cycle, up to 4: the coarse
+                           correction of each level is gamma cycles of the next, each further
+                           one on the residual the previous ones left (the coarsest direct
+                           solve is not repeated); more robust BSR for small K (Sec. 5.1)   */
 } biot_mg_opts;
 
 /* FGMRES controls (in) and results (out). */

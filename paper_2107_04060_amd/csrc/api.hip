@@ -75,6 +75,7 @@ struct Level {
     DevBuf x32, b32, r32, x2_32;        // FP32 work vectors (padded)
     DevBuf bs64, bs32;                  // BSR scratch vector (padded)
     DevBuf sch64, sch32;                // BSR Schur sweeps: s and two pressure buffers (6 planes)
+    DevBuf wx64, wb64, wx32, wb32;      // W-cycles: accumulated correction, residual of a revisit
     double cS = 0;                      // (1/M + alpha^2 / (lambda + mu)) |T| of this level
     template <typename T>
     LevelView<T> view() const;
@@ -344,6 +345,8 @@ struct VecSet<double> {
     static double* r(Level& l) { return l.r64.as<double>(); }
     static double* s(Level& l) { return l.bs64.as<double>(); }
     static double* sch(Level& l) { return l.sch64.as<double>(); }
+    static double* wx(Level& l) { return l.wx64.as<double>(); }
+    static double* wb(Level& l) { return l.wb64.as<double>(); }
 };
 template <>
 struct VecSet<float> {
@@ -352,6 +355,8 @@ struct VecSet<float> {
     static float* r(Level& l) { return l.r32.as<float>(); }
     static float* s(Level& l) { return l.bs32.as<float>(); }
     static float* sch(Level& l) { return l.sch32.as<float>(); }
+    static float* wx(Level& l) { return l.wx32.as<float>(); }
+    static float* wb(Level& l) { return l.wb32.as<float>(); }
 };
 
 // Event pair for one launch when kernel timing is on for this level (kind 0 Vanka, 1 residual):
@@ -450,6 +455,19 @@ static T* vcycle_level(biot_ctx* c, int l, const T* b, T* buf0, T* buf1, hipStre
     launch_residual_restrict<T>(lv.view<T>(), lc.L, cur, b, bc, c->K_uniform, (T)(1.0 / c->K_scalar),
                                 PW<T>::get(c), st, &tm);
     T* xc = vcycle_level<T>(c, l + 1, bc, XBuf<T>::get(lc, 0), XBuf<T>::get(lc, 1), st);
+    if (c->opts.gamma > 1 && l + 2 < (int)c->levels.size()) {
+        // W-cycle: gamma - 1 further cycles of level l + 1 on the residual left by the previous
+        // ones (the coarsest level's direct solve is exact and not repeated)
+        T* acc = VecSet<T>::wx(lc);
+        T* rc = VecSet<T>::wb(lc);
+        BIOT_HIP(hipMemcpyAsync(acc, xc, lc.L.len * sizeof(T), hipMemcpyDeviceToDevice, st));
+        for (int g = 1; g < c->opts.gamma; ++g) {
+            launch_apply<T>(lc.view<T>(), acc, bc, rc, 1, st);
+            T* d = vcycle_level<T>(c, l + 1, rc, XBuf<T>::get(lc, 0), XBuf<T>::get(lc, 1), st);
+            launch_add<T>(acc, d, lc.L.len, st);
+        }
+        xc = acc;
+    }
     int s0 = 0;
     if (c->opts.nu2 > 0) {
         // prolongation fused into the first post-smoothing step
@@ -789,6 +807,7 @@ int biot_setup_hierarchy(biot_ctx* c, const biot_mg_opts* o, void* stream) {
         require(o->smoother != BIOT_SMOOTHER_BSR || (std::isfinite(o->omega_J) && o->omega_J > 0),
                 "BSR needs omega_J > 0");
         require(o->schur_sweeps >= 0 && o->schur_sweeps <= 64, "schur_sweeps in [0, 64]");
+        require(o->gamma >= 0 && o->gamma <= 4, "gamma (cycle index) in [0, 4]");
         require(o->schur_sweeps <= 1 || (std::isfinite(o->omega_S) && o->omega_S > 0 && o->omega_S <= 1),
                 "Schur sweeps need omega_S in (0, 1]");
         const int nc = c->n >> (o->levels - 1);
@@ -816,6 +835,21 @@ int biot_setup_hierarchy(biot_ctx* c, const biot_mg_opts* o, void* stream) {
         for (auto& lv : c->levels)
             launch_convert(lv->kinv64.as<double>(), lv->kinv32.as<float>(), 2 * lv->L.plane, st);
         c->opts = *o;
+        if (c->opts.gamma < 1) c->opts.gamma = 1;
+        if (c->opts.gamma > 1) {
+            // W-cycle buffers of the levels that are revisited (all but the finest and coarsest)
+            for (size_t l = 1; l + 1 < c->levels.size(); ++l) {
+                Level& lw = *c->levels[l];
+                const size_t len = (size_t)lw.L.len;
+                if (o->precision == BIOT_PREC_FP64) {
+                    lw.wx64.alloc(len * sizeof(double));
+                    lw.wb64.alloc(len * sizeof(double));
+                } else {
+                    lw.wx32.alloc(len * sizeof(float));
+                    lw.wb32.alloc(len * sizeof(float));
+                }
+            }
+        }
         if (o->precision != BIOT_PREC_FP64) alloc_fp32(c, st);
         for (auto& lp : c->levels) lp->patch32 = o->precision == BIOT_PREC_FP32_PATCH;
         if (o->smoother == BIOT_SMOOTHER_BSR) levels_bsr(c, st);

@@ -35,6 +35,9 @@ struct LevelView {
 // vector plumbing
 void launch_fill(double* x, long long n, double v, hipStream_t st);
 void launch_fill(float* x, long long n, float v, hipStream_t st);
+// y += x over n entries
+template <typename T>
+void launch_add(T* y, const T* x, long long n, hipStream_t st);
 void launch_pack(const double* canon, double* padded, const Layout& L, const Canon& C, hipStream_t st);
 void launch_unpack(const double* padded, double* canon, const Layout& L, const Canon& C, hipStream_t st);
 void launch_convert(const double* src, float* dst, long long n, hipStream_t st);

@@ -38,6 +38,22 @@ void launch_fill(float* x, long long n, float v, hipStream_t st) {
     hipLaunchKernelGGL(k_fill<float>, dim3(blocks), dim3(256), 0, st, x, n, v);
 }
 
+template <typename T>
+__global__ void k_add(T* __restrict__ y, const T* __restrict__ x, long long n) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long stride = (long long)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) y[i] += x[i];
+}
+
+template <typename T>
+void launch_add(T* y, const T* x, long long n, hipStream_t st) {
+    int blocks = (int)std::min<long long>((n + 255) / 256, 65536);
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_add<T>, dim3(blocks), dim3(256), 0, st, y, x, n);
+}
+template void launch_add<double>(double*, const double*, long long, hipStream_t);
+template void launch_add<float>(float*, const float*, long long, hipStream_t);
+
 // canonical index k -> (type, i, j) of the free DoF
 __device__ inline void canon_decode(long long k, const Canon& C, int n, int& t, int& i, int& j) {
     t = 0;
