@@ -16,7 +16,7 @@ import scipy.linalg as sla
 from .mesh import Mesh
 from .fem import Assembly, coarsen_inverse_K
 from .transfer import prolongation
-from .smoothers import AdditiveVanka, InexactBSR, patch_table
+from .smoothers import MulticolorVanka, AdditiveVanka, InexactBSR, patch_table
 
 
 class Level:
@@ -32,7 +32,8 @@ class Hierarchy:
     """Levels 0 (finest, n) .. L-1 (coarsest, n_coarse)."""
 
     def __init__(self, n, params, K_tri=1.0, smoother="vanka", omega=1.0, omega_J=1.0,
-                 nu1=1, nu2=1, n_coarse=4, levels=None, schur_sweeps=1, omega_S=1.0, gamma=1):
+                 nu1=1, nu2=1, n_coarse=4, levels=None, schur_sweeps=1, omega_S=1.0, gamma=1,
+                 vanka_colors=0):
         if levels is not None:
             n_coarse = n >> (levels - 1)
         self.params = params
@@ -53,7 +54,11 @@ class Hierarchy:
         for l in range(len(self.levels) - 1):
             _, self.levels[l].P = prolongation(self.levels[l].mesh, self.levels[l + 1].mesh)
         for lev in self.levels[:-1]:
-            if smoother == "vanka":
+            if smoother == "vanka" and vanka_colors:
+                if vanka_colors != MulticolorVanka.NCOLORS:
+                    raise ValueError("vanka_colors: 0 (additive) or 4")
+                lev.smoother = MulticolorVanka(lev.A, lev.mesh, omega)
+            elif smoother == "vanka":
                 _, slots = patch_table(lev.mesh, "full")
                 lev.smoother = AdditiveVanka(lev.A, slots, omega)
             elif smoother == "bsr":
