@@ -110,6 +110,10 @@ typedef struct {
                            correction of each level is gamma cycles of the next, each further
                            one on the residual the previous ones left (the coarsest direct
                            solve is not repeated); more robust BSR for small K (Sec. 5.1)   */
+    int vanka_colors;   /* Vanka: 0 = additive (Sec. 3.2.1, weights D_l); 4 = multiplicative in
+                           four colours (i mod 2) + 2 (j mod 2) of the patch vertex, each colour
+                           on the residual the previous one left, unweighted (a colour's patches
+                           share no DoF); four launches per smoothing step                    */
 } biot_mg_opts;
 
 /* FGMRES controls (in) and results (out). */

@@ -395,18 +395,34 @@ static SchurSweeps<T> schur_sweeps(biot_ctx* c, Level& lv) {
     return SchurSweeps<T>{c->opts.schur_sweeps, (T)c->opts.omega_S, (T)lv.cS, VecSet<T>::sch(lv)};
 }
 
+// Multiplicative Vanka: the colours of a step are separate launches, each reading the iterate
+// the previous one wrote.
+static int vanka_colors(const biot_mg_opts& o) {
+    return o.smoother == BIOT_SMOOTHER_VANKA && o.vanka_colors == 4 ? 4 : 1;
+}
+
 // One relaxation step on level l from the iterate x (nullptr: zero).  Vanka writes the new
-// iterate to dst (dst != x); BSR updates in place (dst == x, or x == nullptr).  Returns dst.
+// iterate to dst (dst != x); its multiplicative form alternates between dst and alt (the other
+// buffer of the pair, != dst) and returns the buffer it ended in.  BSR updates in place
+// (dst == x, or x == nullptr).  Returns the buffer holding the new iterate.
 template <typename T>
-static T* relax(biot_ctx* c, int l, const T* x, const T* b, T* dst, hipStream_t st) {
+static T* relax(biot_ctx* c, int l, const T* x, const T* b, T* dst, T* alt, hipStream_t st) {
     Level& lv = *c->levels[l];
     LevelView<T> v = lv.view<T>();
     const T om = (T)c->opts.omega;
     if (c->opts.smoother == BIOT_SMOOTHER_VANKA) {
-        const LaunchTiming tm = x ? prof_events(c, 0, l) : LaunchTiming{};
-        launch_vanka_step<T>(v, x, b, dst, c->K_uniform, (T)(1.0 / c->K_scalar), om, st, nullptr, nullptr, nullptr,
-                             &tm);
-        return dst;
+        const int nc = vanka_colors(c->opts);
+        if (nc > 1 && (!alt || alt == dst)) throw ArgError{"multiplicative Vanka needs a second buffer"};
+        const T* src = x;
+        T* out = dst;
+        for (int col = 0; col < nc; ++col) {
+            const LaunchTiming tm = src ? prof_events(c, 0, l) : LaunchTiming{};
+            launch_vanka_step<T>(v, src, b, out, c->K_uniform, (T)(1.0 / c->K_scalar), om, st, nullptr, nullptr,
+                                 nullptr, &tm, nc > 1 ? col : -1);
+            src = out;
+            out = out == dst ? alt : dst;
+        }
+        return const_cast<T*>(src);
     }
     const SchurSweeps<T> sw = schur_sweeps<T>(c, lv);
     launch_bsr_step<T>(v, dst, b, VecSet<T>::r(lv), VecSet<T>::s(lv), x == nullptr, c->K_uniform,
@@ -418,7 +434,8 @@ static T* relax(biot_ctx* c, int l, const T* x, const T* b, T* dst, hipStream_t 
 // step from zero writes buffer 0).
 static int buffer_moves(const biot_mg_opts& o) {
     if (o.smoother != BIOT_SMOOTHER_VANKA) return 0;
-    return (o.nu1 > 0 ? o.nu1 - 1 : 0) + o.nu2;
+    const int nc = vanka_colors(o);
+    return (o.nu1 > 0 ? o.nu1 * nc - 1 : 0) + o.nu2 * nc;
 }
 
 template <typename T>
@@ -444,7 +461,11 @@ static T* vcycle_level(biot_ctx* c, int l, const T* b, T* buf0, T* buf1, hipStre
     const bool inplace = c->opts.smoother != BIOT_SMOOTHER_VANKA;
     T* cur = nullptr;
     auto next = [&]() { return cur == nullptr ? buf0 : (inplace ? cur : (cur == buf0 ? buf1 : buf0)); };
-    for (int s = 0; s < c->opts.nu1; ++s) cur = relax<T>(c, l, cur, b, next(), st);
+    auto other = [&](T* d) { return d == buf0 ? buf1 : buf0; };
+    for (int s = 0; s < c->opts.nu1; ++s) {
+        T* d = next();
+        cur = relax<T>(c, l, cur, b, d, other(d), st);
+    }
     if (!cur) {
         launch_fill(buf0, lv.L.len, (T)0, st);
         cur = buf0;
@@ -473,10 +494,14 @@ static T* vcycle_level(biot_ctx* c, int l, const T* b, T* buf0, T* buf1, hipStre
         // prolongation fused into the first post-smoothing step
         const T kinv_s = (T)(1.0 / c->K_scalar);
         if (!inplace) {
-            T* dst = next();
-            launch_vanka_step<T>(lv.view<T>(), cur, b, dst, c->K_uniform, kinv_s, (T)c->opts.omega, st, xc, &lc.L,
-                                 PW<T>::get(c));
-            cur = dst;
+            // multiplicative form: colour 0 with the prolongation, then colours 1..3
+            const int nc = vanka_colors(c->opts);
+            for (int col = 0; col < nc; ++col) {
+                T* dst = next();
+                launch_vanka_step<T>(lv.view<T>(), cur, b, dst, c->K_uniform, kinv_s, (T)c->opts.omega, st,
+                                     col == 0 ? xc : nullptr, &lc.L, PW<T>::get(c), nullptr, nc > 1 ? col : -1);
+                cur = dst;
+            }
         } else {
             T* other = cur == buf0 ? buf1 : buf0;
             const SchurSweeps<T> sw = schur_sweeps<T>(c, lv);
@@ -487,7 +512,10 @@ static T* vcycle_level(biot_ctx* c, int l, const T* b, T* buf0, T* buf1, hipStre
     } else {
         launch_prolong_add<T>(lv.L, lc.L, xc, cur, PW<T>::get(c), st);
     }
-    for (int s = s0; s < c->opts.nu2; ++s) cur = relax<T>(c, l, cur, b, next(), st);
+    for (int s = s0; s < c->opts.nu2; ++s) {
+        T* d = next();
+        cur = relax<T>(c, l, cur, b, d, other(d), st);
+    }
     return cur;
 }
 
@@ -808,6 +836,7 @@ int biot_setup_hierarchy(biot_ctx* c, const biot_mg_opts* o, void* stream) {
                 "BSR needs omega_J > 0");
         require(o->schur_sweeps >= 0 && o->schur_sweeps <= 64, "schur_sweeps in [0, 64]");
         require(o->gamma >= 0 && o->gamma <= 4, "gamma (cycle index) in [0, 4]");
+        require(o->vanka_colors == 0 || o->vanka_colors == 4, "vanka_colors: 0 (additive) or 4");
         require(o->schur_sweeps <= 1 || (std::isfinite(o->omega_S) && o->omega_S > 0 && o->omega_S <= 1),
                 "Schur sweeps need omega_S in (0, 1]");
         const int nc = c->n >> (o->levels - 1);
@@ -915,13 +944,13 @@ int biot_smooth(biot_ctx* c, int level, double* x, const double* b, void* stream
         const bool vanka = c->opts.smoother == BIOT_SMOOTHER_VANKA;
         if (c->opts.precision == BIOT_PREC_FP64) {
             double* x0 = lv.x64.as<double>();
-            double* res = relax<double>(c, level, x0, lv.b64.as<double>(), vanka ? lv.x2_64.as<double>() : x0, st);
+            double* res = relax<double>(c, level, x0, lv.b64.as<double>(), vanka ? lv.x2_64.as<double>() : x0, x0, st);
             launch_unpack(res, x, lv.L, lv.C, st);
         } else {
             float* x0 = lv.x32.as<float>();
             launch_convert(lv.x64.as<double>(), x0, lv.L.len, st);
             launch_convert(lv.b64.as<double>(), lv.b32.as<float>(), lv.L.len, st);
-            float* res = relax<float>(c, level, x0, lv.b32.as<float>(), vanka ? lv.x2_32.as<float>() : x0, st);
+            float* res = relax<float>(c, level, x0, lv.b32.as<float>(), vanka ? lv.x2_32.as<float>() : x0, x0, st);
             launch_convert(res, lv.x64.as<double>(), lv.L.len, st);
             launch_unpack(lv.x64.as<double>(), x, lv.L, lv.C, st);
         }

@@ -59,10 +59,12 @@ struct LaunchTiming {
 // vertex class (lv.minv, full inverses), 1/K = kinv_s; else per-patch elimination with lv.kinv.
 // xc != nullptr: the iterate is x_in + P x_c (coarse level layout *Lc, prolongation weights
 // pw), i.e. the prolongation of the coarse-grid correction is fused into the step.
+// color in 0..3: one colour step of the multiplicative form (only the patches of vertices of that
+// colour, unweighted); -1: the additive step.
 template <typename T>
 void launch_vanka_step(const LevelView<T>& lv, const T* x_in, const T* b, T* x_out, bool uniform, T kinv_s,
                        T omega, hipStream_t st, const T* xc = nullptr, const Layout* Lc = nullptr,
-                       const T* pw = nullptr, const LaunchTiming* tm = nullptr);
+                       const T* pw = nullptr, const LaunchTiming* tm = nullptr, int color = -1);
 
 // grid transfers
 // (w: the NPWEIGHTS prolongation weights of structure.h, device)

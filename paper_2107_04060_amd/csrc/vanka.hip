@@ -25,6 +25,10 @@ __device__ inline double vanka_weight(int t, int i, int j, int n) {
     return (i == n - 1 && j == n - 1) ? 0.5 : 1.0 / 3.0;
 }
 
+// colour of the patch of vertex (i, j) in the multiplicative form: adjacent vertices differ in a
+// parity, so the patches of one colour share no DoF
+__host__ __device__ constexpr int vertex_color(int i, int j) { return (i & 1) + 2 * (j & 1); }
+
 // LDS offset of patch slot s relative to the residual entry of its vertex (rs[0][vj+1][vi+1])
 __host__ __device__ constexpr int pslot_off(int s) {
     const int tt[PATCH] = {T_UX, T_UY, T_BH, T_BH, T_BV, T_BV, T_BD, T_BD, T_WH, T_WH,
@@ -85,7 +89,7 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
                                                 const DevPatchClass<P>* __restrict__ cls,
                                                 const P* __restrict__ wblk, const double* __restrict__ minv,
                                                 T omega, const T* __restrict__ xc, const Layout& Lc,
-                                                const T* __restrict__ pw, int bx, int by,
+                                                const T* __restrict__ pw, int color, int bx, int by,
                                                 VankaLds<T, P, UNIFORM, NCLS, PROL>& sh) {
     static_assert(!(PROL && ZERO), "the prolongation needs an iterate");
     auto& xs = sh.u.a.xs;
@@ -305,12 +309,14 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
                 acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(cf[0][ks], bf[sb][ks], acc0, 0, 0, 0);
                 acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(cf[1][ks], bf[sb][ks], acc1, 0, 0, 0);
             }
-            // rows a = kq + 4 v + 16 mb of the lane's patch
+            // rows a = kq + 4 v + 16 mb of the lane's patch; a colour step keeps its colour's
+            // patches only
             if (own) {
+                const bool keep = color < 0 || vertex_color(i0 + pti, j0 + ptj) == color;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    sh.u.so[kq + 4 * v][ptj][pti] = (T)acc0[v];
-                    if (kq + 4 * v + 16 < PATCH) sh.u.so[kq + 4 * v + 16][ptj][pti] = (T)acc1[v];
+                    sh.u.so[kq + 4 * v][ptj][pti] = keep ? (T)acc0[v] : (T)0;
+                    if (kq + 4 * v + 16 < PATCH) sh.u.so[kq + 4 * v + 16][ptj][pti] = keep ? (T)acc1[v] : (T)0;
                 }
             }
         }
@@ -322,7 +328,7 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
 #pragma unroll
         for (int s = 0; s < PATCH; ++s) out[s] = 0;
         const bool inner = cilo == 1 && cihi == 1 && cjlo == 1 && cjhi == 1;
-        const bool act = patch && vi <= n && vj <= n;
+        const bool act = patch && vi <= n && vj <= n && (color < 0 || vertex_color(vi, vj) == color);
         P rr[PATCH], kv[6];
         if (act) {
 #pragma unroll
@@ -380,7 +386,8 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
             static_for(std::make_integer_sequence<int, NTYPES>{}, [&](auto tc) {
                 constexpr int t = decltype(tc)::value;
                 if (ggroup(t, NZ) == tz && dof_free(t, si, sj, n))
-                    x_out[t * L.plane + s0] = xown[t] + omega * (T)vanka_weight(t, si, sj, n) * c[t];
+                    x_out[t * L.plane + s0] =
+                        xown[t] + omega * (color < 0 ? (T)vanka_weight(t, si, sj, n) : (T)1) * c[t];
             });
         }
     }
@@ -394,12 +401,12 @@ __global__ __launch_bounds__(TPB * NZ, NZ == 2 ? 4 : (sizeof(P) == 4 ? 2 : 1)) v
                                                     const P* __restrict__ wblk,
                                                     const double* __restrict__ minv, T omega,
                                                     const T* __restrict__ xc, Layout Lc,
-                                                    const T* __restrict__ pw) {
+                                                    const T* __restrict__ pw, int color) {
     __shared__ VankaLds<T, P, UNIFORM, NCLS, PROL> sh;
     int bx, by;
     xcd_tile(bx, by);
     vanka_step_tile<T, P, UNIFORM, ZERO, NCLS, PROL, NZ>(x_in, b, x_out, L, kinv, kinv_s, coef, cls, wblk, minv, omega,
-                                                      xc, Lc, pw, bx, by, sh);
+                                                      xc, Lc, pw, color, bx, by, sh);
 }
 
 // thread layers of the constant-K step (two: 512 threads per tile, each phase split over twice
@@ -409,7 +416,8 @@ constexpr int VANKA_LAYERS = 2;
 
 template <typename T, typename P, bool UNIFORM, bool ZERO, bool PROL>
 static void launch_vanka_step_t(const LevelView<T>& lv, const T* x_in, const T* b, T* x_out, T kinv_s, T omega,
-                                const T* xc, const Layout& Lc, const T* pw, const LaunchTiming* tm, hipStream_t st) {
+                                const T* xc, const Layout& Lc, const T* pw, const LaunchTiming* tm, hipStream_t st,
+                                int color) {
     constexpr int NZ = UNIFORM ? VANKA_LAYERS : 1;
     dim3 blk(TB, TB, NZ);
     dim3 grd((lv.L.n + 1 + VO - 1) / VO, (lv.L.n + 1 + VO - 1) / VO);
@@ -426,46 +434,51 @@ static void launch_vanka_step_t(const LevelView<T>& lv, const T* x_in, const T* 
     // a tile spans at most two vertex classes per direction unless it covers the whole mesh
     if (lv.L.n + 1 <= VT)
         hipExtLaunchKernelGGL((k_vanka_step<T, P, UNIFORM, ZERO, 9, PROL, NZ>), grd, blk, 0, st, e0, e1, 0, x_in, b,
-                              x_out, lv.L, lv.kinv, kinv_s, lv.coef, cls, wblk, lv.minv, omega, xc, Lc, pw);
+                              x_out, lv.L, lv.kinv, kinv_s, lv.coef, cls, wblk, lv.minv, omega, xc, Lc, pw,
+                              color);
     else
         hipExtLaunchKernelGGL((k_vanka_step<T, P, UNIFORM, ZERO, 4, PROL, NZ>), grd, blk, 0, st, e0, e1, 0, x_in, b,
-                              x_out, lv.L, lv.kinv, kinv_s, lv.coef, cls, wblk, lv.minv, omega, xc, Lc, pw);
+                              x_out, lv.L, lv.kinv, kinv_s, lv.coef, cls, wblk, lv.minv, omega, xc, Lc, pw,
+                              color);
 }
 
 // the ZERO / PROL forms of one (T, P, UNIFORM)
 template <typename T, typename P, bool UNIFORM>
 static void launch_vanka_forms(const LevelView<T>& lv, const T* x_in, const T* b, T* x_out, T kinv_s, T omega,
-                               const T* xc, const Layout& lc, const T* pw, const LaunchTiming* tm, hipStream_t st) {
+                               const T* xc, const Layout& lc, const T* pw, const LaunchTiming* tm, hipStream_t st,
+                               int color) {
     if (xc)
-        launch_vanka_step_t<T, P, UNIFORM, false, true>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st);
+        launch_vanka_step_t<T, P, UNIFORM, false, true>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st, color);
     else if (x_in)
-        launch_vanka_step_t<T, P, UNIFORM, false, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st);
+        launch_vanka_step_t<T, P, UNIFORM, false, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st, color);
     else
-        launch_vanka_step_t<T, P, UNIFORM, true, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st);
+        launch_vanka_step_t<T, P, UNIFORM, true, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st, color);
 }
 
 template <typename T>
 void launch_vanka_step(const LevelView<T>& lv, const T* x_in, const T* b, T* x_out, bool uniform, T kinv_s,
-                       T omega, hipStream_t st, const T* xc, const Layout* Lc, const T* pw, const LaunchTiming* tm) {
+                       T omega, hipStream_t st, const T* xc, const Layout* Lc, const T* pw, const LaunchTiming* tm,
+                       int color) {
+    if (color < -1 || color > 3) throw ArgError{"Vanka colour: -1 (additive) or 0..3"};
     const Layout lc = Lc ? *Lc : lv.L;
     if (xc && !x_in) throw ArgError{"the prolongation needs an iterate"};
     if (uniform) {
-        launch_vanka_forms<T, double, true>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st);
+        launch_vanka_forms<T, double, true>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st, color);
         return;
     }
     if constexpr (std::is_same_v<T, float>) {
         if (lv.patch32) {
-            launch_vanka_forms<T, float, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st);
+            launch_vanka_forms<T, float, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st, color);
             return;
         }
     }
-    launch_vanka_forms<T, double, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st);
+    launch_vanka_forms<T, double, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st, color);
 }
 template void launch_vanka_step<double>(const LevelView<double>&, const double*, const double*, double*, bool,
                                         double, double, hipStream_t, const double*, const Layout*, const double*,
-                                        const LaunchTiming*);
+                                        const LaunchTiming*, int);
 template void launch_vanka_step<float>(const LevelView<float>&, const float*, const float*, float*, bool, float,
                                        float, hipStream_t, const float*, const Layout*, const float*,
-                                       const LaunchTiming*);
+                                       const LaunchTiming*, int);
 
 }  // namespace biot
