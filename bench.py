@@ -223,6 +223,40 @@ def schur_extra(binding, inputs, torch, sweeps=2, omega_S=1.0):
                       "sweeps_%d" % sweeps: {"iters": tot[sweeps][0], "ms": round(tot[sweeps][1], 1)}}}
 
 
+def multicolor_extra(binding, inputs, torch, omega_m=0.9):
+    """Vanka on the sweep256 parameter sets, one solve at a time (FP64, 1e-8): the paper's additive
+    V(2,2) cycle against the four-colour multiplicative V(1,1) cycle (weight omega_m).  Per unit of
+    smoothing traffic: a fused Vanka launch moves the same bytes in both forms; an additive V(2,2)
+    cycle makes 4 launches per level, a multiplicative V(1,1) cycle 8."""
+    w = inputs.workload("sweep256")
+    n, levels = w["n"], w["levels"]
+    b = torch.tensor(inputs.rhs_uniform(n, w["seed"]), dtype=torch.float64, device="cuda")
+    rows = []
+    tot = {"additive": [0, 0.0, 0], "multiplicative": [0, 0.0, 0]}
+    for case in w["cases"]:
+        om, omj = inputs.relaxation_weights("vanka", case["nu"], case["K"])
+        row = {"nu": case["nu"], "K": case["K"]}
+        for form, nu12, omega, colors, per_cycle in (("additive", 2, om, 0, 4), ("multiplicative", 1, omega_m, 4, 8)):
+            s = binding.BiotSolver(n, case["lam"], case["mu"], alpha=w["alpha"], M=w["M"], mu_f=w["mu_f"],
+                                   tau=w["tau"], K=case["K"])
+            s.setup(levels=levels, smoother="vanka", nu1=nu12, nu2=nu12, omega=omega, omega_J=omj,
+                    vanka_colors=colors)
+            s.solve(b, tol=1e-8, restart=30, maxit=500)                 # warm-up
+            (x, info), ms = _timed(lambda: s.solve(b, tol=1e-8, restart=30, maxit=500))
+            s.close()
+            row[form] = {"iters": info["iters"], "ms": round(ms, 2), "converged": bool(info["converged"]),
+                         "fused_launches_per_level": per_cycle * info["iters"]}
+            tot[form][0] += info["iters"]
+            tot[form][1] += ms
+            tot[form][2] += per_cycle * info["iters"]
+        rows.append(row)
+    return {"workload": "sweep256 Vanka parameter sets, one solve at a time, FP64, 1e-8; additive V(2,2) with the "
+                        "LFA weights, multiplicative V(1,1) with omega %.2f" % omega_m,
+            "cases": rows,
+            "total": {k: {"iters": v[0], "ms": round(v[1], 1), "fused_launches_per_level": v[2]}
+                      for k, v in tot.items()}}
+
+
 def precision_extra(binding, inputs, torch):
     """The 1024 x 1024 heterogeneous-permeability workload solved by the plain FP64 form and by the
     two precision forms: "fp32" (FP32 vectors and residuals, FP64 patch arithmetic and Krylov) and
@@ -487,7 +521,8 @@ def main():
         extras = {"precision_form": precision_extra(binding, inputs, torch),
                   "adjoint": adjoint_extra(binding, inputs, torch),
                   "kernels_2048": large_mesh_extra(binding, inputs, torch),
-                  "bsr_schur_sweeps": schur_extra(binding, inputs, torch)}
+                  "bsr_schur_sweeps": schur_extra(binding, inputs, torch),
+                  "vanka_multiplicative": multicolor_extra(binding, inputs, torch)}
     if args.block2048:
         extras = extras or {}
         extras["block2048"] = block2048_extra(binding, inputs, torch)
