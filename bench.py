@@ -388,11 +388,20 @@ def main():
     b = torch.tensor(b_np, dtype=torch.float64, device="cuda")
     x = torch.empty_like(b)
     runs = []
+    # the parameter sets of sweep256 carry a scalar K; the other workloads a per-triangle field
+    if args.workload != "sweep256":
+        smoothers = [sm for sm in smoothers if sm in w["smoothers"]]
+    Kfield = None
+    if any("K" not in case for case in w["cases"]):
+        Kfield = torch.tensor(inputs.permeability_triangles(args.workload), dtype=torch.float64, device="cuda")
     for sm in smoothers:
         for case in w["cases"]:
-            om, omj = weights(sm, case["nu"], case["K"])
+            if args.workload == "sweep256":
+                om, omj = weights(sm, case["nu"], case["K"])
+            else:
+                om, omj = inputs.relaxation_weights(sm, workload=args.workload)
             s = binding.BiotSolver(n, case["lam"], case["mu"], alpha=w["alpha"], M=w["M"], mu_f=w["mu_f"],
-                                   tau=w["tau"], K=case["K"])
+                                   tau=w["tau"], K=case.get("K", Kfield))
             nu12 = w["nu12"][sm]
             s.setup(levels=levels, smoother=sm, nu1=nu12, nu2=nu12, omega=om, omega_J=omj,
                     precision=args.precision)
@@ -481,7 +490,7 @@ def main():
     per_case = []
     for k, r in enumerate(runs):
         info = infos[k]
-        per_case.append({"smoother": r["smoother"], "nu": r["case"]["nu"], "K": r["case"]["K"],
+        per_case.append({"smoother": r["smoother"], "nu": r["case"]["nu"], "K": r["case"].get("K", "field"),
                          "omega": r["omega"], "omega_J": r["omega_J"], "iters": info["iters"],
                          "rel_res_true": info["rel_res_true"], "converged": info["converged"],
                          "solve_ms_sequential": round(seq[k]["solve_ms"], 3)})
@@ -496,8 +505,8 @@ def main():
                   "per_smoother": per_smoother}
     all_conv = all(i["converged"] for i in infos)
     word = 8 if args.precision == "fp64" else 4
-    # fused step with constant K: read x_in and b, write x_out
-    bytes_per_launch = 3 * word * nf
+    # fused step: read x_in and b, write x_out; with a permeability field also read 1/K (2 n^2)
+    bytes_per_launch = 3 * word * nf + (2 * word * n * n if Kfield is not None else 0)
     roofline = None
     if vk_n > 0:
         avg_s = vk_ms / vk_n * 1e-3
@@ -527,7 +536,7 @@ def main():
         extras = extras or {}
         extras["block2048"] = block2048_extra(binding, inputs, torch)
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "sweep256":
         r0 = runs[0]
         cpu = cpu_baseline(r0["case"], b_np, infos[0]["iters"], r0["nu12"], r0["omega"], r0["omega_J"],
                            r0["smoother"], n, levels)
