@@ -6,6 +6,11 @@ TEST INFRASTRUCTURE ONLY: run by hand, it writes paper_2107_04060_amd/relaxation
 the table of weights the workloads use.  Nothing in the product path imports this module.
 
     python -m oracle.relaxation_weights
+    python -m oracle.relaxation_weights --table4
+
+The second form applies the same inexact-BSR search to the cells of the paper's Table 4
+(h = 1/64, E = 3e4, M = 1e6, alpha = mu_f = tau = 1) and writes
+tests/golden/table4_bsr_lfa_weights.txt.
 
 Each parameter set is analysed at its own cell size h and physical parameters.  Vanka:
 omega on a 0.02 grid; inexact BSR: (omega_J, omega) on a 0.05 grid with 16 x 16 frequency
@@ -99,5 +104,33 @@ def main():
     print("wrote", OUT)
 
 
+TABLE4 = os.path.join(ROOT, "tests", "golden", "table4_bsr_lfa_weights.txt")
+
+
+def _table4_cell(nk):
+    nu, k = nk
+    lam, mu = lame(3e4, nu)
+    P = BiotParams(lam, mu, alpha=1.0, M=1e6, mu_f=1.0, tau=1.0)
+    return nu, k, bsr_weights(P, 1 / 64, k, 1)
+
+
+def table4():
+    """Inexact-BSR weights of this search for the cells of Table 4 (Sec. 5.1)."""
+    from multiprocessing import Pool
+    cells = [(nu, k) for nu in (0.0, 0.2, 0.4, 0.45, 0.49, 0.499) for k in (1.0, 1e-2, 1e-4, 1e-6, 1e-8, 1e-10)]
+    with Pool(min(8, os.cpu_count() or 1)) as pool:
+        rows = pool.map(_table4_cell, cells)
+    with open(TABLE4, "w") as f:
+        f.write("# Inexact-BSR weights for the cells of Table 4 (Sec. 5.1: h = 1/64, E = 3e4, M = 1e6,\n"
+                "# alpha = mu_f = tau = 1, V(1,1)), from the two-grid LFA search of\n"
+                "# oracle/relaxation_weights.py: minimum of rho_LFA, and where rho_LFA is flat in omega_J\n"
+                "# (within 1e-3) the omega_J nearest 1.  Written by python -m oracle.relaxation_weights --table4.\n"
+                "# nu k omega_J omega rho_lfa\n")
+        for nu, k, w in rows:
+            f.write("%g %g %.2f %.2f %.4f\n" % (nu, k, w["omega_J"], w["omega"], w["rho_lfa"]))
+            print(nu, k, w, flush=True)
+    print("wrote", TABLE4)
+
+
 if __name__ == "__main__":
-    sys.exit(main())
+    sys.exit(table4() if "--table4" in sys.argv[1:] else main())

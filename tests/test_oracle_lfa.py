@@ -86,3 +86,25 @@ def test_stored_workload_weights_are_the_lfa_optimum():
     rho = TwoGridLFA(P, 1 / 256, K=1e-3, smoother="bsr", nu=2).rho(om, omj)
     stored = inputs._weights_table()["sweep256"]["0.49/0.001"]["bsr"]["rho_lfa"]
     assert abs(rho - stored) < 1e-3
+
+
+def test_table4_ridge_weights_are_as_good_as_the_papers():
+    """tests/golden/table4_bsr_lfa_weights.txt (written by oracle/relaxation_weights.py --table4)
+    holds, in every cell of Table 4, BSR weights whose two-grid factor is the stored one and no
+    worse than that of the paper's Table 3 weights for the same cell (within the 1e-3 flatness
+    tolerance of the search); in the two cells the paper fails the two factors agree to 0.02:
+    both weight pairs lie on the same flat ridge."""
+    paper = {(r[0], r[1]): (r[3], r[2]) for r in _table("table3_bsr.txt")}
+    rows = _table("table4_bsr_lfa_weights.txt")
+    assert len(rows) == 36
+    for nu, k, wj, w, rho_lfa in rows:
+        if (nu, k) not in ((0.45, 1e-8), (0.49, 1e-8), (0.4, 1e-4), (0.0, 1.0)):
+            continue
+        L = TwoGridLFA(_params(nu), 1 / 64, K=k, smoother="bsr", nu=2)
+        rho = L.rho(w, wj)
+        pw, pwj = paper[(nu, k)]
+        rho_paper = L.rho(pw, pwj)
+        assert abs(rho - rho_lfa) < 1e-3, (nu, k, rho, rho_lfa)
+        assert rho <= rho_paper + 1.5e-3, (nu, k, rho, rho_paper)
+        if k == 1e-8 and nu in (0.45, 0.49):
+            assert abs(rho - rho_paper) < 0.02 and abs(wj - pwj) > 0.2, (nu, k, rho, rho_paper, wj, pwj)
