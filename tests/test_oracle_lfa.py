@@ -90,10 +90,11 @@ def test_stored_workload_weights_are_the_lfa_optimum():
 
 def test_table4_ridge_weights_are_as_good_as_the_papers():
     """tests/golden/table4_bsr_lfa_weights.txt (written by oracle/relaxation_weights.py --table4)
-    holds, in every cell of Table 4, BSR weights whose two-grid factor is the stored one and no
-    worse than that of the paper's Table 3 weights for the same cell (within the 1e-3 flatness
-    tolerance of the search); in the two cells the paper fails the two factors agree to 0.02:
-    both weight pairs lie on the same flat ridge."""
+    holds one BSR weight pair per cell of Table 4.  In sampled cells (the paper's two failures,
+    the cell where the paper's weights need 341 iterations here, and one plain cell) the stored
+    two-grid factor is reproduced and is no worse than that of the paper's Table 3 weights
+    (within the search's 1e-3 flatness tolerance); in the two failing cells the two factors agree
+    to 0.02 while omega_J differs by more than 0.2: both pairs lie on the same flat ridge."""
     paper = {(r[0], r[1]): (r[3], r[2]) for r in _table("table3_bsr.txt")}
     rows = _table("table4_bsr_lfa_weights.txt")
     assert len(rows) == 36
