@@ -1,0 +1,125 @@
+"""Edge cases of the solve boundary on the GPU (FGMRES + V-cycle, Sec. 5.1), checked against the
+oracle where a value is computed:
+
+* a zero right-hand side returns x = 0 at once, converged, with no iteration;
+* an iteration limit returns BIOT_NOT_CONVERGED with the information filled in and the last
+  iterate, which is the oracle FGMRES's iterate after the same number of steps (with restarts in
+  between), and whose true residual, recomputed on the CPU, is the reported one;
+* NaN or Inf in the right-hand side returns BIOT_ERR_NAN, and the context still solves afterwards;
+* invalid hierarchy options return BIOT_ERR_ARG and leave the context usable for a valid setup;
+* a two-level hierarchy (one smoothing level over the direct solve) takes the oracle's iteration
+  count.
+
+All solves use Vanka V(2,2) with omega = 0.9 on the 16 x 16 workload's physics (lambda = mu = 1,
+K = 1, M from E / (alpha^2 M) = 0.03).  V(1,1) with that weight does not converge there, in the
+oracle as on the GPU: FGMRES(30) stays at relative residual 0.99 for 500 iterations.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_2107_04060_amd import inputs  # noqa: E402
+from oracle.fem import Assembly  # noqa: E402
+from oracle.krylov import fgmres  # noqa: E402
+from oracle.mesh import Mesh  # noqa: E402
+from oracle.multigrid import Hierarchy  # noqa: E402
+from gpu_cases import case, params  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def binding():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2107_04060_amd import binding as b
+    b.load()
+    return b
+
+
+def _t(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _solver(binding, n=16, levels=3, setup=True):
+    lam, mu, al, M, mf_, tau = case("small")
+    s = binding.BiotSolver(n, lam, mu, alpha=al, M=M, mu_f=mf_, tau=tau, K=1.0)
+    if setup:
+        s.setup(levels=levels, smoother="vanka", nu1=2, nu2=2, omega=0.9)
+    return s
+
+
+def test_zero_rhs(binding):
+    print("zero right-hand side n=16", flush=True)
+    s = _solver(binding)
+    x, info = s.solve(torch.zeros(s.nf(), dtype=torch.float64, device="cuda"))
+    s.close()
+    assert info["code"] == binding.BIOT_OK and info["converged"] and info["iters"] == 0
+    assert int(torch.count_nonzero(x)) == 0
+
+
+def test_iteration_limit_returns_the_last_iterate(binding):
+    n = 16
+    print("iteration limit n=16 restart 2 maxit 5", flush=True)
+    s = _solver(binding, n)
+    b = inputs.rhs_uniform(n, 0)
+    x, info = s.solve(_t(b), tol=1e-14, restart=2, maxit=5)
+    s.close()
+    x = x.cpu().numpy()
+    assert info["code"] == binding.BIOT_NOT_CONVERGED and not info["converged"] and info["iters"] == 5
+    A = Assembly(Mesh(n), params("small"), 1.0).A
+    rel = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+    H = Hierarchy(n, params("small"), smoother="vanka", omega=0.9, nu1=2, nu2=2, levels=3)
+    xo, io = fgmres(H.A, b, H.vcycle, tol=1e-14, restart=2, maxit=5)
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    print("  rel. residual %.3e (reported %.3e, oracle %.3e); iterate rel diff %.2e"
+          % (rel, info["rel_res_true"], io["rel_res_true"], err), flush=True)
+    assert not io["converged"] and io["iters"] == 5
+    assert abs(rel - info["rel_res_true"]) <= 1e-9 * rel
+    assert err < 1e-9
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf])
+def test_nonfinite_rhs_is_reported_and_the_context_survives(binding, bad):
+    n = 16
+    print("non-finite right-hand side (%r) n=16" % bad, flush=True)
+    s = _solver(binding, n)
+    b = inputs.rhs_uniform(n, 0)
+    bb = b.copy()
+    bb[17] = bad
+    with pytest.raises(binding.BiotError) as e:
+        s.solve(_t(bb))
+    assert e.value.code == binding.BIOT_ERR_NAN
+    x, info = s.solve(_t(b), tol=1e-8)
+    s.close()
+    assert info["converged"] and info["rel_res_true"] <= 1e-8
+
+
+def test_invalid_options_leave_the_context_usable(binding):
+    print("invalid hierarchy options n=16", flush=True)
+    s = _solver(binding, setup=False)
+    bad = [dict(levels=1), dict(levels=3, nu1=0, nu2=0), dict(levels=3, omega=0.0), dict(levels=3, omega=np.nan),
+           dict(levels=5), dict(levels=3, gamma=5), dict(levels=3, vanka_colors=2)]
+    for kw in bad:
+        with pytest.raises(binding.BiotError) as e:
+            s.setup(**kw)
+        assert e.value.code == binding.BIOT_ERR_ARG, kw
+    s.setup(levels=3, smoother="vanka", nu1=2, nu2=2, omega=0.9)
+    x, info = s.solve(_t(inputs.rhs_uniform(16, 0)), tol=1e-8)
+    s.close()
+    assert info["converged"]
+
+
+def test_two_level_hierarchy_matches_oracle(binding):
+    n = 8
+    print("two-level hierarchy n=8", flush=True)
+    s = _solver(binding, n, levels=2)
+    b = inputs.rhs_uniform(n, 3)
+    x, info = s.solve(_t(b), tol=1e-10, restart=30, maxit=100)
+    s.close()
+    H = Hierarchy(n, params("small"), smoother="vanka", omega=0.9, nu1=2, nu2=2, levels=2)
+    xo, io = fgmres(H.A, b, H.vcycle, tol=1e-10, restart=30, maxit=100)
+    print("  gpu %d iterations, oracle %d" % (info["iters"], io["iters"]), flush=True)
+    assert info["converged"] and io["converged"] and abs(info["iters"] - io["iters"]) <= 1
+    assert np.linalg.norm(H.A @ (x.cpu().numpy() - xo)) <= 2e-10 * np.linalg.norm(b)
