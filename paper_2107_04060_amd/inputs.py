@@ -88,7 +88,7 @@ def workload(name):
         E = young_from_lame(lam, mu)
         return dict(name=name, n=16, levels=3, cases=[dict(lam=lam, mu=mu, K=1.0)],
                     alpha=1.0, M=biot_modulus(E), mu_f=1.0, tau=1.0, seed=0,
-                    smoothers=["vanka"], nu12={"vanka": 1, "bsr": 1})
+                    smoothers=["vanka"], nu12={"vanka": 2, "bsr": 1})
     if name == "sweep256":
         cases = []
         for nu in (0.2, 0.49, 0.4999):
