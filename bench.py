@@ -369,7 +369,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build measures one GPU only (the solver has no multi-GPU path); "
+        print("bench.py: the solver runs on one GPU (it has no multi-GPU path); "
               "--gpus %d is not supported" % max(args.gpus, world), file=sys.stderr)
         sys.exit(2)
     import numpy as np
