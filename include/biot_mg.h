@@ -42,7 +42,10 @@
  * no other call allocates.
  *
  * Errors.  Every int-returning function returns one of the BIOT_* codes below and, on
- * failure, leaves a message for biot_last_error().  No C++ exception crosses the ABI.
+ * failure, leaves a message for biot_last_error().  No C++ exception crosses the ABI.  An
+ * invalid argument is rejected before anything changes, and after BIOT_ERR_NAN from
+ * biot_solve (NaN or Inf in the right-hand side or met during the iteration) the context
+ * stays valid for further solves.
  */
 #ifndef BIOT_MG_H
 #define BIOT_MG_H
