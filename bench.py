@@ -67,7 +67,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="sweep256")
+    ap.add_argument("--workload", default="sweep256", choices=["sweep256", "small", "grf1024"],
+                    help="the timed workload; block2048 and adjoint512 run as extras (--block2048)")
     ap.add_argument("--smoothers", default="vanka,bsr")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "fp32_patch"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
