@@ -93,6 +93,11 @@ def weights(smoother, nu, K):
     return inputs.relaxation_weights(smoother, nu, K)
 
 
+def poisson(case):
+    """Poisson ratio of a parameter set given by its Lame parameters."""
+    return round(case["lam"] / (2.0 * (case["lam"] + case["mu"])), 6)
+
+
 def cpu_baseline(case, b, iters, nu12, omega, omega_J, smoother, n, levels):
     """Oracle (plain FP64 NumPy/SciPy, single thread) on a bounded sample of the workload:
     the time of one FGMRES iteration (one V-cycle, one matvec, Gram-Schmidt) of one
@@ -491,7 +496,7 @@ def main():
     per_case = []
     for k, r in enumerate(runs):
         info = infos[k]
-        per_case.append({"smoother": r["smoother"], "nu": r["case"]["nu"], "K": r["case"].get("K", "field"),
+        per_case.append({"smoother": r["smoother"], "nu": r["case"].get("nu", poisson(r["case"])), "K": r["case"].get("K", "field"),
                          "omega": r["omega"], "omega_J": r["omega_J"], "iters": info["iters"],
                          "rel_res_true": info["rel_res_true"], "converged": info["converged"],
                          "solve_ms_sequential": round(seq[k]["solve_ms"], 3)})
