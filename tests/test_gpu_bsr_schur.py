@@ -80,3 +80,24 @@ def test_schur_sweeps_rescue_failing_cells(binding, nu, omega, omega_J):
     assert io["converged"] and io["iters"] <= 30
     assert res["fp64"]["converged"] and abs(res["fp64"]["iters"] - io["iters"]) <= 1
     assert res["fp32"]["converged"] and res["fp32"]["iters"] <= io["iters"] + 3
+
+
+def test_many_sweeps_approach_the_exact_schur_solve(binding):
+    """Towards the exact Schur solve (the oracle pins that the sweeps converge to a sparse LU
+    solve of S_hat): on the paper's failing cell nu = 0.45, k = 1e-8 with the paper's weights,
+    2, 8 and 64 sweeps all converge, more sweeps never take more iterations, and 8 and 64 sweeps
+    differ by at most two."""
+    lam, mu = inputs.lame(3e4, 0.45)
+    P = BiotParams(lam, mu, alpha=1.0, M=1e6, mu_f=1.0, tau=1.0)
+    b = _t(mf.rhs(64, P))
+    its = {}
+    for sw in (2, 8, 64):
+        s = binding.BiotSolver(64, lam, mu, alpha=1.0, M=1e6, mu_f=1.0, tau=1.0, K=1e-8)
+        s.setup(levels=4, smoother="bsr", nu1=1, nu2=1, omega=0.74, omega_J=1.26, schur_sweeps=sw, omega_S=1.0)
+        _, info = s.solve(b, tol=1e-6, restart=30, maxit=100)
+        s.close()
+        assert info["converged"], sw
+        its[sw] = info["iters"]
+    print("  nu 0.45 k 1e-8, Schur sweeps -> iterations: %s" % its, flush=True)
+    assert its[64] <= its[8] <= its[2]
+    assert its[8] - its[64] <= 2
