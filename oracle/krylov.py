@@ -91,3 +91,64 @@ def fgmres_fixed(A, b, precond, iters):
     e1[0] = bnorm
     y, *_ = np.linalg.lstsq(H, e1, rcond=None)
     return Z.T @ y
+
+
+def gmres_left(A, b, precond, tol=1e-8, restart=30, maxit=500):
+    """Restarted GMRES on the left-preconditioned system M^{-1} A x = M^{-1} b, x0 = 0, stopping
+    when the preconditioned residual ||M^{-1}(b - A x)||_2 <= tol ||M^{-1} b||_2 (the relative
+    residual of the system GMRES actually solves).  Modified Gram-Schmidt, Givens rotations; the
+    preconditioner must be a fixed linear operator (one V-cycle from a zero initial guess is).
+    Return (x, info) with info = dict(iters, converged, rel_res_prec, rel_res_true, history)."""
+    n = b.shape[0]
+    x = np.zeros(n)
+    bnorm = np.linalg.norm(b)
+    if bnorm == 0.0:
+        return x, dict(iters=0, converged=True, rel_res_prec=0.0, rel_res_true=0.0, history=[0.0])
+    z = precond(b)
+    znorm = np.linalg.norm(z)
+    beta = znorm
+    hist = [1.0]
+    it = 0
+    while True:
+        if beta <= tol * znorm or it >= maxit:
+            r = b - A @ x
+            return x, dict(iters=it, converged=bool(beta <= tol * znorm), rel_res_prec=beta / znorm,
+                           rel_res_true=np.linalg.norm(r) / bnorm, history=hist)
+        m = restart
+        V = np.zeros((m + 1, n))
+        H = np.zeros((m + 1, m))
+        cs = np.zeros(m)
+        sn = np.zeros(m)
+        g = np.zeros(m + 1)
+        g[0] = beta
+        V[0] = z / beta
+        k = 0
+        for j in range(m):
+            w = precond(A @ V[j])
+            for i in range(j + 1):                  # modified Gram-Schmidt
+                H[i, j] = np.dot(w, V[i])
+                w = w - H[i, j] * V[i]
+            H[j + 1, j] = np.linalg.norm(w)
+            if H[j + 1, j] != 0.0:
+                V[j + 1] = w / H[j + 1, j]
+            for i in range(j):                      # previous rotations
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            den = np.hypot(H[j, j], H[j + 1, j])
+            cs[j] = H[j, j] / den
+            sn[j] = H[j + 1, j] / den
+            H[j, j] = den
+            H[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            it += 1
+            k = j + 1
+            hist.append(abs(g[j + 1]) / znorm)
+            if abs(g[j + 1]) <= tol * znorm or it >= maxit:
+                break
+        y = np.linalg.solve(np.triu(H[:k, :k]), g[:k])
+        x = x + V[:k].T @ y
+        z = precond(b - A @ x)
+        beta = np.linalg.norm(z)
+        hist[-1] = beta / znorm
