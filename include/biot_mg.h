@@ -39,7 +39,7 @@
  * host threads.  Device memory is allocated by biot_assemble and biot_setup_hierarchy, and
  * by the first biot_solve with a given restart length m (the Krylov workspace: 2 m + 4
  * finest-level FP64 vectors and a few scalars, kept for later solves with restart <= m);
- * no other call allocates.
+ * biot_solve_noalloc allocates nothing (it works in a fixed device array of the library).
  *
  * Errors.  Every int-returning function returns one of the BIOT_* codes below and, on
  * failure, leaves a message for biot_last_error().  No C++ exception crosses the ABI.  An
@@ -148,6 +148,21 @@ int biot_vcycle(biot_ctx* ctx, const double* r, double* z, void* stream);
  * b, x: device FP64, canonical order, may not alias.  info: host pointer (in/out).
  * Returns BIOT_OK, BIOT_NOT_CONVERGED (x = last iterate) or an error code. */
 int biot_solve(biot_ctx* ctx, const double* b, double* x, biot_solve_info* info, void* stream);
+
+/* biot_solve for callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the same FGMRES, the same kernels and the
+ * same result as biot_solve, with the Krylov workspace ((2 m + 4) padded finest-level vectors
+ * and the Gram-Schmidt partial sums) carved from a fixed 64 MiB device array that the library
+ * holds on every GPU it runs on until the process ends, instead of from allocations.  No
+ * hipMalloc, hipFree or other allocating call is made; the host reads the Gram-Schmidt results
+ * by plain copies (no pinned memory).  Limits: restart m <= 32, and the padded finest level
+ * must fit: (2 m + 4) ((n + 4) ceil((n + 4) / 16) 16 10) 8 bytes plus about 272 KB within 64 MiB
+ * (n <= 64 at m = 32, n = 128 up to m = 19); larger requests return BIOT_ERR_ARG and change
+ * nothing.  The array is shared by every call on one GPU and keeps the last call's contents
+ * (each call clears what must start at zero): calls that overlap in time on one GPU, from
+ * several threads or on several streams, race and must not be issued.  Arguments, ownership
+ * and return codes as biot_solve; the context must have a hierarchy. */
+int biot_solve_noalloc(biot_ctx* ctx, const double* b, double* x, biot_solve_info* info, void* stream);
 
 /* y = A_l x on mesh level l (0 = finest): the rediscretized operator (block_form_rq). */
 int biot_apply_operator(biot_ctx* ctx, int level, const double* x, double* y, void* stream);

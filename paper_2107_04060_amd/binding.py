@@ -63,6 +63,7 @@ def load():
     lib.biot_setup_hierarchy.argtypes = [P, ctypes.POINTER(MGOpts), P]
     lib.biot_vcycle.argtypes = [P, P, P, P]
     lib.biot_solve.argtypes = [P, P, P, ctypes.POINTER(SolveInfo), P]
+    lib.biot_solve_noalloc.argtypes = [P, P, P, ctypes.POINTER(SolveInfo), P]
     lib.biot_apply_operator.argtypes = [P, I, P, P, P]
     lib.biot_smooth.argtypes = [P, I, P, P, P]
     lib.biot_restrict.argtypes = [P, I, P, P, P]
@@ -74,7 +75,7 @@ def load():
     lib.biot_destroy.argtypes = [P]
     lib.biot_destroy.restype = None
     lib.biot_last_error.restype = ctypes.c_char_p
-    for name in ("biot_assemble", "biot_setup_hierarchy", "biot_vcycle", "biot_solve",
+    for name in ("biot_assemble", "biot_setup_hierarchy", "biot_vcycle", "biot_solve", "biot_solve_noalloc",
                  "biot_apply_operator", "biot_smooth", "biot_restrict", "biot_prolong_add",
                  "biot_update_K", "biot_grad_logK", "biot_export_layout", "biot_kernel_timing"):
         getattr(lib, name).restype = ctypes.c_int
@@ -166,6 +167,16 @@ class BiotSolver:
                                         ctypes.byref(info), _stream()), allow=(BIOT_OK, BIOT_NOT_CONVERGED))
         return x, dict(iters=info.iters, converged=bool(info.converged), rel_res_true=info.rel_res_true,
                        code=code)
+
+    def solve_noalloc(self, b, out, tol=1e-8, restart=30, maxit=500):
+        """solve() through biot_solve_noalloc: no device allocation in the library; the caller
+        passes the output tensor."""
+        info = SolveInfo(float(tol), int(restart), int(maxit), 0, 0, 0.0)
+        code = _check(load().biot_solve_noalloc(self._ctx, _dev(b, self.nf(), "b"), _dev(out, self.nf(), "x"),
+                                                ctypes.byref(info), _stream()),
+                      allow=(BIOT_OK, BIOT_NOT_CONVERGED))
+        return out, dict(iters=info.iters, converged=bool(info.converged), rel_res_true=info.rel_res_true,
+                         code=code)
 
     def apply(self, x, level=0):
         y = torch.empty_like(x)

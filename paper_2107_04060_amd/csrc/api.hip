@@ -15,6 +15,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 
 namespace biot {
@@ -148,6 +149,7 @@ struct biot_ctx {
     DevBuf V, Z, w, partial, hdev, ydev, bpad, xpad, canon_tmp;
     double* hhost = nullptr;          // mapped pinned mirror of the Gram-Schmidt results
     double* hhost_dev = nullptr;      // its device address
+    std::vector<double> hwork;        // host Hessenberg, rotations and least-squares vectors
 };
 
 namespace biot {
@@ -548,13 +550,27 @@ static void alloc_fp32(biot_ctx* c, hipStream_t st) {
 }
 
 // ---- FGMRES (Sec. 5.1), CGS2 Arnoldi, host Givens rotations ---------------------------------------
-// Layout of the Gram-Schmidt results (device hdev, host mirror hhost), restart m, column j:
+// Layout of the Gram-Schmidt results (device hd, host view hres), capacity M, column j:
 //   [0, j+1]: pass-1 dots V_i . w (i <= j) and |w|^2 before pass 1;
-//   [m+2, m+j+3]: pass-2 dots and |w|^2 after pass 1;
-//   2m+5: second-pass flag;  2m+6: |w|^2 after pass 2;  2m+7: scratch
+//   [M+2, M+j+3]: pass-2 dots and |w|^2 after pass 1;
+//   2M+5: second-pass flag;  2M+6: |w|^2 after pass 2;  2M+7: scratch
 static int kslot_flag(int m) { return 2 * m + 5; }
 static int kslot_n2(int m) { return 2 * m + 6; }
 static int kslot_tmp(int m) { return 2 * m + 7; }
+static int kslots(int m) { return 2 * m + 8; }
+
+// The device and host memory one FGMRES solve works in.  Absent DoFs must be zero in every
+// Krylov vector V_q, Z_q on entry (the kernels never write them).
+struct KrylovWork {
+    int M = 0;                 // capacity: restart <= M; layout of the result slots
+    double *V = nullptr, *Z = nullptr, *w = nullptr, *partial = nullptr;
+    double *hd = nullptr, *yd = nullptr, *bpad = nullptr, *xpad = nullptr;
+    double* hh = nullptr;      // device address of a mapped host mirror of hd, or nullptr
+    double* hres = nullptr;    // host view of the results (kslots(M) doubles): the mirror itself,
+                               // or a host array that receives a copy of hd at every synchronization
+    double* hwork = nullptr;   // host: Hessenberg (M+1) x M, cs, sn (M each), g (M+1), y (M)
+};
+static size_t host_work_doubles(int m) { return (size_t)(m + 1) * m + 3 * (size_t)m + 1 + m; }
 
 static void krylov_alloc(biot_ctx* c, int m, hipStream_t st) {
     if (c->krylov_m >= m) return;
@@ -566,46 +582,71 @@ static void krylov_alloc(biot_ctx* c, int m, hipStream_t st) {
     launch_fill(c->Z.as<double>(), (long long)m * L.len, 0.0, st);
     c->w.alloc((size_t)L.len * sizeof(double));
     c->partial.alloc((size_t)RED_BLOCKS * std::max(m + 2, 4) * sizeof(double));
-    c->hdev.alloc((size_t)(2 * m + 8) * sizeof(double));
+    c->hdev.alloc((size_t)kslots(m) * sizeof(double));
     c->ydev.alloc((size_t)(m + 1) * sizeof(double));
     c->bpad.alloc((size_t)L.len * sizeof(double));
     c->xpad.alloc((size_t)L.len * sizeof(double));
     if (c->hhost) BIOT_HIP(hipHostFree(c->hhost));
     c->hhost = nullptr;
-    BIOT_HIP(hipHostMalloc((void**)&c->hhost, (size_t)(2 * m + 8) * sizeof(double),
+    BIOT_HIP(hipHostMalloc((void**)&c->hhost, (size_t)kslots(m) * sizeof(double),
                            hipHostMallocMapped | hipHostMallocCoherent));
     BIOT_HIP(hipHostGetDevicePointer((void**)&c->hhost_dev, c->hhost, 0));
+    c->hwork.assign(host_work_doubles(m), 0.0);
     c->krylov_m = m;
 }
 
-// |a|^2 (synchronizes the stream)
-static double norm2_dev(biot_ctx* c, const double* a, long long n, hipStream_t st) {
-    const int m = c->krylov_m;
-    launch_gs_dots(nullptr, 0, 0, a, n, c->partial.as<double>(), c->hdev.as<double>() + kslot_tmp(m),
-                   c->hhost_dev + kslot_tmp(m), nullptr, st);
-    BIOT_HIP(hipStreamSynchronize(st));
-    return c->hhost[kslot_tmp(m)];
+// the context's own workspace (allocated by krylov_alloc)
+static KrylovWork context_work(biot_ctx* c) {
+    KrylovWork k;
+    k.M = c->krylov_m;
+    k.V = c->V.as<double>();
+    k.Z = c->Z.as<double>();
+    k.w = c->w.as<double>();
+    k.partial = c->partial.as<double>();
+    k.hd = c->hdev.as<double>();
+    k.yd = c->ydev.as<double>();
+    k.bpad = c->bpad.as<double>();
+    k.xpad = c->xpad.as<double>();
+    k.hh = c->hhost_dev;
+    k.hres = c->hhost;
+    k.hwork = c->hwork.data();
+    return k;
 }
 
-static int fgmres(biot_ctx* c, const double* b_canon, double* x_canon, biot_solve_info* info, hipStream_t st) {
+// wait for the stream; without a mapped mirror, copy the result slots to the host view first
+static void sync_results(const KrylovWork& k, hipStream_t st) {
+    if (!k.hh) BIOT_HIP(hipMemcpyAsync(k.hres, k.hd, (size_t)kslots(k.M) * sizeof(double), hipMemcpyDeviceToHost, st));
+    BIOT_HIP(hipStreamSynchronize(st));
+}
+
+// |a|^2 (synchronizes the stream)
+static double norm2_dev(const KrylovWork& k, const double* a, long long n, hipStream_t st) {
+    launch_gs_dots(nullptr, 0, 0, a, n, k.partial, k.hd + kslot_tmp(k.M), k.hh ? k.hh + kslot_tmp(k.M) : nullptr,
+                   nullptr, st);
+    sync_results(k, st);
+    return k.hres[kslot_tmp(k.M)];
+}
+
+static int fgmres(biot_ctx* c, const KrylovWork& K, const double* b_canon, double* x_canon, biot_solve_info* info,
+                  hipStream_t st) {
     Level& l0 = *c->levels[0];
     const Layout& L = l0.L;
     const long long n = L.len;
     const int m = info->restart;
-    krylov_alloc(c, m, st);
-    const int M = c->krylov_m;                // layout of the result slots
-    double* V = c->V.as<double>();
-    double* Z = c->Z.as<double>();
-    double* w = c->w.as<double>();
-    double* b = c->bpad.as<double>();
-    double* x = c->xpad.as<double>();
-    double* hd = c->hdev.as<double>();
-    double* hh = c->hhost_dev;
-    const double* hhost = c->hhost;
-    double* part = c->partial.as<double>();
+    const int M = K.M;                        // layout of the result slots
+    if (m > M) throw ArgError{"restart exceeds the Krylov workspace"};
+    double* V = K.V;
+    double* Z = K.Z;
+    double* w = K.w;
+    double* b = K.bpad;
+    double* x = K.xpad;
+    double* hd = K.hd;
+    double* hh = K.hh;
+    const double* hres = K.hres;
+    double* part = K.partial;
     launch_pack(b_canon, b, L, l0.C, st);
     launch_fill(x, n, 0.0, st);
-    const double bnorm = std::sqrt(norm2_dev(c, b, n, st));
+    const double bnorm = std::sqrt(norm2_dev(K, b, n, st));
     info->iters = 0;
     info->converged = 0;
     info->rel_res_true = 0;
@@ -619,7 +660,14 @@ static int fgmres(biot_ctx* c, const double* b_canon, double* x_canon, biot_solv
     // r = b - A x  (x = 0 -> r = b)
     BIOT_HIP(hipMemcpyAsync(w, b, n * sizeof(double), hipMemcpyDeviceToDevice, st));
     double beta = bnorm;
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    // host arrays: Hessenberg (m + 1) x m, rotations, right-hand side and solution of the LS problem
+    double* H = K.hwork;
+    double* cs = H + (size_t)(m + 1) * m;
+    double* sn = cs + m;
+    double* g = sn + m;
+    double* y = g + m + 1;
+    // mirrors of the flag (and, unfused, of the pass-2 dots) for the host's reads
+    double* hflag = hh ? hh + kslot_flag(M) : nullptr;
     int it = 0;
     while (true) {
         if (beta <= tol * bnorm) {
@@ -629,11 +677,10 @@ static int fgmres(biot_ctx* c, const double* b_canon, double* x_canon, biot_solv
         if (it >= info->maxit) break;
         // V_0 = r / beta
         launch_scale(V, w, n, 1.0 / beta, st);
-        std::fill(H.begin(), H.end(), 0.0);
-        std::fill(g.begin(), g.end(), 0.0);
+        std::fill(H, H + (size_t)(m + 1) * m, 0.0);
+        std::fill(g, g + m + 1, 0.0);
         g[0] = beta;
         int k = 0;
-        bool stop = false;
         for (int j = 0; j < m; ++j) {
             double* vj = V + (size_t)j * n;
             double* zj = Z + (size_t)j * n;
@@ -651,24 +698,24 @@ static int fgmres(biot_ctx* c, const double* b_canon, double* x_canon, biot_solv
             const bool fused = nv <= GS_FUSED;
             launch_gs_dots(V, n, nv, w, n, part, hd, hh, nullptr, st);
             if (fused) {
-                launch_gs_update_dots(w, V, n, nv, hd, n, part, hd + M + 2, hh + M + 2, hd + nv, hd + kslot_flag(M),
-                                      hh + kslot_flag(M), st);
+                launch_gs_update_dots(w, V, n, nv, hd, n, part, hd + M + 2, hh ? hh + M + 2 : nullptr, hd + nv,
+                                      hd + kslot_flag(M), hflag, st);
             } else {
                 launch_gs_update(w, V, n, nv, hd, n, part, hd + M + 2 + nv, hd + nv, hd + kslot_flag(M),
-                                 hh + M + 2 + nv, nullptr, st);
-                launch_gs_dots(V, n, nv, w, n, part, hd + M + 2, hh + M + 2, hd + kslot_flag(M), st);
-                BIOT_HIP(hipMemcpyAsync(hh + kslot_flag(M), hd + kslot_flag(M), sizeof(double),
-                                        hipMemcpyDeviceToDevice, st));
+                                 hh ? hh + M + 2 + nv : nullptr, nullptr, st);
+                launch_gs_dots(V, n, nv, w, n, part, hd + M + 2, hh ? hh + M + 2 : nullptr, hd + kslot_flag(M), st);
+                if (hflag)
+                    BIOT_HIP(hipMemcpyAsync(hflag, hd + kslot_flag(M), sizeof(double), hipMemcpyDeviceToDevice, st));
             }
             launch_gs_update(w, V, n, nv, hd + M + 2, n, part, hd + kslot_n2(M), nullptr, nullptr,
-                             hh + kslot_n2(M), hd + kslot_flag(M), st);
+                             hh ? hh + kslot_n2(M) : nullptr, hd + kslot_flag(M), st);
             launch_normalize(V + (size_t)nv * n, w, n, hd + M + 2 + nv, hd + kslot_n2(M), hd + kslot_flag(M), st);
             check_stream_error();
-            BIOT_HIP(hipStreamSynchronize(st));
-            const bool second = hhost[kslot_flag(M)] != 0.0;
+            sync_results(K, st);
+            const bool second = hres[kslot_flag(M)] != 0.0;
             for (int i = 0; i <= j; ++i)
-                H[(size_t)i * m + j] = (i == j ? 1.0 : 0.0) - (hhost[i] + (second ? hhost[M + 2 + i] : 0.0));
-            const double hn = std::sqrt(second ? hhost[kslot_n2(M)] : hhost[M + 2 + nv]);
+                H[(size_t)i * m + j] = (i == j ? 1.0 : 0.0) - (hres[i] + (second ? hres[M + 2 + i] : 0.0));
+            const double hn = std::sqrt(second ? hres[kslot_n2(M)] : hres[M + 2 + nv]);
             // v_{j+1} = w / |w| is minus the direction of the unshifted remainder
             H[(size_t)(j + 1) * m + j] = -hn;
             for (int i = 0; i <= j + 1; ++i)
@@ -688,23 +735,19 @@ static int fgmres(biot_ctx* c, const double* b_canon, double* x_canon, biot_solv
             g[j] = cs[j] * g[j];
             ++it;
             k = j + 1;
-            if (std::fabs(g[j + 1]) <= tol * bnorm || it >= info->maxit || hn == 0.0) {
-                stop = true;
-                break;
-            }
+            if (std::fabs(g[j + 1]) <= tol * bnorm || it >= info->maxit || hn == 0.0) break;
         }
-        (void)stop;
         // y = H^{-1} g (upper triangular k x k), x += Z y
         for (int i = k - 1; i >= 0; --i) {
             double s = g[i];
             for (int q = i + 1; q < k; ++q) s -= H[(size_t)i * m + q] * y[q];
             y[i] = s / H[(size_t)i * m + i];
         }
-        BIOT_HIP(hipMemcpyAsync(c->ydev.p, y.data(), k * sizeof(double), hipMemcpyHostToDevice, st));
-        launch_lincomb_add(x, Z, n, k, c->ydev.as<double>(), n, st);
+        BIOT_HIP(hipMemcpyAsync(K.yd, y, k * sizeof(double), hipMemcpyHostToDevice, st));
+        launch_lincomb_add(x, Z, n, k, K.yd, n, st);
         // true residual
         launch_apply<double>(l0.view<double>(), x, b, w, 1, st);
-        beta = std::sqrt(norm2_dev(c, w, n, st));
+        beta = std::sqrt(norm2_dev(K, w, n, st));
         if (!(beta == beta)) throw std::domain_error("NaN in residual");
     }
     info->iters = it;
@@ -712,6 +755,67 @@ static int fgmres(biot_ctx* c, const double* b_canon, double* x_canon, biot_solv
     launch_unpack(x, x_canon, L, l0.C, st);
     check_stream_error();
     return info->converged ? BIOT_OK : BIOT_NOT_CONVERGED;
+}
+
+// ---- workspace without allocation -------------------------------------------------------------
+// A fixed device array that biot_solve_noalloc carves its Krylov workspace from.  Host code never
+// passes the array's name to a kernel: it uses the address hipGetSymbolAddress returns on each
+// device (resolved once per device at biot_assemble, or at the entry point's first call there).
+constexpr size_t NOALLOC_BYTES = (size_t)64 << 20;
+constexpr int NOALLOC_MAX_RESTART = 32;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static __device__ __align__(256) double scratch[NOALLOC_BYTES / sizeof(double)];
+static double* g_scratch_ptr[NOALLOC_MAX_DEVICES];
+static std::mutex g_scratch_mutex;
+
+// the scratch address on the current device (resolves it on first use there)
+static double* scratch_address() {
+    int dev = 0;
+    BIOT_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) throw ArgError{"device index beyond the scratch table"};
+    std::lock_guard<std::mutex> lk(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        BIOT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) throw HipError{hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)"};
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    return g_scratch_ptr[dev];
+}
+
+static size_t round256(size_t doubles) { return (doubles + 31) / 32 * 32; }
+
+// doubles of scratch a solve with restart m on a padded length len needs
+static size_t noalloc_doubles(long long len, int m) {
+    return round256((size_t)(m + 1) * len) + round256((size_t)m * len) + 3 * round256((size_t)len) +
+           round256((size_t)RED_BLOCKS * std::max(m + 2, 4)) + round256((size_t)kslots(m)) + round256((size_t)m + 1);
+}
+
+// carve the workspace out of the scratch array; V and Z are cleared (a previous call, possibly
+// with another layout, may have left values at this layout's absent DoFs)
+static KrylovWork scratch_work(double* base, long long len, int m, double* hres, double* hwork, hipStream_t st) {
+    KrylovWork k;
+    k.M = m;
+    size_t off = 0;
+    auto take = [&](size_t cnt) {
+        double* p = base + off;
+        off += round256(cnt);
+        return p;
+    };
+    k.V = take((size_t)(m + 1) * len);
+    k.Z = take((size_t)m * len);
+    k.w = take(len);
+    k.bpad = take(len);
+    k.xpad = take(len);
+    k.partial = take((size_t)RED_BLOCKS * std::max(m + 2, 4));
+    k.hd = take(kslots(m));
+    k.yd = take((size_t)m + 1);
+    launch_fill(k.V, (long long)(m + 1) * len, 0.0, st);
+    launch_fill(k.Z, (long long)m * len, 0.0, st);
+    k.hh = nullptr;
+    k.hres = hres;
+    k.hwork = hwork;
+    return k;
 }
 
 }  // namespace biot
@@ -780,6 +884,13 @@ int biot_assemble(const biot_problem* prob, void* stream, biot_ctx** out) {
         require(std::isfinite(prob->alpha) && std::isfinite(prob->lambda) && std::isfinite(prob->mu),
                 "non-finite parameter");
         require(prob->K_tri != nullptr || prob->K_scalar > 0, "need K_scalar > 0 when K_tri is NULL");
+        // the no-allocation solve's scratch address on this device (set-up of the library on a
+        // device; a failure here is reported by biot_solve_noalloc, which tries again)
+        try {
+            (void)scratch_address();
+        } catch (const HipError&) {
+            (void)hipGetLastError();
+        }
         std::unique_ptr<biot_ctx> c(new biot_ctx);
         c->n = n;
         c->phys = PhysParams{prob->lambda, prob->mu, prob->alpha, prob->inv_M, prob->mu_f, prob->tau};
@@ -913,7 +1024,31 @@ int biot_solve(biot_ctx* c, const double* b, double* x, biot_solve_info* info, v
         require(info->restart >= 1 && info->restart <= 200, "restart in [1, 200]");
         require(info->maxit >= 0, "maxit >= 0");
         require(info->tol >= 0 && std::isfinite(info->tol), "tol >= 0");
-        return fgmres(c, b, x, info, S(stream));
+        krylov_alloc(c, info->restart, S(stream));
+        return fgmres(c, context_work(c), b, x, info, S(stream));
+    });
+}
+
+int biot_solve_noalloc(biot_ctx* c, const double* b, double* x, biot_solve_info* info, void* stream) {
+    return guarded([&]() {
+        require_hierarchy(c);
+        require(b && x && b != x, "b and x must be distinct non-null device pointers");
+        require(info != nullptr, "null info");
+        require(info->restart >= 1 && info->restart <= NOALLOC_MAX_RESTART,
+                "biot_solve_noalloc: restart in [1, 32]");
+        require(info->maxit >= 0, "maxit >= 0");
+        require(info->tol >= 0 && std::isfinite(info->tol), "tol >= 0");
+        const long long len = c->levels[0]->L.len;
+        const size_t need = noalloc_doubles(len, info->restart) * sizeof(double);
+        if (need > NOALLOC_BYTES)
+            throw ArgError{"biot_solve_noalloc: mesh n = " + std::to_string(c->n) + " with restart " +
+                           std::to_string(info->restart) + " needs " + std::to_string(need >> 20) +
+                           " MiB of workspace, more than the fixed 64 MiB"};
+        hipStream_t st = S(stream);
+        double* base = scratch_address();
+        double hres[2 * NOALLOC_MAX_RESTART + 8];
+        double hwork[(NOALLOC_MAX_RESTART + 1) * NOALLOC_MAX_RESTART + 4 * NOALLOC_MAX_RESTART + 1];
+        return fgmres(c, scratch_work(base, len, info->restart, hres, hwork, st), b, x, info, st);
     });
 }
 
