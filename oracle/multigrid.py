@@ -33,7 +33,7 @@ class Hierarchy:
 
     def __init__(self, n, params, K_tri=1.0, smoother="vanka", omega=1.0, omega_J=1.0,
                  nu1=1, nu2=1, n_coarse=4, levels=None, schur_sweeps=1, omega_S=1.0, gamma=1,
-                 vanka_colors=0):
+                 vanka_colors=0, schur_cg=0):
         if levels is not None:
             n_coarse = n >> (levels - 1)
         self.params = params
@@ -62,7 +62,7 @@ class Hierarchy:
                 _, slots = patch_table(lev.mesh, "full")
                 lev.smoother = AdditiveVanka(lev.A, slots, omega)
             elif smoother == "bsr":
-                lev.smoother = InexactBSR(lev.asm, omega, omega_J, schur_sweeps, omega_S)
+                lev.smoother = InexactBSR(lev.asm, omega, omega_J, schur_sweeps, omega_S, schur_cg)
             else:
                 raise ValueError(smoother)
         self.coarse_lu = sla.lu_factor(self.levels[-1].A.toarray())

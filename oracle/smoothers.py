@@ -153,9 +153,11 @@ class InexactBSR:
     S_hat dp = s, S_hat = c_u M_p + A_pw (tau D_w)^{-1} A_pw^T.  schur_sweeps = 1 is the paper's
     form: one weighted-Jacobi step dp = omega_J s / diag(S_hat).  schur_sweeps = k > 1 runs k
     Jacobi sweeps with weight omega_S from dp = 0 instead, a short inner iteration on S_hat
-    (exact BSR as k grows)."""
+    (exact BSR as k grows).  schur_cg = k > 0 runs k steps of conjugate gradients on S_hat
+    (symmetric positive definite) preconditioned by diag(S_hat), from dp = 0: exact BSR (the
+    exact solve of the approximate Schur complement, Sec. 3.2.2) as k grows."""
 
-    def __init__(self, asm, omega, omega_J, schur_sweeps=1, omega_S=1.0):
+    def __init__(self, asm, omega, omega_J, schur_sweeps=1, omega_S=1.0, schur_cg=0):
         mesh = asm.mesh
         P = asm.params
         A = asm.A.tocsr()
@@ -181,14 +183,38 @@ class InexactBSR:
         self.cMp = c_u * Mp
         self.schur_sweeps = int(schur_sweeps)
         self.omega_S = float(omega_S)
-        if self.schur_sweeps < 1:
-            raise ValueError("schur_sweeps >= 1")
+        self.schur_cg = int(schur_cg)
+        if self.schur_sweeps < 1 or self.schur_cg < 0:
+            raise ValueError("schur_sweeps >= 1, schur_cg >= 0")
 
     def schur_apply(self, dp):
         """S_hat dp = c_u M_p dp + A_pw (tau D_w)^{-1} A_pw^T dp."""
         return self.cMp * dp + self.Apw @ ((self.Apw.T @ dp) / self.Dww)
 
+    def schur_cg_solve(self, s):
+        """k steps of diag(S_hat)-preconditioned conjugate gradients on S_hat dp = s, dp0 = 0
+        (Hestenes-Stiefel with the preconditioned residual z = r / diag(S_hat))."""
+        dp = np.zeros_like(s)
+        r = s.copy()
+        z = r / self.diagS
+        p = z.copy()
+        rho = r @ z
+        for _ in range(self.schur_cg):
+            if rho == 0.0:
+                break
+            q = self.schur_apply(p)
+            alpha = rho / (p @ q)
+            dp = dp + alpha * p
+            r = r - alpha * q
+            z = r / self.diagS
+            rho_new = r @ z
+            p = z + (rho_new / rho) * p
+            rho = rho_new
+        return dp
+
     def schur_solve(self, s):
+        if self.schur_cg > 0:
+            return self.schur_cg_solve(s)
         if self.schur_sweeps == 1:
             return self.omega_J * s / self.diagS
         dp = np.zeros_like(s)
