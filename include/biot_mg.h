@@ -39,7 +39,8 @@
  * host threads.  Device memory is allocated by biot_assemble and biot_setup_hierarchy, and
  * by the first biot_solve with a given restart length m (the Krylov workspace: 2 m + 4
  * finest-level FP64 vectors and a few scalars, kept for later solves with restart <= m);
- * biot_solve_noalloc allocates nothing (it works in a fixed device array of the library).
+ * biot_solve_noalloc allocates nothing (it works in a fixed device array of the library);
+ * biot_export_layout, a diagnostic call, allocates and frees a temporary buffer.
  *
  * Errors.  Every int-returning function returns one of the BIOT_* codes below and, on
  * failure, leaves a message for biot_last_error().  No C++ exception crosses the ABI.  An
@@ -92,7 +93,8 @@ typedef struct {
     double tau;         /* time step > 0                                                    */
     double K_scalar;    /* permeability used when K_tri == NULL; > 0                        */
     const double* K_tri;/* device pointer to 2 n^2 per-triangle permeabilities (> 0), or NULL;
-                           read during biot_assemble only                                    */
+                           read during biot_assemble only, checked on the device as in
+                           biot_update_K                                                     */
 } biot_problem;
 
 /* Multigrid options (Sec. 3, 4.3, 5.1). */
@@ -117,16 +119,35 @@ typedef struct {
                            four colours (i mod 2) + 2 (j mod 2) of the patch vertex, each colour
                            on the residual the previous one left, unweighted (a colour's patches
                            share no DoF); four launches per smoothing step                    */
+    int schur_cg;       /* BSR: 0 = as schur_sweeps says; k in 1..64 = the pressure correction
+                           from k steps of conjugate gradients on the approximate Schur complement
+                           S_hat = c_u M_p + tau B_w D_w^{-1} B_w^T (symmetric positive definite),
+                           preconditioned by diag(S_hat), from zero: exact BSR (Sec. 3.2.2) in the
+                           limit.  Five launches per CG step and level, dot products reduced on
+                           the device in a fixed order (no host synchronization).  Excludes
+                           schur_sweeps >= 2.                                                 */
+    int gamma_from;     /* with gamma >= 2: only levels l >= gamma_from (0 = finest) repeat their
+                           coarse correction gamma times, finer levels take one; 0 = every level
+                           (the W-cycle).  A W-cycle below a V-cycle: the coarse levels, cheap in
+                           bytes, are revisited, the fine ones are not.                        */
 } biot_mg_opts;
 
 /* FGMRES controls (in) and results (out). */
 typedef struct {
-    double tol;         /* in: stop when ||b - A x||_2 <= tol ||b||_2 (true residual)       */
+    double tol;         /* in: stop when ||b - A x||_2 <= tol ||b||_2 (true residual; side 0)
+                           or ||M^{-1}(b - A x)||_2 <= tol ||M^{-1} b||_2 (side 1)           */
     int restart;        /* in: Krylov dimension m per cycle, 1..200                          */
-    int maxit;          /* in: maximum total FGMRES iterations                               */
+    int maxit;          /* in: maximum total iterations                                      */
     int iters;          /* out: iterations performed                                         */
     int converged;      /* out: 1 if the tolerance was met                                   */
     double rel_res_true;/* out: ||b - A x||_2 / ||b||_2 recomputed in FP64 at the end        */
+    int side;           /* in: 0 = right-preconditioned flexible GMRES (Sec. 5.1; default);
+                           1 = left-preconditioned GMRES on M^{-1} A x = M^{-1} b, stopping on
+                           the preconditioned residual (a reading of the paper's "relative
+                           residual" under which its Vanka iteration counts are reproduced; M,
+                           one V-cycle, must then be a fixed linear operator, i.e. no
+                           schur_cg)                                                          */
+    double rel_res_prec;/* out (side 1): ||M^{-1}(b - A x)||_2 / ||M^{-1} b||_2 at the end   */
 } biot_solve_info;
 
 /* Assemble the rediscretized operator on the finest mesh (Sec. 2.3, block_form_rq):
@@ -178,10 +199,17 @@ int biot_restrict(biot_ctx* ctx, int level, const double* r_f, double* r_c, void
  * (Sec. 3.1). */
 int biot_prolong_add(biot_ctx* ctx, int level, const double* x_c, double* x_f, void* stream);
 
-/* Re-assemble for new per-triangle permeabilities (device pointer, 2 n^2 values > 0):
- * updates 1/K on every level, the patch data and the coarsest inverse.  The hierarchy
- * options stay. */
+/* Re-assemble for new per-triangle permeabilities (Sec. 2.1: K enters the Darcy block
+ * tau M_w(K) only): K_tri is a device pointer to 2 n^2 values.  Every value is checked on the
+ * device first (K > 0, finite, 1/K finite and non-zero; the call synchronizes the stream for
+ * the check); on failure BIOT_ERR_ARG is returned and nothing changes.  Then 1/K is updated
+ * on every level, with the patch data and the coarsest inverse.  The hierarchy options stay. */
 int biot_update_K(biot_ctx* ctx, const double* K_tri, void* stream);
+
+/* As biot_update_K for the log-permeability theta_T = ln K_T (device pointer, 2 n^2 values;
+ * checked on the device: finite with |theta| < 700): 1/K_T = exp(-theta_T) is formed on the
+ * device, the parametrization whose derivative biot_grad_logK returns. */
+int biot_update_logK(biot_ctx* ctx, const double* theta_tri, void* stream);
 
 /* Per-triangle gradient of lambda^T A x with respect to theta_T = ln K_T, negated:
  *   g_T = -lam^T (dA/dtheta_T) x = tau mu_f exp(-theta_T) lam_w|_T^T M_w^T(K=1) w|_T,
@@ -189,16 +217,24 @@ int biot_update_K(biot_ctx* ctx, const double* K_tri, void* stream);
  * Sec. 2.1).  x, lam: canonical finest-level vectors; g_tri: 2 n^2 outputs. */
 int biot_grad_logK(biot_ctx* ctx, const double* x, const double* lam, double* g_tri, void* stream);
 
-/* Layout export (host memory).  counts (optional, 12 ints): [n, n_free, 10 block sizes].
+/* Layout export (host memory): the mesh numbering of Sec. 2.1 (squares cut as Appendix A
+ * draws them) and the 20-DoF vertex patches of Sec. 3.2.1 (Fig. patches, right), for checking
+ * the library's index arithmetic against another implementation.
+ * counts (optional, 12 ints): [n, n_free, 10 block sizes].
  * patch_table (optional, host, ((n+1)^2 - 2) x 20 ints): the 20-slot Vanka patch of every
  * vertex except (0,0) and (n,n), vertices in row-major (j, i) order, slots
  *   [ux(v), uy(v), b on H(i-1,j), H(i,j), V(i,j-1), V(i,j), D(i-1,j), D(i,j-1),
  *    w on the same six edges, p on L(i,j), L(i-1,j), L(i,j-1), U(i-1,j-1), U(i-1,j), U(i,j-1)]
  * holding canonical indices, -1 for absent or eliminated DoFs.  Computed on the device by
- * the same index arithmetic the Vanka kernels use.  Synchronizes the stream. */
+ * the same index arithmetic the Vanka kernels use, into a temporary device buffer of
+ * ((n+1)^2 - 2) x 20 ints that this call allocates and frees (a diagnostic call: the one
+ * exception to the allocation rule above).  Synchronizes the stream. */
 int biot_export_layout(biot_ctx* ctx, int* counts, int* patch_table, void* stream);
 
-/* Kernel timing with HIP events (instrumentation, not part of the method).
+/* Kernel timing with HIP events (instrumentation, not a step of the method: no passage of
+ * the paper defines it; it measures the HBM traffic rate of the finest-level kernels).  The
+ * first launches timed after enable = 1 create HIP events (host-side runtime objects, kept by
+ * the context and reused); no device memory is allocated.
  * enable = 1: start recording an event pair around every launch, on mesh level `level`,
  *             of the fused residual + additive-Vanka step (steps on an iterate that is not
  *             identically zero and that do not also add the prolongated coarse correction)

@@ -33,12 +33,13 @@ class Hierarchy:
 
     def __init__(self, n, params, K_tri=1.0, smoother="vanka", omega=1.0, omega_J=1.0,
                  nu1=1, nu2=1, n_coarse=4, levels=None, schur_sweeps=1, omega_S=1.0, gamma=1,
-                 vanka_colors=0, schur_cg=0):
+                 vanka_colors=0, schur_cg=0, gamma_from=0):
         if levels is not None:
             n_coarse = n >> (levels - 1)
         self.params = params
         self.nu1, self.nu2 = int(nu1), int(nu2)
         self.gamma = int(gamma)                 # coarse corrections per level: 1 V-cycle, 2 W-cycle
+        self.gamma_from = int(gamma_from)       # levels finer than this take one coarse correction
         if self.gamma < 1:
             raise ValueError("gamma >= 1")
         self.levels = []
@@ -75,7 +76,7 @@ class Hierarchy:
         """One V(nu1, nu2) cycle for A_level x = b from x = 0; with gamma > 1 the coarse
         correction is gamma cycles of the next level (a W-cycle for gamma = 2), each further one
         on the residual left by the previous ones, except at the coarsest level, whose direct
-        solve is exact."""
+        solve is exact, and on levels finer than gamma_from, which take one."""
         lev = self.levels[level]
         if level == len(self.levels) - 1:
             return sla.lu_solve(self.coarse_lu, b)
@@ -85,7 +86,7 @@ class Hierarchy:
         r = b - lev.A @ x
         bc = lev.P.T @ r
         xc = self.vcycle(bc, level + 1)
-        if level + 1 < len(self.levels) - 1:
+        if level + 1 < len(self.levels) - 1 and level >= self.gamma_from:
             for _ in range(self.gamma - 1):
                 xc = xc + self.vcycle(bc - self.levels[level + 1].A @ xc, level + 1)
         x = x + lev.P @ xc

@@ -21,6 +21,7 @@ BIOT_ERR_SINGULAR = -4
 BIOT_ERR_NAN = -5
 SMOOTHERS = {"vanka": 0, "bsr": 1}
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_patch": 2}
+SIDES = {"right": 0, "left": 1}
 
 _lib = None
 
@@ -41,12 +42,14 @@ class MGOpts(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int), ("smoother", ctypes.c_int), ("nu1", ctypes.c_int),
                 ("nu2", ctypes.c_int), ("omega", ctypes.c_double), ("omega_J", ctypes.c_double),
                 ("precision", ctypes.c_int), ("schur_sweeps", ctypes.c_int), ("omega_S", ctypes.c_double),
-                ("gamma", ctypes.c_int), ("vanka_colors", ctypes.c_int)]
+                ("gamma", ctypes.c_int), ("vanka_colors", ctypes.c_int), ("schur_cg", ctypes.c_int),
+                ("gamma_from", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
-                ("iters", ctypes.c_int), ("converged", ctypes.c_int), ("rel_res_true", ctypes.c_double)]
+                ("iters", ctypes.c_int), ("converged", ctypes.c_int), ("rel_res_true", ctypes.c_double),
+                ("side", ctypes.c_int), ("rel_res_prec", ctypes.c_double)]
 
 
 def load():
@@ -69,6 +72,7 @@ def load():
     lib.biot_restrict.argtypes = [P, I, P, P, P]
     lib.biot_prolong_add.argtypes = [P, I, P, P, P]
     lib.biot_update_K.argtypes = [P, P, P]
+    lib.biot_update_logK.argtypes = [P, P, P]
     lib.biot_grad_logK.argtypes = [P, P, P, P, P]
     lib.biot_export_layout.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), P]
     lib.biot_kernel_timing.argtypes = [P, I, I, ctypes.POINTER(ctypes.c_double), P]
@@ -77,7 +81,8 @@ def load():
     lib.biot_last_error.restype = ctypes.c_char_p
     for name in ("biot_assemble", "biot_setup_hierarchy", "biot_vcycle", "biot_solve", "biot_solve_noalloc",
                  "biot_apply_operator", "biot_smooth", "biot_restrict", "biot_prolong_add",
-                 "biot_update_K", "biot_grad_logK", "biot_export_layout", "biot_kernel_timing"):
+                 "biot_update_K", "biot_update_logK", "biot_grad_logK", "biot_export_layout",
+                 "biot_kernel_timing"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -148,9 +153,10 @@ class BiotSolver:
         return n_free(self.n >> level)
 
     def setup(self, levels, smoother="vanka", nu1=2, nu2=2, omega=0.8, omega_J=1.0, precision="fp64",
-              schur_sweeps=1, omega_S=1.0, gamma=1, vanka_colors=0):
+              schur_sweeps=1, omega_S=1.0, gamma=1, vanka_colors=0, schur_cg=0, gamma_from=0):
         o = MGOpts(int(levels), SMOOTHERS[smoother], int(nu1), int(nu2), float(omega), float(omega_J),
-                   PRECISIONS[precision], int(schur_sweeps), float(omega_S), int(gamma), int(vanka_colors))
+                   PRECISIONS[precision], int(schur_sweeps), float(omega_S), int(gamma), int(vanka_colors),
+                   int(schur_cg), int(gamma_from))
         _check(load().biot_setup_hierarchy(self._ctx, ctypes.byref(o), _stream()))
         self.levels = int(levels)
         return self
@@ -160,23 +166,25 @@ class BiotSolver:
         _check(load().biot_vcycle(self._ctx, _dev(r, self.nf(), "r"), _dev(z), _stream()))
         return z
 
-    def solve(self, b, tol=1e-8, restart=30, maxit=500, out=None):
+    def solve(self, b, tol=1e-8, restart=30, maxit=500, out=None, side="right"):
+        """side "right": flexible GMRES stopping on the true residual; "left": GMRES on the
+        left-preconditioned system stopping on the preconditioned residual."""
         x = torch.empty_like(b) if out is None else out
-        info = SolveInfo(float(tol), int(restart), int(maxit), 0, 0, 0.0)
+        info = SolveInfo(float(tol), int(restart), int(maxit), 0, 0, 0.0, SIDES[side], 0.0)
         code = _check(load().biot_solve(self._ctx, _dev(b, self.nf(), "b"), _dev(x, self.nf(), "x"),
                                         ctypes.byref(info), _stream()), allow=(BIOT_OK, BIOT_NOT_CONVERGED))
         return x, dict(iters=info.iters, converged=bool(info.converged), rel_res_true=info.rel_res_true,
-                       code=code)
+                       rel_res_prec=info.rel_res_prec, code=code)
 
-    def solve_noalloc(self, b, out, tol=1e-8, restart=30, maxit=500):
+    def solve_noalloc(self, b, out, tol=1e-8, restart=30, maxit=500, side="right"):
         """solve() through biot_solve_noalloc: no device allocation in the library; the caller
         passes the output tensor."""
-        info = SolveInfo(float(tol), int(restart), int(maxit), 0, 0, 0.0)
+        info = SolveInfo(float(tol), int(restart), int(maxit), 0, 0, 0.0, SIDES[side], 0.0)
         code = _check(load().biot_solve_noalloc(self._ctx, _dev(b, self.nf(), "b"), _dev(out, self.nf(), "x"),
                                                 ctypes.byref(info), _stream()),
                       allow=(BIOT_OK, BIOT_NOT_CONVERGED))
         return out, dict(iters=info.iters, converged=bool(info.converged), rel_res_true=info.rel_res_true,
-                         code=code)
+                         rel_res_prec=info.rel_res_prec, code=code)
 
     def apply(self, x, level=0):
         y = torch.empty_like(x)
@@ -204,6 +212,12 @@ class BiotSolver:
     def update_K(self, K):
         self._K = K.to(device="cuda", dtype=torch.float64).contiguous()
         _check(load().biot_update_K(self._ctx, _dev(self._K, 2 * self.n * self.n, "K"), _stream()))
+
+    def update_logK(self, theta):
+        """Re-assemble for the per-triangle log-permeability theta = ln K (1/K = exp(-theta)
+        is formed in the library)."""
+        self._K = theta.to(device="cuda", dtype=torch.float64).contiguous()
+        _check(load().biot_update_logK(self._ctx, _dev(self._K, 2 * self.n * self.n, "theta"), _stream()))
 
     def grad_logK(self, x, lam):
         g = torch.empty(2 * self.n * self.n, dtype=torch.float64, device=x.device)
@@ -237,7 +251,7 @@ class SolveFn(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, theta, b, solver, tol, restart, maxit, adj_tol):
-        solver.update_K(torch.exp(theta.detach()))
+        solver.update_logK(theta.detach())
         token = object()
         solver._k_token = token
         x, info = solver.solve(b.detach().contiguous(), tol=tol, restart=restart, maxit=maxit)
@@ -255,7 +269,7 @@ class SolveFn(torch.autograd.Function):
         tol, restart, maxit = ctx.opts
         if getattr(ctx.solver, "_k_token", None) is not ctx.token:
             # the solver was re-assembled for another theta since this forward pass
-            ctx.solver.update_K(torch.exp(theta))
+            ctx.solver.update_logK(theta)
             ctx.solver._k_token = ctx.token
         lam, info = ctx.solver.solve(gx.contiguous(), tol=tol, restart=restart, maxit=maxit)
         if not info["converged"]:

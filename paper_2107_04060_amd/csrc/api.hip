@@ -75,7 +75,8 @@ struct Level {
     DevBuf x64, b64, r64, t64, x2_64;   // FP64 work vectors (padded); x64 / x2_64: iterate pair
     DevBuf x32, b32, r32, x2_32;        // FP32 work vectors (padded)
     DevBuf bs64, bs32;                  // BSR scratch vector (padded)
-    DevBuf sch64, sch32;                // BSR Schur sweeps: s and two pressure buffers (6 planes)
+    DevBuf sch64, sch32;                // BSR Schur sweeps (s, two pressure buffers) or CG (dp, r, z, p, q): 10 planes
+    DevBuf cgred;                       // BSR Schur CG: partial sums and scalars (doubles)
     DevBuf wx64, wb64, wx32, wb32;      // W-cycles: accumulated correction, residual of a revisit
     double cS = 0;                      // (1/M + alpha^2 / (lambda + mu)) |T| of this level
     template <typename T>
@@ -132,6 +133,7 @@ struct biot_ctx {
     // coarsest level
     int coarse_N = 0;
     DevBuf coarse_A, coarse_inv, coarse_idx, coarse_map, status;
+    DevBuf kcheck;                    // status word of the permeability checks (one int)
     // local RT0 mass (K = 1) of L and U for the adjoint gradient
     DevBuf mloc;
     // kernel timing (instrumentation)
@@ -268,9 +270,27 @@ static void level_patch_data(Level& lv, bool uniform, double Kinv, hipStream_t s
     upload(lv.uinv32, convert_uinv<float>(ucls), st);
 }
 
-static void levels_kinv(biot_ctx* c, const double* K_tri, hipStream_t st) {
+// reject a per-triangle field (2 n^2 device values) with an unusable value before anything
+// changes: mode 0 permeabilities, mode 1 log-permeabilities (synchronizes the stream)
+static void check_field(biot_ctx* c, const double* v, int mode, hipStream_t st) {
+    launch_check_field(v, 2LL * c->n * c->n, mode, c->kcheck.as<int>(), st);
+    check_stream_error();
+    int bad = 0;
+    BIOT_HIP(hipMemcpyAsync(&bad, c->kcheck.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    BIOT_HIP(hipStreamSynchronize(st));
+    if (bad)
+        throw ArgError{mode == 0 ? "permeability: every K must be finite and > 0 with 1/K finite"
+                                 : "log-permeability: every theta = ln K must be finite with |theta| < 700"};
+}
+
+// 1/K on every level from the finest level's (mode 0: K_tri, or K_scalar if null; mode 1:
+// exp(-theta))
+static void levels_kinv(biot_ctx* c, const double* K_tri, hipStream_t st, int mode = 0) {
     Level& l0 = *c->levels[0];
-    launch_kinv_from_K(K_tri, c->K_scalar, l0.kinv64.as<double>(), l0.L, st);
+    if (mode == 0)
+        launch_kinv_from_K(K_tri, c->K_scalar, l0.kinv64.as<double>(), l0.L, st);
+    else
+        launch_kinv_from_logK(K_tri, l0.kinv64.as<double>(), l0.L, st);
     for (size_t l = 1; l < c->levels.size(); ++l)
         launch_kinv_coarsen(c->levels[l - 1]->kinv64.as<double>(), c->levels[l - 1]->L,
                             c->levels[l]->kinv64.as<double>(), c->levels[l]->L, st);
@@ -291,10 +311,12 @@ static void levels_bsr(biot_ctx* c, hipStream_t st) {
             lv.bs32.alloc(len * sizeof(float));
             launch_fill(lv.bs64.as<double>(), lv.L.len, 0.0, st);
             launch_fill(lv.bs32.as<float>(), lv.L.len, 0.0f, st);
-            lv.sch64.alloc(6 * lv.L.plane * sizeof(double));
-            lv.sch32.alloc(6 * lv.L.plane * sizeof(float));
-            launch_fill(lv.sch64.as<double>(), 6 * lv.L.plane, 0.0, st);
-            launch_fill(lv.sch32.as<float>(), 6 * lv.L.plane, 0.0f, st);
+            lv.sch64.alloc(10 * lv.L.plane * sizeof(double));
+            lv.sch32.alloc(10 * lv.L.plane * sizeof(float));
+            launch_fill(lv.sch64.as<double>(), 10 * lv.L.plane, 0.0, st);
+            launch_fill(lv.sch32.as<float>(), 10 * lv.L.plane, 0.0f, st);
+            lv.cgred.alloc((2 * (size_t)cg_partials(lv.L) + 3) * sizeof(double));
+            launch_fill(lv.cgred.as<double>(), 2LL * cg_partials(lv.L) + 3, 0.0, st);
         }
         const double area = 0.5 * lv.h * lv.h;
         lv.cS = cu * area;
@@ -394,7 +416,10 @@ struct XBuf<float> {
 // BSR Schur sweeps of level l (sweeps <= 1: the single step, no descriptor needed)
 template <typename T>
 static SchurSweeps<T> schur_sweeps(biot_ctx* c, Level& lv) {
-    return SchurSweeps<T>{c->opts.schur_sweeps, (T)c->opts.omega_S, (T)lv.cS, VecSet<T>::sch(lv)};
+    SchurSweeps<T> sw{c->opts.schur_sweeps, (T)c->opts.omega_S, (T)lv.cS, VecSet<T>::sch(lv)};
+    sw.cg = c->opts.schur_cg;
+    sw.red = lv.cgred.as<double>();
+    return sw;
 }
 
 // Multiplicative Vanka: the colours of a step are separate launches, each reading the iterate
@@ -478,7 +503,7 @@ static T* vcycle_level(biot_ctx* c, int l, const T* b, T* buf0, T* buf1, hipStre
     launch_residual_restrict<T>(lv.view<T>(), lc.L, cur, b, bc, c->K_uniform, (T)(1.0 / c->K_scalar),
                                 PW<T>::get(c), st, &tm);
     T* xc = vcycle_level<T>(c, l + 1, bc, XBuf<T>::get(lc, 0), XBuf<T>::get(lc, 1), st);
-    if (c->opts.gamma > 1 && l + 2 < (int)c->levels.size()) {
+    if (c->opts.gamma > 1 && l >= c->opts.gamma_from && l + 2 < (int)c->levels.size()) {
         // W-cycle: gamma - 1 further cycles of level l + 1 on the residual left by the previous
         // ones (the coarsest level's direct solve is exact and not repeated)
         T* acc = VecSet<T>::wx(lc);
@@ -560,7 +585,7 @@ static int kslot_tmp(int m) { return 2 * m + 7; }
 static int kslots(int m) { return 2 * m + 8; }
 
 // The device and host memory one FGMRES solve works in.  Absent DoFs must be zero in every
-// Krylov vector V_q, Z_q on entry (the kernels never write them).
+// Krylov vector V_q, Z_q and in w on entry (the kernels never write them).
 struct KrylovWork {
     int M = 0;                 // capacity: restart <= M; layout of the result slots
     double *V = nullptr, *Z = nullptr, *w = nullptr, *partial = nullptr;
@@ -581,6 +606,7 @@ static void krylov_alloc(biot_ctx* c, int m, hipStream_t st) {
     launch_fill(c->V.as<double>(), (long long)(m + 1) * L.len, 0.0, st);
     launch_fill(c->Z.as<double>(), (long long)m * L.len, 0.0, st);
     c->w.alloc((size_t)L.len * sizeof(double));
+    launch_fill(c->w.as<double>(), L.len, 0.0, st);
     c->partial.alloc((size_t)RED_BLOCKS * std::max(m + 2, 4) * sizeof(double));
     c->hdev.alloc((size_t)kslots(m) * sizeof(double));
     c->ydev.alloc((size_t)(m + 1) * sizeof(double));
@@ -650,6 +676,7 @@ static int fgmres(biot_ctx* c, const KrylovWork& K, const double* b_canon, doubl
     info->iters = 0;
     info->converged = 0;
     info->rel_res_true = 0;
+    info->rel_res_prec = 0;
     if (!(bnorm == bnorm) || std::isinf(bnorm)) throw std::domain_error("NaN/Inf in right-hand side");
     if (bnorm == 0.0) {
         launch_unpack(x, x_canon, L, l0.C, st);
@@ -657,9 +684,27 @@ static int fgmres(biot_ctx* c, const KrylovWork& K, const double* b_canon, doubl
         return BIOT_OK;
     }
     const double tol = info->tol;
-    // r = b - A x  (x = 0 -> r = b)
-    BIOT_HIP(hipMemcpyAsync(w, b, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-    double beta = bnorm;
+    // right preconditioning (flexible GMRES): the Krylov space of A M^{-1}, stopping on the true
+    // residual |b - A x| <= tol |b|.  Left preconditioning: GMRES on M^{-1} A x = M^{-1} b,
+    // stopping on the preconditioned residual |M^{-1}(b - A x)| <= tol |M^{-1} b| (the Z vectors
+    // are not needed; the first one is scratch).
+    const bool left = info->side == 1;
+    double* tmp = Z;
+    double znorm = bnorm;           // the stopping test's reference norm
+    double beta;
+    if (left) {
+        // the cycle writes the free DoFs of its output only: w must hold zeros elsewhere
+        launch_fill(w, n, 0.0, st);
+        precond(c, b, w, st);
+        znorm = std::sqrt(norm2_dev(K, w, n, st));
+        if (!(znorm == znorm) || std::isinf(znorm)) throw std::domain_error("NaN/Inf in the preconditioned right-hand side");
+        beta = znorm;
+    } else {
+        // r = b - A x  (x = 0 -> r = b)
+        BIOT_HIP(hipMemcpyAsync(w, b, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+        beta = bnorm;
+    }
+    double rtrue = bnorm;
     // host arrays: Hessenberg (m + 1) x m, rotations, right-hand side and solution of the LS problem
     double* H = K.hwork;
     double* cs = H + (size_t)(m + 1) * m;
@@ -670,7 +715,7 @@ static int fgmres(biot_ctx* c, const KrylovWork& K, const double* b_canon, doubl
     double* hflag = hh ? hh + kslot_flag(M) : nullptr;
     int it = 0;
     while (true) {
-        if (beta <= tol * bnorm) {
+        if (beta <= tol * znorm) {
             info->converged = 1;
             break;
         }
@@ -684,13 +729,19 @@ static int fgmres(biot_ctx* c, const KrylovWork& K, const double* b_canon, doubl
         for (int j = 0; j < m; ++j) {
             double* vj = V + (size_t)j * n;
             double* zj = Z + (size_t)j * n;
-            precond(c, vj, zj, st);
-            // Arnoldi on the shifted vector w = v_j - A z_j (A z_j = v_j - w): with a good
-            // preconditioner A z_j is close to v_j, so A z_j itself lies almost entirely in the
-            // Krylov basis and orthogonalizing it cancels nearly everything, while the shifted
-            // vector keeps the part that is new.  Its coefficients are h'_i = delta_ij - h_i and
-            // the orthogonalized remainder is -h_{j+1,j} v_{j+1}.
-            launch_apply<double>(l0.view<double>(), zj, vj, w, 1, st);
+            if (left) {
+                // w = M^{-1} A v_j
+                launch_apply<double>(l0.view<double>(), vj, nullptr, tmp, 0, st);
+                precond(c, tmp, w, st);
+            } else {
+                precond(c, vj, zj, st);
+                // Arnoldi on the shifted vector w = v_j - A z_j (A z_j = v_j - w): with a good
+                // preconditioner A z_j is close to v_j, so A z_j itself lies almost entirely in the
+                // Krylov basis and orthogonalizing it cancels nearly everything, while the shifted
+                // vector keeps the part that is new.  Its coefficients are h'_i = delta_ij - h_i and
+                // the orthogonalized remainder is -h_{j+1,j} v_{j+1}.
+                launch_apply<double>(l0.view<double>(), zj, vj, w, 1, st);
+            }
             // CGS with a second pass when the first one cancels (|w| drops below |w_0| / sqrt 2).
             // Pass one's update also forms pass two's dot products (V is read once for both), so
             // the second pass costs one more update only when it runs.
@@ -713,11 +764,16 @@ static int fgmres(biot_ctx* c, const KrylovWork& K, const double* b_canon, doubl
             check_stream_error();
             sync_results(K, st);
             const bool second = hres[kslot_flag(M)] != 0.0;
-            for (int i = 0; i <= j; ++i)
-                H[(size_t)i * m + j] = (i == j ? 1.0 : 0.0) - (hres[i] + (second ? hres[M + 2 + i] : 0.0));
             const double hn = std::sqrt(second ? hres[kslot_n2(M)] : hres[M + 2 + nv]);
-            // v_{j+1} = w / |w| is minus the direction of the unshifted remainder
-            H[(size_t)(j + 1) * m + j] = -hn;
+            if (left) {
+                for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hres[i] + (second ? hres[M + 2 + i] : 0.0);
+                H[(size_t)(j + 1) * m + j] = hn;
+            } else {
+                for (int i = 0; i <= j; ++i)
+                    H[(size_t)i * m + j] = (i == j ? 1.0 : 0.0) - (hres[i] + (second ? hres[M + 2 + i] : 0.0));
+                // v_{j+1} = w / |w| is minus the direction of the unshifted remainder
+                H[(size_t)(j + 1) * m + j] = -hn;
+            }
             for (int i = 0; i <= j + 1; ++i)
                 if (!(H[(size_t)i * m + j] == H[(size_t)i * m + j])) throw std::domain_error("NaN in Arnoldi");
             for (int i = 0; i < j; ++i) {
@@ -735,7 +791,7 @@ static int fgmres(biot_ctx* c, const KrylovWork& K, const double* b_canon, doubl
             g[j] = cs[j] * g[j];
             ++it;
             k = j + 1;
-            if (std::fabs(g[j + 1]) <= tol * bnorm || it >= info->maxit || hn == 0.0) break;
+            if (std::fabs(g[j + 1]) <= tol * znorm || it >= info->maxit || hn == 0.0) break;
         }
         // y = H^{-1} g (upper triangular k x k), x += Z y
         for (int i = k - 1; i >= 0; --i) {
@@ -744,14 +800,22 @@ static int fgmres(biot_ctx* c, const KrylovWork& K, const double* b_canon, doubl
             y[i] = s / H[(size_t)i * m + i];
         }
         BIOT_HIP(hipMemcpyAsync(K.yd, y, k * sizeof(double), hipMemcpyHostToDevice, st));
-        launch_lincomb_add(x, Z, n, k, K.yd, n, st);
-        // true residual
-        launch_apply<double>(l0.view<double>(), x, b, w, 1, st);
-        beta = std::sqrt(norm2_dev(K, w, n, st));
-        if (!(beta == beta)) throw std::domain_error("NaN in residual");
+        launch_lincomb_add(x, left ? V : Z, n, k, K.yd, n, st);
+        // true residual; left: the preconditioned residual that restarts the iteration
+        if (left) {
+            launch_apply<double>(l0.view<double>(), x, b, tmp, 1, st);
+            rtrue = std::sqrt(norm2_dev(K, tmp, n, st));
+            precond(c, tmp, w, st);
+            beta = std::sqrt(norm2_dev(K, w, n, st));
+        } else {
+            launch_apply<double>(l0.view<double>(), x, b, w, 1, st);
+            beta = rtrue = std::sqrt(norm2_dev(K, w, n, st));
+        }
+        if (!(beta == beta) || !(rtrue == rtrue)) throw std::domain_error("NaN in residual");
     }
     info->iters = it;
-    info->rel_res_true = beta / bnorm;
+    info->rel_res_true = rtrue / bnorm;
+    info->rel_res_prec = left ? beta / znorm : 0.0;
     launch_unpack(x, x_canon, L, l0.C, st);
     check_stream_error();
     return info->converged ? BIOT_OK : BIOT_NOT_CONVERGED;
@@ -812,6 +876,7 @@ static KrylovWork scratch_work(double* base, long long len, int m, double* hres,
     k.yd = take((size_t)m + 1);
     launch_fill(k.V, (long long)(m + 1) * len, 0.0, st);
     launch_fill(k.Z, (long long)m * len, 0.0, st);
+    launch_fill(k.w, len, 0.0, st);
     k.hh = nullptr;
     k.hres = hres;
     k.hwork = hwork;
@@ -883,7 +948,9 @@ int biot_assemble(const biot_problem* prob, void* stream, biot_ctx** out) {
         require(prob->mu_f > 0 && prob->tau > 0, "need mu_f > 0 and tau > 0");
         require(std::isfinite(prob->alpha) && std::isfinite(prob->lambda) && std::isfinite(prob->mu),
                 "non-finite parameter");
-        require(prob->K_tri != nullptr || prob->K_scalar > 0, "need K_scalar > 0 when K_tri is NULL");
+        require(prob->K_tri != nullptr || (prob->K_scalar > 0 && std::isfinite(prob->K_scalar) &&
+                                           std::isfinite(1.0 / prob->K_scalar)),
+                "need finite K_scalar > 0 (with finite 1/K) when K_tri is NULL");
         // the no-allocation solve's scratch address on this device (set-up of the library on a
         // device; a failure here is reported by biot_solve_noalloc, which tries again)
         try {
@@ -897,6 +964,8 @@ int biot_assemble(const biot_problem* prob, void* stream, biot_ctx** out) {
         c->K_scalar = prob->K_scalar;
         c->K_uniform = (prob->K_tri == nullptr);
         hipStream_t st = S(stream);
+        c->kcheck.alloc(sizeof(int));
+        if (prob->K_tri) check_field(c.get(), prob->K_tri, 0, st);
         c->levels.emplace_back(new Level);
         level_alloc(*c->levels[0], n, st);
         level_stencil(*c->levels[0], c->phys, st);
@@ -947,9 +1016,12 @@ int biot_setup_hierarchy(biot_ctx* c, const biot_mg_opts* o, void* stream) {
                 "BSR needs omega_J > 0");
         require(o->schur_sweeps >= 0 && o->schur_sweeps <= 64, "schur_sweeps in [0, 64]");
         require(o->gamma >= 0 && o->gamma <= 4, "gamma (cycle index) in [0, 4]");
+        require(o->gamma_from >= 0 && o->gamma_from < o->levels, "gamma_from in [0, levels)");
         require(o->vanka_colors == 0 || o->vanka_colors == 4, "vanka_colors: 0 (additive) or 4");
         require(o->schur_sweeps <= 1 || (std::isfinite(o->omega_S) && o->omega_S > 0 && o->omega_S <= 1),
                 "Schur sweeps need omega_S in (0, 1]");
+        require(o->schur_cg >= 0 && o->schur_cg <= 64, "schur_cg in [0, 64]");
+        require(o->schur_cg == 0 || o->schur_sweeps <= 1, "schur_cg and schur_sweeps > 1 exclude each other");
         const int nc = c->n >> (o->levels - 1);
         require(nc <= 16, "coarsest mesh must have at most 16 cells per side (dense direct solve)");
         hipStream_t st = S(stream);
@@ -1024,6 +1096,7 @@ int biot_solve(biot_ctx* c, const double* b, double* x, biot_solve_info* info, v
         require(info->restart >= 1 && info->restart <= 200, "restart in [1, 200]");
         require(info->maxit >= 0, "maxit >= 0");
         require(info->tol >= 0 && std::isfinite(info->tol), "tol >= 0");
+        require(info->side == 0 || info->side == 1, "side: 0 (right) or 1 (left)");
         krylov_alloc(c, info->restart, S(stream));
         return fgmres(c, context_work(c), b, x, info, S(stream));
     });
@@ -1038,6 +1111,7 @@ int biot_solve_noalloc(biot_ctx* c, const double* b, double* x, biot_solve_info*
                 "biot_solve_noalloc: restart in [1, 32]");
         require(info->maxit >= 0, "maxit >= 0");
         require(info->tol >= 0 && std::isfinite(info->tol), "tol >= 0");
+        require(info->side == 0 || info->side == 1, "side: 0 (right) or 1 (left)");
         const long long len = c->levels[0]->L.len;
         const size_t need = noalloc_doubles(len, info->restart) * sizeof(double);
         if (need > NOALLOC_BYTES)
@@ -1129,18 +1203,26 @@ int biot_prolong_add(biot_ctx* c, int level, const double* x_c, double* x_f, voi
     });
 }
 
+// re-assembly for a new per-triangle field: mode 0 permeabilities, mode 1 log-permeabilities
+static int update_perm(biot_ctx* c, const double* field, int mode, void* stream) {
+    require_ctx(c);
+    require(field != nullptr, mode == 0 ? "null K" : "null theta");
+    hipStream_t st = S(stream);
+    check_field(c, field, mode, st);
+    c->K_uniform = false;
+    levels_kinv(c, field, st, mode);
+    if (c->have_hierarchy && c->opts.smoother == BIOT_SMOOTHER_BSR) levels_bsr(c, st);
+    if (c->have_hierarchy) coarse_factor(c, st);
+    check_stream_error();
+    return BIOT_OK;
+}
+
 int biot_update_K(biot_ctx* c, const double* K_tri, void* stream) {
-    return guarded([&]() {
-        require_ctx(c);
-        require(K_tri != nullptr, "null K");
-        hipStream_t st = S(stream);
-        c->K_uniform = false;
-        levels_kinv(c, K_tri, st);
-        if (c->have_hierarchy && c->opts.smoother == BIOT_SMOOTHER_BSR) levels_bsr(c, st);
-        if (c->have_hierarchy) coarse_factor(c, st);
-        check_stream_error();
-        return BIOT_OK;
-    });
+    return guarded([&]() { return update_perm(c, K_tri, 0, stream); });
+}
+
+int biot_update_logK(biot_ctx* c, const double* theta_tri, void* stream) {
+    return guarded([&]() { return update_perm(c, theta_tri, 1, stream); });
 }
 
 int biot_grad_logK(biot_ctx* c, const double* x, const double* lam, double* g_tri, void* stream) {

@@ -484,6 +484,173 @@ __global__ __launch_bounds__(256) void k_schur_sweep(const T* __restrict__ s_in,
     });
 }
 
+// ---- conjugate gradients on the approximate Schur complement (exact BSR in the limit) ------------
+// k steps of diag(S_hat)-preconditioned CG on S_hat dp = s from dp = 0, with s as in k_schur_init.
+// Every dot product is summed per block (fixed order: a wave butterfly, then the waves in order)
+// into red[slot * np + block], and one block of k_cg_scalars adds the np partial sums in a fixed
+// order and updates the recurrence's scalars on the device, so no step waits for the host.
+// Scalars (double): sc[0] rho = r . z, sc[1] alpha, sc[2] beta.  Vectors: 2 planes each (p_L, p_U).
+constexpr int CG_SLOT_RZ = 0, CG_SLOT_PQ = 1;
+
+template <typename T>
+__device__ __forceinline__ void cg_block_sum(double v, double* __restrict__ red, int slot, int np) {
+    __shared__ double wsum[4];
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    const double t = wave_sum(v);
+    if ((tid & 63) == 0) wsum[tid >> 6] = t;
+    __syncthreads();
+    if (tid == 0) red[(long long)slot * np + blockIdx.y * gridDim.x + blockIdx.x] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+}
+
+// s and the CG start: r = s, z = s / diag(S_hat), p = z, dp = 0; partial sums of r . z
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_init(const T* __restrict__ r, const T* __restrict__ t,
+                                                 const T* __restrict__ coef, const T* __restrict__ d, Layout L,
+                                                 T* __restrict__ cr, T* __restrict__ cz, T* __restrict__ cp,
+                                                 T* __restrict__ dp, double* __restrict__ red, int np) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    double acc_rz = 0;
+    if (i <= L.n && j <= L.n) {
+        const long long s0 = slot_index(L, i, j);
+        static_for(std::integer_sequence<int, T_PL, T_PU>{}, [&](auto tc) {
+            constexpr int tp = decltype(tc)::value;
+            T acc = 0;
+            static_for(std::make_integer_sequence<int, SST.n[tp]>{}, [&](auto ec) {
+                constexpr int e = decltype(ec)::value;
+                constexpr SEnt en = SST.e[tp][e];
+                if constexpr (tfield(en.in) != 2)
+                    acc += coef[SST.off[tp] + e] * t[en.in * L.plane + s0 + (long long)en.dj * L.pitch + en.di];
+            });
+            const bool f = dof_free(tp, i, j, L.n);
+            const T sv = f ? acc - r[tp * L.plane + s0] : (T)0;
+            const T zv = f ? sv * d[(BSR_S + tp - T_PL) * L.plane + s0] : (T)0;
+            const long long q = (tp - T_PL) * L.plane + s0;
+            cr[q] = sv;
+            cz[q] = zv;
+            cp[q] = zv;
+            dp[q] = 0;
+            acc_rz += (double)sv * (double)zv;
+        });
+    }
+    cg_block_sum<T>(acc_rz, red, CG_SLOT_RZ, np);
+}
+
+// q = S_hat p (as in k_schur_sweep); partial sums of p . q
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_apply(const T* __restrict__ cp, const T* __restrict__ coef,
+                                                  const T* __restrict__ d, Layout L, T cS, T* __restrict__ cq,
+                                                  double* __restrict__ red, int np) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    double acc_pq = 0;
+    if (i <= L.n && j <= L.n) {
+        const long long s0 = slot_index(L, i, j);
+        static_for(std::integer_sequence<int, T_PL, T_PU>{}, [&](auto tc) {
+            constexpr int tp = decltype(tc)::value;
+            const long long q = (tp - T_PL) * L.plane + s0;
+            if (!dof_free(tp, i, j, L.n)) {
+                cq[q] = (T)0;
+                return;
+            }
+            const T pv = cp[q];
+            T sd = cS * pv;
+            static_for(std::make_integer_sequence<int, SST.n[tp]>{}, [&](auto ec) {
+                constexpr int e1 = decltype(ec)::value;
+                constexpr SEnt en1 = SST.e[tp][e1];
+                if constexpr (tfield(en1.in) == 1) {
+                    if (dof_free(en1.in, i + en1.di, j + en1.dj, L.n)) {
+                        const long long ws = s0 + (long long)en1.dj * L.pitch + en1.di;
+                        T g = 0;
+                        static_for(std::make_integer_sequence<int, SST.n[en1.in]>{}, [&](auto fc) {
+                            constexpr int e2 = decltype(fc)::value;
+                            constexpr SEnt en2 = SST.e[en1.in][e2];
+                            if constexpr (tfield(en2.in) == 2)
+                                g += coef[SST.off[en1.in] + e2] *
+                                     cp[(en2.in - T_PL) * L.plane + ws + (long long)en2.dj * L.pitch + en2.di];
+                        });
+                        sd += coef[SST.off[tp] + e1] * g * d[(BSR_W + en1.in - T_WH) * L.plane + ws];
+                    }
+                }
+            });
+            cq[q] = sd;
+            acc_pq += (double)pv * (double)sd;
+        });
+    }
+    cg_block_sum<T>(acc_pq, red, CG_SLOT_PQ, np);
+}
+
+// mode 0: rho = sum of the r . z partials; mode 1: alpha = rho / (p . q) (0 when p . q = 0);
+// mode 2: rho' = sum of the r . z partials, beta = rho' / rho (0 when rho = 0), rho = rho'
+__global__ __launch_bounds__(256) void k_cg_scalars(const double* __restrict__ red, int np, int mode,
+                                                    double* __restrict__ sc) {
+    __shared__ double wsum[4];
+    const int slot = mode == 1 ? CG_SLOT_PQ : CG_SLOT_RZ;
+    double v = 0;
+    for (int b = threadIdx.x; b < np; b += blockDim.x) v += red[(long long)slot * np + b];
+    const double t = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double tot = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+        if (mode == 0) {
+            sc[0] = tot;
+        } else if (mode == 1) {
+            sc[1] = tot != 0.0 ? sc[0] / tot : 0.0;
+        } else {
+            sc[2] = sc[0] != 0.0 ? tot / sc[0] : 0.0;
+            sc[0] = tot;
+        }
+    }
+}
+
+// dp += alpha p, r -= alpha q, z = r / diag(S_hat); partial sums of r . z
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_update(const T* __restrict__ cp, const T* __restrict__ cq,
+                                                   const T* __restrict__ d, Layout L, const double* __restrict__ sc,
+                                                   T* __restrict__ dp, T* __restrict__ cr, T* __restrict__ cz,
+                                                   double* __restrict__ red, int np) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    double acc_rz = 0;
+    if (i <= L.n && j <= L.n) {
+        const T alpha = (T)sc[1];
+        const long long s0 = slot_index(L, i, j);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const long long q = k * L.plane + s0;
+            if (!dof_free(T_PL + k, i, j, L.n)) continue;
+            dp[q] += alpha * cp[q];
+            const T rv = cr[q] - alpha * cq[q];
+            const T zv = rv * d[(BSR_S + k) * L.plane + s0];
+            cr[q] = rv;
+            cz[q] = zv;
+            acc_rz += (double)rv * (double)zv;
+        }
+    }
+    cg_block_sum<T>(acc_rz, red, CG_SLOT_RZ, np);
+}
+
+// p = z + beta p
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_direction(const T* __restrict__ cz, Layout L, const double* __restrict__ sc,
+                                                      T* __restrict__ cp) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i > L.n || j > L.n) return;
+    const T beta = (T)sc[2];
+    const long long s0 = slot_index(L, i, j);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const long long q = k * L.plane + s0;
+        if (dof_free(T_PL + k, i, j, L.n)) cp[q] = cz[q] + beta * cp[q];
+    }
+}
+
+int cg_partials(const Layout& L) {
+    return ((L.n + 1 + 63) / 64) * ((L.n + 1 + 3) / 4);
+}
+
 template <typename T>
 void launch_bsr_step(const LevelView<T>& lv, T* x, const T* b, T* r, T* t, bool x_is_zero, bool uniform, T kinv_s,
                      T omega, T omega_J, const T* xc, const Layout* Lc, const T* pw, T* xtmp, hipStream_t st,
@@ -509,7 +676,33 @@ void launch_bsr_step(const LevelView<T>& lv, T* x, const T* b, T* r, T* t, bool 
 #undef BIOT_BSR_FIRST
     const T* xsrc = xc ? xtmp : x;
     const T* dp = nullptr;
-    if (sw && sw->sweeps > 1) {
+    if (sw && sw->cg > 0) {
+        if (!sw->buf || !sw->red) throw ArgError{"Schur CG needs its buffers"};
+        // sw->buf: dp, r, z, p, q (2 planes each); sw->red: 2 np partial sums, then 3 scalars
+        const long long pl2 = 2 * lv.L.plane;
+        T* cdp = sw->buf;
+        T* cr = cdp + pl2;
+        T* cz = cr + pl2;
+        T* cp = cz + pl2;
+        T* cq = cp + pl2;
+        const int np = cg_partials(lv.L);
+        double* red = sw->red;
+        double* sc = red + 2 * np;
+        dim3 cb(64, 4);
+        dim3 cg((lv.L.n + 1 + 63) / 64, (lv.L.n + 1 + 3) / 4);
+        hipLaunchKernelGGL(k_cg_init<T>, cg, cb, 0, st, r, t, lv.coef, lv.bsrd, lv.L, cr, cz, cp, cdp, red, np);
+        hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(256), 0, st, red, np, 0, sc);
+        for (int k = 0; k < sw->cg; ++k) {
+            hipLaunchKernelGGL(k_cg_apply<T>, cg, cb, 0, st, cp, lv.coef, lv.bsrd, lv.L, sw->cS, cq, red, np);
+            hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(256), 0, st, red, np, 1, sc);
+            hipLaunchKernelGGL(k_cg_update<T>, cg, cb, 0, st, cp, cq, lv.bsrd, lv.L, sc, cdp, cr, cz, red, np);
+            if (k + 1 < sw->cg) {
+                hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(256), 0, st, red, np, 2, sc);
+                hipLaunchKernelGGL(k_cg_direction<T>, cg, cb, 0, st, cz, lv.L, sc, cp);
+            }
+        }
+        dp = cdp;
+    } else if (sw && sw->sweeps > 1) {
         if (!sw->buf) throw ArgError{"Schur sweeps need their buffer"};
         // sw->buf: s (2 planes), then two pressure buffers of 2 planes each
         T* sv = sw->buf;

@@ -87,13 +87,19 @@ void launch_bsr_diag(const LevelView<T>& lv, T cS, T* d, hipStream_t st);
 // sw (optional): the pressure correction from sweeps > 1 weighted-Jacobi sweeps (weight omega_S)
 // on the approximate Schur complement instead of the single step with omega_J; cS = (1/M +
 // alpha^2 / (lambda + mu)) |T|; buf: 6 zero-initialized planes of the level.
+// cg > 0 (instead of sweeps): the pressure correction from cg steps of diag(S_hat)-preconditioned
+// conjugate gradients on S_hat from zero; buf: 10 planes, red: 2 cg_partials(L) + 3 doubles.
 template <typename T>
 struct SchurSweeps {
     int sweeps;
     T omega_S;
     T cS;
     T* buf;
+    int cg = 0;
+    double* red = nullptr;
 };
+// partial sums per dot product of the Schur CG on a level
+int cg_partials(const Layout& L);
 template <typename T>
 void launch_bsr_step(const LevelView<T>& lv, T* x, const T* b, T* r, T* t, bool x_is_zero, bool uniform, T kinv_s,
                      T omega, T omega_J, const T* xc, const Layout* Lc, const T* pw, T* xtmp, hipStream_t st,
@@ -109,6 +115,11 @@ void launch_gauss_jordan(double* A, double* Inv, int N, int* status, hipStream_t
 // permeability
 void launch_kinv_from_K(const double* K_tri, double K_scalar, double* kinv, const Layout& L, hipStream_t st);
 void launch_kinv_coarsen(const double* kf, const Layout& Lf, double* kc, const Layout& Lc, hipStream_t st);
+// 1/K = exp(-theta) on the finest level from per-triangle theta = ln K
+void launch_kinv_from_logK(const double* theta_tri, double* kinv, const Layout& L, hipStream_t st);
+// *bad (device int) = 1 if any of the n values is unusable: mode 0 a permeability (K > 0, 1/K
+// finite and non-zero), mode 1 a log-permeability (|theta| < 700); else 0
+void launch_check_field(const double* v, long long n, int mode, int* bad, hipStream_t st);
 
 // Krylov BLAS-1 (FP64)
 void launch_scale(double* dst, const double* src, long long n, double s, hipStream_t st);

@@ -333,6 +333,48 @@ void launch_kinv_from_K(const double* K_tri, double K_scalar, double* kinv, cons
     hipLaunchKernelGGL(k_kinv_from_K, grd, blk, 0, st, K_tri, K_scalar, kinv, L);
 }
 
+// 1/K = exp(-theta) per triangle from the log-permeability theta = ln K
+__global__ void k_kinv_from_logK(const double* __restrict__ th, double* __restrict__ kinv, Layout L) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= L.n || j >= L.n) return;
+    const long long c = (long long)j * L.n + i;
+    const long long nn = (long long)L.n * L.n;
+    kinv[slot_index(L, i, j)] = exp(-th[c]);
+    kinv[L.plane + slot_index(L, i, j)] = exp(-th[nn + c]);
+}
+
+void launch_kinv_from_logK(const double* theta_tri, double* kinv, const Layout& L, hipStream_t st) {
+    launch_fill(kinv, 2 * L.plane, 0.0, st);
+    dim3 blk(64, 4), grd((L.n + 63) / 64, (L.n + 3) / 4);
+    hipLaunchKernelGGL(k_kinv_from_logK, grd, blk, 0, st, theta_tri, kinv, L);
+}
+
+// *bad = 1 when a value is unusable: mode 0 (permeability K) unless K > 0 with 1/K finite
+// and non-zero; mode 1 (theta = ln K) unless exp(-theta) is finite and non-zero.  Every
+// thread that finds one stores the same value.
+__global__ void k_check_field(const double* __restrict__ v, long long n, int mode, int* __restrict__ bad) {
+    long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    bool ok = true;
+    for (; e < n; e += stride) {
+        const double a = v[e];
+        if (mode == 0) {
+            const double r = 1.0 / a;
+            ok = ok && (a > 0.0) && isfinite(a) && isfinite(r) && r > 0.0;
+        } else {
+            ok = ok && isfinite(a) && a > -700.0 && a < 700.0;
+        }
+    }
+    if (!ok) *bad = 1;
+}
+
+void launch_check_field(const double* v, long long n, int mode, int* bad, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, st, bad, 1LL, 0);
+    const int blocks = (int)std::min<long long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_check_field, dim3(std::max(blocks, 1)), dim3(256), 0, st, v, n, mode, bad);
+}
+
 __global__ void k_kinv_coarsen(const double* __restrict__ kf, Layout Lf, double* __restrict__ kc, Layout Lc) {
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     const int J = blockIdx.y * blockDim.y + threadIdx.y;

@@ -17,15 +17,14 @@ def _bench():
     return mod
 
 
-def test_traffic_is_taken_only_for_the_profiled_sources(monkeypatch):
+def test_traffic_is_taken_only_for_the_profiled_sources(monkeypatch, tmp_path):
     b = _bench()
-    with open(b.TRAFFIC_PROFILE) as f:
-        text = f.read()
-    assert "kernel_source_sha256: %s" % b.kernel_source_hash() in text
-    t = b.measured_traffic()
-    assert isinstance(t, int) and t > 0
+    prof = tmp_path / "summary.md"
+    prof.write_text("kernel_source_sha256: %s\ntraffic_bytes_per_launch: 123456\n" % b.kernel_source_hash())
+    assert b.measured_traffic(str(prof)) == 123456
     monkeypatch.setattr(b, "kernel_source_hash", lambda: "0" * 64)
-    assert b.measured_traffic() is None
+    assert b.measured_traffic(str(prof)) is None
+    assert b.measured_traffic(str(tmp_path / "missing.md")) is None
 
 
 def test_more_than_one_gpu_is_refused():

@@ -50,18 +50,21 @@ def _gpu_solver(binding, w, n, levels):
 
 def _gpu_pressure(s, theta, b, n, tol):
     """Pressure block of the GPU solution for theta (the observations, for theta_obs)."""
-    s.update_K(_t(np.exp(theta)))
+    s.update_logK(_t(theta))
     x, info = s.solve(_t(b), tol=tol, restart=30, maxit=1000)
     assert info["converged"]
     return x[10 * n * n - 8 * n + 2 - 2 * n * n:].cpu().numpy()
 
 
-def test_grad_kernel_parity(binding):
+@pytest.mark.parametrize("name", ["small", "scaled"])
+def test_grad_kernel_parity(binding, name):
+    """The per-triangle gradient kernel against the oracle's per-triangle terms; "scaled" has
+    tau = 1e-2, mu_f = 2.5 and alpha = 0.8, so a factor of tau mu_f dropped or doubled fails."""
     n = 16
     K = perm(n, "hetero")
-    s = solver(binding, torch, n, "small", 1.0)
+    s = solver(binding, torch, n, name, 1.0)
     s.update_K(_t(K))
-    asm = Assembly(Mesh(n), params("small"), K)
+    asm = Assembly(Mesh(n), params(name), K)
     rng = np.random.default_rng(8)
     x = rng.standard_normal(asm.n_free)
     lam = rng.standard_normal(asm.n_free)
@@ -93,8 +96,8 @@ def test_autograd_matches_oracle_dense_adjoint(binding):
     p_obs = spla.spsolve(asm_obs.A.tocsc(), b)[asm_obs.slices()[2]]
     Lo, go, _, _ = adjoint.loss_and_grad(n, P, theta, b, p_obs)
     print("  loss %.10e oracle %.10e; grad rel diff %.2e" % (L, Lo, rel(g, go)), flush=True)
-    assert abs(L - Lo) <= 1e-8 * abs(Lo)
-    assert rel(g, go) < 1e-7
+    assert abs(L - Lo) <= 1e-10 * abs(Lo)
+    assert rel(g, go) < 1e-10
     s.close()
 
 
@@ -148,5 +151,5 @@ def test_finite_differences_512(binding):
         e = abs(fd - an) / max(abs(an), 1e-300)
         worst = max(worst, e)
         print("  dir %2d  fd %.10e  adjoint %.10e  rel %.2e" % (k, fd, an, e), flush=True)
-    assert worst < 1e-4
+    assert worst < 1e-5
     s.close()

@@ -1,5 +1,8 @@
 """GPU parity of the HIP path (through the C ABI) against the CPU oracle.
 
+Every comparison takes the larger of the relative 2-norm difference and the largest entrywise
+difference relative to the largest reference entry (tests/gpu_cases.py).
+
 Tolerances.  The library and the oracle evaluate the same FP64 arithmetic in different
 orders, so stencil and transfer outputs agree to a few ulps.  Patch solves differ: the
 oracle factors each 20 x 20 patch matrix with LU, the library eliminates onto the six
@@ -20,6 +23,7 @@ from oracle.fem import Assembly, BiotParams  # noqa: E402
 from oracle.smoothers import patch_table, AdditiveVanka  # noqa: E402
 from oracle.multigrid import Hierarchy  # noqa: E402
 from oracle.krylov import fgmres  # noqa: E402
+from gpu_cases import perm as _K, params as _params, solver, rel as _rel, block_perm  # noqa: E402
 
 TOL = 1e-10
 EPS = np.finfo(float).eps
@@ -39,45 +43,12 @@ def binding():
     return b
 
 
-def _case(name):
-    """(lam, mu, alpha, M, mu_f, tau) of the parity cases."""
-    if name == "small":                      # the 16 x 16 workload's physics
-        lam, mu = 1.0, 1.0
-        return lam, mu, 1.0, inputs.biot_modulus(inputs.young_from_lame(lam, mu)), 1.0, 1.0
-    if name == "stiff":                      # nearly incompressible, low permeability
-        lam, mu = inputs.lame(1.0, 0.49)
-        return lam, mu, 1.0, inputs.biot_modulus(1.0), 1.0, 1.0
-    raise KeyError(name)
-
-
-def _K(n, kind, seed=11):
-    if kind == "const":
-        return 1.0
-    rng = np.random.default_rng(seed)
-    return np.exp(rng.uniform(np.log(0.2), np.log(5.0), 2 * n * n))
-
-
-def _gpu(binding, n, case, Kk, levels=None, smoother="vanka", nu=2, omega=0.8, omega_J=1.0, precision="fp64"):
-    lam, mu, al, M, mf, tau = _case(case)
-    K = Kk if np.isscalar(Kk) else torch.tensor(Kk, dtype=torch.float64, device="cuda")
-    s = binding.BiotSolver(n, lam, mu, alpha=al, M=M, mu_f=mf, tau=tau, K=K)
-    if levels:
-        s.setup(levels=levels, smoother=smoother, nu1=nu, nu2=nu, omega=omega, omega_J=omega_J,
-                precision=precision)
-    return s
-
-
-def _params(case):
-    lam, mu, al, M, mf, tau = _case(case)
-    return BiotParams(lam, mu, alpha=al, M=M, mu_f=mf, tau=tau)
+def _gpu(binding, n, name, Kk, levels=None, **kw):
+    return solver(binding, torch, n, name, Kk, levels=levels, **kw)
 
 
 def _t(a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
-
-
-def _rel(a, b):
-    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
 @pytest.mark.parametrize("n", [4, 8, 16, 64])
@@ -128,11 +99,14 @@ def test_coarse_operators_and_transfers(binding, kind):
     s.close()
 
 
-@pytest.mark.parametrize("n,kind,case", [(8, "const", "small"), (16, "hetero", "small"), (32, "hetero", "stiff")])
+@pytest.mark.parametrize("n,kind,case", [(8, "const", "small"), (16, "hetero", "small"), (32, "hetero", "stiff"),
+                                         (64, "const", "stiff")])
 def test_vanka_step_parity(binding, n, kind, case):
-    """One additive Vanka step x <- x + omega sum_l V_l^T D_l A_l^-1 V_l (b - A x)."""
+    """One additive Vanka step x <- x + omega sum_l V_l^T D_l A_l^-1 V_l (b - A x).  At n = 64 with
+    constant K most tiles of 14 x 14 vertices meet no boundary: the class inverses applied on the
+    matrix cores to interior patches, the path the 256 x 256 sweep runs."""
     K = _K(n, kind)
-    s = _gpu(binding, n, case, K, levels=2, omega=0.8)
+    s = _gpu(binding, n, case, K, levels=2 if n <= 32 else int(np.log2(n // 16)) + 1, omega=0.8)
     asm = Assembly(Mesh(n), _params(case), K)
     _, slots = patch_table(asm.mesh, "full")
     vk = AdditiveVanka(asm.A, slots, omega=0.8)
@@ -147,10 +121,13 @@ def test_vanka_step_parity(binding, n, kind, case):
 
 
 @pytest.mark.parametrize("n,levels,kind,case", [(16, 3, "const", "small"), (32, 4, "hetero", "small"),
-                                                (64, 5, "hetero", "stiff")])
+                                                (64, 5, "hetero", "stiff"), (64, 5, "const", "stiff"),
+                                                (128, 6, "const", "small")])
 def test_vcycle_parity(binding, n, levels, kind, case):
     """z = V(2,2) r from a zero initial guess: smoothing, restriction, recursion, coarse
-    direct solve, prolongation (Sec. 3)."""
+    direct solve, prolongation (Sec. 3).  The constant-K cases at n = 64 and 128 run the FP64
+    class-inverse Vanka step in all three of its variants (from zero, plain, with the fused
+    prolongation) on tiles that meet no boundary."""
     print("vcycle parity n=%d" % n, flush=True)
     K = _K(n, kind)
     s = _gpu(binding, n, case, K, levels=levels, nu=2, omega=0.8)
@@ -222,3 +199,60 @@ def test_solve_256_true_residual(binding):
     assert info["converged"]
     assert np.linalg.norm(b - A @ x) <= 1e-8 * np.linalg.norm(b) * (1 + 1e-6)
     s.close()
+
+
+@pytest.mark.parametrize("n,levels,precision", [(64, 5, "fp64"), (64, 5, "fp32"), (128, 6, "fp64")])
+def test_block_contrast_vcycle_parity(binding, n, levels, precision):
+    """The physics of the 2048 x 2048 workload at a smaller mesh: K = 1 or 1e-6 on tiles of 1/32
+    of the side, nu = 0.4999, V(2,2) Vanka with its weight 0.72.  FP64: to 4 eps kappa of the
+    oracle's patch and coarsest matrices.  FP32 form (FP32 vectors, FP64 patch arithmetic): to
+    1e-4 of the FP64 oracle, the bound of the other FP32-form cycle tests."""
+    print("block vcycle parity n=%d %s" % (n, precision), flush=True)
+    K = block_perm(n)
+    s = _gpu(binding, n, "block", K, levels=levels, nu=2, omega=0.72, precision=precision)
+    H = Hierarchy(n, _params("block"), K_tri=K, smoother="vanka", omega=0.72, nu1=2, nu2=2, levels=levels)
+    r = inputs.rhs_uniform(n, 9)
+    z = s.vcycle(_t(r)).cpu().numpy()
+    ref = H.vcycle(r)
+    tol, kap = _tol_from_patches([Al for lev in H.levels[:-1] for _, Al in lev.smoother.groups],
+                                 [np.linalg.cond(H.levels[-1].A.toarray())])
+    if precision != "fp64":
+        tol = max(tol, 1e-4)
+    err = _rel(z, ref)
+    print("  rel diff %.2e  tol %.2e  (kappa %.2e)" % (err, tol, kap), flush=True)
+    assert err < tol
+    s.close()
+
+
+def test_block_contrast_solution_matches_direct_solve(binding):
+    """The block-contrast physics at n = 64: FGMRES (restart 100) to 1e-10 against a sparse
+    direct solve, per field (u, w, and p with its mean removed), each bounded by
+    ||A^{-1}||_2 ||b - A x|| relative to the field's norm; ||A^{-1}||_2 = 1 / min |eigenvalue|
+    (A is symmetric) by shift-invert Lanczos."""
+    import scipy.sparse.linalg as spla
+    n, levels = 64, 5
+    K = block_perm(n)
+    s = _gpu(binding, n, "block", K, levels=levels, nu=2, omega=0.72)
+    asm = Assembly(Mesh(n), _params("block"), K)
+    A = asm.A.tocsc()
+    b = inputs.rhs_uniform(n, 3)
+    x, info = s.solve(_t(b), tol=1e-10, restart=100, maxit=1500)
+    s.close()
+    x = x.cpu().numpy()
+    xs = spla.spsolve(A, b)
+    lam_min = abs(spla.eigsh(A, k=1, sigma=0.0, which="LM", return_eigenvectors=False)[0])
+    res = np.linalg.norm(b - A @ x)
+    bound = res / lam_min
+    su, sw, sp = asm.slices()
+    out = []
+    for name, sl in (("u", su), ("w", sw), ("p", sp)):
+        a, r = x[sl], xs[sl]
+        if name == "p":
+            a, r = a - a.mean(), r - r.mean()
+        out.append((name, np.linalg.norm(a - r) / np.linalg.norm(r), bound / np.linalg.norm(r)))
+        print("  %s: rel error %.2e, bound %.2e" % out[-1], flush=True)
+    print("  iterations %d, rel. residual %.2e, min |eig| %.3e" % (info["iters"], info["rel_res_true"], lam_min),
+          flush=True)
+    assert info["converged"] and res <= 1.0001e-10 * np.linalg.norm(b)
+    for name, e, bnd in out:
+        assert e <= 1.01 * bnd + 1e-12, (name, e, bnd)

@@ -6,12 +6,17 @@ K = k; Vanka V(2,2) with the Table 2 weights, inexact BSR V(1,1) with the Table 
 Asserted:
   * parity with the oracle: on sampled cells the GPU takes the oracle's iteration count (+-1)
     for the same right-hand side, and both reach 1e-6 in the true residual;
-  * against the paper's counts (tests/golden/table4_iterations.txt): every cell the paper
-    solves in fewer than 100 iterations converges here, and after the paper's number of
-    iterations its true relative residual is below 1e-4.  The counts themselves are about 1.3
-    times the printed ones; at the printed counts the residual stands at 1e-5 to 8e-5 in every
-    such cell, a constant factor that the text's description of the stopping test does not
-    account for.  BSR at nu = 0.4, k = 1e-4 stalls near 1e-5 before it reaches 1e-6;
+  * the Vanka row under the left-preconditioned reading of the stopping test (GMRES on
+    M^{-1} A x = M^{-1} b, stopping on the preconditioned residual): every one of the 36 cells
+    within +-2 of the paper's count (tests/golden/table4_iterations.txt), on the GPU, with the
+    oracle's count (+-1) on sampled cells;
+  * with right-preconditioned FGMRES stopping on the true residual (the library's default):
+    every cell the paper solves in fewer than 100 iterations converges here, and after the
+    paper's number of iterations its true relative residual is below 1e-4.  The counts
+    themselves are about 1.3 times the printed ones; at the printed counts the residual stands
+    at 1e-5 to 8e-5 in every such cell.  No reading tried reproduces the BSR row (the readings
+    and their counts are tabulated in the design notes).  BSR at nu = 0.4, k = 1e-4 stalls near
+    1e-5 before it reaches 1e-6 with restart 30;
   * the two BSR cells the paper reports as failures (452 and 299 iterations at nu = 0.45 and
     0.49, k = 1e-8) fail here too: they do not reach 1e-6 within four times the median count
     of the rest of their row, and after the paper's count their residual is still above 1e-3.
@@ -29,7 +34,7 @@ from paper_2107_04060_amd import inputs  # noqa: E402
 from oracle import manufactured as mf  # noqa: E402
 from oracle.fem import BiotParams  # noqa: E402
 from oracle.multigrid import Hierarchy  # noqa: E402
-from oracle.krylov import fgmres  # noqa: E402
+from oracle.krylov import fgmres, gmres_left  # noqa: E402
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 KS = [1.0, 1e-2, 1e-4, 1e-6, 1e-8, 1e-10]
@@ -108,6 +113,43 @@ def test_table4_row(binding, sm, nu):
             assert r < 1e-4, (k, pc, r)
         else:
             assert not info["converged"] and r > 1e-3, (k, info, r)
+
+
+@pytest.mark.parametrize("nu", NUS)
+def test_table4_vanka_row_left_preconditioned(binding, nu):
+    """The Vanka row under the left-preconditioned reading: within +-2 of the paper's count in
+    every cell."""
+    paper = _paper_counts()
+    out = []
+    for k in KS:
+        s, P = _gpu_solver(binding, "vanka", nu, k)
+        b = torch.tensor(mf.rhs(N, P), dtype=torch.float64, device="cuda")
+        _, info = s.solve(b, tol=TOL, restart=30, maxit=100, side="left")
+        s.close()
+        out.append((k, info))
+        print("  vanka nu %-5g k %-6g left-preconditioned: %3d iterations (paper %3d), preconditioned %.1e, "
+              "true %.1e" % (nu, k, info["iters"], paper[("vanka", nu, k)], info["rel_res_prec"],
+                             info["rel_res_true"]), flush=True)
+    for k, info in out:
+        assert info["converged"] and info["rel_res_prec"] <= TOL * (1 + 1e-9), (k, info)
+        assert abs(info["iters"] - paper[("vanka", nu, k)]) <= 2, (k, info["iters"])
+
+
+@pytest.mark.parametrize("nu,k", [(0.0, 1e-4), (0.45, 1e-8), (0.499, 1.0)])
+def test_table4_left_preconditioned_matches_oracle(binding, nu, k):
+    s, P = _gpu_solver(binding, "vanka", nu, k)
+    b = mf.rhs(N, P)
+    _, info = s.solve(torch.tensor(b, dtype=torch.float64, device="cuda"), tol=TOL, restart=30, maxit=100,
+                      side="left")
+    s.close()
+    om, _ = _weights()[("vanka", nu, k)]
+    H = Hierarchy(N, P, K_tri=k, smoother="vanka", omega=om, nu1=2, nu2=2, levels=LEVELS)
+    _, io = gmres_left(H.A, b, H.vcycle, tol=TOL, restart=30, maxit=100)
+    print("  vanka nu %g k %g left: gpu %d (%.2e) oracle %d (%.2e)"
+          % (nu, k, info["iters"], info["rel_res_prec"], io["iters"], io["rel_res_prec"]), flush=True)
+    assert io["converged"] and info["converged"]
+    assert abs(io["iters"] - info["iters"]) <= 1
+    assert abs(info["rel_res_true"] - io["rel_res_true"]) <= 0.05 * io["rel_res_true"]
 
 
 @pytest.mark.parametrize("sm,nu,k", [("vanka", 0.4, 1.0), ("vanka", 0.0, 1e-8), ("bsr", 0.2, 1.0),

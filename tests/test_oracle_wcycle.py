@@ -69,3 +69,27 @@ def test_wcycle_converges_where_the_vcycle_stalls(nu, k):
     _, info = fgmres(H.A, b, H.vcycle, tol=1e-6, restart=30, maxit=100)
     print("nu %g k %g BSR W(1,1): %d iterations" % (nu, k, info["iters"]))
     assert info["converged"] and info["iters"] <= 60
+
+
+def test_gamma_from_keeps_the_fine_levels_to_one_correction():
+    """gamma_from = 1 on four levels: the finest level takes one coarse correction, which is the
+    W-cycle of the three coarser levels, composed here by hand from the full W-cycle hierarchy's
+    own level-1 cycle; gamma_from = levels - 2 repeats nothing and is the V-cycle."""
+    n = 32
+    b = inputs.rhs_uniform(n, 5)
+    kw = dict(K_tri=1e-2, smoother="vanka", omega=0.8, nu1=2, nu2=2, levels=4)
+    Hw = Hierarchy(n, _P(), gamma=2, **kw)
+    Hf = Hierarchy(n, _P(), gamma=2, gamma_from=1, **kw)
+    lev = Hw.levels[0]
+    x = np.zeros_like(b)
+    for _ in range(2):
+        x = lev.smoother.smooth(x, b)
+    xc = Hw.vcycle(lev.P.T @ (b - lev.A @ x), level=1)
+    x = x + lev.P @ xc
+    for _ in range(2):
+        x = lev.smoother.smooth(x, b)
+    got = Hf.vcycle(b)
+    assert np.linalg.norm(got - x) <= 1e-13 * np.linalg.norm(x)
+    assert np.linalg.norm(got - Hw.vcycle(b)) > 1e-6 * np.linalg.norm(x)
+    v = Hierarchy(n, _P(), **kw).vcycle(b)
+    assert np.array_equal(Hierarchy(n, _P(), gamma=2, gamma_from=2, **kw).vcycle(b), v)
