@@ -307,6 +307,9 @@ static void levels_bsr(biot_ctx* c, hipStream_t st) {
         if (!lv.bsrd64.p) {
             lv.bsrd64.alloc(5 * lv.L.plane * sizeof(double));
             lv.bsrd32.alloc(5 * lv.L.plane * sizeof(float));
+            // the diagonal kernels write the mesh slots only; the ghost ring stays zero
+            launch_fill(lv.bsrd64.as<double>(), 5 * lv.L.plane, 0.0, st);
+            launch_fill(lv.bsrd32.as<float>(), 5 * lv.L.plane, 0.0f, st);
             lv.bs64.alloc(len * sizeof(double));
             lv.bs32.alloc(len * sizeof(float));
             launch_fill(lv.bs64.as<double>(), lv.L.len, 0.0, st);
@@ -1053,12 +1056,19 @@ int biot_setup_hierarchy(biot_ctx* c, const biot_mg_opts* o, void* stream) {
             for (size_t l = 1; l + 1 < c->levels.size(); ++l) {
                 Level& lw = *c->levels[l];
                 const size_t len = (size_t)lw.L.len;
+                // zero-filled: the ghost ring and absent DoFs must hold zero (the residual of a
+                // revisit is written on the mesh slots only, and the cycle stages windows that
+                // reach into the ghost ring)
                 if (o->precision == BIOT_PREC_FP64) {
                     lw.wx64.alloc(len * sizeof(double));
                     lw.wb64.alloc(len * sizeof(double));
+                    launch_fill(lw.wx64.as<double>(), lw.L.len, 0.0, st);
+                    launch_fill(lw.wb64.as<double>(), lw.L.len, 0.0, st);
                 } else {
                     lw.wx32.alloc(len * sizeof(float));
                     lw.wb32.alloc(len * sizeof(float));
+                    launch_fill(lw.wx32.as<float>(), lw.L.len, 0.0f, st);
+                    launch_fill(lw.wb32.as<float>(), lw.L.len, 0.0f, st);
                 }
             }
         }
