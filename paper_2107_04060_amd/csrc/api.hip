@@ -77,7 +77,7 @@ struct Level {
     DevBuf bs64, bs32;                  // BSR scratch vector (padded)
     DevBuf sch64, sch32;                // BSR Schur sweeps (s, two pressure buffers) or CG (dp, r, z, p, q): 10 planes
     DevBuf cgred;                       // BSR Schur CG: partial sums and scalars (doubles)
-    DevBuf wx64, wb64, wx32, wb32;      // W-cycles: accumulated correction, residual of a revisit
+    DevBuf fac64;                       // variable K: the factors of every vertex patch (PFAC planes)
     double cS = 0;                      // (1/M + alpha^2 / (lambda + mu)) |T| of this level
     template <typename T>
     LevelView<T> view() const;
@@ -97,6 +97,7 @@ LevelView<double> Level::view<double>() const {
     v.uinv = uinv64.as<double>();
     v.bsrd = bsrd64.as<double>();
     v.minv = minv64.as<double>();
+    v.fac = fac64.as<double>();
     return v;
 }
 template <>
@@ -113,6 +114,7 @@ LevelView<float> Level::view<float>() const {
     v.uinv = uinv32.as<float>();
     v.bsrd = bsrd32.as<float>();
     v.minv = minv64.as<double>();
+    v.fac = fac64.as<double>();
     return v;
 }
 
@@ -297,6 +299,22 @@ static void levels_kinv(biot_ctx* c, const double* K_tri, hipStream_t st, int mo
     for (auto& lv : c->levels) launch_convert(lv->kinv64.as<double>(), lv->kinv32.as<float>(), 2 * lv->L.plane, st);
 }
 
+// Variable K: the factors of every vertex patch of the smoothing levels with at most FAC_MAX_N
+// cells per side, from the current 1/K (they depend on the permeability only; a relaxation step
+// applies them).  On these levels a launch covers few tiles and the length of one patch's
+// dependent chain sets its time; on larger ones the FP64 factor loads (624 B per patch, read
+// through partial cache lines in a colour step) cost more than forming the factors on the spot.
+constexpr int FAC_MAX_N = 256;
+static void levels_factors(biot_ctx* c, hipStream_t st) {
+    if (c->K_uniform) return;
+    for (size_t l = 0; l + 1 < c->levels.size(); ++l) {
+        Level& lv = *c->levels[l];
+        if (lv.n > FAC_MAX_N) continue;
+        if (!lv.fac64.p) lv.fac64.alloc((size_t)PFAC * lv.L.plane * sizeof(double));
+        launch_patch_factors(lv.view<double>(), lv.fac64.as<double>(), st);
+    }
+}
+
 // BSR diagonal data of every smoothing level from the current 1/K (Appendix D)
 static void levels_bsr(biot_ctx* c, hipStream_t st) {
     const PhysParams& p = c->phys;
@@ -372,8 +390,6 @@ struct VecSet<double> {
     static double* r(Level& l) { return l.r64.as<double>(); }
     static double* s(Level& l) { return l.bs64.as<double>(); }
     static double* sch(Level& l) { return l.sch64.as<double>(); }
-    static double* wx(Level& l) { return l.wx64.as<double>(); }
-    static double* wb(Level& l) { return l.wb64.as<double>(); }
 };
 template <>
 struct VecSet<float> {
@@ -382,8 +398,6 @@ struct VecSet<float> {
     static float* r(Level& l) { return l.r32.as<float>(); }
     static float* s(Level& l) { return l.bs32.as<float>(); }
     static float* sch(Level& l) { return l.sch32.as<float>(); }
-    static float* wx(Level& l) { return l.wx32.as<float>(); }
-    static float* wb(Level& l) { return l.wb32.as<float>(); }
 };
 
 // Event pair for one launch when kernel timing is on for this level (kind 0 Vanka, 1 residual):
@@ -482,14 +496,15 @@ struct PW<float> {
 // V(nu1, nu2) cycle on level l for A_l x = b from x = 0, iterate buffers buf0 / buf1 (both zero
 // on absent DoFs).  Returns the buffer that holds the result.
 template <typename T>
-static T* vcycle_level(biot_ctx* c, int l, const T* b, T* buf0, T* buf1, hipStream_t st) {
+static T* vcycle_level(biot_ctx* c, int l, const T* b, T* buf0, T* buf1, hipStream_t st, T* x0 = nullptr) {
     Level& lv = *c->levels[l];
     if (l == (int)c->levels.size() - 1) {
         launch_coarse_solve<T>(c->coarse_inv.as<double>(), c->coarse_N, c->coarse_idx.as<int>(), b, buf0, st);
         return buf0;
     }
     const bool inplace = c->opts.smoother != BIOT_SMOOTHER_VANKA;
-    T* cur = nullptr;
+    // the iterate: zero, or x0 (buf0 or buf1) when the cycle continues from a previous one
+    T* cur = x0;
     auto next = [&]() { return cur == nullptr ? buf0 : (inplace ? cur : (cur == buf0 ? buf1 : buf0)); };
     auto other = [&](T* d) { return d == buf0 ? buf1 : buf0; };
     for (int s = 0; s < c->opts.nu1; ++s) {
@@ -507,17 +522,11 @@ static T* vcycle_level(biot_ctx* c, int l, const T* b, T* buf0, T* buf1, hipStre
                                 PW<T>::get(c), st, &tm);
     T* xc = vcycle_level<T>(c, l + 1, bc, XBuf<T>::get(lc, 0), XBuf<T>::get(lc, 1), st);
     if (c->opts.gamma > 1 && l >= c->opts.gamma_from && l + 2 < (int)c->levels.size()) {
-        // W-cycle: gamma - 1 further cycles of level l + 1 on the residual left by the previous
-        // ones (the coarsest level's direct solve is exact and not repeated)
-        T* acc = VecSet<T>::wx(lc);
-        T* rc = VecSet<T>::wb(lc);
-        BIOT_HIP(hipMemcpyAsync(acc, xc, lc.L.len * sizeof(T), hipMemcpyDeviceToDevice, st));
-        for (int g = 1; g < c->opts.gamma; ++g) {
-            launch_apply<T>(lc.view<T>(), acc, bc, rc, 1, st);
-            T* d = vcycle_level<T>(c, l + 1, rc, XBuf<T>::get(lc, 0), XBuf<T>::get(lc, 1), st);
-            launch_add<T>(acc, d, lc.L.len, st);
-        }
-        xc = acc;
+        // W-cycle: gamma - 1 further cycles of level l + 1, each continuing from the iterate the
+        // previous one left (with linear smoothing the same as a cycle from zero on the residual
+        // it left, added to it); the coarsest level's direct solve is exact and not repeated
+        for (int g = 1; g < c->opts.gamma; ++g)
+            xc = vcycle_level<T>(c, l + 1, bc, XBuf<T>::get(lc, 0), XBuf<T>::get(lc, 1), st, xc);
     }
     int s0 = 0;
     if (c->opts.nu2 > 0) {
@@ -1049,29 +1058,9 @@ int biot_setup_hierarchy(biot_ctx* c, const biot_mg_opts* o, void* stream) {
                                 c->levels[l]->kinv64.as<double>(), c->levels[l]->L, st);
         for (auto& lv : c->levels)
             launch_convert(lv->kinv64.as<double>(), lv->kinv32.as<float>(), 2 * lv->L.plane, st);
+        levels_factors(c, st);
         c->opts = *o;
         if (c->opts.gamma < 1) c->opts.gamma = 1;
-        if (c->opts.gamma > 1) {
-            // W-cycle buffers of the levels that are revisited (all but the finest and coarsest)
-            for (size_t l = 1; l + 1 < c->levels.size(); ++l) {
-                Level& lw = *c->levels[l];
-                const size_t len = (size_t)lw.L.len;
-                // zero-filled: the ghost ring and absent DoFs must hold zero (the residual of a
-                // revisit is written on the mesh slots only, and the cycle stages windows that
-                // reach into the ghost ring)
-                if (o->precision == BIOT_PREC_FP64) {
-                    lw.wx64.alloc(len * sizeof(double));
-                    lw.wb64.alloc(len * sizeof(double));
-                    launch_fill(lw.wx64.as<double>(), lw.L.len, 0.0, st);
-                    launch_fill(lw.wb64.as<double>(), lw.L.len, 0.0, st);
-                } else {
-                    lw.wx32.alloc(len * sizeof(float));
-                    lw.wb32.alloc(len * sizeof(float));
-                    launch_fill(lw.wx32.as<float>(), lw.L.len, 0.0f, st);
-                    launch_fill(lw.wb32.as<float>(), lw.L.len, 0.0f, st);
-                }
-            }
-        }
         if (o->precision != BIOT_PREC_FP64) alloc_fp32(c, st);
         for (auto& lp : c->levels) lp->patch32 = o->precision == BIOT_PREC_FP32_PATCH;
         if (o->smoother == BIOT_SMOOTHER_BSR) levels_bsr(c, st);
@@ -1221,6 +1210,7 @@ static int update_perm(biot_ctx* c, const double* field, int mode, void* stream)
     check_field(c, field, mode, st);
     c->K_uniform = false;
     levels_kinv(c, field, st, mode);
+    if (c->have_hierarchy) levels_factors(c, st);
     if (c->have_hierarchy && c->opts.smoother == BIOT_SMOOTHER_BSR) levels_bsr(c, st);
     if (c->have_hierarchy) coarse_factor(c, st);
     check_stream_error();

@@ -30,6 +30,8 @@ struct LevelView {
     const T* uinv;                 // 9 x 8 x 8 displacement-patch inverses (BSR; identity on absent DoFs)
     const T* bsrd;                 // BSR diagonal data, 5 planes (k_bsr_wdiag / k_bsr_sdiag)
     const double* minv;            // 9 x 20 x 20 full patch inverses (uniform K), or null
+    const double* fac;             // variable K: the FP64 factors of every vertex patch (PFAC planes of
+                                   // the level's slot layout, patch_factor), or null
 };
 
 // vector plumbing
@@ -65,6 +67,10 @@ template <typename T>
 void launch_vanka_step(const LevelView<T>& lv, const T* x_in, const T* b, T* x_out, bool uniform, T kinv_s,
                        T omega, hipStream_t st, const T* xc = nullptr, const Layout* Lc = nullptr,
                        const T* pw = nullptr, const LaunchTiming* tm = nullptr, int color = -1);
+
+// the permeability-dependent factors of every vertex patch of a level (variable K, FP64):
+// fac[q * L.plane + slot(i, j)], q < PFAC (patch_solve.h)
+void launch_patch_factors(const LevelView<double>& lv, double* fac, hipStream_t st);
 
 // grid transfers
 // (w: the NPWEIGHTS prolongation weights of structure.h, device)

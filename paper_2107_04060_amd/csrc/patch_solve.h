@@ -7,7 +7,8 @@
 // The pressure constant on the star is an exact eigenvector of S with eigenvalue (1/M)|T|
 // (the patch velocities carry no net flux of it): its coefficient is solved for in closed
 // form, gamma = -sum(rp) / sum(c), and S is made well conditioned by a rank-one shift on
-// that direction before the Cholesky factorization.
+// that direction before the Cholesky factorization.  The factorizations depend on the
+// permeability only (patch_factor); a relaxation step applies them (patch_apply).
 #pragma once
 #include "kernels.h"
 
@@ -85,80 +86,103 @@ __host__ __device__ inline void star_w_factor(const DevPatchClass<T>& pc, const 
     chol6p(w);
 }
 
-// rr: patch residual (absent slots hold 0); kv: 1/K of the six star triangles;
-// wblk: RT0 mass blocks of the star triangles (1/K = 1); out[a * ostride], a = 0..19.
-// with_mean = false omits the star-mean pressure term (the deflated solve).
-// ALLP: every slot of the patch is present (interior class), known at compile time.
-// With W = L L^T, Q W^-1 Q^T = Z^T Z for Z = L^-1 Q^T, Q W^-1 r_w = Z^T zr for zr = L^-1 r_w, and
-// x_w = L^-T (zr - Z x_p): seven forward substitutions and one backward one, no divisions
-// beyond the two factorizations.
-template <typename T, bool ALLP = false>
-__host__ __device__ inline void patch_solve(const T rr[PATCH], const DevPatchClass<T>& pc, const T kv[6],
-                                            const T* __restrict__ wblk, T* out, int ostride,
-                                            bool with_mean = true) {
+// The residual-independent part of a patch solve, which depends on the permeability only:
+// w = L_W (Cholesky factor of the star's RT0 mass W, 1 / L_jj on the diagonal), z[q] = L_W^-1
+// (row q of Q)^T, and s = the Cholesky factor of S = C + G + Z^T Z with the rank-one shift on the
+// star-constant direction (see patch_apply).  78 values; stored per patch by k_patch_factors so
+// that a relaxation step only applies them.
+constexpr int PFAC = 21 + 36 + 21;
+template <typename T>
+struct PatchFac {
     T w[21];
-    star_w_factor<T, ALLP>(pc, kv, wblk, w);
-    // zr = L^-1 r_w; z[q] = L^-1 (row q of Q)^T
-    T zr[6];
-#pragma unroll
-    for (int a = 0; a < 6; ++a) zr[a] = rr[8 + a];
-    fwd6p(w, zr);
     T z[6][6];
+    T s[21];
+};
+
+static_assert(sizeof(PatchFac<double>) == PFAC * sizeof(double), "factor record layout");
+
+template <typename T, bool ALLP = false>
+__host__ __device__ inline void patch_factor(const DevPatchClass<T>& pc, const T kv[6], const T* __restrict__ wblk,
+                                             PatchFac<T>& f) {
+    star_w_factor<T, ALLP>(pc, kv, wblk, f.w);
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
 #pragma unroll
-        for (int a = 0; a < 6; ++a) z[q][a] = pc.Q[q][a];
-        fwd6p(w, z[q]);
+        for (int a = 0; a < 6; ++a) f.z[q][a] = pc.Q[q][a];
+        fwd6p(f.w, f.z[q]);
     }
-    // S = C + G + Z^T Z, rhs = H^T r_u + Z^T zr - r_p
-    T s[21], rhs[6];
+    // S = C + G + Z^T Z, then the shift beta (1 1^T on the present pressures), beta = tr(S) / k^2
+    int k = 0;
+    T tr = 0;
 #pragma unroll
     for (int q1 = 0; q1 < 6; ++q1) {
 #pragma unroll
         for (int q2 = 0; q2 <= q1; ++q2) {
             T v = pc.G[q1][q2];
 #pragma unroll
-            for (int a = 0; a < 6; ++a) v += z[q1][a] * z[q2][a];
-            s[tri6(q1, q2)] = v;
+            for (int a = 0; a < 6; ++a) v += f.z[q1][a] * f.z[q2][a];
+            f.s[tri6(q1, q2)] = v;
         }
-        s[tri6(q1, q1)] += pc.c[q1];
+        f.s[tri6(q1, q1)] += pc.c[q1];
+        if (ALLP || pc.present[14 + q1]) {
+            ++k;
+            tr += f.s[tri6(q1, q1)];
+        }
+    }
+    const T rk = (T)1 / (T)k;
+    const T beta = tr * rk * rk;
+#pragma unroll
+    for (int q1 = 0; q1 < 6; ++q1)
+#pragma unroll
+        for (int q2 = 0; q2 <= q1; ++q2) {
+            if (ALLP || (pc.present[14 + q1] && pc.present[14 + q2]))
+                f.s[tri6(q1, q2)] += beta;
+            else
+                f.s[tri6(q1, q2)] = (q1 == q2) ? (T)1 : (T)0;
+        }
+    chol6p(f.s);
+}
+
+// rr: patch residual (absent slots hold 0); f: the patch's factors (patch_factor); out[a *
+// ostride], a = 0..19.  with_mean = false omits the star-mean pressure term (the deflated solve).
+// ALLP: every slot of the patch is present (interior class), known at compile time.
+// With W = L L^T, Q W^-1 Q^T = Z^T Z for Z = L^-1 Q^T, Q W^-1 r_w = Z^T zr for zr = L^-1 r_w, and
+// x_w = L^-T (zr - Z x_p): one forward and one backward substitution with L, none with a division.
+template <typename T, bool ALLP = false>
+__host__ __device__ inline void patch_apply(const T rr[PATCH], const DevPatchClass<T>& pc, const PatchFac<T>& f,
+                                            T* out, int ostride, bool with_mean = true) {
+    T zr[6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) zr[a] = rr[8 + a];
+    fwd6p(f.w, zr);
+    // rhs = H^T r_u + Z^T zr - r_p
+    T rhs[6];
+#pragma unroll
+    for (int q1 = 0; q1 < 6; ++q1) {
         T v = -rr[14 + q1];
 #pragma unroll
         for (int a = 0; a < 8; ++a) v += pc.H[a][q1] * rr[a];
 #pragma unroll
-        for (int a = 0; a < 6; ++a) v += z[q1][a] * zr[a];
+        for (int a = 0; a < 6; ++a) v += f.z[q1][a] * zr[a];
         rhs[q1] = v;
     }
-    // star-mean pressure in closed form; rank-one shift on the remaining system
+    // star-mean pressure in closed form; the shifted system (factored in f.s) for the rest
     int k = 0;
-    T sum_rp = 0, csum = 0, tr = 0, mrhs = 0;
+    T sum_rp = 0, csum = 0, mrhs = 0;
 #pragma unroll
     for (int q = 0; q < 6; ++q)
         if (ALLP || pc.present[14 + q]) {
             ++k;
             sum_rp += rr[14 + q];
             csum += pc.c[q];
-            tr += s[tri6(q, q)];
             mrhs += rhs[q];
         }
     const T gamma = -sum_rp / csum;
-    const T rk = (T)1 / (T)k;
-    mrhs *= rk;
-    const T beta = tr * rk * rk;
+    mrhs *= (T)1 / (T)k;
 #pragma unroll
-    for (int q1 = 0; q1 < 6; ++q1) {
-#pragma unroll
-        for (int q2 = 0; q2 <= q1; ++q2) {
-            if (ALLP || (pc.present[14 + q1] && pc.present[14 + q2]))
-                s[tri6(q1, q2)] += beta;
-            else
-                s[tri6(q1, q2)] = (q1 == q2) ? (T)1 : (T)0;
-        }
-        rhs[q1] = (ALLP || pc.present[14 + q1]) ? rhs[q1] - mrhs : (T)0;
-    }
-    chol6p(s);
-    fwd6p(s, rhs);
-    bwd6p(s, rhs);
+    for (int q1 = 0; q1 < 6; ++q1) rhs[q1] = (ALLP || pc.present[14 + q1]) ? rhs[q1] - mrhs : (T)0;
+    fwd6p(f.s, rhs);
+    bwd6p(f.s, rhs);
     // x_p = xp0 + gamma on the present pressures.  The star constant carries no flux
     // (Bh^T 1 = Q^T 1 = 0), so the back-substitutions take the deflated part xp0 alone: the
     // same values in exact arithmetic, without cancelling the often large gamma in rounding.
@@ -181,15 +205,27 @@ __host__ __device__ inline void patch_solve(const T rr[PATCH], const DevPatchCla
     for (int a = 0; a < 6; ++a) {
         T v = zr[a];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) v -= z[q][a] * xp[q];
+        for (int q = 0; q < 6; ++q) v -= f.z[q][a] * xp[q];
         xw[a] = v;
     }
-    bwd6p(w, xw);
+    bwd6p(f.w, xw);
 #pragma unroll
     for (int a = 0; a < 6; ++a) out[(8 + a) * ostride] = (ALLP || pc.present[8 + a]) ? xw[a] : (T)0;
 #pragma unroll
     for (int q = 0; q < 6; ++q)
         out[(14 + q) * ostride] = (ALLP || pc.present[14 + q]) ? xp[q] + (with_mean ? gamma : (T)0) : (T)0;
+}
+
+// rr: patch residual (absent slots hold 0); kv: 1/K of the six star triangles;
+// wblk: RT0 mass blocks of the star triangles (1/K = 1); out[a * ostride], a = 0..19:
+// the factors of the patch formed on the spot, then applied.
+template <typename T, bool ALLP = false>
+__host__ __device__ inline void patch_solve(const T rr[PATCH], const DevPatchClass<T>& pc, const T kv[6],
+                                            const T* __restrict__ wblk, T* out, int ostride,
+                                            bool with_mean = true) {
+    PatchFac<T> f;
+    patch_factor<T, ALLP>(pc, kv, wblk, f);
+    patch_apply<T, ALLP>(rr, pc, f, out, ostride, with_mean);
 }
 
 }  // namespace biot

@@ -88,6 +88,7 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
                                                 T kinv_s, const T* __restrict__ coef,
                                                 const DevPatchClass<P>* __restrict__ cls,
                                                 const P* __restrict__ wblk, const double* __restrict__ minv,
+                                                const double* __restrict__ fac,
                                                 T omega, const T* __restrict__ xc, const Layout& Lc,
                                                 const T* __restrict__ pw, int color, int bx, int by,
                                                 VankaLds<T, P, UNIFORM, NCLS, PROL>& sh) {
@@ -323,7 +324,11 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
     } else {
         // per-patch elimination (permeability varies from patch to patch) in precision P, class
         // data from LDS.  A tile that meets no boundary holds interior-class patches only, every
-        // slot present.
+        // slot present.  With fac (FP64, the small levels): the permeability-dependent factors of
+        // the patch were formed at set-up (k_patch_factors) and are only applied here, which
+        // shortens the dependent chain that bounds a launch on a few tiles; otherwise they are
+        // formed on the spot.
+        constexpr bool FACOK = std::is_same_v<P, double>;
         P out[PATCH];
 #pragma unroll
         for (int s = 0; s < PATCH; ++s) out[s] = 0;
@@ -343,8 +348,25 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
                 star_tri(kq, ut, di, dj);
                 kv[kq] = (P)sh.ks[ut][ty + 2 + dj][tx + 2 + di];
             }
+            // the patch's stored factors (FP64)
+            auto load_fac = [&](PatchFac<double>& f) {
+                const double* fp = fac + slot_index(L, vi, vj);
+                double* fv = reinterpret_cast<double*>(&f);
+#pragma unroll
+                for (int q = 0; q < PFAC; ++q) fv[q] = fp[(long long)q * L.plane];
+            };
             if (inner) {
-                patch_solve<P, true>(rr, sh.pcs[0], kv, wblk, out, 1);
+                if constexpr (FACOK) {
+                    if (fac) {
+                        PatchFac<double> f;
+                        load_fac(f);
+                        patch_apply<P, true>(rr, sh.pcs[0], f, out, 1);
+                    } else {
+                        patch_solve<P, true>(rr, sh.pcs[0], kv, wblk, out, 1);
+                    }
+                } else {
+                    patch_solve<P, true>(rr, sh.pcs[0], kv, wblk, out, 1);
+                }
             } else {
                 const int ci = vi == 0 ? 0 : (vi == n ? 2 : 1);
                 const int cj = vj == 0 ? 0 : (vj == n ? 2 : 1);
@@ -352,7 +374,19 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
                 bool keep = false;
 #pragma unroll
                 for (int s = 0; s < 14; ++s) keep = keep || pc.present[s];
-                if (keep) patch_solve<P>(rr, pc, kv, wblk, out, 1);
+                if (keep) {
+                    if constexpr (FACOK) {
+                        if (fac) {
+                            PatchFac<double> f;
+                            load_fac(f);
+                            patch_apply<P>(rr, pc, f, out, 1);
+                        } else {
+                            patch_solve<P>(rr, pc, kv, wblk, out, 1);
+                        }
+                    } else {
+                        patch_solve<P>(rr, pc, kv, wblk, out, 1);
+                    }
+                }
             }
         }
         __syncthreads();
@@ -399,14 +433,15 @@ __global__ __launch_bounds__(TPB * NZ, NZ == 2 ? 4 : (sizeof(P) == 4 ? 2 : 1)) v
                                                     T kinv_s, const T* __restrict__ coef,
                                                     const DevPatchClass<P>* __restrict__ cls,
                                                     const P* __restrict__ wblk,
-                                                    const double* __restrict__ minv, T omega,
+                                                    const double* __restrict__ minv,
+                                                    const double* __restrict__ fac, T omega,
                                                     const T* __restrict__ xc, Layout Lc,
                                                     const T* __restrict__ pw, int color) {
     __shared__ VankaLds<T, P, UNIFORM, NCLS, PROL> sh;
     int bx, by;
     xcd_tile(bx, by);
-    vanka_step_tile<T, P, UNIFORM, ZERO, NCLS, PROL, NZ>(x_in, b, x_out, L, kinv, kinv_s, coef, cls, wblk, minv, omega,
-                                                      xc, Lc, pw, color, bx, by, sh);
+    vanka_step_tile<T, P, UNIFORM, ZERO, NCLS, PROL, NZ>(x_in, b, x_out, L, kinv, kinv_s, coef, cls, wblk, minv, fac,
+                                                      omega, xc, Lc, pw, color, bx, by, sh);
 }
 
 // thread layers of the constant-K step (two: 512 threads per tile, each phase split over twice
@@ -434,12 +469,12 @@ static void launch_vanka_step_t(const LevelView<T>& lv, const T* x_in, const T* 
     // a tile spans at most two vertex classes per direction unless it covers the whole mesh
     if (lv.L.n + 1 <= VT)
         hipExtLaunchKernelGGL((k_vanka_step<T, P, UNIFORM, ZERO, 9, PROL, NZ>), grd, blk, 0, st, e0, e1, 0, x_in, b,
-                              x_out, lv.L, lv.kinv, kinv_s, lv.coef, cls, wblk, lv.minv, omega, xc, Lc, pw,
-                              color);
+                              x_out, lv.L, lv.kinv, kinv_s, lv.coef, cls, wblk, lv.minv, lv.fac, omega, xc, Lc,
+                              pw, color);
     else
         hipExtLaunchKernelGGL((k_vanka_step<T, P, UNIFORM, ZERO, 4, PROL, NZ>), grd, blk, 0, st, e0, e1, 0, x_in, b,
-                              x_out, lv.L, lv.kinv, kinv_s, lv.coef, cls, wblk, lv.minv, omega, xc, Lc, pw,
-                              color);
+                              x_out, lv.L, lv.kinv, kinv_s, lv.coef, cls, wblk, lv.minv, lv.fac, omega, xc, Lc,
+                              pw, color);
 }
 
 // the ZERO / PROL forms of one (T, P, UNIFORM)
@@ -473,6 +508,46 @@ void launch_vanka_step(const LevelView<T>& lv, const T* x_in, const T* b, T* x_o
         }
     }
     launch_vanka_forms<T, double, false>(lv, x_in, b, x_out, kinv_s, omega, xc, lc, pw, tm, st, color);
+}
+
+// ---- permeability-dependent patch factors (set-up and re-assembly) ---------------------------------
+// One thread per vertex (i, j) of [0, n]^2: the factors of its patch (patch_factor) from the
+// vertex class and the 1/K of its six star triangles; vertices without a patch are skipped.
+__global__ __launch_bounds__(256) void k_patch_factors(Layout L, const double* __restrict__ kinv,
+                                                       const DevPatchClass<double>* __restrict__ cls,
+                                                       const double* __restrict__ wblk, double* __restrict__ fac) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int n = L.n;
+    if (i > n || j > n) return;
+    const int ci = i == 0 ? 0 : (i == n ? 2 : 1);
+    const int cj = j == 0 ? 0 : (j == n ? 2 : 1);
+    const DevPatchClass<double>& pc = cls[3 * cj + ci];
+    bool keep = false;
+#pragma unroll
+    for (int s = 0; s < 14; ++s) keep = keep || pc.present[s];
+    if (!keep) return;
+    double kv[6];
+#pragma unroll
+    for (int kq = 0; kq < 6; ++kq) {
+        int ut, di, dj;
+        star_tri(kq, ut, di, dj);
+        kv[kq] = kinv[ut * L.plane + slot_index(L, i + di, j + dj)];
+    }
+    PatchFac<double> f;
+    if (ci == 1 && cj == 1)
+        patch_factor<double, true>(pc, kv, wblk, f);
+    else
+        patch_factor<double>(pc, kv, wblk, f);
+    const double* fv = reinterpret_cast<const double*>(&f);
+    double* fp = fac + slot_index(L, i, j);
+#pragma unroll
+    for (int q = 0; q < PFAC; ++q) fp[(long long)q * L.plane] = fv[q];
+}
+
+void launch_patch_factors(const LevelView<double>& lv, double* fac, hipStream_t st) {
+    dim3 blk(64, 4), grd((lv.L.n + 1 + 63) / 64, (lv.L.n + 1 + 3) / 4);
+    hipLaunchKernelGGL(k_patch_factors, grd, blk, 0, st, lv.L, lv.kinv, lv.cls, lv.wblk, fac);
 }
 template void launch_vanka_step<double>(const LevelView<double>&, const double*, const double*, double*, bool,
                                         double, double, hipStream_t, const double*, const Layout*, const double*,
