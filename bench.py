@@ -27,11 +27,12 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 BLOCK_RESTART = 100          # FGMRES restart of the block-contrast workload
 # the cycle of the block-contrast workload: the fastest to 1e-8 among the V-, W- and partial
-# W-cycles with additive and multiplicative Vanka measured on it (the V(2,2) cycle with the LFA
-# weight takes 178 iterations, 3.6 s per solve)
-BLOCK_CYCLE = dict(nu12=1, omega=1.0, colors=4, gamma=2, gamma_from=3)
+# W-cycles with additive and multiplicative Vanka and 8 to 10 levels measured on it (the
+# V(2,2) cycle with the LFA weight on 10 levels takes 178 iterations, 3.6 s per solve)
+BLOCK_CYCLE = dict(nu12=1, omega=1.0, colors=4, gamma=2, gamma_from=2, levels=9)
 CSRC = os.path.join(ROOT, "paper_2107_04060_amd", "csrc")
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_vanka_step_sweep256_fp64.md")
+BLOCK_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_vanka_step_block2048_fp64.md")
 
 
 # sources that define the finest-level Vanka step (its traffic summary is valid while they are
@@ -91,6 +92,8 @@ def parse():
     ap.add_argument("--gamma-from", type=int, default=BLOCK_CYCLE["gamma_from"],
                     help="block2048: levels from this one down repeat their coarse correction gamma times")
     ap.add_argument("--restart", type=int, default=BLOCK_RESTART, help="block2048: FGMRES restart")
+    ap.add_argument("--levels", type=int, default=BLOCK_CYCLE["levels"],
+                    help="block2048: mesh levels (9: direct solve on the 8 x 8 mesh)")
     ap.add_argument("--reference", type=int, default=1,
                     help="block2048: also solve the first timed right-hand side to 1e-10 in FP64 (restart 100) "
                          "as the reference of the per-field errors")
@@ -362,7 +365,7 @@ def cpu_baseline_block(n_gpu, iters_gpu, cyc, n_sample=256):
         rng = np.random.default_rng(w["seed"])
         K = inputs.squares_to_triangles(inputs.block_contrast_squares(n_sample, n_sample // 32, rng))
         p = BiotParams(c["lam"], c["mu"], alpha=w["alpha"], M=w["M"], mu_f=w["mu_f"], tau=w["tau"])
-        lv = int(np.log2(n_sample // 4)) + 1
+        lv = int(np.log2(n_sample // cyc.get("n_coarse", 4))) + 1
         H = Hierarchy(n_sample, p, K_tri=K, smoother="vanka", omega=cyc["omega"], nu1=cyc["nu1"], nu2=cyc["nu2"],
                       levels=lv, gamma=cyc["gamma"], gamma_from=cyc["gamma_from"], vanka_colors=cyc["vanka_colors"])
         b = inputs.rhs_uniform(n_sample, w["seed"])
@@ -385,7 +388,7 @@ def main_block2048(args, binding, inputs, torch):
     steps = 8 if args.steps is None else args.steps
     w = inputs.workload("block2048")
     c = w["cases"][0]
-    n, levels = w["n"], w["levels"]
+    n, levels = w["n"], args.levels
     nf = inputs.n_free(n)
     nrhs = w["n_rhs"]
     forms = [f for f in args.forms.split(",") if f]
@@ -460,9 +463,12 @@ def main_block2048(args, binding, inputs, torch):
             if t["vanka_launches"]:
                 avg = t["vanka_ms"] / t["vanka_launches"] * 1e-3
                 vb = 3 * word * nf + 2 * word * n * n
-                roofline = {"kernel": "k_vanka_step (fused residual + additive Vanka, variable K, finest level)",
+                roofline = {"kernel": "k_vanka_step<double, double, false, false, 4, false, 1> (fused residual + "
+                                      "Vanka step on a non-zero iterate, variable K, finest level; in the "
+                                      "multiplicative cycle one colour per launch)",
                             "bound": "hbm", "achieved": round(vb / avg / 1e9, 1), "peak": HBM_PEAK_GBS,
-                            "unit": "GB/s", "frac": round(vb / avg / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                            "unit": "GB/s", "frac": round(vb / avg / 1e9 / HBM_PEAK_GBS, 4),
+                            "traffic": measured_traffic(BLOCK_TRAFFIC_PROFILE) if form == "fp64" else None,
                             "avg_launch_us": round(avg * 1e6, 2), "launches": t["vanka_launches"],
                             "algorithmic_bytes_per_launch": vb,
                             "timed_in": "the timed steps of the first form (HIP events on the solve's stream)"}
@@ -498,7 +504,7 @@ def main_block2048(args, binding, inputs, torch):
         del xref
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline_block(n, res[forms[0]]["mean_iters"], cyc)
+        cpu = cpu_baseline_block(n, res[forms[0]]["mean_iters"], dict(cyc, n_coarse=n >> (levels - 1)))
     head = res[forms[0]]
     out = {
         "metric": "FGMRES+V-cycle solve to rel.res 1e-8: MDOF/s (free DoFs 10n^2-8n+2 per right-hand-side solve)",
@@ -508,9 +514,9 @@ def main_block2048(args, binding, inputs, torch):
         "config": {"workload": "block2048", "n": n, "levels": levels, "free_dofs": nf,
                    "physics": "K 1 or 1e-6 per 64x64-cell block (seed 3), nu 0.4999, E 1, tau 1, M E/0.03",
                    "cycle": "%s Vanka, %d pre- and post-smoothing steps, omega %.2f, cycle index %d on levels >= %d "
-                            "(finer levels: one coarse correction), 10 levels" % (
+                            "(finer levels: one coarse correction), %d levels (direct solve at %d x %d)" % (
                                 "multiplicative (4 colours)" if args.colors else "additive", args.nu12, om,
-                                args.gamma, args.gamma_from),
+                                args.gamma, args.gamma_from, levels, n >> (levels - 1), n >> (levels - 1)),
                    "restart": restart, "tol": args.tol,
                    "step": "one right-hand-side solve from x = 0, hierarchy reused", "rhs_order": order,
                    "forms": forms, "all_converged": all(res[f].get("all_converged", False) for f in forms)},
