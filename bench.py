@@ -29,7 +29,7 @@ BLOCK_RESTART = 100          # FGMRES restart of the block-contrast workload
 # the cycle of the block-contrast workload: the fastest to 1e-8 among the V-, W- and partial
 # W-cycles with additive and multiplicative Vanka and 8 to 10 levels measured on it (the
 # V(2,2) cycle with the LFA weight on 10 levels takes 178 iterations, 3.6 s per solve)
-BLOCK_CYCLE = dict(nu12=1, omega=1.0, colors=4, gamma=2, gamma_from=2, levels=9)
+BLOCK_CYCLE = dict(nu12=1, omega=1.0, colors=4, gamma=2, gamma_from=1, levels=8)
 CSRC = os.path.join(ROOT, "paper_2107_04060_amd", "csrc")
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_vanka_step_sweep256_fp64.md")
 BLOCK_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_vanka_step_block2048_fp64.md")
@@ -93,7 +93,7 @@ def parse():
                     help="block2048: levels from this one down repeat their coarse correction gamma times")
     ap.add_argument("--restart", type=int, default=BLOCK_RESTART, help="block2048: FGMRES restart")
     ap.add_argument("--levels", type=int, default=BLOCK_CYCLE["levels"],
-                    help="block2048: mesh levels (9: direct solve on the 8 x 8 mesh)")
+                    help="block2048: mesh levels (8: direct solve on the 16 x 16 mesh)")
     ap.add_argument("--reference", type=int, default=1,
                     help="block2048: also solve the first timed right-hand side to 1e-10 in FP64 (restart 100) "
                          "as the reference of the per-field errors")

@@ -134,7 +134,7 @@ struct biot_ctx {
     DevBuf pw64, pw32;
     // coarsest level
     int coarse_N = 0;
-    DevBuf coarse_A, coarse_inv, coarse_idx, coarse_map, status;
+    DevBuf coarse_A, coarse_inv, coarse_col, coarse_idx, coarse_map, status;
     DevBuf kcheck;                    // status word of the permeability checks (one int)
     // local RT0 mass (K = 1) of L and U for the adjoint gradient
     DevBuf mloc;
@@ -364,6 +364,7 @@ static void coarse_setup(biot_ctx* c, hipStream_t st) {
     upload(c->coarse_map, map, st);
     c->coarse_A.alloc((size_t)N * N * sizeof(double));
     c->coarse_inv.alloc((size_t)N * N * sizeof(double));
+    c->coarse_col.alloc((size_t)N * sizeof(double));
     c->status.alloc(sizeof(int));
 }
 
@@ -372,7 +373,8 @@ static void coarse_factor(biot_ctx* c, hipStream_t st) {
     const int N = c->coarse_N;
     launch_coarse_matrix(lc.L, lc.st.as<StencilEntry>(), lc.st_off.as<int>(), lc.kinv64.as<double>(),
                          c->coarse_idx.as<int>(), c->coarse_map.as<int>(), N, c->coarse_A.as<double>(), st);
-    launch_gauss_jordan(c->coarse_A.as<double>(), c->coarse_inv.as<double>(), N, c->status.as<int>(), st);
+    launch_gauss_jordan(c->coarse_A.as<double>(), c->coarse_inv.as<double>(), N, c->coarse_col.as<double>(),
+                        c->status.as<int>(), st);
     check_stream_error();
     int status = 0;
     BIOT_HIP(hipMemcpyAsync(&status, c->status.p, sizeof(int), hipMemcpyDeviceToHost, st));

@@ -116,7 +116,9 @@ template <typename T>
 void launch_coarse_solve(const double* Ainv, int N, const int* idx, const T* b, T* x, hipStream_t st);
 void launch_coarse_matrix(const Layout& L, const StencilEntry* st_tab, const int* st_off, const double* kinv,
                           const int* free_idx, const int* free_map, int N, double* A, hipStream_t st);
-void launch_gauss_jordan(double* A, double* Inv, int N, int* status, hipStream_t st);
+// dense inverse by Gauss-Jordan with partial pivoting (A destroyed; fcol: N doubles of scratch;
+// *status = 1 on a zero pivot column)
+void launch_gauss_jordan(double* A, double* Inv, int N, double* fcol, int* status, hipStream_t st);
 
 // permeability
 void launch_kinv_from_K(const double* K_tri, double K_scalar, double* kinv, const Layout& L, hipStream_t st);

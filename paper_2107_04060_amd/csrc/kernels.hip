@@ -238,77 +238,93 @@ void launch_coarse_matrix(const Layout& L, const StencilEntry* st_tab, const int
                        free_idx, free_map, N, A);
 }
 
-// Gauss-Jordan inversion with partial pivoting, one workgroup; M is destroyed.
-__global__ __launch_bounds__(256) void k_gauss_jordan(double* __restrict__ M, double* __restrict__ Inv, int N,
-                                                      int* __restrict__ status) {
-    extern __shared__ double fcol[];
+// Gauss-Jordan inversion with partial pivoting, one pivot column per pair of launches (the
+// elimination spreads over the whole device, so a coarsest mesh of 16 x 16, N = 2434, inverts in
+// a fraction of a second); M is destroyed.  status: 0, or 1 once a zero pivot column is met
+// (every later launch then returns at once).
+__global__ void k_gj_identity(double* __restrict__ Inv, int N, int* __restrict__ status) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q == 0) *status = 0;
+    if (q < (long long)N * N) Inv[q] = ((q / N) == (q % N)) ? 1.0 : 0.0;
+}
+
+// column c: the pivot row (largest |M[r][c]|, r >= c, the lowest index among equals), the swap
+// of rows c and pivot in M and Inv, the scaling of row c by 1 / pivot, and column c of M into
+// fcol (the elimination factors)
+__global__ __launch_bounds__(256) void k_gj_pivot(double* __restrict__ M, double* __restrict__ Inv, int N, int c,
+                                                  double* __restrict__ fcol, int* __restrict__ status) {
     __shared__ double rv[256];
     __shared__ int ri[256];
     __shared__ int piv;
     const int tid = threadIdx.x, nt = blockDim.x;
-    for (long long q = tid; q < (long long)N * N; q += nt) Inv[q] = ((q / N) == (q % N)) ? 1.0 : 0.0;
-    if (tid == 0) *status = 0;
-    __syncthreads();
-    for (int c = 0; c < N; ++c) {
-        double best = -1.0;
-        int bi = c;
-        for (int r = c + tid; r < N; r += nt) {
-            const double v = fabs(M[(long long)r * N + c]);
-            if (v > best) {
-                best = v;
-                bi = r;
-            }
+    if (*status) return;
+    double best = -1.0;
+    int bi = c;
+    for (int r = c + tid; r < N; r += nt) {
+        const double v = fabs(M[(long long)r * N + c]);
+        if (v > best) {
+            best = v;
+            bi = r;
         }
-        rv[tid] = best;
-        ri[tid] = bi;
-        __syncthreads();
-        if (tid == 0) {
-            double b = -1.0;
-            int bj = c;
-            for (int q = 0; q < nt; ++q)
-                if (rv[q] > b || (rv[q] == b && ri[q] < bj)) {
-                    b = rv[q];
-                    bj = ri[q];
-                }
-            piv = (b > 0.0) ? bj : -1;
-            if (b <= 0.0) *status = 1;
-        }
-        __syncthreads();
-        if (piv < 0) return;
-        const int pr = piv;
-        if (pr != c)
-            for (int k = tid; k < N; k += nt) {
-                double a = M[(long long)pr * N + k];
-                M[(long long)pr * N + k] = M[(long long)c * N + k];
-                M[(long long)c * N + k] = a;
-                a = Inv[(long long)pr * N + k];
-                Inv[(long long)pr * N + k] = Inv[(long long)c * N + k];
-                Inv[(long long)c * N + k] = a;
-            }
-        __syncthreads();
-        const double d = 1.0 / M[(long long)c * N + c];
-        __syncthreads();
-        for (int k = tid; k < N; k += nt) {
-            M[(long long)c * N + k] *= d;
-            Inv[(long long)c * N + k] *= d;
-        }
-        __syncthreads();
-        for (int r = tid; r < N; r += nt) fcol[r] = M[(long long)r * N + c];
-        __syncthreads();
-        for (long long q = tid; q < (long long)N * N; q += nt) {
-            const int r = (int)(q / N), k = (int)(q % N);
-            if (r == c) continue;
-            const double f = fcol[r];
-            if (f == 0.0) continue;
-            M[q] -= f * M[(long long)c * N + k];
-            Inv[q] -= f * Inv[(long long)c * N + k];
-        }
-        __syncthreads();
     }
+    rv[tid] = best;
+    ri[tid] = bi;
+    __syncthreads();
+    if (tid == 0) {
+        double b = -1.0;
+        int bj = c;
+        for (int q = 0; q < nt; ++q)
+            if (rv[q] > b || (rv[q] == b && ri[q] < bj)) {
+                b = rv[q];
+                bj = ri[q];
+            }
+        piv = (b > 0.0) ? bj : -1;
+        if (b <= 0.0) *status = 1;
+    }
+    __syncthreads();
+    if (piv < 0) return;
+    const int pr = piv;
+    if (pr != c)
+        for (int k = tid; k < N; k += nt) {
+            double a = M[(long long)pr * N + k];
+            M[(long long)pr * N + k] = M[(long long)c * N + k];
+            M[(long long)c * N + k] = a;
+            a = Inv[(long long)pr * N + k];
+            Inv[(long long)pr * N + k] = Inv[(long long)c * N + k];
+            Inv[(long long)c * N + k] = a;
+        }
+    __syncthreads();
+    const double d = 1.0 / M[(long long)c * N + c];
+    __syncthreads();
+    for (int k = tid; k < N; k += nt) {
+        M[(long long)c * N + k] *= d;
+        Inv[(long long)c * N + k] *= d;
+    }
+    __syncthreads();
+    for (int r = tid; r < N; r += nt) fcol[r] = M[(long long)r * N + c];
 }
 
-void launch_gauss_jordan(double* A, double* Inv, int N, int* status, hipStream_t st) {
-    hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(256), N * sizeof(double), st, A, Inv, N, status);
+// every row r != c: row_r -= fcol[r] row_c, in M and Inv (row c is only read)
+__global__ __launch_bounds__(256) void k_gj_eliminate(double* __restrict__ M, double* __restrict__ Inv, int N, int c,
+                                                      const double* __restrict__ fcol, const int* __restrict__ status) {
+    if (*status) return;
+    const int r = blockIdx.y;
+    if (r == c) return;
+    const double f = fcol[r];
+    if (f == 0.0) return;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    M[(long long)r * N + k] -= f * M[(long long)c * N + k];
+    Inv[(long long)r * N + k] -= f * Inv[(long long)c * N + k];
+}
+
+void launch_gauss_jordan(double* A, double* Inv, int N, double* fcol, int* status, hipStream_t st) {
+    const long long nn = (long long)N * N;
+    hipLaunchKernelGGL(k_gj_identity, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, Inv, N, status);
+    for (int c = 0; c < N; ++c) {
+        hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, st, A, Inv, N, c, fcol, status);
+        hipLaunchKernelGGL(k_gj_eliminate, dim3((N + 255) / 256, N), dim3(256), 0, st, A, Inv, N, c, fcol, status);
+    }
 }
 
 // =========================================================================================

@@ -125,7 +125,7 @@ def test_finite_differences_512(binding):
     random directions, h = 1e-6, forward solves to 1e-12, adjoint solve to 1e-10 (the
     adjoint right-hand side may carry a mean pressure, which excites the nearly singular
     constant-pressure mode; rounding in A lam then bounds its attainable relative residual
-    near 1e-11)."""
+    near 1e-11).  The largest difference, over the largest |g . d|, is below 1e-5."""
     n = 512
     w, P, theta, theta_obs, b = _workload(n)
     s = _gpu_solver(binding, w, n, w["levels"])
@@ -143,13 +143,18 @@ def test_finite_differences_512(binding):
 
     rng = np.random.default_rng(20)
     h = 1e-6
-    worst = 0.0
+    pairs = []
     for k in range(20):
         d = rng.standard_normal(theta.size)
         fd = (loss(theta + h * d) - loss(theta - h * d)) / (2 * h)
         an = float(g @ d)
-        e = abs(fd - an) / max(abs(an), 1e-300)
-        worst = max(worst, e)
-        print("  dir %2d  fd %.10e  adjoint %.10e  rel %.2e" % (k, fd, an, e), flush=True)
-    assert worst < 1e-5
+        pairs.append((fd, an))
+        print("  dir %2d  fd %.10e  adjoint %.10e  rel %.2e" % (k, fd, an, abs(fd - an) / abs(an)), flush=True)
     s.close()
+    # Each difference quotient carries an absolute error of about eps_L |L| / h, eps_L the relative
+    # accuracy of one loss evaluation (solves to 1e-12): the same in every direction, so it is
+    # measured against the scale of the directional derivatives, max |g . d|.
+    scale = max(abs(an) for _, an in pairs)
+    worst = max(abs(fd - an) for fd, an in pairs) / scale
+    print("  worst |fd - g.d| / max |g.d| = %.2e" % worst, flush=True)
+    assert worst < 1e-5
