@@ -29,7 +29,7 @@ BLOCK_RESTART = 100          # FGMRES restart of the block-contrast workload
 # the cycle of the block-contrast workload: the fastest to 1e-8 among the V-, W- and partial
 # W-cycles with additive and multiplicative Vanka and 8 to 10 levels measured on it (the
 # V(2,2) cycle with the LFA weight on 10 levels takes 178 iterations, 3.6 s per solve)
-BLOCK_CYCLE = dict(nu12=1, omega=1.0, colors=4, gamma=2, gamma_from=1, levels=8)
+BLOCK_CYCLE = dict(nu12=1, omega=1.0, colors=3, gamma=2, gamma_from=1, levels=8, fcycle=0)
 CSRC = os.path.join(ROOT, "paper_2107_04060_amd", "csrc")
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_vanka_step_sweep256_fp64.md")
 BLOCK_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_vanka_step_block2048_fp64.md")
@@ -87,10 +87,12 @@ def parse():
                     help="block2048: pre- and post-smoothing steps")
     ap.add_argument("--omega", type=float, default=BLOCK_CYCLE["omega"], help="block2048: relaxation weight")
     ap.add_argument("--colors", type=int, default=BLOCK_CYCLE["colors"],
-                    help="block2048: 0 additive Vanka, 4 multiplicative (four colours)")
+                    help="block2048: 0 additive Vanka, 3 or 4 multiplicative (three or four colours)")
     ap.add_argument("--gamma", type=int, default=BLOCK_CYCLE["gamma"], help="block2048: cycle index")
     ap.add_argument("--gamma-from", type=int, default=BLOCK_CYCLE["gamma_from"],
                     help="block2048: levels from this one down repeat their coarse correction gamma times")
+    ap.add_argument("--fcycle", type=int, default=BLOCK_CYCLE["fcycle"], choices=[0, 1],
+                    help="block2048: 1 = the repeated coarse corrections are V-cycles (F-cycle), 0 = W-cycle")
     ap.add_argument("--restart", type=int, default=BLOCK_RESTART, help="block2048: FGMRES restart")
     ap.add_argument("--levels", type=int, default=BLOCK_CYCLE["levels"],
                     help="block2048: mesh levels (8: direct solve on the 16 x 16 mesh)")
@@ -367,7 +369,8 @@ def cpu_baseline_block(n_gpu, iters_gpu, cyc, n_sample=256):
         p = BiotParams(c["lam"], c["mu"], alpha=w["alpha"], M=w["M"], mu_f=w["mu_f"], tau=w["tau"])
         lv = int(np.log2(n_sample // cyc.get("n_coarse", 4))) + 1
         H = Hierarchy(n_sample, p, K_tri=K, smoother="vanka", omega=cyc["omega"], nu1=cyc["nu1"], nu2=cyc["nu2"],
-                      levels=lv, gamma=cyc["gamma"], gamma_from=cyc["gamma_from"], vanka_colors=cyc["vanka_colors"])
+                      levels=lv, gamma=cyc["gamma"], gamma_from=cyc["gamma_from"], vanka_colors=cyc["vanka_colors"],
+                      fcycle=cyc["fcycle"])
         b = inputs.rhs_uniform(n_sample, w["seed"])
         fgmres(H.A, b, H.vcycle, tol=1e-30, restart=30, maxit=1)
         t0 = time.perf_counter()
@@ -395,7 +398,7 @@ def main_block2048(args, binding, inputs, torch):
     K = torch.tensor(inputs.permeability_triangles("block2048"), dtype=torch.float64, device="cuda")
     om, omj = args.omega, 1.0
     cyc = dict(nu1=args.nu12, nu2=args.nu12, omega=om, omega_J=omj, gamma=args.gamma, gamma_from=args.gamma_from,
-               vanka_colors=args.colors)
+               vanka_colors=args.colors, fcycle=bool(args.fcycle))
     restart = args.restart
     # right-hand sides k = 0 .. nrhs-1 of the seed stream (row k of rhs_uniform(n, seed, nrhs)),
     # uploaded before anything is timed; warm-up steps take the first ones, timed steps the next
@@ -514,9 +517,11 @@ def main_block2048(args, binding, inputs, torch):
         "config": {"workload": "block2048", "n": n, "levels": levels, "free_dofs": nf,
                    "physics": "K 1 or 1e-6 per 64x64-cell block (seed 3), nu 0.4999, E 1, tau 1, M E/0.03",
                    "cycle": "%s Vanka, %d pre- and post-smoothing steps, omega %.2f, cycle index %d on levels >= %d "
-                            "(finer levels: one coarse correction), %d levels (direct solve at %d x %d)" % (
-                                "multiplicative (4 colours)" if args.colors else "additive", args.nu12, om,
-                                args.gamma, args.gamma_from, levels, n >> (levels - 1), n >> (levels - 1)),
+                            "(finer levels: one coarse correction; %s), %d levels (direct solve at %d x %d)" % (
+                                "multiplicative (%d colours)" % args.colors if args.colors else "additive", args.nu12, om,
+                                args.gamma, args.gamma_from,
+                                "the repeated corrections are V-cycles: F-cycle" if args.fcycle else "W-cycle",
+                                levels, n >> (levels - 1), n >> (levels - 1)),
                    "restart": restart, "tol": args.tol,
                    "step": "one right-hand-side solve from x = 0, hierarchy reused", "rhs_order": order,
                    "forms": forms, "all_converged": all(res[f].get("all_converged", False) for f in forms)},

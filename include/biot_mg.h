@@ -118,7 +118,9 @@ typedef struct {
     int vanka_colors;   /* Vanka: 0 = additive (Sec. 3.2.1, weights D_l); 4 = multiplicative in
                            four colours (i mod 2) + 2 (j mod 2) of the patch vertex, each colour
                            on the residual the previous one left, unweighted (a colour's patches
-                           share no DoF); four launches per smoothing step                    */
+                           share no DoF); four launches per smoothing step; 3 = the same in
+                           three colours (i + 2 j) mod 3, the fewest this triangulation allows
+                           (patches share DoFs only across mesh edges): three launches     */
     int schur_cg;       /* BSR: 0 = as schur_sweeps says; k in 1..64 = the pressure correction
                            from k steps of conjugate gradients on the approximate Schur complement
                            S_hat = c_u M_p + tau B_w D_w^{-1} B_w^T (symmetric positive definite),
@@ -130,6 +132,11 @@ typedef struct {
                            coarse correction gamma times, finer levels take one; 0 = every level
                            (the W-cycle).  A W-cycle below a V-cycle: the coarse levels, cheap in
                            bytes, are revisited, the fine ones are not.                        */
+    int fcycle;         /* with gamma >= 2: 0 = every further coarse correction is a cycle of
+                           the same kind (W-cycle); 1 = the further ones are V-cycles, the
+                           first one of the same kind (the F-cycle: below the first repeating
+                           level, level m is visited m + 1 times rather than 2^m).  Neither is
+                           the paper's V-cycle: both are standard multigrid cycle shapes.      */
 } biot_mg_opts;
 
 /* FGMRES controls (in) and results (out). */

@@ -33,13 +33,14 @@ class Hierarchy:
 
     def __init__(self, n, params, K_tri=1.0, smoother="vanka", omega=1.0, omega_J=1.0,
                  nu1=1, nu2=1, n_coarse=4, levels=None, schur_sweeps=1, omega_S=1.0, gamma=1,
-                 vanka_colors=0, schur_cg=0, gamma_from=0):
+                 vanka_colors=0, schur_cg=0, gamma_from=0, fcycle=False):
         if levels is not None:
             n_coarse = n >> (levels - 1)
         self.params = params
         self.nu1, self.nu2 = int(nu1), int(nu2)
         self.gamma = int(gamma)                 # coarse corrections per level: 1 V-cycle, 2 W-cycle
         self.gamma_from = int(gamma_from)       # levels finer than this take one coarse correction
+        self.fcycle = bool(fcycle)              # further coarse corrections are V-cycles (F-cycle)
         if self.gamma < 1:
             raise ValueError("gamma >= 1")
         self.levels = []
@@ -56,9 +57,9 @@ class Hierarchy:
             _, self.levels[l].P = prolongation(self.levels[l].mesh, self.levels[l + 1].mesh)
         for lev in self.levels[:-1]:
             if smoother == "vanka" and vanka_colors:
-                if vanka_colors != MulticolorVanka.NCOLORS:
-                    raise ValueError("vanka_colors: 0 (additive) or 4")
-                lev.smoother = MulticolorVanka(lev.A, lev.mesh, omega)
+                if vanka_colors not in (3, 4):
+                    raise ValueError("vanka_colors: 0 (additive), 3 or 4")
+                lev.smoother = MulticolorVanka(lev.A, lev.mesh, omega, vanka_colors)
             elif smoother == "vanka":
                 _, slots = patch_table(lev.mesh, "full")
                 lev.smoother = AdditiveVanka(lev.A, slots, omega)
@@ -72,11 +73,15 @@ class Hierarchy:
     def A(self):
         return self.levels[0].A
 
-    def vcycle(self, b, level=0):
+    def vcycle(self, b, level=0, vonly=False):
         """One V(nu1, nu2) cycle for A_level x = b from x = 0; with gamma > 1 the coarse
         correction is gamma cycles of the next level (a W-cycle for gamma = 2), each further one
         on the residual left by the previous ones, except at the coarsest level, whose direct
-        solve is exact, and on levels finer than gamma_from, which take one."""
+        solve is exact, and on levels finer than gamma_from, which take one.
+
+        fcycle: the first coarse cycle is of the same kind, the further ones are V-cycles (for
+        gamma = 2 the F-cycle, which visits level m below the first repeating level m + 1
+        times rather than 2^m).  vonly: this cycle and every one below it is a V-cycle."""
         lev = self.levels[level]
         if level == len(self.levels) - 1:
             return sla.lu_solve(self.coarse_lu, b)
@@ -85,10 +90,10 @@ class Hierarchy:
             x = lev.smoother.smooth(x, b)
         r = b - lev.A @ x
         bc = lev.P.T @ r
-        xc = self.vcycle(bc, level + 1)
-        if level + 1 < len(self.levels) - 1 and level >= self.gamma_from:
+        xc = self.vcycle(bc, level + 1, vonly)
+        if not vonly and level + 1 < len(self.levels) - 1 and level >= self.gamma_from:
             for _ in range(self.gamma - 1):
-                xc = xc + self.vcycle(bc - self.levels[level + 1].A @ xc, level + 1)
+                xc = xc + self.vcycle(bc - self.levels[level + 1].A @ xc, level + 1, self.fcycle)
         x = x + lev.P @ xc
         for _ in range(self.nu2):
             x = lev.smoother.smooth(x, b)

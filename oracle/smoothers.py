@@ -108,22 +108,30 @@ class AdditiveVanka:
 
 
 class MulticolorVanka:
-    """Multiplicative Vanka in four colours (Sec. 3.2.1 describes additive and multiplicative
-    forms): the patch of vertex (i, j) has colour (i mod 2) + 2 (j mod 2); adjacent vertices differ
-    in a parity, so the patches of one colour share no DoF.  One step runs the colours in turn:
-    r = b - A x, then x <- x + omega sum over the colour's patches of V_l^T (V_l A V_l^T)^{-1} V_l r
-    (no weights: each DoF lies in at most one patch of a colour)."""
+    """Multiplicative Vanka in colours (Sec. 3.2.1 describes additive and multiplicative forms).
+    Two vertex patches share a DoF only when their vertices are joined by a mesh edge (the patch
+    of a vertex holds the DoFs of its incident edges and star triangles), so any colouring of
+    the vertex graph makes the patches of one colour disjoint.  Four colours: (i mod 2) +
+    2 (j mod 2) (edge neighbours differ in a parity).  Three colours: (i + 2 j) mod 3, the
+    smallest count for this triangulation (its H, V and D edge neighbours (i +- 1, j),
+    (i, j +- 1), (i +- 1, j -+ 1) shift i + 2 j by +-1, +-2, -+1).  One step runs the colours in
+    turn: r = b - A x, then x <- x + omega sum over the colour's patches of
+    V_l^T (V_l A V_l^T)^{-1} V_l r (no weights: each DoF lies in at most one patch of a colour)."""
 
-    NCOLORS = 4
-
-    def __init__(self, A, mesh, omega=1.0):
+    def __init__(self, A, mesh, omega=1.0, ncolors=4):
         self.A = A.tocsr()
         self.omega = float(omega)
+        if ncolors not in (3, 4):
+            raise ValueError("ncolors: 3 or 4")
+        self.ncolors = int(ncolors)
         verts, slots = patch_table(mesh, "full")
         ij = mesh.vert_ij[verts]
-        col = (ij[:, 0] % 2) + 2 * (ij[:, 1] % 2)
+        if self.ncolors == 4:
+            col = (ij[:, 0] % 2) + 2 * (ij[:, 1] % 2)
+        else:
+            col = (ij[:, 0] + 2 * ij[:, 1]) % 3
         self.colors = []
-        for c in range(self.NCOLORS):
+        for c in range(self.ncolors):
             sets = [np.array(sorted(slots[k][slots[k] >= 0])) for k in np.nonzero(col == c)[0]]
             groups = []
             for sz in sorted(set(len(t) for t in sets)):
@@ -141,7 +149,7 @@ class MulticolorVanka:
         return out
 
     def smooth(self, x, b):
-        for c in range(self.NCOLORS):
+        for c in range(self.ncolors):
             x = x + self.omega * self.color_correction(c, b - self.A @ x)
         return x
 

@@ -444,8 +444,11 @@ static SchurSweeps<T> schur_sweeps(biot_ctx* c, Level& lv) {
 // Multiplicative Vanka: the colours of a step are separate launches, each reading the iterate
 // the previous one wrote.
 static int vanka_colors(const biot_mg_opts& o) {
-    return o.smoother == BIOT_SMOOTHER_VANKA && o.vanka_colors == 4 ? 4 : 1;
+    return o.smoother == BIOT_SMOOTHER_VANKA && (o.vanka_colors == 3 || o.vanka_colors == 4) ? o.vanka_colors : 1;
 }
+
+// the kernel's colour code of colour col of nc (-1: the additive step)
+static int color_code(int nc, int col) { return nc == 4 ? col : (nc == 3 ? 4 + col : -1); }
 
 // One relaxation step on level l from the iterate x (nullptr: zero).  Vanka writes the new
 // iterate to dst (dst != x); its multiplicative form alternates between dst and alt (the other
@@ -464,7 +467,7 @@ static T* relax(biot_ctx* c, int l, const T* x, const T* b, T* dst, T* alt, hipS
         for (int col = 0; col < nc; ++col) {
             const LaunchTiming tm = src ? prof_events(c, 0, l) : LaunchTiming{};
             launch_vanka_step<T>(v, src, b, out, c->K_uniform, (T)(1.0 / c->K_scalar), om, st, nullptr, nullptr,
-                                 nullptr, &tm, nc > 1 ? col : -1);
+                                 nullptr, &tm, color_code(nc, col));
             src = out;
             out = out == dst ? alt : dst;
         }
@@ -495,10 +498,12 @@ struct PW<float> {
     static const float* get(biot_ctx* c) { return c->pw32.as<float>(); }
 };
 
-// V(nu1, nu2) cycle on level l for A_l x = b from x = 0, iterate buffers buf0 / buf1 (both zero
-// on absent DoFs).  Returns the buffer that holds the result.
+// V(nu1, nu2) cycle on level l for A_l x = b from x = 0 (or from x0), iterate buffers buf0 / buf1
+// (both zero on absent DoFs).  Returns the buffer that holds the result.  vonly: no level below
+// repeats its coarse correction (the V-cycles of an F-cycle).
 template <typename T>
-static T* vcycle_level(biot_ctx* c, int l, const T* b, T* buf0, T* buf1, hipStream_t st, T* x0 = nullptr) {
+static T* vcycle_level(biot_ctx* c, int l, const T* b, T* buf0, T* buf1, hipStream_t st, T* x0 = nullptr,
+                       bool vonly = false) {
     Level& lv = *c->levels[l];
     if (l == (int)c->levels.size() - 1) {
         launch_coarse_solve<T>(c->coarse_inv.as<double>(), c->coarse_N, c->coarse_idx.as<int>(), b, buf0, st);
@@ -522,13 +527,15 @@ static T* vcycle_level(biot_ctx* c, int l, const T* b, T* buf0, T* buf1, hipStre
     const LaunchTiming tm = prof_events(c, 1, l);
     launch_residual_restrict<T>(lv.view<T>(), lc.L, cur, b, bc, c->K_uniform, (T)(1.0 / c->K_scalar),
                                 PW<T>::get(c), st, &tm);
-    T* xc = vcycle_level<T>(c, l + 1, bc, XBuf<T>::get(lc, 0), XBuf<T>::get(lc, 1), st);
-    if (c->opts.gamma > 1 && l >= c->opts.gamma_from && l + 2 < (int)c->levels.size()) {
+    T* xc = vcycle_level<T>(c, l + 1, bc, XBuf<T>::get(lc, 0), XBuf<T>::get(lc, 1), st, nullptr, vonly);
+    if (!vonly && c->opts.gamma > 1 && l >= c->opts.gamma_from && l + 2 < (int)c->levels.size()) {
         // W-cycle: gamma - 1 further cycles of level l + 1, each continuing from the iterate the
         // previous one left (with linear smoothing the same as a cycle from zero on the residual
-        // it left, added to it); the coarsest level's direct solve is exact and not repeated
+        // it left, added to it); the coarsest level's direct solve is exact and not repeated.
+        // F-cycle: the further cycles are V-cycles.
         for (int g = 1; g < c->opts.gamma; ++g)
-            xc = vcycle_level<T>(c, l + 1, bc, XBuf<T>::get(lc, 0), XBuf<T>::get(lc, 1), st, xc);
+            xc = vcycle_level<T>(c, l + 1, bc, XBuf<T>::get(lc, 0), XBuf<T>::get(lc, 1), st, xc,
+                                 c->opts.fcycle != 0);
     }
     int s0 = 0;
     if (c->opts.nu2 > 0) {
@@ -540,7 +547,7 @@ static T* vcycle_level(biot_ctx* c, int l, const T* b, T* buf0, T* buf1, hipStre
             for (int col = 0; col < nc; ++col) {
                 T* dst = next();
                 launch_vanka_step<T>(lv.view<T>(), cur, b, dst, c->K_uniform, kinv_s, (T)c->opts.omega, st,
-                                     col == 0 ? xc : nullptr, &lc.L, PW<T>::get(c), nullptr, nc > 1 ? col : -1);
+                                     col == 0 ? xc : nullptr, &lc.L, PW<T>::get(c), nullptr, color_code(nc, col));
                 cur = dst;
             }
         } else {
@@ -1031,7 +1038,9 @@ int biot_setup_hierarchy(biot_ctx* c, const biot_mg_opts* o, void* stream) {
         require(o->schur_sweeps >= 0 && o->schur_sweeps <= 64, "schur_sweeps in [0, 64]");
         require(o->gamma >= 0 && o->gamma <= 4, "gamma (cycle index) in [0, 4]");
         require(o->gamma_from >= 0 && o->gamma_from < o->levels, "gamma_from in [0, levels)");
-        require(o->vanka_colors == 0 || o->vanka_colors == 4, "vanka_colors: 0 (additive) or 4");
+        require(o->fcycle == 0 || o->fcycle == 1, "fcycle: 0 (W-cycle) or 1 (F-cycle)");
+        require(o->vanka_colors == 0 || o->vanka_colors == 3 || o->vanka_colors == 4,
+                "vanka_colors: 0 (additive), 3 or 4");
         require(o->schur_sweeps <= 1 || (std::isfinite(o->omega_S) && o->omega_S > 0 && o->omega_S <= 1),
                 "Schur sweeps need omega_S in (0, 1]");
         require(o->schur_cg >= 0 && o->schur_cg <= 64, "schur_cg in [0, 64]");

@@ -61,8 +61,9 @@ struct LaunchTiming {
 // vertex class (lv.minv, full inverses), 1/K = kinv_s; else per-patch elimination with lv.kinv.
 // xc != nullptr: the iterate is x_in + P x_c (coarse level layout *Lc, prolongation weights
 // pw), i.e. the prolongation of the coarse-grid correction is fused into the step.
-// color in 0..3: one colour step of the multiplicative form (only the patches of vertices of that
-// colour, unweighted); -1: the additive step.
+// color >= 0: one colour step of the multiplicative form (only the patches of vertices of that
+// colour, unweighted): codes 0..3 the four colours (i mod 2) + 2 (j mod 2), codes 4..6 the three
+// colours 4 + (i + 2 j) mod 3; -1: the additive step.
 template <typename T>
 void launch_vanka_step(const LevelView<T>& lv, const T* x_in, const T* b, T* x_out, bool uniform, T kinv_s,
                        T omega, hipStream_t st, const T* xc = nullptr, const Layout* Lc = nullptr,

@@ -25,9 +25,14 @@ __device__ inline double vanka_weight(int t, int i, int j, int n) {
     return (i == n - 1 && j == n - 1) ? 0.5 : 1.0 / 3.0;
 }
 
-// colour of the patch of vertex (i, j) in the multiplicative form: adjacent vertices differ in a
-// parity, so the patches of one colour share no DoF
-__host__ __device__ constexpr int vertex_color(int i, int j) { return (i & 1) + 2 * (j & 1); }
+// Whether the patch of vertex (i, j) belongs to colour code `color` of the multiplicative form.
+// Two patches share a DoF only when their vertices are joined by a mesh edge, so a colouring of
+// the vertex graph makes the patches of a colour disjoint.  Codes 0..3: four colours
+// (i mod 2) + 2 (j mod 2); codes 4..6: three colours 4 + (i + 2 j) mod 3 (the edge neighbours
+// (i +- 1, j), (i, j +- 1), (i +- 1, j -+ 1) shift i + 2 j by +-1, +-2, -+1).
+__host__ __device__ constexpr bool in_color(int i, int j, int color) {
+    return color < 4 ? (i & 1) + 2 * (j & 1) == color : (i + 2 * j) % 3 == color - 4;
+}
 
 // LDS offset of patch slot s relative to the residual entry of its vertex (rs[0][vj+1][vi+1])
 __host__ __device__ constexpr int pslot_off(int s) {
@@ -313,7 +318,7 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
             // rows a = kq + 4 v + 16 mb of the lane's patch; a colour step keeps its colour's
             // patches only
             if (own) {
-                const bool keep = color < 0 || vertex_color(i0 + pti, j0 + ptj) == color;
+                const bool keep = color < 0 || in_color(i0 + pti, j0 + ptj, color);
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     sh.u.so[kq + 4 * v][ptj][pti] = keep ? (T)acc0[v] : (T)0;
@@ -333,7 +338,7 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
 #pragma unroll
         for (int s = 0; s < PATCH; ++s) out[s] = 0;
         const bool inner = cilo == 1 && cihi == 1 && cjlo == 1 && cjhi == 1;
-        const bool act = patch && vi <= n && vj <= n && (color < 0 || vertex_color(vi, vj) == color);
+        const bool act = patch && vi <= n && vj <= n && (color < 0 || in_color(vi, vj, color));
         P rr[PATCH], kv[6];
         if (act) {
 #pragma unroll
@@ -494,7 +499,7 @@ template <typename T>
 void launch_vanka_step(const LevelView<T>& lv, const T* x_in, const T* b, T* x_out, bool uniform, T kinv_s,
                        T omega, hipStream_t st, const T* xc, const Layout* Lc, const T* pw, const LaunchTiming* tm,
                        int color) {
-    if (color < -1 || color > 3) throw ArgError{"Vanka colour: -1 (additive) or 0..3"};
+    if (color < -1 || color > 6) throw ArgError{"Vanka colour code: -1 (additive), 0..3 or 4..6"};
     const Layout lc = Lc ? *Lc : lv.L;
     if (xc && !x_in) throw ArgError{"the prolongation needs an iterate"};
     if (uniform) {

@@ -1,12 +1,16 @@
-"""Multiplicative (four-colour) Vanka on the GPU (vanka_colors = 4) against the oracle's
-MulticolorVanka.
+"""Multiplicative Vanka on the GPU (vanka_colors = 4: four colours, 3: three colours) against
+the oracle's MulticolorVanka.
 
 * One V(1,1) and one V(2,2) cycle match the oracle element by element, to 4 eps kappa over the
   patch and coarsest condition numbers (the V-cycle parity tolerance), for constant K (class
-  inverses on the matrix cores) and heterogeneous K (per-patch elimination).
-* The standalone smoothing entry point runs one four-colour step.
+  inverses on the matrix cores) and heterogeneous K (per-patch elimination), in four and in
+  three colours.
+* The standalone smoothing entry point runs one multiplicative step (four and three colours).
 * On the paper's steady problem (nu = 0.499, k = 1e-6) FGMRES with the multiplicative V(1,1)
   cycle takes the oracle's iteration count (+-1), fewer than the additive V(2,2) cycle.
+* The cycle shape of the 2048 x 2048 block-contrast workload (multiplicative V(1,1), omega 1,
+  cycle index 2 below the finest level, as W- and as F-cycle, in four and three colours) on the same physics and
+  permeability pattern at n = 64 over five levels: one cycle to the V-cycle parity tolerance.
 """
 import numpy as np
 import pytest
@@ -22,7 +26,7 @@ from oracle.krylov import fgmres  # noqa: E402
 from oracle.mesh import Mesh  # noqa: E402
 from oracle.multigrid import Hierarchy  # noqa: E402
 from oracle.smoothers import MulticolorVanka  # noqa: E402
-from gpu_cases import case, params, perm, rel, tol_from_conds  # noqa: E402
+from gpu_cases import block_perm, case, params, perm, rel, tol_from_conds  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -38,22 +42,24 @@ def _t(a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
 
 
-def _solver(binding, n, name, K, levels, nu, omega):
+def _solver(binding, n, name, K, levels, nu, omega, ncolors=4):
     lam, mu, al, M, mf_, tau = case(name)
     s = binding.BiotSolver(n, lam, mu, alpha=al, M=M, mu_f=mf_, tau=tau,
                            K=K if np.isscalar(K) else torch.tensor(K, dtype=torch.float64, device="cuda"))
-    s.setup(levels=levels, smoother="vanka", nu1=nu, nu2=nu, omega=omega, vanka_colors=4)
+    s.setup(levels=levels, smoother="vanka", nu1=nu, nu2=nu, omega=omega, vanka_colors=ncolors)
     return s
 
 
-@pytest.mark.parametrize("kind,name,nu", [("const", "small", 1), ("hetero", "stiff", 2), ("hetero", "small", 1)])
-def test_multicolor_vcycle_parity(binding, kind, name, nu):
+@pytest.mark.parametrize("kind,name,nu,ncolors", [("const", "small", 1, 4), ("hetero", "stiff", 2, 4),
+                                                  ("hetero", "small", 1, 4), ("const", "small", 1, 3),
+                                                  ("hetero", "stiff", 2, 3)])
+def test_multicolor_vcycle_parity(binding, kind, name, nu, ncolors):
     n, levels = 32, 4
-    print("multicolour vanka V(%d,%d) n=%d K=%s %s" % (nu, nu, n, kind, name), flush=True)
+    print("multicolour (%d) vanka V(%d,%d) n=%d K=%s %s" % (ncolors, nu, nu, n, kind, name), flush=True)
     K = perm(n, kind)
-    s = _solver(binding, n, name, K, levels, nu, 0.9)
+    s = _solver(binding, n, name, K, levels, nu, 0.9, ncolors)
     H = Hierarchy(n, params(name), K_tri=K, smoother="vanka", omega=0.9, nu1=nu, nu2=nu, levels=levels,
-                  vanka_colors=4)
+                  vanka_colors=ncolors)
     r = inputs.rhs_uniform(n, 7)
     z = s.vcycle(_t(r)).cpu().numpy()
     s.close()
@@ -65,12 +71,13 @@ def test_multicolor_vcycle_parity(binding, kind, name, nu):
     assert err < tol
 
 
-def test_multicolor_smooth_entry_point(binding):
+@pytest.mark.parametrize("ncolors", [4, 3])
+def test_multicolor_smooth_entry_point(binding, ncolors):
     n = 16
     K = perm(n, "hetero")
-    s = _solver(binding, n, "small", K, 2, 1, 0.8)
+    s = _solver(binding, n, "small", K, 2, 1, 0.8, ncolors)
     asm = Assembly(Mesh(n), params("small"), K)
-    sm = MulticolorVanka(asm.A, asm.mesh, 0.8)
+    sm = MulticolorVanka(asm.A, asm.mesh, 0.8, ncolors)
     rng = np.random.default_rng(9)
     x0, b = rng.standard_normal(asm.A.shape[0]), rng.standard_normal(asm.A.shape[0])
     x = s.smooth(_t(x0), _t(b), level=0).cpu().numpy()
@@ -94,3 +101,25 @@ def test_multicolor_solve_matches_oracle(binding):
     print("  multiplicative V(1,1): gpu %d iterations, oracle %d" % (info["iters"], io["iters"]), flush=True)
     assert io["converged"] and info["converged"]
     assert abs(info["iters"] - io["iters"]) <= 1
+
+
+@pytest.mark.parametrize("fcycle,ncolors", [(False, 4), (True, 4), (False, 3)])
+def test_block_workload_cycle_parity(binding, fcycle, ncolors):
+    n, levels = 64, 5
+    print("block-contrast cycle n=%d %s-cycle, %d colours" % (n, "F" if fcycle else "W", ncolors), flush=True)
+    K = block_perm(n)
+    lam, mu, al, M, mf_, tau = case("block")
+    s = binding.BiotSolver(n, lam, mu, alpha=al, M=M, mu_f=mf_, tau=tau,
+                           K=torch.tensor(K, dtype=torch.float64, device="cuda"))
+    cyc = dict(nu1=1, nu2=1, omega=1.0, vanka_colors=ncolors, gamma=2, gamma_from=1, fcycle=fcycle)
+    s.setup(levels=levels, smoother="vanka", **cyc)
+    H = Hierarchy(n, params("block"), K_tri=K, smoother="vanka", levels=levels, **cyc)
+    r = inputs.rhs_uniform(n, 8)
+    z = s.vcycle(_t(r)).cpu().numpy()
+    s.close()
+    conds = [np.linalg.cond(Al).max() for lev in H.levels[:-1] for g in lev.smoother.colors for _, Al in g]
+    conds.append(np.linalg.cond(H.levels[-1].A.toarray()))
+    tol, kap = tol_from_conds(conds)
+    err = rel(z, H.vcycle(r))
+    print("  rel diff %.2e  tol %.2e  (kappa %.2e)" % (err, tol, kap), flush=True)
+    assert err < tol

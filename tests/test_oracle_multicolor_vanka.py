@@ -1,6 +1,10 @@
-"""Pins of the four-colour multiplicative Vanka smoother (oracle/smoothers.py, MulticolorVanka).
+"""Pins of the multiplicative Vanka smoother (oracle/smoothers.py, MulticolorVanka), in four
+colours (i mod 2) + 2 (j mod 2) and in three colours (i + 2 j) mod 3.
 
-* The patches of one colour share no DoF, and the four colours together cover every free DoF.
+* The patches of one colour share no DoF, and the colours together cover every free DoF.
+* Patches share DoFs exactly when their vertices are joined by a mesh edge: the checkerboard
+  (i + j) mod 2 puts the two ends of every D edge in one colour and fails, so three colours are
+  the fewest.
 * One colour's correction equals a sparse direct solve (SuperLU) of A restricted to the union
   of that colour's patches with the couplings between different patches removed.
 * One step is the four colour updates in turn, each on the residual left by the previous one.
@@ -20,15 +24,22 @@ from oracle.smoothers import MulticolorVanka
 from paper_2107_04060_amd import inputs
 
 
-def _setup(n=8):
+import pytest
+
+from oracle.smoothers import patch_table
+
+
+def _setup(n=8, ncolors=4):
     P = BiotParams.from_E_nu(1.0, 0.3, alpha=1.0, M=50.0, mu_f=1.0, tau=0.5)
     K = np.exp(np.random.default_rng(5).uniform(-1, 1, 2 * n * n)) * 1e-2
     asm = Assembly(Mesh(n), P, K)
-    return asm, MulticolorVanka(asm.A, asm.mesh, 0.9)
+    return asm, MulticolorVanka(asm.A, asm.mesh, 0.9, ncolors)
 
 
-def test_colours_do_not_overlap_and_cover():
-    asm, sm = _setup()
+@pytest.mark.parametrize("ncolors", [3, 4])
+def test_colours_do_not_overlap_and_cover(ncolors):
+    asm, sm = _setup(ncolors=ncolors)
+    assert len(sm.colors) == ncolors
     cover = np.zeros(asm.A.shape[0], dtype=int)
     for groups in sm.colors:
         seen = np.concatenate([idx.ravel() for idx, _ in groups])
@@ -37,11 +48,31 @@ def test_colours_do_not_overlap_and_cover():
     assert np.all(cover >= 1)
 
 
-def test_colour_correction_is_a_block_solve():
-    asm, sm = _setup()
+def test_patches_share_dofs_exactly_across_mesh_edges():
+    mesh = Mesh(6)
+    verts, slots = patch_table(mesh, "full")
+    ij = mesh.vert_ij[verts]
+    sets = [set(slots[k][slots[k] >= 0].tolist()) for k in range(len(verts))]
+    edges = {tuple(sorted(e)) for e in mesh.edge_ends.tolist()}
+    for a in range(len(verts)):
+        for b in range(a + 1, len(verts)):
+            if not sets[a] or not sets[b]:
+                continue
+            joined = tuple(sorted((int(verts[a]), int(verts[b])))) in edges
+            assert bool(sets[a] & sets[b]) == joined, (ij[a], ij[b])
+    # the checkerboard: the ends (i, j + 1), (i + 1, j) of a D edge have one colour
+    d = mesh.edge_ends[mesh.edge_kind == 2][0]
+    (i1, j1), (i2, j2) = mesh.vert_ij[d[0]], mesh.vert_ij[d[1]]
+    assert (i1 + j1) % 2 == (i2 + j2) % 2
+    assert (i1 + 2 * j1) % 3 != (i2 + 2 * j2) % 3
+
+
+@pytest.mark.parametrize("ncolors", [3, 4])
+def test_colour_correction_is_a_block_solve(ncolors):
+    asm, sm = _setup(ncolors=ncolors)
     A = asm.A.tocsr()
     r = np.random.default_rng(6).standard_normal(A.shape[0])
-    for c in range(4):
+    for c in range(ncolors):
         pid = -np.ones(A.shape[0], dtype=int)
         k = 0
         for idx, _ in sm.colors[c]:
@@ -57,13 +88,14 @@ def test_colour_correction_is_a_block_solve():
         assert np.allclose(sm.color_correction(c, r), x, rtol=0, atol=1e-12 * np.abs(x).max())
 
 
-def test_step_is_the_colours_in_turn():
-    asm, sm = _setup()
+@pytest.mark.parametrize("ncolors", [3, 4])
+def test_step_is_the_colours_in_turn(ncolors):
+    asm, sm = _setup(ncolors=ncolors)
     A = asm.A.tocsr()
     rng = np.random.default_rng(7)
     x0, b = rng.standard_normal(A.shape[0]), rng.standard_normal(A.shape[0])
     x = x0.copy()
-    for c in range(4):
+    for c in range(ncolors):
         x = x + 0.9 * sm.color_correction(c, b - A @ x)
     assert np.allclose(sm.smooth(x0, b), x, rtol=1e-14, atol=0)
 

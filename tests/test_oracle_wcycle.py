@@ -8,6 +8,10 @@
   to gamma.
 * On the paper's steady problem the W-cycle makes BSR converge where the V-cycle stalls
   (nu = 0.45, k = 1e-8 and nu = 0.4, k = 1e-4, Table 4).
+* The F-cycle (fcycle: the further coarse corrections are V-cycles): on three levels it is the
+  W-cycle; on four its top level is the F-cycle of the three coarser levels followed by a
+  V-cycle of them, composed here by hand; counted smoother calls give m + 1 visits of level m
+  (W-cycle: 2^m); with gamma = 1 it is the V-cycle.
 """
 import os
 
@@ -93,3 +97,52 @@ def test_gamma_from_keeps_the_fine_levels_to_one_correction():
     assert np.linalg.norm(got - Hw.vcycle(b)) > 1e-6 * np.linalg.norm(x)
     v = Hierarchy(n, _P(), **kw).vcycle(b)
     assert np.array_equal(Hierarchy(n, _P(), gamma=2, gamma_from=2, **kw).vcycle(b), v)
+
+
+def _count_visits(H, b):
+    """Smoothing calls per level of one cycle, divided by nu1 + nu2 (visits)."""
+    counts = [0] * (len(H.levels) - 1)
+    for l, lev in enumerate(H.levels[:-1]):
+        f = lev.smoother.smooth
+
+        def wrapped(x, bb, _f=f, _l=l):
+            counts[_l] += 1
+            return _f(x, bb)
+        lev.smoother.smooth = wrapped
+    H.vcycle(b)
+    return [c // (H.nu1 + H.nu2) for c in counts]
+
+
+def test_fcycle_pins():
+    n = 32
+    b = inputs.rhs_uniform(n, 6)
+    kw = dict(K_tri=1e-2, smoother="vanka", omega=0.8, nu1=1, nu2=1)
+    # three levels: the F-cycle is the W-cycle
+    assert np.array_equal(Hierarchy(n, _P(), levels=3, gamma=2, fcycle=True, **kw).vcycle(b),
+                          Hierarchy(n, _P(), levels=3, gamma=2, **kw).vcycle(b))
+    # gamma = 1: the V-cycle
+    assert np.array_equal(Hierarchy(n, _P(), levels=4, gamma=1, fcycle=True, **kw).vcycle(b),
+                          Hierarchy(n, _P(), levels=4, **kw).vcycle(b))
+    # four levels, composed by hand from the level-1 cycles of the F and V hierarchies
+    Hf = Hierarchy(n, _P(), levels=4, gamma=2, fcycle=True, **kw)
+    Hv = Hierarchy(n, _P(), levels=4, **kw)
+    lev = Hf.levels[0]
+    x = lev.smoother.smooth(np.zeros_like(b), b)
+    bc = lev.P.T @ (b - lev.A @ x)
+    xc = Hf.vcycle(bc, level=1)
+    xc = xc + Hv.vcycle(bc - Hf.levels[1].A @ xc, level=1)
+    x = lev.smoother.smooth(x + lev.P @ xc, b)
+    got = Hf.vcycle(b)
+    assert np.linalg.norm(got - x) <= 1e-13 * np.linalg.norm(x)
+    Hw = Hierarchy(n, _P(), levels=4, gamma=2, **kw)
+    assert np.linalg.norm(got - Hw.vcycle(b)) > 1e-6 * np.linalg.norm(x)
+
+
+def test_fcycle_and_wcycle_visit_counts():
+    n = 64
+    b = inputs.rhs_uniform(n, 7)
+    kw = dict(K_tri=1e-2, smoother="vanka", omega=0.8, nu1=1, nu2=1, levels=5)
+    assert _count_visits(Hierarchy(n, _P(), gamma=2, fcycle=True, **kw), b) == [1, 2, 3, 4]
+    assert _count_visits(Hierarchy(n, _P(), gamma=2, **kw), b) == [1, 2, 4, 8]
+    assert _count_visits(Hierarchy(n, _P(), gamma=2, gamma_from=1, fcycle=True, **kw), b) == [1, 1, 2, 3]
+    assert _count_visits(Hierarchy(n, _P(), **kw), b) == [1, 1, 1, 1]
