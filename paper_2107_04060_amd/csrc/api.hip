@@ -301,10 +301,11 @@ static void levels_kinv(biot_ctx* c, const double* K_tri, hipStream_t st, int mo
 
 // Variable K: the factors of every vertex patch of the smoothing levels with at most FAC_MAX_N
 // cells per side, from the current 1/K (they depend on the permeability only; a relaxation step
-// applies them).  On these levels a launch covers few tiles and the length of one patch's
-// dependent chain sets its time; on larger ones the FP64 factor loads (624 B per patch, read
-// through partial cache lines in a colour step) cost more than forming the factors on the spot.
-constexpr int FAC_MAX_N = 256;
+// applies them).  Measured on the 2048 x 2048 block-contrast hierarchy: stored factors shorten
+// a colour step at 512^2 (52 us against 60 us) and lengthen it at 1024^2 and 2048^2 (208 against
+// 201 us, 829 against 768 us), where their loads (336 B per patch, read through partial cache
+// lines in a colour step) cost more than forming them on the spot.
+constexpr int FAC_MAX_N = 512;
 static void levels_factors(biot_ctx* c, hipStream_t st) {
     if (c->K_uniform) return;
     for (size_t l = 0; l + 1 < c->levels.size(); ++l) {

@@ -16,6 +16,14 @@
 
 namespace biot {
 
+// Keeps the class-data and residual reads of one phase of an FP64 patch solve from being hoisted
+// into an earlier phase, where they would all be live at once (an empty asm statement with a
+// memory clobber: no instruction).  The FP32 solve fits its registers without it.
+#define BIOT_PHASE_FENCE()                                        \
+    do {                                                          \
+        if constexpr (sizeof(T) == 8) __asm__ volatile("" ::: "memory"); \
+    } while (0)
+
 // packed lower triangle of a symmetric 6 x 6 matrix
 __host__ __device__ constexpr int tri6(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
 
@@ -87,15 +95,15 @@ __host__ __device__ inline void star_w_factor(const DevPatchClass<T>& pc, const 
 }
 
 // The residual-independent part of a patch solve, which depends on the permeability only:
-// w = L_W (Cholesky factor of the star's RT0 mass W, 1 / L_jj on the diagonal), z[q] = L_W^-1
-// (row q of Q)^T, and s = the Cholesky factor of S = C + G + Z^T Z with the rank-one shift on the
-// star-constant direction (see patch_apply).  78 values; stored per patch by k_patch_factors so
-// that a relaxation step only applies them.
-constexpr int PFAC = 21 + 36 + 21;
+// w = L_W (Cholesky factor of the star's RT0 mass W, 1 / L_jj on the diagonal) and s = the
+// Cholesky factor of S = C + G + Q W^-1 Q^T with the rank-one shift on the star-constant
+// direction (see patch_apply).  Both the factorization and the relaxation step apply
+// W^-1 = L_W^-T L_W^-1 and read Q from the class data, so that only w, s and one 6-vector are
+// live (42 values per patch, stored by k_patch_factors on the small levels).
+constexpr int PFAC = 21 + 21;
 template <typename T>
 struct PatchFac {
     T w[21];
-    T z[6][6];
     T s[21];
 };
 
@@ -105,24 +113,30 @@ template <typename T, bool ALLP = false>
 __host__ __device__ inline void patch_factor(const DevPatchClass<T>& pc, const T kv[6], const T* __restrict__ wblk,
                                              PatchFac<T>& f) {
     star_w_factor<T, ALLP>(pc, kv, wblk, f.w);
+    BIOT_PHASE_FENCE();
+    // S = C + G + Q W^-1 Q^T one column at a time (y = W^-1 (row q2 of Q)^T), so that only one
+    // 6-vector is live besides the two factors; then the shift beta (1 1^T on the present
+    // pressures), beta = tr(S) / k^2
 #pragma unroll
-    for (int q = 0; q < 6; ++q) {
+    for (int q2 = 0; q2 < 6; ++q2) {
+        T y[6];
 #pragma unroll
-        for (int a = 0; a < 6; ++a) f.z[q][a] = pc.Q[q][a];
-        fwd6p(f.w, f.z[q]);
+        for (int a = 0; a < 6; ++a) y[a] = pc.Q[q2][a];
+        fwd6p(f.w, y);
+        bwd6p(f.w, y);
+#pragma unroll
+        for (int q1 = q2; q1 < 6; ++q1) {
+            T v = pc.G[q1][q2];
+#pragma unroll
+            for (int a = 0; a < 6; ++a) v += pc.Q[q1][a] * y[a];
+            f.s[tri6(q1, q2)] = v;
+        }
+        BIOT_PHASE_FENCE();
     }
-    // S = C + G + Z^T Z, then the shift beta (1 1^T on the present pressures), beta = tr(S) / k^2
     int k = 0;
     T tr = 0;
 #pragma unroll
     for (int q1 = 0; q1 < 6; ++q1) {
-#pragma unroll
-        for (int q2 = 0; q2 <= q1; ++q2) {
-            T v = pc.G[q1][q2];
-#pragma unroll
-            for (int a = 0; a < 6; ++a) v += f.z[q1][a] * f.z[q2][a];
-            f.s[tri6(q1, q2)] = v;
-        }
         f.s[tri6(q1, q1)] += pc.c[q1];
         if (ALLP || pc.present[14 + q1]) {
             ++k;
@@ -143,27 +157,31 @@ __host__ __device__ inline void patch_factor(const DevPatchClass<T>& pc, const T
     chol6p(f.s);
 }
 
-// rr: patch residual (absent slots hold 0); f: the patch's factors (patch_factor); out[a *
-// ostride], a = 0..19.  with_mean = false omits the star-mean pressure term (the deflated solve).
-// ALLP: every slot of the patch is present (interior class), known at compile time.
-// With W = L L^T, Q W^-1 Q^T = Z^T Z for Z = L^-1 Q^T, Q W^-1 r_w = Z^T zr for zr = L^-1 r_w, and
-// x_w = L^-T (zr - Z x_p): one forward and one backward substitution with L, none with a division.
-template <typename T, bool ALLP = false>
-__host__ __device__ inline void patch_apply(const T rr[PATCH], const DevPatchClass<T>& pc, const PatchFac<T>& f,
-                                            T* out, int ostride, bool with_mean = true) {
-    T zr[6];
+// rr(s): the patch residual at slot s (absent slots hold 0), read where each phase needs it (an
+// array, or the staged residual in LDS, so that it need not stay in registers); f: the patch's
+// factors (patch_factor); out[a * ostride], a = 0..19.  with_mean = false omits the star-mean
+// pressure term (the deflated solve).  ALLP: every slot of the patch is present (interior
+// class), known at compile time.
+// With W = L L^T: Q W^-1 r_w = Q y for y = L^-T L^-1 r_w, and x_w = L^-T L^-1 (r_w - Q^T x_p):
+// four substitutions with L, none with a division, and Q read from the class data.
+template <typename T, bool ALLP = false, typename RR>
+__host__ __device__ inline void patch_apply(RR&& rr, const DevPatchClass<T>& pc, const PatchFac<T>& f, T* out,
+                                            int ostride, bool with_mean = true) {
+    T y[6];
 #pragma unroll
-    for (int a = 0; a < 6; ++a) zr[a] = rr[8 + a];
-    fwd6p(f.w, zr);
-    // rhs = H^T r_u + Z^T zr - r_p
+    for (int a = 0; a < 6; ++a) y[a] = rr(8 + a);
+    fwd6p(f.w, y);
+    bwd6p(f.w, y);
+    BIOT_PHASE_FENCE();
+    // rhs = H^T r_u + Q W^-1 r_w - r_p
     T rhs[6];
 #pragma unroll
     for (int q1 = 0; q1 < 6; ++q1) {
-        T v = -rr[14 + q1];
+        T v = -rr(14 + q1);
 #pragma unroll
-        for (int a = 0; a < 8; ++a) v += pc.H[a][q1] * rr[a];
+        for (int a = 0; a < 8; ++a) v += pc.H[a][q1] * rr(a);
 #pragma unroll
-        for (int a = 0; a < 6; ++a) v += f.z[q1][a] * zr[a];
+        for (int a = 0; a < 6; ++a) v += pc.Q[q1][a] * y[a];
         rhs[q1] = v;
     }
     // star-mean pressure in closed form; the shifted system (factored in f.s) for the rest
@@ -173,7 +191,7 @@ __host__ __device__ inline void patch_apply(const T rr[PATCH], const DevPatchCla
     for (int q = 0; q < 6; ++q)
         if (ALLP || pc.present[14 + q]) {
             ++k;
-            sum_rp += rr[14 + q];
+            sum_rp += rr(14 + q);
             csum += pc.c[q];
             mrhs += rhs[q];
         }
@@ -181,8 +199,10 @@ __host__ __device__ inline void patch_apply(const T rr[PATCH], const DevPatchCla
     mrhs *= (T)1 / (T)k;
 #pragma unroll
     for (int q1 = 0; q1 < 6; ++q1) rhs[q1] = (ALLP || pc.present[14 + q1]) ? rhs[q1] - mrhs : (T)0;
+    BIOT_PHASE_FENCE();
     fwd6p(f.s, rhs);
     bwd6p(f.s, rhs);
+    BIOT_PHASE_FENCE();
     // x_p = xp0 + gamma on the present pressures.  The star constant carries no flux
     // (Bh^T 1 = Q^T 1 = 0), so the back-substitutions take the deflated part xp0 alone: the
     // same values in exact arithmetic, without cancelling the often large gamma in rounding.
@@ -194,20 +214,22 @@ __host__ __device__ inline void patch_apply(const T rr[PATCH], const DevPatchCla
     for (int a = 0; a < 8; ++a) {
         T v = 0;
 #pragma unroll
-        for (int b = 0; b < 8; ++b) v += pc.Ainv[a][b] * rr[b];
+        for (int b = 0; b < 8; ++b) v += pc.Ainv[a][b] * rr(b);
 #pragma unroll
         for (int q = 0; q < 6; ++q) v -= pc.H[a][q] * xp[q];
         out[a * ostride] = (ALLP || pc.present[a]) ? v : (T)0;
     }
-    // x_w = W^-1 (r_w - Q^T x_p) = L^-T (zr - sum_q x_p[q] z[q])
+    BIOT_PHASE_FENCE();
+    // x_w = W^-1 (r_w - Q^T x_p)
     T xw[6];
 #pragma unroll
     for (int a = 0; a < 6; ++a) {
-        T v = zr[a];
+        T v = rr(8 + a);
 #pragma unroll
-        for (int q = 0; q < 6; ++q) v -= f.z[q][a] * xp[q];
+        for (int q = 0; q < 6; ++q) v -= pc.Q[q][a] * xp[q];
         xw[a] = v;
     }
+    fwd6p(f.w, xw);
     bwd6p(f.w, xw);
 #pragma unroll
     for (int a = 0; a < 6; ++a) out[(8 + a) * ostride] = (ALLP || pc.present[8 + a]) ? xw[a] : (T)0;
@@ -225,7 +247,7 @@ __host__ __device__ inline void patch_solve(const T rr[PATCH], const DevPatchCla
                                             bool with_mean = true) {
     PatchFac<T> f;
     patch_factor<T, ALLP>(pc, kv, wblk, f);
-    patch_apply<T, ALLP>(rr, pc, f, out, ostride, with_mean);
+    patch_apply<T, ALLP>([&](int s) { return rr[s]; }, pc, f, out, ostride, with_mean);
 }
 
 }  // namespace biot

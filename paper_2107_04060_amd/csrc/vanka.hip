@@ -61,6 +61,34 @@ __device__ __forceinline__ void mfma_class_frag(const double* M, int lane, doubl
         }
 }
 
+// One variable-K patch solve: the patch's factors (stored, fp != nullptr, FP64 only, or formed from
+// the 1/K of its star), then the solve, which reads the patch residual from the staged residual in
+// LDS where it needs it (it stays there until the barrier after the patch phase).
+template <typename T, typename P, bool ALLP, bool FACOK>
+__device__ __forceinline__ void vanka_patch(const DevPatchClass<P>& pc, const P (&kv)[6], const P* __restrict__ wblk,
+                                            const double* __restrict__ fp, long long plane,
+                                            const T (&rs)[NTYPES][RW][RW], int tx, int ty, P (&out)[PATCH]) {
+    PatchFac<P> f;
+    bool stored = false;
+    if constexpr (FACOK) {
+        if (fp) {
+            double* fv = reinterpret_cast<double*>(&f);
+#pragma unroll
+            for (int q = 0; q < PFAC; ++q) fv[q] = fp[(long long)q * plane];
+            stored = true;
+        }
+    }
+    if (!stored) patch_factor<P, ALLP>(pc, kv, wblk, f);
+    if constexpr (sizeof(P) == 8) __asm__ volatile("" ::: "memory");
+    patch_apply<P, ALLP>(
+        [&](int s) {
+            int t, di, dj;
+            patch_slot(s, t, di, dj);
+            return (P)rs[t][ty + 1 + dj][tx + 1 + di];
+        },
+        pc, f, out, 1);
+}
+
 // LDS of the fused step.  The staged x_in and the residual are dead once the patch residuals
 // are in registers; the patch corrections then reuse their space.
 template <typename T, typename P, bool UNIFORM, int NCLS, bool PROL>
@@ -76,7 +104,12 @@ struct VankaLds {
     double ms[UNIFORM ? NCLS : 1][UNIFORM ? PATCH * PATCH : 1];  // class inverses of the tile (FP64)
     // patch classes of the tile (variable K)
     std::conditional_t<UNIFORM, char, DevPatchClass<P>> pcs[UNIFORM ? 1 : NCLS];
-    T xcs[PROL ? NTYPES : 1][PROL ? PCW : 1][PROL ? PCW : 1];   // coarse iterate (prolongation)
+    // the coarse iterate is dead once the prolongation has been added to the staged window, before
+    // the owned iterate is copied out of it
+    union {
+        T xcs[PROL ? NTYPES : 1][PROL ? PCW : 1][PROL ? PCW : 1];      // coarse iterate (prolongation)
+        T xo[UNIFORM ? 1 : NTYPES][UNIFORM ? 1 : VO][UNIFORM ? 1 : VO];  // iterate on the owned slots (variable K)
+    };
     T cf[NSTENCIL];                                              // stencil coefficients
     T pwl[PROL ? NPWEIGHTS : 1];                                 // prolongation weights
 };
@@ -214,10 +247,18 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
     // ---- patch solves of the tile's vertices ----------------------------------------------------
     const int vi = i0 + tx, vj = j0 + ty;
     const bool patch = tx < VT && ty < VT;
-    T xown[NTYPES];
+    // the iterate on the owned slots, for the gather: in registers for constant K; in LDS for
+    // variable K, whose patch solves need the registers (the staged window is overwritten by the
+    // patch corrections)
+    T xown[UNIFORM ? NTYPES : 1];
+    if constexpr (UNIFORM) {
 #pragma unroll
-    for (int t = 0; t < NTYPES; ++t)
-        xown[t] = (ZERO || !patch || ggroup(t, NZ) != tz) ? (T)0 : xs[t][ty + 2][tx + 2];
+        for (int t = 0; t < NTYPES; ++t)
+            xown[t] = (ZERO || !patch || ggroup(t, NZ) != tz) ? (T)0 : xs[t][ty + 2][tx + 2];
+    } else if (!ZERO && tx < VO && ty < VO) {
+#pragma unroll
+        for (int t = 0; t < NTYPES; ++t) sh.xo[t][ty][tx] = xs[t][ty + 2][tx + 2];
+    }
     // Constant K: FP64 class inverses on the matrix cores for either storage precision T.
     if constexpr (UNIFORM) {
         // The products run over batches of up to 16 patches that share one class inverse: each
@@ -339,39 +380,17 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
         for (int s = 0; s < PATCH; ++s) out[s] = 0;
         const bool inner = cilo == 1 && cihi == 1 && cjlo == 1 && cjhi == 1;
         const bool act = patch && vi <= n && vj <= n && (color < 0 || in_color(vi, vj, color));
-        P rr[PATCH], kv[6];
         if (act) {
-#pragma unroll
-            for (int s = 0; s < PATCH; ++s) {
-                int t, di, dj;
-                patch_slot(s, t, di, dj);
-                rr[s] = (P)rs[t][ty + 1 + dj][tx + 1 + di];
-            }
+            P kv[6];
 #pragma unroll
             for (int kq = 0; kq < 6; ++kq) {
                 int ut, di, dj;
                 star_tri(kq, ut, di, dj);
                 kv[kq] = (P)sh.ks[ut][ty + 2 + dj][tx + 2 + di];
             }
-            // the patch's stored factors (FP64)
-            auto load_fac = [&](PatchFac<double>& f) {
-                const double* fp = fac + slot_index(L, vi, vj);
-                double* fv = reinterpret_cast<double*>(&f);
-#pragma unroll
-                for (int q = 0; q < PFAC; ++q) fv[q] = fp[(long long)q * L.plane];
-            };
+            const double* fp = (FACOK && fac) ? fac + slot_index(L, vi, vj) : nullptr;
             if (inner) {
-                if constexpr (FACOK) {
-                    if (fac) {
-                        PatchFac<double> f;
-                        load_fac(f);
-                        patch_apply<P, true>(rr, sh.pcs[0], f, out, 1);
-                    } else {
-                        patch_solve<P, true>(rr, sh.pcs[0], kv, wblk, out, 1);
-                    }
-                } else {
-                    patch_solve<P, true>(rr, sh.pcs[0], kv, wblk, out, 1);
-                }
+                vanka_patch<T, P, true, FACOK>(sh.pcs[0], kv, wblk, fp, L.plane, rs, tx, ty, out);
             } else {
                 const int ci = vi == 0 ? 0 : (vi == n ? 2 : 1);
                 const int cj = vj == 0 ? 0 : (vj == n ? 2 : 1);
@@ -379,19 +398,7 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
                 bool keep = false;
 #pragma unroll
                 for (int s = 0; s < 14; ++s) keep = keep || pc.present[s];
-                if (keep) {
-                    if constexpr (FACOK) {
-                        if (fac) {
-                            PatchFac<double> f;
-                            load_fac(f);
-                            patch_apply<P>(rr, pc, f, out, 1);
-                        } else {
-                            patch_solve<P>(rr, pc, kv, wblk, out, 1);
-                        }
-                    } else {
-                        patch_solve<P>(rr, pc, kv, wblk, out, 1);
-                    }
-                }
+                if (keep) vanka_patch<T, P, false, FACOK>(pc, kv, wblk, fp, L.plane, rs, tx, ty, out);
             }
         }
         __syncthreads();
@@ -426,14 +433,19 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
                 constexpr int t = decltype(tc)::value;
                 if (ggroup(t, NZ) == tz && dof_free(t, si, sj, n))
                     x_out[t * L.plane + s0] =
-                        xown[t] + omega * (color < 0 ? (T)vanka_weight(t, si, sj, n) : (T)1) * c[t];
+                        (ZERO ? (T)0 : (UNIFORM ? xown[UNIFORM ? t : 0] : sh.xo[UNIFORM ? 0 : t][UNIFORM ? 0 : ty][UNIFORM ? 0 : tx])) +
+                        omega * (color < 0 ? (T)vanka_weight(t, si, sj, n) : (T)1) * c[t];
             });
         }
     }
 }
 
 template <typename T, typename P, bool UNIFORM, bool ZERO, int NCLS, bool PROL, int NZ>
-__global__ __launch_bounds__(TPB * NZ, NZ == 2 ? 4 : (sizeof(P) == 4 ? 2 : 1)) void k_vanka_step(const T* __restrict__ x_in, const T* __restrict__ b,
+// Two waves per SIMD for the per-patch eliminations (two tiles per CU, one tile's latency-bound
+// phases overlapping the other's): in FP64 the compiler then keeps about 50 of the elimination's
+// values in scratch, which costs less than the second tile gains (768 us against 1092 us per
+// colour step at 2048^2 with one wave per SIMD).
+__global__ __launch_bounds__(TPB * NZ, NZ == 2 ? 4 : 2) void k_vanka_step(const T* __restrict__ x_in, const T* __restrict__ b,
                                                     T* __restrict__ x_out, Layout L, const T* __restrict__ kinv,
                                                     T kinv_s, const T* __restrict__ coef,
                                                     const DevPatchClass<P>* __restrict__ cls,
@@ -450,8 +462,8 @@ __global__ __launch_bounds__(TPB * NZ, NZ == 2 ? 4 : (sizeof(P) == 4 ? 2 : 1)) v
 }
 
 // thread layers of the constant-K step (two: 512 threads per tile, each phase split over twice
-// the waves; variable K keeps one layer, its per-patch eliminations already fill a layer: one
-// wave per SIMD in FP64, whose elimination takes over 256 registers, two in FP32)
+// the waves; variable K keeps one layer, its per-patch eliminations already fill a layer at two
+// waves per SIMD)
 constexpr int VANKA_LAYERS = 2;
 
 template <typename T, typename P, bool UNIFORM, bool ZERO, bool PROL>
