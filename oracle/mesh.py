@@ -19,8 +19,14 @@ notes and are pinned by the Appendix A stencils in the tests):
     D(i, j): edge (i, j+1)-(i+1, j), normal (1,1)/sqrt2.  0 <= i, j < n
   * L(i, j) = {(i,j), (i+1,j), (i,j+1)},  U(i, j) = {(i+1,j), (i+1,j+1), (i,j+1)}.
     Local edge k of a triangle is the edge opposite local vertex k.
-  * Dirichlet data u = 0 and w.n = 0 on the whole boundary: the P1 DoFs of boundary
-    vertices and the bubble / RT0 DoFs of boundary edges are eliminated.
+  * Boundary conditions (bc):
+      "dirichlet" (the default, Sec. 5.1): u = 0 and w.n = 0 on the whole boundary: the P1 DoFs
+        of boundary vertices and the bubble / RT0 DoFs of boundary edges are eliminated.
+      "terzaghi" (Sec. 5, Terzaghi's problem): the column is loaded and drained on x = 0
+        (traction and p = 0, both natural: u and w.n free there), fixed and impermeable on
+        x = 1 (u = 0, w.n = 0), and on rollers, impermeable, on y = 0 and y = 1 (u.n = u_y = 0,
+        w.n = 0; u_x free).  Eliminated: u_x, u_y at x = 1; u_y at y = 0, 1; bubble and RT0 on
+        the edges of x = 1, y = 0 and y = 1.
   * Canonical free-DoF order, each block row-major in (j, i):
       [u_x(interior vertices), u_y(interior vertices), b_H, b_V, b_D (interior edges),
        w_H, w_V, w_D (interior edges), p_L, p_U]
@@ -33,11 +39,16 @@ SQRT2 = np.sqrt(2.0)
 class Mesh:
     """Uniform n x n triangulated square with the full and the free DoF numbering."""
 
-    def __init__(self, n):
+    BCS = ("dirichlet", "terzaghi")
+
+    def __init__(self, n, bc="dirichlet"):
         n = int(n)
         if n < 1:
             raise ValueError("n must be >= 1")
+        if bc not in self.BCS:
+            raise ValueError("bc: one of %s" % (self.BCS,))
         self.n = n
+        self.bc = bc
         self.h = 1.0 / n
         nv1 = n + 1
         # ---- entity counts and ids ------------------------------------------------
@@ -112,11 +123,18 @@ class Mesh:
         self.off_w = self.off_b + self.n_edge
         self.off_p = self.off_w + self.n_edge
         self.n_full = self.off_p + self.n_tri
+        if bc == "dirichlet":
+            ux_free = uy_free = self.vert_interior
+            e_free = self.edge_interior
+        else:
+            ux_free = vi < n
+            uy_free = (vi < n) & (vj > 0) & (vj < n)
+            e_free = np.where(kind == 0, (ej > 0) & (ej < n), np.where(kind == 1, ei < n, True))
         free = np.zeros(self.n_full, dtype=bool)
-        free[self.off_ux:self.off_ux + self.n_vert] = self.vert_interior
-        free[self.off_uy:self.off_uy + self.n_vert] = self.vert_interior
-        free[self.off_b:self.off_b + self.n_edge] = self.edge_interior
-        free[self.off_w:self.off_w + self.n_edge] = self.edge_interior
+        free[self.off_ux:self.off_ux + self.n_vert] = ux_free
+        free[self.off_uy:self.off_uy + self.n_vert] = uy_free
+        free[self.off_b:self.off_b + self.n_edge] = e_free
+        free[self.off_w:self.off_w + self.n_edge] = e_free
         free[self.off_p:] = True
         self.free_mask = free
         self.free_full = np.nonzero(free)[0]          # canonical index -> full index
@@ -124,8 +142,8 @@ class Mesh:
         self.full_to_free[self.free_full] = np.arange(self.free_full.size)
         self.n_free = int(self.free_full.size)
         # number of free DoFs of each field in canonical order
-        nu = 2 * int(self.vert_interior.sum()) + int(self.edge_interior.sum())
-        nw = int(self.edge_interior.sum())
+        nu = int(ux_free.sum()) + int(uy_free.sum()) + int(e_free.sum())
+        nw = int(e_free.sum())
         self.n_u, self.n_w, self.n_p = nu, nw, self.n_tri
 
     # ---- entity id helpers -------------------------------------------------------------

@@ -8,7 +8,9 @@ Paper passages followed:
     multilevel cycle replaces A_H^{-1} by the same cycle on the coarser level.
   * Sec. 5.1: direct solve on the coarsest mesh.
 Readings: coarsest mesh 4 x 4 unless told otherwise; one omega on every level; the
-heterogeneous permeability is coarsened by averaging 1/K over the four children.
+heterogeneous permeability is coarsened by averaging 1/K over the four children; every level
+takes the boundary conditions of the finest (bc), and the Vanka patch shift (vanka_shift,
+Sec. 5, Terzaghi's problem) applies on every level.
 """
 import numpy as np
 import scipy.linalg as sla
@@ -20,8 +22,8 @@ from .smoothers import MulticolorVanka, AdditiveVanka, InexactBSR, patch_table
 
 
 class Level:
-    def __init__(self, n, params, K_tri):
-        self.mesh = Mesh(n)
+    def __init__(self, n, params, K_tri, bc="dirichlet"):
+        self.mesh = Mesh(n, bc)
         self.asm = Assembly(self.mesh, params, K_tri)
         self.A = self.asm.A
         self.P = None          # prolongation from the next coarser level
@@ -33,7 +35,7 @@ class Hierarchy:
 
     def __init__(self, n, params, K_tri=1.0, smoother="vanka", omega=1.0, omega_J=1.0,
                  nu1=1, nu2=1, n_coarse=4, levels=None, schur_sweeps=1, omega_S=1.0, gamma=1,
-                 vanka_colors=0, schur_cg=0, gamma_from=0, fcycle=False):
+                 vanka_colors=0, schur_cg=0, gamma_from=0, fcycle=False, bc="dirichlet", vanka_shift=0.0):
         if levels is not None:
             n_coarse = n >> (levels - 1)
         self.params = params
@@ -47,7 +49,7 @@ class Hierarchy:
         Kinv = 1.0 / np.broadcast_to(np.asarray(K_tri, dtype=np.float64), (2 * n * n,))
         nn = n
         while True:
-            lev = Level(nn, params, 1.0 / Kinv)
+            lev = Level(nn, params, 1.0 / Kinv, bc)
             self.levels.append(lev)
             if nn <= n_coarse:
                 break
@@ -62,7 +64,7 @@ class Hierarchy:
                 lev.smoother = MulticolorVanka(lev.A, lev.mesh, omega, vanka_colors)
             elif smoother == "vanka":
                 _, slots = patch_table(lev.mesh, "full")
-                lev.smoother = AdditiveVanka(lev.A, slots, omega)
+                lev.smoother = AdditiveVanka(lev.A, slots, omega, vanka_shift)
             elif smoother == "bsr":
                 lev.smoother = InexactBSR(lev.asm, omega, omega_J, schur_sweeps, omega_S, schur_cg)
             else:

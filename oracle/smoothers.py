@@ -74,11 +74,16 @@ def _dense_blocks(A, idx):
 
 
 class AdditiveVanka:
-    """x <- x + omega * sum_l V_l^T D_l (V_l A V_l^T)^{-1} V_l (b - A x)."""
+    """x <- x + omega * sum_l V_l^T D_l (V_l A V_l^T + shift I)^{-1} V_l (b - A x).
 
-    def __init__(self, A, slots, omega=1.0):
+    shift: added to the diagonal of every patch matrix.  Sec. 5 (Terzaghi's problem) adds 1e-8
+    there when M = infinity, where the pressure block of A vanishes and the vertex patches are
+    hard to invert; 0 otherwise."""
+
+    def __init__(self, A, slots, omega=1.0, shift=0.0):
         self.A = A.tocsr()
         self.omega = float(omega)
+        self.shift = float(shift)
         n = A.shape[0]
         mult = np.zeros(n)
         self.groups = []   # (index array (P, s), patch matrices (P, s, s))
@@ -88,7 +93,7 @@ class AdditiveVanka:
             idx = np.array([t for t in sets if len(t) == s], dtype=np.int64)
             if s == 0:
                 continue
-            self.groups.append((idx, _dense_blocks(self.A, idx)))
+            self.groups.append((idx, _dense_blocks(self.A, idx) + self.shift * np.eye(s)))
             np.add.at(mult, idx.ravel(), 1.0)
         if np.any(mult == 0):
             raise ValueError("some DoF lies in no patch")

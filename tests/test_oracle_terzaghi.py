@@ -1,0 +1,146 @@
+"""Pins of Terzaghi's consolidation problem in the oracle (oracle/terzaghi.py; Sec. 5, Table 6).
+
+* The series solution (with the pressure series read with sines) satisfies the problem, checked
+  by finite differences of the series, not by its own algebra: the load sigma_xx = -p0
+  everywhere, the mass balance d_t(alpha d_x u_x) = k d_xx p (M = infinity), p = 0 on the
+  drained face, no flux through x = 1, u = 0 at x = 1, u -> 0 and p -> p0 as t -> 0+.  The
+  printed cosine series fails the load and the drained face.
+* The mixed boundary conditions leave 10 n^2 - 2 n free DoFs (u_x: n (n + 1), u_y: n (n - 1),
+  edges: 3 n^2 - n for the bubbles and as many for RT0, 2 n^2 pressures).
+* Backward Euler with direct solves converges to the series at t = tau_hat / 10 at first order
+  in h with tau proportional to h: |u - u_h|_{H^1} and ||p - p_h||_{L^2} halve per refinement.
+* Undrained response: a first step much shorter than tau_hat leaves p = p0 away from the
+  drained face.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle.fem import Assembly, lame_from_E_nu
+from oracle.mesh import Mesh
+from oracle.terzaghi import Terzaghi, exact_p, exact_ux, tau_hat
+
+NU, K = 0.4, 1e-6
+
+
+def _lm():
+    return lame_from_E_nu(3e4, NU)
+
+
+def test_series_satisfies_the_problem():
+    lam, mu = _lm()
+    th = tau_hat(K, lam, mu)
+    xs = np.array([0.1, 0.3, 0.5, 0.7, 0.9])
+    hx = 1e-4
+    for t in (th / 100, th / 10, th):
+        p = exact_p(xs, t, K, lam, mu)
+        dux = (exact_ux(xs + hx, t, K, lam, mu) - exact_ux(xs - hx, t, K, lam, mu)) / (2 * hx)
+        # the load: (lambda + 2 mu) d_x u_x - alpha p = -p0
+        assert np.max(np.abs((lam + 2 * mu) * dux - p + 1.0)) < 1e-6
+        # mass balance with 1/M = 0, mu_f = 1: d_t (d_x u_x) = k d_xx p
+        ht = 1e-4 * th
+        dt_div = ((exact_ux(xs + hx, t + ht, K, lam, mu) - exact_ux(xs - hx, t + ht, K, lam, mu))
+                  - (exact_ux(xs + hx, t - ht, K, lam, mu) - exact_ux(xs - hx, t - ht, K, lam, mu))) / (4 * hx * ht)
+        hp = 1e-3
+        dxx_p = (exact_p(xs + hp, t, K, lam, mu) - 2 * p + exact_p(xs - hp, t, K, lam, mu)) / hp ** 2
+        scale = np.max(np.abs(K * dxx_p))
+        assert np.max(np.abs(dt_div - K * dxx_p)) < 1e-4 * scale
+        # boundaries: drained x = 0, no flux and no displacement at x = 1
+        assert abs(exact_p(0.0, t, K, lam, mu)) < 1e-12
+        assert abs(exact_ux(1.0, t, K, lam, mu)) < 1e-12 * (1.0 / (lam + 2 * mu))
+        dp1 = (exact_p(1.0, t, K, lam, mu) - exact_p(1.0 - hp, t, K, lam, mu)) / hp
+        assert abs(dp1) < 1e-2 * np.max(np.abs(p))
+    # t -> 0+: the undrained state p = p0, u = 0
+    t0 = th * 1e-7
+    assert np.max(np.abs(exact_p(xs, t0, K, lam, mu, terms=40000) - 1.0)) < 1e-3
+    assert np.max(np.abs(exact_ux(xs, t0, K, lam, mu, terms=40000))) < 1e-3 / (lam + 2 * mu)
+
+
+def test_printed_cosine_series_fails_the_load():
+    """With cos(a_i x) in the pressure series, p does not vanish on the drained face and the
+    stress balance sigma_xx = -p0 fails: the reading (sines) is forced."""
+    lam, mu = _lm()
+    th = tau_hat(K, lam, mu)
+    t, terms = th / 10, 2000
+    a = (2 * np.arange(terms) + 1) * np.pi / 2
+    c = K * (lam + 2 * mu)
+
+    def p_cos(x):
+        return np.sum(2.0 / a * np.exp(-a ** 2 * c * t) * np.cos(np.multiply.outer(x, a)), axis=-1)
+
+    assert abs(p_cos(np.array(0.0))) > 0.1
+    xs = np.array([0.1, 0.5, 0.9])
+    hx = 1e-4
+    dux = (exact_ux(xs + hx, t, K, lam, mu) - exact_ux(xs - hx, t, K, lam, mu)) / (2 * hx)
+    assert np.max(np.abs((lam + 2 * mu) * dux - p_cos(xs) + 1.0)) > 0.1
+
+
+@pytest.mark.parametrize("n", [4, 8, 16])
+def test_mixed_boundary_free_counts(n):
+    m = Mesh(n, "terzaghi")
+    assert m.n_free == 10 * n * n - 2 * n
+    assert m.n_u == 5 * n * n - n and m.n_w == 3 * n * n - n and m.n_p == 2 * n * n
+
+
+def _run(n, steps_per_tenth):
+    T = Terzaghi(n, NU, K)
+    steps = steps_per_tenth
+    T.tau = T.tau_hat / 10 / steps
+    T.params.tau = T.tau
+    T.asm = Assembly(T.mesh, T.params, T.k)
+    lu = spla.splu(T.A.tocsc())
+    x = T.run(steps, lambda b, m: lu.solve(b))
+    return T.errors(x, steps * T.tau)
+
+
+def test_backward_euler_converges_to_the_series():
+    e = [_run(n, 10 * n // 8) for n in (8, 16, 32)]
+    print("errors (H1 u, L2 p):", e)
+    for (u0, p0), (u1, p1) in zip(e, e[1:]):
+        assert 1.8 < u0 / u1 < 2.2
+        assert 1.8 < p0 / p1 < 2.2
+    assert e[-1][1] < 0.02
+
+
+def test_first_step_is_undrained():
+    lam, mu = _lm()
+    T = Terzaghi(16, NU, K, tau=tau_hat(K, lam, mu) * 1e-6)
+    x = T.run(1, lambda b, m: spla.spsolve(T.A.tocsc(), b))
+    m = T.mesh
+    p = x[m.off_p:]
+    cx = m.vert_xy[m.tri_vert][:, :, 0].mean(axis=1)   # x of the triangle centroids
+    far = cx > 0.25
+    assert np.max(np.abs(p[far] - 1.0)) < 1e-2
+
+
+def test_shift_removes_the_star_constant_null_mode():
+    """With M = infinity an interior Vanka patch matrix has the constant pressure on its star
+    in its null space (the patch velocities carry no net flux of it), which is why the patches
+    are shifted by 1e-8 on the diagonal (Sec. 5); the shifted patches are invertible and the
+    smoother built with them reproduces a LAPACK solve of each shifted block."""
+    from oracle.smoothers import AdditiveVanka, patch_table
+    T = Terzaghi(8, NU, K)
+    verts, slots = patch_table(T.mesh, "full")
+    ij = T.mesh.vert_ij[verts]
+    k = int(np.nonzero((ij[:, 0] == 4) & (ij[:, 1] == 4))[0][0])
+    s = slots[k]
+    assert np.all(s >= 0)
+    Al = T.A.toarray()[np.ix_(s, s)]
+    v = np.zeros(20)
+    v[14:] = 1.0
+    assert np.linalg.norm(Al @ v) < 1e-12 * np.linalg.norm(Al)
+    sv = np.linalg.svd(Al, compute_uv=False)
+    assert sv[-1] < 1e-12 * sv[0]
+    sm = AdditiveVanka(T.A, slots, 1.0, shift=1e-8)
+    for idx, B in sm.groups:
+        if idx.shape[1] != 20:
+            continue
+        rows = np.nonzero((idx == np.sort(s)).all(axis=1))[0]
+        if rows.size:
+            Bk = B[rows[0]]
+            ref = T.A.toarray()[np.ix_(np.sort(s), np.sort(s))] + 1e-8 * np.eye(20)
+            assert np.array_equal(Bk, ref)
+            assert np.linalg.svd(Bk, compute_uv=False)[-1] > 1e-9
+            break
+    else:
+        raise AssertionError("patch not found")
