@@ -29,7 +29,7 @@ BLOCK_RESTART = 100          # FGMRES restart of the block-contrast workload
 # the cycle of the block-contrast workload: the fastest to 1e-8 among the V-, W- and partial
 # W-cycles with additive and multiplicative Vanka and 8 to 10 levels measured on it (the
 # V(2,2) cycle with the LFA weight on 10 levels takes 178 iterations, 3.6 s per solve)
-BLOCK_CYCLE = dict(nu12=1, omega=1.0, colors=3, gamma=2, gamma_from=1, levels=8, fcycle=0)
+BLOCK_CYCLE = dict(nu12=1, omega=1.1, colors=3, gamma=2, gamma_from=1, levels=8, fcycle=0)
 CSRC = os.path.join(ROOT, "paper_2107_04060_amd", "csrc")
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_vanka_step_sweep256_fp64.md")
 BLOCK_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_vanka_step_block2048_fp64.md")

@@ -192,13 +192,20 @@ __global__ __launch_bounds__(256) void k_coarse_solve(const double* __restrict__
     extern __shared__ double bb[];
     for (int k = threadIdx.x; k < N; k += blockDim.x) bb[k] = (double)b[idx[k]];
     __syncthreads();
-    // one row per wave: the lanes read consecutive entries of the row, then a butterfly sum
+    // one row per wave: the lanes read consecutive entries of the row into eight partial sums
+    // (eight loads of each lane in flight, not one after another), then a butterfly sum
     const int lane = threadIdx.x & 63;
     const int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (k >= N) return;
     const double* row = Ainv + (long long)k * N;
-    double s = 0;
-    for (int l = lane; l < N; l += 64) s += row[l] * bb[l];
+    double ps[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int l = lane;
+    for (; l + 7 * 64 < N; l += 8 * 64) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) ps[u] += row[l + u * 64] * bb[l + u * 64];
+    }
+    for (int u = 0; l < N; l += 64, ++u) ps[u] += row[l] * bb[l];
+    double s = ((ps[0] + ps[1]) + (ps[2] + ps[3])) + ((ps[4] + ps[5]) + (ps[6] + ps[7]));
     s = wave_sum(s);
     if (lane == 0) x[idx[k]] = (T)s;
 }

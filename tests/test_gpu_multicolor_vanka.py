@@ -8,7 +8,7 @@ the oracle's MulticolorVanka.
 * The standalone smoothing entry point runs one multiplicative step (four and three colours).
 * On the paper's steady problem (nu = 0.499, k = 1e-6) FGMRES with the multiplicative V(1,1)
   cycle takes the oracle's iteration count (+-1), fewer than the additive V(2,2) cycle.
-* The cycle shape of the 2048 x 2048 block-contrast workload (multiplicative V(1,1), omega 1,
+* The cycle shape of the 2048 x 2048 block-contrast workload (multiplicative V(1,1), omega 1.1,
   cycle index 2 below the finest level, as W- and as F-cycle, in four and three colours) on the same physics and
   permeability pattern at n = 64 over five levels: one cycle to the V-cycle parity tolerance.
 """
@@ -111,7 +111,7 @@ def test_block_workload_cycle_parity(binding, fcycle, ncolors):
     lam, mu, al, M, mf_, tau = case("block")
     s = binding.BiotSolver(n, lam, mu, alpha=al, M=M, mu_f=mf_, tau=tau,
                            K=torch.tensor(K, dtype=torch.float64, device="cuda"))
-    cyc = dict(nu1=1, nu2=1, omega=1.0, vanka_colors=ncolors, gamma=2, gamma_from=1, fcycle=fcycle)
+    cyc = dict(nu1=1, nu2=1, omega=1.1, vanka_colors=ncolors, gamma=2, gamma_from=1, fcycle=fcycle)
     s.setup(levels=levels, smoother="vanka", **cyc)
     H = Hierarchy(n, params("block"), K_tri=K, smoother="vanka", levels=levels, **cyc)
     r = inputs.rhs_uniform(n, 8)
