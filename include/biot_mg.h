@@ -137,6 +137,10 @@ typedef struct {
                            first one of the same kind (the F-cycle: below the first repeating
                            level, level m is visited m + 1 times rather than 2^m).  Neither is
                            the paper's V-cycle: both are standard multigrid cycle shapes.      */
+    int gamma_to;       /* with gamma >= 2: 0 = no upper limit; k >= 1: levels l >= k take one
+                           coarse correction again, so only gamma_from <= l < gamma_to repeat
+                           (below gamma_to the cycle is a V-cycle, visited as often as level
+                           gamma_to)                                                          */
 } biot_mg_opts;
 
 /* FGMRES controls (in) and results (out). */

@@ -35,7 +35,8 @@ class Hierarchy:
 
     def __init__(self, n, params, K_tri=1.0, smoother="vanka", omega=1.0, omega_J=1.0,
                  nu1=1, nu2=1, n_coarse=4, levels=None, schur_sweeps=1, omega_S=1.0, gamma=1,
-                 vanka_colors=0, schur_cg=0, gamma_from=0, fcycle=False, bc="dirichlet", vanka_shift=0.0):
+                 vanka_colors=0, schur_cg=0, gamma_from=0, fcycle=False, bc="dirichlet", vanka_shift=0.0,
+                 gamma_to=0):
         if levels is not None:
             n_coarse = n >> (levels - 1)
         self.params = params
@@ -43,6 +44,7 @@ class Hierarchy:
         self.gamma = int(gamma)                 # coarse corrections per level: 1 V-cycle, 2 W-cycle
         self.gamma_from = int(gamma_from)       # levels finer than this take one coarse correction
         self.fcycle = bool(fcycle)              # further coarse corrections are V-cycles (F-cycle)
+        self.gamma_to = int(gamma_to)           # > 0: levels from this one down take one correction
         if self.gamma < 1:
             raise ValueError("gamma >= 1")
         self.levels = []
@@ -64,7 +66,7 @@ class Hierarchy:
                 lev.smoother = MulticolorVanka(lev.A, lev.mesh, omega, vanka_colors)
             elif smoother == "vanka":
                 _, slots = patch_table(lev.mesh, "full")
-                lev.smoother = AdditiveVanka(lev.A, slots, omega, vanka_shift)
+                lev.smoother = AdditiveVanka(lev.A, slots, omega, vanka_shift, lev.mesh.n_u + lev.mesh.n_w)
             elif smoother == "bsr":
                 lev.smoother = InexactBSR(lev.asm, omega, omega_J, schur_sweeps, omega_S, schur_cg)
             else:
@@ -79,7 +81,8 @@ class Hierarchy:
         """One V(nu1, nu2) cycle for A_level x = b from x = 0; with gamma > 1 the coarse
         correction is gamma cycles of the next level (a W-cycle for gamma = 2), each further one
         on the residual left by the previous ones, except at the coarsest level, whose direct
-        solve is exact, and on levels finer than gamma_from, which take one.
+        solve is exact, and on levels finer than gamma_from or (gamma_to > 0) from gamma_to down,
+        which take one.
 
         fcycle: the first coarse cycle is of the same kind, the further ones are V-cycles (for
         gamma = 2 the F-cycle, which visits level m below the first repeating level m + 1
@@ -93,7 +96,8 @@ class Hierarchy:
         r = b - lev.A @ x
         bc = lev.P.T @ r
         xc = self.vcycle(bc, level + 1, vonly)
-        if not vonly and level + 1 < len(self.levels) - 1 and level >= self.gamma_from:
+        repeat = level >= self.gamma_from and (self.gamma_to <= 0 or level < self.gamma_to)
+        if not vonly and level + 1 < len(self.levels) - 1 and repeat:
             for _ in range(self.gamma - 1):
                 xc = xc + self.vcycle(bc - self.levels[level + 1].A @ xc, level + 1, self.fcycle)
         x = x + lev.P @ xc

@@ -74,16 +74,23 @@ def _dense_blocks(A, idx):
 
 
 class AdditiveVanka:
-    """x <- x + omega * sum_l V_l^T D_l (V_l A V_l^T + shift I)^{-1} V_l (b - A x).
+    """x <- x + omega * sum_l V_l^T D_l (V_l A V_l^T + shift S)^{-1} V_l (b - A x).
 
-    shift: added to the diagonal of every patch matrix.  Sec. 5 (Terzaghi's problem) adds 1e-8
-    there when M = infinity, where the pressure block of A vanishes and the vertex patches are
-    hard to invert; 0 otherwise."""
+    shift: Sec. 5 (Terzaghi's problem) adds a weight 1e-8 to the diagonal of the Vanka blocks
+    when M = infinity, where the pressure block -(1/M) M_p of A vanishes and an interior patch
+    matrix is singular (the constant pressure on its star).  Reading: the weight enlarges each
+    diagonal block of the patch taken in its definite form, A_u + shift, tau M_w + shift and
+    (1/M) M_p + shift, like a small compressibility; in the symmetric saddle-point numbering
+    used here S is +1 on the displacement and Darcy entries and -1 on the pressure entries
+    (canonical indices >= p_start).  The other sign on the pressures (+shift, a negative
+    compressibility) leaves the nearly incompressible Terzaghi cases of Table 6 unconverged."""
 
-    def __init__(self, A, slots, omega=1.0, shift=0.0):
+    def __init__(self, A, slots, omega=1.0, shift=0.0, p_start=None):
         self.A = A.tocsr()
         self.omega = float(omega)
         self.shift = float(shift)
+        if self.shift != 0.0 and p_start is None:
+            raise ValueError("a patch shift needs p_start, the first pressure index")
         n = A.shape[0]
         mult = np.zeros(n)
         self.groups = []   # (index array (P, s), patch matrices (P, s, s))
@@ -93,7 +100,11 @@ class AdditiveVanka:
             idx = np.array([t for t in sets if len(t) == s], dtype=np.int64)
             if s == 0:
                 continue
-            self.groups.append((idx, _dense_blocks(self.A, idx) + self.shift * np.eye(s)))
+            blocks = _dense_blocks(self.A, idx)
+            if self.shift != 0.0:
+                sgn = np.where(idx >= p_start, -1.0, 1.0)
+                blocks = blocks + self.shift * sgn[:, :, None] * np.eye(s)[None]
+            self.groups.append((idx, blocks))
             np.add.at(mult, idx.ravel(), 1.0)
         if np.any(mult == 0):
             raise ValueError("some DoF lies in no patch")

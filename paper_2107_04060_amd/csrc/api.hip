@@ -529,7 +529,8 @@ static T* vcycle_level(biot_ctx* c, int l, const T* b, T* buf0, T* buf1, hipStre
     launch_residual_restrict<T>(lv.view<T>(), lc.L, cur, b, bc, c->K_uniform, (T)(1.0 / c->K_scalar),
                                 PW<T>::get(c), st, &tm);
     T* xc = vcycle_level<T>(c, l + 1, bc, XBuf<T>::get(lc, 0), XBuf<T>::get(lc, 1), st, nullptr, vonly);
-    if (!vonly && c->opts.gamma > 1 && l >= c->opts.gamma_from && l + 2 < (int)c->levels.size()) {
+    if (!vonly && c->opts.gamma > 1 && l >= c->opts.gamma_from && (c->opts.gamma_to == 0 || l < c->opts.gamma_to) &&
+        l + 2 < (int)c->levels.size()) {
         // W-cycle: gamma - 1 further cycles of level l + 1, each continuing from the iterate the
         // previous one left (with linear smoothing the same as a cycle from zero on the residual
         // it left, added to it); the coarsest level's direct solve is exact and not repeated.
@@ -1040,6 +1041,7 @@ int biot_setup_hierarchy(biot_ctx* c, const biot_mg_opts* o, void* stream) {
         require(o->gamma >= 0 && o->gamma <= 4, "gamma (cycle index) in [0, 4]");
         require(o->gamma_from >= 0 && o->gamma_from < o->levels, "gamma_from in [0, levels)");
         require(o->fcycle == 0 || o->fcycle == 1, "fcycle: 0 (W-cycle) or 1 (F-cycle)");
+        require(o->gamma_to >= 0 && o->gamma_to < o->levels, "gamma_to in [0, levels)");
         require(o->vanka_colors == 0 || o->vanka_colors == 3 || o->vanka_colors == 4,
                 "vanka_colors: 0 (additive), 3 or 4");
         require(o->schur_sweeps <= 1 || (std::isfinite(o->omega_S) && o->omega_S > 0 && o->omega_S <= 1),

@@ -9,7 +9,8 @@ the oracle's MulticolorVanka.
 * On the paper's steady problem (nu = 0.499, k = 1e-6) FGMRES with the multiplicative V(1,1)
   cycle takes the oracle's iteration count (+-1), fewer than the additive V(2,2) cycle.
 * The cycle shape of the 2048 x 2048 block-contrast workload (multiplicative V(1,1), omega 1.1,
-  cycle index 2 below the finest level, as W- and as F-cycle, in four and three colours) on the same physics and
+  cycle index 2 below the finest level, as W- and as F-cycle, in four and three colours, and
+  with the repetition stopped below level 2 (gamma_to)) on the same physics and
   permeability pattern at n = 64 over five levels: one cycle to the V-cycle parity tolerance.
 """
 import numpy as np
@@ -103,15 +104,16 @@ def test_multicolor_solve_matches_oracle(binding):
     assert abs(info["iters"] - io["iters"]) <= 1
 
 
-@pytest.mark.parametrize("fcycle,ncolors", [(False, 4), (True, 4), (False, 3)])
-def test_block_workload_cycle_parity(binding, fcycle, ncolors):
+@pytest.mark.parametrize("fcycle,ncolors,gamma_to", [(False, 4, 0), (True, 4, 0), (False, 3, 0), (False, 3, 2)])
+def test_block_workload_cycle_parity(binding, fcycle, ncolors, gamma_to):
     n, levels = 64, 5
-    print("block-contrast cycle n=%d %s-cycle, %d colours" % (n, "F" if fcycle else "W", ncolors), flush=True)
+    print("block-contrast cycle n=%d %s-cycle, %d colours, gamma_to %d" % (n, "F" if fcycle else "W", ncolors, gamma_to),
+          flush=True)
     K = block_perm(n)
     lam, mu, al, M, mf_, tau = case("block")
     s = binding.BiotSolver(n, lam, mu, alpha=al, M=M, mu_f=mf_, tau=tau,
                            K=torch.tensor(K, dtype=torch.float64, device="cuda"))
-    cyc = dict(nu1=1, nu2=1, omega=1.1, vanka_colors=ncolors, gamma=2, gamma_from=1, fcycle=fcycle)
+    cyc = dict(nu1=1, nu2=1, omega=1.1, vanka_colors=ncolors, gamma=2, gamma_from=1, fcycle=fcycle, gamma_to=gamma_to)
     s.setup(levels=levels, smoother="vanka", **cyc)
     H = Hierarchy(n, params("block"), K_tri=K, smoother="vanka", levels=levels, **cyc)
     r = inputs.rhs_uniform(n, 8)

@@ -146,3 +146,16 @@ def test_fcycle_and_wcycle_visit_counts():
     assert _count_visits(Hierarchy(n, _P(), gamma=2, **kw), b) == [1, 2, 4, 8]
     assert _count_visits(Hierarchy(n, _P(), gamma=2, gamma_from=1, fcycle=True, **kw), b) == [1, 1, 2, 3]
     assert _count_visits(Hierarchy(n, _P(), **kw), b) == [1, 1, 1, 1]
+
+
+def test_gamma_to_stops_the_repetition():
+    """gamma_to = k: only levels gamma_from <= l < k repeat their coarse correction, so the levels
+    below k are visited as often as level k; gamma_to = gamma_from is the V-cycle."""
+    n = 64
+    b = inputs.rhs_uniform(n, 9)
+    kw = dict(K_tri=1e-2, smoother="vanka", omega=0.8, nu1=1, nu2=1, levels=6)
+    assert _count_visits(Hierarchy(n, _P(), gamma=2, gamma_from=1, **kw), b) == [1, 1, 2, 4, 8]
+    assert _count_visits(Hierarchy(n, _P(), gamma=2, gamma_from=1, gamma_to=3, **kw), b) == [1, 1, 2, 4, 4]
+    assert _count_visits(Hierarchy(n, _P(), gamma=2, gamma_from=0, gamma_to=2, **kw), b) == [1, 2, 4, 4, 4]
+    v = Hierarchy(n, _P(), **kw).vcycle(b)
+    assert np.array_equal(Hierarchy(n, _P(), gamma=2, gamma_from=2, gamma_to=2, **kw).vcycle(b), v)
