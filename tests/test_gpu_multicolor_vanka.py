@@ -125,3 +125,26 @@ def test_block_workload_cycle_parity(binding, fcycle, ncolors, gamma_to):
     err = rel(z, H.vcycle(r))
     print("  rel diff %.2e  tol %.2e  (kappa %.2e)" % (err, tol, kap), flush=True)
     assert err < tol
+
+
+def test_block_workload_solve_matches_oracle(binding):
+    """The 2048 x 2048 workload's solver (three-colour multiplicative V(1,1), omega 1.1, cycle
+    index 2 below the finest level, direct solve at 16 x 16, FGMRES restart 100 to 1e-8) on the
+    same physics and permeability pattern at n = 128 over four levels: the GPU takes the
+    oracle's FGMRES iteration count (+-1) and both reach 1e-8 in the true residual."""
+    n, levels = 128, 4
+    K = block_perm(n)
+    lam, mu, al, M, mf_, tau = case("block")
+    cyc = dict(nu1=1, nu2=1, omega=1.1, vanka_colors=3, gamma=2, gamma_from=1)
+    s = binding.BiotSolver(n, lam, mu, alpha=al, M=M, mu_f=mf_, tau=tau,
+                           K=torch.tensor(K, dtype=torch.float64, device="cuda"))
+    s.setup(levels=levels, smoother="vanka", **cyc)
+    b = inputs.rhs_uniform(n, 3)
+    _, info = s.solve(_t(b), tol=1e-8, restart=100, maxit=300)
+    s.close()
+    H = Hierarchy(n, params("block"), K_tri=K, smoother="vanka", levels=levels, **cyc)
+    _, io = fgmres(H.A, b, H.vcycle, tol=1e-8, restart=100, maxit=300)
+    print("  block workload cycle at n=%d: gpu %d iterations (%.2e), oracle %d (%.2e)"
+          % (n, info["iters"], info["rel_res_true"], io["iters"], io["rel_res_true"]), flush=True)
+    assert info["converged"] and io["converged"]
+    assert abs(info["iters"] - io["iters"]) <= 1
