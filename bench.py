@@ -26,6 +26,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 BLOCK_RESTART = 100          # FGMRES restart of the block-contrast workload
+BLOCK_REORTH = 0.01          # its Gram-Schmidt threshold: a second pass after two digits of cancellation
 # the cycle of the block-contrast workload: the fastest to 1e-8 among the V-, W- and partial
 # W-cycles with additive and multiplicative Vanka and 8 to 10 levels measured on it (the
 # V(2,2) cycle with the LFA weight on 10 levels takes 178 iterations, 3.6 s per solve)
@@ -94,6 +95,8 @@ def parse():
     ap.add_argument("--fcycle", type=int, default=BLOCK_CYCLE["fcycle"], choices=[0, 1],
                     help="block2048: 1 = the repeated coarse corrections are V-cycles (F-cycle), 0 = W-cycle")
     ap.add_argument("--restart", type=int, default=BLOCK_RESTART, help="block2048: FGMRES restart")
+    ap.add_argument("--reorth", type=float, default=BLOCK_REORTH,
+                    help="block2048: Gram-Schmidt second pass when |w1| < reorth |w0| (0: 1/sqrt(2))")
     ap.add_argument("--levels", type=int, default=BLOCK_CYCLE["levels"],
                     help="block2048: mesh levels (8: direct solve on the 16 x 16 mesh)")
     ap.add_argument("--reference", type=int, default=1,
@@ -430,7 +433,8 @@ def main_block2048(args, binding, inputs, torch):
             del src
         try:
             for k in range(args.warmup):
-                _, info = s.solve(rhs[k % nrhs], tol=args.tol, restart=restart, maxit=600, out=x)
+                _, info = s.solve(rhs[k % nrhs], tol=args.tol, restart=restart, maxit=600, out=x,
+                                  reorth=args.reorth)
                 print("block2048 %s warm-up rhs %d: %d iterations" % (form, k % nrhs, info["iters"]),
                       file=sys.stderr, flush=True)
         except binding.BiotError as e:
@@ -448,7 +452,7 @@ def main_block2048(args, binding, inputs, torch):
         t0 = time.perf_counter()
         for k in order:
             ta = time.perf_counter()
-            _, info = s.solve(rhs[k], tol=args.tol, restart=restart, maxit=600, out=x)
+            _, info = s.solve(rhs[k], tol=args.tol, restart=restart, maxit=600, out=x, reorth=args.reorth)
             torch.cuda.synchronize()
             ms.append(round((time.perf_counter() - ta) * 1e3, 1))
             iters.append(info["iters"])
@@ -522,7 +526,7 @@ def main_block2048(args, binding, inputs, torch):
                                 args.gamma, args.gamma_from,
                                 "the repeated corrections are V-cycles: F-cycle" if args.fcycle else "W-cycle",
                                 levels, n >> (levels - 1), n >> (levels - 1)),
-                   "restart": restart, "tol": args.tol,
+                   "restart": restart, "tol": args.tol, "gram_schmidt_second_pass_below": args.reorth,
                    "step": "one right-hand-side solve from x = 0, hierarchy reused", "rhs_order": order,
                    "forms": forms, "all_converged": all(res[f].get("all_converged", False) for f in forms)},
         "precision_forms": res, "roofline": roofline, "residual_kernel": resid, "cpu_baseline": cpu,

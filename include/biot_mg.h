@@ -159,6 +159,10 @@ typedef struct {
                            one V-cycle, must then be a fixed linear operator, i.e. no
                            schur_cg)                                                          */
     double rel_res_prec;/* out (side 1): ||M^{-1}(b - A x)||_2 / ||M^{-1} b||_2 at the end   */
+    double reorth;      /* in: the classical Gram-Schmidt step takes a second pass when the first
+                           one cancels, |w_1| < eta |w_0| (the Daniel-Gragg-Kaufman-Stewart test);
+                           eta = reorth in (0, 1], or 1/sqrt(2) when 0 (the default).  A smaller
+                           eta skips the pass unless more digits cancel (eta = 0.01: two)      */
 } biot_solve_info;
 
 /* Assemble the rediscretized operator on the finest mesh (Sec. 2.3, block_form_rq):

@@ -712,6 +712,7 @@ static int fgmres(biot_ctx* c, const KrylovWork& K, const double* b_canon, doubl
     // stopping on the preconditioned residual |M^{-1}(b - A x)| <= tol |M^{-1} b| (the Z vectors
     // are not needed; the first one is scratch).
     const bool left = info->side == 1;
+    const double eta2 = info->reorth > 0 ? info->reorth * info->reorth : 0.5;   // DGKS threshold, squared
     double* tmp = Z;
     double znorm = bnorm;           // the stopping test's reference norm
     double beta;
@@ -773,10 +774,10 @@ static int fgmres(biot_ctx* c, const KrylovWork& K, const double* b_canon, doubl
             launch_gs_dots(V, n, nv, w, n, part, hd, hh, nullptr, st);
             if (fused) {
                 launch_gs_update_dots(w, V, n, nv, hd, n, part, hd + M + 2, hh ? hh + M + 2 : nullptr, hd + nv,
-                                      hd + kslot_flag(M), hflag, st);
+                                      hd + kslot_flag(M), hflag, st, eta2);
             } else {
                 launch_gs_update(w, V, n, nv, hd, n, part, hd + M + 2 + nv, hd + nv, hd + kslot_flag(M),
-                                 hh ? hh + M + 2 + nv : nullptr, nullptr, st);
+                                 hh ? hh + M + 2 + nv : nullptr, nullptr, st, eta2);
                 launch_gs_dots(V, n, nv, w, n, part, hd + M + 2, hh ? hh + M + 2 : nullptr, hd + kslot_flag(M), st);
                 if (hflag)
                     BIOT_HIP(hipMemcpyAsync(hflag, hd + kslot_flag(M), sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -1110,6 +1111,7 @@ int biot_solve(biot_ctx* c, const double* b, double* x, biot_solve_info* info, v
         require(info->maxit >= 0, "maxit >= 0");
         require(info->tol >= 0 && std::isfinite(info->tol), "tol >= 0");
         require(info->side == 0 || info->side == 1, "side: 0 (right) or 1 (left)");
+        require(info->reorth >= 0 && info->reorth <= 1, "reorth (the DGKS eta) in [0, 1]");
         krylov_alloc(c, info->restart, S(stream));
         return fgmres(c, context_work(c), b, x, info, S(stream));
     });
@@ -1125,6 +1127,7 @@ int biot_solve_noalloc(biot_ctx* c, const double* b, double* x, biot_solve_info*
         require(info->maxit >= 0, "maxit >= 0");
         require(info->tol >= 0 && std::isfinite(info->tol), "tol >= 0");
         require(info->side == 0 || info->side == 1, "side: 0 (right) or 1 (left)");
+        require(info->reorth >= 0 && info->reorth <= 1, "reorth (the DGKS eta) in [0, 1]");
         const long long len = c->levels[0]->L.len;
         const size_t need = noalloc_doubles(len, info->restart) * sizeof(double);
         if (need > NOALLOC_BYTES)

@@ -136,21 +136,21 @@ void launch_lincomb_add(double* x, const double* Z, long long ldz, int nv, const
                         hipStream_t st);
 // one classical Gram-Schmidt pass, each call two launches (partial sums, then a fixed-order
 // reduction; partial: max(RED_BLOCKS x (nv + 1), 4 RED_BLOCKS) doubles).  dots: out[q] = V_q . w,
-// out[nv] = w . w.  update: w -= V h, norm2 = w . w, flag (optional) = (norm2 < 0.5 prev).
+// out[nv] = w . w.  update: w -= V h, norm2 = w . w, flag (optional) = (norm2 < eta2 prev).
 // host: optional mirror of the outputs (mapped memory; flag goes to host[1]).  run_if: every
 // launch returns at once when *run_if == 0.
 void launch_gs_dots(const double* V, long long ldv, int nv, const double* w, long long n, double* partial,
                     double* out, double* host, const double* run_if, hipStream_t st);
 void launch_gs_update(double* w, const double* V, long long ldv, int nv, const double* h, long long n,
                       double* partial, double* norm2, const double* prev, double* flag, double* host,
-                      const double* run_if, hipStream_t st);
+                      const double* run_if, hipStream_t st, double eta2 = 0.5);
 // the first pass's update fused with the second pass's dot products (nv <= GS_FUSED): w -= V h,
-// out[q] = V_q . w (q < nv) and out[nv] = w . w of the new w; flag = (out[nv] < 0.5 prev),
+// out[q] = V_q . w (q < nv) and out[nv] = w . w of the new w; flag = (out[nv] < eta2 prev),
 // mirrored to host_flag; host: optional mirror of out.  Two launches.
 constexpr int GS_FUSED = 32;
 void launch_gs_update_dots(double* w, const double* V, long long ldv, int nv, const double* h, long long n,
                            double* partial, double* out, double* host, const double* prev, double* flag,
-                           double* host_flag, hipStream_t st);
+                           double* host_flag, hipStream_t st, double eta2 = 0.5);
 // dst = src / sqrt(*na), or / sqrt(*nb) when sel != nullptr and *sel != 0
 void launch_normalize(double* dst, const double* src, long long n, const double* na, const double* nb,
                       const double* sel, hipStream_t st);

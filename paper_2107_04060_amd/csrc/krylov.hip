@@ -133,14 +133,14 @@ __global__ __launch_bounds__(256) void k_gs_fused(double* __restrict__ w, const 
 }
 
 // out[q] = sum_b partial[q * np + b], one block per q (fixed order); host: optional mirror.
-// flag (optional): set by the block of q == flag_q to 1 when out[flag_q] < 0.5 * prev (the
-// Daniel-Gragg-Kaufman-Stewart test for a second orthogonalization pass, eta = 1/sqrt(2)), and
-// mirrored to *host_flag when given.
+// flag (optional): set by the block of q == flag_q to 1 when out[flag_q] < eta2 * prev (the
+// Daniel-Gragg-Kaufman-Stewart test for a second orthogonalization pass on squared norms,
+// eta2 = eta^2, eta = 1/sqrt(2) by default), and mirrored to *host_flag when given.
 __global__ __launch_bounds__(256) void k_gs_reduce(const double* __restrict__ partial, int np,
                                                    double* __restrict__ out, double* __restrict__ host,
                                                    const double* __restrict__ prev, double* __restrict__ flag,
                                                    double* __restrict__ host_flag, int flag_q,
-                                                   const double* run_if) {
+                                                   const double* run_if, double eta2) {
     if (run_if && *run_if == 0.0) return;
     __shared__ double wred[4];
     const int q = blockIdx.x;
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(256) void k_gs_reduce(const double* __restrict__ pa
         out[q] = r;
         if (host) host[q] = r;
         if (flag && q == flag_q) {
-            const double f = (r < 0.5 * (*prev)) ? 1.0 : 0.0;
+            const double f = (r < eta2 * (*prev)) ? 1.0 : 0.0;
             *flag = f;
             if (host_flag) *host_flag = f;
         }
@@ -172,25 +172,25 @@ void launch_gs_dots(const double* V, long long ldv, int nv, const double* w, lon
     else
         hipLaunchKernelGGL(k_gs_dots, dim3(np), dim3(256), 0, st, V, ldv, nv, w, n, partial, run_if);
     hipLaunchKernelGGL(k_gs_reduce, dim3(nv + 1), dim3(256), 0, st, partial, np, out, host, nullptr,
-                       nullptr, nullptr, 0, run_if);
+                       nullptr, nullptr, 0, run_if, 0.0);
 }
 
 void launch_gs_update(double* w, const double* V, long long ldv, int nv, const double* h, long long n,
                       double* partial, double* norm2, const double* prev, double* flag, double* host,
-                      const double* run_if, hipStream_t st) {
+                      const double* run_if, hipStream_t st, double eta2) {
     hipLaunchKernelGGL(k_gs_update, dim3(UPD_BLOCKS), dim3(256), 0, st, w, V, ldv, nv, h, n, partial, run_if);
     hipLaunchKernelGGL(k_gs_reduce, dim3(1), dim3(256), 0, st, partial, UPD_BLOCKS, norm2, host, prev, flag,
-                       host ? host + 1 : nullptr, 0, run_if);
+                       host ? host + 1 : nullptr, 0, run_if, eta2);
 }
 
 void launch_gs_update_dots(double* w, const double* V, long long ldv, int nv, const double* h, long long n,
                            double* partial, double* out, double* host, const double* prev, double* flag,
-                           double* host_flag, hipStream_t st) {
+                           double* host_flag, hipStream_t st, double eta2) {
     if (nv < 1 || nv > GS_FUSED) throw ArgError{"fused Gram-Schmidt pass: 1 <= nv <= GS_FUSED"};
     hipLaunchKernelGGL(k_gs_fused<true>, dim3(FUSED_BLOCKS), dim3(256), 0, st, w, V, ldv, nv, h, n, partial,
                        nullptr);
     hipLaunchKernelGGL(k_gs_reduce, dim3(nv + 1), dim3(256), 0, st, partial, FUSED_BLOCKS, out, host, prev, flag,
-                       host_flag, nv, nullptr);
+                       host_flag, nv, nullptr, eta2);
 }
 
 // dst = src / sqrt(*na), or / sqrt(*nb) when sel != nullptr and *sel != 0

@@ -50,3 +50,26 @@ def test_restart_beyond_fused_bound(binding, reference, precision):
         assert abs(info["iters"] - io["iters"]) <= 1
     else:
         assert info["iters"] <= io["iters"] + 3
+
+
+@pytest.mark.parametrize("reorth", [1.0, 1e-12])
+@pytest.mark.parametrize("restart", [30, 60])
+def test_gram_schmidt_threshold(binding, reference, reorth, restart):
+    """The second Gram-Schmidt pass always (reorth = 1: |w_1| <= |w_0| always holds) and never
+    (1e-12), on the fused (restart 30) and the unfused (60) paths: both converge in the oracle's
+    iteration count (+-1) for the oracle's restart, and the true residual is recomputed here."""
+    A, b, io = reference
+    if restart == 30:
+        H = Hierarchy(N, params("stiff"), K_tri=K, smoother="bsr", omega=OM, omega_J=OMJ, nu1=1, nu2=1,
+                      levels=LEVELS)
+        _, io = fgmres(H.A, b, H.vcycle, tol=1e-8, restart=30, maxit=300)
+    s = solver(binding, torch, N, "stiff", K, levels=LEVELS, smoother="bsr", nu=1, omega=OM, omega_J=OMJ)
+    x, info = s.solve(torch.tensor(b, dtype=torch.float64, device="cuda"), tol=1e-8, restart=restart, maxit=300,
+                      reorth=reorth)
+    s.close()
+    x = x.cpu().numpy()
+    print("  reorth %g restart %d: gpu %d iterations, oracle %d" % (reorth, restart, info["iters"], io["iters"]),
+          flush=True)
+    assert info["converged"]
+    assert np.linalg.norm(b - A @ x) <= 1e-8 * np.linalg.norm(b) * (1 + 1e-6)
+    assert abs(info["iters"] - io["iters"]) <= 1
