@@ -159,13 +159,14 @@ __host__ __device__ inline void patch_factor(const DevPatchClass<T>& pc, const T
 
 // rr(s): the patch residual at slot s (absent slots hold 0), read where each phase needs it (an
 // array, or the staged residual in LDS, so that it need not stay in registers); f: the patch's
-// factors (patch_factor); out[a * ostride], a = 0..19.  with_mean = false omits the star-mean
+// factors (patch_factor); out[a * ostride], a = 0..19, of any type O the values convert to (the
+// caller's registers, or the corrections in LDS).  with_mean = false omits the star-mean
 // pressure term (the deflated solve).  ALLP: every slot of the patch is present (interior
 // class), known at compile time.
 // With W = L L^T: Q W^-1 r_w = Q y for y = L^-T L^-1 r_w, and x_w = L^-T L^-1 (r_w - Q^T x_p):
 // four substitutions with L, none with a division, and Q read from the class data.
-template <typename T, bool ALLP = false, typename RR>
-__host__ __device__ inline void patch_apply(RR&& rr, const DevPatchClass<T>& pc, const PatchFac<T>& f, T* out,
+template <typename T, bool ALLP = false, typename RR, typename O>
+__host__ __device__ inline void patch_apply(RR&& rr, const DevPatchClass<T>& pc, const PatchFac<T>& f, O* out,
                                             int ostride, bool with_mean = true) {
     T y[6];
 #pragma unroll
@@ -217,7 +218,7 @@ __host__ __device__ inline void patch_apply(RR&& rr, const DevPatchClass<T>& pc,
         for (int b = 0; b < 8; ++b) v += pc.Ainv[a][b] * rr(b);
 #pragma unroll
         for (int q = 0; q < 6; ++q) v -= pc.H[a][q] * xp[q];
-        out[a * ostride] = (ALLP || pc.present[a]) ? v : (T)0;
+        out[a * ostride] = (O)((ALLP || pc.present[a]) ? v : (T)0);
     }
     BIOT_PHASE_FENCE();
     // x_w = W^-1 (r_w - Q^T x_p)
@@ -232,10 +233,10 @@ __host__ __device__ inline void patch_apply(RR&& rr, const DevPatchClass<T>& pc,
     fwd6p(f.w, xw);
     bwd6p(f.w, xw);
 #pragma unroll
-    for (int a = 0; a < 6; ++a) out[(8 + a) * ostride] = (ALLP || pc.present[8 + a]) ? xw[a] : (T)0;
+    for (int a = 0; a < 6; ++a) out[(8 + a) * ostride] = (O)((ALLP || pc.present[8 + a]) ? xw[a] : (T)0);
 #pragma unroll
     for (int q = 0; q < 6; ++q)
-        out[(14 + q) * ostride] = (ALLP || pc.present[14 + q]) ? xp[q] + (with_mean ? gamma : (T)0) : (T)0;
+        out[(14 + q) * ostride] = (O)((ALLP || pc.present[14 + q]) ? xp[q] + (with_mean ? gamma : (T)0) : (T)0);
 }
 
 // rr: patch residual (absent slots hold 0); kv: 1/K of the six star triangles;

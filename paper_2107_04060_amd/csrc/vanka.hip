@@ -440,11 +440,11 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
     }
 }
 
-template <typename T, typename P, bool UNIFORM, bool ZERO, int NCLS, bool PROL, int NZ>
 // Two waves per SIMD for the per-patch eliminations (two tiles per CU, one tile's latency-bound
 // phases overlapping the other's): in FP64 the compiler then keeps about 50 of the elimination's
 // values in scratch, which costs less than the second tile gains (768 us against 1092 us per
 // colour step at 2048^2 with one wave per SIMD).
+template <typename T, typename P, bool UNIFORM, bool ZERO, int NCLS, bool PROL, int NZ>
 __global__ __launch_bounds__(TPB * NZ, NZ == 2 ? 4 : 2) void k_vanka_step(const T* __restrict__ x_in, const T* __restrict__ b,
                                                     T* __restrict__ x_out, Layout L, const T* __restrict__ kinv,
                                                     T kinv_s, const T* __restrict__ coef,
