@@ -11,7 +11,8 @@
  * symmetric saddle-point matrix
  *     A = [[A_u^RQ, 0, alpha B_u^T], [0, tau M_w, tau B_w^T], [alpha B_u, tau B_w, -(1/M) M_p]]
  * with A_u^RQ = 2 mu A_eps + lambda B_u^T M_p^{-1} B_u (Appendix A), Dirichlet data u = 0
- * and w.n = 0 on the whole boundary (those DoFs are eliminated).
+ * and w.n = 0 on the whole boundary (those DoFs are eliminated), or the mixed conditions of
+ * Terzaghi's column (Sec. 5; biot_problem.bc).
  *
  * Solver (Sec. 3 and 5.1): FGMRES (right preconditioned, flexible, x0 = 0) with one
  * monolithic geometric-multigrid V(nu1, nu2) cycle as preconditioner: rediscretized
@@ -26,7 +27,7 @@
  * each block row-major in (j, i); H(i,j) is the edge (i,j)-(i+1,j) with unit normal +y,
  * V(i,j) the edge (i,j)-(i,j+1) with normal +x, D(i,j) the diagonal (i,j+1)-(i+1,j)
  * with normal (1,1)/sqrt(2); L(i,j) = {(i,j),(i+1,j),(i,j+1)}, U(i,j) = {(i+1,j),
- * (i+1,j+1),(i,j+1)}.  Length 10 n^2 - 8 n + 2.  Bubble DoFs are normal displacements
+ * (i+1,j+1),(i,j+1)}.  Length 10 n^2 - 8 n + 2 (BIOT_BC_TERZAGHI: biot_problem.bc).  Bubble DoFs are normal displacements
  * at edge midpoints (basis 4 l_p l_q n_e), RT0 DoFs normal fluxes (normal component 1).
  * Per-triangle arrays are ordered [L(j n + i) for all cells, then U(j n + i)].
  *
@@ -66,6 +67,9 @@ extern "C" {
 #define BIOT_SMOOTHER_VANKA 0     /* additive Vanka, 20-DoF vertex patches (Sec. 3.2.1)  */
 #define BIOT_SMOOTHER_BSR 1       /* inexact Braess-Sarazin (Sec. 3.2.2, Appendix D)     */
 
+#define BIOT_BC_DIRICHLET 0      /* u = 0 and w.n = 0 on the whole boundary (Sec. 5.1)  */
+#define BIOT_BC_TERZAGHI 1       /* Terzaghi's column (Sec. 5): see biot_problem.bc       */
+
 #define BIOT_PREC_FP64 0          /* whole preconditioner in FP64                         */
 #define BIOT_PREC_FP32_SMOOTHER 1 /* V-cycle vectors, residuals and transfers in FP32;
                                      patch solves and the coarsest solve in FP64 arithmetic;
@@ -95,6 +99,21 @@ typedef struct {
     const double* K_tri;/* device pointer to 2 n^2 per-triangle permeabilities (> 0), or NULL;
                            read during biot_assemble only, checked on the device as in
                            biot_update_K                                                     */
+    int bc;             /* boundary conditions (0 = BIOT_BC_DIRICHLET, as above).
+                           BIOT_BC_TERZAGHI: the column of Sec. 5 (Terzaghi's problem), loaded and
+                           drained on x = 0 (natural: u, the bubbles and w.n of that face are
+                           free; the traction and the zero pressure enter through the right-hand
+                           side), fixed and impermeable on x = 1 (u = 0, w.n = 0), rollers on
+                           y = 0 and y = 1 (u_y = 0, bubble and w.n of their edges 0).  The
+                           canonical order is then [u_x (vertices with i < n), u_y (i < n,
+                           0 < j < n), b_H (0 < j < n), b_V (i < n), b_D (all), w_H, w_V, w_D (as
+                           b), p_L, p_U], each block row-major in (j, i): the full numbering with
+                           the eliminated DoFs skipped, length 10 n^2 - 2 n.  1/M = 0 (M =
+                           infinity) is allowed, n <= 256.  This path runs on compressed-row
+                           operators and explicit patch inverses (natural boundaries break the
+                           translation-invariant stencil of the Dirichlet path): additive Vanka in
+                           FP64 only; biot_solve_noalloc, biot_grad_logK, biot_kernel_timing and
+                           the patch table of biot_export_layout return BIOT_ERR_ARG.          */
 } biot_problem;
 
 /* Multigrid options (Sec. 3, 4.3, 5.1). */
@@ -141,6 +160,12 @@ typedef struct {
                            coarse correction again, so only gamma_from <= l < gamma_to repeat
                            (below gamma_to the cycle is a V-cycle, visited as often as level
                            gamma_to)                                                          */
+    double vanka_shift; /* bc = BIOT_BC_TERZAGHI: every Vanka patch matrix is shifted on its
+                           diagonal, + vanka_shift on the displacement and Darcy entries and
+                           - vanka_shift on the pressure entries (a small compressibility; Sec. 5,
+                           Terzaghi's problem, shifts the blocks by 1e-8 because with 1/M = 0 an
+                           interior patch matrix is singular, so vanka_shift > 0 is required
+                           there); 0 with BIOT_BC_DIRICHLET                                   */
 } biot_mg_opts;
 
 /* FGMRES controls (in) and results (out). */

@@ -22,6 +22,7 @@ BIOT_ERR_NAN = -5
 SMOOTHERS = {"vanka": 0, "bsr": 1}
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_patch": 2}
 SIDES = {"right": 0, "left": 1}
+BCS = {"dirichlet": 0, "terzaghi": 1}
 
 _lib = None
 
@@ -35,7 +36,8 @@ class BiotError(RuntimeError):
 class Problem(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("lambda_", ctypes.c_double), ("mu", ctypes.c_double),
                 ("alpha", ctypes.c_double), ("inv_M", ctypes.c_double), ("mu_f", ctypes.c_double),
-                ("tau", ctypes.c_double), ("K_scalar", ctypes.c_double), ("K_tri", ctypes.c_void_p)]
+                ("tau", ctypes.c_double), ("K_scalar", ctypes.c_double), ("K_tri", ctypes.c_void_p),
+                ("bc", ctypes.c_int)]
 
 
 class MGOpts(ctypes.Structure):
@@ -43,7 +45,8 @@ class MGOpts(ctypes.Structure):
                 ("nu2", ctypes.c_int), ("omega", ctypes.c_double), ("omega_J", ctypes.c_double),
                 ("precision", ctypes.c_int), ("schur_sweeps", ctypes.c_int), ("omega_S", ctypes.c_double),
                 ("gamma", ctypes.c_int), ("vanka_colors", ctypes.c_int), ("schur_cg", ctypes.c_int),
-                ("gamma_from", ctypes.c_int), ("fcycle", ctypes.c_int), ("gamma_to", ctypes.c_int)]
+                ("gamma_from", ctypes.c_int), ("fcycle", ctypes.c_int), ("gamma_to", ctypes.c_int),
+                ("vanka_shift", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -106,18 +109,23 @@ def _dev(t, n=None, name="vector"):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def n_free(n):
-    return 10 * n * n - 8 * n + 2
+def n_free(n, bc="dirichlet"):
+    """Free DoFs of the n x n mesh: 10 n^2 - 8 n + 2 (Dirichlet), 10 n^2 - 2 n (Terzaghi)."""
+    return 10 * n * n - 8 * n + 2 if bc == "dirichlet" else 10 * n * n - 2 * n
 
 
 class BiotSolver:
     """One assembled RQ Biot system with its multigrid hierarchy on the current device."""
 
-    def __init__(self, n, lam, mu, alpha=1.0, M=1e6, mu_f=1.0, tau=1.0, K=1.0):
+    def __init__(self, n, lam, mu, alpha=1.0, M=1e6, mu_f=1.0, tau=1.0, K=1.0, bc="dirichlet"):
+        """bc: "dirichlet" (u = 0, w.n = 0 on the whole boundary) or "terzaghi" (the column of
+        Sec. 5; M = float("inf") allowed)."""
         lib = load()
         self.n = int(n)
+        self.bc = bc
         prob = Problem()
         prob.n = self.n
+        prob.bc = BCS[bc]
         prob.lambda_ = float(lam)
         prob.mu = float(mu)
         prob.alpha = float(alpha)
@@ -150,14 +158,14 @@ class BiotSolver:
             pass
 
     def nf(self, level=0):
-        return n_free(self.n >> level)
+        return n_free(self.n >> level, self.bc)
 
     def setup(self, levels, smoother="vanka", nu1=2, nu2=2, omega=0.8, omega_J=1.0, precision="fp64",
               schur_sweeps=1, omega_S=1.0, gamma=1, vanka_colors=0, schur_cg=0, gamma_from=0, fcycle=False,
-              gamma_to=0):
+              gamma_to=0, vanka_shift=0.0):
         o = MGOpts(int(levels), SMOOTHERS[smoother], int(nu1), int(nu2), float(omega), float(omega_J),
                    PRECISIONS[precision], int(schur_sweeps), float(omega_S), int(gamma), int(vanka_colors),
-                   int(schur_cg), int(gamma_from), int(bool(fcycle)), int(gamma_to))
+                   int(schur_cg), int(gamma_from), int(bool(fcycle)), int(gamma_to), float(vanka_shift))
         _check(load().biot_setup_hierarchy(self._ctx, ctypes.byref(o), _stream()))
         self.levels = int(levels)
         return self

@@ -6,7 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbiot_mg.so")
-SOURCES = ["kernels.hip", "vanka.hip", "bsr.hip", "transfer.hip", "krylov.hip", "api.hip", "host_tables.cpp"]
+SOURCES = ["kernels.hip", "vanka.hip", "bsr.hip", "transfer.hip", "krylov.hip", "sparse.hip", "api.hip",
+           "host_tables.cpp", "sparse_host.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed-FP32 instructions in generated code

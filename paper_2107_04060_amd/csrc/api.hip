@@ -8,6 +8,7 @@
 #include "common.h"
 #include "kernels.h"
 #include "patch_solve.h"
+#include "sparse.h"
 #include "structure.h"
 
 #include <algorithm>
@@ -118,6 +119,28 @@ LevelView<float> Level::view<float>() const {
     return v;
 }
 
+// One level of the general-boundary path (sparse.h): the CSR operator with its assembly lists,
+// the transfers to the next coarser level, the explicit Vanka patch inverses and work vectors,
+// all in the compact free-DoF order of the level.
+struct SpLevel {
+    FreeMap map;
+    int N = 0, nnz = 0, np = 0;
+    DevBuf ptr, col, val, val0, kptr, ktri, kcoef;  // A_l (CSR) and its assembly lists
+    DevBuf kinv;                                    // 2 n^2 per-triangle 1/K
+    DevBuf pptr, pcol, pval;                        // P from the next coarser level (rows: this level)
+    DevBuf rptr, rcol, rval;                        // R = P^T (rows: the next coarser level)
+    DevBuf slots, inv, y, dptr, dlist, wgt;         // additive Vanka: patches, inverses, corrections,
+                                                    // DoF -> (patch, slot) lists, weights D = 1/count
+    DevBuf x, b, r;                                 // iterate, right-hand side, residual
+};
+
+struct SpHier {
+    int bc = 0;
+    std::vector<std::unique_ptr<SpLevel>> lv;       // lv[0] after assembly; the rest after set-up
+    int cN = 0;                                     // coarsest level: dense inverse
+    DevBuf cA, cinv, ccol, cidx, status;
+};
+
 }  // namespace biot
 
 using namespace biot;
@@ -130,6 +153,8 @@ struct biot_ctx {
     bool have_hierarchy = false;
     biot_mg_opts opts{};
     std::vector<std::unique_ptr<Level>> levels;   // levels[0] always exists after assemble
+                                                  // (structured path; empty with sp)
+    std::unique_ptr<SpHier> sp;                   // general-boundary path (bc != Dirichlet)
     // transfers: prolongation weights (structure.h)
     DevBuf pw64, pw32;
     // coarsest level
@@ -569,9 +594,215 @@ static T* vcycle_level(biot_ctx* c, int l, const T* b, T* buf0, T* buf1, hipStre
     return cur;
 }
 
-// z = M^{-1} v on padded FP64 vectors of level 0 (v is not modified; z is zero on absent DoFs
+// ---- general-boundary path (sparse.h) -----------------------------------------------------------
+// Level l of the path: numbering, CSR pattern and assembly lists, per-triangle 1/K and work vectors.
+static void sp_level_alloc(SpLevel& L, int n, int bc, const PhysParams& p, hipStream_t st) {
+    L.map = make_free_map(n, bc);
+    OperatorHost op = build_operator(L.map, p);
+    L.N = L.map.N;
+    L.nnz = (int)op.A.col.size();
+    upload(L.ptr, op.A.ptr, st);
+    upload(L.col, op.A.col, st);
+    upload(L.val0, op.A.val, st);
+    upload(L.kptr, op.kptr, st);
+    upload(L.ktri, op.ktri, st);
+    upload(L.kcoef, op.kcoef, st);
+    L.val.alloc((size_t)std::max(1, L.nnz) * sizeof(double));
+    L.kinv.alloc((size_t)2 * n * n * sizeof(double));
+    for (DevBuf* b : {&L.x, &L.b, &L.r}) {
+        b->alloc((size_t)L.N * sizeof(double));
+        launch_fill(b->as<double>(), L.N, 0.0, st);
+    }
+    BIOT_HIP(hipStreamSynchronize(st));   // the host tables above go out of scope
+}
+
+// transfers between level l (fine) and l + 1, and the Vanka patches of level l
+static void sp_level_links(SpLevel& F, const SpLevel& C, hipStream_t st) {
+    const CsrHost P = build_prolongation(F.map, C.map);
+    const CsrHost R = csr_transpose(P);
+    upload(F.pptr, P.ptr, st);
+    upload(F.pcol, P.col, st);
+    upload(F.pval, P.val, st);
+    upload(F.rptr, R.ptr, st);
+    upload(F.rcol, R.col, st);
+    upload(F.rval, R.val, st);
+    const std::vector<int> slots = build_patches(F.map);
+    F.np = (int)(slots.size() / PATCH);
+    // DoF -> (patch, slot) lists in patch order (a fixed summation order) and D = 1 / count
+    std::vector<int> dptr((size_t)F.N + 1, 0), dlist;
+    for (int q : slots)
+        if (q >= 0) ++dptr[(size_t)q + 1];
+    for (int d = 0; d < F.N; ++d) dptr[(size_t)d + 1] += dptr[d];
+    dlist.resize((size_t)dptr[F.N]);
+    std::vector<int> fill(dptr.begin(), dptr.end() - 1);
+    for (size_t e = 0; e < slots.size(); ++e)
+        if (slots[e] >= 0) dlist[(size_t)fill[slots[e]]++] = (int)e;
+    std::vector<double> wgt((size_t)F.N);
+    for (int d = 0; d < F.N; ++d) {
+        const int cnt = dptr[(size_t)d + 1] - dptr[d];
+        if (cnt == 0) throw std::runtime_error("a free DoF lies in no Vanka patch");
+        wgt[d] = 1.0 / cnt;
+    }
+    upload(F.slots, slots, st);
+    upload(F.dptr, dptr, st);
+    upload(F.dlist, dlist, st);
+    upload(F.wgt, wgt, st);
+    F.inv.alloc((size_t)std::max(1, F.np) * PATCH * PATCH * sizeof(double));
+    F.y.alloc((size_t)std::max(1, F.np) * PATCH * sizeof(double));
+    BIOT_HIP(hipStreamSynchronize(st));   // the host tables above go out of scope
+}
+
+// 1/K of every level from the finest level's field (mode 0: K_tri, or the scalar when null;
+// mode 1: theta = ln K), then the operator values of every level
+static void sp_assemble(biot_ctx* c, const double* field, int mode, hipStream_t st) {
+    SpHier& H = *c->sp;
+    launch_kinv_flat(2LL * c->n * c->n, field, c->K_scalar, mode, H.lv[0]->kinv.as<double>(), st);
+    for (size_t l = 1; l < H.lv.size(); ++l)
+        launch_kinv_coarsen_flat(c->n >> l, H.lv[l - 1]->kinv.as<double>(), H.lv[l]->kinv.as<double>(), st);
+    for (auto& lp : H.lv)
+        launch_csr_assemble(lp->nnz, lp->val0.as<double>(), lp->kptr.as<int>(), lp->ktri.as<int>(),
+                            lp->kcoef.as<double>(), lp->kinv.as<double>(), lp->val.as<double>(), st);
+}
+
+// the permeability-dependent set-up of the hierarchy: patch inverses and the coarsest inverse
+static void sp_factor(biot_ctx* c, hipStream_t st) {
+    SpHier& H = *c->sp;
+    int* status = H.status.as<int>();
+    BIOT_HIP(hipMemsetAsync(status, 0, sizeof(int), st));
+    for (size_t l = 0; l + 1 < H.lv.size(); ++l) {
+        SpLevel& L = *H.lv[l];
+        launch_patch_inverse(L.np, L.slots.as<int>(), L.ptr.as<int>(), L.col.as<int>(), L.val.as<double>(),
+                             c->opts.vanka_shift, L.inv.as<double>(), status, st);
+    }
+    check_stream_error();
+    int bad = 0;
+    BIOT_HIP(hipMemcpyAsync(&bad, status, sizeof(int), hipMemcpyDeviceToHost, st));
+    BIOT_HIP(hipStreamSynchronize(st));
+    if (bad) throw SingularError{"a Vanka patch matrix is singular (with 1/M = 0 set vanka_shift > 0)"};
+    SpLevel& C = *H.lv.back();
+    launch_csr_to_dense(H.cN, C.ptr.as<int>(), C.col.as<int>(), C.val.as<double>(), H.cA.as<double>(), st);
+    launch_gauss_jordan(H.cA.as<double>(), H.cinv.as<double>(), H.cN, H.ccol.as<double>(), status, st);
+    check_stream_error();
+    BIOT_HIP(hipMemcpyAsync(&bad, status, sizeof(int), hipMemcpyDeviceToHost, st));
+    BIOT_HIP(hipStreamSynchronize(st));
+    if (bad) throw SingularError{"coarsest-level operator is singular"};
+}
+
+static void sp_setup(biot_ctx* c, const biot_mg_opts* o, hipStream_t st) {
+    SpHier& H = *c->sp;
+    c->have_hierarchy = false;
+    H.lv.resize(1);
+    for (int l = 1; l < o->levels; ++l) {
+        H.lv.emplace_back(new SpLevel);
+        sp_level_alloc(*H.lv[l], c->n >> l, H.bc, c->phys, st);
+    }
+    for (int l = 0; l + 1 < o->levels; ++l) sp_level_links(*H.lv[l], *H.lv[l + 1], st);
+    H.cN = H.lv.back()->N;
+    H.cA.alloc((size_t)H.cN * H.cN * sizeof(double));
+    H.cinv.alloc((size_t)H.cN * H.cN * sizeof(double));
+    H.ccol.alloc((size_t)H.cN * sizeof(double));
+    std::vector<int> idx((size_t)H.cN);
+    for (int k = 0; k < H.cN; ++k) idx[k] = k;
+    upload(H.cidx, idx, st);
+    H.status.alloc(sizeof(int));
+    c->opts = *o;
+    if (c->opts.gamma < 1) c->opts.gamma = 1;
+    // coarse 1/K from the finest level's (still in lv[0].kinv), then every operator
+    for (size_t l = 1; l < H.lv.size(); ++l)
+        launch_kinv_coarsen_flat(c->n >> l, H.lv[l - 1]->kinv.as<double>(), H.lv[l]->kinv.as<double>(), st);
+    for (size_t l = 1; l < H.lv.size(); ++l) {
+        SpLevel& L = *H.lv[l];
+        launch_csr_assemble(L.nnz, L.val0.as<double>(), L.kptr.as<int>(), L.ktri.as<int>(), L.kcoef.as<double>(),
+                            L.kinv.as<double>(), L.val.as<double>(), st);
+    }
+    sp_factor(c, st);
+    c->have_hierarchy = true;
+}
+
+// y = A_l x (mode 0) or y = b - A_l x (mode 1) on compact vectors of level l
+static void sp_apply(biot_ctx* c, int l, const double* x, const double* b, double* y, int mode, hipStream_t st) {
+    SpLevel& L = *c->sp->lv[l];
+    launch_csr_mv(L.N, L.ptr.as<int>(), L.col.as<int>(), L.val.as<double>(), x, mode == 1 ? b : nullptr, y,
+                  mode == 1 ? -1.0 : 1.0, 1.0, st);
+}
+
+// one additive Vanka step x <- x + omega sum_l V_l^T D_l A_l^{-1} V_l (b - A x) in place
+// (zero: x = 0 on entry, the residual is b)
+static void sp_smooth(biot_ctx* c, int l, double* x, const double* b, bool zero, hipStream_t st) {
+    SpLevel& L = *c->sp->lv[l];
+    const double* r = b;
+    if (!zero) {
+        sp_apply(c, l, x, b, L.r.as<double>(), 1, st);
+        r = L.r.as<double>();
+    }
+    launch_patch_apply(L.np, L.slots.as<int>(), L.inv.as<double>(), r, L.y.as<double>(), st);
+    launch_patch_gather(L.N, L.dptr.as<int>(), L.dlist.as<int>(), L.y.as<double>(), L.wgt.as<double>(),
+                        c->opts.omega, zero ? nullptr : x, x, st);
+}
+
+// The cycle on level l for A_l x = b, from x = 0 (zero) or from the iterate in x, result in x
+// (b != x).  The coarse problem lives in the next level's b and x; a repeated coarse visit
+// continues from the coarse iterate (the same as a cycle on the remaining residual, added).
+static void sp_cycle(biot_ctx* c, int l, const double* b, double* x, bool zero, bool vonly, hipStream_t st) {
+    SpHier& H = *c->sp;
+    const int nl = (int)H.lv.size();
+    if (l == nl - 1) {
+        launch_coarse_solve<double>(H.cinv.as<double>(), H.cN, H.cidx.as<int>(), b, x, st);
+        return;
+    }
+    const biot_mg_opts& o = c->opts;
+    SpLevel& L = *H.lv[l];
+    SpLevel& C = *H.lv[l + 1];
+    bool z = zero;
+    for (int s = 0; s < o.nu1; ++s, z = false) sp_smooth(c, l, x, b, z, st);
+    if (z) launch_fill(x, L.N, 0.0, st);
+    sp_apply(c, l, x, b, L.r.as<double>(), 1, st);
+    launch_csr_mv(C.N, L.rptr.as<int>(), L.rcol.as<int>(), L.rval.as<double>(), L.r.as<double>(), nullptr,
+                  C.b.as<double>(), 1.0, 0.0, st);
+    sp_cycle(c, l + 1, C.b.as<double>(), C.x.as<double>(), true, vonly, st);
+    const bool repeat = !vonly && l + 1 < nl - 1 && l >= o.gamma_from && (o.gamma_to <= 0 || l < o.gamma_to);
+    if (repeat)
+        for (int g = 1; g < o.gamma; ++g) sp_cycle(c, l + 1, C.b.as<double>(), C.x.as<double>(), false, o.fcycle != 0, st);
+    launch_csr_mv(L.N, L.pptr.as<int>(), L.pcol.as<int>(), L.pval.as<double>(), C.x.as<double>(), x, x, 1.0, 1.0, st);
+    for (int s = 0; s < o.nu2; ++s) sp_smooth(c, l, x, b, false, st);
+}
+
+// vector length of the Krylov solve: padded finest level, or the compact free DoFs
+static long long vec_len(biot_ctx* c) { return c->sp ? (long long)c->sp->lv[0]->N : c->levels[0]->L.len; }
+
+static void vec_pack(biot_ctx* c, const double* canon, double* v, hipStream_t st) {
+    if (c->sp) {
+        BIOT_HIP(hipMemcpyAsync(v, canon, (size_t)vec_len(c) * sizeof(double), hipMemcpyDeviceToDevice, st));
+    } else {
+        Level& l0 = *c->levels[0];
+        launch_pack(canon, v, l0.L, l0.C, st);
+    }
+}
+
+static void vec_unpack(biot_ctx* c, const double* v, double* canon, hipStream_t st) {
+    if (c->sp) {
+        BIOT_HIP(hipMemcpyAsync(canon, v, (size_t)vec_len(c) * sizeof(double), hipMemcpyDeviceToDevice, st));
+    } else {
+        Level& l0 = *c->levels[0];
+        launch_unpack(v, canon, l0.L, l0.C, st);
+    }
+}
+
+// y = A x (mode 0) or b - A x (mode 1) on the finest level's Krylov vectors
+static void vec_apply(biot_ctx* c, const double* x, const double* b, double* y, int mode, hipStream_t st) {
+    if (c->sp)
+        sp_apply(c, 0, x, b, y, mode, st);
+    else
+        launch_apply<double>(c->levels[0]->view<double>(), x, b, y, mode, st);
+}
+
+// z = M^{-1} v on the Krylov vectors of level 0 (v is not modified; z is zero on absent DoFs
 // and may be used as an iterate buffer).
 static void precond(biot_ctx* c, const double* v, double* z, hipStream_t st) {
+    if (c->sp) {
+        sp_cycle(c, 0, v, z, true, false, st);
+        return;
+    }
     Level& l0 = *c->levels[0];
     if (c->opts.precision == BIOT_PREC_FP64) {
         // start in the buffer that makes the last step land in z
@@ -622,19 +853,19 @@ static size_t host_work_doubles(int m) { return (size_t)(m + 1) * m + 3 * (size_
 
 static void krylov_alloc(biot_ctx* c, int m, hipStream_t st) {
     if (c->krylov_m >= m) return;
-    const Layout& L = c->levels[0]->L;
-    c->V.alloc((size_t)(m + 1) * L.len * sizeof(double));
-    c->Z.alloc((size_t)m * L.len * sizeof(double));
+    const long long len = vec_len(c);
+    c->V.alloc((size_t)(m + 1) * len * sizeof(double));
+    c->Z.alloc((size_t)m * len * sizeof(double));
     // absent DoFs stay zero in every Krylov vector (the kernels never write them)
-    launch_fill(c->V.as<double>(), (long long)(m + 1) * L.len, 0.0, st);
-    launch_fill(c->Z.as<double>(), (long long)m * L.len, 0.0, st);
-    c->w.alloc((size_t)L.len * sizeof(double));
-    launch_fill(c->w.as<double>(), L.len, 0.0, st);
+    launch_fill(c->V.as<double>(), (long long)(m + 1) * len, 0.0, st);
+    launch_fill(c->Z.as<double>(), (long long)m * len, 0.0, st);
+    c->w.alloc((size_t)len * sizeof(double));
+    launch_fill(c->w.as<double>(), len, 0.0, st);
     c->partial.alloc((size_t)RED_BLOCKS * std::max(m + 2, 4) * sizeof(double));
     c->hdev.alloc((size_t)kslots(m) * sizeof(double));
     c->ydev.alloc((size_t)(m + 1) * sizeof(double));
-    c->bpad.alloc((size_t)L.len * sizeof(double));
-    c->xpad.alloc((size_t)L.len * sizeof(double));
+    c->bpad.alloc((size_t)len * sizeof(double));
+    c->xpad.alloc((size_t)len * sizeof(double));
     if (c->hhost) BIOT_HIP(hipHostFree(c->hhost));
     c->hhost = nullptr;
     BIOT_HIP(hipHostMalloc((void**)&c->hhost, (size_t)kslots(m) * sizeof(double),
@@ -678,9 +909,7 @@ static double norm2_dev(const KrylovWork& k, const double* a, long long n, hipSt
 
 static int fgmres(biot_ctx* c, const KrylovWork& K, const double* b_canon, double* x_canon, biot_solve_info* info,
                   hipStream_t st) {
-    Level& l0 = *c->levels[0];
-    const Layout& L = l0.L;
-    const long long n = L.len;
+    const long long n = vec_len(c);
     const int m = info->restart;
     const int M = K.M;                        // layout of the result slots
     if (m > M) throw ArgError{"restart exceeds the Krylov workspace"};
@@ -693,7 +922,7 @@ static int fgmres(biot_ctx* c, const KrylovWork& K, const double* b_canon, doubl
     double* hh = K.hh;
     const double* hres = K.hres;
     double* part = K.partial;
-    launch_pack(b_canon, b, L, l0.C, st);
+    vec_pack(c, b_canon, b, st);
     launch_fill(x, n, 0.0, st);
     const double bnorm = std::sqrt(norm2_dev(K, b, n, st));
     info->iters = 0;
@@ -702,7 +931,7 @@ static int fgmres(biot_ctx* c, const KrylovWork& K, const double* b_canon, doubl
     info->rel_res_prec = 0;
     if (!(bnorm == bnorm) || std::isinf(bnorm)) throw std::domain_error("NaN/Inf in right-hand side");
     if (bnorm == 0.0) {
-        launch_unpack(x, x_canon, L, l0.C, st);
+        vec_unpack(c, x, x_canon, st);
         info->converged = 1;
         return BIOT_OK;
     }
@@ -755,7 +984,7 @@ static int fgmres(biot_ctx* c, const KrylovWork& K, const double* b_canon, doubl
             double* zj = Z + (size_t)j * n;
             if (left) {
                 // w = M^{-1} A v_j
-                launch_apply<double>(l0.view<double>(), vj, nullptr, tmp, 0, st);
+                vec_apply(c, vj, nullptr, tmp, 0, st);
                 precond(c, tmp, w, st);
             } else {
                 precond(c, vj, zj, st);
@@ -764,7 +993,7 @@ static int fgmres(biot_ctx* c, const KrylovWork& K, const double* b_canon, doubl
                 // Krylov basis and orthogonalizing it cancels nearly everything, while the shifted
                 // vector keeps the part that is new.  Its coefficients are h'_i = delta_ij - h_i and
                 // the orthogonalized remainder is -h_{j+1,j} v_{j+1}.
-                launch_apply<double>(l0.view<double>(), zj, vj, w, 1, st);
+                vec_apply(c, zj, vj, w, 1, st);
             }
             // CGS with a second pass when the first one cancels (|w| drops below |w_0| / sqrt 2).
             // Pass one's update also forms pass two's dot products (V is read once for both), so
@@ -827,12 +1056,12 @@ static int fgmres(biot_ctx* c, const KrylovWork& K, const double* b_canon, doubl
         launch_lincomb_add(x, left ? V : Z, n, k, K.yd, n, st);
         // true residual; left: the preconditioned residual that restarts the iteration
         if (left) {
-            launch_apply<double>(l0.view<double>(), x, b, tmp, 1, st);
+            vec_apply(c, x, b, tmp, 1, st);
             rtrue = std::sqrt(norm2_dev(K, tmp, n, st));
             precond(c, tmp, w, st);
             beta = std::sqrt(norm2_dev(K, w, n, st));
         } else {
-            launch_apply<double>(l0.view<double>(), x, b, w, 1, st);
+            vec_apply(c, x, b, w, 1, st);
             beta = rtrue = std::sqrt(norm2_dev(K, w, n, st));
         }
         if (!(beta == beta) || !(rtrue == rtrue)) throw std::domain_error("NaN in residual");
@@ -840,7 +1069,7 @@ static int fgmres(biot_ctx* c, const KrylovWork& K, const double* b_canon, doubl
     info->iters = it;
     info->rel_res_true = rtrue / bnorm;
     info->rel_res_prec = left ? beta / znorm : 0.0;
-    launch_unpack(x, x_canon, L, l0.C, st);
+    vec_unpack(c, x, x_canon, st);
     check_stream_error();
     return info->converged ? BIOT_OK : BIOT_NOT_CONVERGED;
 }
@@ -954,9 +1183,15 @@ static void require_hierarchy(biot_ctx* c) {
     require(c->have_hierarchy, "biot_setup_hierarchy has not been called");
 }
 
+static int num_levels(biot_ctx* c) { return c->sp ? (int)c->sp->lv.size() : (int)c->levels.size(); }
+
 static void require_level(biot_ctx* c, int level) {
     require_ctx(c);
-    require(level >= 0 && level < (int)c->levels.size(), "level out of range");
+    require(level >= 0 && level < num_levels(c), "level out of range");
+}
+
+static void require_structured(biot_ctx* c, const char* what) {
+    if (c->sp) throw ArgError{std::string(what) + " is not available with bc = BIOT_BC_TERZAGHI"};
 }
 
 extern "C" {
@@ -966,9 +1201,15 @@ int biot_assemble(const biot_problem* prob, void* stream, biot_ctx** out) {
     return guarded([&]() {
         require(prob != nullptr && out != nullptr, "null argument");
         const int n = prob->n;
+        require(prob->bc == BIOT_BC_DIRICHLET || prob->bc == BIOT_BC_TERZAGHI, "bc: BIOT_BC_DIRICHLET or BIOT_BC_TERZAGHI");
+        const bool sparse = prob->bc != BIOT_BC_DIRICHLET;
         require(n >= 4 && n <= 8192 && (n & (n - 1)) == 0, "n must be a power of two in [4, 8192]");
+        require(!sparse || n <= 256, "bc = BIOT_BC_TERZAGHI: n <= 256");
         require(prob->mu > 0 && prob->lambda >= 0, "need mu > 0 and lambda >= 0");
-        require(prob->inv_M > 0 && std::isfinite(prob->inv_M), "need 0 < 1/M < inf");
+        if (sparse)
+            require(prob->inv_M >= 0 && std::isfinite(prob->inv_M), "need 0 <= 1/M < inf");
+        else
+            require(prob->inv_M > 0 && std::isfinite(prob->inv_M), "need 0 < 1/M < inf");
         require(prob->mu_f > 0 && prob->tau > 0, "need mu_f > 0 and tau > 0");
         require(std::isfinite(prob->alpha) && std::isfinite(prob->lambda) && std::isfinite(prob->mu),
                 "non-finite parameter");
@@ -990,6 +1231,17 @@ int biot_assemble(const biot_problem* prob, void* stream, biot_ctx** out) {
         hipStream_t st = S(stream);
         c->kcheck.alloc(sizeof(int));
         if (prob->K_tri) check_field(c.get(), prob->K_tri, 0, st);
+        if (sparse) {
+            c->sp.reset(new SpHier);
+            c->sp->bc = prob->bc;
+            c->sp->lv.emplace_back(new SpLevel);
+            sp_level_alloc(*c->sp->lv[0], n, prob->bc, c->phys, st);
+            sp_assemble(c.get(), prob->K_tri, 0, st);
+            check_stream_error();
+            BIOT_HIP(hipStreamSynchronize(st));
+            *out = c.release();
+            return BIOT_OK;
+        }
         c->levels.emplace_back(new Level);
         level_alloc(*c->levels[0], n, st);
         level_stencil(*c->levels[0], c->phys, st);
@@ -1049,9 +1301,22 @@ int biot_setup_hierarchy(biot_ctx* c, const biot_mg_opts* o, void* stream) {
                 "Schur sweeps need omega_S in (0, 1]");
         require(o->schur_cg >= 0 && o->schur_cg <= 64, "schur_cg in [0, 64]");
         require(o->schur_cg == 0 || o->schur_sweeps <= 1, "schur_cg and schur_sweeps > 1 exclude each other");
+        require(std::isfinite(o->vanka_shift) && o->vanka_shift >= 0, "vanka_shift >= 0");
         const int nc = c->n >> (o->levels - 1);
         require(nc <= 16, "coarsest mesh must have at most 16 cells per side (dense direct solve)");
         hipStream_t st = S(stream);
+        if (c->sp) {
+            require(o->smoother == BIOT_SMOOTHER_VANKA && o->vanka_colors == 0,
+                    "bc = BIOT_BC_TERZAGHI: additive Vanka only (smoother VANKA, vanka_colors 0)");
+            require(o->precision == BIOT_PREC_FP64, "bc = BIOT_BC_TERZAGHI: precision BIOT_PREC_FP64 only");
+            // with 1/M = 0 the pressure constant on the star of an interior vertex is in the null
+            // space of its patch matrix (the patch velocities carry no net flux of it)
+            require(c->phys.inv_M > 0 || o->vanka_shift > 0,
+                    "1/M = 0: the interior Vanka patch matrices are singular; set vanka_shift > 0");
+            sp_setup(c, o, st);
+            return BIOT_OK;
+        }
+        require(o->vanka_shift == 0, "vanka_shift is available with bc = BIOT_BC_TERZAGHI only");
         c->have_hierarchy = false;
         // (re)build levels 1..L-1
         c->levels.resize(1);
@@ -1093,6 +1358,11 @@ int biot_vcycle(biot_ctx* c, const double* r, double* z, void* stream) {
         require_hierarchy(c);
         require(r && z && r != z, "r and z must be distinct non-null device pointers");
         hipStream_t st = S(stream);
+        if (c->sp) {
+            sp_cycle(c, 0, r, z, true, false, st);
+            check_stream_error();
+            return BIOT_OK;
+        }
         Level& l0 = *c->levels[0];
         launch_pack(r, l0.b64.as<double>(), l0.L, l0.C, st);
         precond(c, l0.b64.as<double>(), l0.t64.as<double>(), st);
@@ -1128,6 +1398,7 @@ int biot_solve_noalloc(biot_ctx* c, const double* b, double* x, biot_solve_info*
         require(info->tol >= 0 && std::isfinite(info->tol), "tol >= 0");
         require(info->side == 0 || info->side == 1, "side: 0 (right) or 1 (left)");
         require(info->reorth >= 0 && info->reorth <= 1, "reorth (the DGKS eta) in [0, 1]");
+        require_structured(c, "biot_solve_noalloc");
         const long long len = c->levels[0]->L.len;
         const size_t need = noalloc_doubles(len, info->restart) * sizeof(double);
         if (need > NOALLOC_BYTES)
@@ -1147,6 +1418,11 @@ int biot_apply_operator(biot_ctx* c, int level, const double* x, double* y, void
         require_level(c, level);
         require(x && y && x != y, "x and y must be distinct non-null device pointers");
         hipStream_t st = S(stream);
+        if (c->sp) {
+            sp_apply(c, level, x, nullptr, y, 0, st);
+            check_stream_error();
+            return BIOT_OK;
+        }
         Level& lv = *c->levels[level];
         launch_pack(x, lv.t64.as<double>(), lv.L, lv.C, st);
         launch_apply<double>(lv.view<double>(), lv.t64.as<double>(), nullptr, lv.r64.as<double>(), 0, st);
@@ -1160,9 +1436,14 @@ int biot_smooth(biot_ctx* c, int level, double* x, const double* b, void* stream
     return guarded([&]() {
         require_hierarchy(c);
         require_level(c, level);
-        require(level < (int)c->levels.size() - 1, "no smoother on the coarsest level");
+        require(level < num_levels(c) - 1, "no smoother on the coarsest level");
         require(x && b && (const double*)x != b, "x and b must be distinct non-null device pointers");
         hipStream_t st = S(stream);
+        if (c->sp) {
+            sp_smooth(c, level, x, b, false, st);
+            check_stream_error();
+            return BIOT_OK;
+        }
         Level& lv = *c->levels[level];
         launch_pack(x, lv.x64.as<double>(), lv.L, lv.C, st);
         launch_pack(b, lv.b64.as<double>(), lv.L, lv.C, st);
@@ -1188,9 +1469,16 @@ int biot_restrict(biot_ctx* c, int level, const double* r_f, double* r_c, void* 
     return guarded([&]() {
         require_hierarchy(c);
         require_level(c, level);
-        require(level + 1 < (int)c->levels.size(), "no coarser level");
+        require(level + 1 < num_levels(c), "no coarser level");
         require(r_f && r_c, "null pointer");
         hipStream_t st = S(stream);
+        if (c->sp) {
+            const SpLevel& F = *c->sp->lv[level];
+            const SpLevel& C = *c->sp->lv[level + 1];
+            launch_csr_mv(C.N, F.rptr.as<int>(), F.rcol.as<int>(), F.rval.as<double>(), r_f, nullptr, r_c, 1.0, 0.0, st);
+            check_stream_error();
+            return BIOT_OK;
+        }
         Level& lf = *c->levels[level];
         Level& lc = *c->levels[level + 1];
         launch_pack(r_f, lf.t64.as<double>(), lf.L, lf.C, st);
@@ -1205,9 +1493,15 @@ int biot_prolong_add(biot_ctx* c, int level, const double* x_c, double* x_f, voi
     return guarded([&]() {
         require_hierarchy(c);
         require_level(c, level);
-        require(level + 1 < (int)c->levels.size(), "no coarser level");
-        require(x_c && x_f, "null pointer");
+        require(level + 1 < num_levels(c), "no coarser level");
+        require(x_c && x_f && x_c != (const double*)x_f, "x_c and x_f must be distinct non-null device pointers");
         hipStream_t st = S(stream);
+        if (c->sp) {
+            const SpLevel& F = *c->sp->lv[level];
+            launch_csr_mv(F.N, F.pptr.as<int>(), F.pcol.as<int>(), F.pval.as<double>(), x_c, x_f, x_f, 1.0, 1.0, st);
+            check_stream_error();
+            return BIOT_OK;
+        }
         Level& lf = *c->levels[level];
         Level& lc = *c->levels[level + 1];
         launch_pack(x_c, lc.t64.as<double>(), lc.L, lc.C, st);
@@ -1226,6 +1520,12 @@ static int update_perm(biot_ctx* c, const double* field, int mode, void* stream)
     hipStream_t st = S(stream);
     check_field(c, field, mode, st);
     c->K_uniform = false;
+    if (c->sp) {
+        sp_assemble(c, field, mode, st);
+        if (c->have_hierarchy) sp_factor(c, st);
+        check_stream_error();
+        return BIOT_OK;
+    }
     levels_kinv(c, field, st, mode);
     if (c->have_hierarchy) levels_factors(c, st);
     if (c->have_hierarchy && c->opts.smoother == BIOT_SMOOTHER_BSR) levels_bsr(c, st);
@@ -1246,6 +1546,7 @@ int biot_grad_logK(biot_ctx* c, const double* x, const double* lam, double* g_tr
     return guarded([&]() {
         require_ctx(c);
         require(x && lam && g_tri, "null pointer");
+        require_structured(c, "biot_grad_logK");
         hipStream_t st = S(stream);
         Level& l0 = *c->levels[0];
         launch_pack(x, l0.t64.as<double>(), l0.L, l0.C, st);
@@ -1261,6 +1562,16 @@ int biot_export_layout(biot_ctx* c, int* counts, int* patch_table, void* stream)
     return guarded([&]() {
         require_ctx(c);
         hipStream_t st = S(stream);
+        if (c->sp) {
+            require(patch_table == nullptr, "bc = BIOT_BC_TERZAGHI: the patch table is not exported");
+            const FreeMap& m = c->sp->lv[0]->map;
+            if (counts) {
+                counts[0] = c->n;
+                counts[1] = m.N;
+                for (int t = 0; t < NTYPES; ++t) counts[2 + t] = (int)m.block[t];
+            }
+            return BIOT_OK;
+        }
         Level& l0 = *c->levels[0];
         if (counts) {
             counts[0] = c->n;
@@ -1283,6 +1594,7 @@ int biot_export_layout(biot_ctx* c, int* counts, int* patch_table, void* stream)
 int biot_kernel_timing(biot_ctx* c, int enable, int level, double* out, void* stream) {
     return guarded([&]() {
         require_level(c, level);
+        require_structured(c, "biot_kernel_timing");
         hipStream_t st = S(stream);
         if (enable) {
             c->prof_on = true;

@@ -6,6 +6,7 @@
 // (A_u^RQ = 2 mu A_eps + lambda B_u^T M_p^-1 B_u), Sec. 3 (eq. block_interp, R = P^T),
 // Sec. 3.1 (divergence-preserving P_u), Sec. 3.2.1 (vertex patches).
 #include "common.h"
+#include "sparse.h"
 #include "structure.h"
 
 #include <array>
@@ -173,6 +174,10 @@ void local_matrix(const ElemMats& E, const PhysParams& p, double A[13][13], bool
 }
 
 }  // namespace
+
+void element_matrices(const PhysParams& p, double h, double A[2][13][13], bool kw[2][13][13]) {
+    for (int u = 0; u < 2; ++u) local_matrix(element_mats(make_tri(u == 1), h), p, A[u], kw[u]);
+}
 
 void build_stencil_coef(const PhysParams& p, double h, double* coef) {
     Tri tris[2] = {make_tri(false), make_tri(true)};
@@ -425,6 +430,14 @@ void build_prolong_weights(double* w) {
                             w[widx(t, pi, pj, q)] = r.w;
                 }
             }
+}
+
+void local_prolongation_entries(std::vector<LocalProlong>& out) {
+    std::vector<RawP> raw;
+    local_prolongation(false, raw);
+    local_prolongation(true, raw);
+    out.clear();
+    for (auto& r : raw) out.push_back({r.t_f, r.fi, r.fj, r.t_c, r.cI, r.cJ, r.w});
 }
 
 void build_transfer_tables(std::vector<ProlongEntry>& pro, std::vector<RestrictEntry>& res) {

@@ -1,0 +1,238 @@
+// Kernels of the general-boundary path (sparse.h): CSR products, on-device assembly of the
+// operator values from per-triangle 1/K, and the additive Vanka step on explicit patch
+// inverses.  Paper: Sec. 2.1 (K enters tau M_w(K) only), Sec. 3 (R = P^T), Sec. 3.2.1 (additive
+// Vanka: x <- x + omega sum_l V_l^T D_l A_l^{-1} V_l (b - A x)), Sec. 5 (Terzaghi: the Vanka
+// blocks shifted by a small weight on the diagonal when M = infinity).
+//
+// These levels are small (the path serves meshes up to 256 x 256): every kernel is one thread
+// per row, patch entry or DoF, latency bound, with the loads of a thread independent of each
+// other so that they overlap.
+#include "sparse.h"
+
+namespace biot {
+
+namespace {
+
+constexpr int TPB = 256;
+
+inline unsigned blocks(long long n, int tpb = TPB) { return (unsigned)((n + tpb - 1) / tpb); }
+
+__global__ __launch_bounds__(TPB) void k_csr_mv(int rows, const int* __restrict__ ptr, const int* __restrict__ col,
+                                                const double* __restrict__ val, const double* __restrict__ x,
+                                                const double* z, double* y, double a, double c) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows) return;
+    double s = 0.0;
+    if (x)
+        for (int q = ptr[r]; q < ptr[r + 1]; ++q) s += val[q] * x[col[q]];
+    y[r] = (z ? c * z[r] : 0.0) + a * s;
+}
+
+__global__ __launch_bounds__(TPB) void k_csr_assemble(int nnz, const double* __restrict__ val0,
+                                                      const int* __restrict__ kptr, const int* __restrict__ ktri,
+                                                      const double* __restrict__ kcoef,
+                                                      const double* __restrict__ kinv, double* __restrict__ val) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    double v = val0[e];
+    for (int q = kptr[e]; q < kptr[e + 1]; ++q) v += kcoef[q] * kinv[ktri[q]];
+    val[e] = v;
+}
+
+__global__ __launch_bounds__(TPB) void k_kinv_flat(long long ntri, const double* __restrict__ K, double Ks, int mode,
+                                                   double* __restrict__ kinv) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntri) return;
+    kinv[t] = mode == 1 ? exp(-K[t]) : 1.0 / (K ? K[t] : Ks);
+}
+
+// coarse L(I, J) = {(2I, 2J), (2I+2, 2J), (2I, 2J+2)} in fine units: children L(2I, 2J),
+// L(2I+1, 2J), L(2I, 2J+1) and the middle U(2I, 2J); coarse U(I, J): U(2I+1, 2J), U(2I+1, 2J+1),
+// U(2I, 2J+1) and the middle L(2I+1, 2J+1)
+__global__ __launch_bounds__(TPB) void k_kinv_coarsen_flat(int nc, const double* __restrict__ kf,
+                                                           double* __restrict__ kc) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nn = nc * nc;
+    if (q >= 2 * nn) return;
+    const int upper = q >= nn, c = q - upper * nn, I = c % nc, J = c / nc;
+    const int nf = 2 * nc, mf = nf * nf;
+    auto L = [&](int i, int j) { return kf[j * nf + i]; };
+    auto U = [&](int i, int j) { return kf[mf + j * nf + i]; };
+    const double s = upper ? (U(2 * I + 1, 2 * J) + U(2 * I + 1, 2 * J + 1)) + (U(2 * I, 2 * J + 1) + L(2 * I + 1, 2 * J + 1))
+                           : (L(2 * I, 2 * J) + L(2 * I + 1, 2 * J)) + (L(2 * I, 2 * J + 1) + U(2 * I, 2 * J));
+    kc[q] = 0.25 * s;
+}
+
+// One wave per patch: the 20 x 20 shifted patch matrix (identity on absent slots) next to the
+// identity in LDS, Gauss-Jordan with partial pivoting over the rows, the inverse written
+// column-major (inv[p][b * 20 + a] = A_p^{-1}[a][b]) so that the apply reads it coalesced.
+constexpr int PW = 2 * PATCH;
+__global__ __launch_bounds__(64) void k_patch_inverse(int np, const int* __restrict__ slots,
+                                                      const int* __restrict__ ptr, const int* __restrict__ col,
+                                                      const double* __restrict__ val, double shift,
+                                                      double* __restrict__ inv, int* __restrict__ status) {
+    __shared__ double M[PATCH][PW + 1];
+    __shared__ int sl[PATCH];
+    __shared__ int piv;
+    const int p = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (p >= np) return;
+    if (lane < PATCH) sl[lane] = slots[(long long)p * PATCH + lane];
+    __syncthreads();
+    for (int e = lane; e < PATCH * PW; e += 64) {
+        const int a = e / PW, b = e % PW;
+        double v = 0.0;
+        if (b >= PATCH) {
+            v = (b - PATCH == a) ? 1.0 : 0.0;
+        } else if (sl[a] < 0 || sl[b] < 0) {
+            v = (a == b) ? 1.0 : 0.0;
+        } else {
+            // entry (sl[a], sl[b]) of the CSR row: binary search over the sorted columns
+            int lo = ptr[sl[a]], hi = ptr[sl[a] + 1] - 1;
+            const int want = sl[b];
+            while (lo <= hi) {
+                const int mid = (lo + hi) >> 1;
+                const int cm = col[mid];
+                if (cm == want) {
+                    v = val[mid];
+                    break;
+                }
+                if (cm < want) lo = mid + 1;
+                else hi = mid - 1;
+            }
+            if (a == b) v += (a < 14 ? shift : -shift);
+        }
+        M[a][b] = v;
+    }
+    __syncthreads();
+    for (int k = 0; k < PATCH; ++k) {
+        if (lane == 0) {
+            int best = k;
+            double bv = fabs(M[k][k]);
+            for (int r = k + 1; r < PATCH; ++r)
+                if (fabs(M[r][k]) > bv) {
+                    bv = fabs(M[r][k]);
+                    best = r;
+                }
+            piv = best;
+            if (!(bv > 0.0) || !isfinite(bv)) *status = 1;
+        }
+        __syncthreads();
+        const int r0 = piv;
+        if (r0 != k)
+            for (int b = lane; b < PW; b += 64) {
+                const double t = M[k][b];
+                M[k][b] = M[r0][b];
+                M[r0][b] = t;
+            }
+        __syncthreads();
+        const double d = M[k][k];
+        const double rd = d != 0.0 ? 1.0 / d : 0.0;
+        __syncthreads();
+        for (int b = lane; b < PW; b += 64) M[k][b] *= rd;
+        __syncthreads();
+        for (int e = lane; e < PATCH * PW; e += 64) {
+            const int r = e / PW, b = e % PW;
+            if (r == k) continue;
+            const double f = M[r][k];
+            if (b != k) M[r][b] -= f * M[k][b];
+        }
+        __syncthreads();
+        // column k of the other rows is zero now (kept out of the loop above so that every
+        // thread read the old M[r][k])
+        if (lane < PATCH && lane != k) M[lane][k] = 0.0;
+        __syncthreads();
+    }
+    double* out = inv + (long long)p * PATCH * PATCH;
+    for (int e = lane; e < PATCH * PATCH; e += 64) {
+        const int b = e / PATCH, a = e % PATCH;
+        out[e] = M[a][PATCH + b];
+    }
+}
+
+__global__ __launch_bounds__(TPB) void k_patch_apply(int np, const int* __restrict__ slots,
+                                                     const double* __restrict__ inv, const double* __restrict__ r,
+                                                     double* __restrict__ y) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)np * PATCH) return;
+    const long long p = t / PATCH;
+    const int a = (int)(t - p * PATCH);
+    const int* s = slots + p * PATCH;
+    double v = 0.0;
+    if (s[a] >= 0) {
+        const double* A = inv + p * PATCH * PATCH + a;
+#pragma unroll 4
+        for (int b = 0; b < PATCH; ++b) {
+            const int q = s[b];
+            if (q >= 0) v += A[b * PATCH] * r[q];
+        }
+    }
+    y[t] = v;
+}
+
+__global__ __launch_bounds__(TPB) void k_patch_gather(int N, const int* __restrict__ dptr,
+                                                      const int* __restrict__ dlist, const double* __restrict__ y,
+                                                      const double* __restrict__ wgt, double omega, const double* x,
+                                                      double* xout) {
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= N) return;
+    double s = 0.0;
+    for (int q = dptr[d]; q < dptr[d + 1]; ++q) s += y[dlist[q]];
+    xout[d] = (x ? x[d] : 0.0) + omega * wgt[d] * s;
+}
+
+__global__ __launch_bounds__(TPB) void k_csr_to_dense(int N, const int* __restrict__ ptr, const int* __restrict__ col,
+                                                      const double* __restrict__ val, double* __restrict__ D) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= N) return;
+    double* row = D + (long long)r * N;
+    for (int c = 0; c < N; ++c) row[c] = 0.0;
+    for (int q = ptr[r]; q < ptr[r + 1]; ++q) row[col[q]] = val[q];
+}
+
+}  // namespace
+
+void launch_csr_mv(int rows, const int* ptr, const int* col, const double* val, const double* x, const double* z,
+                   double* y, double a, double c, hipStream_t st) {
+    if (rows <= 0) return;
+    hipLaunchKernelGGL(k_csr_mv, dim3(blocks(rows)), dim3(TPB), 0, st, rows, ptr, col, val, x, z, y, a, c);
+}
+
+void launch_csr_assemble(int nnz, const double* val0, const int* kptr, const int* ktri, const double* kcoef,
+                         const double* kinv, double* val, hipStream_t st) {
+    if (nnz <= 0) return;
+    hipLaunchKernelGGL(k_csr_assemble, dim3(blocks(nnz)), dim3(TPB), 0, st, nnz, val0, kptr, ktri, kcoef, kinv, val);
+}
+
+void launch_kinv_flat(long long ntri, const double* K, double Ks, int mode, double* kinv, hipStream_t st) {
+    if (ntri <= 0) return;
+    hipLaunchKernelGGL(k_kinv_flat, dim3(blocks(ntri)), dim3(TPB), 0, st, ntri, K, Ks, mode, kinv);
+}
+
+void launch_kinv_coarsen_flat(int nc, const double* kf, double* kc, hipStream_t st) {
+    hipLaunchKernelGGL(k_kinv_coarsen_flat, dim3(blocks(2LL * nc * nc)), dim3(TPB), 0, st, nc, kf, kc);
+}
+
+void launch_patch_inverse(int np, const int* slots, const int* ptr, const int* col, const double* val, double shift,
+                          double* inv, int* status, hipStream_t st) {
+    if (np <= 0) return;
+    hipLaunchKernelGGL(k_patch_inverse, dim3(np), dim3(64), 0, st, np, slots, ptr, col, val, shift, inv, status);
+}
+
+void launch_patch_apply(int np, const int* slots, const double* inv, const double* r, double* y, hipStream_t st) {
+    if (np <= 0) return;
+    hipLaunchKernelGGL(k_patch_apply, dim3(blocks((long long)np * PATCH)), dim3(TPB), 0, st, np, slots, inv, r, y);
+}
+
+void launch_patch_gather(int N, const int* dptr, const int* dlist, const double* y, const double* wgt, double omega,
+                         const double* x, double* xout, hipStream_t st) {
+    if (N <= 0) return;
+    hipLaunchKernelGGL(k_patch_gather, dim3(blocks(N)), dim3(TPB), 0, st, N, dptr, dlist, y, wgt, omega, x, xout);
+}
+
+void launch_csr_to_dense(int N, const int* ptr, const int* col, const double* val, double* D, hipStream_t st) {
+    if (N <= 0) return;
+    hipLaunchKernelGGL(k_csr_to_dense, dim3(blocks(N, 64)), dim3(64), 0, st, N, ptr, col, val, D);
+}
+
+}  // namespace biot

@@ -56,3 +56,37 @@ def test_invalid_arguments_are_rejected_without_touching_the_device():
     assert not ctx.value
     code = lib.biot_solve(None, None, None, None, None)
     assert code == binding.BIOT_ERR_ARG
+
+
+def test_boundary_condition_arguments_are_validated_on_the_host():
+    """bc outside {Dirichlet, Terzaghi}, Terzaghi above n = 256 and 1/M = 0 with Dirichlet data
+    are rejected before any HIP call; 1/M = 0 passes validation only with Terzaghi's bc."""
+    from paper_2107_04060_amd import binding
+    lib = binding.load()
+
+    def try_assemble(n, bc, inv_M):
+        prob = binding.Problem()
+        prob.n, prob.bc = n, bc
+        prob.lambda_, prob.mu, prob.alpha = 1.0, 1.0, 1.0
+        prob.inv_M, prob.mu_f, prob.tau, prob.K_scalar = inv_M, 1.0, 1.0, 1.0
+        ctx = ctypes.c_void_p()
+        code = lib.biot_assemble(ctypes.byref(prob), None, ctypes.byref(ctx))
+        assert not ctx.value
+        return code, lib.biot_last_error()
+
+    code, msg = try_assemble(16, 2, 0.03)
+    assert code == binding.BIOT_ERR_ARG and b"bc" in msg
+    code, msg = try_assemble(512, binding.BCS["terzaghi"], 0.0)
+    assert code == binding.BIOT_ERR_ARG and b"256" in msg
+    code, msg = try_assemble(16, binding.BCS["dirichlet"], 0.0)
+    assert code == binding.BIOT_ERR_ARG and b"1/M" in msg
+    code, msg = try_assemble(16, binding.BCS["terzaghi"], -1.0)
+    assert code == binding.BIOT_ERR_ARG and b"1/M" in msg
+
+
+def test_free_counts_of_the_binding():
+    from paper_2107_04060_amd import binding
+    from oracle.mesh import Mesh
+    for n in (4, 8, 16):
+        assert binding.n_free(n) == Mesh(n).n_free
+        assert binding.n_free(n, "terzaghi") == Mesh(n, "terzaghi").n_free
