@@ -13,6 +13,12 @@ JSON line.
 
 --workload sweep256 (also small, grf1024) runs the 256 x 256 sweep instead: one step = the 18
 solves of its 9 parameter sets x {Vanka V(2,2), BSR V(1,1)}, concurrently on --streams streams.
+
+--workload terzaghi runs Terzaghi's column (Sec. 5, Table 6: h = 1/64, M = infinity, k = 1e-6,
+tau = tau_hat / 100, additive Vanka V(2,2) with the 1e-8 patch shift, left-preconditioned
+GMRES(30) to 1e-6) on the general-boundary path: one step = one backward-Euler time step (its
+right-hand side formed on the device, then the solve), ten per Poisson ratio.  The default run
+appends the same measurement to its line ("terzaghi_table6"; --no-terzaghi skips it).
 """
 import argparse
 import json
@@ -80,8 +86,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=None,
                     help="timed steps (default: 8 right-hand sides for block2048, 3 sweeps for sweep256)")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="block2048", choices=["block2048", "sweep256", "small", "grf1024"],
-                    help="the timed workload")
+    ap.add_argument("--workload", default="block2048",
+                    choices=["block2048", "sweep256", "small", "grf1024", "terzaghi"], help="the timed workload")
+    ap.add_argument("--no-terzaghi", action="store_true",
+                    help="block2048: skip the Terzaghi (Table 6) runs appended to the line")
+    ap.add_argument("--terzaghi-n", type=int, default=64, help="terzaghi: cells per side (<= 256)")
     ap.add_argument("--forms", default="fp64,fp32",
                     help="block2048: the precision forms timed in turn (the first one gives value)")
     ap.add_argument("--nu12", type=int, default=BLOCK_CYCLE["nu12"],
@@ -388,6 +397,76 @@ def cpu_baseline_block(n_gpu, iters_gpu, cyc, n_sample=256):
                       % (n_sample, n_sample, nf_s, t_it, cores, n_gpu, n_gpu, iters_gpu)}
 
 
+TABLE6_PAPER = {0.4: 7.3, 0.45: 7.6, 0.49: 8.7, 0.499: 14.5}   # Table 6: average iterations
+
+
+def terzaghi_runs(binding, inputs, torch, n=None, reps=1):
+    """Terzaghi's column for each Poisson ratio of Table 6: set-up, then `steps` backward-Euler
+    steps from u = 0, each a right-hand side formed on the device (the load plus the pressure rows
+    of A applied to the previous displacement: alpha B_u u^{m-1}) and one left-preconditioned
+    GMRES(30) solve to 1e-6.  The steps are timed together (HIP synchronization at both ends);
+    `reps` repeats the ten steps, the last repetition is reported."""
+    import numpy as np
+    tz = inputs.TERZAGHI
+    n = tz["n"] if n is None else n
+    levels = max(2, int(round(np.log2(n))) - 2)          # direct solve on the 8 x 8 mesh
+    load = torch.tensor(inputs.terzaghi_load(n, tz["p0"]), dtype=torch.float64, device="cuda")
+    nf = inputs.n_free_terzaghi(n)
+    rows = {}
+    for nu in tz["nu"]:
+        lam, mu = inputs.lame(tz["E"], nu)
+        tau = inputs.terzaghi_tau_hat(tz["k"], lam, mu) / 100.0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = binding.BiotSolver(n, lam, mu, alpha=1.0, M=float("inf"), mu_f=1.0, tau=tau, K=tz["k"], bc="terzaghi")
+        s.setup(levels=levels, nu1=2, nu2=2, omega=0.8, vanka_shift=1e-8)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        blocks = s.export_layout(patches=False)["blocks"]
+        n_u, n_w = sum(blocks[:5]), sum(blocks[5:8])
+        for _ in range(reps):
+            x = torch.zeros(nf, dtype=torch.float64, device="cuda")
+            its = []
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(tz["steps"]):
+                xu = x.clone()
+                xu[n_u:] = 0.0
+                y = s.apply(xu)
+                b = load.clone()
+                b[n_u + n_w:] = y[n_u + n_w:]
+                x, info = s.solve(b, tol=1e-6, restart=30, maxit=60, side="left")
+                if not info["converged"]:
+                    raise RuntimeError("Terzaghi nu %g: a step did not converge" % nu)
+                its.append(info["iters"])
+            torch.cuda.synchronize()
+            total = time.perf_counter() - t0
+        s.close()
+        rows[repr(nu)] = {"iters": its, "mean_iters": round(float(np.mean(its)), 2), "paper_mean": TABLE6_PAPER[nu],
+                          "ms_per_step": round(total * 1e3 / tz["steps"], 3), "setup_s": round(setup_s, 3),
+                          "MDOF/s": round(tz["steps"] * nf / total / 1e6, 3)}
+        print("terzaghi n %d nu %g: %s, %.2f ms per step" % (n, nu, its, total * 1e3 / tz["steps"]), file=sys.stderr,
+              flush=True)
+    return {"workload": "Terzaghi column (Sec. 5, Table 6): %d x %d (%d free DoFs, %d levels), E 3e4, k 1e-6, M inf, "
+                        "tau tau_hat/100, %d steps, additive Vanka V(2,2) omega 0.8 with the 1e-8 shift, left GMRES(30) "
+                        "to 1e-6; general-boundary path (CSR)" % (n, n, nf, levels, tz["steps"]),
+            "n": n, "free_dofs": nf, "runs": rows}
+
+
+def main_terzaghi(args, binding, inputs, torch):
+    """--workload terzaghi: the Table 6 runs as the timed workload (value: MDOF/s over all steps)."""
+    res = terzaghi_runs(binding, inputs, torch, n=args.terzaghi_n, reps=1 + args.warmup)
+    runs = list(res["runs"].values())
+    ms = sum(r["ms_per_step"] for r in runs) / len(runs)
+    out = {"metric": "Terzaghi column backward-Euler steps (right-hand side + left GMRES(30) to 1e-6): MDOF/s",
+           "value": round(res["free_dofs"] / (ms * 1e-3) / 1e6, 3), "unit": "MDOF/s", "n_gpus": 1,
+           "steps": inputs.TERZAGHI["steps"] * len(runs), "warmup": args.warmup, "ms_per_step": round(ms, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "terzaghi", "n": res["n"], "free_dofs": res["free_dofs"]},
+           "terzaghi_table6": res, "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
 def main_block2048(args, binding, inputs, torch):
     """The block-contrast workload: one step = one right-hand-side solve, hierarchy reused."""
     import numpy as np
@@ -531,6 +610,8 @@ def main_block2048(args, binding, inputs, torch):
                    "forms": forms, "all_converged": all(res[f].get("all_converged", False) for f in forms)},
         "precision_forms": res, "roofline": roofline, "residual_kernel": resid, "cpu_baseline": cpu,
     }
+    if not args.no_terzaghi:
+        out["terzaghi_table6"] = terzaghi_runs(binding, inputs, torch)
     print(json.dumps(out), flush=True)
 
 
@@ -550,6 +631,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "block2048":
         main_block2048(args, binding, inputs, torch)
+    elif args.workload == "terzaghi":
+        main_terzaghi(args, binding, inputs, torch)
     else:
         if args.steps is None:
             args.steps = 3

@@ -4,9 +4,10 @@
 // Vanka: x <- x + omega sum_l V_l^T D_l A_l^{-1} V_l (b - A x)), Sec. 5 (Terzaghi: the Vanka
 // blocks shifted by a small weight on the diagonal when M = infinity).
 //
-// These levels are small (the path serves meshes up to 256 x 256): every kernel is one thread
-// per row, patch entry or DoF, latency bound, with the loads of a thread independent of each
-// other so that they overlap.
+// These levels are small (the path serves meshes up to 256 x 256) and their launches latency
+// bound: a CSR row is spread over LPR lanes (a few entries each, then a butterfly sum), a
+// patch entry's 20 loads are issued together (full unroll), so that no thread walks a long
+// chain of dependent loads.
 #include "sparse.h"
 
 namespace biot {
@@ -14,18 +15,23 @@ namespace biot {
 namespace {
 
 constexpr int TPB = 256;
+constexpr int LPR = 8;   // lanes per CSR row (consecutive lanes of one wave)
 
 inline unsigned blocks(long long n, int tpb = TPB) { return (unsigned)((n + tpb - 1) / tpb); }
 
+// every lane of a wave takes part in the butterfly, rows past the end with zero sums
 __global__ __launch_bounds__(TPB) void k_csr_mv(int rows, const int* __restrict__ ptr, const int* __restrict__ col,
                                                 const double* __restrict__ val, const double* __restrict__ x,
                                                 const double* z, double* y, double a, double c) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= rows) return;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long r = t / LPR;
+    const int lane = (int)(t % LPR);
     double s = 0.0;
-    if (x)
-        for (int q = ptr[r]; q < ptr[r + 1]; ++q) s += val[q] * x[col[q]];
-    y[r] = (z ? c * z[r] : 0.0) + a * s;
+    if (r < rows && x)
+        for (int q = ptr[r] + lane; q < ptr[r + 1]; q += LPR) s += val[q] * x[col[q]];
+#pragma unroll
+    for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, LPR);
+    if (r < rows && lane == 0) y[r] = (z ? c * z[r] : 0.0) + a * s;
 }
 
 __global__ __launch_bounds__(TPB) void k_csr_assemble(int nnz, const double* __restrict__ val0,
@@ -150,6 +156,9 @@ __global__ __launch_bounds__(64) void k_patch_inverse(int np, const int* __restr
     }
 }
 
+// The slot indices are loaded first (five 16-byte loads), then every residual entry with an
+// unconditional load (absent slots read entry 0 and are selected away): no branch between the
+// loads, so the 20 gathers are in flight together instead of one after another.
 __global__ __launch_bounds__(TPB) void k_patch_apply(int np, const int* __restrict__ slots,
                                                      const double* __restrict__ inv, const double* __restrict__ r,
                                                      double* __restrict__ y) {
@@ -157,17 +166,24 @@ __global__ __launch_bounds__(TPB) void k_patch_apply(int np, const int* __restri
     if (t >= (long long)np * PATCH) return;
     const long long p = t / PATCH;
     const int a = (int)(t - p * PATCH);
-    const int* s = slots + p * PATCH;
-    double v = 0.0;
-    if (s[a] >= 0) {
-        const double* A = inv + p * PATCH * PATCH + a;
-#pragma unroll 4
-        for (int b = 0; b < PATCH; ++b) {
-            const int q = s[b];
-            if (q >= 0) v += A[b * PATCH] * r[q];
-        }
+    const int4* s4 = reinterpret_cast<const int4*>(slots + p * PATCH);   // 80-byte rows: 16-byte aligned
+    int q[PATCH];
+#pragma unroll
+    for (int k = 0; k < PATCH / 4; ++k) {
+        const int4 v = s4[k];
+        q[4 * k] = v.x;
+        q[4 * k + 1] = v.y;
+        q[4 * k + 2] = v.z;
+        q[4 * k + 3] = v.w;
     }
-    y[t] = v;
+    const double* A = inv + p * PATCH * PATCH + a;
+    double v = 0.0;
+#pragma unroll
+    for (int b = 0; b < PATCH; ++b) {
+        const double rb = r[q[b] >= 0 ? q[b] : 0];
+        v += A[b * PATCH] * (q[b] >= 0 ? rb : 0.0);
+    }
+    y[t] = slots[t] >= 0 ? v : 0.0;
 }
 
 __global__ __launch_bounds__(TPB) void k_patch_gather(int N, const int* __restrict__ dptr,
@@ -195,7 +211,8 @@ __global__ __launch_bounds__(TPB) void k_csr_to_dense(int N, const int* __restri
 void launch_csr_mv(int rows, const int* ptr, const int* col, const double* val, const double* x, const double* z,
                    double* y, double a, double c, hipStream_t st) {
     if (rows <= 0) return;
-    hipLaunchKernelGGL(k_csr_mv, dim3(blocks(rows)), dim3(TPB), 0, st, rows, ptr, col, val, x, z, y, a, c);
+    hipLaunchKernelGGL(k_csr_mv, dim3(blocks((long long)rows * LPR)), dim3(TPB), 0, st, rows, ptr, col, val, x, z, y,
+                       a, c);
 }
 
 void launch_csr_assemble(int nnz, const double* val0, const int* kptr, const int* ktri, const double* kcoef,

@@ -44,6 +44,39 @@ def n_free(n):
     return 10 * n * n - 8 * n + 2
 
 
+def n_free_terzaghi(n):
+    """Free DoFs of the n x n mesh under Terzaghi's boundary conditions: 10 n^2 - 2 n."""
+    return 10 * n * n - 2 * n
+
+
+# Terzaghi's column (Sec. 5, Terzaghi's problem): E = 3e4, alpha = mu_f = 1, M = infinity,
+# k = 1e-6, a unit load on the face x = 0; steps of tau_hat / 100, ten of them, on the 64 x 64 mesh
+TERZAGHI = dict(E=3.0e4, k=1e-6, p0=1.0, n=64, steps=10, levels=4, nu=(0.4, 0.45, 0.49, 0.499))
+
+
+def terzaghi_tau_hat(k, lam, mu):
+    """The time scale of the column's slowest mode, 1 / (0.25 pi^2 k (lambda + 2 mu))."""
+    return 1.0 / (0.25 * np.pi ** 2 * k * (lam + 2.0 * mu))
+
+
+def terzaghi_load(n, p0=1.0):
+    """The displacement part of the right-hand side of Terzaghi's column, in the canonical free
+    order of the mixed boundary conditions: the traction (p0, 0) on the face x = 0 integrated
+    against the basis, p0 h at the u_x of each face vertex (p0 h / 2 at the two corners) and
+    (2/3) p0 h at the bubble of each face edge (the vertical edges V(0, j), normal +x, whose
+    bubble integrates to 2/3 of the edge length).  The blocks before b_V: u_x (n (n + 1)), u_y,
+    b_H (n (n - 1) each); u_x of vertex (0, j) is entry j n, b_V of edge V(0, j) entry j n of its
+    block."""
+    h = 1.0 / n
+    b = np.zeros(n_free_terzaghi(n))
+    for j in range(n + 1):
+        b[j * n] = p0 * (h / 2.0 if j in (0, n) else h)
+    off_bv = n * (n + 1) + 2 * n * (n - 1)
+    for j in range(n):
+        b[off_bv + j * n] = p0 * 2.0 * h / 3.0
+    return b
+
+
 def rhs_uniform(n, seed, count=1):
     """Right-hand side(s) iid uniform[-1, 1] in the canonical free-DoF order."""
     rng = np.random.default_rng(seed)

@@ -175,3 +175,14 @@ def test_table6_counts(nu):
     T.run(10, solve)
     print("nu %g: %s, average %.1f (paper %.1f)" % (nu, its, np.mean(its), TABLE6[nu]))
     assert abs(np.mean(its) - TABLE6[nu]) <= 2.0
+
+
+def test_load_recipe_of_the_gpu_runs():
+    """The traction load that the GPU runs and the benchmark build without the oracle
+    (paper_2107_04060_amd/inputs.py) equals the oracle's, restricted to the free DoFs."""
+    from paper_2107_04060_amd import inputs
+    for n in (4, 16, 64):
+        T = Terzaghi(n, 0.45, K)
+        assert np.array_equal(inputs.terzaghi_load(n), T.load_u[T.mesh.free_full])
+        assert inputs.n_free_terzaghi(n) == T.mesh.n_free
+        assert inputs.terzaghi_tau_hat(K, T.lam, T.mu) == T.tau_hat
