@@ -35,8 +35,10 @@ BLOCK_RESTART = 100          # FGMRES restart of the block-contrast workload
 BLOCK_REORTH = 0.01          # its Gram-Schmidt threshold: a second pass after two digits of cancellation
 # the cycle of the block-contrast workload: the fastest to 1e-8 among the V-, W- and partial
 # W-cycles with additive and multiplicative Vanka and 8 to 10 levels measured on it (the
-# V(2,2) cycle with the LFA weight on 10 levels takes 178 iterations, 3.6 s per solve)
-BLOCK_CYCLE = dict(nu12=1, omega=1.1, colors=3, gamma=2, gamma_from=1, levels=8, fcycle=0)
+# V(2,2) cycle with the LFA weight on 10 levels takes 178 iterations, 3.6 s per solve); the levels
+# of 64 x 64 cells and below smooth on CSR operators with explicit patch inverses (468 -> 408 ms
+# per solve; 32: 427, 128: 412, 256: 441)
+BLOCK_CYCLE = dict(nu12=1, omega=1.1, colors=3, gamma=2, gamma_from=1, levels=8, fcycle=0, csr_below=64)
 CSRC = os.path.join(ROOT, "paper_2107_04060_amd", "csrc")
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_vanka_step_sweep256_fp64.md")
 BLOCK_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_vanka_step_block2048_fp64.md")
@@ -104,6 +106,9 @@ def parse():
     ap.add_argument("--fcycle", type=int, default=BLOCK_CYCLE["fcycle"], choices=[0, 1],
                     help="block2048: 1 = the repeated coarse corrections are V-cycles (F-cycle), 0 = W-cycle")
     ap.add_argument("--restart", type=int, default=BLOCK_RESTART, help="block2048: FGMRES restart")
+    ap.add_argument("--csr-below", type=int, default=BLOCK_CYCLE["csr_below"],
+                    help="block2048, FP64 form: levels below the finest with at most this many cells per side "
+                         "smooth on CSR operators and explicit patch inverses (0: off)")
     ap.add_argument("--reorth", type=float, default=BLOCK_REORTH,
                     help="block2048: Gram-Schmidt second pass when |w1| < reorth |w0| (0: 1/sqrt(2))")
     ap.add_argument("--levels", type=int, default=BLOCK_CYCLE["levels"],
@@ -501,7 +506,8 @@ def main_block2048(args, binding, inputs, torch):
         s = binding.BiotSolver(n, c["lam"], c["mu"], alpha=w["alpha"], M=w["M"], mu_f=w["mu_f"], tau=w["tau"], K=K)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        s.setup(levels=levels, smoother="vanka", precision=form, **cyc)
+        s.setup(levels=levels, smoother="vanka", precision=form, csr_below=args.csr_below if form == "fp64" else 0,
+                **cyc)
         torch.cuda.synchronize()
         setup_s = time.perf_counter() - t0
         if fi == 0 and args.copy_calib_mb > 0:
@@ -606,6 +612,7 @@ def main_block2048(args, binding, inputs, torch):
                                 "the repeated corrections are V-cycles: F-cycle" if args.fcycle else "W-cycle",
                                 levels, n >> (levels - 1), n >> (levels - 1)),
                    "restart": restart, "tol": args.tol, "gram_schmidt_second_pass_below": args.reorth,
+                   "csr_levels_below": args.csr_below,
                    "step": "one right-hand-side solve from x = 0, hierarchy reused", "rhs_order": order,
                    "forms": forms, "all_converged": all(res[f].get("all_converged", False) for f in forms)},
         "precision_forms": res, "roofline": roofline, "residual_kernel": resid, "cpu_baseline": cpu,

@@ -166,6 +166,12 @@ typedef struct {
                            Terzaghi's problem, shifts the blocks by 1e-8 because with 1/M = 0 an
                            interior patch matrix is singular, so vanka_shift > 0 is required
                            there); 0 with BIOT_BC_DIRICHLET                                   */
+    int csr_below;      /* 0 = off; k > 0 (FP64 Vanka, Dirichlet): the smoothing levels below the
+                           finest with n_l <= k cells per side run on compressed-row operators and
+                           explicit patch inverses instead of the fused stencil kernels (the same
+                           operator, patches, colours and cycle; two short launches per colour step
+                           where one fused launch is bound by the latency of a single block).  A
+                           performance option: the result is the same up to rounding.          */
 } biot_mg_opts;
 
 /* FGMRES controls (in) and results (out). */

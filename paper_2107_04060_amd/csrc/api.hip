@@ -132,6 +132,8 @@ struct SpLevel {
     DevBuf slots, inv, y, dptr, dlist, wgt;         // additive Vanka: patches, inverses, corrections,
                                                     // DoF -> (patch, slot) lists, weights D = 1/count
     DevBuf x, b, r;                                 // iterate, right-hand side, residual
+    DevBuf clist;                                   // multiplicative Vanka: patches by colour
+    std::vector<int> coff;                          // colour c: clist[coff[c] .. coff[c+1])
 };
 
 struct SpHier {
@@ -155,6 +157,8 @@ struct biot_ctx {
     std::vector<std::unique_ptr<Level>> levels;   // levels[0] always exists after assemble
                                                   // (structured path; empty with sp)
     std::unique_ptr<SpHier> sp;                   // general-boundary path (bc != Dirichlet)
+    std::unique_ptr<SpHier> small;                // Dirichlet path: levels small_from .. L-1 on CSR
+    int small_from = -1;                          // (opts.csr_below; FP64 Vanka only)
     // transfers: prolongation weights (structure.h)
     DevBuf pw64, pw32;
     // coarsest level
@@ -524,6 +528,8 @@ struct PW<float> {
     static const float* get(biot_ctx* c) { return c->pw32.as<float>(); }
 };
 
+static double* small_entry(biot_ctx* c, const double* b, double* buf0, double* x0, bool vonly, hipStream_t st);
+
 // V(nu1, nu2) cycle on level l for A_l x = b from x = 0 (or from x0), iterate buffers buf0 / buf1
 // (both zero on absent DoFs).  Returns the buffer that holds the result.  vonly: no level below
 // repeats its coarse correction (the V-cycles of an F-cycle).
@@ -531,6 +537,10 @@ template <typename T>
 static T* vcycle_level(biot_ctx* c, int l, const T* b, T* buf0, T* buf1, hipStream_t st, T* x0 = nullptr,
                        bool vonly = false) {
     Level& lv = *c->levels[l];
+    if constexpr (std::is_same_v<T, double>) {
+        // the small levels run on CSR operators and explicit patch inverses
+        if (c->small && l == c->small_from) return small_entry(c, b, buf0, x0, vonly, st);
+    }
     if (l == (int)c->levels.size() - 1) {
         launch_coarse_solve<T>(c->coarse_inv.as<double>(), c->coarse_N, c->coarse_idx.as<int>(), b, buf0, st);
         return buf0;
@@ -617,7 +627,7 @@ static void sp_level_alloc(SpLevel& L, int n, int bc, const PhysParams& p, hipSt
 }
 
 // transfers between level l (fine) and l + 1, and the Vanka patches of level l
-static void sp_level_links(SpLevel& F, const SpLevel& C, hipStream_t st) {
+static void sp_level_links(SpLevel& F, const SpLevel& C, hipStream_t st, int ncolors = 1) {
     const CsrHost P = build_prolongation(F.map, C.map);
     const CsrHost R = csr_transpose(P);
     upload(F.pptr, P.ptr, st);
@@ -626,8 +636,24 @@ static void sp_level_links(SpLevel& F, const SpLevel& C, hipStream_t st) {
     upload(F.rptr, R.ptr, st);
     upload(F.rcol, R.col, st);
     upload(F.rval, R.val, st);
-    const std::vector<int> slots = build_patches(F.map);
+    std::vector<int> verts;
+    const std::vector<int> slots = build_patches(F.map, &verts);
     F.np = (int)(slots.size() / PATCH);
+    if (ncolors > 1) {
+        // the colours of the structured kernels: (i mod 2) + 2 (j mod 2), or (i + 2 j) mod 3
+        std::vector<int> clist;
+        F.coff.assign((size_t)ncolors + 1, 0);
+        const int n1 = F.map.n + 1;
+        for (int col = 0; col < ncolors; ++col) {
+            for (int p = 0; p < F.np; ++p) {
+                const int i = verts[p] % n1, j = verts[p] / n1;
+                const int cp = ncolors == 4 ? (i & 1) + 2 * (j & 1) : (i + 2 * j) % 3;
+                if (cp == col) clist.push_back(p);
+            }
+            F.coff[(size_t)col + 1] = (int)clist.size();
+        }
+        upload(F.clist, clist, st);
+    }
     // DoF -> (patch, slot) lists in patch order (a fixed summation order) and D = 1 / count
     std::vector<int> dptr((size_t)F.N + 1, 0), dlist;
     for (int q : slots)
@@ -728,16 +754,20 @@ static void sp_apply(biot_ctx* c, int l, const double* x, const double* b, doubl
 
 // one additive Vanka step x <- x + omega sum_l V_l^T D_l A_l^{-1} V_l (b - A x) in place
 // (zero: x = 0 on entry, the residual is b)
-static void sp_smooth(biot_ctx* c, int l, double* x, const double* b, bool zero, hipStream_t st) {
-    SpLevel& L = *c->sp->lv[l];
+static void sp_smooth_level(SpLevel& L, double omega, double* x, const double* b, bool zero, hipStream_t st) {
     const double* r = b;
     if (!zero) {
-        sp_apply(c, l, x, b, L.r.as<double>(), 1, st);
+        launch_csr_mv(L.N, L.ptr.as<int>(), L.col.as<int>(), L.val.as<double>(), x, b, L.r.as<double>(), -1.0, 1.0,
+                      st);
         r = L.r.as<double>();
     }
     launch_patch_apply(L.np, L.slots.as<int>(), L.inv.as<double>(), r, L.y.as<double>(), st);
-    launch_patch_gather(L.N, L.dptr.as<int>(), L.dlist.as<int>(), L.y.as<double>(), L.wgt.as<double>(),
-                        c->opts.omega, zero ? nullptr : x, x, st);
+    launch_patch_gather(L.N, L.dptr.as<int>(), L.dlist.as<int>(), L.y.as<double>(), L.wgt.as<double>(), omega,
+                        zero ? nullptr : x, x, st);
+}
+
+static void sp_smooth(biot_ctx* c, int l, double* x, const double* b, bool zero, hipStream_t st) {
+    sp_smooth_level(*c->sp->lv[l], c->opts.omega, x, b, zero, st);
 }
 
 // The cycle on level l for A_l x = b, from x = 0 (zero) or from the iterate in x, result in x
@@ -765,6 +795,122 @@ static void sp_cycle(biot_ctx* c, int l, const double* b, double* x, bool zero, 
         for (int g = 1; g < o.gamma; ++g) sp_cycle(c, l + 1, C.b.as<double>(), C.x.as<double>(), false, o.fcycle != 0, st);
     launch_csr_mv(L.N, L.pptr.as<int>(), L.pcol.as<int>(), L.pval.as<double>(), C.x.as<double>(), x, x, 1.0, 1.0, st);
     for (int s = 0; s < o.nu2; ++s) sp_smooth(c, l, x, b, false, st);
+}
+
+// ---- small levels of the Dirichlet path on CSR (opts.csr_below) ---------------------------------
+// Below some size a level's fused stencil launch is bound by the latency chain of one block
+// (about 15 us whatever the level's size), while the CSR residual and the explicit-inverse patch
+// apply take a few microseconds each.  Levels small_from .. L-2 then smooth on CSR operators
+// (the same rediscretization, assembled from the same per-triangle 1/K) with explicit patch
+// inverses; the coarsest level keeps its dense inverse (in the canonical order, which is the
+// compact order of these levels).  Their vectors are compact; the finer structured level hands
+// its restricted residual over by an unpack and takes the result back by a pack.
+
+// 1/K, operator values and patch inverses of the small levels from the structured levels' 1/K
+static void small_refresh(biot_ctx* c, hipStream_t st) {
+    SpHier& H = *c->small;
+    int* status = H.status.as<int>();
+    BIOT_HIP(hipMemsetAsync(status, 0, sizeof(int), st));
+    for (size_t k = 0; k < H.lv.size(); ++k) {
+        SpLevel& L = *H.lv[k];
+        const Level& lv = *c->levels[(size_t)c->small_from + k];
+        launch_kinv_unpad(lv.L, lv.kinv64.as<double>(), L.kinv.as<double>(), st);
+        launch_csr_assemble(L.nnz, L.val0.as<double>(), L.kptr.as<int>(), L.ktri.as<int>(), L.kcoef.as<double>(),
+                            L.kinv.as<double>(), L.val.as<double>(), st);
+        if (k + 1 < H.lv.size())
+            launch_patch_inverse(L.np, L.slots.as<int>(), L.ptr.as<int>(), L.col.as<int>(), L.val.as<double>(), 0.0,
+                                 L.inv.as<double>(), status, st);
+    }
+    check_stream_error();
+    int bad = 0;
+    BIOT_HIP(hipMemcpyAsync(&bad, status, sizeof(int), hipMemcpyDeviceToHost, st));
+    BIOT_HIP(hipStreamSynchronize(st));
+    if (bad) throw SingularError{"a Vanka patch matrix of a small level is singular"};
+}
+
+static void small_setup(biot_ctx* c, hipStream_t st) {
+    c->small.reset();
+    c->small_from = -1;
+    const biot_mg_opts& o = c->opts;
+    if (o.csr_below <= 0) return;
+    const int L = (int)c->levels.size();
+    int s = 1;
+    while (s < L - 1 && (c->n >> s) > o.csr_below) ++s;
+    if (s >= L - 1) return;                      // no smoothing level is that small
+    std::unique_ptr<SpHier> H(new SpHier);
+    H->bc = BC_DIRICHLET;
+    for (int l = s; l < L; ++l) {
+        H->lv.emplace_back(new SpLevel);
+        sp_level_alloc(*H->lv.back(), c->n >> l, BC_DIRICHLET, c->phys, st);
+    }
+    for (size_t k = 0; k + 1 < H->lv.size(); ++k) sp_level_links(*H->lv[k], *H->lv[k + 1], st, vanka_colors(o));
+    std::vector<int> idx((size_t)c->coarse_N);
+    for (int k = 0; k < c->coarse_N; ++k) idx[k] = k;
+    upload(H->cidx, idx, st);
+    H->status.alloc(sizeof(int));
+    c->small = std::move(H);
+    c->small_from = s;
+    small_refresh(c, st);
+}
+
+// one smoothing step on small level k (additive, or the colours in turn), x in place
+static void small_smooth(biot_ctx* c, SpLevel& L, double* x, const double* b, bool zero, hipStream_t st) {
+    const int nc = vanka_colors(c->opts);
+    const double om = c->opts.omega;
+    if (nc == 1) {
+        sp_smooth_level(L, om, x, b, zero, st);
+        return;
+    }
+    if (zero) launch_fill(x, L.N, 0.0, st);
+    for (int col = 0; col < nc; ++col) {
+        const double* r = b;
+        if (!(zero && col == 0)) {
+            launch_csr_mv(L.N, L.ptr.as<int>(), L.col.as<int>(), L.val.as<double>(), x, b, L.r.as<double>(), -1.0,
+                          1.0, st);
+            r = L.r.as<double>();
+        }
+        launch_patch_apply_add(L.coff[(size_t)col + 1] - L.coff[col], L.clist.as<int>() + L.coff[col],
+                               L.slots.as<int>(), L.inv.as<double>(), r, om, x, st);
+    }
+}
+
+// the cycle on small level k (global level small_from + k), as vcycle_level: from zero or from
+// the iterate in x, result in x; the same repetition rule
+static void small_cycle(biot_ctx* c, int k, const double* b, double* x, bool zero, bool vonly, hipStream_t st) {
+    SpHier& H = *c->small;
+    const int g = c->small_from + k;
+    const int nl = (int)c->levels.size();
+    if (g == nl - 1) {
+        launch_coarse_solve<double>(c->coarse_inv.as<double>(), c->coarse_N, H.cidx.as<int>(), b, x, st);
+        return;
+    }
+    const biot_mg_opts& o = c->opts;
+    SpLevel& L = *H.lv[k];
+    SpLevel& C = *H.lv[(size_t)k + 1];
+    bool z = zero;
+    for (int s = 0; s < o.nu1; ++s, z = false) small_smooth(c, L, x, b, z, st);
+    if (z) launch_fill(x, L.N, 0.0, st);
+    launch_csr_mv(L.N, L.ptr.as<int>(), L.col.as<int>(), L.val.as<double>(), x, b, L.r.as<double>(), -1.0, 1.0, st);
+    launch_csr_mv(C.N, L.rptr.as<int>(), L.rcol.as<int>(), L.rval.as<double>(), L.r.as<double>(), nullptr,
+                  C.b.as<double>(), 1.0, 0.0, st);
+    small_cycle(c, k + 1, C.b.as<double>(), C.x.as<double>(), true, vonly, st);
+    if (!vonly && o.gamma > 1 && g >= o.gamma_from && (o.gamma_to == 0 || g < o.gamma_to) && g + 2 < nl)
+        for (int gg = 1; gg < o.gamma; ++gg)
+            small_cycle(c, k + 1, C.b.as<double>(), C.x.as<double>(), false, o.fcycle != 0, st);
+    launch_csr_mv(L.N, L.pptr.as<int>(), L.pcol.as<int>(), L.pval.as<double>(), C.x.as<double>(), x, x, 1.0, 1.0, st);
+    for (int s = 0; s < o.nu2; ++s) small_smooth(c, L, x, b, false, st);
+}
+
+// entry from the structured cycle at level small_from: b and x0 (or nullptr) padded; the result
+// is packed into buf0 (zero on absent DoFs, as every iterate buffer)
+static double* small_entry(biot_ctx* c, const double* b, double* buf0, double* x0, bool vonly, hipStream_t st) {
+    const Level& lv = *c->levels[c->small_from];
+    SpLevel& L = *c->small->lv[0];
+    launch_unpack(b, L.b.as<double>(), lv.L, lv.C, st);
+    if (x0) launch_unpack(x0, L.x.as<double>(), lv.L, lv.C, st);
+    small_cycle(c, 0, L.b.as<double>(), L.x.as<double>(), x0 == nullptr, vonly, st);
+    launch_pack(L.x.as<double>(), buf0, lv.L, lv.C, st);
+    return buf0;
 }
 
 // vector length of the Krylov solve: padded finest level, or the compact free DoFs
@@ -1302,6 +1448,9 @@ int biot_setup_hierarchy(biot_ctx* c, const biot_mg_opts* o, void* stream) {
         require(o->schur_cg >= 0 && o->schur_cg <= 64, "schur_cg in [0, 64]");
         require(o->schur_cg == 0 || o->schur_sweeps <= 1, "schur_cg and schur_sweeps > 1 exclude each other");
         require(std::isfinite(o->vanka_shift) && o->vanka_shift >= 0, "vanka_shift >= 0");
+        require(o->csr_below >= 0, "csr_below >= 0");
+        require(o->csr_below == 0 || (o->smoother == BIOT_SMOOTHER_VANKA && o->precision == BIOT_PREC_FP64),
+                "csr_below: FP64 Vanka only");
         const int nc = c->n >> (o->levels - 1);
         require(nc <= 16, "coarsest mesh must have at most 16 cells per side (dense direct solve)");
         hipStream_t st = S(stream);
@@ -1346,6 +1495,7 @@ int biot_setup_hierarchy(biot_ctx* c, const biot_mg_opts* o, void* stream) {
         if (o->smoother == BIOT_SMOOTHER_BSR) levels_bsr(c, st);
         coarse_setup(c, st);
         coarse_factor(c, st);
+        small_setup(c, st);
         check_stream_error();
         BIOT_HIP(hipStreamSynchronize(st));
         c->have_hierarchy = true;
@@ -1530,6 +1680,7 @@ static int update_perm(biot_ctx* c, const double* field, int mode, void* stream)
     if (c->have_hierarchy) levels_factors(c, st);
     if (c->have_hierarchy && c->opts.smoother == BIOT_SMOOTHER_BSR) levels_bsr(c, st);
     if (c->have_hierarchy) coarse_factor(c, st);
+    if (c->have_hierarchy && c->small) small_refresh(c, st);
     check_stream_error();
     return BIOT_OK;
 }

@@ -58,7 +58,7 @@ CsrHost csr_transpose(const CsrHost& a);
 // 20-slot vertex patches (slot order of the layout export in the ABI), -1 for absent or
 // eliminated DoFs; only vertices whose patch holds a free displacement or Darcy DoF are kept,
 // in row-major (j, i) order.  Returns npatch x PATCH ints.
-std::vector<int> build_patches(const FreeMap& m);
+std::vector<int> build_patches(const FreeMap& m, std::vector<int>* verts = nullptr);
 
 // local tables shared with the structured path (host_tables.cpp)
 void element_matrices(const PhysParams& p, double h, double A[2][13][13], bool kw[2][13][13]);
@@ -95,5 +95,11 @@ void launch_patch_gather(int N, const int* dptr, const int* dlist, const double*
                          const double* x, double* xout, hipStream_t st);
 // row-major dense copy of a CSR matrix (N x N)
 void launch_csr_to_dense(int N, const int* ptr, const int* col, const double* val, double* D, hipStream_t st);
+// one colour step of multiplicative Vanka on explicit inverses: for the npc patches plist[k] of
+// one colour (no two share a DoF), x[slots[p][a]] += omega (A_p^{-1} V_p r)[a]
+void launch_patch_apply_add(int npc, const int* plist, const int* slots, const double* inv, const double* r,
+                            double omega, double* x, hipStream_t st);
+// per-triangle 1/K of a level of the padded layout (two planes) in the flat triangle order
+void launch_kinv_unpad(const Layout& L, const double* kinv_padded, double* flat, hipStream_t st);
 
 }  // namespace biot

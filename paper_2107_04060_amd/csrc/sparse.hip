@@ -186,6 +186,49 @@ __global__ __launch_bounds__(TPB) void k_patch_apply(int np, const int* __restri
     y[t] = slots[t] >= 0 ? v : 0.0;
 }
 
+// multiplicative colour step: as k_patch_apply for the colour's patches, the correction added
+// to the iterate in place (the colour's patches are disjoint: every DoF is written by at most one
+// thread)
+__global__ __launch_bounds__(TPB) void k_patch_apply_add(int npc, const int* __restrict__ plist,
+                                                         const int* __restrict__ slots,
+                                                         const double* __restrict__ inv, const double* __restrict__ r,
+                                                         double omega, double* __restrict__ x) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)npc * PATCH) return;
+    const long long k = t / PATCH;
+    const int a = (int)(t - k * PATCH);
+    const long long p = plist[k];
+    const int4* s4 = reinterpret_cast<const int4*>(slots + p * PATCH);
+    int q[PATCH];
+#pragma unroll
+    for (int m = 0; m < PATCH / 4; ++m) {
+        const int4 v = s4[m];
+        q[4 * m] = v.x;
+        q[4 * m + 1] = v.y;
+        q[4 * m + 2] = v.z;
+        q[4 * m + 3] = v.w;
+    }
+    const double* A = inv + p * PATCH * PATCH + a;
+    double v = 0.0;
+#pragma unroll
+    for (int b = 0; b < PATCH; ++b) {
+        const double rb = r[q[b] >= 0 ? q[b] : 0];
+        v += A[b * PATCH] * (q[b] >= 0 ? rb : 0.0);
+    }
+    const int d = slots[p * PATCH + a];
+    if (d >= 0) x[d] += omega * v;
+}
+
+__global__ __launch_bounds__(TPB) void k_kinv_unpad(Layout L, const double* __restrict__ kp, double* __restrict__ kf) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long nn = (long long)L.n * L.n;
+    if (q >= 2 * nn) return;
+    const int u = q >= nn;
+    const long long c = q - u * nn;
+    const int i = (int)(c % L.n), j = (int)(c / L.n);
+    kf[q] = kp[u * L.plane + slot_index(L, i, j)];
+}
+
 __global__ __launch_bounds__(TPB) void k_patch_gather(int N, const int* __restrict__ dptr,
                                                       const int* __restrict__ dlist, const double* __restrict__ y,
                                                       const double* __restrict__ wgt, double omega, const double* x,
@@ -245,6 +288,17 @@ void launch_patch_gather(int N, const int* dptr, const int* dlist, const double*
                          const double* x, double* xout, hipStream_t st) {
     if (N <= 0) return;
     hipLaunchKernelGGL(k_patch_gather, dim3(blocks(N)), dim3(TPB), 0, st, N, dptr, dlist, y, wgt, omega, x, xout);
+}
+
+void launch_patch_apply_add(int npc, const int* plist, const int* slots, const double* inv, const double* r,
+                            double omega, double* x, hipStream_t st) {
+    if (npc <= 0) return;
+    hipLaunchKernelGGL(k_patch_apply_add, dim3(blocks((long long)npc * PATCH)), dim3(TPB), 0, st, npc, plist, slots,
+                       inv, r, omega, x);
+}
+
+void launch_kinv_unpad(const Layout& L, const double* kinv_padded, double* flat, hipStream_t st) {
+    hipLaunchKernelGGL(k_kinv_unpad, dim3(blocks(2LL * L.n * L.n)), dim3(TPB), 0, st, L, kinv_padded, flat);
 }
 
 void launch_csr_to_dense(int N, const int* ptr, const int* col, const double* val, double* D, hipStream_t st) {

@@ -212,9 +212,10 @@ CsrHost csr_transpose(const CsrHost& a) {
     return t;
 }
 
-std::vector<int> build_patches(const FreeMap& m) {
+std::vector<int> build_patches(const FreeMap& m, std::vector<int>* verts) {
     const int n = m.n;
     std::vector<int> out;
+    if (verts) verts->clear();
     for (int j = 0; j <= n; ++j)
         for (int i = 0; i <= n; ++i) {
             const int s[PATCH] = {
@@ -230,7 +231,10 @@ std::vector<int> build_patches(const FreeMap& m) {
                 m.index(T_PU, i - 1, j),     m.index(T_PU, i, j - 1)};
             bool keep = false;
             for (int a = 0; a < 14; ++a) keep = keep || s[a] >= 0;
-            if (keep) out.insert(out.end(), s, s + PATCH);
+            if (keep) {
+                out.insert(out.end(), s, s + PATCH);
+                if (verts) verts->push_back(j * (n + 1) + i);
+            }
         }
     return out;
 }

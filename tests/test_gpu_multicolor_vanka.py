@@ -104,27 +104,69 @@ def test_multicolor_solve_matches_oracle(binding):
     assert abs(info["iters"] - io["iters"]) <= 1
 
 
-@pytest.mark.parametrize("fcycle,ncolors,gamma_to", [(False, 4, 0), (True, 4, 0), (False, 3, 0), (False, 3, 2)])
-def test_block_workload_cycle_parity(binding, fcycle, ncolors, gamma_to):
+@pytest.mark.parametrize("fcycle,ncolors,gamma_to,csr_below", [(False, 4, 0, 0), (True, 4, 0, 0), (False, 3, 0, 0),
+                                                                 (False, 3, 2, 0), (False, 3, 0, 32), (False, 3, 0, 16),
+                                                                 (True, 4, 0, 32), (False, 0, 0, 32)])
+def test_block_workload_cycle_parity(binding, fcycle, ncolors, gamma_to, csr_below):
+    """csr_below > 0: the levels with at most that many cells per side (below the finest) smooth
+    on CSR operators and explicit patch inverses; the cycle is the same."""
     n, levels = 64, 5
-    print("block-contrast cycle n=%d %s-cycle, %d colours, gamma_to %d" % (n, "F" if fcycle else "W", ncolors, gamma_to),
-          flush=True)
+    print("block-contrast cycle n=%d %s-cycle, %d colours, gamma_to %d, csr_below %d"
+          % (n, "F" if fcycle else "W", ncolors, gamma_to, csr_below), flush=True)
     K = block_perm(n)
     lam, mu, al, M, mf_, tau = case("block")
     s = binding.BiotSolver(n, lam, mu, alpha=al, M=M, mu_f=mf_, tau=tau,
                            K=torch.tensor(K, dtype=torch.float64, device="cuda"))
-    cyc = dict(nu1=1, nu2=1, omega=1.1, vanka_colors=ncolors, gamma=2, gamma_from=1, fcycle=fcycle, gamma_to=gamma_to)
-    s.setup(levels=levels, smoother="vanka", **cyc)
+    cyc = dict(nu1=1, nu2=1, omega=1.1 if ncolors else 0.7, vanka_colors=ncolors, gamma=2, gamma_from=1,
+               fcycle=fcycle, gamma_to=gamma_to)
+    s.setup(levels=levels, smoother="vanka", csr_below=csr_below, **cyc)
     H = Hierarchy(n, params("block"), K_tri=K, smoother="vanka", levels=levels, **cyc)
     r = inputs.rhs_uniform(n, 8)
     z = s.vcycle(_t(r)).cpu().numpy()
     s.close()
-    conds = [np.linalg.cond(Al).max() for lev in H.levels[:-1] for g in lev.smoother.colors for _, Al in g]
+    if ncolors:
+        conds = [np.linalg.cond(Al).max() for lev in H.levels[:-1] for g in lev.smoother.colors for _, Al in g]
+    else:
+        conds = [np.linalg.cond(B).max() for lev in H.levels[:-1] for _, B in lev.smoother.groups]
     conds.append(np.linalg.cond(H.levels[-1].A.toarray()))
     tol, kap = tol_from_conds(conds)
     err = rel(z, H.vcycle(r))
     print("  rel diff %.2e  tol %.2e  (kappa %.2e)" % (err, tol, kap), flush=True)
     assert err < tol
+
+
+def test_csr_small_levels_solve_and_update(binding):
+    """The block workload's solver at n = 128 with the levels of 32 x 32 cells and below on CSR
+    (csr_below = 32): the same FGMRES iteration count and the same solution as the stencil
+    levels (to the solve's tolerance), and after a permeability update the small levels are
+    re-assembled (the cycle matches the oracle's on the new K)."""
+    n, levels = 128, 4
+    K = block_perm(n)
+    lam, mu, al, M, mf_, tau = case("block")
+    cyc = dict(nu1=1, nu2=1, omega=1.1, vanka_colors=3, gamma=2, gamma_from=1)
+    Kt = torch.tensor(K, dtype=torch.float64, device="cuda")
+    s0 = binding.BiotSolver(n, lam, mu, alpha=al, M=M, mu_f=mf_, tau=tau, K=Kt)
+    s0.setup(levels=levels, smoother="vanka", **cyc)
+    s1 = binding.BiotSolver(n, lam, mu, alpha=al, M=M, mu_f=mf_, tau=tau, K=Kt)
+    s1.setup(levels=levels, smoother="vanka", csr_below=32, **cyc)
+    b = _t(inputs.rhs_uniform(n, 3))
+    x0, i0 = s0.solve(b, tol=1e-8, restart=100, maxit=300)
+    x1, i1 = s1.solve(b, tol=1e-8, restart=100, maxit=300)
+    d = rel(x1.cpu().numpy(), x0.cpu().numpy())
+    print("  csr_below 32: %d iterations (%.2e), stencil levels %d (%.2e), solution rel diff %.2e"
+          % (i1["iters"], i1["rel_res_true"], i0["iters"], i0["rel_res_true"], d), flush=True)
+    assert i0["converged"] and i1["converged"] and abs(i1["iters"] - i0["iters"]) <= 1
+    assert d < 1e-6
+    K2 = K * np.exp(np.random.default_rng(31).uniform(-1, 1, K.size))
+    s1.update_K(torch.tensor(K2, dtype=torch.float64, device="cuda"))
+    r = inputs.rhs_uniform(n, 9)
+    z = s1.vcycle(_t(r)).cpu().numpy()
+    s0.close()
+    s1.close()
+    H = Hierarchy(n, params("block"), K_tri=K2, smoother="vanka", levels=levels, **cyc)
+    err = rel(z, H.vcycle(r))
+    print("  after update_K: cycle rel diff %.2e" % err, flush=True)
+    assert err < 1e-8
 
 
 def test_block_workload_solve_matches_oracle(binding):
