@@ -36,8 +36,8 @@ BLOCK_REORTH = 0.01          # its Gram-Schmidt threshold: a second pass after t
 # the cycle of the block-contrast workload: the fastest to 1e-8 among the V-, W- and partial
 # W-cycles with additive and multiplicative Vanka and 8 to 10 levels measured on it (the
 # V(2,2) cycle with the LFA weight on 10 levels takes 178 iterations, 3.6 s per solve); the levels
-# of 64 x 64 cells and below smooth on CSR operators with explicit patch inverses (468 -> 408 ms
-# per solve; 32: 427, 128: 412, 256: 441)
+# of 64 x 64 cells and below smooth on CSR operators with explicit patch inverses (468 -> 395 ms
+# per solve with the fused colour step; 128: 395, 256: 428)
 BLOCK_CYCLE = dict(nu12=1, omega=1.1, colors=3, gamma=2, gamma_from=1, levels=8, fcycle=0, csr_below=64)
 CSRC = os.path.join(ROOT, "paper_2107_04060_amd", "csrc")
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_vanka_step_sweep256_fp64.md")

@@ -862,16 +862,10 @@ static void small_smooth(biot_ctx* c, SpLevel& L, double* x, const double* b, bo
         return;
     }
     if (zero) launch_fill(x, L.N, 0.0, st);
-    for (int col = 0; col < nc; ++col) {
-        const double* r = b;
-        if (!(zero && col == 0)) {
-            launch_csr_mv(L.N, L.ptr.as<int>(), L.col.as<int>(), L.val.as<double>(), x, b, L.r.as<double>(), -1.0,
-                          1.0, st);
-            r = L.r.as<double>();
-        }
-        launch_patch_apply_add(L.coff[(size_t)col + 1] - L.coff[col], L.clist.as<int>() + L.coff[col],
-                               L.slots.as<int>(), L.inv.as<double>(), r, om, x, st);
-    }
+    for (int col = 0; col < nc; ++col)
+        launch_colour_step(L.coff[(size_t)col + 1] - L.coff[col], L.clist.as<int>() + L.coff[col], L.slots.as<int>(),
+                           L.inv.as<double>(), L.ptr.as<int>(), L.col.as<int>(), L.val.as<double>(), b, x, om,
+                           zero && col == 0, st);
 }
 
 // the cycle on small level k (global level small_from + k), as vcycle_level: from zero or from

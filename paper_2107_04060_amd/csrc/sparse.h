@@ -99,6 +99,12 @@ void launch_csr_to_dense(int N, const int* ptr, const int* col, const double* va
 // one colour (no two share a DoF), x[slots[p][a]] += omega (A_p^{-1} V_p r)[a]
 void launch_patch_apply_add(int npc, const int* plist, const int* slots, const double* inv, const double* r,
                             double omega, double* x, hipStream_t st);
+// the same colour step fused with its residual, in place: for the colour's patches (vertices of
+// one colour share no mesh edge, so a patch's residual rows read no DoF another patch of the
+// colour writes), r = b - A x on the patch rows, then x += omega A_p^{-1} r; xzero: x = 0 on
+// entry (r = b; x must hold zeros)
+void launch_colour_step(int npc, const int* plist, const int* slots, const double* inv, const int* ptr, const int* col,
+                        const double* val, const double* b, double* x, double omega, bool xzero, hipStream_t st);
 // per-triangle 1/K of a level of the padded layout (two planes) in the flat triangle order
 void launch_kinv_unpad(const Layout& L, const double* kinv_padded, double* flat, hipStream_t st);
 

@@ -219,6 +219,53 @@ __global__ __launch_bounds__(TPB) void k_patch_apply_add(int npc, const int* __r
     if (d >= 0) x[d] += omega * v;
 }
 
+// One fused colour step of multiplicative Vanka, in place: per patch of the colour, the residual
+// of its 20 rows (LPR_C lanes per row, butterfly sum), then the explicit inverse applied and the
+// correction added to x.  In place is safe: a patch's rows couple only DoFs on the triangles of
+// its vertex's star, and no other patch of the colour owns one of those (vertices of one colour
+// share no mesh edge, so their stars share no triangle, edge or vertex); every x a block reads
+// is therefore either its own patch's, written by the block after its reads, or another
+// colour's, not written in this launch.  xzero: x = 0 on entry (the residual is b).
+constexpr int LPR_C = 4;                                  // lanes per row
+constexpr int PPB_C = TPB / (PATCH * LPR_C);              // patches per block (3)
+__global__ __launch_bounds__(TPB) void k_colour_step(int npc, const int* __restrict__ plist,
+                                                     const int* __restrict__ slots, const double* __restrict__ inv,
+                                                     const int* __restrict__ ptr, const int* __restrict__ col,
+                                                     const double* __restrict__ val, const double* __restrict__ b,
+                                                     double* x, double omega, int xzero) {
+    __shared__ double rsh[PPB_C][PATCH];
+    const int t = threadIdx.x;
+    const int k0 = blockIdx.x * PPB_C;
+    // phase 1: residual rows
+    {
+        const int kl = t / (PATCH * LPR_C), a = (t / LPR_C) % PATCH, sub = t % LPR_C;
+        const int k = k0 + kl;
+        int d = -1;
+        if (kl < PPB_C && k < npc) d = slots[(long long)plist[k] * PATCH + a];
+        double s = 0.0;
+        if (d >= 0 && !xzero)
+            for (int q = ptr[d] + sub; q < ptr[d + 1]; q += LPR_C) s += val[q] * x[col[q]];
+#pragma unroll
+        for (int o = LPR_C / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, LPR_C);
+        if (kl < PPB_C && sub == 0) rsh[kl][a] = d >= 0 ? b[d] - s : 0.0;
+    }
+    __syncthreads();
+    // phase 2: correction of slot a of patch kl
+    if (t < PPB_C * PATCH) {
+        const int kl = t / PATCH, a = t % PATCH;
+        const int k = k0 + kl;
+        if (k < npc) {
+            const long long p = plist[k];
+            const double* A = inv + p * PATCH * PATCH + a;
+            double v = 0.0;
+#pragma unroll
+            for (int bb = 0; bb < PATCH; ++bb) v += A[bb * PATCH] * rsh[kl][bb];
+            const int d = slots[p * PATCH + a];
+            if (d >= 0) x[d] += omega * v;
+        }
+    }
+}
+
 __global__ __launch_bounds__(TPB) void k_kinv_unpad(Layout L, const double* __restrict__ kp, double* __restrict__ kf) {
     const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long nn = (long long)L.n * L.n;
@@ -295,6 +342,13 @@ void launch_patch_apply_add(int npc, const int* plist, const int* slots, const d
     if (npc <= 0) return;
     hipLaunchKernelGGL(k_patch_apply_add, dim3(blocks((long long)npc * PATCH)), dim3(TPB), 0, st, npc, plist, slots,
                        inv, r, omega, x);
+}
+
+void launch_colour_step(int npc, const int* plist, const int* slots, const double* inv, const int* ptr, const int* col,
+                        const double* val, const double* b, double* x, double omega, bool xzero, hipStream_t st) {
+    if (npc <= 0) return;
+    hipLaunchKernelGGL(k_colour_step, dim3((unsigned)((npc + PPB_C - 1) / PPB_C)), dim3(TPB), 0, st, npc, plist, slots,
+                       inv, ptr, col, val, b, x, omega, xzero ? 1 : 0);
 }
 
 void launch_kinv_unpad(const Layout& L, const double* kinv_padded, double* flat, hipStream_t st) {
