@@ -106,6 +106,9 @@ def parse():
     ap.add_argument("--fcycle", type=int, default=BLOCK_CYCLE["fcycle"], choices=[0, 1],
                     help="block2048: 1 = the repeated coarse corrections are V-cycles (F-cycle), 0 = W-cycle")
     ap.add_argument("--restart", type=int, default=BLOCK_RESTART, help="block2048: FGMRES restart")
+    ap.add_argument("--additive-levels", type=int, default=0,
+                    help="block2048: the finest levels taking the additive step instead of the colours")
+    ap.add_argument("--omega-additive", type=float, default=0.0, help="block2048: their weight (0: --omega)")
     ap.add_argument("--csr-below", type=int, default=BLOCK_CYCLE["csr_below"],
                     help="block2048, FP64 form: levels below the finest with at most this many cells per side "
                          "smooth on CSR operators and explicit patch inverses (0: off)")
@@ -485,7 +488,8 @@ def main_block2048(args, binding, inputs, torch):
     K = torch.tensor(inputs.permeability_triangles("block2048"), dtype=torch.float64, device="cuda")
     om, omj = args.omega, 1.0
     cyc = dict(nu1=args.nu12, nu2=args.nu12, omega=om, omega_J=omj, gamma=args.gamma, gamma_from=args.gamma_from,
-               vanka_colors=args.colors, fcycle=bool(args.fcycle))
+               vanka_colors=args.colors, fcycle=bool(args.fcycle), additive_levels=args.additive_levels,
+               omega_additive=args.omega_additive)
     restart = args.restart
     # right-hand sides k = 0 .. nrhs-1 of the seed stream (row k of rhs_uniform(n, seed, nrhs)),
     # uploaded before anything is timed; warm-up steps take the first ones, timed steps the next

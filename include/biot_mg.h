@@ -169,9 +169,13 @@ typedef struct {
     int csr_below;      /* 0 = off; k > 0 (FP64 Vanka, Dirichlet): the smoothing levels below the
                            finest with n_l <= k cells per side run on compressed-row operators and
                            explicit patch inverses instead of the fused stencil kernels (the same
-                           operator, patches, colours and cycle; two short launches per colour step
-                           where one fused launch is bound by the latency of a single block).  A
-                           performance option: the result is the same up to rounding.          */
+                           operator, patches, colours and cycle; one short launch per colour step
+                           where the fused stencil launch is bound by the latency of a single
+                           block).  A performance option: the result is the same up to rounding. */
+    int additive_levels;/* with vanka_colors 3 or 4: the finest additive_levels levels take the
+                           additive step (Sec. 3.2.1, weights D_l) instead of the colours, the
+                           coarser ones the multiplicative form; 0 = every level multiplicative */
+    double omega_additive; /* the weight of those additive levels; 0 = omega                   */
 } biot_mg_opts;
 
 /* FGMRES controls (in) and results (out). */

@@ -36,7 +36,7 @@ class Hierarchy:
     def __init__(self, n, params, K_tri=1.0, smoother="vanka", omega=1.0, omega_J=1.0,
                  nu1=1, nu2=1, n_coarse=4, levels=None, schur_sweeps=1, omega_S=1.0, gamma=1,
                  vanka_colors=0, schur_cg=0, gamma_from=0, fcycle=False, bc="dirichlet", vanka_shift=0.0,
-                 gamma_to=0):
+                 gamma_to=0, additive_levels=0, omega_additive=0.0):
         if levels is not None:
             n_coarse = n >> (levels - 1)
         self.params = params
@@ -59,8 +59,14 @@ class Hierarchy:
             nn //= 2
         for l in range(len(self.levels) - 1):
             _, self.levels[l].P = prolongation(self.levels[l].mesh, self.levels[l + 1].mesh)
-        for lev in self.levels[:-1]:
-            if smoother == "vanka" and vanka_colors:
+        # additive_levels: with vanka_colors, the finest levels take the additive step (weight
+        # omega_additive, or omega when 0) and the coarser ones the colours
+        for l, lev in enumerate(self.levels[:-1]):
+            if smoother == "vanka" and vanka_colors and l < additive_levels:
+                _, slots = patch_table(lev.mesh, "full")
+                lev.smoother = AdditiveVanka(lev.A, slots, omega_additive if omega_additive > 0 else omega,
+                                             vanka_shift, lev.mesh.n_u + lev.mesh.n_w)
+            elif smoother == "vanka" and vanka_colors:
                 if vanka_colors not in (3, 4):
                     raise ValueError("vanka_colors: 0 (additive), 3 or 4")
                 lev.smoother = MulticolorVanka(lev.A, lev.mesh, omega, vanka_colors)

@@ -46,7 +46,8 @@ class MGOpts(ctypes.Structure):
                 ("precision", ctypes.c_int), ("schur_sweeps", ctypes.c_int), ("omega_S", ctypes.c_double),
                 ("gamma", ctypes.c_int), ("vanka_colors", ctypes.c_int), ("schur_cg", ctypes.c_int),
                 ("gamma_from", ctypes.c_int), ("fcycle", ctypes.c_int), ("gamma_to", ctypes.c_int),
-                ("vanka_shift", ctypes.c_double), ("csr_below", ctypes.c_int)]
+                ("vanka_shift", ctypes.c_double), ("csr_below", ctypes.c_int), ("additive_levels", ctypes.c_int),
+                ("omega_additive", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -162,13 +163,15 @@ class BiotSolver:
 
     def setup(self, levels, smoother="vanka", nu1=2, nu2=2, omega=0.8, omega_J=1.0, precision="fp64",
               schur_sweeps=1, omega_S=1.0, gamma=1, vanka_colors=0, schur_cg=0, gamma_from=0, fcycle=False,
-              gamma_to=0, vanka_shift=0.0, csr_below=0):
+              gamma_to=0, vanka_shift=0.0, csr_below=0, additive_levels=0, omega_additive=0.0):
         """csr_below: levels below the finest with at most this many cells per side smooth on
-        CSR operators and explicit patch inverses (FP64 Vanka; the same cycle up to rounding)."""
+        CSR operators and explicit patch inverses (FP64 Vanka; the same cycle up to rounding).
+        additive_levels, omega_additive: with vanka_colors, the finest additive_levels levels take
+        the additive step with weight omega_additive (0: omega)."""
         o = MGOpts(int(levels), SMOOTHERS[smoother], int(nu1), int(nu2), float(omega), float(omega_J),
                    PRECISIONS[precision], int(schur_sweeps), float(omega_S), int(gamma), int(vanka_colors),
                    int(schur_cg), int(gamma_from), int(bool(fcycle)), int(gamma_to), float(vanka_shift),
-                   int(csr_below))
+                   int(csr_below), int(additive_levels), float(omega_additive))
         _check(load().biot_setup_hierarchy(self._ctx, ctypes.byref(o), _stream()))
         self.levels = int(levels)
         return self

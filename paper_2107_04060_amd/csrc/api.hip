@@ -477,6 +477,12 @@ static int vanka_colors(const biot_mg_opts& o) {
     return o.smoother == BIOT_SMOOTHER_VANKA && (o.vanka_colors == 3 || o.vanka_colors == 4) ? o.vanka_colors : 1;
 }
 
+// colours and weight of level l: the finest additive_levels levels take the additive step
+static int vanka_colors_at(const biot_mg_opts& o, int l) { return l < o.additive_levels ? 1 : vanka_colors(o); }
+static double omega_at(const biot_mg_opts& o, int l) {
+    return l < o.additive_levels && o.omega_additive > 0 ? o.omega_additive : o.omega;
+}
+
 // the kernel's colour code of colour col of nc (-1: the additive step)
 static int color_code(int nc, int col) { return nc == 4 ? col : (nc == 3 ? 4 + col : -1); }
 
@@ -488,9 +494,9 @@ template <typename T>
 static T* relax(biot_ctx* c, int l, const T* x, const T* b, T* dst, T* alt, hipStream_t st) {
     Level& lv = *c->levels[l];
     LevelView<T> v = lv.view<T>();
-    const T om = (T)c->opts.omega;
+    const T om = (T)omega_at(c->opts, l);
     if (c->opts.smoother == BIOT_SMOOTHER_VANKA) {
-        const int nc = vanka_colors(c->opts);
+        const int nc = vanka_colors_at(c->opts, l);
         if (nc > 1 && (!alt || alt == dst)) throw ArgError{"multiplicative Vanka needs a second buffer"};
         const T* src = x;
         T* out = dst;
@@ -511,9 +517,9 @@ static T* relax(biot_ctx* c, int l, const T* x, const T* b, T* dst, T* alt, hipS
 
 // Times the iterate moves to the other buffer during the smoothing on one level (the first
 // step from zero writes buffer 0).
-static int buffer_moves(const biot_mg_opts& o) {
+static int buffer_moves(const biot_mg_opts& o, int l) {
     if (o.smoother != BIOT_SMOOTHER_VANKA) return 0;
-    const int nc = vanka_colors(o);
+    const int nc = vanka_colors_at(o, l);
     return (o.nu1 > 0 ? o.nu1 * nc - 1 : 0) + o.nu2 * nc;
 }
 
@@ -580,10 +586,10 @@ static T* vcycle_level(biot_ctx* c, int l, const T* b, T* buf0, T* buf1, hipStre
         const T kinv_s = (T)(1.0 / c->K_scalar);
         if (!inplace) {
             // multiplicative form: colour 0 with the prolongation, then colours 1..3
-            const int nc = vanka_colors(c->opts);
+            const int nc = vanka_colors_at(c->opts, l);
             for (int col = 0; col < nc; ++col) {
                 T* dst = next();
-                launch_vanka_step<T>(lv.view<T>(), cur, b, dst, c->K_uniform, kinv_s, (T)c->opts.omega, st,
+                launch_vanka_step<T>(lv.view<T>(), cur, b, dst, c->K_uniform, kinv_s, (T)omega_at(c->opts, l), st,
                                      col == 0 ? xc : nullptr, &lc.L, PW<T>::get(c), nullptr, color_code(nc, col));
                 cur = dst;
             }
@@ -843,7 +849,8 @@ static void small_setup(biot_ctx* c, hipStream_t st) {
         H->lv.emplace_back(new SpLevel);
         sp_level_alloc(*H->lv.back(), c->n >> l, BC_DIRICHLET, c->phys, st);
     }
-    for (size_t k = 0; k + 1 < H->lv.size(); ++k) sp_level_links(*H->lv[k], *H->lv[k + 1], st, vanka_colors(o));
+    for (size_t k = 0; k + 1 < H->lv.size(); ++k)
+        sp_level_links(*H->lv[k], *H->lv[k + 1], st, vanka_colors_at(o, s + (int)k));
     std::vector<int> idx((size_t)c->coarse_N);
     for (int k = 0; k < c->coarse_N; ++k) idx[k] = k;
     upload(H->cidx, idx, st);
@@ -853,10 +860,10 @@ static void small_setup(biot_ctx* c, hipStream_t st) {
     small_refresh(c, st);
 }
 
-// one smoothing step on small level k (additive, or the colours in turn), x in place
-static void small_smooth(biot_ctx* c, SpLevel& L, double* x, const double* b, bool zero, hipStream_t st) {
-    const int nc = vanka_colors(c->opts);
-    const double om = c->opts.omega;
+// one smoothing step on small level g (additive, or the colours in turn), x in place
+static void small_smooth(biot_ctx* c, int g, SpLevel& L, double* x, const double* b, bool zero, hipStream_t st) {
+    const int nc = vanka_colors_at(c->opts, g);
+    const double om = omega_at(c->opts, g);
     if (nc == 1) {
         sp_smooth_level(L, om, x, b, zero, st);
         return;
@@ -882,7 +889,7 @@ static void small_cycle(biot_ctx* c, int k, const double* b, double* x, bool zer
     SpLevel& L = *H.lv[k];
     SpLevel& C = *H.lv[(size_t)k + 1];
     bool z = zero;
-    for (int s = 0; s < o.nu1; ++s, z = false) small_smooth(c, L, x, b, z, st);
+    for (int s = 0; s < o.nu1; ++s, z = false) small_smooth(c, g, L, x, b, z, st);
     if (z) launch_fill(x, L.N, 0.0, st);
     launch_csr_mv(L.N, L.ptr.as<int>(), L.col.as<int>(), L.val.as<double>(), x, b, L.r.as<double>(), -1.0, 1.0, st);
     launch_csr_mv(C.N, L.rptr.as<int>(), L.rcol.as<int>(), L.rval.as<double>(), L.r.as<double>(), nullptr,
@@ -892,7 +899,7 @@ static void small_cycle(biot_ctx* c, int k, const double* b, double* x, bool zer
         for (int gg = 1; gg < o.gamma; ++gg)
             small_cycle(c, k + 1, C.b.as<double>(), C.x.as<double>(), false, o.fcycle != 0, st);
     launch_csr_mv(L.N, L.pptr.as<int>(), L.pcol.as<int>(), L.pval.as<double>(), C.x.as<double>(), x, x, 1.0, 1.0, st);
-    for (int s = 0; s < o.nu2; ++s) small_smooth(c, L, x, b, false, st);
+    for (int s = 0; s < o.nu2; ++s) small_smooth(c, g, L, x, b, false, st);
 }
 
 // entry from the structured cycle at level small_from: b and x0 (or nullptr) padded; the result
@@ -946,7 +953,7 @@ static void precond(biot_ctx* c, const double* v, double* z, hipStream_t st) {
     Level& l0 = *c->levels[0];
     if (c->opts.precision == BIOT_PREC_FP64) {
         // start in the buffer that makes the last step land in z
-        const bool even = buffer_moves(c->opts) % 2 == 0;
+        const bool even = buffer_moves(c->opts, 0) % 2 == 0;
         double* other = l0.x64.as<double>();
         double* res = vcycle_level<double>(c, 0, v, even ? z : other, even ? other : z, st);
         if (res != z) BIOT_HIP(hipMemcpyAsync(z, res, l0.L.len * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -1443,6 +1450,8 @@ int biot_setup_hierarchy(biot_ctx* c, const biot_mg_opts* o, void* stream) {
         require(o->schur_cg == 0 || o->schur_sweeps <= 1, "schur_cg and schur_sweeps > 1 exclude each other");
         require(std::isfinite(o->vanka_shift) && o->vanka_shift >= 0, "vanka_shift >= 0");
         require(o->csr_below >= 0, "csr_below >= 0");
+        require(o->additive_levels >= 0 && o->additive_levels < o->levels, "additive_levels in [0, levels)");
+        require(std::isfinite(o->omega_additive) && o->omega_additive >= 0, "omega_additive >= 0");
         require(o->csr_below == 0 || (o->smoother == BIOT_SMOOTHER_VANKA && o->precision == BIOT_PREC_FP64),
                 "csr_below: FP64 Vanka only");
         const int nc = c->n >> (o->levels - 1);

@@ -104,30 +104,33 @@ def test_multicolor_solve_matches_oracle(binding):
     assert abs(info["iters"] - io["iters"]) <= 1
 
 
-@pytest.mark.parametrize("fcycle,ncolors,gamma_to,csr_below", [(False, 4, 0, 0), (True, 4, 0, 0), (False, 3, 0, 0),
-                                                                 (False, 3, 2, 0), (False, 3, 0, 32), (False, 3, 0, 16),
-                                                                 (True, 4, 0, 32), (False, 0, 0, 32)])
-def test_block_workload_cycle_parity(binding, fcycle, ncolors, gamma_to, csr_below):
+@pytest.mark.parametrize("fcycle,ncolors,gamma_to,csr_below,add", [
+    (False, 4, 0, 0, 0), (True, 4, 0, 0, 0), (False, 3, 0, 0, 0), (False, 3, 2, 0, 0), (False, 3, 0, 32, 0),
+    (False, 3, 0, 16, 0), (True, 4, 0, 32, 0), (False, 0, 0, 32, 0), (False, 3, 0, 0, 1), (False, 3, 0, 32, 2)])
+def test_block_workload_cycle_parity(binding, fcycle, ncolors, gamma_to, csr_below, add):
     """csr_below > 0: the levels with at most that many cells per side (below the finest) smooth
-    on CSR operators and explicit patch inverses; the cycle is the same."""
+    on CSR operators and explicit patch inverses; the cycle is the same.  add > 0: the finest
+    `add` levels take the additive step (weight 0.7), the coarser ones the colours."""
     n, levels = 64, 5
-    print("block-contrast cycle n=%d %s-cycle, %d colours, gamma_to %d, csr_below %d"
-          % (n, "F" if fcycle else "W", ncolors, gamma_to, csr_below), flush=True)
+    print("block-contrast cycle n=%d %s-cycle, %d colours, gamma_to %d, csr_below %d, additive levels %d"
+          % (n, "F" if fcycle else "W", ncolors, gamma_to, csr_below, add), flush=True)
     K = block_perm(n)
     lam, mu, al, M, mf_, tau = case("block")
     s = binding.BiotSolver(n, lam, mu, alpha=al, M=M, mu_f=mf_, tau=tau,
                            K=torch.tensor(K, dtype=torch.float64, device="cuda"))
     cyc = dict(nu1=1, nu2=1, omega=1.1 if ncolors else 0.7, vanka_colors=ncolors, gamma=2, gamma_from=1,
-               fcycle=fcycle, gamma_to=gamma_to)
+               fcycle=fcycle, gamma_to=gamma_to, additive_levels=add, omega_additive=0.7 if add else 0.0)
     s.setup(levels=levels, smoother="vanka", csr_below=csr_below, **cyc)
     H = Hierarchy(n, params("block"), K_tri=K, smoother="vanka", levels=levels, **cyc)
     r = inputs.rhs_uniform(n, 8)
     z = s.vcycle(_t(r)).cpu().numpy()
     s.close()
-    if ncolors:
-        conds = [np.linalg.cond(Al).max() for lev in H.levels[:-1] for g in lev.smoother.colors for _, Al in g]
-    else:
-        conds = [np.linalg.cond(B).max() for lev in H.levels[:-1] for _, B in lev.smoother.groups]
+    conds = []
+    for lev in H.levels[:-1]:
+        if hasattr(lev.smoother, "colors"):
+            conds += [np.linalg.cond(Al).max() for g in lev.smoother.colors for _, Al in g]
+        else:
+            conds += [np.linalg.cond(B).max() for _, B in lev.smoother.groups]
     conds.append(np.linalg.cond(H.levels[-1].A.toarray()))
     tol, kap = tol_from_conds(conds)
     err = rel(z, H.vcycle(r))

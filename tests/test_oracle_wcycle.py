@@ -159,3 +159,19 @@ def test_gamma_to_stops_the_repetition():
     assert _count_visits(Hierarchy(n, _P(), gamma=2, gamma_from=0, gamma_to=2, **kw), b) == [1, 2, 4, 4, 4]
     v = Hierarchy(n, _P(), **kw).vcycle(b)
     assert np.array_equal(Hierarchy(n, _P(), gamma=2, gamma_from=2, gamma_to=2, **kw).vcycle(b), v)
+
+
+def test_additive_levels_pins():
+    """additive_levels = 0 is the multiplicative hierarchy; additive_levels = levels - 1 (every
+    smoothing level additive, with omega_additive) is the additive hierarchy of that weight; one
+    additive level is neither (the finest level's smoother is additive, the rest coloured)."""
+    n = 32
+    b = inputs.rhs_uniform(n, 11)
+    kw = dict(K_tri=1e-2, smoother="vanka", nu1=1, nu2=1, levels=4, gamma=2, gamma_from=1)
+    m = Hierarchy(n, _P(), omega=1.1, vanka_colors=3, **kw).vcycle(b)
+    assert np.array_equal(Hierarchy(n, _P(), omega=1.1, vanka_colors=3, additive_levels=0, **kw).vcycle(b), m)
+    a = Hierarchy(n, _P(), omega=0.7, **kw).vcycle(b)
+    assert np.array_equal(Hierarchy(n, _P(), omega=1.1, vanka_colors=3, additive_levels=3, omega_additive=0.7,
+                                    **kw).vcycle(b), a)
+    h = Hierarchy(n, _P(), omega=1.1, vanka_colors=3, additive_levels=1, omega_additive=0.7, **kw).vcycle(b)
+    assert np.linalg.norm(h - m) > 1e-6 * np.linalg.norm(m) and np.linalg.norm(h - a) > 1e-6 * np.linalg.norm(a)
