@@ -110,8 +110,8 @@ def parse():
                     help="block2048: the finest levels taking the additive step instead of the colours")
     ap.add_argument("--omega-additive", type=float, default=0.0, help="block2048: their weight (0: --omega)")
     ap.add_argument("--csr-below", type=int, default=BLOCK_CYCLE["csr_below"],
-                    help="block2048, FP64 form: levels below the finest with at most this many cells per side "
-                         "smooth on CSR operators and explicit patch inverses (0: off)")
+                    help="block2048: levels below the finest with at most this many cells per side smooth on CSR "
+                         "operators and explicit patch inverses, in FP64 (0: off)")
     ap.add_argument("--reorth", type=float, default=BLOCK_REORTH,
                     help="block2048: Gram-Schmidt second pass when |w1| < reorth |w0| (0: 1/sqrt(2))")
     ap.add_argument("--levels", type=int, default=BLOCK_CYCLE["levels"],
@@ -510,8 +510,7 @@ def main_block2048(args, binding, inputs, torch):
         s = binding.BiotSolver(n, c["lam"], c["mu"], alpha=w["alpha"], M=w["M"], mu_f=w["mu_f"], tau=w["tau"], K=K)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        s.setup(levels=levels, smoother="vanka", precision=form, csr_below=args.csr_below if form == "fp64" else 0,
-                **cyc)
+        s.setup(levels=levels, smoother="vanka", precision=form, csr_below=args.csr_below, **cyc)
         torch.cuda.synchronize()
         setup_s = time.perf_counter() - t0
         if fi == 0 and args.copy_calib_mb > 0:

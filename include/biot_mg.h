@@ -166,12 +166,14 @@ typedef struct {
                            Terzaghi's problem, shifts the blocks by 1e-8 because with 1/M = 0 an
                            interior patch matrix is singular, so vanka_shift > 0 is required
                            there); 0 with BIOT_BC_DIRICHLET                                   */
-    int csr_below;      /* 0 = off; k > 0 (FP64 Vanka, Dirichlet): the smoothing levels below the
+    int csr_below;      /* 0 = off; k > 0 (Vanka, Dirichlet): the smoothing levels below the
                            finest with n_l <= k cells per side run on compressed-row operators and
                            explicit patch inverses instead of the fused stencil kernels (the same
                            operator, patches, colours and cycle; one short launch per colour step
                            where the fused stencil launch is bound by the latency of a single
-                           block).  A performance option: the result is the same up to rounding. */
+                           block).  These levels compute in FP64 in every precision form (the
+                           FP32 forms convert at the first of them).  A performance option: the
+                           result is the same up to rounding.                                   */
     int additive_levels;/* with vanka_colors 3 or 4: the finest additive_levels levels take the
                            additive step (Sec. 3.2.1, weights D_l) instead of the colours, the
                            coarser ones the multiplicative form; 0 = every level multiplicative */

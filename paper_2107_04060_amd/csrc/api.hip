@@ -543,9 +543,20 @@ template <typename T>
 static T* vcycle_level(biot_ctx* c, int l, const T* b, T* buf0, T* buf1, hipStream_t st, T* x0 = nullptr,
                        bool vonly = false) {
     Level& lv = *c->levels[l];
-    if constexpr (std::is_same_v<T, double>) {
-        // the small levels run on CSR operators and explicit patch inverses
-        if (c->small && l == c->small_from) return small_entry(c, b, buf0, x0, vonly, st);
+    if (c->small && l == c->small_from) {
+        // the small levels run on CSR operators and explicit patch inverses, in FP64
+        if constexpr (std::is_same_v<T, double>) {
+            return small_entry(c, b, buf0, x0, vonly, st);
+        } else {
+            // FP32 forms: through the level's FP64 buffers (zero on absent DoFs)
+            double* bd = lv.b64.as<double>();
+            double* xd = lv.x64.as<double>();
+            launch_convert(b, bd, lv.L.len, st);
+            if (x0) launch_convert(x0, xd, lv.L.len, st);
+            double* r = small_entry(c, bd, lv.x2_64.as<double>(), x0 ? xd : nullptr, vonly, st);
+            launch_convert(r, buf0, lv.L.len, st);
+            return buf0;
+        }
     }
     if (l == (int)c->levels.size() - 1) {
         launch_coarse_solve<T>(c->coarse_inv.as<double>(), c->coarse_N, c->coarse_idx.as<int>(), b, buf0, st);
@@ -1452,8 +1463,7 @@ int biot_setup_hierarchy(biot_ctx* c, const biot_mg_opts* o, void* stream) {
         require(o->csr_below >= 0, "csr_below >= 0");
         require(o->additive_levels >= 0 && o->additive_levels < o->levels, "additive_levels in [0, levels)");
         require(std::isfinite(o->omega_additive) && o->omega_additive >= 0, "omega_additive >= 0");
-        require(o->csr_below == 0 || (o->smoother == BIOT_SMOOTHER_VANKA && o->precision == BIOT_PREC_FP64),
-                "csr_below: FP64 Vanka only");
+        require(o->csr_below == 0 || o->smoother == BIOT_SMOOTHER_VANKA, "csr_below: Vanka only");
         const int nc = c->n >> (o->levels - 1);
         require(nc <= 16, "coarsest mesh must have at most 16 cells per side (dense direct solve)");
         hipStream_t st = S(stream);

@@ -24,7 +24,7 @@ from paper_2107_04060_amd import inputs  # noqa: E402
 from oracle.mesh import Mesh  # noqa: E402
 from oracle.fem import Assembly  # noqa: E402
 from oracle.multigrid import Hierarchy  # noqa: E402
-from gpu_cases import perm, params, solver, rel  # noqa: E402
+from gpu_cases import block_perm, case, perm, params, solver, rel  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -85,3 +85,22 @@ def test_fp32_solve_reaches_fp64_tolerance(binding, smoother, precision):
     print("  %s iters fp64 %d %s %d; %s error vs direct solve: u %.2e w %.2e p %.2e"
           % (smoother, i64["iters"], precision, i32["iters"], precision, errs["u"], errs["w"], errs["p"]), flush=True)
     assert i32["iters"] <= i64["iters"] + 3
+
+
+@pytest.mark.parametrize("precision,csr_below", [("fp32", 32), ("fp32", 16), ("fp32_patch", 32)])
+def test_fp32_forms_with_csr_small_levels(binding, precision, csr_below):
+    """The FP32 forms with the small levels on CSR (computed in FP64, converted at the first of
+    them): the block workload's cycle (three colours, cycle index 2 below the finest level) within
+    the FP32 form's tolerance of the FP64 oracle."""
+    n, levels = 64, 5
+    K = block_perm(n)
+    lam, mu, al, M, mf_, tau = case("block")
+    cyc = dict(nu1=1, nu2=1, omega=1.1, vanka_colors=3, gamma=2, gamma_from=1)
+    s = binding.BiotSolver(n, lam, mu, alpha=al, M=M, mu_f=mf_, tau=tau, K=_t(K))
+    s.setup(levels=levels, smoother="vanka", precision=precision, csr_below=csr_below, **cyc)
+    H = Hierarchy(n, params("block"), K_tri=K, smoother="vanka", levels=levels, **cyc)
+    r = inputs.rhs_uniform(n, 12)
+    err = rel(s.vcycle(_t(r)).cpu().numpy(), H.vcycle(r))
+    s.close()
+    print("  %s csr_below %d: cycle rel diff %.2e" % (precision, csr_below, err), flush=True)
+    assert err < (5e-2 if precision == "fp32_patch" else 1e-4)
