@@ -223,9 +223,10 @@ def schur_extra(binding, inputs, torch, cg=4):
             "total": {f: {"iters": v[0], "ms": round(v[1], 1)} for f, v in tot.items()}}
 
 
-def multicolor_extra(binding, inputs, torch, omega_m=0.9):
+def multicolor_extra(binding, inputs, torch, omega_m=None):
     """Vanka on the sweep256 parameter sets, one solve at a time (FP64, 1e-8): the paper's additive
-    V(2,2) cycle against the four-colour multiplicative V(1,1) cycle (weight omega_m).  Per unit of
+    V(2,2) cycle against the four-colour multiplicative V(1,1) cycle (weight omega_m, or by default
+    the set's weight from the oracle's search on the 64 x 64 mesh, vanka_mult).  Per unit of
     smoothing traffic: a fused Vanka launch moves the same bytes in both forms; an additive V(2,2)
     cycle makes 4 launches per level, a multiplicative V(1,1) cycle 8."""
     w = inputs.workload("sweep256")
@@ -235,8 +236,9 @@ def multicolor_extra(binding, inputs, torch, omega_m=0.9):
     tot = {"additive": [0, 0.0, 0], "multiplicative": [0, 0.0, 0]}
     for case in w["cases"]:
         om, omj = inputs.relaxation_weights("vanka", case["nu"], case["K"])
-        row = {"nu": case["nu"], "K": case["K"]}
-        for form, nu12, omega, colors, per_cycle in (("additive", 2, om, 0, 4), ("multiplicative", 1, omega_m, 4, 8)):
+        om_m = omega_m if omega_m else inputs.relaxation_weights("vanka_mult", case["nu"], case["K"])[0]
+        row = {"nu": case["nu"], "K": case["K"], "omega_multiplicative": om_m}
+        for form, nu12, omega, colors, per_cycle in (("additive", 2, om, 0, 4), ("multiplicative", 1, om_m, 4, 8)):
             s = binding.BiotSolver(n, case["lam"], case["mu"], alpha=w["alpha"], M=w["M"], mu_f=w["mu_f"],
                                    tau=w["tau"], K=case["K"])
             s.setup(levels=levels, smoother="vanka", nu1=nu12, nu2=nu12, omega=omega, omega_J=omj,
@@ -251,7 +253,8 @@ def multicolor_extra(binding, inputs, torch, omega_m=0.9):
             tot[form][2] += per_cycle * info["iters"]
         rows.append(row)
     return {"workload": "sweep256 Vanka parameter sets, one solve at a time, FP64, 1e-8; additive V(2,2) with the "
-                        "LFA weights, multiplicative V(1,1) with omega %.2f" % omega_m,
+                        "LFA weights, multiplicative V(1,1) with %s" % (
+                            "omega %.2f" % omega_m if omega_m else "the weights of the oracle's 64 x 64 search"),
             "cases": rows,
             "total": {k: {"iters": v[0], "ms": round(v[1], 1), "fused_launches_per_level": v[2]}
                       for k, v in tot.items()}}

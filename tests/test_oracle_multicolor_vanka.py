@@ -110,3 +110,26 @@ def test_multiplicative_cycle_needs_fewer_iterations():
     _, im = fgmres(mul.A, b, mul.vcycle, tol=1e-6, restart=30, maxit=200)
     print("additive V(2,2) %d iterations, multiplicative V(1,1) %d" % (ia["iters"], im["iters"]))
     assert ia["converged"] and im["converged"] and im["iters"] < ia["iters"]
+
+
+@pytest.mark.slow
+def test_stored_multiplicative_weight_reproduces():
+    """The multiplicative-Vanka weight stored for the sweep256 set nu = 0.2, K = 1
+    (paper_2107_04060_amd/relaxation_weights.json, written by python -m oracle.relaxation_weights
+    --multiplicative) is 0.6: the oracle's FGMRES counts on the 64 x 64 mesh at omega 0.6 and 0.9
+    are those stored, and 0.9, the weight used before the search, takes three times as many."""
+    import json
+    import os
+    from oracle.krylov import fgmres
+    from oracle.relaxation_weights import lame
+    path = os.path.join(os.path.dirname(os.path.dirname(__file__)), "paper_2107_04060_amd", "relaxation_weights.json")
+    e = json.load(open(path))["sweep256"]["0.2/1"]["vanka_mult"]
+    assert e["omega"] == 0.6
+    lam, mu = lame(1.0, 0.2)
+    P = BiotParams(lam, mu, alpha=1.0, M=1.0 / 0.03, mu_f=1.0, tau=1.0)
+    b = np.random.default_rng(1).uniform(-1.0, 1.0, 10 * 64 * 64 - 8 * 64 + 2)
+    for om in (0.6, 0.9):
+        H = Hierarchy(64, P, K_tri=1.0, smoother="vanka", omega=om, nu1=1, nu2=1, levels=5, vanka_colors=4)
+        _, info = fgmres(H.A, b, H.vcycle, tol=1e-8, restart=30, maxit=150)
+        assert info["converged"] and info["iters"] == e["counts_64"]["%.1f" % om]
+    assert e["counts_64"]["0.9"] >= 3 * e["counts_64"]["0.6"]
