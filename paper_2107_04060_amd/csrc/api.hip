@@ -134,6 +134,8 @@ struct SpLevel {
     DevBuf x, b, r;                                 // iterate, right-hand side, residual
     DevBuf clist;                                   // multiplicative Vanka: patches by colour
     std::vector<int> coff;                          // colour c: clist[coff[c] .. coff[c+1])
+    DevBuf crow, cbeg, cend;                        // their slots' rows and CSR row bounds
+    std::vector<int> ptr_h;                         // CSR row pointer (host copy)
 };
 
 struct SpHier {
@@ -628,6 +630,7 @@ static void sp_level_alloc(SpLevel& L, int n, int bc, const PhysParams& p, hipSt
     OperatorHost op = build_operator(L.map, p);
     L.N = L.map.N;
     L.nnz = (int)op.A.col.size();
+    L.ptr_h = op.A.ptr;
     upload(L.ptr, op.A.ptr, st);
     upload(L.col, op.A.col, st);
     upload(L.val0, op.A.val, st);
@@ -644,7 +647,8 @@ static void sp_level_alloc(SpLevel& L, int n, int bc, const PhysParams& p, hipSt
 }
 
 // transfers between level l (fine) and l + 1, and the Vanka patches of level l
-static void sp_level_links(SpLevel& F, const SpLevel& C, hipStream_t st, int ncolors = 1) {
+static void sp_level_links(SpLevel& F, const SpLevel& C, hipStream_t st, int ncolors = 1,
+                           const std::vector<int>* rowptr = nullptr) {
     const CsrHost P = build_prolongation(F.map, C.map);
     const CsrHost R = csr_transpose(P);
     upload(F.pptr, P.ptr, st);
@@ -670,6 +674,22 @@ static void sp_level_links(SpLevel& F, const SpLevel& C, hipStream_t st, int nco
             F.coff[(size_t)col + 1] = (int)clist.size();
         }
         upload(F.clist, clist, st);
+        if (rowptr) {
+            std::vector<int> crow(clist.size() * PATCH), cbeg(crow.size(), 0), cend(crow.size(), 0);
+            for (size_t k = 0; k < clist.size(); ++k)
+                for (int a = 0; a < PATCH; ++a) {
+                    const int d = slots[(size_t)clist[k] * PATCH + a];
+                    const size_t e = k * PATCH + a;
+                    crow[e] = d;
+                    if (d >= 0) {
+                        cbeg[e] = (*rowptr)[(size_t)d];
+                        cend[e] = (*rowptr)[(size_t)d + 1];
+                    }
+                }
+            upload(F.crow, crow, st);
+            upload(F.cbeg, cbeg, st);
+            upload(F.cend, cend, st);
+        }
     }
     // DoF -> (patch, slot) lists in patch order (a fixed summation order) and D = 1 / count
     std::vector<int> dptr((size_t)F.N + 1, 0), dlist;
@@ -861,7 +881,7 @@ static void small_setup(biot_ctx* c, hipStream_t st) {
         sp_level_alloc(*H->lv.back(), c->n >> l, BC_DIRICHLET, c->phys, st);
     }
     for (size_t k = 0; k + 1 < H->lv.size(); ++k)
-        sp_level_links(*H->lv[k], *H->lv[k + 1], st, vanka_colors_at(o, s + (int)k));
+        sp_level_links(*H->lv[k], *H->lv[k + 1], st, vanka_colors_at(o, s + (int)k), &H->lv[k]->ptr_h);
     std::vector<int> idx((size_t)c->coarse_N);
     for (int k = 0; k < c->coarse_N; ++k) idx[k] = k;
     upload(H->cidx, idx, st);
@@ -880,10 +900,12 @@ static void small_smooth(biot_ctx* c, int g, SpLevel& L, double* x, const double
         return;
     }
     if (zero) launch_fill(x, L.N, 0.0, st);
-    for (int col = 0; col < nc; ++col)
-        launch_colour_step(L.coff[(size_t)col + 1] - L.coff[col], L.clist.as<int>() + L.coff[col], L.slots.as<int>(),
-                           L.inv.as<double>(), L.ptr.as<int>(), L.col.as<int>(), L.val.as<double>(), b, x, om,
-                           zero && col == 0, st);
+    for (int col = 0; col < nc; ++col) {
+        const size_t o = (size_t)L.coff[col] * PATCH;
+        launch_colour_step(L.coff[(size_t)col + 1] - L.coff[col], L.clist.as<int>() + L.coff[col],
+                           L.crow.as<int>() + o, L.cbeg.as<int>() + o, L.cend.as<int>() + o, L.inv.as<double>(),
+                           L.col.as<int>(), L.val.as<double>(), b, x, om, zero && col == 0, st);
+    }
 }
 
 // the cycle on small level k (global level small_from + k), as vcycle_level: from zero or from

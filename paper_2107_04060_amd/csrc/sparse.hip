@@ -226,43 +226,53 @@ __global__ __launch_bounds__(TPB) void k_patch_apply_add(int npc, const int* __r
 // share no mesh edge, so their stars share no triangle, edge or vertex); every x a block reads
 // is therefore either its own patch's, written by the block after its reads, or another
 // colour's, not written in this launch.  xzero: x = 0 on entry (the residual is b).
+// The colour's rows are listed per (patch, slot) with their CSR bounds (crow, cbeg, cend), so
+// that a lane reaches x in three dependent loads; a phase-2 thread loads its inverse column
+// before the barrier.
 constexpr int LPR_C = 4;                                  // lanes per row
 constexpr int PPB_C = TPB / (PATCH * LPR_C);              // patches per block (3)
 __global__ __launch_bounds__(TPB) void k_colour_step(int npc, const int* __restrict__ plist,
-                                                     const int* __restrict__ slots, const double* __restrict__ inv,
-                                                     const int* __restrict__ ptr, const int* __restrict__ col,
-                                                     const double* __restrict__ val, const double* __restrict__ b,
-                                                     double* x, double omega, int xzero) {
+                                                     const int* __restrict__ crow, const int* __restrict__ cbeg,
+                                                     const int* __restrict__ cend, const double* __restrict__ inv,
+                                                     const int* __restrict__ col, const double* __restrict__ val,
+                                                     const double* __restrict__ b, double* x, double omega,
+                                                     int xzero) {
     __shared__ double rsh[PPB_C][PATCH];
     const int t = threadIdx.x;
     const int k0 = blockIdx.x * PPB_C;
+    // phase 2's inverse column, loaded first (independent of phase 1)
+    const bool p2 = t < PPB_C * PATCH && k0 + t / PATCH < npc;
+    double ac[PATCH];
+    if (p2) {
+        const long long p = plist[k0 + t / PATCH];
+        const double* A = inv + p * PATCH * PATCH + t % PATCH;
+#pragma unroll
+        for (int bb = 0; bb < PATCH; ++bb) ac[bb] = A[bb * PATCH];
+    }
     // phase 1: residual rows
     {
         const int kl = t / (PATCH * LPR_C), a = (t / LPR_C) % PATCH, sub = t % LPR_C;
-        const int k = k0 + kl;
-        int d = -1;
-        if (kl < PPB_C && k < npc) d = slots[(long long)plist[k] * PATCH + a];
+        const long long e = (long long)(k0 + kl) * PATCH + a;
+        const bool live = kl < PPB_C && k0 + kl < npc;
+        const int d = live ? crow[e] : -1;
         double s = 0.0;
-        if (d >= 0 && !xzero)
-            for (int q = ptr[d] + sub; q < ptr[d + 1]; q += LPR_C) s += val[q] * x[col[q]];
+        if (d >= 0 && !xzero) {
+            const int hi = cend[e];
+            for (int q = cbeg[e] + sub; q < hi; q += LPR_C) s += val[q] * x[col[q]];
+        }
 #pragma unroll
         for (int o = LPR_C / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, LPR_C);
         if (kl < PPB_C && sub == 0) rsh[kl][a] = d >= 0 ? b[d] - s : 0.0;
     }
     __syncthreads();
     // phase 2: correction of slot a of patch kl
-    if (t < PPB_C * PATCH) {
+    if (p2) {
         const int kl = t / PATCH, a = t % PATCH;
-        const int k = k0 + kl;
-        if (k < npc) {
-            const long long p = plist[k];
-            const double* A = inv + p * PATCH * PATCH + a;
-            double v = 0.0;
+        double v = 0.0;
 #pragma unroll
-            for (int bb = 0; bb < PATCH; ++bb) v += A[bb * PATCH] * rsh[kl][bb];
-            const int d = slots[p * PATCH + a];
-            if (d >= 0) x[d] += omega * v;
-        }
+        for (int bb = 0; bb < PATCH; ++bb) v += ac[bb] * rsh[kl][bb];
+        const int d = crow[(long long)(k0 + kl) * PATCH + a];
+        if (d >= 0) x[d] += omega * v;
     }
 }
 
@@ -344,11 +354,12 @@ void launch_patch_apply_add(int npc, const int* plist, const int* slots, const d
                        inv, r, omega, x);
 }
 
-void launch_colour_step(int npc, const int* plist, const int* slots, const double* inv, const int* ptr, const int* col,
-                        const double* val, const double* b, double* x, double omega, bool xzero, hipStream_t st) {
+void launch_colour_step(int npc, const int* plist, const int* crow, const int* cbeg, const int* cend,
+                        const double* inv, const int* col, const double* val, const double* b, double* x,
+                        double omega, bool xzero, hipStream_t st) {
     if (npc <= 0) return;
-    hipLaunchKernelGGL(k_colour_step, dim3((unsigned)((npc + PPB_C - 1) / PPB_C)), dim3(TPB), 0, st, npc, plist, slots,
-                       inv, ptr, col, val, b, x, omega, xzero ? 1 : 0);
+    hipLaunchKernelGGL(k_colour_step, dim3((unsigned)((npc + PPB_C - 1) / PPB_C)), dim3(TPB), 0, st, npc, plist, crow,
+                       cbeg, cend, inv, col, val, b, x, omega, xzero ? 1 : 0);
 }
 
 void launch_kinv_unpad(const Layout& L, const double* kinv_padded, double* flat, hipStream_t st) {
