@@ -63,3 +63,44 @@ def test_grf1024_true_residual(binding, problem, precision):
     # residual of 1e-8 |b| where K reaches 1e-6): agreement to 1 % is asked
     assert rel <= 1.01e-8
     assert abs(rel - info["rel_res_true"]) <= 1e-2 * rel
+
+
+@pytest.mark.timeout(600)
+def test_block2048_bench_cycle_at_full_size(binding):
+    """The block-contrast workload at its full size (2048 x 2048, 41,926,658 free DoFs) in the
+    launch configuration the benchmark times (bench.py's cycle: three colours, omega 1.1, cycle
+    index 2 below the finest level, 8 levels, the levels of 64 x 64 cells and below on CSR with
+    explicit patch inverses), against the same cycle on the stencil kernels alone (csr_below 0).
+    Both paths are parity-checked against the oracle at n <= 128; at this size (the oracle cannot
+    hold it) they must agree with each other: the same FGMRES iteration count, both at 1e-8 in
+    the library's recomputed true residual, and solutions within the solve's tolerance of each
+    other.  Restart 40 (more than the 28 iterations needed, so no restart occurs)."""
+    import bench
+    w = inputs.workload("block2048")
+    c = w["cases"][0]
+    n = w["n"]
+    cyc = dict(bench.BLOCK_CYCLE)
+    levels, csr = cyc.pop("levels"), cyc.pop("csr_below")
+    cfg = dict(nu1=cyc["nu12"], nu2=cyc["nu12"], omega=cyc["omega"], vanka_colors=cyc["colors"], gamma=cyc["gamma"],
+               gamma_from=cyc["gamma_from"], fcycle=bool(cyc["fcycle"]))
+    assert csr > 0
+    K = torch.tensor(inputs.permeability_triangles("block2048"), dtype=torch.float64, device="cuda")
+    rng = np.random.default_rng(w["seed"])
+    rng.uniform(-1.0, 1.0, inputs.n_free(n))                        # right-hand side 0 is the warm-up's
+    b = torch.tensor(rng.uniform(-1.0, 1.0, inputs.n_free(n)), dtype=torch.float64, device="cuda")
+    out = {}
+    for cb in (csr, 0):
+        print("block2048 at full size, csr_below %d" % cb, flush=True)
+        s = binding.BiotSolver(n, c["lam"], c["mu"], alpha=w["alpha"], M=w["M"], mu_f=w["mu_f"], tau=w["tau"], K=K)
+        s.setup(levels=levels, smoother="vanka", csr_below=cb, **cfg)
+        x, info = s.solve(b, tol=1e-8, restart=40, maxit=200, reorth=bench.BLOCK_REORTH)
+        s.close()
+        out[cb] = (x, info)
+        print("  %d iterations, true rel. residual %.3e" % (info["iters"], info["rel_res_true"]), flush=True)
+    (x1, i1), (x0, i0) = out[csr], out[0]
+    assert i1["converged"] and i0["converged"]
+    assert i1["rel_res_true"] <= 1e-8 and i0["rel_res_true"] <= 1e-8
+    assert i1["iters"] == i0["iters"]
+    d = (torch.linalg.vector_norm(x1 - x0) / torch.linalg.vector_norm(x0)).item()
+    print("  solutions differ by %.2e (relative)" % d, flush=True)
+    assert d < 1e-6
