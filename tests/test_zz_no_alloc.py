@@ -69,6 +69,33 @@ def test_noalloc_solve_matches_solve_twice_second_smaller(binding):
     assert out[0][5] >= 16 << 20, out[0][5]
 
 
+def test_noalloc_with_csr_small_levels(binding):
+    """The same with the small levels on CSR (csr_below) and the multiplicative W-cycle of the
+    block workload: their buffers are set up with the hierarchy, so the no-allocation solve still
+    allocates nothing and matches biot_solve."""
+    from gpu_cases import block_perm, case
+    n, levels = 64, 5
+    lam, mu, al, M, mf_, tau = case("block")
+    K = torch.tensor(block_perm(n), dtype=torch.float64, device="cuda")
+    s = binding.BiotSolver(n, lam, mu, alpha=al, M=M, mu_f=mf_, tau=tau, K=K)
+    s.setup(levels=levels, smoother="vanka", nu1=1, nu2=1, omega=1.1, vanka_colors=3, gamma=2, gamma_from=1,
+            csr_below=16)
+    b = torch.tensor(inputs.rhs_uniform(n, 4), dtype=torch.float64, device="cuda")
+    s.solve(b, tol=1e-8, restart=30, maxit=300)                   # workspace of biot_solve, kernels loaded
+    x_na = torch.empty_like(b)
+    f0 = _free()
+    x_na, i_na = s.solve_noalloc(b, x_na, tol=1e-8, restart=30, maxit=300)
+    f1 = _free()
+    x_ref, i_ref = s.solve(b, tol=1e-8, restart=30, maxit=300)
+    s.close()
+    d = (x_na - x_ref).abs().max().item() / x_ref.abs().max().item()
+    print("  csr_below 16: noalloc %d iters, solve %d iters, max|diff|/max|x| %.1e, free memory change %d B"
+          % (i_na["iters"], i_ref["iters"], d, f1 - f0), flush=True)
+    assert i_na["converged"] and i_na["iters"] == i_ref["iters"]
+    assert d <= 1e-12
+    assert f0 - f1 <= 2 << 20
+
+
 def test_noalloc_rejects_requests_beyond_its_workspace(binding):
     s = _solver(binding, 128, 6)
     b = torch.zeros(s.nf(), dtype=torch.float64, device="cuda")
