@@ -135,6 +135,8 @@ struct SpLevel {
     DevBuf clist;                                   // multiplicative Vanka: patches by colour
     std::vector<int> coff;                          // colour c: clist[coff[c] .. coff[c+1])
     DevBuf crow, cbeg, cend;                        // their slots' rows and CSR row bounds
+    DevBuf zlist0;                                  // the DoFs outside colour 0's patches
+    int nz0 = 0;
     std::vector<int> ptr_h;                         // CSR row pointer (host copy)
 };
 
@@ -689,6 +691,15 @@ static void sp_level_links(SpLevel& F, const SpLevel& C, hipStream_t st, int nco
             upload(F.crow, crow, st);
             upload(F.cbeg, cbeg, st);
             upload(F.cend, cend, st);
+            // a zero-start colour 0 also writes the zeros of the DoFs its patches do not hold
+            std::vector<char> cov((size_t)F.N, 0);
+            for (size_t e = 0; e < (size_t)F.coff[1] * PATCH; ++e)
+                if (crow[e] >= 0) cov[(size_t)crow[e]] = 1;
+            std::vector<int> zl;
+            for (int d = 0; d < F.N; ++d)
+                if (!cov[(size_t)d]) zl.push_back(d);
+            F.nz0 = (int)zl.size();
+            upload(F.zlist0, zl, st);
         }
     }
     // DoF -> (patch, slot) lists in patch order (a fixed summation order) and D = 1 / count
@@ -899,12 +910,12 @@ static void small_smooth(biot_ctx* c, int g, SpLevel& L, double* x, const double
         sp_smooth_level(L, om, x, b, zero, st);
         return;
     }
-    if (zero) launch_fill(x, L.N, 0.0, st);
     for (int col = 0; col < nc; ++col) {
         const size_t o = (size_t)L.coff[col] * PATCH;
         launch_colour_step(L.coff[(size_t)col + 1] - L.coff[col], L.clist.as<int>() + L.coff[col],
                            L.crow.as<int>() + o, L.cbeg.as<int>() + o, L.cend.as<int>() + o, L.inv.as<double>(),
-                           L.col.as<int>(), L.val.as<double>(), b, x, om, zero && col == 0, st);
+                           L.col.as<int>(), L.val.as<double>(), b, x, om, zero && col == 0, st, L.zlist0.as<int>(),
+                           L.nz0);
     }
 }
 

@@ -101,12 +101,14 @@ void launch_patch_apply_add(int npc, const int* plist, const int* slots, const d
                             double omega, double* x, hipStream_t st);
 // the same colour step fused with its residual, in place: for the colour's patches (vertices of
 // one colour share no mesh edge, so a patch's residual rows read no DoF another patch of the
-// colour writes), r = b - A x on the patch rows, then x += omega A_p^{-1} r; xzero: x = 0 on
-// entry (r = b; x must hold zeros).  crow[k * PATCH + a]: the DoF of slot a of the colour's
-// k-th patch (-1 absent), cbeg / cend its CSR row bounds (plist[k] the patch, for its inverse)
+// colour writes), r = b - A x on the patch rows, then x += omega A_p^{-1} r; xzero: the iterate
+// is zero (r = b; x is not read: the colour's DoFs are assigned, and the nz DoFs of zlist, those
+// no patch of the colour holds, are set to zero in the same launch).  crow[k * PATCH + a]: the
+// DoF of slot a of the colour's k-th patch (-1 absent), cbeg / cend its CSR row bounds (plist[k]
+// the patch, for its inverse)
 void launch_colour_step(int npc, const int* plist, const int* crow, const int* cbeg, const int* cend,
                         const double* inv, const int* col, const double* val, const double* b, double* x,
-                        double omega, bool xzero, hipStream_t st);
+                        double omega, bool xzero, hipStream_t st, const int* zlist = nullptr, int nz = 0);
 // per-triangle 1/K of a level of the padded layout (two planes) in the flat triangle order
 void launch_kinv_unpad(const Layout& L, const double* kinv_padded, double* flat, hipStream_t st);
 

@@ -225,7 +225,9 @@ __global__ __launch_bounds__(TPB) void k_patch_apply_add(int npc, const int* __r
 // its vertex's star, and no other patch of the colour owns one of those (vertices of one colour
 // share no mesh edge, so their stars share no triangle, edge or vertex); every x a block reads
 // is therefore either its own patch's, written by the block after its reads, or another
-// colour's, not written in this launch.  xzero: x = 0 on entry (the residual is b).
+// colour's, not written in this launch.  xzero: the iterate is zero (the residual is b, x is not
+// read): the corrections are assigned, and blocks past the colour's patches write the zeros of
+// the DoFs no patch of the colour holds (zlist, nz), so that x needs no clearing beforehand.
 // The colour's rows are listed per (patch, slot) with their CSR bounds (crow, cbeg, cend), so
 // that a lane reaches x in three dependent loads; a phase-2 thread loads its inverse column
 // before the barrier.
@@ -236,9 +238,16 @@ __global__ __launch_bounds__(TPB) void k_colour_step(int npc, const int* __restr
                                                      const int* __restrict__ cend, const double* __restrict__ inv,
                                                      const int* __restrict__ col, const double* __restrict__ val,
                                                      const double* __restrict__ b, double* x, double omega,
-                                                     int xzero) {
+                                                     int xzero, const int* __restrict__ zlist, int nz) {
     __shared__ double rsh[PPB_C][PATCH];
     const int t = threadIdx.x;
+    const int npb = (npc + PPB_C - 1) / PPB_C;
+    if ((int)blockIdx.x >= npb) {
+        // zero-start: the DoFs outside the colour's patches
+        const long long z = (long long)(blockIdx.x - npb) * blockDim.x + t;
+        if (z < nz) x[zlist[z]] = 0.0;
+        return;
+    }
     const int k0 = blockIdx.x * PPB_C;
     // phase 2's inverse column, loaded first (independent of phase 1)
     const bool p2 = t < PPB_C * PATCH && k0 + t / PATCH < npc;
@@ -272,7 +281,7 @@ __global__ __launch_bounds__(TPB) void k_colour_step(int npc, const int* __restr
 #pragma unroll
         for (int bb = 0; bb < PATCH; ++bb) v += ac[bb] * rsh[kl][bb];
         const int d = crow[(long long)(k0 + kl) * PATCH + a];
-        if (d >= 0) x[d] += omega * v;
+        if (d >= 0) x[d] = (xzero ? 0.0 : x[d]) + omega * v;
     }
 }
 
@@ -356,10 +365,12 @@ void launch_patch_apply_add(int npc, const int* plist, const int* slots, const d
 
 void launch_colour_step(int npc, const int* plist, const int* crow, const int* cbeg, const int* cend,
                         const double* inv, const int* col, const double* val, const double* b, double* x,
-                        double omega, bool xzero, hipStream_t st) {
-    if (npc <= 0) return;
-    hipLaunchKernelGGL(k_colour_step, dim3((unsigned)((npc + PPB_C - 1) / PPB_C)), dim3(TPB), 0, st, npc, plist, crow,
-                       cbeg, cend, inv, col, val, b, x, omega, xzero ? 1 : 0);
+                        double omega, bool xzero, hipStream_t st, const int* zlist, int nz) {
+    if (!xzero) nz = 0;
+    const unsigned npb = (unsigned)((npc + PPB_C - 1) / PPB_C), nzb = (unsigned)((nz + TPB - 1) / TPB);
+    if (npb + nzb == 0) return;
+    hipLaunchKernelGGL(k_colour_step, dim3(npb + nzb), dim3(TPB), 0, st, npc, plist, crow, cbeg, cend, inv, col, val,
+                       b, x, omega, xzero ? 1 : 0, zlist, nz);
 }
 
 void launch_kinv_unpad(const Layout& L, const double* kinv_padded, double* flat, hipStream_t st) {
