@@ -185,26 +185,42 @@ template void launch_apply<float>(const LevelView<float>&, const float*, const f
 // =========================================================================================
 // coarsest level: dense inverse applied one row per wave (Sec. 5.1 direct solve)
 // =========================================================================================
-template <typename T>
+// Rows of up to CS_RMAX x 64 entries (the 16 x 16 coarsest mesh has 2434) are loaded whole into
+// registers first, every load of a lane in flight at once and before the right-hand side is
+// staged, so the row's latency overlaps the staging; longer rows go through the loop.  The
+// partial sums take the same entries in the same order either way.
+constexpr int CS_RMAX = 40;
+template <typename T, bool REG>
 __global__ __launch_bounds__(256) void k_coarse_solve(const double* __restrict__ Ainv, int N,
                                                       const int* __restrict__ idx, const T* __restrict__ b,
                                                       T* __restrict__ x) {
     extern __shared__ double bb[];
-    for (int k = threadIdx.x; k < N; k += blockDim.x) bb[k] = (double)b[idx[k]];
-    __syncthreads();
     // one row per wave: the lanes read consecutive entries of the row into eight partial sums
-    // (eight loads of each lane in flight, not one after another), then a butterfly sum
+    // (entry lane + 64 u goes to sum u mod 8), then a butterfly sum
     const int lane = threadIdx.x & 63;
     const int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (k >= N) return;
-    const double* row = Ainv + (long long)k * N;
-    double ps[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int l = lane;
-    for (; l + 7 * 64 < N; l += 8 * 64) {
+    const double* row = Ainv + (long long)(k < N ? k : N - 1) * N;
+    double rv[REG ? CS_RMAX : 1];
+    if constexpr (REG) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) ps[u] += row[l + u * 64] * bb[l + u * 64];
+        for (int u = 0; u < CS_RMAX; ++u) rv[u] = lane + u * 64 < N ? row[lane + u * 64] : 0.0;
     }
-    for (int u = 0; l < N; l += 64, ++u) ps[u] += row[l] * bb[l];
+    for (int q = threadIdx.x; q < N; q += blockDim.x) bb[q] = (double)b[idx[q]];
+    __syncthreads();
+    if (k >= N) return;
+    double ps[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if constexpr (REG) {
+#pragma unroll
+        for (int u = 0; u < CS_RMAX; ++u)
+            if (lane + u * 64 < N) ps[u % 8] += rv[u] * bb[lane + u * 64];
+    } else {
+        int l = lane;
+        for (; l + 7 * 64 < N; l += 8 * 64) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) ps[u] += row[l + u * 64] * bb[l + u * 64];
+        }
+        for (int u = 0; l < N; l += 64, ++u) ps[u] += row[l] * bb[l];
+    }
     double s = ((ps[0] + ps[1]) + (ps[2] + ps[3])) + ((ps[4] + ps[5]) + (ps[6] + ps[7]));
     s = wave_sum(s);
     if (lane == 0) x[idx[k]] = (T)s;
@@ -212,7 +228,12 @@ __global__ __launch_bounds__(256) void k_coarse_solve(const double* __restrict__
 
 template <typename T>
 void launch_coarse_solve(const double* Ainv, int N, const int* idx, const T* b, T* x, hipStream_t st) {
-    hipLaunchKernelGGL(k_coarse_solve<T>, dim3((N + 3) / 4), dim3(256), N * sizeof(double), st, Ainv, N, idx, b, x);
+    if (N <= CS_RMAX * 64)
+        hipLaunchKernelGGL((k_coarse_solve<T, true>), dim3((N + 3) / 4), dim3(256), N * sizeof(double), st, Ainv, N, idx,
+                           b, x);
+    else
+        hipLaunchKernelGGL((k_coarse_solve<T, false>), dim3((N + 3) / 4), dim3(256), N * sizeof(double), st, Ainv, N,
+                           idx, b, x);
 }
 template void launch_coarse_solve<double>(const double*, int, const int*, const double*, double*, hipStream_t);
 template void launch_coarse_solve<float>(const double*, int, const int*, const float*, float*, hipStream_t);
