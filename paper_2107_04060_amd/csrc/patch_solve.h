@@ -13,6 +13,7 @@
 #include "kernels.h"
 
 #include <cmath>
+#include <type_traits>
 
 namespace biot {
 
@@ -72,10 +73,19 @@ __host__ __device__ inline void bwd6p(const T l[21], T v[6]) {
     }
 }
 
+// 1/K of star triangle k from an array or from an accessor kv(k) (read where it is used)
+template <typename T, typename KV>
+__host__ __device__ inline T kv_at(const KV& kv, int k) {
+    if constexpr (std::is_invocable_v<const KV&, int>)
+        return kv(k);
+    else
+        return kv[k];
+}
+
 // W: RT0 mass on the six star edges, star triangle k holding the edge pair star_wpair(k, .),
 // unit diagonal on absent edges; factored in place
-template <typename T, bool ALLP = false>
-__host__ __device__ inline void star_w_factor(const DevPatchClass<T>& pc, const T kv[6], const T* __restrict__ wblk,
+template <typename T, bool ALLP = false, typename KV>
+__host__ __device__ inline void star_w_factor(const DevPatchClass<T>& pc, const KV& kv, const T* __restrict__ wblk,
                                               T w[21]) {
 #pragma unroll
     for (int q = 0; q < 21; ++q) w[q] = 0;
@@ -86,7 +96,7 @@ __host__ __device__ inline void star_w_factor(const DevPatchClass<T>& pc, const 
 #pragma unroll
             for (int q = 0; q <= p; ++q) {
                 const int a = star_wpair(kq, p), b = star_wpair(kq, q);
-                if (ALLP || (pc.present[8 + a] && pc.present[8 + b])) w[tri6(a, b)] += wblk[(kq * 2 + p) * 2 + q] * kv[kq];
+                if (ALLP || (pc.present[8 + a] && pc.present[8 + b])) w[tri6(a, b)] += wblk[(kq * 2 + p) * 2 + q] * kv_at<T>(kv, kq);
             }
 #pragma unroll
     for (int a = 0; a < 6; ++a)
@@ -109,8 +119,8 @@ struct PatchFac {
 
 static_assert(sizeof(PatchFac<double>) == PFAC * sizeof(double), "factor record layout");
 
-template <typename T, bool ALLP = false>
-__host__ __device__ inline void patch_factor(const DevPatchClass<T>& pc, const T kv[6], const T* __restrict__ wblk,
+template <typename T, bool ALLP = false, typename KV>
+__host__ __device__ inline void patch_factor(const DevPatchClass<T>& pc, const KV& kv, const T* __restrict__ wblk,
                                              PatchFac<T>& f) {
     star_w_factor<T, ALLP>(pc, kv, wblk, f.w);
     BIOT_PHASE_FENCE();

@@ -64,8 +64,8 @@ __device__ __forceinline__ void mfma_class_frag(const double* M, int lane, doubl
 // One variable-K patch solve: the patch's factors (stored, fp != nullptr, FP64 only, or formed from
 // the 1/K of its star), then the solve, which reads the patch residual from the staged residual in
 // LDS where it needs it (it stays there until the barrier after the patch phase).
-template <typename T, typename P, bool ALLP, bool FACOK>
-__device__ __forceinline__ void vanka_patch(const DevPatchClass<P>& pc, const P (&kv)[6], const P* __restrict__ wblk,
+template <typename T, typename P, bool ALLP, bool FACOK, typename KV>
+__device__ __forceinline__ void vanka_patch(const DevPatchClass<P>& pc, const KV& kv, const P* __restrict__ wblk,
                                             const double* __restrict__ fp, long long plane,
                                             const T (&rs)[NTYPES][RW][RW], int tx, int ty, P (&out)[PATCH]) {
     PatchFac<P> f;
@@ -381,13 +381,12 @@ __device__ __forceinline__ void vanka_step_tile(const T* __restrict__ x_in, cons
         const bool inner = cilo == 1 && cihi == 1 && cjlo == 1 && cjhi == 1;
         const bool act = patch && vi <= n && vj <= n && (color < 0 || in_color(vi, vj, color));
         if (act) {
-            P kv[6];
-#pragma unroll
-            for (int kq = 0; kq < 6; ++kq) {
+            // 1/K of the star triangles, read from the staged field where the factorization uses it
+            auto kv = [&](int kq) {
                 int ut, di, dj;
                 star_tri(kq, ut, di, dj);
-                kv[kq] = (P)sh.ks[ut][ty + 2 + dj][tx + 2 + di];
-            }
+                return (P)sh.ks[ut][ty + 2 + dj][tx + 2 + di];
+            };
             const double* fp = (FACOK && fac) ? fac + slot_index(L, vi, vj) : nullptr;
             if (inner) {
                 vanka_patch<T, P, true, FACOK>(sh.pcs[0], kv, wblk, fp, L.plane, rs, tx, ty, out);
