@@ -256,3 +256,21 @@ def test_update_K_reassembles_every_level():
         assert rel(_cpu(s.apply(_gpu(x), level=l)), lev.A @ x) < 1e-13
     b = rng.standard_normal(H.A.shape[0])
     assert rel(_cpu(s.vcycle(_gpu(b))), H.vcycle(b)) < 1e-8
+
+
+def test_update_logK_on_the_general_path():
+    """biot_update_logK on the general-boundary path: 1/K = exp(-theta) formed on the device, every
+    level re-assembled; the operators match the oracle's for K = exp(theta)."""
+    n, levels = 16, 3
+    s, P = _solver(n, 0.49, levels=levels)
+    theta = np.log(K_TZ) + np.random.default_rng(37).uniform(-1.5, 1.5, 2 * n * n)
+    s.update_logK(_gpu(theta))
+    K = np.exp(theta)
+    H = Hierarchy(n, P, K_tri=K, smoother="vanka", omega=0.8, nu1=2, nu2=2, levels=levels, bc="terzaghi",
+                  vanka_shift=SHIFT)
+    rng = np.random.default_rng(41)
+    for l, lev in enumerate(H.levels):
+        x = rng.standard_normal(lev.A.shape[0])
+        assert rel(_cpu(s.apply(_gpu(x), level=l)), lev.A @ x) < 1e-13, l
+    b = rng.standard_normal(H.A.shape[0])
+    assert rel(_cpu(s.vcycle(_gpu(b))), H.vcycle(b)) < 1e-8
