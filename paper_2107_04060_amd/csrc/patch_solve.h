@@ -82,6 +82,76 @@ __host__ __device__ inline T kv_at(const KV& kv, int k) {
         return kv[k];
 }
 
+// Sparsity of W and of its Cholesky factor in slot order.  W couples two star edges only through
+// the star triangle holding both (star_wpair): the six edges form a cycle.  Eliminating in slot
+// order fills three more pairs; the other six entries of the packed factor stay zero, and the
+// factorization and substitutions below skip them (the same values as the dense forms, whose
+// skipped terms are exact zeros).
+struct WPattern {
+    bool nz[6][6];
+};
+__host__ __device__ constexpr WPattern w_pattern() {
+    WPattern P{};
+    for (int i = 0; i < 6; ++i) P.nz[i][i] = true;
+    for (int k = 0; k < 6; ++k) {
+        const int a = star_wpair(k, 0), b = star_wpair(k, 1);
+        P.nz[a][b] = P.nz[b][a] = true;
+    }
+    for (int j = 0; j < 6; ++j)                     // symbolic elimination, column j
+        for (int i = j + 1; i < 6; ++i)
+            for (int l = j + 1; l < 6; ++l)
+                if (P.nz[i][j] && P.nz[l][j]) P.nz[i][l] = P.nz[l][i] = true;
+    return P;
+}
+__host__ __device__ constexpr bool wnz(int i, int j) { return w_pattern().nz[i][j]; }
+
+// chol6p, fwd6p and bwd6p on the pattern of W
+template <typename T>
+__host__ __device__ inline void chol6w(T a[21]) {
+#pragma unroll
+    for (int jj = 0; jj < 6; ++jj) {
+        T d = a[tri6(jj, jj)];
+#pragma unroll
+        for (int k = 0; k < jj; ++k)
+            if (wnz(jj, k)) d -= a[tri6(jj, k)] * a[tri6(jj, k)];
+        const T inv = (T)1 / sqrt(d);
+        a[tri6(jj, jj)] = inv;
+#pragma unroll
+        for (int ii = jj + 1; ii < 6; ++ii) {
+            if (!wnz(ii, jj)) continue;
+            T s = a[tri6(ii, jj)];
+#pragma unroll
+            for (int k = 0; k < jj; ++k)
+                if (wnz(ii, k) && wnz(jj, k)) s -= a[tri6(ii, k)] * a[tri6(jj, k)];
+            a[tri6(ii, jj)] = s * inv;
+        }
+    }
+}
+
+template <typename T>
+__host__ __device__ inline void fwd6w(const T l[21], T v[6]) {
+#pragma unroll
+    for (int ii = 0; ii < 6; ++ii) {
+        T s = v[ii];
+#pragma unroll
+        for (int k = 0; k < ii; ++k)
+            if (wnz(ii, k)) s -= l[tri6(ii, k)] * v[k];
+        v[ii] = s * l[tri6(ii, ii)];
+    }
+}
+
+template <typename T>
+__host__ __device__ inline void bwd6w(const T l[21], T v[6]) {
+#pragma unroll
+    for (int ii = 5; ii >= 0; --ii) {
+        T s = v[ii];
+#pragma unroll
+        for (int k = ii + 1; k < 6; ++k)
+            if (wnz(k, ii)) s -= l[tri6(k, ii)] * v[k];
+        v[ii] = s * l[tri6(ii, ii)];
+    }
+}
+
 // W: RT0 mass on the six star edges, star triangle k holding the edge pair star_wpair(k, .),
 // unit diagonal on absent edges; factored in place
 template <typename T, bool ALLP = false, typename KV>
@@ -101,7 +171,7 @@ __host__ __device__ inline void star_w_factor(const DevPatchClass<T>& pc, const 
 #pragma unroll
     for (int a = 0; a < 6; ++a)
         if (!ALLP && !pc.present[8 + a]) w[tri6(a, a)] = 1;
-    chol6p(w);
+    chol6w(w);
 }
 
 // The residual-independent part of a patch solve, which depends on the permeability only:
@@ -132,8 +202,8 @@ __host__ __device__ inline void patch_factor(const DevPatchClass<T>& pc, const K
         T y[6];
 #pragma unroll
         for (int a = 0; a < 6; ++a) y[a] = pc.Q[q2][a];
-        fwd6p(f.w, y);
-        bwd6p(f.w, y);
+        fwd6w(f.w, y);
+        bwd6w(f.w, y);
 #pragma unroll
         for (int q1 = q2; q1 < 6; ++q1) {
             T v = pc.G[q1][q2];
@@ -181,8 +251,8 @@ __host__ __device__ inline void patch_apply(RR&& rr, const DevPatchClass<T>& pc,
     T y[6];
 #pragma unroll
     for (int a = 0; a < 6; ++a) y[a] = rr(8 + a);
-    fwd6p(f.w, y);
-    bwd6p(f.w, y);
+    fwd6w(f.w, y);
+    bwd6w(f.w, y);
     BIOT_PHASE_FENCE();
     // rhs = H^T r_u + Q W^-1 r_w - r_p
     T rhs[6];
@@ -240,8 +310,8 @@ __host__ __device__ inline void patch_apply(RR&& rr, const DevPatchClass<T>& pc,
         for (int q = 0; q < 6; ++q) v -= pc.Q[q][a] * xp[q];
         xw[a] = v;
     }
-    fwd6p(f.w, xw);
-    bwd6p(f.w, xw);
+    fwd6w(f.w, xw);
+    bwd6w(f.w, xw);
 #pragma unroll
     for (int a = 0; a < 6; ++a) out[(8 + a) * ostride] = (O)((ALLP || pc.present[8 + a]) ? xw[a] : (T)0);
 #pragma unroll
