@@ -14,7 +14,7 @@
  * and w.n = 0 on the whole boundary (those DoFs are eliminated), or the mixed conditions of
  * Terzaghi's column (Sec. 5; biot_problem.bc).
  *
- * Solver (Sec. 3 and 5.1): FGMRES (right preconditioned, flexible, x0 = 0) with one
+ * Solver (Sec. 3 and 5.1): FGMRES (right preconditioned, flexible, from x0 = 0 or a given guess) with one
  * monolithic geometric-multigrid V(nu1, nu2) cycle as preconditioner: rediscretized
  * coarse operators, block prolongation diag(P_u, P_w, P_p) with the divergence-
  * preserving P_u of Sec. 3.1, restriction P^T, additive Vanka (Sec. 3.2.1) or inexact
@@ -200,6 +200,12 @@ typedef struct {
                            one cancels, |w_1| < eta |w_0| (the Daniel-Gragg-Kaufman-Stewart test);
                            eta = reorth in (0, 1], or 1/sqrt(2) when 0 (the default).  A smaller
                            eta skips the pass unless more digits cancel (eta = 0.01: two)      */
+    int x0;             /* in: 0 = start from x = 0 (default); 1 = x holds the initial guess on
+                           entry (canonical order).  The stopping test stays relative to ||b||
+                           (side 0) or ||M^{-1} b|| (side 1), so a good guess saves iterations:
+                           a time-stepping caller passes the previous step's solution, the
+                           reading under which the paper's Table 5 counts are reproduced.
+                           Other values are rejected (BIOT_ERR_ARG)                          */
 } biot_solve_info;
 
 /* Assemble the rediscretized operator on the finest mesh (Sec. 2.3, block_form_rq):
@@ -217,7 +223,8 @@ int biot_setup_hierarchy(biot_ctx* ctx, const biot_mg_opts* opts, void* stream);
  * r and z: device FP64, canonical order of the finest level; may not alias. */
 int biot_vcycle(biot_ctx* ctx, const double* r, double* z, void* stream);
 
-/* Solve A x = b by FGMRES preconditioned with biot_vcycle (Sec. 5.1), x0 = 0.
+/* Solve A x = b by FGMRES preconditioned with biot_vcycle (Sec. 5.1), from x0 = 0 or, with
+ * info->x0 = 1, from the guess x holds on entry.
  * b, x: device FP64, canonical order, may not alias.  info: host pointer (in/out).
  * Returns BIOT_OK, BIOT_NOT_CONVERGED (x = last iterate) or an error code. */
 int biot_solve(biot_ctx* ctx, const double* b, double* x, biot_solve_info* info, void* stream);

@@ -53,7 +53,8 @@ class MGOpts(ctypes.Structure):
 class SolveInfo(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
                 ("iters", ctypes.c_int), ("converged", ctypes.c_int), ("rel_res_true", ctypes.c_double),
-                ("side", ctypes.c_int), ("rel_res_prec", ctypes.c_double), ("reorth", ctypes.c_double)]
+                ("side", ctypes.c_int), ("rel_res_prec", ctypes.c_double), ("reorth", ctypes.c_double),
+                ("x0", ctypes.c_int)]
 
 
 def load():
@@ -181,21 +182,27 @@ class BiotSolver:
         _check(load().biot_vcycle(self._ctx, _dev(r, self.nf(), "r"), _dev(z), _stream()))
         return z
 
-    def solve(self, b, tol=1e-8, restart=30, maxit=500, out=None, side="right", reorth=0.0):
+    def solve(self, b, tol=1e-8, restart=30, maxit=500, out=None, side="right", reorth=0.0, x0=None):
         """side "right": flexible GMRES stopping on the true residual; "left": GMRES on the
         left-preconditioned system stopping on the preconditioned residual.  reorth: the DGKS
-        threshold of the second Gram-Schmidt pass (0: 1/sqrt(2))."""
+        threshold of the second Gram-Schmidt pass (0: 1/sqrt(2)).  x0: initial guess (device FP64,
+        canonical order; copied into the output first), else zero."""
         x = torch.empty_like(b) if out is None else out
-        info = SolveInfo(float(tol), int(restart), int(maxit), 0, 0, 0.0, SIDES[side], 0.0, float(reorth))
+        if x0 is not None:
+            _dev(x0, self.nf(), "x0")
+            x.copy_(x0.reshape(x.shape))
+        info = SolveInfo(float(tol), int(restart), int(maxit), 0, 0, 0.0, SIDES[side], 0.0, float(reorth),
+                         0 if x0 is None else 1)
         code = _check(load().biot_solve(self._ctx, _dev(b, self.nf(), "b"), _dev(x, self.nf(), "x"),
                                         ctypes.byref(info), _stream()), allow=(BIOT_OK, BIOT_NOT_CONVERGED))
         return x, dict(iters=info.iters, converged=bool(info.converged), rel_res_true=info.rel_res_true,
                        rel_res_prec=info.rel_res_prec, code=code)
 
-    def solve_noalloc(self, b, out, tol=1e-8, restart=30, maxit=500, side="right", reorth=0.0):
+    def solve_noalloc(self, b, out, tol=1e-8, restart=30, maxit=500, side="right", reorth=0.0, warm=False):
         """solve() through biot_solve_noalloc: no device allocation in the library; the caller
-        passes the output tensor."""
-        info = SolveInfo(float(tol), int(restart), int(maxit), 0, 0, 0.0, SIDES[side], 0.0, float(reorth))
+        passes the output tensor (with warm=True it holds the initial guess on entry)."""
+        info = SolveInfo(float(tol), int(restart), int(maxit), 0, 0, 0.0, SIDES[side], 0.0, float(reorth),
+                         1 if warm else 0)
         code = _check(load().biot_solve_noalloc(self._ctx, _dev(b, self.nf(), "b"), _dev(out, self.nf(), "x"),
                                                 ctypes.byref(info), _stream()),
                       allow=(BIOT_OK, BIOT_NOT_CONVERGED))

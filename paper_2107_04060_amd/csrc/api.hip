@@ -1114,7 +1114,10 @@ static int fgmres(biot_ctx* c, const KrylovWork& K, const double* b_canon, doubl
     const double* hres = K.hres;
     double* part = K.partial;
     vec_pack(c, b_canon, b, st);
+    // the padding slots hold zeros; with x0 the free slots take the caller's initial guess
     launch_fill(x, n, 0.0, st);
+    const bool warm = info->x0 == 1;
+    if (warm) vec_pack(c, x_canon, x, st);
     const double bnorm = std::sqrt(norm2_dev(K, b, n, st));
     info->iters = 0;
     info->converged = 0;
@@ -1122,6 +1125,7 @@ static int fgmres(biot_ctx* c, const KrylovWork& K, const double* b_canon, doubl
     info->rel_res_prec = 0;
     if (!(bnorm == bnorm) || std::isinf(bnorm)) throw std::domain_error("NaN/Inf in right-hand side");
     if (bnorm == 0.0) {
+        launch_fill(x, n, 0.0, st);
         vec_unpack(c, x, x_canon, st);
         info->converged = 1;
         return BIOT_OK;
@@ -1136,6 +1140,7 @@ static int fgmres(biot_ctx* c, const KrylovWork& K, const double* b_canon, doubl
     double* tmp = Z;
     double znorm = bnorm;           // the stopping test's reference norm
     double beta;
+    double rtrue = bnorm;
     if (left) {
         // the cycle writes the free DoFs of its output only: w must hold zeros elsewhere
         launch_fill(w, n, 0.0, st);
@@ -1143,12 +1148,23 @@ static int fgmres(biot_ctx* c, const KrylovWork& K, const double* b_canon, doubl
         znorm = std::sqrt(norm2_dev(K, w, n, st));
         if (!(znorm == znorm) || std::isinf(znorm)) throw std::domain_error("NaN/Inf in the preconditioned right-hand side");
         beta = znorm;
+        if (warm) {
+            // the preconditioned residual of the initial guess
+            vec_apply(c, x, b, tmp, 1, st);
+            rtrue = std::sqrt(norm2_dev(K, tmp, n, st));
+            precond(c, tmp, w, st);
+            beta = std::sqrt(norm2_dev(K, w, n, st));
+        }
+    } else if (warm) {
+        // r = b - A x0
+        vec_apply(c, x, b, w, 1, st);
+        beta = rtrue = std::sqrt(norm2_dev(K, w, n, st));
     } else {
         // r = b - A x  (x = 0 -> r = b)
         BIOT_HIP(hipMemcpyAsync(w, b, n * sizeof(double), hipMemcpyDeviceToDevice, st));
         beta = bnorm;
     }
-    double rtrue = bnorm;
+    if (!(beta == beta) || std::isinf(beta)) throw std::domain_error("NaN/Inf in the initial residual");
     // host arrays: Hessenberg (m + 1) x m, rotations, right-hand side and solution of the LS problem
     double* H = K.hwork;
     double* cs = H + (size_t)(m + 1) * m;
@@ -1578,6 +1594,7 @@ int biot_solve(biot_ctx* c, const double* b, double* x, biot_solve_info* info, v
         require(info->tol >= 0 && std::isfinite(info->tol), "tol >= 0");
         require(info->side == 0 || info->side == 1, "side: 0 (right) or 1 (left)");
         require(info->reorth >= 0 && info->reorth <= 1, "reorth (the DGKS eta) in [0, 1]");
+        require(info->x0 == 0 || info->x0 == 1, "x0: 0 (zero initial guess) or 1 (x holds it)");
         krylov_alloc(c, info->restart, S(stream));
         return fgmres(c, context_work(c), b, x, info, S(stream));
     });
@@ -1594,6 +1611,7 @@ int biot_solve_noalloc(biot_ctx* c, const double* b, double* x, biot_solve_info*
         require(info->tol >= 0 && std::isfinite(info->tol), "tol >= 0");
         require(info->side == 0 || info->side == 1, "side: 0 (right) or 1 (left)");
         require(info->reorth >= 0 && info->reorth <= 1, "reorth (the DGKS eta) in [0, 1]");
+        require(info->x0 == 0 || info->x0 == 1, "x0: 0 (zero initial guess) or 1 (x holds it)");
         require_structured(c, "biot_solve_noalloc");
         const long long len = c->levels[0]->L.len;
         const size_t need = noalloc_doubles(len, info->restart) * sizeof(double);

@@ -172,3 +172,52 @@ def test_update_logK_matches_update_K(binding):
     s2.close()
     assert np.abs(a1 - a2).max() <= 1e-14 * np.abs(a1).max()
     assert np.abs(z1 - z2).max() <= 1e-10 * np.abs(z1).max()
+
+
+def test_initial_guess_iterate_matches_oracle(binding):
+    """x0 = 1: FGMRES from a seeded guess, stopped at the iteration limit; the iterate is the
+    oracle FGMRES's from the same guess, and the no-allocation entry point gives the same bits."""
+    n = 16
+    print("initial guess n=16 restart 2 maxit 5", flush=True)
+    s = _solver(binding, n)
+    b = inputs.rhs_uniform(n, 0)
+    g = np.random.default_rng(5).standard_normal(s.nf())
+    x, info = s.solve(_t(b), tol=1e-14, restart=2, maxit=5, x0=_t(g))
+    xn, infon = s.solve_noalloc(_t(b), _t(g), tol=1e-14, restart=2, maxit=5, warm=True)
+    s.close()
+    assert info["code"] == binding.BIOT_NOT_CONVERGED and info["iters"] == 5
+    assert torch.equal(x, xn) and infon["iters"] == 5
+    H = Hierarchy(n, params("small"), smoother="vanka", omega=0.9, nu1=2, nu2=2, levels=3)
+    xo, io = fgmres(H.A, b, H.vcycle, tol=1e-14, restart=2, maxit=5, x0=g)
+    err = np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo)
+    print("  iterate rel diff %.2e; rel. residual %.3e (oracle %.3e)"
+          % (err, info["rel_res_true"], io["rel_res_true"]), flush=True)
+    assert err < 1e-9
+    assert abs(info["rel_res_true"] - io["rel_res_true"]) <= 1e-9 * io["rel_res_true"]
+
+
+@pytest.mark.parametrize("side", ["right", "left"])
+def test_converged_initial_guess_takes_no_iteration(binding, side):
+    n = 16
+    s = _solver(binding, n)
+    b = _t(inputs.rhs_uniform(n, 0))
+    xs, _ = s.solve(b, tol=1e-12, restart=30, maxit=200, side=side)
+    x, info = s.solve(b, tol=1e-8, restart=30, maxit=200, side=side, x0=xs)
+    s.close()
+    assert info["code"] == binding.BIOT_OK and info["converged"] and info["iters"] == 0
+    assert torch.equal(x, xs)
+
+
+def test_invalid_initial_guess_flag_is_rejected(binding):
+    import ctypes
+    n = 16
+    s = _solver(binding, n)
+    b = _t(inputs.rhs_uniform(n, 0))
+    x = torch.zeros_like(b)
+    info = binding.SolveInfo(1e-8, 30, 100, 0, 0, 0.0, 0, 0.0, 0.0, 2)
+    code = binding.load().biot_solve(s._ctx, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                     ctypes.byref(info), binding._stream())
+    xs, ok = s.solve(b, tol=1e-8, restart=30, maxit=200)
+    s.close()
+    assert code == binding.BIOT_ERR_ARG
+    assert ok["converged"]

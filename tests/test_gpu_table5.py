@@ -6,11 +6,12 @@ residual 1e-10; E = 3e4, M = 1e6, alpha = mu_f = 1.
 
 Asserted:
   * Table 5 (h = 1/64, tau = 1/128, 64 steps): every step of every cell converges, and the
-    average iteration count stays within 1.5 times the paper's (tests/golden/
-    table5_iterations.txt).  As with Table 4 the counts of right-preconditioned FGMRES on the
-    true residual run above the printed ones by a roughly constant factor;
-    The left-preconditioned reading that reproduces Table 4's Vanka row does not reproduce
-    this table (16 to 22 iterations per step against 13 to 16; the design notes list both);
+    average iteration count is within 2 of the paper's (tests/golden/table5_iterations.txt)
+    when each step's solve starts from the previous step's solution (the interpolant's free
+    values at step 1) with the tolerance relative to the right-hand side.  From zero the counts
+    run 1.2 to 1.36 times the printed ones (17 to 19 against 13 to 16); that run is kept for
+    one cell as a bound;
+  * the GPU's per-step counts under that reading equal the oracle's (+-1) on a sampled cell;
   * convergence with tau = h at nu = 0.4 and 0.499, k = 1e-6 (the paper's study): the GPU's
     errors at t = 0.5 match the oracle's (direct solves) to 1% at h = 1/16 and 1/32, and the
     rates are first order for u in H^1 and at least first order for p in L^2.
@@ -54,22 +55,25 @@ def binding():
     return b
 
 
-def _gpu_run(binding, n, nu, k, tau, steps):
-    """(final full state, iterations per step, all converged)."""
+def _gpu_run(binding, n, nu, k, tau, steps, warm=False):
+    """(final full state, iterations per step, all converged); warm: each solve starts from the
+    previous state's free values."""
     P = BiotParams.from_E_nu(3e4, nu, alpha=1.0, M=1e6, mu_f=1.0, tau=tau)
     prob = mt.SmoothProblem(n, P, k)
     s = binding.BiotSolver(n, P.lam, P.mu, alpha=1.0, M=1e6, mu_f=1.0, tau=tau, K=k)
     s.setup(levels=int(np.log2(n // 8)) + 1, smoother="vanka", nu1=2, nu2=2, omega=_omega(nu, k), omega_J=1.0)
     iters, conv = [], True
 
-    def solve(b, m):
+    def solve(b, m, guess=None):
         nonlocal conv
-        x, info = s.solve(torch.tensor(b, dtype=torch.float64, device="cuda"), tol=1e-10, restart=30, maxit=300)
+        x0 = None if guess is None else torch.tensor(guess, dtype=torch.float64, device="cuda")
+        x, info = s.solve(torch.tensor(b, dtype=torch.float64, device="cuda"), tol=1e-10, restart=30, maxit=300,
+                          x0=x0)
         iters.append(info["iters"])
         conv = conv and bool(info["converged"])
         return x.cpu().numpy()
 
-    x = prob.run(steps, solve)
+    x = prob.run(steps, solve, warm=warm)
     s.close()
     return prob, x, iters, conv
 
@@ -79,14 +83,42 @@ def test_table5_row(binding, nu):
     paper = {float(r[0]): [float(v) for v in r[1:]] for r in _rows("table5_iterations.txt")}[nu]
     out = []
     for k, pc in zip(KS, paper):
-        _, _, iters, conv = _gpu_run(binding, 64, nu, k, 1.0 / 128, 64)
+        _, _, iters, conv = _gpu_run(binding, 64, nu, k, 1.0 / 128, 64, warm=True)
         avg = float(np.mean(iters))
         out.append((k, pc, avg, conv, max(iters)))
         print("  nu %-5g k %-6g average %.2f iterations (max %d, paper %.1f)%s"
               % (nu, k, avg, max(iters), pc, "" if conv else "  NOT CONVERGED"), flush=True)
     for k, pc, avg, conv, mx in out:
         assert conv, (nu, k)
-        assert avg <= 1.5 * pc, (nu, k, avg, pc)
+        assert abs(avg - pc) <= 2, (nu, k, avg, pc)
+
+
+def test_table5_from_zero_bound(binding):
+    """The same cell from zero initial guesses: converged, at most 1.5 times the paper's count."""
+    _, _, iters, conv = _gpu_run(binding, 64, 0.4, 1e-6, 1.0 / 128, 8)
+    assert conv and np.mean(iters) <= 1.5 * 14.0, iters
+
+
+def test_table5_warm_counts_match_oracle(binding):
+    """Per-step FGMRES counts of three warm-started steps (nu 0.499, k 1) on the GPU and on the
+    oracle, within one iteration of each other."""
+    from oracle.krylov import fgmres
+    from oracle.multigrid import Hierarchy
+    nu, k = 0.499, 1.0
+    _, _, gi, conv = _gpu_run(binding, 64, nu, k, 1.0 / 128, 3, warm=True)
+    P = BiotParams.from_E_nu(3e4, nu, alpha=1.0, M=1e6, mu_f=1.0, tau=1.0 / 128)
+    prob = mt.SmoothProblem(64, P, k)
+    H = Hierarchy(64, P, K_tri=k, smoother="vanka", omega=_omega(nu, k), nu1=2, nu2=2, levels=4)
+    oi = []
+
+    def solve(b, m, guess):
+        x, info = fgmres(H.A, b, H.vcycle, tol=1e-10, restart=30, maxit=60, x0=guess)
+        oi.append(info["iters"])
+        return x
+
+    prob.run(3, solve, warm=True)
+    print("GPU", gi, "oracle", oi)
+    assert conv and all(abs(a - b) <= 1 for a, b in zip(gi, oi)), (gi, oi)
 
 
 @pytest.mark.parametrize("nu", [0.4, 0.499])
