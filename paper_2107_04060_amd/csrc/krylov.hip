@@ -4,6 +4,8 @@
 #include "tile.h"
 
 #include <algorithm>
+#include <cstdint>
+#include <type_traits>
 
 #include <hip/hip_runtime.h>
 
@@ -81,55 +83,113 @@ __global__ __launch_bounds__(256) void k_gs_update(double* __restrict__ w, const
     if (threadIdx.x == 0) partial[blockIdx.x] = wred[0] + wred[1] + wred[2] + wred[3];
 }
 
-// Single pass over V_q (q < nv <= GS_FUSED) and w: partial sums of V_q . w (slots 0..nv-1) and
-// w . w (slot nv).  UPDATE: first w -= sum_q h[q] V_q, the sums then taken on the new w (the
-// dot products of the next Gram-Schmidt pass, taken while V is read for this one).  Contiguous
-// chunks per block; every element's V_q are loaded at once and stay in registers.
-constexpr int FUSED_BLOCKS = 512;          // blocks of the single-pass kernels
-template <bool UPDATE>
+// Single pass over V_q (q < nv <= NVB <= GS_FUSED) and w: partial sums of V_q . w (slots
+// 0..nv-1) and w . w (slot nv).  UPDATE: first w -= sum_q h[q] V_q, the sums then taken on the new
+// w (the dot products of the next Gram-Schmidt pass, taken while V is read for this one).
+// Contiguous chunks per block; every element's V_q are loaded at once and stay in registers,
+// sized by the bucket NVB (8, 16 or 32) so that short bases keep more waves resident.  VEC = 2:
+// each lane moves two consecutive elements per 16-byte load (n even, vectors 16-byte aligned).
+// blocks of the single-pass kernels: 512 contiguous chunks up to 4 M elements (fastest there),
+// 1024 above (more 16-byte loads in flight on the 2048^2 mesh's vectors)
+static int fused_blocks(long long n) { return n >= (1LL << 22) ? 1024 : 512; }
+static_assert(1024 <= RED_BLOCKS, "the partial-sum buffer holds RED_BLOCKS sums per slot");
+template <bool UPDATE, int NVB, int VEC>
 __global__ __launch_bounds__(256) void k_gs_fused(double* __restrict__ w, const double* __restrict__ V,
                                                   long long ldv, int nv, const double* __restrict__ h,
                                                   long long n, double* __restrict__ partial,
                                                   const double* run_if) {
+    static_assert(NVB <= GS_FUSED && (VEC == 1 || VEC == 2), "fused Gram-Schmidt bucket");
+    using vec_t = std::conditional_t<VEC == 2, double2, double>;
     if (run_if && *run_if == 0.0) return;
-    __shared__ double red[4][GS_FUSED + 1];
+    __shared__ double red[4][NVB + 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const long long chunk = (n + gridDim.x - 1) / gridDim.x;
+    const long long ng = n / VEC;                               // element groups (n % VEC == 0)
+    const long long chunk = (ng + gridDim.x - 1) / gridDim.x;
     const long long lo = (long long)blockIdx.x * chunk;
-    const long long hi = min(n, lo + chunk);
-    double hq[GS_FUSED], acc[GS_FUSED + 1];
+    const long long hi = min(ng, lo + chunk);
+    double hq[NVB], acc[NVB + 1];
 #pragma unroll
-    for (int q = 0; q < GS_FUSED; ++q) hq[q] = (UPDATE && q < nv) ? h[q] : 0.0;
+    for (int q = 0; q < NVB; ++q) hq[q] = (UPDATE && q < nv) ? h[q] : 0.0;
 #pragma unroll
-    for (int q = 0; q <= GS_FUSED; ++q) acc[q] = 0;
-    for (long long e = lo + threadIdx.x; e < hi; e += blockDim.x) {
-        double v[GS_FUSED];
+    for (int q = 0; q <= NVB; ++q) acc[q] = 0;
+    const vec_t* Vv = reinterpret_cast<const vec_t*>(V);
+    vec_t* wv = reinterpret_cast<vec_t*>(w);
+    const long long ldg = ldv / VEC;
+    for (long long g = lo + threadIdx.x; g < hi; g += blockDim.x) {
+        if constexpr (VEC == 2) {
+            double2 v[NVB];
 #pragma unroll
-        for (int q = 0; q < GS_FUSED; ++q) v[q] = q < nv ? V[(long long)q * ldv + e] : 0.0;
-        double sv = w[e];
-        if constexpr (UPDATE) {
+            for (int q = 0; q < NVB; ++q) v[q] = q < nv ? Vv[(long long)q * ldg + g] : double2{0.0, 0.0};
+            double2 sv = wv[g];
+            if constexpr (UPDATE) {
 #pragma unroll
-            for (int q = 0; q < GS_FUSED; ++q) sv -= hq[q] * v[q];
-            w[e] = sv;
+                for (int q = 0; q < NVB; ++q) {
+                    sv.x -= hq[q] * v[q].x;
+                    sv.y -= hq[q] * v[q].y;
+                }
+                wv[g] = sv;
+            }
+#pragma unroll
+            for (int q = 0; q < NVB; ++q) {
+                acc[q] += v[q].x * sv.x;
+                acc[q] += v[q].y * sv.y;
+            }
+            acc[NVB] += sv.x * sv.x;
+            acc[NVB] += sv.y * sv.y;
+        } else {
+            double v[NVB];
+#pragma unroll
+            for (int q = 0; q < NVB; ++q) v[q] = q < nv ? Vv[(long long)q * ldg + g] : 0.0;
+            double sv = wv[g];
+            if constexpr (UPDATE) {
+#pragma unroll
+                for (int q = 0; q < NVB; ++q) sv -= hq[q] * v[q];
+                wv[g] = sv;
+            }
+#pragma unroll
+            for (int q = 0; q < NVB; ++q) acc[q] += v[q] * sv;
+            acc[NVB] += sv * sv;
         }
-#pragma unroll
-        for (int q = 0; q < GS_FUSED; ++q) acc[q] += v[q] * sv;
-        acc[GS_FUSED] += sv * sv;
     }
-    // output slots: q < nv the dot products, nv the w . w (accumulated in acc[GS_FUSED])
+    // output slots: q < nv the dot products, nv the w . w (accumulated in acc[NVB])
 #pragma unroll
-    for (int q = 0; q <= GS_FUSED; ++q) {
-        if (q < nv || q == GS_FUSED) {
+    for (int q = 0; q <= NVB; ++q) {
+        if (q < nv || q == NVB) {
             const double t = wave_sum(acc[q]);
             if (lane == 0) red[wave][q] = t;
         }
     }
     __syncthreads();
     const int q = threadIdx.x;
-    if (q < nv || q == GS_FUSED) {
+    if (q < nv || q == NVB) {
         const double r = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
-        partial[(long long)(q == GS_FUSED ? nv : q) * gridDim.x + blockIdx.x] = r;
+        partial[(long long)(q == NVB ? nv : q) * gridDim.x + blockIdx.x] = r;
     }
+}
+
+// launch k_gs_fused on the smallest register bucket that holds nv vectors
+template <bool UPDATE>
+static void launch_gs_fused(double* w, const double* V, long long ldv, int nv, const double* h, long long n,
+                            double* partial, const double* run_if, hipStream_t st) {
+    const bool v2 = n % 2 == 0 && ldv % 2 == 0 && reinterpret_cast<uintptr_t>(V) % 16 == 0 &&
+                    reinterpret_cast<uintptr_t>(w) % 16 == 0;
+    const dim3 grd(fused_blocks(n)), blk(256);
+#define BIOT_GS_FUSED(NVB)                                                                                      \
+    do {                                                                                                      \
+        if (v2)                                                                                               \
+            hipLaunchKernelGGL((k_gs_fused<UPDATE, NVB, 2>), grd, blk, 0, st, w, V, ldv, nv, h, n, partial,      \
+                               run_if);                                                                       \
+        else                                                                                                  \
+            hipLaunchKernelGGL((k_gs_fused<UPDATE, NVB, 1>), grd, blk, 0, st, w, V, ldv, nv, h, n, partial,      \
+                               run_if);                                                                       \
+    } while (0)
+    if (nv <= 8)
+        BIOT_GS_FUSED(8);
+    else if (nv <= 16)
+        BIOT_GS_FUSED(16);
+    else
+        BIOT_GS_FUSED(32);
+#undef BIOT_GS_FUSED
 }
 
 // out[q] = sum_b partial[q * np + b], one block per q (fixed order); host: optional mirror.
@@ -165,10 +225,9 @@ __global__ __launch_bounds__(256) void k_gs_reduce(const double* __restrict__ pa
 void launch_gs_dots(const double* V, long long ldv, int nv, const double* w, long long n, double* partial,
                     double* out, double* host, const double* run_if, hipStream_t st) {
     // one pass over all vectors up to GS_FUSED of them, else groups of GSV per pass
-    const int np = nv <= GS_FUSED ? FUSED_BLOCKS : DOT_BLOCKS;
+    const int np = nv <= GS_FUSED ? fused_blocks(n) : DOT_BLOCKS;
     if (nv <= GS_FUSED)
-        hipLaunchKernelGGL(k_gs_fused<false>, dim3(np), dim3(256), 0, st, const_cast<double*>(w), V, ldv, nv,
-                           nullptr, n, partial, run_if);
+        launch_gs_fused<false>(const_cast<double*>(w), V, ldv, nv, nullptr, n, partial, run_if, st);
     else
         hipLaunchKernelGGL(k_gs_dots, dim3(np), dim3(256), 0, st, V, ldv, nv, w, n, partial, run_if);
     hipLaunchKernelGGL(k_gs_reduce, dim3(nv + 1), dim3(256), 0, st, partial, np, out, host, nullptr,
@@ -187,9 +246,8 @@ void launch_gs_update_dots(double* w, const double* V, long long ldv, int nv, co
                            double* partial, double* out, double* host, const double* prev, double* flag,
                            double* host_flag, hipStream_t st, double eta2) {
     if (nv < 1 || nv > GS_FUSED) throw ArgError{"fused Gram-Schmidt pass: 1 <= nv <= GS_FUSED"};
-    hipLaunchKernelGGL(k_gs_fused<true>, dim3(FUSED_BLOCKS), dim3(256), 0, st, w, V, ldv, nv, h, n, partial,
-                       nullptr);
-    hipLaunchKernelGGL(k_gs_reduce, dim3(nv + 1), dim3(256), 0, st, partial, FUSED_BLOCKS, out, host, prev, flag,
+    launch_gs_fused<true>(w, V, ldv, nv, h, n, partial, nullptr, st);
+    hipLaunchKernelGGL(k_gs_reduce, dim3(nv + 1), dim3(256), 0, st, partial, fused_blocks(n), out, host, prev, flag,
                        host_flag, nv, nullptr, eta2);
 }
 
